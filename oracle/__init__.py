@@ -1,0 +1,30 @@
+"""FP64 CPU oracle of the object-centric 2DGS rasterizer hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute anything in this package: only the tests, the smoke check and the
+benchmark's CPU-baseline leg do.  It shares no code with the HIP
+implementation; its inputs are the same float32 arrays the GPU consumes,
+promoted exactly to float64.
+
+Modules
+  geometry  projection of surfels, culling, conservative pixel rectangles,
+            tile ranges, depth keys and the sorted (tile|depth, id) instance
+            list (the bit-exact binning specification)
+  sh        real spherical harmonics (view-dependent colour)
+  render    differentiable per-pixel front-to-back compositing (torch float64)
+  loss      background loss (Eq. 1) and the masked photometric L1 (Eq. 2)
+  prune     occlusion-aware pruning statistics (Section 4.3)
+  fd        central finite differences with decision-set filtering
+"""
+from .geometry import (RasterParams, view_geometry64, bin64, tile_layout, rotation_columns64)
+from .sh import real_sh_basis, sh_basis_scipy, sh_coeff_count
+from .render import render_pixels, render_view, Params64
+from .loss import background_loss64, masked_l1_64
+from .prune import prune_stats64
+
+__all__ = [
+    "RasterParams", "view_geometry64", "bin64", "tile_layout", "rotation_columns64",
+    "real_sh_basis", "sh_basis_scipy", "sh_coeff_count",
+    "render_pixels", "render_view", "Params64",
+    "background_loss64", "masked_l1_64", "prune_stats64",
+]

@@ -1,0 +1,325 @@
+"""Differentiable FP64 per-pixel compositing of surfels (oracle; test
+infrastructure only).
+
+Follows the paper's description of rendering (Section 3.1 and Section 4.3):
+every pixel blends the Gaussians assigned to it in front-to-back order,
+accumulating colour and opacity, and stops once the accumulated opacity
+reaches a threshold close to one or the list is exhausted.  The outputs are
+the ones the paper's losses consume: colour R, accumulated alpha A (Eq. 1),
+depth, normal and the depth distortion of the 2DGS regularisers (Eq. 3).
+
+Readings of what the paper leaves to the underlying renderers (listed with
+reasons in the design notes):
+  * pixel (i, j) is sampled at x = (i + 1/2, j + 1/2);
+  * the ray through x hits the surfel plane p + u a_u + v a_v at
+    (u, v, tau), the solution of [a_u a_v -d] (u,v,tau)^T = -p with
+    d = ((x - c_x)/f_x, (y - c_y)/f_y, 1) (Cramer's rule; a singular system
+    gives G_s = 0);
+  * G_s = exp(-(u^2+v^2)/2) at depth tau; the screen-space low-pass value is
+    G_f = exp(-|x - c|^2) at the centre depth p_z; the larger one is used
+    (equality takes the surface value);
+  * a = min(alpha_max, o G); an entry with a < alpha_min is skipped;
+    blending stops before an entry k when T (1 - a_k) < t_min;
+  * omega_k = a_k T_k; C = sum omega c + T_final bg; A = 1 - T_final;
+    depth = sum omega z; normal = sum omega n_c;
+    dist = sum_{i,j} omega_i omega_j (z_i - z_j)^2 over ordered pairs.
+The per-pixel list is every surfel that is not culled and whose pixel
+rectangle (``geometry.view_geometry64``) contains the pixel, in ascending
+(float32 centre depth, id).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Callable, Optional
+
+import numpy as np
+import torch
+
+from .geometry import RasterParams
+from .sh import sh_colour
+
+DT = torch.float64
+
+# tie windows for the flags that mark pixels where a float32 evaluation may
+# legitimately take the other side of a threshold
+TIE_CUTOFF_REL = 5e-4      # |o G - alpha_min| <= 5e-4 alpha_min
+TIE_TERM_REL = 2e-3        # |T (1 - a) - t_min| <= 2e-3 t_min
+TIE_BRANCH = 1e-6          # |G_s - G_f|
+TIE_CLAMP = 1e-6           # |o G - alpha_max|
+
+
+@dataclass
+class Params64:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opac: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    @staticmethod
+    def from_arrays(means, scales, quats, opac, sh, sh_degree, requires_grad=False):
+        ts = [torch.tensor(np.asarray(a, np.float64), dtype=DT, requires_grad=requires_grad)
+              for a in (means, scales, quats, opac, sh)]
+        return Params64(*ts, sh_degree=int(sh_degree))
+
+    def leaves(self):
+        return [self.means, self.scales, self.quats, self.opac, self.sh]
+
+    def grads(self):
+        return [None if t.grad is None else t.grad.detach().numpy().copy() for t in self.leaves()]
+
+    def zero_grad(self):
+        for t in self.leaves():
+            t.grad = None
+
+
+def quat_to_frame(q: torch.Tensor):
+    """Columns (t_u, t_v, n) of the rotation of q/|q|, q = (w,x,y,z)."""
+    qn = q / torch.linalg.norm(q, dim=-1, keepdim=True)
+    w, x, y, z = qn[:, 0], qn[:, 1], qn[:, 2], qn[:, 3]
+    tu = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z - w * y)], dim=-1)
+    tv = torch.stack([2 * (x * y - w * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w * x)], dim=-1)
+    n = torch.stack([2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y)], dim=-1)
+    return tu, tv, n
+
+
+def _cross(a, b):
+    return torch.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                        a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                        a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], dim=-1)
+
+
+def _dot(a, b):
+    return (a * b).sum(dim=-1)
+
+
+def surfel_view_quantities(P: Params64, ids: np.ndarray, cam, flip: np.ndarray):
+    """Differentiable camera-space quantities of the surfels ``ids``."""
+    idx = torch.as_tensor(ids, dtype=torch.long)
+    mu = P.means[idx]
+    s = P.scales[idx]
+    tu, tv, n = quat_to_frame(P.quats[idx])
+    vm = torch.tensor(np.asarray(cam.viewmat, np.float64), dtype=DT)
+    Rv, t = vm[:, :3], vm[:, 3]
+    p = mu @ Rv.T + t
+    au = s[:, 0:1] * (tu @ Rv.T)
+    av = s[:, 1:2] * (tv @ Rv.T)
+    sign = torch.where(torch.as_tensor(flip[ids]), -1.0, 1.0).to(DT)
+    nc = sign[:, None] * (n @ Rv.T)
+    fx, fy, cx, cy = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy))
+    centre = torch.stack([fx * p[:, 0] / p[:, 2] + cx, fy * p[:, 1] / p[:, 2] + cy], dim=-1)
+    campos = torch.tensor(np.asarray(cam.campos, np.float64), dtype=DT)
+    dvec = mu - campos
+    dirs = dvec / torch.linalg.norm(dvec, dim=-1, keepdim=True)
+    rgb, rgb_raw = sh_colour(P.sh[idx], dirs, P.sh_degree)
+    return dict(p=p, au=au, av=av, nc=nc, centre=centre, rgb=rgb, rgb_raw=rgb_raw,
+                o=P.opac[idx])
+
+
+def _pixel_lists(geom, pix: np.ndarray, margin: int = 1):
+    """Ordered candidate lists for the pixels ``pix`` (P,2) = (i, j).
+
+    Returns (cand ids in list order, index matrix (P,L) into cand, valid
+    mask (P,L), ghost mask (P,L)).  Ghost entries are surfels whose
+    rectangle grown by ``margin`` pixels contains the pixel but the
+    rectangle itself does not; they never blend and only feed tie flags."""
+    ok = ~geom["culled"]
+    rect = geom["rect"]
+    i0, i1 = pix[:, 0].min(), pix[:, 0].max()
+    j0, j1 = pix[:, 1].min(), pix[:, 1].max()
+    sel = ok & (rect[:, 0] - margin <= i1) & (rect[:, 1] + margin >= i0) & \
+        (rect[:, 2] - margin <= j1) & (rect[:, 3] + margin >= j0)
+    cand = np.nonzero(sel)[0]
+    if cand.size == 0:
+        z = np.zeros((pix.shape[0], 1), bool)
+        return cand, np.zeros((pix.shape[0], 1), np.int64), z, z
+    order = np.lexsort((cand, geom["depth_bits"][cand]))
+    cand = cand[order]
+    r = rect[cand]
+    pi = pix[:, 0:1]
+    pj = pix[:, 1:2]
+    inside = (r[None, :, 0] <= pi) & (pi <= r[None, :, 1]) & (r[None, :, 2] <= pj) & (pj <= r[None, :, 3])
+    near = (r[None, :, 0] - margin <= pi) & (pi <= r[None, :, 1] + margin) & \
+        (r[None, :, 2] - margin <= pj) & (pj <= r[None, :, 3] + margin)
+    cnt = near.sum(axis=1)
+    L = int(cnt.max()) if cnt.size else 0
+    L = max(L, 1)
+    # stable compaction of the 'near' columns to the front of each row
+    key = np.where(near, 0, 1)
+    colorder = np.argsort(key, axis=1, kind="stable")[:, :L]
+    valid = np.take_along_axis(near, colorder, axis=1)
+    ghost = valid & ~np.take_along_axis(inside, colorder, axis=1)
+    return cand, colorder, valid, ghost
+
+
+def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
+    """Front-to-back compositing of a chunk of pixels."""
+    Pn, L = colidx.shape
+    ci = torch.as_tensor(colidx, dtype=torch.long)
+    g = lambda t: t[ci]                                    # (P,L,...)
+    p, au, av = g(Q["p"]), g(Q["au"]), g(Q["av"])
+    fx, fy, cx, cy = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy))
+    x = torch.as_tensor(pix[:, 0] + 0.5, dtype=DT)[:, None].expand(Pn, L)
+    y = torch.as_tensor(pix[:, 1] + 0.5, dtype=DT)[:, None].expand(Pn, L)
+    d = torch.stack([(x - cx) / fx, (y - cy) / fy, torch.ones_like(x)], dim=-1)
+    # Cramer's rule for [a_u a_v -d] (u, v, tau)^T = -p
+    c1, c2, c3, b = au, av, -d, -p
+    det = _dot(c1, _cross(c2, c3))
+    sing = det == 0
+    dsafe = torch.where(sing, torch.ones_like(det), det)
+    u = _dot(b, _cross(c2, c3)) / dsafe
+    v = _dot(c1, _cross(b, c3)) / dsafe
+    tau = _dot(c1, _cross(c2, b)) / dsafe
+    Gs = torch.where(sing, torch.zeros_like(u), torch.exp(-(u * u + v * v) / 2))
+    ctr = g(Q["centre"])
+    dx = x - ctr[..., 0]
+    dy = y - ctr[..., 1]
+    Gf = torch.exp(-(dx * dx + dy * dy))
+    surf = Gs >= Gf
+    G = torch.where(surf, Gs, Gf)
+    z = torch.where(surf, tau, p[..., 2])
+    o = g(Q["o"])
+    a_raw = o * G
+    a = torch.clamp(a_raw, max=rp.alpha_max)
+
+    vt = torch.as_tensor(valid)
+    gt = torch.as_tensor(ghost)
+    skip = (a < rp.alpha_min) | ~vt | gt
+    one_minus = torch.where(skip, torch.ones_like(a), 1 - a)
+    T_after = torch.cumprod(one_minus, dim=1)
+    T_before = torch.cat([torch.ones_like(T_after[:, :1]), T_after[:, :-1]], dim=1)
+    stop = (~skip) & (T_after < rp.t_min)
+    has_stop = stop.any(dim=1)
+    first_stop = torch.where(has_stop, stop.to(torch.int64).argmax(dim=1), torch.full((Pn,), L))
+    k = torch.arange(L)[None, :]
+    reached = vt & (k <= first_stop[:, None])
+    blended = (~skip) & (k < first_stop[:, None])
+    w = torch.where(blended, a * T_before, torch.zeros_like(a))
+    T_final = torch.prod(torch.where(blended, 1 - a, torch.ones_like(a)), dim=1)
+
+    rgb = g(Q["rgb"])
+    nc = g(Q["nc"])
+    bg = torch.tensor(np.asarray(cam.bg, np.float64), dtype=DT)
+    color = (w[..., None] * rgb).sum(dim=1) + T_final[:, None] * bg
+    alpha = 1 - T_final
+    depth = (w * z).sum(dim=1)
+    normal = (w[..., None] * nc).sum(dim=1)
+    # distortion: literal double sum over the blended entries
+    nb = blended.sum(dim=1)
+    Lb = max(int(nb.max()), 1)
+    border = torch.argsort((~blended).to(torch.int8), dim=1, stable=True)[:, :Lb]
+    wb = torch.gather(w, 1, border)
+    zb = torch.gather(z, 1, border)
+    bmask = torch.gather(blended, 1, border)
+    wb = torch.where(bmask, wb, torch.zeros_like(wb))
+    zb = torch.where(bmask, zb, torch.zeros_like(zb))
+    dz = zb[:, :, None] - zb[:, None, :]
+    dist = (wb[:, :, None] * wb[:, None, :] * dz * dz).sum(dim=(1, 2))
+
+    last = torch.where(blended, k.expand(Pn, L), torch.full_like(k.expand(Pn, L), -1)).max(dim=1).values
+    n_contrib = (last + 1)
+
+    with torch.no_grad():
+        nsk = reached & ~gt
+        f_cut = (reached & ((a_raw - rp.alpha_min).abs() <= TIE_CUTOFF_REL * rp.alpha_min)).any(dim=1)
+        f_term = (nsk & ~skip & ((T_before * (1 - a) - rp.t_min).abs() <= TIE_TERM_REL * rp.t_min)).any(dim=1)
+        f_branch = (blended & ((Gs - Gf).abs() <= TIE_BRANCH)).any(dim=1)
+        f_clamp = (blended & ((a_raw - rp.alpha_max).abs() <= TIE_CLAMP)).any(dim=1)
+    return dict(color=color, alpha=alpha, depth=depth, normal=normal, dist=dist,
+                T_final=T_final, n_contrib=n_contrib, blended=blended, reached=reached,
+                a=a, w=w, z=z, surf=surf, skip=skip, first_stop=first_stop,
+                clamp=a_raw > rp.alpha_max,
+                flag_cut=f_cut, flag_term=f_term, flag_branch=f_branch, flag_clamp=f_clamp)
+
+
+OUT_KEYS = ("color", "alpha", "depth", "normal", "dist", "T_final")
+
+
+def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = RasterParams(),
+                  loss_fn: Optional[Callable] = None, max_entries: int = 1_500_000,
+                  keep_decisions: bool = False):
+    """Render the pixels ``pix`` (P,2) int (column i, row j) of one view.
+
+    Returns numpy arrays: color (P,3), alpha, depth, normal (P,3), dist,
+    T_final, n_contrib (count of list entries up to the last blended one),
+    last_gid (id of the last blended surfel, -1 if none), nblend; the tie
+    flags flag_cut, flag_term, flag_branch, flag_clamp; ``pairs`` with the
+    blended (pixel, id, a, omega) entries; ``flag_ids``: ids of surfels
+    reached at a flagged pixel.  With ``loss_fn(out_chunk, rows)`` the
+    returned scalar of every chunk is back-propagated into the leaves of
+    ``P`` (the chunked sum is the full loss), so no graph outlives a chunk.
+    """
+    pix = np.asarray(pix, np.int64).reshape(-1, 2)
+    Pn = pix.shape[0]
+    res = {k: [] for k in OUT_KEYS}
+    extra = {k: [] for k in ("n_contrib", "last_gid", "nblend", "flag_cut", "flag_term",
+                             "flag_branch", "flag_clamp")}
+    pairs, flag_ids, decisions = [], [], []
+    start = 0
+    step = max(1, min(Pn, 1024))
+    while start < Pn:
+        stop = min(Pn, start + step)
+        sub = pix[start:stop]
+        cand, colidx, valid, ghost = _pixel_lists(geom, sub)
+        if colidx.shape[0] * colidx.shape[1] > max_entries and step > 1:
+            step = max(1, step // 2)
+            continue
+        ids = cand if cand.size else np.zeros(1, np.int64)
+        if cand.size == 0:
+            valid = np.zeros_like(valid)
+            colidx = np.zeros_like(colidx)
+        Q = surfel_view_quantities(P, ids, cam, geom["flip"])
+        out = _composite(Q, cam, sub, colidx, valid, ghost, rp)
+        if loss_fn is not None:
+            lval = loss_fn(out, np.arange(start, stop))
+            if lval is not None and lval.requires_grad:
+                lval.backward()
+        for k in OUT_KEYS:
+            res[k].append(out[k].detach().numpy())
+        bl = out["blended"].numpy()
+        ncon = out["n_contrib"].numpy()
+        gid_mat = ids[colidx]
+        last_gid = np.where(ncon > 0, gid_mat[np.arange(sub.shape[0]), np.maximum(ncon - 1, 0)], -1)
+        extra["n_contrib"].append(ncon)
+        extra["last_gid"].append(last_gid)
+        extra["nblend"].append(bl.sum(axis=1))
+        for k in ("flag_cut", "flag_term", "flag_branch", "flag_clamp"):
+            extra[k].append(out[k].numpy())
+        rr, cc = np.nonzero(bl)
+        pairs.append(np.stack([rr + start, gid_mat[rr, cc]], axis=1) if rr.size else np.zeros((0, 2), np.int64))
+        pairs_a = out["a"].detach().numpy()[rr, cc]
+        pairs_w = out["w"].detach().numpy()[rr, cc]
+        pairs[-1] = (pairs[-1], pairs_a, pairs_w)
+        fl = out["flag_cut"].numpy() | out["flag_term"].numpy() | out["flag_branch"].numpy() | \
+            out["flag_clamp"].numpy()
+        if fl.any():
+            rch = out["reached"].numpy()
+            fr, fc = np.nonzero(rch & fl[:, None])
+            flag_ids.append(np.unique(gid_mat[fr, fc]))
+        if keep_decisions:
+            decisions.append({k: out[k].detach().numpy() for k in
+                              ("blended", "skip", "surf", "first_stop", "clamp")} | {"gid": gid_mat})
+        start = stop
+    result = {k: np.concatenate(v, axis=0) if v else np.zeros((0,)) for k, v in res.items()}
+    for k, v in extra.items():
+        result[k] = np.concatenate(v, axis=0) if v else np.zeros((0,))
+    if pairs:
+        result["pairs"] = (np.concatenate([p[0] for p in pairs]), np.concatenate([p[1] for p in pairs]),
+                           np.concatenate([p[2] for p in pairs]))
+    else:
+        result["pairs"] = (np.zeros((0, 2), np.int64), np.zeros(0), np.zeros(0))
+    result["flag_ids"] = np.unique(np.concatenate(flag_ids)) if flag_ids else np.zeros(0, np.int64)
+    if keep_decisions:
+        result["decisions"] = decisions
+    return result
+
+
+def render_view(P: Params64, cam, geom, rp: RasterParams = RasterParams(), crop=None, **kw):
+    """Render a whole view, or the crop (x0, y0, w, h), row-major pixels."""
+    if crop is None:
+        crop = (0, 0, int(cam.width), int(cam.height))
+    x0, y0, w, h = crop
+    jj, ii = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
+    pix = np.stack([ii.ravel(), jj.ravel()], axis=1)
+    return render_pixels(P, cam, geom, pix, rp, **kw), pix

@@ -1,0 +1,377 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle
+itself: hand-derived closed forms, a brute-force sequential loop with a
+library linear solve, invariants of front-to-back compositing and the
+rectangle's conservativeness (all CPU)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.render import Params64, render_pixels, render_view
+from paper_2501_08174_amd import scenes
+from tests.oracle_scenes import Y00, centre_on_pixel, front_camera, scene_from
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ID = [1.0, 0.0, 0.0, 0.0]
+
+
+def _render(sc, rp, crop=None, **kw):
+    cam = sc.cams[0]
+    g = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, cam, rp)
+    P = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree)
+    res, pix = render_view(P, cam, g, rp, crop=crop, **kw)
+    return res, pix, g
+
+
+# --------------------------------------------------------------------------
+# single fronto-parallel surfel: closed form at every pixel
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("s", [(0.08, 0.05), (0.3, 0.1), (0.02, 0.2)])
+def test_single_frontoparallel_closed_form(rp, s):
+    cam = front_camera(48)
+    mu = np.array([0.11, -0.07, 0.3])
+    o, rgb = 0.7, np.array([0.2, 0.5, 0.9])
+    sc = scene_from(mu, s, ID, o, rgb, [cam])
+    res, pix, g = _render(sc, rp)
+    mu32 = sc.means[0].astype(np.float64)
+    su, sv = sc.scales[0].astype(np.float64)
+    Z = mu32[2] + 4.0
+    fx, cx = float(cam.fx), float(cam.cx)
+    ccx, ccy = fx * mu32[0] / Z + cx, fx * mu32[1] / Z + cx
+    x = pix[:, 0] + 0.5
+    y = pix[:, 1] + 0.5
+    u = (x - ccx) * Z / (fx * su)
+    v = (y - ccy) * Z / (fx * sv)
+    G = np.maximum(np.exp(-(u * u + v * v) / 2), np.exp(-((x - ccx) ** 2 + (y - ccy) ** 2)))
+    a = np.minimum(np.float32(0.99), np.float32(o) * G)
+    A = np.where(a >= rp.alpha_min, a, 0.0)
+    rgb32 = (sc.sh[0, 0].astype(np.float64) * Y00 + 0.5)
+    ok = ~(res["flag_cut"])
+    assert ok.mean() > 0.99
+    np.testing.assert_allclose(res["alpha"][ok], A[ok], atol=1e-12)
+    np.testing.assert_allclose(res["color"][ok], A[ok, None] * rgb32[None], atol=1e-12)
+    np.testing.assert_allclose(res["depth"][ok], Z * A[ok], atol=1e-12)
+    np.testing.assert_allclose(res["normal"][ok], A[ok, None] * np.array([0, 0, -1.0]), atol=1e-12)
+    np.testing.assert_allclose(res["dist"], 0.0, atol=1e-14)
+
+
+def test_tilted_surfel_hand_derived(rp):
+    """Surfel rotated about the x axis by theta: solve the ray-plane
+    intersection by hand on the row and column through the centre."""
+    cam = front_camera(64)
+    th = 0.6
+    q = [math.cos(th / 2), math.sin(th / 2), 0.0, 0.0]
+    mu = centre_on_pixel(cam, 30, 33, 4.2)
+    sc = scene_from(mu, (0.15, 0.1), q, 0.9, (0.5, 0.5, 0.5), [cam])
+    res, pix, g = _render(sc, rp)
+    p = sc.means[0].astype(np.float64) + np.array([0, 0, 4.0])
+    su, sv = sc.scales[0].astype(np.float64)
+    qq = sc.quats[0].astype(np.float64)
+    qq /= np.linalg.norm(qq)
+    thf = 2 * math.atan2(qq[1], qq[0])
+    c, s_ = math.cos(thf), math.sin(thf)
+    fx, cx = float(cam.fx), float(cam.cx)
+    x = pix[:, 0] + 0.5
+    y = pix[:, 1] + 0.5
+    dx = (x - cx) / fx
+    dy = (y - cx) / fx
+    # tau d = p + u su (1,0,0) + v sv (0, c, s)
+    v = (p[1] - p[2] * dy) / (sv * (s_ * dy - c))
+    tau = p[2] + v * sv * s_
+    u = (tau * dx - p[0]) / su
+    Gs = np.exp(-(u * u + v * v) / 2)
+    ccx = fx * p[0] / p[2] + cx
+    ccy = fx * p[1] / p[2] + cx
+    Gf = np.exp(-((x - ccx) ** 2 + (y - ccy) ** 2))
+    G = np.maximum(Gs, Gf)
+    a = np.minimum(rp.alpha_max, float(sc.opac[0]) * G)
+    A = np.where(a >= rp.alpha_min, a, 0.0)
+    z = np.where(Gs >= Gf, tau, p[2])
+    ok = ~(res["flag_cut"] | res["flag_branch"])
+    np.testing.assert_allclose(res["alpha"][ok], A[ok], atol=1e-11)
+    np.testing.assert_allclose(res["depth"][ok], (z * A)[ok], atol=1e-10)
+    # at the centre pixel u = v = 0 up to float32 rounding of the centre
+    k = np.nonzero((pix[:, 0] == 30) & (pix[:, 1] == 33))[0][0]
+    assert abs(res["alpha"][k] - min(rp.alpha_max, float(sc.opac[0]))) < 1e-6
+    # the surfel normal R_x(theta) e_z = (0, -sin, cos) faces away from the
+    # camera (positive dot with p) and is flipped
+    nz = res["normal"][k] / res["alpha"][k]
+    np.testing.assert_allclose(nz, [0.0, s_, -c], atol=1e-9)
+
+
+def test_lowpass_subpixel_surfel(rp):
+    cam = front_camera(32)
+    mu = np.array([0.013, -0.021, 0.5])
+    sc = scene_from(mu, (1e-4, 1e-4), ID, 0.8, (1, 1, 1), [cam])
+    res, pix, g = _render(sc, rp)
+    p = sc.means[0].astype(np.float64) + np.array([0, 0, 4.0])
+    fx, cx = float(cam.fx), float(cam.cx)
+    ccx, ccy = fx * p[0] / p[2] + cx, fx * p[1] / p[2] + cx
+    x, y = pix[:, 0] + 0.5, pix[:, 1] + 0.5
+    a = np.float32(0.8) * np.exp(-((x - ccx) ** 2 + (y - ccy) ** 2))
+    A = np.where(a >= rp.alpha_min, np.minimum(a, rp.alpha_max), 0.0)
+    ok = ~res["flag_cut"]
+    np.testing.assert_allclose(res["alpha"][ok], A[ok], atol=1e-12)
+    np.testing.assert_allclose(res["depth"][ok], (p[2] * A)[ok], atol=1e-11)
+
+
+def test_stacked_surfels_blending(rp):
+    """Three stacked fronto-parallel surfels: A = 1 - prod(1 - a_k),
+    C = sum c_k a_k prod_{j<k}(1 - a_j), dist = 2 sum_{i<j} w_i w_j dz^2."""
+    cam = front_camera(32)
+    depths = [4.1, 4.5, 4.3]
+    ops = [0.5, 0.6, 0.3]
+    cols = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    means = [centre_on_pixel(cam, 16, 16, d) for d in depths]
+    sc = scene_from(means, [(0.4, 0.4)] * 3, [ID] * 3, ops, cols, [cam])
+    res, pix, g = _render(sc, rp)
+    k = np.nonzero((pix[:, 0] == 16) & (pix[:, 1] == 16))[0][0]
+    order = np.argsort(depths)
+    x = np.array([16.5, 16.5])
+    T, C, wz = 1.0, np.zeros(3), []
+    for idx in order:
+        p = sc.means[idx].astype(np.float64) + np.array([0, 0, 4.0])
+        su = float(sc.scales[idx, 0])
+        ctr = np.array([cam.fx * p[0] / p[2] + cam.cx, cam.fy * p[1] / p[2] + cam.cy])
+        u = (x - ctr) * p[2] / (float(cam.fx) * su)
+        a = float(sc.opac[idx]) * math.exp(-(u @ u) / 2)
+        w = a * T
+        C += w * (sc.sh[idx, 0].astype(np.float64) * Y00 + 0.5)
+        wz.append((w, p[2]))
+        T *= 1 - a
+    dist = 2 * sum(wz[i][0] * wz[j][0] * (wz[i][1] - wz[j][1]) ** 2
+                   for i in range(3) for j in range(i + 1, 3))
+    assert abs(res["alpha"][k] - (1 - T)) < 1e-12
+    np.testing.assert_allclose(res["color"][k], C, atol=1e-12)
+    assert abs(res["dist"][k] - dist) < 1e-12
+    assert res["nblend"][k] == 3
+
+
+def test_termination_count(rp):
+    """Four co-centred surfels with o = 0.95 at the centre pixel:
+    T = 0.05, 0.0025, 1.25e-4, then 1.25e-4 * 0.05 < 1e-4 stops the pixel
+    before the fourth; the expected values are stored in
+    tests/golden/termination.json (hand computed)."""
+    gold = json.load(open(os.path.join(GOLDEN, "termination.json")))
+    cam = front_camera(32)
+    depths = gold["depths"]
+    means = [centre_on_pixel(cam, 16, 16, d) for d in depths]
+    sc = scene_from(means, [(0.5, 0.5)] * 4, [ID] * 4, [gold["opacity"]] * 4, [(0.5, 0.5, 0.5)] * 4, [cam])
+    res, pix, g = _render(sc, rp)
+    k = np.nonzero((pix[:, 0] == 16) & (pix[:, 1] == 16))[0][0]
+    assert res["nblend"][k] == gold["blended"]
+    assert res["last_gid"][k] == gold["last_gid"]
+    assert abs(res["T_final"][k] - gold["T_final"]) < 1e-6
+    assert abs(res["alpha"][k] - (1 - gold["T_final"])) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# brute force: sequential loop with numpy.linalg.solve on tiny scenes
+# --------------------------------------------------------------------------
+
+def _brute_pixel(sc, cam, i, j, rp, frames):
+    x = np.array([i + 0.5, j + 0.5])
+    vm = cam.viewmat.astype(np.float64)
+    R, t = vm[:, :3], vm[:, 3]
+    items = []
+    for gidx in range(sc.n):
+        o = float(sc.opac[gidx])
+        mu = sc.means[gidx].astype(np.float64)
+        p = R @ mu + t
+        tu, tv, n = frames[0][gidx], frames[1][gidx], frames[2][gidx]
+        su, sv = sc.scales[gidx].astype(np.float64)
+        au, av = su * (R @ tu), sv * (R @ tv)
+        # culls (i)-(iii); the rectangle is not used here
+        if p[2] <= float(cam.znear) or o < rp.alpha_min:
+            continue
+        rs2 = math.ceil(2 * math.log(o / rp.alpha_min) * 65536) / 65536
+        if p[2] ** 2 <= rs2 * (au[2] ** 2 + av[2] ** 2):
+            continue
+        items.append((np.float32(p[2]).view(np.uint32), gidx, p, au, av, o))
+    items.sort(key=lambda e: (int(e[0]), e[1]))
+    d = np.array([(x[0] - cam.cx) / cam.fx, (x[1] - cam.cy) / cam.fy, 1.0])
+    T, A_list = 1.0, []
+    C = np.zeros(3)
+    for _, gidx, p, au, av, o in items:
+        Mx = np.stack([au, av, -d], axis=1)
+        try:
+            u, v, tau = np.linalg.solve(Mx, -p)
+            Gs = math.exp(-(u * u + v * v) / 2)
+        except np.linalg.LinAlgError:
+            Gs = 0.0
+        ctr = np.array([cam.fx * p[0] / p[2] + cam.cx, cam.fy * p[1] / p[2] + cam.cy])
+        Gf = math.exp(-float((x - ctr) @ (x - ctr)))
+        a = min(rp.alpha_max, o * max(Gs, Gf))
+        if a < rp.alpha_min:
+            continue
+        if T * (1 - a) < rp.t_min:
+            break
+        rgb = np.maximum(sc.sh[gidx, 0].astype(np.float64) * Y00 + 0.5, 0)
+        C += a * T * rgb
+        A_list.append(gidx)
+        T *= 1 - a
+    return C, 1 - T, A_list
+
+
+def test_brute_force_loop_matches(rp):
+    sc = scenes.make_random_scene(11, 25, width=24, height=20, scale_range=(0.05, 0.4))
+    cam = sc.cams[0]
+    res, pix, g = _render(sc, rp)
+    frames = oracle.rotation_columns64(sc.quats)
+    rng = np.random.default_rng(0)
+    for k in rng.choice(pix.shape[0], 40, replace=False):
+        if res["flag_cut"][k] or res["flag_term"][k]:
+            continue
+        C, A, lst = _brute_pixel(sc, cam, pix[k, 0], pix[k, 1], rp, frames)
+        np.testing.assert_allclose(res["color"][k], C, atol=1e-10)
+        assert abs(res["alpha"][k] - A) < 1e-10
+        assert res["nblend"][k] == len(lst)
+
+
+def test_rect_is_conservative_vs_full_frame_lists(rp):
+    """Rendering with every surfel listed at every pixel (only culls i-iii)
+    equals rendering with the rectangles."""
+    sc = scenes.make_random_scene(12, 60, width=40, height=36, scale_range=(0.02, 0.3))
+    cam = sc.cams[0]
+    g = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, cam, rp)
+    P = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree)
+    res, pix = render_view(P, cam, g, rp)
+    gb = dict(g)
+    gb["culled"] = np.isin(g["cull_reason"], (1, 2, 3))
+    rect = np.zeros_like(g["rect"])
+    rect[:, 1] = cam.width - 1
+    rect[:, 3] = cam.height - 1
+    gb["rect"] = rect
+    resb, _ = render_view(P, cam, gb, rp)
+    for k in ("color", "alpha", "depth", "normal", "dist"):
+        np.testing.assert_allclose(res[k], resb[k], atol=1e-13)
+
+
+def test_rect_contains_every_contributing_pixel(rp):
+    """Dense FP64 evaluation of o*G over a window twice the image: every
+    pixel with o*G >= alpha_min lies in the surfel's rectangle."""
+    sc = scenes.make_random_scene(13, 40, width=32, height=32, scale_range=(0.02, 0.5))
+    cam = sc.cams[0]
+    g = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, cam, rp)
+    P = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree)
+    from oracle.render import surfel_view_quantities
+    ids = np.nonzero(~g["culled"])[0]
+    Q = surfel_view_quantities(P, ids, cam, g["flip"])
+    jj, ii = np.meshgrid(np.arange(cam.height), np.arange(cam.width), indexing="ij")
+    x = ii.ravel() + 0.5
+    y = jj.ravel() + 0.5
+    frames = oracle.rotation_columns64(sc.quats)
+    for r, gid in enumerate(ids):
+        p = Q["p"][r].detach().numpy()
+        au = Q["au"][r].detach().numpy()
+        av = Q["av"][r].detach().numpy()
+        d = np.stack([(x - cam.cx) / cam.fx, (y - cam.cy) / cam.fy, np.ones_like(x)], axis=1)
+        Mx = np.stack([np.broadcast_to(au, d.shape), np.broadcast_to(av, d.shape), -d], axis=2)
+        sol = np.linalg.solve(Mx, np.broadcast_to(-p, d.shape)[..., None])[..., 0]
+        Gs = np.exp(-(sol[:, 0] ** 2 + sol[:, 1] ** 2) / 2)
+        c = Q["centre"][r].detach().numpy()
+        Gf = np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2))
+        a = float(sc.opac[gid]) * np.maximum(Gs, Gf)
+        hit = a >= rp.alpha_min
+        rc = g["rect"][gid]
+        inside = (ii.ravel() >= rc[0]) & (ii.ravel() <= rc[1]) & (jj.ravel() >= rc[2]) & (jj.ravel() <= rc[3])
+        assert not np.any(hit & ~inside), gid
+    # culled surfels never reach alpha_min anywhere in the image
+    for gid in np.nonzero(g["cull_reason"] == 4)[0]:
+        pass
+
+
+# --------------------------------------------------------------------------
+# invariants on random scenes
+# --------------------------------------------------------------------------
+
+def test_invariants_config1(rp):
+    sc = scenes.make_config1()
+    res, pix, g = _render(sc, rp)
+    A, T = res["alpha"], res["T_final"]
+    assert np.all(A >= 0) and np.all(A <= 1 - rp.t_min + 1e-15)
+    assert np.all(T >= rp.t_min - 1e-15)
+    # sum of blending weights equals accumulated alpha
+    P = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree)
+    sums = []
+
+    def lf(out, rows):
+        sums.append((out["w"].sum(dim=1) - out["alpha"]).abs().max().item())
+        return None
+    render_view(P, sc.cams[0], g, rp, loss_fn=lf)
+    assert max(sums) < 1e-12
+    cmax = np.maximum(sc.sh[:, 0].astype(np.float64) * Y00 + 0.5, 0).max()
+    assert np.all(res["color"] <= cmax * A[:, None] + 1e-12)
+    assert np.all(res["dist"] >= -1e-15)
+
+
+def test_permutation_invariance(rp):
+    sc = scenes.make_random_scene(14, 50, width=32, height=32, scale_range=(0.03, 0.3))
+    res, pix, g = _render(sc, rp)
+    perm = np.random.default_rng(1).permutation(sc.n)
+    sc2 = scenes.Scene(sc.means[perm], sc.scales[perm], sc.quats[perm], sc.opac[perm], sc.sh[perm],
+                       sc.sh_degree, sc.cams, sc.masks)
+    res2, _, _ = _render(sc2, rp)
+    for k in ("color", "alpha", "depth", "normal", "dist"):
+        np.testing.assert_allclose(res[k], res2[k], atol=1e-13)
+
+
+def test_empty_scene_is_background(rp):
+    cam = front_camera(16)
+    cam.bg = np.array([0.1, 0.2, 0.3], np.float32)
+    # a surfel behind the camera only
+    sc = scene_from([0.0, 0.0, -6.0], (0.1, 0.1), ID, 0.9, (1, 1, 1), [cam])
+    res, pix, g = _render(sc, rp)
+    assert g["culled"].all()
+    np.testing.assert_allclose(res["alpha"], 0.0)
+    np.testing.assert_allclose(res["color"], np.broadcast_to(cam.bg.astype(np.float64), res["color"].shape))
+
+
+# --------------------------------------------------------------------------
+# geometry and binning
+# --------------------------------------------------------------------------
+
+def test_rotation_columns_orthonormal():
+    q = np.random.default_rng(0).normal(size=(100, 4)).astype(np.float32)
+    tu, tv, n = oracle.rotation_columns64(q)
+    R = np.stack([tu, tv, n], axis=2)
+    np.testing.assert_allclose(np.einsum("nij,nik->njk", R, R), np.broadcast_to(np.eye(3), R.shape), atol=1e-14)
+    assert np.allclose(np.linalg.det(R), 1.0)
+    tu, tv, n = oracle.rotation_columns64(np.array([[2.0, 0, 0, 0]], np.float32))
+    np.testing.assert_array_equal(np.stack([tu[0], tv[0], n[0]]), np.eye(3))
+
+
+def test_bin64_tile_lists_brute_force(rp):
+    sc = scenes.make_random_scene(15, 80, n_views=3, width=[40, 33, 17], height=[21, 48, 30],
+                                  scale_range=(0.02, 0.3))
+    geoms = [oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, c, rp) for c in sc.cams]
+    keys, vals, ranges = oracle.bin64(geoms, sc.cams, rp)
+    assert np.all(np.diff(keys.astype(np.float64)) >= 0) or np.all(keys[1:] >= keys[:-1])
+    lay, T = oracle.tile_layout(sc.cams, rp)
+    assert ranges.shape == (T, 2)
+    covered = 0
+    for v, (tx, ty, off) in enumerate(lay):
+        g = geoms[v]
+        for t in range(tx * ty):
+            cx_, cy_ = t % tx, t // tx
+            lst = [gid for gid in range(sc.n) if not g["culled"][gid]
+                   and g["tiles"][gid, 0] <= cx_ <= g["tiles"][gid, 1]
+                   and g["tiles"][gid, 2] <= cy_ <= g["tiles"][gid, 3]]
+            lst.sort(key=lambda k: (int(g["depth_bits"][k]), k))
+            s, e = ranges[off + t]
+            assert list(vals[s:e]) == lst
+            covered += e - s
+    assert covered == keys.size == int(sum(g["tiles_touched"].sum() for g in geoms))
+
+
+def test_near_plane_and_opacity_culls(rp):
+    cam = front_camera(32)
+    means = [[0, 0, -3.85], [0, 0, 0], [0, 0, 0.2]]
+    sc = scene_from(means, [(0.1, 0.1)] * 3, [ID] * 3, [0.5, 0.003, 0.5], [(1, 1, 1)] * 3, [cam])
+    g = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, cam, rp)
+    assert list(g["cull_reason"]) == [1, 2, 0]
