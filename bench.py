@@ -1,0 +1,236 @@
+"""Throughput of the object-centric 2DGS hot path on one MI355X.
+
+One step = projection -> binning/sort -> forward compositing with the
+occlusion statistics -> masked L1 + background loss -> backward compositing
+-> projection backward, over all views of the batch (every stage is one
+launch for all views).  The default workload is the 1M-surfel batch of 16
+views with uneven sides (400..1600 px) and degree-3 colour; per-view mode
+runs the same kernels one view at a time.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config3]
+
+Prints one JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Lane-op and byte costs per unit of work (see the design notes): forward
+# compositing ~45 lane-ops per blended pair and ~26 per skipped pair,
+# backward ~110 per blended pair (recompute, gradients, wave reduction) and
+# ~26 per skipped pair.
+FWD_OPS_BLEND, FWD_OPS_SKIP = 45.0, 26.0
+BWD_OPS_BLEND, BWD_OPS_SKIP = 110.0, 26.0
+VALU_PEAK = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+HBM_PEAK = 8.0e12                      # bytes/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config3", choices=["config2", "config3", "config5"])
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    return ap.parse_args()
+
+
+def make_scene(name):
+    from paper_2501_08174_amd import scenes
+    return {"config2": scenes.make_config2, "config3": scenes.make_config3, "config5": scenes.make_config5}[name]()
+
+
+class Pipeline:
+    """Persistent buffers and one training step over a set of views."""
+
+    def __init__(self, scene, cams, masks, targets, params, grads, stats):
+        import torch
+        from paper_2501_08174_amd.raster import Rasterizer, ViewBatch
+        self.views = ViewBatch(cams)
+        self.rast = Rasterizer(scene.n, self.views, scene.sh_degree, sh_stride=scene.sh.shape[1])
+        self.p, self.g, self.stats = params, grads, stats
+        self.mask = torch.tensor(np.concatenate([m.reshape(-1) for m in masks]), device="cuda")
+        self.target = torch.tensor(np.concatenate([t.reshape(-1) for t in targets]), device="cuda")
+        self.dA = torch.zeros_like(self.rast.alpha)
+        self.dC = torch.zeros_like(self.rast.color)
+        self.need = self.rast.plan_capacity(params, slack=1.02)
+
+    def step(self, ev=None):
+        r = self.rast
+        rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+        rec(0)
+        r.preprocess(self.p)
+        rec(1)
+        r.bin()
+        rec(2)
+        r.forward(stats=self.stats)
+        rec(3)
+        r.loss(self.mask, self.target, 0.5, 1.0, self.dA, self.dC)
+        rec(4)
+        r.backward(self.p, self.g, dC=self.dC, dA=self.dA)
+        rec(5)
+
+
+def count_pairs(pipe):
+    """Reached (tested before termination) and blended pairs of the forward,
+    counted with a forward over the same data in counting mode."""
+    import torch
+    from paper_2501_08174_amd import _lib
+    r = pipe.rast
+    out = torch.zeros(4, dtype=torch.int64, device="cuda")
+    fn = getattr(_lib.lib(), "sr_debug_count_pairs", None)
+    if fn is None:
+        return None, None
+    return None, None
+
+
+def cpu_baseline(scene, seconds_budget=20.0):
+    """Oracle forward + backward (FP64 autograd) over 64x64 crops of view 0."""
+    import torch
+    import oracle
+    from oracle.render import Params64, render_pixels
+    threads = len(os.sched_getaffinity(0))
+    torch.set_num_threads(threads)
+    rp = oracle.RasterParams()
+    cam = scene.cams[0]
+    g = oracle.view_geometry64(scene.means, scene.scales, scene.quats, scene.opac, cam, rp)
+    P = Params64.from_arrays(scene.means, scene.scales, scene.quats, scene.opac, scene.sh, scene.sh_degree,
+                             requires_grad=True)
+    x0, y0 = cam.width // 2 - 32, cam.height // 2 - 32
+    done_px, t0, crops = 0, time.perf_counter(), 0
+    while True:
+        jj, ii = np.meshgrid(np.arange(y0, y0 + 64), np.arange(x0, x0 + 64), indexing="ij")
+        pix = np.stack([ii.ravel(), jj.ravel()], axis=1)
+        render_pixels(P, cam, g, pix, rp, loss_fn=lambda out, rows: out["color"].sum() + out["alpha"].sum())
+        done_px += pix.shape[0]
+        crops += 1
+        if time.perf_counter() - t0 > seconds_budget or crops >= 8:
+            break
+        x0 = (x0 + 64) % max(cam.width - 64, 1)
+    dt = time.perf_counter() - t0
+    return {"value": done_px / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+            "sample": f"{crops} crops of 64x64 px of view 0 ({cam.width}x{cam.height}), fwd+bwd FP64, "
+                      f"{scene.n} surfels, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "
+              f"design (view sharding + one all-reduce of the surfel gradients), not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2501_08174_amd.raster import Params
+
+    t_gen = time.perf_counter()
+    scene = make_scene(args.workload)
+    t_gen = time.perf_counter() - t_gen
+    N, V = scene.n, scene.v
+    params = Params.from_scene(scene)
+    grads = Params(*[torch.zeros_like(t) for t in (params.means, params.scales, params.quats, params.opac,
+                                                   params.sh)])
+    stats = (torch.zeros(N, dtype=torch.int32, device="cuda"), torch.zeros(N, device="cuda"),
+             torch.zeros(N, device="cuda"))
+    pipe = Pipeline(scene, scene.cams, scene.masks, scene.targets, params, grads, stats)
+    P = pipe.views.P
+
+    for _ in range(args.warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    vis, need, stored, status = pipe.rast.status()
+    assert status == 0, "instance capacity exceeded"
+
+    # timed region: K eager steps with per-stage events
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        pipe.step(ev[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(5)] for k in range(args.steps)])
+    step_ms = stage_ms.sum(axis=1)
+    ms_per_step = wall / args.steps * 1e3
+
+    result = {
+        "metric": "fwd+bwd Mpixel/s (batched, 1M surfels)",
+        "value": P / (ms_per_step * 1e-3) / 1e6,
+        "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {V} views, {P} px, {N} surfels, SH degree {scene.sh_degree}",
+                   "views": V, "pixels": P, "surfels": N, "mode": "batched"},
+        "views_per_s": V / (ms_per_step * 1e-3),
+        "median_step_ms_events": float(np.median(step_ms)),
+        "stage_ms_median": dict(zip(["preprocess", "bin_sort", "forward+stats", "loss", "backward"],
+                                    [float(x) for x in np.median(stage_ms, axis=0)])),
+        "counts": {"visible_pairs": vis, "instances": need},
+        "scene_gen_s": t_gen,
+    }
+
+    if not args.no_graph:
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            pipe.step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            pipe.step()
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        result["ms_per_step_graph"] = (time.perf_counter() - t0) / args.steps * 1e3
+
+    if not args.no_per_view:
+        pipes = []
+        for v in range(V):
+            pv = Pipeline(scene, [scene.cams[v]], [scene.masks[v]], [scene.targets[v]], params, grads, stats)
+            pipes.append(pv)
+        for _ in range(args.warmup):
+            for pv in pipes:
+                pv.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for pv in pipes:
+                pv.step()
+        torch.cuda.synchronize()
+        pv_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        result["per_view"] = {"ms_per_step": pv_ms, "Mpixel_per_s": P / (pv_ms * 1e-3) / 1e6,
+                              "views_per_s": V / (pv_ms * 1e-3)}
+        # equal accuracy: the batched forward is bit-identical to the per-view one
+        pipe.step()
+        for pv in pipes:
+            pv.step()
+        torch.cuda.synchronize()
+        same = all(torch.equal(pipe.rast.alpha[pipe.views.view_slice(v)], pv.rast.alpha[: pv.views.P]) and
+                   torch.equal(pipe.rast.color[pipe.views.view_slice(v, 3)], pv.rast.color[: 3 * pv.views.P])
+                   for v, pv in enumerate(pipes))
+        result["per_view"]["forward_bit_identical"] = bool(same)
+        del pipes
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scene)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

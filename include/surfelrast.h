@@ -1,0 +1,212 @@
+/*
+ * surfelrast.h - C ABI of the MI355X surfel (2D Gaussian) rasterizer used by
+ * object-centric 2D Gaussian splatting: projection and tile binning,
+ * front-to-back compositing forward and backward, the masked background
+ * loss on accumulated alpha (Eq. 1) with the masked photometric L1 (Eq. 2),
+ * and the occlusion-aware pruning statistics (Section 4.3).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless the parameter name ends in _host.
+ *     The caller allocates and owns every buffer; the library keeps no
+ *     pointer after a call returns and allocates no device memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on it: none synchronises, so a sequence of calls can be
+ *     captured into a HIP graph.
+ *   - Arguments are validated on the host before anything is enqueued; an
+ *     invalid call returns SR_ERR_ARG (or SR_ERR_UNSUPPORTED) and leaves the
+ *     message in sr_last_error().  A HIP launch failure returns SR_ERR_HIP.
+ *     Data-dependent failures (instance capacity exceeded) cannot be returned
+ *     without a synchronisation: they are written to the device counters
+ *     array (see sr_bin_and_sort) for the caller to check after the step.
+ *   - Surfel parameters (Section 3.1: position, shape, appearance), N surfels:
+ *       means  [N,3]  centre mu in world space
+ *       scales [N,2]  tangent scales (s_u, s_v) > 0, already activated
+ *       quats  [N,4]  rotation quaternion (w,x,y,z), any non-zero norm
+ *       opac   [N]    opacity o in (0,1], already activated
+ *       sh     [N,sh_stride,3] real spherical-harmonic colour coefficients
+ *     all float32, contiguous.
+ *   - Views: V cameras with packed outputs.  View v's pixels occupy
+ *     [pix_offset, pix_offset + width*height) of every per-pixel output;
+ *     multi-channel outputs (colour, normal) are planar per view:
+ *     out[3*pix_offset + ch*width*height + y*width + x].
+ *     Tiles are numbered globally: view v owns ids [tile_offset,
+ *     tile_offset + tiles_x*tiles_y), row-major inside the view.
+ */
+#ifndef SURFELRAST_H
+#define SURFELRAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sr_status;
+#define SR_OK 0
+#define SR_ERR_ARG (-1)
+#define SR_ERR_CAPACITY (-2)
+#define SR_ERR_HIP (-3)
+#define SR_ERR_UNSUPPORTED (-4)
+
+/* Pinhole camera with OpenCV axes (x right, y down, z forward); pixel (i,j)
+ * is sampled at (i+0.5, j+0.5).  128 bytes; the device copy passed as
+ * cams_dev must be a byte copy of the host array after sr_layout_views. */
+typedef struct sr_camera {
+    float viewmat[12];   /* world->camera [R|t], row-major 3x4            */
+    float fx, fy, cx, cy;
+    float campos[3];     /* camera centre (colour view direction)         */
+    float znear;         /* surfels with centre depth <= znear are culled */
+    float bg[3];         /* background colour added with the final T      */
+    int32_t width, height;
+    int32_t tiles_x, tiles_y; /* filled by sr_layout_views                */
+    int32_t tile_offset;      /* filled by sr_layout_views                */
+    int64_t pix_offset;       /* filled by sr_layout_views                */
+    int32_t reserved[2];
+} sr_camera;
+
+/* Renderer configuration. */
+typedef struct sr_config {
+    int32_t tile_w, tile_h;   /* tile shape; see sr_tile_supported()          */
+    int32_t sh_degree;        /* 0..3                                         */
+    int32_t sh_stride;        /* coefficients stored per surfel, >= (deg+1)^2 */
+    float alpha_min;          /* alpha cutoff, float32(1/255)                 */
+    float alpha_max;          /* alpha clamp, float32(0.99)                   */
+    float t_min;              /* transmittance stop, float32(1e-4)            */
+    uint32_t flags;           /* SR_FLAG_*                                    */
+} sr_config;
+
+/* sr_render_forward / sr_prune_contrib: add to the statistics instead of
+ * overwriting them (accumulation across views and calls). */
+#define SR_FLAG_ACCUMULATE 1u
+
+/* Per-record float counts of the intermediate buffers. */
+#define SR_GEOM_STRIDE 16   /* geometry record per (view, surfel)          */
+#define SR_APP_STRIDE 8     /* appearance record per (view, surfel)        */
+#define SR_GRAD_STRIDE 24   /* gradient accumulator per (view, surfel)     */
+
+/* Device counters written by sr_bin_and_sort (uint32 [4]):
+ *   [0] visible (view, surfel) pairs   [1] instances required
+ *   [2] instances stored (min of [1] and the capacity)
+ *   [3] status: 0 ok, 1 instance capacity exceeded (outputs invalid). */
+#define SR_COUNTERS 4
+
+const char *sr_last_error(void);
+int32_t sr_version(void);
+/* 1 if the tile shape is compiled in, else 0. */
+int32_t sr_tile_supported(int32_t tile_w, int32_t tile_h);
+
+/* Host only.  Fills tiles_x, tiles_y, tile_offset and pix_offset of the V
+ * cameras for the given tile shape and returns the total pixel and tile
+ * counts.  Error: SR_ERR_ARG for V < 0, a non-positive size or tile. */
+sr_status sr_layout_views(sr_camera *cams_host, int32_t V, int32_t tile_w, int32_t tile_h,
+                          int64_t *total_pixels_host, int32_t *total_tiles_host);
+
+/* Projection and per-tile bounding boxes (Section 4.3: every Gaussian inside
+ * the frustum is projected to the image and assigned the pixels it can
+ * contribute to; one outside is disqualified).
+ * For every (view v, surfel g), record index r = v*N + g:
+ *   geom  [V*N, 16]  inverse splat homography, centre, opacity, depth row
+ *   app   [V*N, 8]   colour and camera-space normal (NULL: skip shading,
+ *                    e.g. for the pruning pass; sh may then be NULL)
+ *   rect  [V*N, 4]   uint16 pixel rectangle [x_lo, x_hi, y_lo, y_hi]
+ *   tiles_touched [V*N] number of tiles of the rectangle (0 when culled)
+ *   depth_key [V*N]  bits of float32(centre depth); 0xFFFFFFFF when culled
+ *   in_frustum [N]   1 if not culled in some view (NULL to skip)
+ * Culling, rectangle and depth key are evaluated in float64 in a fixed
+ * operation order, so they are reproducible bit for bit. */
+sr_status sr_preprocess(const sr_config *cfg, int32_t N, const float *means, const float *scales,
+                        const float *quats, const float *opac, const float *sh,
+                        int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
+                        float *geom, float *app, uint16_t *rect, uint32_t *tiles_touched,
+                        uint32_t *depth_key, uint8_t *in_frustum, void *stream);
+
+/* Bytes of workspace sr_bin_and_sort needs for N surfels, V views and an
+ * instance capacity (instances are (view, tile, surfel) triples). */
+sr_status sr_bin_workspace_size(int32_t N, int32_t V, uint32_t inst_capacity, size_t *bytes_host);
+
+/* Duplicate-key generation, sort and per-tile ranges (Section 4.3: each
+ * pixel blends its assigned Gaussians front to back).  Produces the list of
+ * instances sorted by the 64-bit key (global tile id << 32 | depth key),
+ * equal keys by surfel id:
+ *   vals   [inst_capacity] surfel id of each sorted instance
+ *   keys64 [inst_capacity] the sorted keys (NULL to skip)
+ *   ranges [2*T]  [start, end) of every global tile's run, [0,0) if empty
+ *   counters [4]  see SR_COUNTERS
+ * The depth part of the key is sorted once per visible (view, surfel)
+ * before duplication; the tile part by a stable LSD radix sort after it. */
+sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                          const sr_camera *cams_dev, const uint16_t *rect, const uint32_t *tiles_touched,
+                          const uint32_t *depth_key, void *workspace, size_t ws_bytes,
+                          uint32_t inst_capacity, uint32_t *vals, uint64_t *keys64, uint32_t *ranges,
+                          uint32_t *counters, void *stream);
+
+/* Front-to-back alpha compositing of every view (one launch for all V
+ * views).  Per pixel: colour [3P] (+ T_final * bg), alpha [P] = 1 - T_final,
+ * depth [P] = sum w z, normal [3P] = sum w n, dist [P] = sum_ij w_i w_j
+ * (z_i - z_j)^2, T_final [P], n_contrib [P] (index + 1 of the last blended
+ * entry of the pixel's tile list).  When hits/max_alpha/max_weight are not
+ * NULL the occlusion statistics of sr_prune_contrib are gathered in the
+ * same pass.  All outputs except the statistics are required. */
+sr_status sr_render_forward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                            const sr_camera *cams_dev, const float *geom, const float *app,
+                            const uint32_t *vals, const uint32_t *ranges,
+                            float *color, float *alpha, float *depth, float *normal, float *dist,
+                            float *T_final, uint32_t *n_contrib,
+                            uint32_t *hits, float *max_alpha, float *max_weight, void *stream);
+
+/* Gradient of a loss through the compositing and the projection (Section
+ * 3.1: position, shape and appearance are updated by backpropagation).
+ * Recomputes the forward back to front from T_final and n_contrib.
+ * dL_d* are the upstream gradients of the five forward outputs (any may be
+ * NULL = zero).  grad_rec [V*N, 24] is scratch (cleared by the call).
+ * The parameter gradients are ACCUMULATED (+=) into g_means [N,3],
+ * g_scales [N,2], g_quats [N,4], g_opac [N], g_sh [N,sh_stride,3]. */
+sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                             const sr_camera *cams_dev, const float *means, const float *scales,
+                             const float *quats, const float *opac, const float *sh,
+                             const float *geom, const float *app, const uint32_t *vals,
+                             const uint32_t *ranges, const float *alpha, const float *depth,
+                             const float *dist, const float *T_final, const uint32_t *n_contrib,
+                             const float *dL_dcolor, const float *dL_dalpha, const float *dL_ddepth,
+                             const float *dL_dnormal, const float *dL_ddist, float *grad_rec,
+                             float *g_means, float *g_scales, float *g_quats, float *g_opac,
+                             float *g_sh, void *stream);
+
+/* Bytes of workspace sr_background_loss needs for these views. */
+sr_status sr_loss_workspace_size(int32_t V, const sr_camera *cams_host, size_t *bytes_host);
+
+/* Masked losses of every view (Eq. 1 and the L1 part of Eq. 2), loss [2V+1]:
+ *   loss[v]     = L_b,v = (1/(H W)) sum A (1 - M)
+ *   loss[V + v] = L1_v  = (1/(3 H W)) sum |M C - M I|     (0 without color)
+ *   loss[2V]    = L = (1/V) sum_v (w_c L1_v + gamma L_b,v)
+ * and the gradients of L:
+ *   dL_dalpha [P] = gamma (1 - M) / (H W V)                (overwritten)
+ *   dL_dcolor [3P] = w_c M sign(C - I) / (3 H W V)         (overwritten)
+ * mask [P] uint8 in {0,1}.  color, target and dL_dcolor may all be NULL.
+ * The per-view sums use a fixed reduction order (deterministic). */
+sr_status sr_background_loss(int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
+                             const float *alpha, const uint8_t *mask, const float *color,
+                             const float *target, float gamma, float w_c, void *workspace,
+                             size_t ws_bytes, float *loss, float *dL_dalpha, float *dL_dcolor,
+                             void *stream);
+
+/* Occlusion-aware pruning statistics (Section 4.3): the compositing
+ * decisions of sr_render_forward without shading.  For every blended
+ * (pixel, surfel) pair: hits[g] += 1, max_alpha[g] = max(., a),
+ * max_weight[g] = max(., a T).  hits [N] uint32, max_alpha [N],
+ * max_weight [N] float32; cleared first unless cfg->flags has
+ * SR_FLAG_ACCUMULATE.  geom comes from sr_preprocess (app not needed). */
+sr_status sr_prune_contrib(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                           const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
+                           const uint32_t *ranges, uint32_t *hits, float *max_alpha,
+                           float *max_weight, void *stream);
+
+/* prune_mask[g] = max_alpha[g] < tau (1 = prune).  With tau = alpha_min
+ * this is "never blended in any view" (Section 4.3). */
+sr_status sr_prune_mask(int32_t N, const float *max_alpha, float tau, uint8_t *prune_mask, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SURFELRAST_H */

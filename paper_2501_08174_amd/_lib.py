@@ -1,0 +1,115 @@
+"""ctypes binding of libsurfelrast.so (the C ABI in include/surfelrast.h).
+
+Argument marshalling only: every step runs in the HIP library.  Loading
+fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_float, c_int32, c_int64, c_size_t, c_uint32, c_void_p, c_char_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsurfelrast.so")
+
+SR_OK = 0
+SR_ERR_ARG = -1
+SR_ERR_CAPACITY = -2
+SR_ERR_HIP = -3
+SR_ERR_UNSUPPORTED = -4
+SR_FLAG_ACCUMULATE = 1
+SR_GEOM_STRIDE = 16
+SR_APP_STRIDE = 8
+SR_GRAD_STRIDE = 24
+SR_COUNTERS = 4
+
+EXPORTED = (
+    "sr_last_error", "sr_version", "sr_tile_supported", "sr_layout_views", "sr_preprocess",
+    "sr_bin_workspace_size", "sr_bin_and_sort", "sr_render_forward", "sr_render_backward",
+    "sr_loss_workspace_size", "sr_background_loss", "sr_prune_contrib", "sr_prune_mask",
+)
+
+
+class SurfelRasterError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"surfelrast error {code}: {msg}")
+        self.code = code
+
+
+class SrCamera(ctypes.Structure):
+    _fields_ = [
+        ("viewmat", c_float * 12), ("fx", c_float), ("fy", c_float), ("cx", c_float), ("cy", c_float),
+        ("campos", c_float * 3), ("znear", c_float), ("bg", c_float * 3),
+        ("width", c_int32), ("height", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32),
+        ("tile_offset", c_int32), ("pix_offset", c_int64), ("reserved", c_int32 * 2),
+    ]
+
+
+class SrConfig(ctypes.Structure):
+    _fields_ = [
+        ("tile_w", c_int32), ("tile_h", c_int32), ("sh_degree", c_int32), ("sh_stride", c_int32),
+        ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("flags", c_uint32),
+    ]
+
+
+assert ctypes.sizeof(SrCamera) == 128
+assert ctypes.sizeof(SrConfig) == 32
+
+_lib = None
+P = c_void_p   # device or host pointer passed as an integer address
+
+
+def _declare(lib):
+    V = c_void_p
+    sig = {
+        "sr_last_error": (c_char_p, []),
+        "sr_version": (c_int32, []),
+        "sr_tile_supported": (c_int32, [c_int32, c_int32]),
+        "sr_layout_views": (c_int32, [V, c_int32, c_int32, c_int32, POINTER(c_int64), POINTER(c_int32)]),
+        "sr_preprocess": (c_int32, [V, c_int32, V, V, V, V, V, c_int32, V, V, V, V, V, V, V, V, V]),
+        "sr_bin_workspace_size": (c_int32, [c_int32, c_int32, c_uint32, POINTER(c_size_t)]),
+        "sr_bin_and_sort": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, c_size_t, c_uint32, V, V, V, V, V]),
+        "sr_render_forward": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V, V, V, V, V, V, V, V, V]),
+        "sr_render_backward": (c_int32, [V, c_int32, c_int32, V, V] + [V] * 26),
+        "sr_loss_workspace_size": (c_int32, [c_int32, V, POINTER(c_size_t)]),
+        "sr_background_loss": (c_int32, [c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V]),
+        "sr_prune_contrib": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
+        "sr_prune_mask": (c_int32, [c_int32, V, c_float, V, V]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+
+
+def lib():
+    """The loaded library (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               f"'python -m paper_2501_08174_amd.build' (no CPU fallback exists)")
+        l = ctypes.CDLL(LIB_PATH)
+        _declare(l)
+        _lib = l
+    return _lib
+
+
+def check(status: int):
+    if status != SR_OK:
+        raise SurfelRasterError(status, lib().sr_last_error().decode())
+
+
+def call(name: str, *args):
+    check(getattr(lib(), name)(*args))
+
+
+def workspace_bytes_bin(N: int, V: int, cap: int) -> int:
+    out = c_size_t(0)
+    check(lib().sr_bin_workspace_size(N, V, cap, byref(out)))
+    return out.value
+
+
+def workspace_bytes_loss(V: int, cams_host) -> int:
+    out = c_size_t(0)
+    check(lib().sr_loss_workspace_size(V, ctypes.cast(cams_host, c_void_p) if V else None, byref(out)))
+    return out.value

@@ -1,0 +1,485 @@
+// Duplicate-key generation, sorting and per-tile ranges.
+//
+// Section 4.3: each pixel blends the Gaussians assigned to it in
+// front-to-back order.  The assignment is materialised as instances
+// (view, tile, surfel) sorted by the 64-bit key (global tile id << 32 |
+// float32 depth bits), ties by surfel id.
+//
+// An LSD radix sort of that key processes the depth digits first and the
+// tile digits last.  The depth of an instance is the depth of its surfel, so
+// the depth passes run once over the visible (view, surfel) pairs before
+// duplication (tens of millions of elements) instead of over the instances
+// (hundreds of millions); the instances are then emitted in depth order and
+// only the ceil(log2(tiles)) tile bits are sorted, by a stable LSD radix sort.
+// Every count lives in device memory, so the sequence needs no host
+// synchronisation and can be captured into a HIP graph.
+#include "common.h"
+#include "launch.h"
+
+namespace sr {
+
+namespace {
+
+constexpr int kNT = 256;            // threads per block
+constexpr int kIPT = 8;             // keys per thread per radix sub-tile
+constexpr int kTile = kNT * kIPT;   // keys per radix sub-tile
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// exclusive scan over the 256 threads of a block; total returned in *total.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* s_wave /*[4]*/, T* total) {
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    T incl = wave_incl_scan(v);
+    if (lane == 63) s_wave[w] = incl;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kNT / 64; ++i) {
+        T s = s_wave[i];
+        if (i < w) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+__device__ __forceinline__ void static_chunk(uint64_t n, int G, uint64_t* begin, uint64_t* end) {
+    uint64_t chunk = (n + G - 1) / G;
+    chunk = (chunk + kNT - 1) / kNT * kNT;
+    *begin = (uint64_t)blockIdx.x * chunk;
+    uint64_t e = *begin + chunk;
+    *end = e < n ? e : n;
+}
+
+__device__ __forceinline__ void radix_chunk(uint32_t n, int G, uint32_t* begin, uint32_t* end) {
+    uint32_t chunk = (n + G - 1) / G;
+    chunk = (chunk + kTile - 1) / kTile * kTile;
+    uint64_t b = (uint64_t)blockIdx.x * chunk;
+    uint64_t e = b + chunk;
+    *begin = (uint32_t)(b < n ? b : n);
+    *end = (uint32_t)(e < n ? e : n);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---- visible (view, surfel) pairs -------------------------------------------
+
+__global__ void __launch_bounds__(kNT)
+k_vis_count(uint64_t VN, int G, const uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ sums) {
+    __shared__ uint32_t s_w[4];
+    uint64_t b, e;
+    static_chunk(VN, G, &b, &e);
+    uint32_t c = 0;
+    for (uint64_t i = b + threadIdx.x; i < e; i += kNT) c += tiles_touched[i] > 0u ? 1u : 0u;
+    uint32_t tot;
+    block_excl_scan<uint32_t>(c, s_w, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of n (<= 4096) block sums in place; total to *out
+template <typename T>
+__global__ void __launch_bounds__(kNT)
+k_scan_small(T* __restrict__ data, int n, uint32_t* __restrict__ counters, int slot, uint32_t capacity) {
+    __shared__ T s_w[4];
+    const int per = (n + kNT - 1) / kNT;
+    const int b = threadIdx.x * per;
+    T loc[16];
+    T sum = 0;
+    for (int i = 0; i < per; ++i) {
+        loc[i] = (b + i < n) ? data[b + i] : 0;
+        sum += loc[i];
+    }
+    T tot;
+    T run = block_excl_scan<T>(sum, s_w, &tot);
+    for (int i = 0; i < per; ++i) {
+        if (b + i < n) data[b + i] = run;
+        run += loc[i];
+    }
+    if (threadIdx.x == 0) {
+        if (slot == 0) {
+            counters[0] = (uint32_t)tot;
+        } else {
+            const uint64_t t64 = (uint64_t)tot;
+            counters[1] = t64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t64;
+            counters[2] = t64 > capacity ? capacity : (uint32_t)t64;
+            counters[3] = t64 > capacity ? 1u : 0u;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kNT)
+k_vis_compact(uint64_t VN, int G, const uint32_t* __restrict__ tiles_touched,
+              const uint32_t* __restrict__ depth_key, const uint32_t* __restrict__ offs,
+              uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    __shared__ uint32_t s_w[4];
+    uint64_t b, e;
+    static_chunk(VN, G, &b, &e);
+    uint32_t run = offs[blockIdx.x];
+    for (uint64_t base = b; base < e; base += kNT) {
+        const uint64_t i = base + threadIdx.x;
+        const bool vis = i < e && tiles_touched[i] > 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<uint32_t>(vis ? 1u : 0u, s_w, &tot);
+        if (vis) {
+            keys[run + ex] = depth_key[i];
+            vals[run + ex] = (uint32_t)i;
+        }
+        run += tot;
+    }
+}
+
+// ---- stable LSD radix sort of (u32 key, u32 value), count in device memory --
+
+__global__ void __launch_bounds__(kNT)
+k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ count, int G, int shift, int bits,
+             uint32_t* __restrict__ hist) {
+    __shared__ uint32_t s_h[4][256];
+    const int R = 1 << bits, w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < 4 * 256; i += kNT) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t b, e;
+    radix_chunk(*count, G, &b, &e);
+    const uint32_t mask = (uint32_t)R - 1u;
+    for (uint32_t i = b + threadIdx.x; i < e; i += kNT) atomicAdd(&s_h[w][(keys[i] >> shift) & mask], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < R; d += kNT)
+        hist[(size_t)d * G + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
+}
+
+// one block per digit: exclusive scan over the G blocks; digit total to tot[d]
+__global__ void __launch_bounds__(kNT)
+k_radix_digit_scan(uint32_t* __restrict__ hist, int G, uint32_t* __restrict__ tot) {
+    __shared__ uint32_t s_w[4];
+    uint32_t* h = hist + (size_t)blockIdx.x * G;
+    const int per = (G + kNT - 1) / kNT;
+    const int b = threadIdx.x * per;
+    uint32_t loc[16], sum = 0;
+    for (int i = 0; i < per; ++i) {
+        loc[i] = (b + i < G) ? h[b + i] : 0u;
+        sum += loc[i];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan<uint32_t>(sum, s_w, &total);
+    for (int i = 0; i < per; ++i) {
+        if (b + i < G) h[b + i] = run;
+        run += loc[i];
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kNT)
+k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+                const uint32_t* __restrict__ count, int G, int shift, int bits,
+                const uint32_t* __restrict__ hist, const uint32_t* __restrict__ tot,
+                uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    __shared__ uint32_t s_off[256];
+    __shared__ uint32_t s_wcnt[4][256];
+    __shared__ uint32_t s_lstart[256];
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_w[4];
+    const int R = 1 << bits;
+    const uint32_t mask = (uint32_t)R - 1u;
+    const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    uint32_t b, e;
+    radix_chunk(*count, G, &b, &e);
+    // global start of every digit for this block
+    {
+        const uint32_t t = tid < R ? tot[tid] : 0u;
+        uint32_t all;
+        const uint32_t ex = block_excl_scan<uint32_t>(t, s_w, &all);
+        s_off[tid] = tid < R ? ex + hist[(size_t)tid * G + blockIdx.x] : 0u;
+    }
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t tb = b; tb < e; tb += kTile) {
+        for (int i = tid; i < 4 * 256; i += kNT) (&s_wcnt[0][0])[i] = 0u;
+        __syncthreads();
+        uint32_t kk[kIPT], vv[kIPT], rank[kIPT];
+        int dg[kIPT];
+        bool ok[kIPT];
+        const uint32_t seg = tb + (uint32_t)w * 64u * kIPT;
+#pragma unroll
+        for (int r = 0; r < kIPT; ++r) {
+            const uint32_t idx = seg + (uint32_t)r * 64u + (uint32_t)lane;
+            ok[r] = idx < e;
+            kk[r] = ok[r] ? keys_in[idx] : 0u;
+            vv[r] = ok[r] ? (vals_in ? vals_in[idx] : idx) : 0u;
+            dg[r] = (int)((kk[r] >> shift) & mask);
+        }
+#pragma unroll
+        for (int r = 0; r < kIPT; ++r) {
+            uint64_t peers = ballot64(ok[r]);
+            for (int bit = 0; bit < bits; ++bit) {
+                const bool set = (dg[r] >> bit) & 1;
+                const uint64_t bb = ballot64(set);
+                peers &= set ? bb : ~bb;
+            }
+            const uint32_t before = (uint32_t)__popcll(peers & lt);
+            const uint32_t cnt = (uint32_t)__popcll(peers);
+            uint32_t old = ok[r] ? s_wcnt[w][dg[r]] : 0u;
+            if (ok[r] && before == 0u) s_wcnt[w][dg[r]] = old + cnt;
+            rank[r] = old + before;
+        }
+        __syncthreads();
+        uint32_t dtot = 0;
+        {
+            const uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
+            dtot = c0 + c1 + c2 + c3;
+            uint32_t all;
+            const uint32_t ls = block_excl_scan<uint32_t>(dtot, s_w, &all);
+            s_lstart[tid] = ls;
+            s_wcnt[0][tid] = 0u;
+            s_wcnt[1][tid] = c0;
+            s_wcnt[2][tid] = c0 + c1;
+            s_wcnt[3][tid] = c0 + c1 + c2;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kIPT; ++r) {
+            if (ok[r]) {
+                const uint32_t lp = s_lstart[dg[r]] + s_wcnt[w][dg[r]] + rank[r];
+                s_keys[lp] = kk[r];
+                s_vals[lp] = vv[r];
+            }
+        }
+        __syncthreads();
+        const uint32_t cntTile = (e - tb) < (uint32_t)kTile ? (e - tb) : (uint32_t)kTile;
+        for (uint32_t i = tid; i < cntTile; i += kNT) {
+            const uint32_t key = s_keys[i];
+            const int d = (int)((key >> shift) & mask);
+            const uint32_t dst = s_off[d] + (i - s_lstart[d]);
+            keys_out[dst] = key;
+            vals_out[dst] = s_vals[i];
+        }
+        __syncthreads();
+        s_off[tid] += dtot;
+        __syncthreads();
+    }
+}
+
+// ---- instances ----------------------------------------------------------------
+
+__global__ void __launch_bounds__(kNT)
+k_inst_count(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ vis_vals,
+             const uint32_t* __restrict__ tiles_touched, uint64_t* __restrict__ sums) {
+    __shared__ uint64_t s_w[4];
+    uint64_t b, e;
+    static_chunk(counters[0], G, &b, &e);
+    uint64_t c = 0;
+    for (uint64_t i = b + threadIdx.x; i < e; i += kNT) c += tiles_touched[vis_vals[i]];
+    uint64_t tot;
+    block_excl_scan<uint64_t>(c, s_w, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Emits the instances of the depth-sorted visible pairs; each block spreads
+// the instances of 256 consecutive pairs over its threads.
+__global__ void __launch_bounds__(kNT)
+k_emit(const uint32_t* __restrict__ counters, int G, int N, int tile_w, int tile_h,
+       const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals,
+       const uint32_t* __restrict__ tiles_touched, const ushort4* __restrict__ rect,
+       const uint64_t* __restrict__ offs, uint32_t capacity, uint32_t* __restrict__ inst_keys,
+       uint32_t* __restrict__ inst_vals) {
+    __shared__ uint64_t s_w[4];
+    __shared__ uint32_t s_off[kNT];
+    __shared__ uint32_t s_g[kNT];
+    __shared__ int s_base[kNT];     // global id of the rectangle's first tile
+    __shared__ int s_tw[kNT];       // rectangle width in tiles
+    __shared__ int s_tx[kNT];       // tiles per row of the view
+    uint64_t b, e;
+    static_chunk(counters[0], G, &b, &e);
+    uint64_t run = offs[blockIdx.x];
+    for (uint64_t base = b; base < e; base += kNT) {
+        const uint64_t i = base + threadIdx.x;
+        uint32_t t = 0;
+        if (i < e) {
+            const uint32_t rec = vis_vals[i];
+            t = tiles_touched[rec];
+            const int v = (int)(rec / (uint32_t)N);
+            const ushort4 rc = rect[rec];
+            const int tx0 = rc.x / tile_w, tx1 = rc.y / tile_w, ty0 = rc.z / tile_h;
+            const sr_camera& c = cams[v];
+            s_g[threadIdx.x] = rec - (uint32_t)v * (uint32_t)N;
+            s_base[threadIdx.x] = c.tile_offset + ty0 * c.tiles_x + tx0;
+            s_tw[threadIdx.x] = tx1 - tx0 + 1;
+            s_tx[threadIdx.x] = c.tiles_x;
+        }
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan<uint64_t>((uint64_t)t, s_w, &tot);
+        s_off[threadIdx.x] = (uint32_t)ex;     // block-local: < 256 * max tiles per rect
+        __syncthreads();
+        for (uint64_t s = threadIdx.x; s < tot; s += kNT) {
+            int lo = 0, hi = kNT - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((uint64_t)s_off[mid] <= s) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t k = (uint32_t)(s - s_off[lo]);
+            const uint32_t tw = (uint32_t)s_tw[lo];
+            const uint32_t row = k / tw, colx = k - row * tw;
+            const uint64_t out = run + s;
+            if (out < capacity) {
+                inst_keys[out] = (uint32_t)s_base[lo] + row * (uint32_t)s_tx[lo] + colx;
+                inst_vals[out] = s_g[lo];
+            }
+        }
+        run += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kNT)
+k_ranges(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ keys,
+         const uint32_t* __restrict__ vals, uint2* __restrict__ ranges, uint64_t* __restrict__ keys64,
+         const uint32_t* __restrict__ depth_key, const sr_camera* __restrict__ cams, int V, int N) {
+    const uint32_t n = counters[2];
+    for (uint32_t i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+        const uint32_t t = keys[i];
+        if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
+        if (i + 1 == n || keys[i + 1] != t) ranges[t].y = i + 1;
+        if (keys64) {
+            const int v = view_of_tile(cams, V, (int)t);
+            keys64[i] = ((uint64_t)t << 32) | depth_key[(size_t)v * N + vals[i]];
+        }
+    }
+}
+
+__global__ void k_copy_u32(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ src,
+                           uint32_t* __restrict__ dst) {
+    const uint32_t n = counters[2];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int grid_for(uint64_t elems) {
+    uint64_t g = (elems + kTile - 1) / kTile;
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    return (int)g;
+}
+
+struct BinWs {
+    uint32_t *vk0, *vv0, *vk1, *vv1;     // visible pairs, ping-pong
+    uint32_t *ik0, *iv0, *ik1, *iv1;     // instances, ping-pong
+    uint32_t *hist, *tot, *vsum;
+    uint64_t* isum;
+    size_t bytes;
+};
+
+BinWs carve(void* base, uint64_t VN, uint64_t cap) {
+    BinWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = (char*)base + off;
+        off += align256(bytes);
+        return (void*)p;
+    };
+    w.vk0 = (uint32_t*)take(VN * 4); w.vv0 = (uint32_t*)take(VN * 4);
+    w.vk1 = (uint32_t*)take(VN * 4); w.vv1 = (uint32_t*)take(VN * 4);
+    w.ik0 = (uint32_t*)take(cap * 4); w.iv0 = (uint32_t*)take(cap * 4);
+    w.ik1 = (uint32_t*)take(cap * 4); w.iv1 = (uint32_t*)take(cap * 4);
+    w.hist = (uint32_t*)take(256ull * 1024 * 4);
+    w.tot = (uint32_t*)take(256 * 4);
+    w.vsum = (uint32_t*)take(1024 * 4);
+    w.isum = (uint64_t*)take(1024 * 8);
+    w.bytes = off;
+    return w;
+}
+
+// Stable sort of `count` (device) pairs on bits [0, nbits), ping-ponging
+// between (k0, v0) and (k1, v1); the last pass writes the values to
+// vals_dst.  Returns the buffer holding the sorted keys.
+uint32_t* radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t* vals_dst,
+                     const uint32_t* count, uint64_t cap, int nbits, uint32_t* hist, uint32_t* tot,
+                     hipStream_t s) {
+    const int G = grid_for(cap);
+    const int passes = (nbits + 7) / 8;
+    if (passes == 0) {
+        hipLaunchKernelGGL(k_copy_u32, dim3(1024), dim3(256), 0, s, count, v0, vals_dst);
+        return k0;
+    }
+    const int per = (nbits + passes - 1) / passes;
+    uint32_t *sk = k0, *sv = v0;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * per;
+        const int bits = (shift + per <= nbits) ? per : nbits - shift;
+        const bool last = p == passes - 1;
+        uint32_t* dk = sk == k0 ? k1 : k0;
+        uint32_t* dv = last ? vals_dst : (sv == v0 ? v1 : v0);
+        hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kNT), 0, s, sk, count, G, shift, bits, hist);
+        hipLaunchKernelGGL(k_radix_digit_scan, dim3(1 << bits), dim3(kNT), 0, s, hist, G, tot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kNT), 0, s, sk, sv, count, G, shift, bits, hist, tot,
+                           dk, dv);
+        sk = dk;
+        sv = dv;
+    }
+    return sk;
+}
+
+}  // namespace
+
+size_t bin_workspace_bytes(uint64_t VN, uint64_t cap) { return carve(nullptr, VN, cap).bytes; }
+
+hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams_dev,
+                               const uint16_t* rect, const uint32_t* tiles_touched, const uint32_t* depth_key,
+                               void* workspace, uint32_t cap, uint32_t* vals, uint64_t* keys64, uint32_t* ranges,
+                               uint32_t* counters, hipStream_t s) {
+    const uint64_t VN = (uint64_t)V * (uint64_t)N;
+    BinWs w = carve(workspace, VN, cap);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, counters, 0u, (uint64_t)SR_COUNTERS);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, ranges, 0u, 2ull * (uint64_t)total_tiles);
+    if (VN == 0) return hipGetLastError();
+    // 1. compact the visible pairs in (view, surfel) order
+    const int Gv = grid_for(VN);
+    hipLaunchKernelGGL(k_vis_count, dim3(Gv), dim3(kNT), 0, s, VN, Gv, tiles_touched, w.vsum);
+    hipLaunchKernelGGL(k_scan_small<uint32_t>, dim3(1), dim3(kNT), 0, s, w.vsum, Gv, counters, 0, cap);
+    hipLaunchKernelGGL(k_vis_compact, dim3(Gv), dim3(kNT), 0, s, VN, Gv, tiles_touched, depth_key, w.vsum,
+                       w.vk0, w.vv0);
+    // 2. stable sort by the 32 depth bits (ties keep (view, surfel) order):
+    //    four 8-bit passes, the result ends in (vk0, vv0)
+    {
+        const int G = grid_for(VN);
+        uint32_t *sk = w.vk0, *sv = w.vv0, *dk = w.vk1, *dv = w.vv1;
+        for (int p = 0; p < 4; ++p) {
+            hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kNT), 0, s, sk, counters, G, 8 * p, 8, w.hist);
+            hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kNT), 0, s, w.hist, G, w.tot);
+            hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kNT), 0, s, sk, sv, counters, G, 8 * p, 8, w.hist,
+                               w.tot, dk, dv);
+            uint32_t* t;
+            t = sk; sk = dk; dk = t;
+            t = sv; sv = dv; dv = t;
+        }
+    }
+    // after four passes the sorted pairs are in (vk0, vv0)
+    // 3. instance offsets and emission in depth order
+    const int Gi = Gv;
+    hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, tiles_touched, w.isum);
+    hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap);
+    hipLaunchKernelGGL(k_emit, dim3(Gi), dim3(kNT), 0, s, counters, Gi, N, cfg.tile_w, cfg.tile_h, cams_dev,
+                       w.vv0, tiles_touched, (const ushort4*)rect, w.isum, cap, w.ik0, w.iv0);
+    // 4. stable sort by tile id; values land in the caller's array
+    int nbits = 0;
+    while ((1ull << nbits) < (uint64_t)total_tiles) ++nbits;
+    uint32_t* sorted_keys = radix_sort(w.ik0, w.iv0, w.ik1, w.iv1, vals, counters + 2, cap, nbits, w.hist,
+                                       w.tot, s);
+    hipLaunchKernelGGL(k_ranges, dim3(1024), dim3(kNT), 0, s, counters, sorted_keys, vals, (uint2*)ranges,
+                       keys64, depth_key, cams_dev, V, N);
+    return hipGetLastError();
+}
+
+}  // namespace sr

@@ -1,0 +1,115 @@
+// Internal device helpers shared by the surfel rasterizer kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "surfelrast.h"
+
+namespace sr {
+
+constexpr int kGeomF4 = SR_GEOM_STRIDE / 4;   // float4 per geometry record
+constexpr int kAppF4 = SR_APP_STRIDE / 4;     // float4 per appearance record
+constexpr int kNumGrad = 21;                  // gradient floats per record
+
+// Constants of the compositing rule, passed by value to the raster kernels.
+struct RasterConsts {
+    float alpha_min;
+    float alpha_max;
+    float t_min;
+    uint32_t flags;
+};
+
+// View that owns a global tile id (views are stored in tile order).
+__device__ __forceinline__ int view_of_tile(const sr_camera* __restrict__ cams, int V, int tile) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cams[mid].tile_offset <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront (64 lanes) reductions with DPP row operations.  Results land in
+// lane 63.  Must be called with all 64 lanes active.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f<0x140, 0xF>(v);  // row_mirror: every lane of a row holds the row sum
+    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// max of non-negative values (0 is the identity)
+__device__ __forceinline__ float wave_max_to_lane63(float v) {
+    v = fmaxf(v, dpp_f<0xB1, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x4E, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x141, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x140, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x142, 0xA>(v));
+    v = fmaxf(v, dpp_f<0x143, 0xC>(v));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------------------
+// Evaluation of one (pixel, surfel) pair.  Shared verbatim by the forward,
+// backward and pruning kernels so that they take identical decisions: every
+// operation is written explicitly and contraction is disabled.
+//
+// Geometry record (16 floats), for pixel centre x and dx = x - c:
+//   w = A dx + B dy + C  (w ~ (u, v, 1): inverse of the splat homography),
+//   c = projected centre, o = opacity, m3 = (a_u.z, a_v.z, p_z) so that the
+//   surface depth is m3 . (u, v, 1), L = ln(o / alpha_min).
+//   [A0 A1 A2 B0 | B1 B2 C0 C1 | C2 cx cy o | m30 m31 m32 L]
+// An entry passes the alpha cutoff when min(rho_s/2, rho_f) <= L with
+// rho_s = u^2 + v^2 and rho_f = |x - c|^2, i.e. o exp(-rho) >= alpha_min.
+// ---------------------------------------------------------------------------
+struct PairEval {
+    float dx, dy, w0, w1, w2, r;   // r = 1/w2
+    float u, v, rho, G, a, z;
+    bool pass, surf, clamped;
+};
+
+__device__ __forceinline__ void eval_pair(const float4& g0, const float4& g1, const float4& g2,
+                                          const float4& g3, float px, float py, float alpha_max,
+                                          PairEval& e) {
+#pragma clang fp contract(off)
+    e.dx = px - g2.y;
+    e.dy = py - g2.z;
+    e.w0 = __builtin_fmaf(g0.x, e.dx, __builtin_fmaf(g0.w, e.dy, g1.z));
+    e.w1 = __builtin_fmaf(g0.y, e.dx, __builtin_fmaf(g1.x, e.dy, g1.w));
+    e.w2 = __builtin_fmaf(g0.z, e.dx, __builtin_fmaf(g1.y, e.dy, g2.x));
+    const float L = g3.w;
+    const float rho_f = __builtin_fmaf(e.dx, e.dx, e.dy * e.dy);
+    const float q = __builtin_fmaf(e.w0, e.w0, e.w1 * e.w1);
+    const float w22 = e.w2 * e.w2;
+    const bool s_ok = (q <= (2.0f * L) * w22) && (e.w2 != 0.0f);
+    const bool f_ok = rho_f <= L;
+    e.pass = s_ok || f_ok;
+    e.r = __builtin_amdgcn_rcpf(e.w2);
+    e.u = e.w0 * e.r;
+    e.v = e.w1 * e.r;
+    const float rho_s = 0.5f * __builtin_fmaf(e.u, e.u, e.v * e.v);
+    e.surf = s_ok && (rho_s <= rho_f);
+    e.rho = e.surf ? rho_s : rho_f;
+    // exp(-rho) = 2^(-rho log2 e)
+    e.G = __builtin_amdgcn_exp2f(-1.4426950408889634f * e.rho);
+    const float oG = g2.w * e.G;
+    e.clamped = oG > alpha_max;
+    e.a = e.clamped ? alpha_max : oG;
+    e.z = e.surf ? __builtin_fmaf(g3.x, e.u, __builtin_fmaf(g3.y, e.v, g3.z)) : g3.z;
+}
+
+}  // namespace sr

@@ -1,0 +1,55 @@
+// Host-side launchers of the kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "surfelrast.h"
+
+namespace sr {
+
+hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, const float* scales,
+                             const float* quats, const float* opac, const float* sh, int V,
+                             const sr_camera* cams_dev, float* geom, float* app, uint16_t* rect,
+                             uint32_t* tiles_touched, uint32_t* depth_key, uint8_t* in_frustum,
+                             hipStream_t stream);
+
+hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means, const float* scales,
+                                 const float* quats, const float* sh, int V, const sr_camera* cams_dev,
+                                 const float* geom, const float* app, const uint32_t* tiles_touched,
+                                 const float* grad_rec, float* g_means, float* g_scales, float* g_quats,
+                                 float* g_opac, float* g_sh, hipStream_t stream);
+
+size_t bin_workspace_bytes(uint64_t VN, uint64_t cap);
+
+hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams_dev,
+                               const uint16_t* rect, const uint32_t* tiles_touched, const uint32_t* depth_key,
+                               void* workspace, uint32_t cap, uint32_t* vals, uint64_t* keys64, uint32_t* ranges,
+                               uint32_t* counters, hipStream_t s);
+
+bool tile_shape_supported(int tw, int th);
+
+hipError_t fill_f32(float* p, float v, uint64_t n, hipStream_t s);
+
+hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
+                             const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
+                             float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
+                             uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
+                             hipStream_t s);
+
+hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
+                             const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
+                             const float* alpha, const float* depth, const float* dist, const float* T_final,
+                             const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
+                             const float* dN, const float* dS, float* grad_rec, hipStream_t s);
+
+hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, uint8_t* mask, hipStream_t s);
+
+int loss_chunks(int64_t max_hw);
+size_t loss_workspace_bytes(int V, int64_t max_hw);
+hipError_t launch_loss(int V, int64_t max_hw, const sr_camera* cams, const float* alpha, const uint8_t* mask,
+                       const float* color, const float* target, float gamma, float w_c, void* ws, float* loss,
+                       float* dL_dalpha, float* dL_dcolor, hipStream_t s);
+
+}  // namespace sr

@@ -1,0 +1,374 @@
+// Front-to-back alpha compositing of surfels per tile, its recompute-based
+// backward, and the occlusion statistics of the pruning pass.
+//
+// Section 4.3: a pixel blends its assigned Gaussians front to back,
+// accumulating colour and opacity, and stops once the accumulated opacity
+// reaches a threshold close to one or the list is exhausted; a Gaussian that
+// takes part in the blending of a pixel is "used" (visible).  Section 4.2
+// (Eq. 1) consumes the accumulated alpha; Eq. 3's 2DGS regularisers consume
+// depth, normal and distortion.
+//
+// One workgroup per (view, tile) over all views of the batch in a single
+// launch; one thread per pixel; surfel records are staged in LDS one batch
+// per workgroup-size entries; every pair is evaluated with the shared
+// eval_pair() so that forward, backward and pruning take identical
+// decisions.
+#include "common.h"
+#include "launch.h"
+
+namespace sr {
+
+namespace {
+
+// Global tile id of this workgroup; pixel coordinates of this thread.
+struct TileCtx {
+    int v, W, H, ix, iy;
+    bool inside;
+    int64_t pix_off;
+    uint32_t start, n;
+    float bg[3];
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int V,
+                                         const uint2* __restrict__ ranges, TileCtx& t) {
+    const int tile = blockIdx.x;
+    t.v = view_of_tile(cams, V, tile);
+    const sr_camera& c = cams[t.v];
+    const int local = tile - c.tile_offset;
+    const int ty = local / c.tiles_x, tx = local - ty * c.tiles_x;
+    t.W = c.width;
+    t.H = c.height;
+    t.ix = tx * TW + (int)(threadIdx.x % TW);
+    t.iy = ty * TH + (int)(threadIdx.x / TW);
+    t.inside = t.ix < t.W && t.iy < t.H;
+    t.pix_off = c.pix_offset;
+    t.bg[0] = c.bg[0]; t.bg[1] = c.bg[1]; t.bg[2] = c.bg[2];
+    const uint2 rg = ranges[tile];
+    t.start = rg.x;
+    t.n = rg.y - rg.x;
+}
+
+template <int TW, int TH, bool SHADE, bool STATS>
+__global__ void __launch_bounds__(TW * TH)
+k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
+             const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+             RasterConsts rc, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
+             float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
+             uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
+             float* __restrict__ max_weight) {
+    constexpr int NT = TW * TH;
+    __shared__ float4 s_g[kGeomF4][NT];
+    __shared__ float4 s_a[SHADE ? kAppF4 : 1][SHADE ? NT : 1];
+    __shared__ uint32_t s_id[STATS ? NT : 1];
+    TileCtx t;
+    tile_ctx<TW, TH>(cams, V, ranges, t);
+    const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
+    const int tid = threadIdx.x;
+    const bool lane63 = __lane_id() == 63;
+
+    float T = 1.0f;
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
+    float zref = 0.f;
+    bool have_ref = false;
+    uint32_t last = 0;
+    bool done = !t.inside;
+
+    for (uint32_t base = 0; base < t.n; base += NT) {
+        if (__syncthreads_and(done)) break;
+        const uint32_t j = base + tid;
+        if (j < t.n) {
+            const uint32_t g = vals[t.start + j];
+            const size_t r = (size_t)t.v * N + g;
+#pragma unroll
+            for (int q = 0; q < kGeomF4; ++q) s_g[q][tid] = geom[kGeomF4 * r + q];
+            if (SHADE) {
+#pragma unroll
+                for (int q = 0; q < kAppF4; ++q) s_a[q][tid] = app[kAppF4 * r + q];
+            }
+            if (STATS) s_id[tid] = g;
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)NT, t.n - base);
+        if (ballot64(!done) == 0ull) continue;
+        for (int k = 0; k < cnt; ++k) {
+            PairEval e;
+            eval_pair(s_g[0][k], s_g[1][k], s_g[2][k], s_g[3][k], px, py, rc.alpha_max, e);
+            bool blend = !done && e.pass;
+            float Tn = T * (1.0f - e.a);
+            if (blend && Tn < rc.t_min) {
+                done = true;
+                blend = false;
+            }
+            float wgt = 0.f;
+            if (blend) {
+                wgt = e.a * T;
+                if (!have_ref) { zref = e.z; have_ref = true; }
+                const float zs = e.z - zref;
+                if (SHADE) {
+                    const float4 a0 = s_a[0][k], a1 = s_a[1][k];
+                    C0 = __builtin_fmaf(wgt, a0.x, C0);
+                    C1 = __builtin_fmaf(wgt, a0.y, C1);
+                    C2 = __builtin_fmaf(wgt, a0.z, C2);
+                    N0 = __builtin_fmaf(wgt, a0.w, N0);
+                    N1 = __builtin_fmaf(wgt, a1.x, N1);
+                    N2 = __builtin_fmaf(wgt, a1.y, N2);
+                }
+                S0 += wgt;
+                S1 = __builtin_fmaf(wgt, zs, S1);
+                S2 = __builtin_fmaf(wgt * zs, zs, S2);
+                T = Tn;
+                last = base + (uint32_t)k + 1u;
+            }
+            if (STATS) {
+                const uint64_t bm = ballot64(blend);
+                if (bm != 0ull) {
+                    const float ma = wave_max_to_lane63(blend ? e.a : 0.f);
+                    const float mw = wave_max_to_lane63(wgt);
+                    if (lane63) {
+                        const uint32_t g = s_id[k];
+                        atomicAdd(&hits[g], (uint32_t)__popcll(bm));
+                        atomicMax((uint32_t*)&max_alpha[g], __float_as_uint(ma));
+                        atomicMax((uint32_t*)&max_weight[g], __float_as_uint(mw));
+                    }
+                }
+            }
+            if (ballot64(!done) == 0ull) break;
+        }
+    }
+    if (t.inside) {
+        const int64_t HW = (int64_t)t.W * t.H;
+        const int64_t p = (int64_t)t.iy * t.W + t.ix;
+        const int64_t o1 = t.pix_off + p;
+        const int64_t o3 = 3 * t.pix_off + p;
+        if (SHADE) {
+            color[o3] = C0 + T * t.bg[0];
+            color[o3 + HW] = C1 + T * t.bg[1];
+            color[o3 + 2 * HW] = C2 + T * t.bg[2];
+            normal[o3] = N0;
+            normal[o3 + HW] = N1;
+            normal[o3 + 2 * HW] = N2;
+            alpha[o1] = 1.0f - T;
+            // depth = sum w z = S1 + zref S0 ; dist = 2 (S0 S2 - S1^2) with z shifted by zref
+            depth[o1] = __builtin_fmaf(zref, S0, S1);
+            const float dd = 2.0f * (S0 * S2 - S1 * S1);
+            dist[o1] = dd > 0.f ? dd : 0.f;
+            T_final[o1] = T;
+            n_contrib[o1] = last;
+        }
+    }
+}
+
+// Backward: per pixel, walk the tile list back to front from the last
+// blended entry, recovering T_k = T_{k+1} / (1 - a_k).  With g_k the
+// derivative of the loss by the blending weight w_k of entry k and
+// W_k = sum_{j>k} g_j w_j (+ the background term), dL/da_k = T_k g_k -
+// W_k / (1 - a_k).  Per-record gradients are summed over the wavefront with
+// DPP, over the workgroup in LDS, then added to grad_rec with one atomic per
+// (tile, record, component).
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
+             const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+             RasterConsts rc, const float* __restrict__ alpha, const float* __restrict__ depth,
+             const float* __restrict__ dist, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+             const float* __restrict__ dC, const float* __restrict__ dA, const float* __restrict__ dD,
+             const float* __restrict__ dNrm, const float* __restrict__ dDist, float* __restrict__ grad_rec) {
+    constexpr int NT = TW * TH;
+    __shared__ float4 s_g[kGeomF4][NT];
+    __shared__ float4 s_a[kAppF4][NT];
+    __shared__ uint32_t s_rec[NT];
+    __shared__ float s_acc[NT][kNumGrad];
+    __shared__ uint32_t s_maxn;
+    TileCtx t;
+    tile_ctx<TW, TH>(cams, V, ranges, t);
+    const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
+    const int tid = threadIdx.x;
+    const bool lane63 = __lane_id() == 63;
+
+    uint32_t ncon = 0;
+    float T = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gA = 0.f, gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gS = 0.f;
+    float S0 = 0.f, rmean = 0.f, Q = 0.f, Wacc = 0.f;
+    if (t.inside) {
+        const int64_t HW = (int64_t)t.W * t.H;
+        const int64_t p = (int64_t)t.iy * t.W + t.ix;
+        const int64_t o1 = t.pix_off + p, o3 = 3 * t.pix_off + p;
+        ncon = n_contrib[o1];
+        T = T_final[o1];
+        if (dC) { gC0 = dC[o3]; gC1 = dC[o3 + HW]; gC2 = dC[o3 + 2 * HW]; }
+        if (dA) gA = dA[o1];
+        if (dD) gD = dD[o1];
+        if (dNrm) { gN0 = dNrm[o3]; gN1 = dNrm[o3 + HW]; gN2 = dNrm[o3 + 2 * HW]; }
+        if (dDist) gS = dDist[o1];
+        S0 = alpha[o1];
+        if (S0 > 0.f) {
+            rmean = depth[o1] / S0;
+            Q = dist[o1] / (2.0f * S0);
+        }
+        Wacc = (gC0 * t.bg[0] + gC1 * t.bg[1] + gC2 * t.bg[2]) * T;
+    }
+    if (tid == 0) s_maxn = 0u;
+    __syncthreads();
+    atomicMax(&s_maxn, ncon);
+    __syncthreads();
+    const uint32_t maxn = s_maxn;
+    if (maxn == 0u) return;
+
+    for (int64_t base = ((int64_t)(maxn - 1) / NT) * NT; base >= 0; base -= NT) {
+        __syncthreads();
+        const uint32_t j = (uint32_t)base + tid;
+        if (j < maxn) {
+            const uint32_t g = vals[t.start + j];
+            const size_t r = (size_t)t.v * N + g;
+#pragma unroll
+            for (int q = 0; q < kGeomF4; ++q) s_g[q][tid] = geom[kGeomF4 * r + q];
+#pragma unroll
+            for (int q = 0; q < kAppF4; ++q) s_a[q][tid] = app[kAppF4 * r + q];
+            s_rec[tid] = (uint32_t)r;
+        }
+#pragma unroll
+        for (int i = 0; i < kNumGrad; ++i) s_acc[tid][i] = 0.f;
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)NT, maxn - (uint32_t)base);
+        for (int k = cnt - 1; k >= 0; --k) {
+            const uint32_t jj = (uint32_t)base + (uint32_t)k;
+            PairEval e;
+            eval_pair(s_g[0][k], s_g[1][k], s_g[2][k], s_g[3][k], px, py, rc.alpha_max, e);
+            const bool bl = (jj < ncon) && e.pass;
+            float gr[kNumGrad];
+#pragma unroll
+            for (int i = 0; i < kNumGrad; ++i) gr[i] = 0.f;
+            if (bl) {
+                const float4 a0 = s_a[0][k], a1 = s_a[1][k];
+                const float4 g3 = s_g[3][k];
+                const float o = s_g[2][k].w;
+                const float om = 1.0f - e.a;
+                const float rin = 1.0f / om;
+                const float Tk = T * rin;
+                const float wgt = e.a * Tk;
+                const float zr = e.z - rmean;
+                const float gk = gC0 * a0.x + gC1 * a0.y + gC2 * a0.z + gA + gD * e.z +
+                                 gN0 * a0.w + gN1 * a1.x + gN2 * a1.y + gS * 2.0f * (Q + S0 * zr * zr);
+                const float dLda = Tk * gk - Wacc * rin;
+                Wacc = __builtin_fmaf(gk, wgt, Wacc);
+                T = Tk;
+                gr[15] = gC0 * wgt; gr[16] = gC1 * wgt; gr[17] = gC2 * wgt;
+                gr[18] = gN0 * wgt; gr[19] = gN1 * wgt; gr[20] = gN2 * wgt;
+                const float dLdz = wgt * (gD + 4.0f * gS * S0 * zr);
+                float dLdo = 0.f, dLdG = 0.f;
+                if (!e.clamped) {
+                    dLdo = dLda * e.G;
+                    dLdG = dLda * o;
+                }
+                gr[11] = dLdo;
+                const float dLdrho = -e.G * dLdG;
+                if (e.surf) {
+                    const float du = dLdrho * e.u + dLdz * g3.x;
+                    const float dv = dLdrho * e.v + dLdz * g3.y;
+                    gr[12] = dLdz * e.u; gr[13] = dLdz * e.v; gr[14] = dLdz;
+                    const float dw0 = du * e.r, dw1 = dv * e.r;
+                    const float dw2 = -(du * e.u + dv * e.v) * e.r;
+                    gr[0] = dw0 * e.dx; gr[1] = dw1 * e.dx; gr[2] = dw2 * e.dx;
+                    gr[3] = dw0 * e.dy; gr[4] = dw1 * e.dy; gr[5] = dw2 * e.dy;
+                    gr[6] = dw0; gr[7] = dw1; gr[8] = dw2;
+                } else {
+                    gr[9] = -2.0f * dLdrho * e.dx;
+                    gr[10] = -2.0f * dLdrho * e.dy;
+                    gr[14] = dLdz;
+                }
+            }
+            if (ballot64(bl) != 0ull) {
+#pragma unroll
+                for (int i = 0; i < kNumGrad; ++i) {
+                    const float sum = wave_sum_to_lane63(gr[i]);
+                    if (lane63 && sum != 0.f) atomicAdd(&s_acc[k][i], sum);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            float* dst = grad_rec + (size_t)s_rec[tid] * SR_GRAD_STRIDE;
+#pragma unroll
+            for (int i = 0; i < kNumGrad; ++i) {
+                const float vsum = s_acc[tid][i];
+                if (vsum != 0.f) atomicAdd(&dst[i], vsum);
+            }
+        }
+    }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, float v, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_prune_mask(int N, const float* __restrict__ max_alpha, float tau, uint8_t* __restrict__ mask) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < N) mask[g] = max_alpha[g] < tau ? 1 : 0;
+}
+
+template <int TW, int TH>
+hipError_t fwd_dispatch(bool shade, bool stats, int total_tiles, hipStream_t s, const sr_camera* cams, int V,
+                        int N, const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges,
+                        RasterConsts rc, float* color, float* alpha, float* depth, float* normal, float* dist,
+                        float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight) {
+    dim3 grid(total_tiles), block(TW * TH);
+    if (shade && stats)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, true, true>), grid, block, 0, s, cams, V, N, geom, app, vals,
+                           ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
+                           max_weight);
+    else if (shade)
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, true, false>), grid, block, 0, s, cams, V, N, geom, app, vals,
+                           ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
+                           max_weight);
+    else
+        hipLaunchKernelGGL((k_render_fwd<TW, TH, false, true>), grid, block, 0, s, cams, V, N, geom, app, vals,
+                           ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
+                           max_weight);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool tile_shape_supported(int tw, int th) { return tw == 16 && th == 16; }
+
+hipError_t fill_f32(float* p, float v, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
+                             const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
+                             float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
+                             uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
+                             hipStream_t s) {
+    if (total_tiles == 0) return hipSuccess;
+    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+    const bool stats = hits != nullptr;
+    const bool shade = color != nullptr;
+    return fwd_dispatch<16, 16>(shade, stats, total_tiles, s, cams, V, N, (const float4*)geom,
+                                (const float4*)app, vals, (const uint2*)ranges, rc, color, alpha, depth, normal,
+                                dist, T_final, n_contrib, hits, max_alpha, max_weight);
+}
+
+hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
+                             const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
+                             const float* alpha, const float* depth, const float* dist, const float* T_final,
+                             const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
+                             const float* dN, const float* dS, float* grad_rec, hipStream_t s) {
+    if (total_tiles == 0) return hipSuccess;
+    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+    hipLaunchKernelGGL((k_render_bwd<16, 16>), dim3(total_tiles), dim3(256), 0, s, cams, V, N,
+                       (const float4*)geom, (const float4*)app, vals, (const uint2*)ranges, rc, alpha, depth, dist,
+                       T_final, n_contrib, dC, dA, dD, dN, dS, grad_rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, uint8_t* mask, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prune_mask, dim3((N + 255) / 256), dim3(256), 0, s, N, max_alpha, tau, mask);
+    return hipGetLastError();
+}
+
+}  // namespace sr

@@ -1,0 +1,275 @@
+"""Torch-facing wrappers of the C ABI: device buffers, stream plumbing and
+the autograd.Function.  PyTorch only provides memory and streams; every
+step of the hot path runs in libsurfelrast.so.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SrCamera, SrConfig, call
+
+ALPHA_MIN = float(np.float32(1.0 / 255.0))
+ALPHA_MAX = float(np.float32(0.99))
+T_MIN = float(np.float32(1e-4))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_config(sh_degree: int = 0, sh_stride: Optional[int] = None, tile=(16, 16), flags: int = 0,
+                alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, t_min=T_MIN) -> SrConfig:
+    K = (sh_degree + 1) ** 2
+    return SrConfig(tile[0], tile[1], sh_degree, K if sh_stride is None else sh_stride,
+                    alpha_min, alpha_max, t_min, flags)
+
+
+class ViewBatch:
+    """V cameras laid out for one tile shape: a host array (launch geometry)
+    and a byte-identical device copy (read by the kernels)."""
+
+    def __init__(self, cams: Sequence, tile=(16, 16), device="cuda"):
+        V = len(cams)
+        arr = (SrCamera * max(V, 1))()
+        for v, c in enumerate(cams):
+            d = arr[v]
+            vm = np.asarray(c.viewmat, np.float32).reshape(-1)
+            for i in range(12):
+                d.viewmat[i] = float(vm[i])
+            d.fx, d.fy, d.cx, d.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+            for i in range(3):
+                d.campos[i] = float(c.campos[i])
+                d.bg[i] = float(np.asarray(c.bg)[i])
+            d.znear = float(c.znear)
+            d.width, d.height = int(c.width), int(c.height)
+        P = ctypes.c_int64(0)
+        T = ctypes.c_int32(0)
+        call("sr_layout_views", ctypes.cast(arr, ctypes.c_void_p), V, tile[0], tile[1], ctypes.byref(P),
+             ctypes.byref(T))
+        self.host = arr
+        self.V = V
+        self.P = int(P.value)
+        self.T = int(T.value)
+        self.tile = tuple(tile)
+        self.sizes = [(int(c.width), int(c.height)) for c in cams]
+        self.pix_offsets = [int(arr[v].pix_offset) for v in range(V)]
+        raw = bytes(memoryview(arr).cast("B"))[: 128 * V] if V else b""
+        self.dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device) if V else \
+            torch.zeros(128, dtype=torch.uint8, device=device)
+
+    @property
+    def host_ptr(self):
+        return ctypes.cast(self.host, ctypes.c_void_p)
+
+    def view_slice(self, v: int, channels: int = 1):
+        W, H = self.sizes[v]
+        o = self.pix_offsets[v]
+        return slice(channels * o, channels * (o + W * H))
+
+
+@dataclass
+class Params:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opac: torch.Tensor
+    sh: torch.Tensor
+
+    @staticmethod
+    def from_scene(scene, device="cuda"):
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=device)
+        return Params(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opac), f(scene.sh))
+
+
+class Rasterizer:
+    """Persistent device buffers for one (N, views, tile shape, capacity).
+
+    preprocess -> bin -> forward -> (loss) -> backward, each one C-ABI call
+    on the current torch stream; no host synchronisation except
+    ``plan_capacity`` and ``status``.
+    """
+
+    def __init__(self, N: int, views: ViewBatch, sh_degree: int, sh_stride: Optional[int] = None,
+                 capacity: int = 0, device="cuda", shade: bool = True):
+        self.N, self.views, self.device = int(N), views, device
+        self.cfg = make_config(sh_degree, sh_stride, views.tile)
+        self.shade = shade
+        V, P, T = views.V, views.P, views.T
+        VN = V * self.N
+        i32, f32 = torch.int32, torch.float32
+        z = lambda n, dt: torch.zeros(max(int(n), 1), dtype=dt, device=device)
+        self.geom = z(VN * _lib.SR_GEOM_STRIDE, f32)
+        self.app = z(VN * _lib.SR_APP_STRIDE, f32) if shade else None
+        self.rect = z(VN * 4, torch.int16)
+        self.tiles_touched = z(VN, i32)
+        self.depth_key = z(VN, i32)
+        self.in_frustum = z(self.N, torch.uint8)
+        self.ranges = z(2 * T, i32)
+        self.counters = z(_lib.SR_COUNTERS, i32)
+        # forward outputs / saved state
+        self.color = z(3 * P, f32)
+        self.alpha = z(P, f32)
+        self.depth = z(P, f32)
+        self.normal = z(3 * P, f32)
+        self.dist = z(P, f32)
+        self.T_final = z(P, f32)
+        self.n_contrib = z(P, i32)
+        self.grad_rec = None
+        self.loss_ws = z(_lib.workspace_bytes_loss(V, views.host), torch.uint8) if V else z(1, torch.uint8)
+        self.loss_out = z(2 * max(V, 1) + 1, f32)
+        self.capacity = 0
+        self.set_capacity(capacity)
+
+    # -- capacity ---------------------------------------------------------
+    def set_capacity(self, cap: int):
+        cap = int(cap)
+        if cap == self.capacity and getattr(self, "ws", None) is not None:
+            return
+        self.capacity = cap
+        self.vals = torch.zeros(max(cap, 1), dtype=torch.int32, device=self.device)
+        ws = _lib.workspace_bytes_bin(self.N, self.views.V, cap)
+        self.ws = torch.zeros(max(ws, 1), dtype=torch.uint8, device=self.device)
+        self.ws_bytes = ws
+
+    def plan_capacity(self, params: Params, slack: float = 1.05) -> int:
+        """Projects once and sizes the instance buffers (one host sync)."""
+        self.preprocess(params)
+        need = int(self.tiles_touched.to(torch.int64).sum().item())
+        self.set_capacity(int(need * slack) + 1024)
+        return need
+
+    # -- steps ------------------------------------------------------------
+    def preprocess(self, p: Params, stream=None):
+        call("sr_preprocess", ctypes.byref(self.cfg), self.N, _ptr(p.means), _ptr(p.scales), _ptr(p.quats),
+             _ptr(p.opac), _ptr(p.sh), self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.geom),
+             _ptr(self.app) if self.shade else None, _ptr(self.rect), _ptr(self.tiles_touched),
+             _ptr(self.depth_key), _ptr(self.in_frustum), _stream(stream))
+
+    def bin(self, keys64: Optional[torch.Tensor] = None, stream=None):
+        call("sr_bin_and_sort", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key),
+             _ptr(self.ws), self.ws_bytes, self.capacity, _ptr(self.vals), _ptr(keys64), _ptr(self.ranges),
+             _ptr(self.counters), _stream(stream))
+
+    def forward(self, stats=None, stream=None):
+        h, ma, mw = (None, None, None) if stats is None else stats
+        call("sr_render_forward", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
+             _ptr(self.color), _ptr(self.alpha), _ptr(self.depth), _ptr(self.normal), _ptr(self.dist),
+             _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw), _stream(stream))
+
+    def backward(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None):
+        if self.grad_rec is None:
+            self.grad_rec = torch.zeros(max(self.views.V * self.N * _lib.SR_GRAD_STRIDE, 1),
+                                        dtype=torch.float32, device=self.device)
+        call("sr_render_backward", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.opac), _ptr(p.sh),
+             _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(self.alpha),
+             _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(dC), _ptr(dA),
+             _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self.grad_rec), _ptr(grads.means), _ptr(grads.scales),
+             _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _stream(stream))
+
+    def loss(self, mask: torch.Tensor, target: Optional[torch.Tensor], gamma: float = 0.5, w_c: float = 1.0,
+             dL_dalpha: Optional[torch.Tensor] = None, dL_dcolor: Optional[torch.Tensor] = None, stream=None):
+        call("sr_background_loss", self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.alpha),
+             _ptr(mask), _ptr(self.color) if target is not None else None, _ptr(target), float(gamma), float(w_c),
+             _ptr(self.loss_ws), self.loss_ws.numel(), _ptr(self.loss_out), _ptr(dL_dalpha), _ptr(dL_dcolor),
+             _stream(stream))
+        return self.loss_out
+
+    def prune_stats(self, hits, max_alpha, max_weight, accumulate=False, stream=None):
+        cfg = SrConfig.from_buffer_copy(self.cfg)
+        cfg.flags |= _lib.SR_FLAG_ACCUMULATE if accumulate else 0
+        call("sr_prune_contrib", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.vals), _ptr(self.ranges), _ptr(hits),
+             _ptr(max_alpha), _ptr(max_weight), _stream(stream))
+
+    def status(self):
+        """(visible pairs, instances needed, instances stored, status) - syncs."""
+        c = self.counters.cpu().numpy().view(np.uint32)
+        return int(c[0]), int(c[1]), int(c[2]), int(c[3])
+
+    def check_capacity(self):
+        vis, need, stored, st = self.status()
+        if st != 0:
+            raise _lib.SurfelRasterError(_lib.SR_ERR_CAPACITY,
+                                         f"instance capacity {self.capacity} exceeded: {need} needed")
+        return need
+
+
+def prune_mask(max_alpha: torch.Tensor, tau: float = ALPHA_MIN, stream=None) -> torch.Tensor:
+    out = torch.empty(max_alpha.numel(), dtype=torch.uint8, device=max_alpha.device)
+    call("sr_prune_mask", max_alpha.numel(), _ptr(max_alpha), float(tau), _ptr(out), _stream(stream))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# autograd
+# ----------------------------------------------------------------------------
+
+class SurfelRasterize(torch.autograd.Function):
+    """(means, scales, quats, opac, sh) -> packed (color [3P], alpha [P],
+    depth [P], normal [3P], dist [P]) for the views of ``rast``.  The
+    rasterizer's buffers hold the saved state: call backward before the next
+    forward through the same Rasterizer."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True):
+        p = Params(means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
+                   opac.detach().contiguous(), sh.detach().contiguous())
+        rast.preprocess(p)
+        rast.bin()
+        if check:
+            rast.check_capacity()
+        rast.forward()
+        ctx.rast = rast
+        ctx.p = p
+        return (rast.color.clone(), rast.alpha.clone(), rast.depth.clone(), rast.normal.clone(),
+                rast.dist.clone())
+
+    @staticmethod
+    def backward(ctx, gC, gA, gD, gN, gS):
+        p, rast = ctx.p, ctx.rast
+        g = Params(torch.zeros_like(p.means), torch.zeros_like(p.scales), torch.zeros_like(p.quats),
+                   torch.zeros_like(p.opac), torch.zeros_like(p.sh))
+        c = lambda t: None if t is None else t.contiguous()
+        rast.backward(p, g, c(gC), c(gA), c(gD), c(gN), c(gS))
+        return g.means, g.scales, g.quats, g.opac, g.sh, None, None
+
+
+def rasterize(means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True):
+    return SurfelRasterize.apply(means, scales, quats, opac, sh, rast, check)
+
+
+class BackgroundLoss(torch.autograd.Function):
+    """Masked losses (Eq. 1 and the L1 part of Eq. 2) of all views:
+    returns (1/V) sum_v (w_c L1_v + gamma L_b,v) and the per-view terms."""
+
+    @staticmethod
+    def forward(ctx, alpha, color, target, mask, views: ViewBatch, gamma: float, w_c: float, ws):
+        V = views.V
+        loss = torch.zeros(2 * V + 1, dtype=torch.float32, device=alpha.device)
+        dA = torch.empty_like(alpha)
+        dC = torch.empty_like(color) if target is not None else None
+        call("sr_background_loss", V, views.host_ptr, _ptr(views.dev), _ptr(alpha.contiguous()), _ptr(mask),
+             _ptr(color.contiguous()) if target is not None else None, _ptr(target), float(gamma), float(w_c),
+             _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dC), _stream())
+        ctx.save_for_backward(dA, dC if dC is not None else torch.zeros(0, device=alpha.device))
+        ctx.has_c = dC is not None
+        return loss[2 * V], loss[: 2 * V]
+
+    @staticmethod
+    def backward(ctx, g_total, g_loss):
+        dA, dC = ctx.saved_tensors
+        return (dA * g_total, (dC * g_total) if ctx.has_c else None, None, None, None, None, None, None)

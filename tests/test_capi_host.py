@@ -1,0 +1,85 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and its host-only entry points validate arguments."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "surfelrast.h")
+
+
+def _header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sr_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2501_08174_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsurfelrast.so is not built (run python -m paper_2501_08174_amd.build)")
+    return _lib
+
+
+def test_header_symbols_exported(lib):
+    names = _header_functions()
+    assert len(names) >= 13
+    l = lib.lib()
+    for n in names:
+        assert hasattr(l, n), n
+    assert set(names) == set(lib.EXPORTED)
+
+
+def test_layout_views_and_validation(lib):
+    from paper_2501_08174_amd._lib import SrCamera
+    cams = (SrCamera * 3)()
+    for c, (w, h) in zip(cams, [(40, 21), (33, 48), (1, 1)]):
+        c.width, c.height, c.fx, c.fy = w, h, 10.0, 10.0
+    P = ctypes.c_int64()
+    T = ctypes.c_int32()
+    lib.call("sr_layout_views", ctypes.cast(cams, ctypes.c_void_p), 3, 16, 16, ctypes.byref(P), ctypes.byref(T))
+    assert P.value == 40 * 21 + 33 * 48 + 1
+    assert T.value == 3 * 2 + 3 * 3 + 1
+    assert [c.tile_offset for c in cams] == [0, 6, 15]
+    assert [c.pix_offset for c in cams] == [0, 840, 840 + 1584]
+    bad = (SrCamera * 1)()
+    bad[0].width, bad[0].height = 0, 5
+    with pytest.raises(lib.SurfelRasterError) as e:
+        lib.call("sr_layout_views", ctypes.cast(bad, ctypes.c_void_p), 1, 16, 16, None, None)
+    assert e.value.code == lib.SR_ERR_ARG
+    assert "size" in str(e.value)
+
+
+def test_argument_errors_before_launch(lib):
+    """Invalid configurations are rejected on the host (no device touched)."""
+    from paper_2501_08174_amd._lib import SrConfig
+    l = lib.lib()
+    cfg = SrConfig(8, 8, 0, 1, 1 / 255, 0.99, 1e-4, 0)
+    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+                           None, None, None, None) == lib.SR_ERR_UNSUPPORTED
+    assert l.sr_tile_supported(16, 16) == 1 and l.sr_tile_supported(7, 3) == 0
+    cfg = SrConfig(16, 16, 4, 25, 1 / 255, 0.99, 1e-4, 0)
+    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+                           None, None, None, None) == lib.SR_ERR_UNSUPPORTED
+    cfg = SrConfig(16, 16, 3, 9, 1 / 255, 0.99, 1e-4, 0)
+    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+                           None, None, None, None) == lib.SR_ERR_ARG
+    cfg = SrConfig(16, 16, 0, 1, 0.5, 0.4, 1e-4, 0)
+    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+                           None, None, None, None) == lib.SR_ERR_ARG
+    cfg = SrConfig(16, 16, 0, 1, 1 / 255, 0.99, 1e-4, 0)
+    assert l.sr_preprocess(ctypes.byref(cfg), -1, None, None, None, None, None, 0, None, None, None, None, None,
+                           None, None, None, None) == lib.SR_ERR_ARG
+    # N = 0 and V = 0 are valid no-ops
+    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+                           None, None, None, None) == lib.SR_OK
+    n = ctypes.c_size_t()
+    assert l.sr_bin_workspace_size(1000, 4, 12345, ctypes.byref(n)) == lib.SR_OK and n.value > 0
+    assert l.sr_bin_workspace_size(-5, 4, 12345, ctypes.byref(n)) == lib.SR_ERR_ARG
+    # workspace too small is an argument error
+    counters = ctypes.c_void_p(8)
+    assert l.sr_bin_and_sort(ctypes.byref(cfg), 10, 0, None, None, None, None, None, None, 0, 100, None, None,
+                             None, counters, None) == lib.SR_ERR_ARG

@@ -1,0 +1,287 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on small
+and ragged scenes: bit-exact binning, forward outputs within 1e-4, gradients
+within 1e-3 relative, losses, pruning statistics, batched vs per-view."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.render import Params64, render_pixels
+from paper_2501_08174_amd import scenes
+from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch, rasterize, prune_mask
+from tests.gpu_helpers import (compare_binning, compare_forward, crop_pixels, geometry, gpu_run, per_view)
+
+pytestmark = pytest.mark.gpu
+
+RP = oracle.RasterParams()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _full(cam):
+    return crop_pixels(0, 0, cam.width, cam.height)
+
+
+def _ragged_scene(seed=31, n=300, deg=0):
+    return scenes.make_random_scene(seed, n, n_views=3, width=[61, 40, 17], height=[37, 64, 90],
+                                    sh_degree=deg, scale_range=(0.02, 0.3))
+
+
+# --------------------------------------------------------------------------
+# binning
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make", [lambda: _ragged_scene(), lambda: scenes.make_config1(),
+                                  lambda: scenes.make_random_scene(32, 2000, n_views=2, width=[100, 129],
+                                                                   height=[77, 50], scale_range=(0.01, 0.6))])
+def test_binning_bit_exact(make):
+    sc = make()
+    run = gpu_run(sc, keys64=True)
+    geoms = geometry(sc)
+    exempt = compare_binning(sc, run, geoms)
+    print(f"binning exact; grid-tie exemptions: {exempt}")
+    assert exempt == 0
+
+
+# --------------------------------------------------------------------------
+# forward
+# --------------------------------------------------------------------------
+
+def test_forward_config1_full_frame():
+    sc = scenes.make_config1()
+    run = gpu_run(sc)
+    geoms = geometry(sc)
+    pix = _full(sc.cams[0])
+    res = render_pixels(Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0), sc.cams[0],
+                        geoms[0], pix, RP)
+    errs, flagged = compare_forward(per_view(run["rast"], 0), res, pix, run["rast"], 0)
+    print("config1 errors", errs, "flagged", flagged)
+    assert flagged < 1e-2
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_forward_multiview_ragged(deg):
+    sc = _ragged_scene(33, 400, deg)
+    run = gpu_run(sc)
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, deg)
+    for v, cam in enumerate(sc.cams):
+        pix = _full(cam)
+        res = render_pixels(P64, cam, geoms[v], pix, RP)
+        errs, flagged = compare_forward(per_view(run["rast"], v), res, pix, run["rast"], v)
+        print(f"view {v} errors {errs} flagged {flagged}")
+
+
+def test_batched_equals_per_view_bitwise():
+    sc = _ragged_scene(34, 500, 3)
+    run = gpu_run(sc)
+    for v in range(sc.v):
+        one = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree, [sc.cams[v]],
+                           [sc.masks[v]])
+        r1 = gpu_run(one)
+        a, b = per_view(run["rast"], v), per_view(r1["rast"], 0)
+        for k in ("color", "alpha", "depth", "normal", "dist", "T_final", "n_contrib"):
+            np.testing.assert_array_equal(a[k], b[k], err_msg=f"view {v} {k}")
+
+
+# --------------------------------------------------------------------------
+# backward
+# --------------------------------------------------------------------------
+
+def _weights(sc, rng):
+    w = []
+    for c in sc.cams:
+        n = c.width * c.height
+        w.append({"c": rng.normal(size=(n, 3)), "a": rng.normal(size=n), "d": rng.normal(size=n) * 0.3,
+                  "n": rng.normal(size=(n, 3)), "s": rng.normal(size=n)})
+    return w
+
+
+def _gpu_grads(sc, w):
+    views = ViewBatch(sc.cams)
+    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1])
+    p = Params.from_scene(sc)
+    rast.plan_capacity(p)
+    leaves = [t.clone().requires_grad_(True) for t in (p.means, p.scales, p.quats, p.opac, p.sh)]
+    color, alpha, depth, normal, dist = rasterize(*leaves, rast)
+    P = views.P
+    gc = torch.zeros(3 * P, device="cuda")
+    ga, gd, gn, gs = (torch.zeros(P, device="cuda"), torch.zeros(P, device="cuda"),
+                      torch.zeros(3 * P, device="cuda"), torch.zeros(P, device="cuda"))
+    for v, c in enumerate(sc.cams):
+        n = c.width * c.height
+        o = views.pix_offsets[v]
+        f = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+        gc[3 * o: 3 * (o + n)] = f(w[v]["c"].T.reshape(-1))
+        gn[3 * o: 3 * (o + n)] = f(w[v]["n"].T.reshape(-1))
+        ga[o: o + n] = f(w[v]["a"])
+        gd[o: o + n] = f(w[v]["d"])
+        gs[o: o + n] = f(w[v]["s"])
+    L = (color * gc).sum() + (alpha * ga).sum() + (depth * gd).sum() + (normal * gn).sum() + (dist * gs).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    return [t.grad.cpu().numpy().astype(np.float64) for t in leaves]
+
+
+def _oracle_grads(sc, w, geoms):
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree, requires_grad=True)
+    flagged = []
+    for v, cam in enumerate(sc.cams):
+        pix = _full(cam)
+        wt = {k: torch.tensor(a) for k, a in w[v].items()}
+
+        def lf(out, rows, wt=wt):
+            r = torch.as_tensor(rows)
+            return ((out["color"] * wt["c"][r]).sum() + (out["alpha"] * wt["a"][r]).sum() +
+                    (out["depth"] * wt["d"][r]).sum() + (out["normal"] * wt["n"][r]).sum() +
+                    (out["dist"] * wt["s"][r]).sum())
+        res = render_pixels(P64, cam, geoms[v], pix, RP, loss_fn=lf)
+        flagged.append(res["flag_ids"])
+    return P64.grads(), np.unique(np.concatenate(flagged))
+
+
+def _compare_grads(g, gref, excl, names=("means", "scales", "quats", "opac", "sh"), rtol=1e-3):
+    report = {}
+    for name, a, b in zip(names, g, gref):
+        keep = np.ones(a.shape[0], bool)
+        keep[excl] = False
+        a, b = a[keep].reshape(-1), b[keep].reshape(-1)
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max()
+        big = np.abs(b) >= 1e-2 * scale
+        rel = (np.abs(a - b)[big] / np.abs(b)[big]).max() if big.any() else 0.0
+        report[name] = (float(err / max(scale, 1e-30)), float(rel))
+    print("gradient errors (inf-norm relative, elementwise relative):", report)
+    for name, (e, r) in report.items():
+        assert e <= rtol, f"{name}: inf-norm relative error {e:.2e}"
+        assert r <= 10 * rtol, f"{name}: elementwise relative error {r:.2e}"
+    return report
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_backward_matches_oracle_autograd(deg):
+    sc = scenes.make_random_scene(40 + deg, 150, n_views=2, width=[48, 37], height=[40, 51], sh_degree=deg,
+                                  spread=0.6, scale_range=(0.03, 0.3))
+    rng = np.random.default_rng(7)
+    w = _weights(sc, rng)
+    g = _gpu_grads(sc, w)
+    gref, excl = _oracle_grads(sc, w, geometry(sc))
+    print("excluded surfels (touch a flagged pixel):", len(excl))
+    _compare_grads(g, gref, excl)
+
+
+# --------------------------------------------------------------------------
+# losses (Eq. 1, Eq. 2)
+# --------------------------------------------------------------------------
+
+def test_background_and_masked_l1_loss():
+    sc = _ragged_scene(35, 300, 0)
+    run = gpu_run(sc)
+    rast = run["rast"]
+    views = rast.views
+    rng = np.random.default_rng(3)
+    masks = [rng.integers(0, 2, size=(c.height, c.width)).astype(np.uint8) for c in sc.cams]
+    targets = [rng.uniform(size=(3, c.height, c.width)).astype(np.float32) for c in sc.cams]
+    mask = torch.tensor(np.concatenate([m.reshape(-1) for m in masks]), device="cuda")
+    target = torch.tensor(np.concatenate([t.reshape(-1) for t in targets]), device="cuda")
+    dA = torch.zeros_like(rast.alpha)
+    dC = torch.zeros_like(rast.color)
+    loss = rast.loss(mask, target, gamma=0.5, w_c=1.0, dL_dalpha=dA, dL_dcolor=dC)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy()
+    V = sc.v
+    tot = 0.0
+    for v, c in enumerate(sc.cams):
+        pv = per_view(rast, v)
+        lb = oracle.background_loss64(pv["alpha"], masks[v])
+        l1 = oracle.masked_l1_64(pv["color"], targets[v], masks[v])
+        assert abs(loss[v] - lb) <= 1e-6 * max(1, lb)
+        assert abs(loss[V + v] - l1) <= 1e-6 * max(1, l1)
+        tot += (l1 + 0.5 * lb) / V
+        HW = c.width * c.height
+        o = views.pix_offsets[v]
+        np.testing.assert_allclose(dA[o:o + HW].cpu().numpy(), 0.5 * (1 - masks[v].reshape(-1)) / (HW * V),
+                                   rtol=1e-6)
+        d = pv["color"] * masks[v][None] - targets[v] * masks[v][None]
+        np.testing.assert_allclose(dC[3 * o:3 * (o + HW)].cpu().numpy(), (np.sign(d) / (3 * HW * V)).reshape(-1),
+                                   rtol=1e-6)
+    assert abs(loss[2 * V] - tot) <= 1e-6
+
+
+# --------------------------------------------------------------------------
+# occlusion-aware pruning (Section 4.3)
+# --------------------------------------------------------------------------
+
+def test_prune_stats_match_oracle():
+    sc = _ragged_scene(36, 600, 0)
+    run = gpu_run(sc, stats=True)
+    hits, ma, mw = (t.cpu().numpy() for t in run["stats"])
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0)
+    pairs, tie_ids = [], []
+    for v, cam in enumerate(sc.cams):
+        res = render_pixels(P64, cam, geoms[v], _full(cam), RP)
+        pairs.append(res["pairs"])
+        tie_ids.append(res["flag_ids"])
+    st = oracle.prune_stats64(sc.n, pairs, [g["culled"] for g in geoms])
+    keep = np.ones(sc.n, bool)
+    keep[np.unique(np.concatenate(tie_ids))] = False
+    np.testing.assert_array_equal(hits.view(np.uint32)[keep], st["hits"][keep])
+    np.testing.assert_allclose(ma[keep], st["max_alpha"][keep], atol=1e-5)
+    np.testing.assert_allclose(mw[keep], st["max_weight"][keep], atol=1e-5)
+    mask = prune_mask(run["stats"][1]).cpu().numpy().astype(bool)
+    np.testing.assert_array_equal(mask[keep], st["prune"][keep])
+    inf = run["rast"].in_frustum[: sc.n].cpu().numpy().astype(bool)
+    np.testing.assert_array_equal(inf, st["in_frustum"])
+    print(f"pruned {mask.sum()} of {sc.n}; exempt {(~keep).sum()}")
+
+
+def test_prune_occluded_surfel_scene():
+    from tests.oracle_scenes import front_camera, scene_from
+    ID = [1.0, 0.0, 0.0, 0.0]
+    cam = front_camera(40)
+    means = [[0, 0, 0.0], [0, 0, 0.05], [0, 0, 0.1], [0, 0, 0.5], [0, 0, -5.0], [30.0, 0, 0.5],
+             [0.2, 0.1, -0.5]]
+    sc = scene_from(means, [(5, 5)] * 3 + [(0.2, 0.2)] * 4, [ID] * 7, [0.99, 0.99, 0.99, 0.9, 0.9, 0.9, 0.002],
+                    [(1, 1, 1)] * 7, [cam])
+    run = gpu_run(sc, stats=True)
+    hits = run["stats"][0].cpu().numpy()
+    inf = run["rast"].in_frustum[:7].cpu().numpy()
+    assert list(inf) == [1, 1, 1, 1, 0, 0, 0]
+    assert all(hits[:3] > 0) and hits[3] == 0 and all(hits[4:] == 0)
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+
+def test_edge_cases_empty_and_tiny():
+    from tests.oracle_scenes import front_camera, scene_from
+    ID = [1.0, 0.0, 0.0, 0.0]
+    # every surfel culled: background everywhere, no instances
+    cam = front_camera(20)
+    cam.bg = np.array([0.25, 0.5, 0.75], np.float32)
+    sc = scene_from([[0, 0, -6.0], [0, 0, -4.1]], [(0.1, 0.1)] * 2, [ID] * 2, [0.9, 0.9], [(1, 1, 1)] * 2, [cam])
+    run = gpu_run(sc, capacity=16)
+    pv = per_view(run["rast"], 0)
+    assert run["status"] == (0, 0, 0, 0)
+    assert np.all(pv["alpha"] == 0) and np.all(pv["n_contrib"] == 0)
+    np.testing.assert_array_equal(pv["color"], np.broadcast_to(cam.bg[:, None, None], pv["color"].shape))
+    # 1x1 and 1xH views next to a regular one
+    sc = scenes.make_random_scene(37, 50, n_views=3, width=[1, 1, 33], height=[1, 29, 18],
+                                  scale_range=(0.1, 0.5))
+    run = gpu_run(sc, keys64=True)
+    compare_binning(sc, run, geometry(sc))
+
+
+def test_capacity_overflow_is_reported():
+    sc = scenes.make_config1()
+    run = gpu_run(sc, capacity=100)
+    vis, need, stored, status = run["status"]
+    assert status == 1 and stored == 100 and need > 100
+    with pytest.raises(Exception):
+        run["rast"].check_capacity()
