@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tile", default="auto", help="WxH tile shape, or 'auto' to pick by timing")
     return ap.parse_args()
 
 
@@ -54,10 +55,10 @@ def make_scene(name):
 class Pipeline:
     """Persistent buffers and one training step over a set of views."""
 
-    def __init__(self, scene, cams, masks, targets, params, grads, stats):
+    def __init__(self, scene, cams, masks, targets, params, grads, stats, tile=(16, 16)):
         import torch
         from paper_2501_08174_amd.raster import Rasterizer, ViewBatch
-        self.views = ViewBatch(cams)
+        self.views = ViewBatch(cams, tile=tile)
         self.rast = Rasterizer(scene.n, self.views, scene.sh_degree, sh_stride=scene.sh.shape[1])
         self.p, self.g, self.stats = params, grads, stats
         self.mask = torch.tensor(np.concatenate([m.reshape(-1) for m in masks]), device="cuda")
@@ -65,6 +66,8 @@ class Pipeline:
         self.dA = torch.zeros_like(self.rast.alpha)
         self.dC = torch.zeros_like(self.rast.color)
         self.need = self.rast.plan_capacity(params, slack=1.02)
+
+    STAGES = ("preprocess", "bin_sort", "forward+stats", "loss", "backward_raster", "backward_project")
 
     def step(self, ev=None):
         r = self.rast
@@ -74,25 +77,14 @@ class Pipeline:
         rec(1)
         r.bin()
         rec(2)
-        r.forward(stats=self.stats)
+        r.forward(stats=self.stats, accumulate=True)
         rec(3)
         r.loss(self.mask, self.target, 0.5, 1.0, self.dA, self.dC)
         rec(4)
-        r.backward(self.p, self.g, dC=self.dC, dA=self.dA)
+        r.backward_raster(dC=self.dC, dA=self.dA)
         rec(5)
-
-
-def count_pairs(pipe):
-    """Reached (tested before termination) and blended pairs of the forward,
-    counted with a forward over the same data in counting mode."""
-    import torch
-    from paper_2501_08174_amd import _lib
-    r = pipe.rast
-    out = torch.zeros(4, dtype=torch.int64, device="cuda")
-    fn = getattr(_lib.lib(), "sr_debug_count_pairs", None)
-    if fn is None:
-        return None, None
-    return None, None
+        r.backward_project(self.p, self.g)
+        rec(6)
 
 
 def cpu_baseline(scene, seconds_budget=20.0):
@@ -142,7 +134,18 @@ def main():
                                                    params.sh)])
     stats = (torch.zeros(N, dtype=torch.int32, device="cuda"), torch.zeros(N, device="cuda"),
              torch.zeros(N, device="cuda"))
-    pipe = Pipeline(scene, scene.cams, scene.masks, scene.targets, params, grads, stats)
+    tune = {}
+    if args.tile == "auto":
+        from paper_2501_08174_amd.autotune import autotune
+        mask = torch.tensor(np.concatenate([m.reshape(-1) for m in scene.masks]), device="cuda")
+        target = torch.tensor(np.concatenate([t.reshape(-1) for t in scene.targets]), device="cuda")
+        tile = autotune(scene.cams, params, scene.sh_degree, scene.sh.shape[1], mask, target, use_cache=False,
+                        report=tune)
+        del mask, target
+        torch.cuda.empty_cache()
+    else:
+        tile = tuple(int(x) for x in args.tile.split("x"))
+    pipe = Pipeline(scene, scene.cams, scene.masks, scene.targets, params, grads, stats, tile)
     P = pipe.views.P
 
     for _ in range(args.warmup):
@@ -152,14 +155,15 @@ def main():
     assert status == 0, "instance capacity exceeded"
 
     # timed region: K eager steps with per-stage events
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    ns = len(Pipeline.STAGES)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         pipe.step(ev[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stage_ms = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(5)] for k in range(args.steps)])
+    stage_ms = np.array([[ev[k][i].elapsed_time(ev[k][i + 1]) for i in range(ns)] for k in range(args.steps)])
     step_ms = stage_ms.sum(axis=1)
     ms_per_step = wall / args.steps * 1e3
 
@@ -172,14 +176,34 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {V} views, {P} px, {N} surfels, SH degree {scene.sh_degree}",
-                   "views": V, "pixels": P, "surfels": N, "mode": "batched"},
+                   "views": V, "pixels": P, "surfels": N, "mode": "batched", "tile": f"{tile[0]}x{tile[1]}"},
+        "autotune_ms": tune.get("ms"),
         "views_per_s": V / (ms_per_step * 1e-3),
         "median_step_ms_events": float(np.median(step_ms)),
-        "stage_ms_median": dict(zip(["preprocess", "bin_sort", "forward+stats", "loss", "backward"],
-                                    [float(x) for x in np.median(stage_ms, axis=0)])),
+        "stage_ms_mean": dict(zip(Pipeline.STAGES, [float(x) for x in stage_ms.mean(axis=0)])),
         "counts": {"visible_pairs": vis, "instances": need},
         "scene_gen_s": t_gen,
     }
+
+    # work accounting for the roofline (outside the timed region)
+    R, B = pipe.rast.count_pairs()
+    R_bwd = int(pipe.rast.n_contrib[:P].to(torch.int64).sum().item())
+    mean_ms = dict(zip(Pipeline.STAGES, stage_ms.mean(axis=0)))
+    fwd_ops = FWD_OPS_BLEND * B + FWD_OPS_SKIP * (R - B)
+    bwd_ops = BWD_OPS_BLEND * B + BWD_OPS_SKIP * max(R_bwd - B, 0)
+    roof = {
+        "forward": {"bound": "alu", "achieved": fwd_ops / (mean_ms["forward+stats"] * 1e-3) / 1e12,
+                    "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s"},
+        "backward_raster": {"bound": "alu", "achieved": bwd_ops / (mean_ms["backward_raster"] * 1e-3) / 1e12,
+                            "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s"},
+    }
+    for k, r in roof.items():
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = None
+    dom = max(roof, key=lambda k: mean_ms["forward+stats" if k == "forward" else k])
+    result["roofline"] = dict(roof[dom], kernel=dom)
+    result["roofline_all"] = roof
+    result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd})
 
     if not args.no_graph:
         g = torch.cuda.CUDAGraph()
@@ -202,7 +226,7 @@ def main():
     if not args.no_per_view:
         pipes = []
         for v in range(V):
-            pv = Pipeline(scene, [scene.cams[v]], [scene.masks[v]], [scene.targets[v]], params, grads, stats)
+            pv = Pipeline(scene, [scene.cams[v]], [scene.masks[v]], [scene.targets[v]], params, grads, stats, tile)
             pipes.append(pv)
         for _ in range(args.warmup):
             for pv in pipes:

@@ -159,7 +159,8 @@ sr_status sr_render_forward(const sr_config *cfg, int32_t N, int32_t V, const sr
  * 3.1: position, shape and appearance are updated by backpropagation).
  * Recomputes the forward back to front from T_final and n_contrib.
  * dL_d* are the upstream gradients of the five forward outputs (any may be
- * NULL = zero).  grad_rec [V*N, 24] is scratch (cleared by the call).
+ * NULL = zero).  grad_rec [V*N, 24] is scratch (cleared by the call, and
+ * left zero).
  * The parameter gradients are ACCUMULATED (+=) into g_means [N,3],
  * g_scales [N,2], g_quats [N,4], g_opac [N], g_sh [N,sh_stride,3]. */
 sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
@@ -172,6 +173,27 @@ sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const s
                              const float *dL_dnormal, const float *dL_ddist, float *grad_rec,
                              float *g_means, float *g_scales, float *g_quats, float *g_opac,
                              float *g_sh, void *stream);
+
+/* The two halves of sr_render_backward, one kernel each.
+ * sr_backward_raster: the compositing backward only; ADDS the per-record
+ * gradients to grad_rec [V*N, 24], which must hold zeros on entry (as left
+ * by sr_backward_project or a fresh zeroed buffer).
+ * sr_backward_project: chains grad_rec to the parameter gradients (+=),
+ * summed over the views, and zeroes every grad_rec record it consumed, so
+ * the buffer is ready for the next step.  tiles_touched (from
+ * sr_preprocess) lets it skip culled records; NULL scans every record. */
+sr_status sr_backward_raster(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                             const sr_camera *cams_dev, const float *geom, const float *app,
+                             const uint32_t *vals, const uint32_t *ranges, const float *alpha,
+                             const float *depth, const float *dist, const float *T_final,
+                             const uint32_t *n_contrib, const float *dL_dcolor, const float *dL_dalpha,
+                             const float *dL_ddepth, const float *dL_dnormal, const float *dL_ddist,
+                             float *grad_rec, void *stream);
+sr_status sr_backward_project(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                              const sr_camera *cams_dev, const float *means, const float *scales,
+                              const float *quats, const float *sh, const float *geom, const float *app,
+                              const uint32_t *tiles_touched, float *grad_rec, float *g_means,
+                              float *g_scales, float *g_quats, float *g_opac, float *g_sh, void *stream);
 
 /* Bytes of workspace sr_background_loss needs for these views. */
 sr_status sr_loss_workspace_size(int32_t V, const sr_camera *cams_host, size_t *bytes_host);
@@ -201,6 +223,15 @@ sr_status sr_prune_contrib(const sr_config *cfg, int32_t N, int32_t V, const sr_
                            const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
                            const uint32_t *ranges, uint32_t *hits, float *max_alpha,
                            float *max_weight, void *stream);
+
+/* Work accounting of the compositing (no outputs): counts[0] = pairs
+ * (pixel, tile-list entry) tested before the pixel terminated, counts[1] =
+ * pairs blended; uint64 [2], overwritten.  The same decisions as
+ * sr_render_forward; used to express throughput as a fraction of the VALU
+ * roofline. */
+sr_status sr_render_count(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                          const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
+                          const uint32_t *ranges, uint64_t *counts, void *stream);
 
 /* prune_mask[g] = max_alpha[g] < tau (1 = prune).  With tau = alpha_min
  * this is "never blended in any view" (Section 4.3). */

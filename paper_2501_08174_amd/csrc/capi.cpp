@@ -196,8 +196,72 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
     }
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, color,
                                             alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                                            max_weight, s),
+                                            max_weight, nullptr, s),
                       "sr_render_forward");
+}
+
+namespace {
+
+sr_status check_backward_raster(const sr_config* cfg, int N, int V, const sr_camera* cams_host,
+                                const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
+                                const uint32_t* ranges, const float* alpha, const float* depth, const float* dist,
+                                const float* T_final, const uint32_t* n_contrib, const float* grad_rec,
+                                int* total_tiles) {
+    SR_TRY(check_cfg(cfg));
+    SR_TRY(check_nv(N, V));
+    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, total_tiles, nullptr));
+    if (N > 0 && V > 0) {
+        SR_NEED(geom); SR_NEED(app); SR_NEED(vals); SR_NEED(ranges);
+        SR_NEED(alpha); SR_NEED(depth); SR_NEED(dist); SR_NEED(T_final); SR_NEED(n_contrib); SR_NEED(grad_rec);
+    }
+    return SR_OK;
+}
+
+sr_status check_backward_project(const sr_config* cfg, int N, int V, const sr_camera* cams_host,
+                                 const sr_camera* cams_dev, const float* means, const float* scales,
+                                 const float* quats, const float* sh, const float* geom, const float* app,
+                                 const float* grad_rec, const float* g_means, const float* g_scales,
+                                 const float* g_quats, const float* g_opac, const float* g_sh) {
+    SR_TRY(check_cfg(cfg));
+    SR_TRY(check_nv(N, V));
+    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, nullptr, nullptr));
+    if (N > 0 && V > 0) {
+        SR_NEED(means); SR_NEED(scales); SR_NEED(quats); SR_NEED(sh); SR_NEED(geom); SR_NEED(app);
+        SR_NEED(grad_rec); SR_NEED(g_means); SR_NEED(g_scales); SR_NEED(g_quats); SR_NEED(g_opac); SR_NEED(g_sh);
+    }
+    return SR_OK;
+}
+
+}  // namespace
+
+sr_status sr_backward_raster(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
+                             const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
+                             const uint32_t* ranges, const float* alpha, const float* depth, const float* dist,
+                             const float* T_final, const uint32_t* n_contrib, const float* dL_dcolor,
+                             const float* dL_dalpha, const float* dL_ddepth, const float* dL_dnormal,
+                             const float* dL_ddist, float* grad_rec, void* stream) {
+    int total_tiles = 0;
+    SR_TRY(check_backward_raster(cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, alpha, depth, dist, T_final,
+                                 n_contrib, grad_rec, &total_tiles));
+    if (N == 0 || V == 0) return SR_OK;
+    return hip_status(sr::launch_render_bwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, alpha, depth,
+                                            dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
+                                            dL_ddist, grad_rec, (hipStream_t)stream),
+                      "sr_backward_raster");
+}
+
+sr_status sr_backward_project(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
+                              const sr_camera* cams_dev, const float* means, const float* scales, const float* quats,
+                              const float* sh, const float* geom, const float* app, const uint32_t* tiles_touched,
+                              float* grad_rec, float* g_means, float* g_scales, float* g_quats, float* g_opac,
+                              float* g_sh, void* stream) {
+    SR_TRY(check_backward_project(cfg, N, V, cams_host, cams_dev, means, scales, quats, sh, geom, app, grad_rec,
+                                  g_means, g_scales, g_quats, g_opac, g_sh));
+    if (N == 0 || V == 0) return SR_OK;
+    return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app,
+                                                tiles_touched, grad_rec, g_means, g_scales, g_quats, g_opac, g_sh,
+                                                (hipStream_t)stream),
+                      "sr_backward_project");
 }
 
 sr_status sr_render_backward(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
@@ -208,17 +272,12 @@ sr_status sr_render_backward(const sr_config* cfg, int32_t N, int32_t V, const s
                              const float* dL_dcolor, const float* dL_dalpha, const float* dL_ddepth,
                              const float* dL_dnormal, const float* dL_ddist, float* grad_rec, float* g_means,
                              float* g_scales, float* g_quats, float* g_opac, float* g_sh, void* stream) {
-    SR_TRY(check_cfg(cfg));
-    SR_TRY(check_nv(N, V));
     int total_tiles = 0;
-    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr));
     (void)opac;
-    if (N > 0 && V > 0) {
-        SR_NEED(means); SR_NEED(scales); SR_NEED(quats); SR_NEED(sh);
-        SR_NEED(geom); SR_NEED(app); SR_NEED(vals); SR_NEED(ranges);
-        SR_NEED(alpha); SR_NEED(depth); SR_NEED(dist); SR_NEED(T_final); SR_NEED(n_contrib);
-        SR_NEED(grad_rec); SR_NEED(g_means); SR_NEED(g_scales); SR_NEED(g_quats); SR_NEED(g_opac); SR_NEED(g_sh);
-    }
+    SR_TRY(check_backward_raster(cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, alpha, depth, dist, T_final,
+                                 n_contrib, grad_rec, &total_tiles));
+    SR_TRY(check_backward_project(cfg, N, V, cams_host, cams_dev, means, scales, quats, sh, geom, app, grad_rec,
+                                  g_means, g_scales, g_quats, g_opac, g_sh));
     if (N == 0 || V == 0) return SR_OK;
     hipStream_t s = (hipStream_t)stream;
     SR_TRY(hip_status(sr::fill_f32(grad_rec, 0.f, (uint64_t)V * N * SR_GRAD_STRIDE, s), "clear grad_rec"));
@@ -226,8 +285,6 @@ sr_status sr_render_backward(const sr_config* cfg, int32_t N, int32_t V, const s
                                             dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
                                             dL_ddist, grad_rec, s),
                       "render backward"));
-    // culled records received no gradient; the projection backward skips
-    // every record whose accumulated gradient is zero
     return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app, nullptr,
                                                 grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, s),
                       "projection backward");
@@ -286,8 +343,25 @@ sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_
     }
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, vals, ranges, nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, hits, max_alpha,
-                                            max_weight, s),
+                                            max_weight, nullptr, s),
                       "sr_prune_contrib");
+}
+
+sr_status sr_render_count(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
+                          const sr_camera* cams_dev, const float* geom, const uint32_t* vals, const uint32_t* ranges,
+                          uint64_t* counts, void* stream) {
+    SR_TRY(check_cfg(cfg));
+    SR_TRY(check_nv(N, V));
+    int total_tiles = 0;
+    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr));
+    SR_NEED(counts);
+    if (total_tiles > 0) { SR_NEED(geom); SR_NEED(vals); SR_NEED(ranges); }
+    hipStream_t s = (hipStream_t)stream;
+    SR_TRY(hip_status(sr::fill_f32((float*)counts, 0.f, 4, s), "clear counts"));
+    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, vals, ranges, nullptr,
+                                            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                            nullptr, (unsigned long long*)counts, s),
+                      "sr_render_count");
 }
 
 sr_status sr_prune_mask(int32_t N, const float* max_alpha, float tau, uint8_t* prune_mask, void* stream) {

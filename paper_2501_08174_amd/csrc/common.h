@@ -20,6 +20,16 @@ struct RasterConsts {
     uint32_t flags;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Neighbouring tiles read mostly the same surfel records, so give every XCD a
+// contiguous run of tiles: block b of round r = b / 8 on XCD x = b % 8 takes
+// tile x * (G / 8) + r.  The last G % 8 blocks keep their own id (bijection).
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    const int full = G >> 3;
+    if (b >= (full << 3)) return b;
+    return (b & 7) * full + (b >> 3);
+}
+
 // View that owns a global tile id (views are stored in tile order).
 __device__ __forceinline__ int view_of_tile(const sr_camera* __restrict__ cams, int V, int tile) {
     int lo = 0, hi = V - 1;
@@ -77,14 +87,15 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 // rho_s = u^2 + v^2 and rho_f = |x - c|^2, i.e. o exp(-rho) >= alpha_min.
 // ---------------------------------------------------------------------------
 struct PairEval {
-    float dx, dy, w0, w1, w2, r;   // r = 1/w2
-    float u, v, rho, G, a, z;
-    bool pass, surf, clamped;
+    float dx, dy, w0, w1, w2, rho_f;
+    bool pass, s_ok;
+    float r, u, v, rho, G, a, z;   // r = 1/w2
+    bool surf, clamped;
 };
 
-__device__ __forceinline__ void eval_pair(const float4& g0, const float4& g1, const float4& g2,
-                                          const float4& g3, float px, float py, float alpha_max,
-                                          PairEval& e) {
+// Stage 1: the cutoff test (no division, no exponential).
+__device__ __forceinline__ void eval_test(const float4& g0, const float4& g1, const float4& g2,
+                                          const float4& g3, float px, float py, PairEval& e) {
 #pragma clang fp contract(off)
     e.dx = px - g2.y;
     e.dy = py - g2.z;
@@ -92,18 +103,22 @@ __device__ __forceinline__ void eval_pair(const float4& g0, const float4& g1, co
     e.w1 = __builtin_fmaf(g0.y, e.dx, __builtin_fmaf(g1.x, e.dy, g1.w));
     e.w2 = __builtin_fmaf(g0.z, e.dx, __builtin_fmaf(g1.y, e.dy, g2.x));
     const float L = g3.w;
-    const float rho_f = __builtin_fmaf(e.dx, e.dx, e.dy * e.dy);
+    e.rho_f = __builtin_fmaf(e.dx, e.dx, e.dy * e.dy);
     const float q = __builtin_fmaf(e.w0, e.w0, e.w1 * e.w1);
     const float w22 = e.w2 * e.w2;
-    const bool s_ok = (q <= (2.0f * L) * w22) && (e.w2 != 0.0f);
-    const bool f_ok = rho_f <= L;
-    e.pass = s_ok || f_ok;
+    e.s_ok = (q <= (2.0f * L) * w22) && (e.w2 != 0.0f);
+    e.pass = e.s_ok || (e.rho_f <= L);
+}
+
+// Stage 2: intersection, Gaussian value, alpha and depth of a passing pair.
+__device__ __forceinline__ void eval_finish(const float4& g2, const float4& g3, float alpha_max, PairEval& e) {
+#pragma clang fp contract(off)
     e.r = __builtin_amdgcn_rcpf(e.w2);
     e.u = e.w0 * e.r;
     e.v = e.w1 * e.r;
     const float rho_s = 0.5f * __builtin_fmaf(e.u, e.u, e.v * e.v);
-    e.surf = s_ok && (rho_s <= rho_f);
-    e.rho = e.surf ? rho_s : rho_f;
+    e.surf = e.s_ok && (rho_s <= e.rho_f);
+    e.rho = e.surf ? rho_s : e.rho_f;
     // exp(-rho) = 2^(-rho log2 e)
     e.G = __builtin_amdgcn_exp2f(-1.4426950408889634f * e.rho);
     const float oG = g2.w * e.G;

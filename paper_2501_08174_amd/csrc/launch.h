@@ -18,7 +18,7 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
 hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means, const float* scales,
                                  const float* quats, const float* sh, int V, const sr_camera* cams_dev,
                                  const float* geom, const float* app, const uint32_t* tiles_touched,
-                                 const float* grad_rec, float* g_means, float* g_scales, float* g_quats,
+                                 float* grad_rec, float* g_means, float* g_scales, float* g_quats,
                                  float* g_opac, float* g_sh, hipStream_t stream);
 
 size_t bin_workspace_bytes(uint64_t VN, uint64_t cap);
@@ -36,7 +36,7 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
                              uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                             hipStream_t s);
+                             unsigned long long* counts, hipStream_t s);
 
 hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,

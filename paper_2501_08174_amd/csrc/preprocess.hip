@@ -261,7 +261,8 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
 // ---------------------------------------------------------------------------
 // Backward of the projection: chains the per-record gradients accumulated by
 // the raster backward (layout below) to the surfel parameters, summed over
-// the views.  One thread per surfel; the parameter gradients are added to.
+// the views, and clears every accumulator it consumed.  One thread per
+// surfel; the parameter gradients are added to.
 //   grad_rec[r*24 + ...]: [0..2] dA (= sum dL/dw * dx), [3..5] dB, [6..8] dC',
 //   [9..10] d centre (low-pass), [11] d opacity, [12..14] d m3,
 //   [15..17] d rgb, [18..20] d normal.
@@ -277,7 +278,7 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
                  const float* __restrict__ quats, const float* __restrict__ sh, int sh_degree,
                  int sh_stride, int V, const sr_camera* __restrict__ cams,
                  const float4* __restrict__ geom, const float4* __restrict__ app,
-                 const uint32_t* __restrict__ tiles_touched, const float* __restrict__ grad_rec,
+                 const uint32_t* __restrict__ tiles_touched, float* __restrict__ grad_rec,
                  float* __restrict__ g_means, float* __restrict__ g_scales, float* __restrict__ g_quats,
                  float* __restrict__ g_opac, float* __restrict__ g_sh) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -301,11 +302,13 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
     for (int v = 0; v < V; ++v) {
         const size_t r = (size_t)v * N + g;
         if (tiles_touched && tiles_touched[r] == 0u) continue;
-        const float* gr = grad_rec + r * SR_GRAD_STRIDE;
+        float* gr = grad_rec + r * SR_GRAD_STRIDE;
         float G[kNumGrad];
         bool any = false;
         for (int i = 0; i < kNumGrad; ++i) { G[i] = gr[i]; any |= (G[i] != 0.0f); }
         if (!any) continue;
+        // consume: leave the accumulator zero for the next backward
+        for (int i = 0; i < kNumGrad; ++i) gr[i] = 0.0f;
         const sr_camera& cam = cams[v];
         float R[9], t[3];
         for (int i = 0; i < 3; ++i) {
@@ -455,7 +458,7 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
 hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means, const float* scales,
                                  const float* quats, const float* sh, int V, const sr_camera* cams_dev,
                                  const float* geom, const float* app, const uint32_t* tiles_touched,
-                                 const float* grad_rec, float* g_means, float* g_scales, float* g_quats,
+                                 float* grad_rec, float* g_means, float* g_scales, float* g_quats,
                                  float* g_opac, float* g_sh, hipStream_t stream) {
     if (N == 0) return hipSuccess;
     hipLaunchKernelGGL(k_preprocess_bwd, dim3((N + 255) / 256), dim3(256), 0, stream, N, means, scales,

@@ -11,7 +11,7 @@
 // One workgroup per (view, tile) over all views of the batch in a single
 // launch; one thread per pixel; surfel records are staged in LDS one batch
 // per workgroup-size entries; every pair is evaluated with the shared
-// eval_pair() so that forward, backward and pruning take identical
+// eval_test()/eval_finish() so that forward, backward and pruning take identical
 // decisions.
 #include "common.h"
 #include "launch.h"
@@ -32,7 +32,7 @@ struct TileCtx {
 template <int TW, int TH>
 __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int V,
                                          const uint2* __restrict__ ranges, TileCtx& t) {
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     t.v = view_of_tile(cams, V, tile);
     const sr_camera& c = cams[t.v];
     const int local = tile - c.tile_offset;
@@ -49,15 +49,23 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
     t.n = rg.y - rg.x;
 }
 
-template <int TW, int TH, bool SHADE, bool STATS>
+// MODE bits: 1 shade (colour, depth, normal, distortion outputs), 2 occlusion
+// statistics, 4 count reached/blended pairs (work accounting).
+constexpr int kShade = 1, kStats = 2, kCount = 4;
+
+template <int TW, int TH, int MODE>
 __global__ void __launch_bounds__(TW * TH)
 k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
              const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
              RasterConsts rc, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
              float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
              uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
-             float* __restrict__ max_weight) {
+             float* __restrict__ max_weight, unsigned long long* __restrict__ counts) {
+    constexpr bool SHADE = (MODE & kShade) != 0;
+    constexpr bool STATS = (MODE & kStats) != 0;
+    constexpr bool COUNT = (MODE & kCount) != 0;
     constexpr int NT = TW * TH;
+    uint64_t n_reached = 0, n_blended = 0;
     __shared__ float4 s_g[kGeomF4][NT];
     __shared__ float4 s_a[SHADE ? kAppF4 : 1][SHADE ? NT : 1];
     __shared__ uint32_t s_id[STATS ? NT : 1];
@@ -93,8 +101,13 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         if (ballot64(!done) == 0ull) continue;
         for (int k = 0; k < cnt; ++k) {
             PairEval e;
-            eval_pair(s_g[0][k], s_g[1][k], s_g[2][k], s_g[3][k], px, py, rc.alpha_max, e);
+            const float4 g2 = s_g[2][k], g3 = s_g[3][k];
+            eval_test(s_g[0][k], s_g[1][k], g2, g3, px, py, e);
+            if (COUNT) n_reached += (uint64_t)__popcll(ballot64(!done));
             bool blend = !done && e.pass;
+            // no pixel of this wave takes the entry: nothing changes
+            if (ballot64(blend) == 0ull) continue;
+            eval_finish(g2, g3, rc.alpha_max, e);
             float Tn = T * (1.0f - e.a);
             if (blend && Tn < rc.t_min) {
                 done = true;
@@ -120,6 +133,7 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
                 T = Tn;
                 last = base + (uint32_t)k + 1u;
             }
+            if (COUNT) n_blended += (uint64_t)__popcll(ballot64(blend));
             if (STATS) {
                 const uint64_t bm = ballot64(blend);
                 if (bm != 0ull) {
@@ -135,6 +149,10 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
             }
             if (ballot64(!done) == 0ull) break;
         }
+    }
+    if (COUNT && __lane_id() == 0) {
+        atomicAdd(&counts[0], (unsigned long long)n_reached);
+        atomicAdd(&counts[1], (unsigned long long)n_blended);
     }
     if (t.inside) {
         const int64_t HW = (int64_t)t.W * t.H;
@@ -233,15 +251,17 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         for (int k = cnt - 1; k >= 0; --k) {
             const uint32_t jj = (uint32_t)base + (uint32_t)k;
             PairEval e;
-            eval_pair(s_g[0][k], s_g[1][k], s_g[2][k], s_g[3][k], px, py, rc.alpha_max, e);
+            const float4 g2 = s_g[2][k], g3 = s_g[3][k];
+            eval_test(s_g[0][k], s_g[1][k], g2, g3, px, py, e);
             const bool bl = (jj < ncon) && e.pass;
+            if (ballot64(bl) == 0ull) continue;
+            eval_finish(g2, g3, rc.alpha_max, e);
             float gr[kNumGrad];
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) gr[i] = 0.f;
             if (bl) {
                 const float4 a0 = s_a[0][k], a1 = s_a[1][k];
-                const float4 g3 = s_g[3][k];
-                const float o = s_g[2][k].w;
+                const float o = g2.w;
                 const float om = 1.0f - e.a;
                 const float rin = 1.0f / om;
                 const float Tk = T * rin;
@@ -277,12 +297,10 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
                     gr[14] = dLdz;
                 }
             }
-            if (ballot64(bl) != 0ull) {
 #pragma unroll
-                for (int i = 0; i < kNumGrad; ++i) {
-                    const float sum = wave_sum_to_lane63(gr[i]);
-                    if (lane63 && sum != 0.f) atomicAdd(&s_acc[k][i], sum);
-                }
+            for (int i = 0; i < kNumGrad; ++i) {
+                const float sum = wave_sum_to_lane63(gr[i]);
+                if (lane63 && sum != 0.f) atomicAdd(&s_acc[k][i], sum);
             }
         }
         __syncthreads();
@@ -307,30 +325,56 @@ __global__ void k_prune_mask(int N, const float* __restrict__ max_alpha, float t
     if (g < N) mask[g] = max_alpha[g] < tau ? 1 : 0;
 }
 
-template <int TW, int TH>
-hipError_t fwd_dispatch(bool shade, bool stats, int total_tiles, hipStream_t s, const sr_camera* cams, int V,
-                        int N, const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges,
-                        RasterConsts rc, float* color, float* alpha, float* depth, float* normal, float* dist,
-                        float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight) {
-    dim3 grid(total_tiles), block(TW * TH);
-    if (shade && stats)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, true, true>), grid, block, 0, s, cams, V, N, geom, app, vals,
-                           ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                           max_weight);
-    else if (shade)
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, true, false>), grid, block, 0, s, cams, V, N, geom, app, vals,
-                           ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                           max_weight);
-    else
-        hipLaunchKernelGGL((k_render_fwd<TW, TH, false, true>), grid, block, 0, s, cams, V, N, geom, app, vals,
-                           ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                           max_weight);
-    return hipGetLastError();
+template <int TW, int TH, int MODE>
+void fwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
+                const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, float* color,
+                float* alpha, float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib,
+                uint32_t* hits, float* max_alpha, float* max_weight, unsigned long long* counts) {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, MODE>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app,
+                       vals, ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
+                       max_weight, counts);
 }
+
+template <int TW, int TH>
+void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
+                  const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges,
+                  RasterConsts rc, float* color, float* alpha, float* depth, float* normal, float* dist,
+                  float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
+                  unsigned long long* counts) {
+#define SR_FWD(M)                                                                                        \
+    fwd_launch<TW, TH, M>(total_tiles, s, cams, V, N, geom, app, vals, ranges, rc, color, alpha, depth, \
+                          normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, counts)
+    switch (mode) {
+        case kShade: SR_FWD(kShade); break;
+        case kShade | kStats: SR_FWD(kShade | kStats); break;
+        case kStats: SR_FWD(kStats); break;
+        default: SR_FWD(kCount); break;
+    }
+#undef SR_FWD
+}
+
+template <int TW, int TH>
+void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
+                const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, const float* alpha,
+                const float* depth, const float* dist, const float* T_final, const uint32_t* n_contrib,
+                const float* dC, const float* dA, const float* dD, const float* dN, const float* dS,
+                float* grad_rec) {
+    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app, vals,
+                       ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, grad_rec);
+}
+
+// Compiled tile shapes (the binning takes any shape; the raster kernels are
+// instantiated for these).
+#define SR_TILE_SHAPES(X) X(16, 16) X(16, 8) X(8, 8) X(32, 8)
 
 }  // namespace
 
-bool tile_shape_supported(int tw, int th) { return tw == 16 && th == 16; }
+bool tile_shape_supported(int tw, int th) {
+#define SR_TS(W, H) if (tw == W && th == H) return true;
+    SR_TILE_SHAPES(SR_TS)
+#undef SR_TS
+    return false;
+}
 
 hipError_t fill_f32(float* p, float v, uint64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
@@ -342,14 +386,20 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
                              uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                             hipStream_t s) {
+                             unsigned long long* counts, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
-    const bool stats = hits != nullptr;
-    const bool shade = color != nullptr;
-    return fwd_dispatch<16, 16>(shade, stats, total_tiles, s, cams, V, N, (const float4*)geom,
-                                (const float4*)app, vals, (const uint2*)ranges, rc, color, alpha, depth, normal,
-                                dist, T_final, n_contrib, hits, max_alpha, max_weight);
+    int mode = counts ? kCount : ((color ? kShade : 0) | (hits ? kStats : 0));
+#define SR_TS(W, H)                                                                                              \
+    if (cfg.tile_w == W && cfg.tile_h == H) {                                                                   \
+        fwd_dispatch<W, H>(mode, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,    \
+                           (const uint2*)ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, \
+                           max_alpha, max_weight, counts);                                                      \
+        return hipGetLastError();                                                                               \
+    }
+    SR_TILE_SHAPES(SR_TS)
+#undef SR_TS
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
@@ -359,10 +409,16 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* dN, const float* dS, float* grad_rec, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
-    hipLaunchKernelGGL((k_render_bwd<16, 16>), dim3(total_tiles), dim3(256), 0, s, cams, V, N,
-                       (const float4*)geom, (const float4*)app, vals, (const uint2*)ranges, rc, alpha, depth, dist,
-                       T_final, n_contrib, dC, dA, dD, dN, dS, grad_rec);
-    return hipGetLastError();
+#define SR_TS(W, H)                                                                                            \
+    if (cfg.tile_w == W && cfg.tile_h == H) {                                                                 \
+        bwd_launch<W, H>(total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,          \
+                         (const uint2*)ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, \
+                         grad_rec);                                                                           \
+        return hipGetLastError();                                                                             \
+    }
+    SR_TILE_SHAPES(SR_TS)
+#undef SR_TS
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, uint8_t* mask, hipStream_t s) {

@@ -162,22 +162,53 @@ class Rasterizer:
              _ptr(self.ws), self.ws_bytes, self.capacity, _ptr(self.vals), _ptr(keys64), _ptr(self.ranges),
              _ptr(self.counters), _stream(stream))
 
-    def forward(self, stats=None, stream=None):
+    def _cfg(self, accumulate: bool):
+        if not accumulate:
+            return self.cfg
+        cfg = SrConfig.from_buffer_copy(self.cfg)
+        cfg.flags |= _lib.SR_FLAG_ACCUMULATE
+        return cfg
+
+    def forward(self, stats=None, accumulate: bool = False, stream=None):
         h, ma, mw = (None, None, None) if stats is None else stats
-        call("sr_render_forward", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        cfg = self._cfg(accumulate)
+        call("sr_render_forward", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.color), _ptr(self.alpha), _ptr(self.depth), _ptr(self.normal), _ptr(self.dist),
              _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw), _stream(stream))
 
-    def backward(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None):
+    def _grad_rec(self):
         if self.grad_rec is None:
+            # zero on allocation; every projection backward leaves it zero
             self.grad_rec = torch.zeros(max(self.views.V * self.N * _lib.SR_GRAD_STRIDE, 1),
                                         dtype=torch.float32, device=self.device)
+        return self.grad_rec
+
+    def backward_raster(self, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None):
+        call("sr_backward_raster", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
+             _ptr(self.alpha), _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib),
+             _ptr(dC), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._grad_rec()), _stream(stream))
+
+    def backward_project(self, p: Params, grads: Params, stream=None):
+        call("sr_backward_project", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.sh), _ptr(self.geom),
+             _ptr(self.app), _ptr(self.tiles_touched), _ptr(self._grad_rec()), _ptr(grads.means),
+             _ptr(grads.scales), _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _stream(stream))
+
+    def backward(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None):
+        """Both halves of the backward; the parameter gradients are added to."""
+        self.backward_raster(dC, dA, dD, dN, dS, stream)
+        self.backward_project(p, grads, stream)
+
+    def backward_combined(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None,
+                          stream=None):
+        """The single-call form (sr_render_backward)."""
         call("sr_render_backward", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.opac), _ptr(p.sh),
              _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(self.alpha),
              _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(dC), _ptr(dA),
-             _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self.grad_rec), _ptr(grads.means), _ptr(grads.scales),
+             _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._grad_rec()), _ptr(grads.means), _ptr(grads.scales),
              _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _stream(stream))
 
     def loss(self, mask: torch.Tensor, target: Optional[torch.Tensor], gamma: float = 0.5, w_c: float = 1.0,
@@ -189,11 +220,18 @@ class Rasterizer:
         return self.loss_out
 
     def prune_stats(self, hits, max_alpha, max_weight, accumulate=False, stream=None):
-        cfg = SrConfig.from_buffer_copy(self.cfg)
-        cfg.flags |= _lib.SR_FLAG_ACCUMULATE if accumulate else 0
+        cfg = self._cfg(accumulate)
         call("sr_prune_contrib", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.vals), _ptr(self.ranges), _ptr(hits),
              _ptr(max_alpha), _ptr(max_weight), _stream(stream))
+
+    def count_pairs(self, stream=None):
+        """(reached pairs, blended pairs) of the current binning - syncs."""
+        out = torch.zeros(2, dtype=torch.int64, device=self.device)
+        call("sr_render_count", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.vals), _ptr(self.ranges), _ptr(out), _stream(stream))
+        c = out.cpu().numpy()
+        return int(c[0]), int(c[1])
 
     def status(self):
         """(visible pairs, instances needed, instances stored, status) - syncs."""

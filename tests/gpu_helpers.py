@@ -12,8 +12,8 @@ from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch
 FWD_TOL = 1e-4
 
 
-def gpu_run(scene, stats=False, keys64=False, capacity=None, device="cuda"):
-    views = ViewBatch(scene.cams, device=device)
+def gpu_run(scene, stats=False, keys64=False, capacity=None, device="cuda", tile=(16, 16)):
+    views = ViewBatch(scene.cams, tile=tile, device=device)
     rast = Rasterizer(scene.n, views, scene.sh_degree, sh_stride=scene.sh.shape[1], device=device)
     p = Params.from_scene(scene, device=device)
     if capacity is None:

@@ -57,10 +57,10 @@ def test_argument_errors_before_launch(lib):
     """Invalid configurations are rejected on the host (no device touched)."""
     from paper_2501_08174_amd._lib import SrConfig
     l = lib.lib()
-    cfg = SrConfig(8, 8, 0, 1, 1 / 255, 0.99, 1e-4, 0)
+    cfg = SrConfig(12, 12, 0, 1, 1 / 255, 0.99, 1e-4, 0)
     assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_UNSUPPORTED
-    assert l.sr_tile_supported(16, 16) == 1 and l.sr_tile_supported(7, 3) == 0
+    assert l.sr_tile_supported(16, 16) == 1 and l.sr_tile_supported(8, 8) == 1 and l.sr_tile_supported(7, 3) == 0
     cfg = SrConfig(16, 16, 4, 25, 1 / 255, 0.99, 1e-4, 0)
     assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_UNSUPPORTED

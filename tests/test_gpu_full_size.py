@@ -1,0 +1,268 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark uses: per-record bit-exact binning over every (view, surfel),
+sampled tile lists, forward/backward on 64x64 crops and sampled pixels the
+oracle evaluates one by one, central finite differences on a 200-surfel
+subset, and the occlusion-pruning invariants of the shell scene."""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.render import Params64, render_pixels
+from paper_2501_08174_amd import scenes
+from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch, rasterize, prune_mask
+from tests.gpu_helpers import compare_forward, crop_pixels, gpu_run, per_view
+
+pytestmark = pytest.mark.gpu
+RP = oracle.RasterParams()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _geoms_parallel(sc, views=None):
+    views = range(sc.v) if views is None else views
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        fut = {v: ex.submit(oracle.view_geometry64, sc.means, sc.scales, sc.quats, sc.opac, sc.cams[v], RP)
+               for v in views}
+        return {v: f.result() for v, f in fut.items()}
+
+
+def _records_bit_exact(sc, rast, geoms):
+    N = sc.n
+    bad_total = 0
+    for v, g in geoms.items():
+        sl = slice(v * N, (v + 1) * N)
+        tt = rast.tiles_touched[sl].cpu().numpy().view(np.uint32)
+        dk = rast.depth_key[sl].cpu().numpy().view(np.uint32)
+        rect = rast.rect[4 * v * N: 4 * (v + 1) * N].cpu().numpy().view(np.uint16).reshape(N, 4)
+        ok = ~g["culled"]
+        mism = (tt != g["tiles_touched"]) | (ok & (dk != g["depth_bits"])) | \
+            (ok[:, None] & (rect.astype(np.int64) != g["rect"])).any(axis=1)
+        bad = mism & ~g["grid_tie"]
+        assert not bad.any(), f"view {v}: {bad.sum()} records differ: {np.nonzero(bad)[0][:5]}"
+        bad_total += int(mism.sum())
+    return bad_total
+
+
+def _tile_list(g, tx_count, local_tile):
+    ty, tx = divmod(local_tile, tx_count)
+    sel = (~g["culled"]) & (g["tiles"][:, 0] <= tx) & (tx <= g["tiles"][:, 1]) & \
+        (g["tiles"][:, 2] <= ty) & (ty <= g["tiles"][:, 3])
+    ids = np.nonzero(sel)[0]
+    return ids[np.lexsort((ids, g["depth_bits"][ids]))]
+
+
+def _sampled_tiles(sc, run, geoms, n_tiles=48, seed=0):
+    rast = run["rast"]
+    views = rast.views
+    rg = rast.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    vals = rast.vals.cpu().numpy().view(np.uint32)
+    k64 = run["keys64"].cpu().numpy().view(np.uint64) if run["keys64"] is not None else None
+    rng = np.random.default_rng(seed)
+    for _ in range(n_tiles):
+        v = int(rng.choice(list(geoms.keys())))
+        h = views.host[v]
+        t = int(rng.integers(0, h.tiles_x * h.tiles_y))
+        want = _tile_list(geoms[v], h.tiles_x, t)
+        s, e = rg[h.tile_offset + t]
+        np.testing.assert_array_equal(vals[s:e], want)
+        if k64 is not None:
+            exp = (np.uint64(h.tile_offset + t) << np.uint64(32)) | geoms[v]["depth_bits"][want].astype(np.uint64)
+            np.testing.assert_array_equal(k64[s:e], exp)
+    # global properties: ranges partition [0, n_inst) in tile order
+    n = run["status"][2]
+    nz = rg[rg[:, 1] > rg[:, 0]]
+    assert nz[0, 0] == 0 and nz[-1, 1] == n and np.all(nz[1:, 0] == nz[:-1, 1])
+
+
+def _crop_forward(sc, rast, geoms, v, x0, y0, P64, w=64, h=64):
+    pix = crop_pixels(x0, y0, w, h)
+    res = render_pixels(P64, sc.cams[v], geoms[v], pix, RP)
+    errs, flagged = compare_forward(per_view(rast, v), res, pix, rast, v)
+    return errs, flagged
+
+
+# --------------------------------------------------------------------------
+# config 2: 800x800, 100k surfels, SH degree 3
+# --------------------------------------------------------------------------
+
+def _gpu_crop_grads(sc, x0, y0, w, h, gamma=0.5, w_c=1.0):
+    """GPU gradients of the crop-restricted loss through the autograd path."""
+    views = ViewBatch(sc.cams)
+    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1])
+    p = Params.from_scene(sc)
+    rast.plan_capacity(p)
+    leaves = [t.clone().requires_grad_(True) for t in (p.means, p.scales, p.quats, p.opac, p.sh)]
+    color, alpha, depth, normal, dist = rasterize(*leaves, rast)
+    cam = sc.cams[0]
+    H, W = cam.height, cam.width
+    m = torch.tensor(sc.masks[0], dtype=torch.float32, device="cuda")
+    tgt = torch.tensor(sc.targets[0], device="cuda")
+    C = color.view(3, H, W)[:, y0:y0 + h, x0:x0 + w]
+    A = alpha.view(H, W)[y0:y0 + h, x0:x0 + w]
+    mc = m[y0:y0 + h, x0:x0 + w]
+    L = w_c * (mc * C - mc * tgt[:, y0:y0 + h, x0:x0 + w]).abs().sum() / (3 * H * W) + \
+        gamma * (A * (1 - mc)).sum() / (H * W)
+    L.backward()
+    torch.cuda.synchronize()
+    return [t.grad.cpu().numpy().astype(np.float64) for t in leaves], float(L.item())
+
+
+def _oracle_crop_loss_fn(sc, x0, y0, w, h, gamma=0.5, w_c=1.0):
+    cam = sc.cams[0]
+    H, W = cam.height, cam.width
+    pix = crop_pixels(x0, y0, w, h)
+    m = torch.tensor(sc.masks[0][pix[:, 1], pix[:, 0]], dtype=torch.float64)
+    tgt = torch.tensor(sc.targets[0][:, pix[:, 1], pix[:, 0]].T, dtype=torch.float64)
+
+    def lf(out, rows):
+        r = torch.as_tensor(rows)
+        mm = m[r]
+        return (w_c * (mm[:, None] * out["color"] - mm[:, None] * tgt[r]).abs().sum() / (3 * H * W)
+                + gamma * (out["alpha"] * (1 - mm)).sum() / (H * W))
+    return pix, lf
+
+
+def test_config2_crop_backward_and_fd_subset():
+    """Gradients of the crop loss: GPU vs oracle autograd on every surfel,
+    and GPU vs central finite differences of the FP64 oracle on 200
+    surfels (seed 22) visible in the crop [368, 432)^2."""
+    sc = scenes.make_config2()
+    x0 = y0 = 368
+    g, Lg = _gpu_crop_grads(sc, x0, y0, 64, 64)
+    geom = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, sc.cams[0], RP)
+    pix, lf = _oracle_crop_loss_fn(sc, x0, y0, 64, 64)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3, requires_grad=True)
+    res = render_pixels(P64, sc.cams[0], geom, pix, RP, loss_fn=lf)
+    gref = P64.grads()
+    from tests.test_gpu_parity import _compare_grads
+    touched = np.unique(res["pairs"][0][:, 1])
+    keep_rows = np.zeros(sc.n, bool)
+    keep_rows[touched] = True
+    keep_rows[res["flag_ids"]] = False
+    excl = np.nonzero(~keep_rows)[0]
+    _compare_grads(g, gref, excl)
+    # finite differences on a 200-surfel subset, one random parameter each
+    rng = np.random.default_rng(22)
+    cand = np.setdiff1d(touched, res["flag_ids"])
+    sub = rng.choice(cand, size=min(200, cand.size), replace=False)
+    P0 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3)
+    names = ("means", "scales", "quats", "opac", "sh")
+    widths = (3, 2, 4, 1, 48)
+    checked, worst = 0, 0.0
+    for gid in sub:
+        k = int(rng.integers(0, 5))
+        name = names[k]
+        j = int(rng.integers(0, widths[k]))
+        rect = geom["rect"][gid]
+        fp = crop_pixels(max(rect[0], x0), max(rect[2], y0), min(rect[1], x0 + 63) - max(rect[0], x0) + 1,
+                         min(rect[3], y0 + 63) - max(rect[2], y0) + 1)
+        rows = (fp[:, 1] - y0) * 64 + (fp[:, 0] - x0)
+        t = getattr(P0, name)
+        flat = gid * widths[k] + j
+        base = float(t.view(-1)[flat])
+        hstep = 1e-6 * max(1.0, abs(base))
+        vals, decs = [], []
+        for sgn in (1, -1):
+            with torch.no_grad():
+                t.view(-1)[flat] = base + sgn * hstep
+                r = render_pixels(P0, sc.cams[0], geom, fp, RP, keep_decisions=True,
+                                  loss_fn=lambda out, rr: vals.append(float(lf(out, rows[rr]))) or None)
+            decs.append([d["blended"].tobytes() + d["surf"].tobytes() + d["clamp"].tobytes()
+                         for d in r["decisions"]])
+        with torch.no_grad():
+            t.view(-1)[flat] = base
+        if decs[0] != decs[1]:
+            continue
+        fd = (sum(vals[: len(vals) // 2]) - sum(vals[len(vals) // 2:])) / (2 * hstep)
+        gg = g[k].reshape(-1)[flat]
+        scale = max(abs(fd), 1e-3 * np.abs(gref[k]).max())
+        err = abs(gg - fd) / scale
+        worst = max(worst, err)
+        assert err <= 1e-3 * 10, (name, gid, j, gg, fd)
+        checked += 1
+    print(f"FD subset: {checked} parameters checked, worst relative error {worst:.2e}")
+    assert checked >= 150
+
+
+# --------------------------------------------------------------------------
+# config 3: 16 views 400..1600 px, 1M surfels (the benchmark workload)
+# --------------------------------------------------------------------------
+
+def test_config3_full_size():
+    sc = scenes.make_config3()
+    run = gpu_run(sc, keys64=True, stats=True)
+    rast = run["rast"]
+    geoms = _geoms_parallel(sc)
+    ex = _records_bit_exact(sc, rast, geoms)
+    print("config3 records bit-exact; grid-tie exemptions", ex)
+    vis, need, stored, status = run["status"]
+    assert status == 0 and vis == sum(int((~g["culled"]).sum()) for g in geoms)
+    assert need == sum(int(g["tiles_touched"].sum()) for g in geoms)
+    _sampled_tiles(sc, run, geoms)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3)
+    rng = np.random.default_rng(3)
+    for v in (0, 5, 12):
+        cam = sc.cams[v]
+        x0 = int(rng.integers(0, cam.width - 64))
+        y0 = int(rng.integers(0, cam.height - 64))
+        errs, fl = _crop_forward(sc, rast, geoms, v, cam.width // 2 - 32, cam.height // 2 - 32, P64)
+        print(f"config3 view {v} centre crop errors {errs} flagged {fl}")
+        errs, fl = _crop_forward(sc, rast, geoms, v, x0, y0, P64, w=32, h=32)
+        print(f"config3 view {v} crop ({x0},{y0}) errors {errs} flagged {fl}")
+
+
+def test_config5_crop():
+    sc = scenes.make_config5()
+    run = gpu_run(sc, stats=True)
+    rast = run["rast"]
+    geoms = _geoms_parallel(sc, views=[0])
+    assert _records_bit_exact(sc, rast, geoms) == 0
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3)
+    errs, fl = _crop_forward(sc, rast, geoms, 0, 948, 513, P64)
+    print("config5 crop errors", errs, "flagged", fl)
+
+
+# --------------------------------------------------------------------------
+# config 4: occlusion pruning over 100 views of the shell scene
+# --------------------------------------------------------------------------
+
+def test_config4_pruning_shell_scene():
+    sc = scenes.make_config4()
+    N = sc.n
+    dev = "cuda"
+    p = Params.from_scene(sc)
+    hits = torch.zeros(N, dtype=torch.int32, device=dev)
+    ma = torch.zeros(N, device=dev)
+    mw = torch.zeros(N, device=dev)
+    inf = torch.zeros(N, dtype=torch.uint8, device=dev)
+    chunk = 20
+    for v0 in range(0, sc.v, chunk):
+        views = ViewBatch(sc.cams[v0:v0 + chunk])
+        rast = Rasterizer(N, views, 0, shade=False)
+        rast.plan_capacity(p)
+        rast.preprocess(p)
+        rast.bin()
+        rast.check_capacity()
+        rast.prune_stats(hits, ma, mw, accumulate=True)
+        inf |= rast.in_frustum[:N]
+        del rast
+    mask = prune_mask(ma).cpu().numpy().astype(bool)
+    h = hits.cpu().numpy()
+    infr = inf.cpu().numpy().astype(bool)
+    n_shell, n_inner = 300_000, 700_000
+    inner = slice(n_shell, n_shell + n_inner)
+    # Section 4.3: the interior is inside the frustum of every view but never blended
+    assert infr[inner].all()
+    assert mask[inner].all() and (h[inner] == 0).all()
+    assert np.array_equal(mask, h == 0)
+    kept_shell = (~mask[:n_shell]).mean()
+    print(f"pruned {mask.sum()} of {N}; shell kept {kept_shell:.3f}; exterior kept "
+          f"{(~mask[n_shell + n_inner:]).mean():.3f}; in-frustum but pruned {(infr & mask).sum()}")
+    assert kept_shell > 0.5
