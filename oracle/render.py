@@ -40,10 +40,14 @@ from .sh import sh_colour
 
 DT = torch.float64
 
-# tie windows for the flags that mark pixels where a float32 evaluation may
-# legitimately take the other side of a threshold
-TIE_CUTOFF_REL = 5e-4      # |o G - alpha_min| <= 5e-4 alpha_min
-TIE_TERM_REL = 2e-3        # |T (1 - a) - t_min| <= 2e-3 t_min
+# Tie windows for the flags that mark pixels where a float32 evaluation may
+# legitimately take the other side of a threshold.  A float32 evaluation of
+# o G carries a relative error of a few 1e-6 (rounding of the record and of
+# rho, exp); T(1 - a) accumulates that error over the blended entries,
+# amplified by a / (1 - a) <= 99 per entry near the alpha clamp.  The windows
+# are an order of magnitude wider than those errors.
+TIE_CUTOFF_REL = 5e-5      # |o G - alpha_min| <= 5e-5 alpha_min
+TIE_TERM_REL = 2e-4        # |T (1 - a) - t_min| <= 2e-4 t_min
 TIE_BRANCH = 1e-6          # |G_s - G_f|
 TIE_CLAMP = 1e-6           # |o G - alpha_max|
 

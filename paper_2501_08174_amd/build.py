@@ -26,6 +26,9 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",
+    # atomics are already reduced by hand (DPP + LDS); keep the compiler from
+    # wrapping every LDS atomic in a lane-serial scan loop
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     # keep packed FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,

@@ -93,7 +93,8 @@ k_vis_count(uint64_t VN, int G, const uint32_t* __restrict__ tiles_touched, uint
 // single block: exclusive scan of n (<= 4096) block sums in place; total to *out
 template <typename T>
 __global__ void __launch_bounds__(kNT)
-k_scan_small(T* __restrict__ data, int n, uint32_t* __restrict__ counters, int slot, uint32_t capacity) {
+k_scan_small(T* __restrict__ data, int n, uint32_t* __restrict__ counters, int slot, uint32_t capacity,
+             uint64_t* __restrict__ total64) {
     __shared__ T s_w[4];
     const int per = (n + kNT - 1) / kNT;
     const int b = threadIdx.x * per;
@@ -114,6 +115,7 @@ k_scan_small(T* __restrict__ data, int n, uint32_t* __restrict__ counters, int s
             counters[0] = (uint32_t)tot;
         } else {
             const uint64_t t64 = (uint64_t)tot;
+            *total64 = t64;
             counters[1] = t64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t64;
             counters[2] = t64 > capacity ? capacity : (uint32_t)t64;
             counters[3] = t64 > capacity ? 1u : 0u;
@@ -154,7 +156,16 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ cou
     uint32_t b, e;
     radix_chunk(*count, G, &b, &e);
     const uint32_t mask = (uint32_t)R - 1u;
-    for (uint32_t i = b + threadIdx.x; i < e; i += kNT) atomicAdd(&s_h[w][(keys[i] >> shift) & mask], 1u);
+    // eight independent loads in flight per thread
+    uint32_t i = b + threadIdx.x;
+    for (; i + 7u * kNT < e; i += 8u * kNT) {
+        uint32_t k[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) k[u] = keys[i + (uint32_t)u * kNT];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) atomicAdd(&s_h[w][(k[u] >> shift) & mask], 1u);
+    }
+    for (; i < e; i += kNT) atomicAdd(&s_h[w][(keys[i] >> shift) & mask], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < R; d += kNT)
         hist[(size_t)d * G + blockIdx.x] = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
@@ -286,58 +297,91 @@ k_inst_count(const uint32_t* __restrict__ counters, int G, const uint32_t* __res
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Emits the instances of the depth-sorted visible pairs; each block spreads
-// the instances of 256 consecutive pairs over its threads.
+// Exclusive instance offset of every depth-sorted visible pair.
 __global__ void __launch_bounds__(kNT)
-k_emit(const uint32_t* __restrict__ counters, int G, int N, int tile_w, int tile_h,
+k_inst_offsets(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ vis_vals,
+               const uint32_t* __restrict__ tiles_touched, const uint64_t* __restrict__ block_offs,
+               uint64_t* __restrict__ offs) {
+    __shared__ uint64_t s_w[4];
+    uint64_t b, e;
+    static_chunk(counters[0], G, &b, &e);
+    uint64_t run = block_offs[blockIdx.x];
+    for (uint64_t base = b; base < e; base += kNT) {
+        const uint64_t i = base + threadIdx.x;
+        const uint64_t t = i < e ? (uint64_t)tiles_touched[vis_vals[i]] : 0ull;
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan<uint64_t>(t, s_w, &tot);
+        if (i < e) offs[i] = run + ex;
+        run += tot;
+    }
+}
+
+constexpr int kEmitPerBlock = 4096;   // instances written per block
+
+// Emits the instances in depth order.  The output space is partitioned:
+// block b writes instances [b*4096, (b+1)*4096), whatever the number of
+// surfels they come from, so surfels covering thousands of tiles (close to
+// a camera, first in depth order) do not serialise on a few blocks.
+__global__ void __launch_bounds__(kNT)
+k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total64, int N, int tile_w, int tile_h,
        const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals,
        const uint32_t* __restrict__ tiles_touched, const ushort4* __restrict__ rect,
-       const uint64_t* __restrict__ offs, uint32_t capacity, uint32_t* __restrict__ inst_keys,
-       uint32_t* __restrict__ inst_vals) {
-    __shared__ uint64_t s_w[4];
-    __shared__ uint32_t s_off[kNT];
+       const uint64_t* __restrict__ offs, uint32_t* __restrict__ inst_keys, uint32_t* __restrict__ inst_vals) {
+    __shared__ uint64_t s_off[kNT];
     __shared__ uint32_t s_g[kNT];
     __shared__ int s_base[kNT];     // global id of the rectangle's first tile
     __shared__ int s_tw[kNT];       // rectangle width in tiles
     __shared__ int s_tx[kNT];       // tiles per row of the view
-    uint64_t b, e;
-    static_chunk(counters[0], G, &b, &e);
-    uint64_t run = offs[blockIdx.x];
-    for (uint64_t base = b; base < e; base += kNT) {
-        const uint64_t i = base + threadIdx.x;
-        uint32_t t = 0;
-        if (i < e) {
+    __shared__ uint32_t s_first;
+    const uint64_t stored = counters[2];          // min(instances, capacity)
+    const uint64_t ob = (uint64_t)blockIdx.x * kEmitPerBlock;
+    if (ob >= stored) return;
+    const uint64_t oe = ob + kEmitPerBlock < stored ? ob + kEmitPerBlock : stored;
+    const uint32_t n_vis = counters[0];
+    const uint64_t total = *total64;
+    if (threadIdx.x == 0) {
+        // last pair whose first instance is <= ob
+        uint32_t lo = 0, hi = n_vis - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (offs[mid] <= ob) lo = mid; else hi = mid - 1;
+        }
+        s_first = lo;
+    }
+    __syncthreads();
+    for (uint32_t e0 = s_first;; e0 += kNT) {
+        const uint32_t i = e0 + threadIdx.x;
+        if (i < n_vis) {
             const uint32_t rec = vis_vals[i];
-            t = tiles_touched[rec];
             const int v = (int)(rec / (uint32_t)N);
             const ushort4 rc = rect[rec];
             const int tx0 = rc.x / tile_w, tx1 = rc.y / tile_w, ty0 = rc.z / tile_h;
             const sr_camera& c = cams[v];
+            s_off[threadIdx.x] = offs[i];
             s_g[threadIdx.x] = rec - (uint32_t)v * (uint32_t)N;
             s_base[threadIdx.x] = c.tile_offset + ty0 * c.tiles_x + tx0;
             s_tw[threadIdx.x] = tx1 - tx0 + 1;
             s_tx[threadIdx.x] = c.tiles_x;
+        } else {
+            s_off[threadIdx.x] = ~0ull;
         }
-        uint64_t tot;
-        const uint64_t ex = block_excl_scan<uint64_t>((uint64_t)t, s_w, &tot);
-        s_off[threadIdx.x] = (uint32_t)ex;     // block-local: < 256 * max tiles per rect
         __syncthreads();
-        for (uint64_t s = threadIdx.x; s < tot; s += kNT) {
+        const uint64_t wend = (e0 + kNT < n_vis) ? offs[e0 + kNT] : total;
+        const uint64_t lo_o = ob > s_off[0] ? ob : s_off[0];
+        const uint64_t hi_o = oe < wend ? oe : wend;
+        for (uint64_t o = lo_o + threadIdx.x; o < hi_o; o += kNT) {
             int lo = 0, hi = kNT - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if ((uint64_t)s_off[mid] <= s) lo = mid; else hi = mid - 1;
+                if (s_off[mid] <= o) lo = mid; else hi = mid - 1;
             }
-            const uint32_t k = (uint32_t)(s - s_off[lo]);
+            const uint32_t k = (uint32_t)(o - s_off[lo]);
             const uint32_t tw = (uint32_t)s_tw[lo];
             const uint32_t row = k / tw, colx = k - row * tw;
-            const uint64_t out = run + s;
-            if (out < capacity) {
-                inst_keys[out] = (uint32_t)s_base[lo] + row * (uint32_t)s_tx[lo] + colx;
-                inst_vals[out] = s_g[lo];
-            }
+            inst_keys[o] = (uint32_t)s_base[lo] + row * (uint32_t)s_tx[lo] + colx;
+            inst_vals[o] = s_g[lo];
         }
-        run += tot;
+        if (wend >= oe || e0 + kNT >= n_vis) break;
         __syncthreads();
     }
 }
@@ -366,10 +410,13 @@ __global__ void k_copy_u32(const uint32_t* __restrict__ counters, const uint32_t
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Blocks of a radix pass: one sub-tile each for small inputs, at most 4096
+// (16 per CU) for large ones; the digit histogram is 256 x G counters.
+constexpr int kMaxRadixBlocks = 4096;
 int grid_for(uint64_t elems) {
     uint64_t g = (elems + kTile - 1) / kTile;
     if (g < 1) g = 1;
-    if (g > 1024) g = 1024;
+    if (g > kMaxRadixBlocks) g = kMaxRadixBlocks;
     return (int)g;
 }
 
@@ -377,7 +424,7 @@ struct BinWs {
     uint32_t *vk0, *vv0, *vk1, *vv1;     // visible pairs, ping-pong
     uint32_t *ik0, *iv0, *ik1, *iv1;     // instances, ping-pong
     uint32_t *hist, *tot, *vsum;
-    uint64_t* isum;
+    uint64_t *isum, *ioff, *itotal;
     size_t bytes;
 };
 
@@ -393,10 +440,12 @@ BinWs carve(void* base, uint64_t VN, uint64_t cap) {
     w.vk1 = (uint32_t*)take(VN * 4); w.vv1 = (uint32_t*)take(VN * 4);
     w.ik0 = (uint32_t*)take(cap * 4); w.iv0 = (uint32_t*)take(cap * 4);
     w.ik1 = (uint32_t*)take(cap * 4); w.iv1 = (uint32_t*)take(cap * 4);
-    w.hist = (uint32_t*)take(256ull * 1024 * 4);
+    w.hist = (uint32_t*)take(256ull * kMaxRadixBlocks * 4);
     w.tot = (uint32_t*)take(256 * 4);
-    w.vsum = (uint32_t*)take(1024 * 4);
-    w.isum = (uint64_t*)take(1024 * 8);
+    w.vsum = (uint32_t*)take(kMaxRadixBlocks * 4);
+    w.isum = (uint64_t*)take(kMaxRadixBlocks * 8);
+    w.ioff = (uint64_t*)take(VN * 8);
+    w.itotal = (uint64_t*)take(8);
     w.bytes = off;
     return w;
 }
@@ -447,7 +496,7 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     // 1. compact the visible pairs in (view, surfel) order
     const int Gv = grid_for(VN);
     hipLaunchKernelGGL(k_vis_count, dim3(Gv), dim3(kNT), 0, s, VN, Gv, tiles_touched, w.vsum);
-    hipLaunchKernelGGL(k_scan_small<uint32_t>, dim3(1), dim3(kNT), 0, s, w.vsum, Gv, counters, 0, cap);
+    hipLaunchKernelGGL(k_scan_small<uint32_t>, dim3(1), dim3(kNT), 0, s, w.vsum, Gv, counters, 0, cap, w.itotal);
     hipLaunchKernelGGL(k_vis_compact, dim3(Gv), dim3(kNT), 0, s, VN, Gv, tiles_touched, depth_key, w.vsum,
                        w.vk0, w.vv0);
     // 2. stable sort by the 32 depth bits (ties keep (view, surfel) order):
@@ -469,16 +518,22 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     // 3. instance offsets and emission in depth order
     const int Gi = Gv;
     hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, tiles_touched, w.isum);
-    hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap);
-    hipLaunchKernelGGL(k_emit, dim3(Gi), dim3(kNT), 0, s, counters, Gi, N, cfg.tile_w, cfg.tile_h, cams_dev,
-                       w.vv0, tiles_touched, (const ushort4*)rect, w.isum, cap, w.ik0, w.iv0);
+    hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap, w.itotal);
+    hipLaunchKernelGGL(k_inst_offsets, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, tiles_touched, w.isum,
+                       w.ioff);
+    const uint64_t emit_blocks = ((uint64_t)cap + kEmitPerBlock - 1) / kEmitPerBlock;
+    if (emit_blocks > 0)
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kNT), 0, s, counters, w.itotal, N, cfg.tile_w,
+                           cfg.tile_h, cams_dev, w.vv0, tiles_touched, (const ushort4*)rect, w.ioff, w.ik0, w.iv0);
     // 4. stable sort by tile id; values land in the caller's array
     int nbits = 0;
     while ((1ull << nbits) < (uint64_t)total_tiles) ++nbits;
     uint32_t* sorted_keys = radix_sort(w.ik0, w.iv0, w.ik1, w.iv1, vals, counters + 2, cap, nbits, w.hist,
                                        w.tot, s);
-    hipLaunchKernelGGL(k_ranges, dim3(1024), dim3(kNT), 0, s, counters, sorted_keys, vals, (uint2*)ranges,
-                       keys64, depth_key, cams_dev, V, N);
+    const uint64_t rblocks = ((uint64_t)cap + kNT - 1) / kNT;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)(rblocks < 1 ? 1 : (rblocks > 0x7FFFFFFF ? 0x7FFFFFFF : rblocks))),
+                       dim3(kNT), 0, s, counters, sorted_keys, vals, (uint2*)ranges, keys64, depth_key, cams_dev, V,
+                       N);
     return hipGetLastError();
 }
 

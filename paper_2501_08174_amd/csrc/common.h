@@ -59,6 +59,15 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
     return v;
 }
 
+// Sum over each row of 16 lanes; every lane of a row ends with its row sum.
+__device__ __forceinline__ float row_sum16(float v) {
+    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f<0x140, 0xF>(v);  // row_mirror
+    return v;
+}
+
 // max of non-negative values (0 is the identity)
 __device__ __forceinline__ float wave_max_to_lane63(float v) {
     v = fmaxf(v, dpp_f<0xB1, 0xF>(v));

@@ -184,7 +184,7 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
 // W_k / (1 - a_k).  Per-record gradients are summed over the wavefront with
 // DPP, over the workgroup in LDS, then added to grad_rec with one atomic per
 // (tile, record, component).
-template <int TW, int TH>
+template <int TW, int TH, int BATCH>
 __global__ void __launch_bounds__(TW * TH)
 k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
              const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
@@ -193,16 +193,17 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
              const float* __restrict__ dC, const float* __restrict__ dA, const float* __restrict__ dD,
              const float* __restrict__ dNrm, const float* __restrict__ dDist, float* __restrict__ grad_rec) {
     constexpr int NT = TW * TH;
-    __shared__ float4 s_g[kGeomF4][NT];
-    __shared__ float4 s_a[kAppF4][NT];
-    __shared__ uint32_t s_rec[NT];
-    __shared__ float s_acc[NT][kNumGrad];
+    static_assert(BATCH <= NT, "one record per thread and batch");
+    __shared__ float4 s_g[kGeomF4][BATCH];
+    __shared__ float4 s_a[kAppF4][BATCH];
+    __shared__ uint32_t s_rec[BATCH];
+    __shared__ float s_acc[BATCH][kNumGrad];
     __shared__ uint32_t s_maxn;
     TileCtx t;
     tile_ctx<TW, TH>(cams, V, ranges, t);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     const int tid = threadIdx.x;
-    const bool lane63 = __lane_id() == 63;
+    const bool row_last = (__lane_id() & 15) == 15;
 
     uint32_t ncon = 0;
     float T = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gA = 0.f, gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gS = 0.f;
@@ -231,24 +232,34 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     __syncthreads();
     const uint32_t maxn = s_maxn;
     if (maxn == 0u) return;
+    // entries at or beyond the wave's own last contributor concern no lane
+    uint32_t wave_maxn = ncon;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)wave_maxn, off, 64);
+        wave_maxn = o > wave_maxn ? o : wave_maxn;
+    }
 
-    for (int64_t base = ((int64_t)(maxn - 1) / NT) * NT; base >= 0; base -= NT) {
+    for (int64_t base = ((int64_t)(maxn - 1) / BATCH) * BATCH; base >= 0; base -= BATCH) {
         __syncthreads();
-        const uint32_t j = (uint32_t)base + tid;
-        if (j < maxn) {
-            const uint32_t g = vals[t.start + j];
-            const size_t r = (size_t)t.v * N + g;
+        if (tid < BATCH) {
+            const uint32_t j = (uint32_t)base + tid;
+            if (j < maxn) {
+                const uint32_t g = vals[t.start + j];
+                const size_t r = (size_t)t.v * N + g;
 #pragma unroll
-            for (int q = 0; q < kGeomF4; ++q) s_g[q][tid] = geom[kGeomF4 * r + q];
+                for (int q = 0; q < kGeomF4; ++q) s_g[q][tid] = geom[kGeomF4 * r + q];
 #pragma unroll
-            for (int q = 0; q < kAppF4; ++q) s_a[q][tid] = app[kAppF4 * r + q];
-            s_rec[tid] = (uint32_t)r;
+                for (int q = 0; q < kAppF4; ++q) s_a[q][tid] = app[kAppF4 * r + q];
+                s_rec[tid] = (uint32_t)r;
+            }
+#pragma unroll
+            for (int i = 0; i < kNumGrad; ++i) s_acc[tid][i] = 0.f;
         }
-#pragma unroll
-        for (int i = 0; i < kNumGrad; ++i) s_acc[tid][i] = 0.f;
         __syncthreads();
-        const int cnt = (int)min((uint32_t)NT, maxn - (uint32_t)base);
-        for (int k = cnt - 1; k >= 0; --k) {
+        const int cnt = (int)min((uint32_t)BATCH, maxn - (uint32_t)base);
+        const int kmax = (int)min((int64_t)cnt, (int64_t)wave_maxn - base);
+        for (int k = kmax - 1; k >= 0; --k) {
             const uint32_t jj = (uint32_t)base + (uint32_t)k;
             PairEval e;
             const float4 g2 = s_g[2][k], g3 = s_g[3][k];
@@ -263,7 +274,7 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
                 const float4 a0 = s_a[0][k], a1 = s_a[1][k];
                 const float o = g2.w;
                 const float om = 1.0f - e.a;
-                const float rin = 1.0f / om;
+                const float rin = __builtin_amdgcn_rcpf(om);
                 const float Tk = T * rin;
                 const float wgt = e.a * Tk;
                 const float zr = e.z - rmean;
@@ -297,10 +308,38 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
                     gr[14] = dLdz;
                 }
             }
+            // 16-lane row sums with DPP, then the last lane of each of the
+            // four rows adds its row sum into the workgroup accumulator.
+            // Components no lane of the wave produced are skipped.
+            const bool any_surf = ballot64(bl && e.surf) != 0ull;
+            const bool any_flat = ballot64(bl && !e.surf) != 0ull;
+            if (any_surf) {
 #pragma unroll
-            for (int i = 0; i < kNumGrad; ++i) {
-                const float sum = wave_sum_to_lane63(gr[i]);
-                if (lane63 && sum != 0.f) atomicAdd(&s_acc[k][i], sum);
+                for (int i = 0; i < 9; ++i) gr[i] = row_sum16(gr[i]);
+                gr[12] = row_sum16(gr[12]);
+                gr[13] = row_sum16(gr[13]);
+            }
+            if (any_flat) {
+                gr[9] = row_sum16(gr[9]);
+                gr[10] = row_sum16(gr[10]);
+            }
+#pragma unroll
+            for (int i = 14; i < kNumGrad; ++i) gr[i] = row_sum16(gr[i]);
+            gr[11] = row_sum16(gr[11]);
+            if (row_last) {
+                if (any_surf) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) atomicAdd(&s_acc[k][i], gr[i]);
+                    atomicAdd(&s_acc[k][12], gr[12]);
+                    atomicAdd(&s_acc[k][13], gr[13]);
+                }
+                if (any_flat) {
+                    atomicAdd(&s_acc[k][9], gr[9]);
+                    atomicAdd(&s_acc[k][10], gr[10]);
+                }
+#pragma unroll
+                for (int i = 14; i < kNumGrad; ++i) atomicAdd(&s_acc[k][i], gr[i]);
+                atomicAdd(&s_acc[k][11], gr[11]);
             }
         }
         __syncthreads();
@@ -353,13 +392,18 @@ void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cam
 #undef SR_FWD
 }
 
+// Records per LDS batch of the backward (fewer than the workgroup size keeps
+// the LDS footprint, and hence occupancy, in check).
+constexpr int kBwdBatch = 128;
+
 template <int TW, int TH>
 void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
                 const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, const float* alpha,
                 const float* depth, const float* dist, const float* T_final, const uint32_t* n_contrib,
                 const float* dC, const float* dA, const float* dD, const float* dN, const float* dS,
                 float* grad_rec) {
-    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app, vals,
+    constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
+    hipLaunchKernelGGL((k_render_bwd<TW, TH, B>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app, vals,
                        ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, grad_rec);
 }
 
