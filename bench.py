@@ -67,9 +67,12 @@ class Pipeline:
         self.dC = torch.zeros_like(self.rast.color)
         self.need = self.rast.plan_capacity(params, slack=1.02)
 
-    STAGES = ("preprocess", "bin_sort", "forward+stats", "loss", "backward_raster", "backward_project")
+    STAGES = ("preprocess", "bin_sort", "train_raster", "backward_project")
+    STAGES_UNFUSED = ("preprocess", "bin_sort", "forward+stats", "loss", "backward_raster", "backward_project")
 
-    def step(self, ev=None):
+    def step(self, ev=None, fused=True):
+        """One training step; the compositing is the fused forward + loss +
+        backward launch (fused=True) or the three separate launches."""
         r = self.rast
         rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
         rec(0)
@@ -77,14 +80,18 @@ class Pipeline:
         rec(1)
         r.bin()
         rec(2)
-        r.forward(stats=self.stats, accumulate=True)
-        rec(3)
-        r.loss(self.mask, self.target, 0.5, 1.0, self.dA, self.dC)
-        rec(4)
-        r.backward_raster(dC=self.dC, dA=self.dA)
-        rec(5)
+        if fused:
+            r.train_step_raster(self.mask, self.target, 0.5, 1.0, stats=self.stats, accumulate=True)
+            rec(3)
+        else:
+            r.forward(stats=self.stats, accumulate=True)
+            rec(3)
+            r.loss(self.mask, self.target, 0.5, 1.0, self.dA, self.dC)
+            rec(4)
+            r.backward_raster(dC=self.dC, dA=self.dA)
+            rec(5)
         r.backward_project(self.p, self.g)
-        rec(6)
+        rec(4 if fused else 6)
 
 
 def cpu_baseline(scene, seconds_budget=20.0):
@@ -191,19 +198,23 @@ def main():
     mean_ms = dict(zip(Pipeline.STAGES, stage_ms.mean(axis=0)))
     fwd_ops = FWD_OPS_BLEND * B + FWD_OPS_SKIP * (R - B)
     bwd_ops = BWD_OPS_BLEND * B + BWD_OPS_SKIP * max(R_bwd - B, 0)
-    roof = {
-        "forward": {"bound": "alu", "achieved": fwd_ops / (mean_ms["forward+stats"] * 1e-3) / 1e12,
-                    "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s"},
-        "backward_raster": {"bound": "alu", "achieved": bwd_ops / (mean_ms["backward_raster"] * 1e-3) / 1e12,
-                            "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s"},
-    }
-    for k, r in roof.items():
-        r["frac"] = r["achieved"] / r["peak"]
-        r["traffic"] = None
-    dom = max(roof, key=lambda k: mean_ms["forward+stats" if k == "forward" else k])
-    result["roofline"] = dict(roof[dom], kernel=dom)
-    result["roofline_all"] = roof
+    ops = fwd_ops + bwd_ops
+    achieved = ops / (mean_ms["train_raster"] * 1e-3) / 1e12
+    result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                          "frac": achieved / (VALU_PEAK / 1e12), "traffic": None,
+                          "kernel": "k_train_raster (fused forward + loss + backward compositing)",
+                          "ops_per_launch": ops}
     result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd})
+
+    # the same step with separate forward / loss / backward launches
+    ns_u = len(Pipeline.STAGES_UNFUSED)
+    ev_u = [[torch.cuda.Event(enable_timing=True) for _ in range(ns_u + 1)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        pipe.step(ev_u[k], fused=False)
+    torch.cuda.synchronize()
+    st_u = np.array([[ev_u[k][i].elapsed_time(ev_u[k][i + 1]) for i in range(ns_u)] for k in range(args.steps)])
+    result["unfused"] = {"ms_per_step": float(st_u.sum(axis=1).mean()),
+                         "stage_ms_mean": dict(zip(Pipeline.STAGES_UNFUSED, [float(x) for x in st_u.mean(axis=0)]))}
 
     if not args.no_graph:
         g = torch.cuda.CUDAGraph()

@@ -213,6 +213,24 @@ sr_status sr_background_loss(int32_t V, const sr_camera *cams_host, const sr_cam
                              size_t ws_bytes, float *loss, float *dL_dalpha, float *dL_dcolor,
                              void *stream);
 
+/* Fused training step of the compositing, one launch for all views: per
+ * tile, the forward of sr_render_forward (same outputs, same decisions;
+ * occlusion statistics when hits/max_alpha/max_weight are given), the masked
+ * L1 + background loss gradients of sr_background_loss for every pixel
+ * (Eq. 1, Eq. 2; mask [P] uint8, target [3P]), and the backward of
+ * sr_backward_raster, with the per-pixel state kept on chip.
+ *   tile_loss [2T]  scratch: per-tile partial sums
+ *   loss [2V+1]     as sr_background_loss (sums in tile order)
+ *   grad_rec        as sr_backward_raster (zeros on entry; gradients added)
+ * Follow with sr_backward_project for the parameter gradients. */
+sr_status sr_train_step_raster(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                               const sr_camera *cams_dev, const float *geom, const float *app,
+                               const uint32_t *vals, const uint32_t *ranges, const uint8_t *mask,
+                               const float *target, float gamma, float w_c, float *color, float *alpha,
+                               float *depth, float *normal, float *dist, float *T_final,
+                               uint32_t *n_contrib, uint32_t *hits, float *max_alpha, float *max_weight,
+                               float *tile_loss, float *loss, float *grad_rec, void *stream);
+
 /* Occlusion-aware pruning statistics (Section 4.3): the compositing
  * decisions of sr_render_forward without shading.  For every blended
  * (pixel, surfel) pair: hits[g] += 1, max_alpha[g] = max(., a),

@@ -51,15 +51,12 @@ def _store(d: Dict[str, dict]):
 
 def time_step(rast: Rasterizer, p: Params, g: Params, mask, target, stats, steps: int = 3) -> float:
     """Mean milliseconds of one training step on the current stream."""
-    dA = torch.zeros_like(rast.alpha)
-    dC = torch.zeros_like(rast.color)
 
     def step():
         rast.preprocess(p)
         rast.bin()
-        rast.forward(stats=stats, accumulate=True)
-        rast.loss(mask, target, 0.5, 1.0, dA, dC)
-        rast.backward(p, g, dC=dC, dA=dA)
+        rast.train_step_raster(mask, target, 0.5, 1.0, stats=stats, accumulate=True)
+        rast.backward_project(p, g)
 
     step()
     torch.cuda.synchronize()

@@ -347,6 +347,38 @@ sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_
                       "sr_prune_contrib");
 }
 
+sr_status sr_train_step_raster(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
+                               const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
+                               const uint32_t* ranges, const uint8_t* mask, const float* target, float gamma,
+                               float w_c, float* color, float* alpha, float* depth, float* normal, float* dist,
+                               float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
+                               float* max_weight, float* tile_loss, float* loss, float* grad_rec, void* stream) {
+    SR_TRY(check_cfg(cfg));
+    SR_TRY(check_nv(N, V));
+    int total_tiles = 0;
+    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr));
+    if (total_tiles > 0) {
+        SR_NEED(geom); SR_NEED(app); SR_NEED(vals); SR_NEED(ranges); SR_NEED(mask); SR_NEED(target);
+        SR_NEED(color); SR_NEED(alpha); SR_NEED(depth); SR_NEED(normal); SR_NEED(dist); SR_NEED(T_final);
+        SR_NEED(n_contrib); SR_NEED(tile_loss); SR_NEED(loss); SR_NEED(grad_rec);
+    }
+    const bool st = hits || max_alpha || max_weight;
+    if (st && !(hits && max_alpha && max_weight))
+        return fail(SR_ERR_ARG, "hits, max_alpha and max_weight must be given together");
+    hipStream_t s = (hipStream_t)stream;
+    if (st && !(cfg->flags & SR_FLAG_ACCUMULATE) && N > 0) {
+        SR_TRY(hip_status(sr::fill_f32((float*)hits, 0.f, (uint64_t)N, s), "clear hits"));
+        SR_TRY(hip_status(sr::fill_f32(max_alpha, 0.f, (uint64_t)N, s), "clear max_alpha"));
+        SR_TRY(hip_status(sr::fill_f32(max_weight, 0.f, (uint64_t)N, s), "clear max_weight"));
+    }
+    if (total_tiles == 0) return SR_OK;
+    SR_TRY(hip_status(sr::launch_train_raster(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, mask, target,
+                                              gamma, w_c, color, alpha, depth, normal, dist, T_final, n_contrib, hits,
+                                              max_alpha, max_weight, tile_loss, grad_rec, s),
+                      "sr_train_step_raster"));
+    return hip_status(sr::launch_loss_from_tiles(V, cams_dev, tile_loss, gamma, w_c, loss, s), "loss totals");
+}
+
 sr_status sr_render_count(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
                           const sr_camera* cams_dev, const float* geom, const uint32_t* vals, const uint32_t* ranges,
                           uint64_t* counts, void* stream) {

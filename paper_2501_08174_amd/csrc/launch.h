@@ -44,6 +44,16 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
                              const float* dN, const float* dS, float* grad_rec, hipStream_t s);
 
+hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
+                               const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
+                               const uint8_t* mask, const float* target, float gamma, float w_c, float* color,
+                               float* alpha, float* depth, float* normal, float* dist, float* T_final,
+                               uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
+                               float* tile_loss, float* grad_rec, hipStream_t s);
+
+hipError_t launch_loss_from_tiles(int V, const sr_camera* cams, const float* tile_loss, float gamma, float w_c,
+                                  float* loss, hipStream_t s);
+
 hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, uint8_t* mask, hipStream_t s);
 
 int loss_chunks(int64_t max_hw);

@@ -95,7 +95,38 @@ k_loss_total(int V, float gamma, float w_c, float* __restrict__ loss) {
     if (threadIdx.x == 0) loss[2 * V] = t / (float)V;
 }
 
+// Per-view totals from the per-tile partial sums of the fused training step
+// (tiles of a view are contiguous), summed in tile order.
+__global__ void __launch_bounds__(kNT)
+k_loss_tiles(const sr_camera* __restrict__ cams, int V, const float* __restrict__ tile_loss,
+             float* __restrict__ loss) {
+    __shared__ float s[kNT];
+    const int v = blockIdx.x;
+    const sr_camera& c = cams[v];
+    const int T0 = c.tile_offset, nt = c.tiles_x * c.tiles_y;
+    float lb = 0.f, l1 = 0.f;
+    for (int i = threadIdx.x; i < nt; i += kNT) {
+        lb += tile_loss[2 * (size_t)(T0 + i)];
+        l1 += tile_loss[2 * (size_t)(T0 + i) + 1];
+    }
+    lb = block_sum(lb, s);
+    l1 = block_sum(l1, s);
+    if (threadIdx.x == 0) {
+        const float HW = (float)c.width * (float)c.height;
+        loss[v] = lb / HW;
+        loss[V + v] = l1 / (3.0f * HW);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_loss_from_tiles(int V, const sr_camera* cams, const float* tile_loss, float gamma, float w_c,
+                                  float* loss, hipStream_t s) {
+    if (V == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_loss_tiles, dim3(V), dim3(kNT), 0, s, cams, V, tile_loss, loss);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(kNT), 0, s, V, gamma, w_c, loss);
+    return hipGetLastError();
+}
 
 int loss_chunks(int64_t max_hw) { return (int)((max_hw + kChunk - 1) / kChunk); }
 

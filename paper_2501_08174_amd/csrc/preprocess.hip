@@ -123,18 +123,26 @@ __device__ __forceinline__ void cross3d(const double* a, const double* b, double
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-template <bool SHADE>
+// DEG: SH degree of the colour (0..3), or -1 to skip shading (pruning pass).
+// One thread per (surfel g, view v), t = g * V + v: the views of one surfel
+// sit in adjacent lanes, so the parameter loads of a wave are shared and the
+// surfel is read from HBM once per batch; in_frustum must hold zeros on entry
+// (each thread that keeps the surfel stores 1).
+template <int DEG>
 __global__ void __launch_bounds__(256)
 k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ scales,
              const float* __restrict__ quats, const float* __restrict__ opac,
-             const float* __restrict__ sh, int sh_degree, int sh_stride, float alpha_min,
+             const float* __restrict__ sh, int sh_stride, float alpha_min,
              int tile_w, int tile_h, int V, const sr_camera* __restrict__ cams,
              float4* __restrict__ geom, float4* __restrict__ app, ushort4* __restrict__ rect,
              uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_key,
              uint8_t* __restrict__ in_frustum) {
 #pragma clang fp contract(off)
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= N) return;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (uint64_t)N * (uint64_t)V) return;
+    const int g = (int)(t / (uint64_t)V);
+    const int v = (int)(t - (uint64_t)g * (uint64_t)V);
+    const size_t r = (size_t)v * N + g;
     const double mu[3] = {(double)means[3 * g], (double)means[3 * g + 1], (double)means[3 * g + 2]};
     const double su = scales[2 * g], sv = scales[2 * g + 1];
     const float o32 = opac[g];
@@ -153,109 +161,103 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
     const double rf = sqrt(rf2);
     const bool cull_opac = o32 < alpha_min;
 
-    float shc[48];
-    int K = 0;
-    if (SHADE) {
-        K = (sh_degree + 1) * (sh_degree + 1);
-        const float* s = sh + (size_t)g * sh_stride * 3;
-        for (int i = 0; i < 3 * K; ++i) shc[i] = s[i];
+    Cam64 c;
+    load_cam64(cams[v], c);
+    double p[3], au[3], av[3], nc[3];
+    for (int i = 0; i < 3; ++i) {
+        p[i] = rowdot(&c.R[3 * i], mu[0], mu[1], mu[2]) + c.t[i];
+        au[i] = su * rowdot(&c.R[3 * i], tu[0], tu[1], tu[2]);
+        av[i] = sv * rowdot(&c.R[3 * i], tv[0], tv[1], tv[2]);
+        nc[i] = rowdot(&c.R[3 * i], nn[0], nn[1], nn[2]);
     }
-    const float mu32[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
+    const double dnp = (nc[0] * p[0] + nc[1] * p[1]) + nc[2] * p[2];
+    if (dnp > 0.0) { nc[0] = -nc[0]; nc[1] = -nc[1]; nc[2] = -nc[2]; }
+    // rows of M = K [a_u a_v p]
+    double m1[3], m2[3], m3[3];
+    const double* col[3] = {au, av, p};
+    for (int j = 0; j < 3; ++j) {
+        m1[j] = c.fx * col[j][0] + c.cx * col[j][2];
+        m2[j] = c.fy * col[j][1] + c.cy * col[j][2];
+        m3[j] = col[j][2];
+    }
+    const double pz = p[2];
+    bool culled = cull_opac || (pz <= c.znear) || ((pz * pz) <= rs2 * (au[2] * au[2] + av[2] * av[2]));
+    int ilo = 0, ihi = -1, jlo = 0, jhi = -1;
+    double ccx = 0.0, ccy = 0.0;
+    if (!culled) {
+        const double d13 = conic_dot(rs2, m1, m3), d11 = conic_dot(rs2, m1, m1);
+        const double d23 = conic_dot(rs2, m2, m3), d22 = conic_dot(rs2, m2, m2);
+        const double d33 = conic_dot(rs2, m3, m3);
+        const double dx_ = d13 * d13 - d11 * d33, dy_ = d23 * d23 - d22 * d33;
+        const double sdx = sqrt(dx_ > 0.0 ? dx_ : 0.0);
+        const double sdy = sqrt(dy_ > 0.0 ? dy_ : 0.0);
+        const double xa = (d13 - sdx) / d33, xb = (d13 + sdx) / d33;
+        const double ya = (d23 - sdy) / d33, yb = (d23 + sdy) / d33;
+        ccx = m1[2] / m3[2];
+        ccy = m2[2] / m3[2];
+        const double xmin = fmin(fmin(xa, xb), ccx - rf), xmax = fmax(fmax(xa, xb), ccx + rf);
+        const double ymin = fmin(fmin(ya, yb), ccy - rf), ymax = fmax(fmax(ya, yb), ccy + rf);
+        // numpy-style NaN propagation: any NaN operand empties the rectangle
+        const bool nan = isnan(dx_) || isnan(dy_) || isnan(xa) || isnan(xb) || isnan(ya) ||
+                         isnan(yb) || isnan(ccx) || isnan(ccy) || isnan(rf);
+        const double flo = fmax(ceil(xmin - 0.5), 0.0), fhi = fmin(floor(xmax - 0.5), c.W - 1.0);
+        const double glo = fmax(ceil(ymin - 0.5), 0.0), ghi = fmin(floor(ymax - 0.5), c.H - 1.0);
+        if (nan || !(flo <= fhi) || !(glo <= ghi)) {
+            culled = true;
+        } else {
+            ilo = (int)flo; ihi = (int)fhi; jlo = (int)glo; jhi = (int)ghi;
+        }
+    }
+    if (culled) {
+        tiles_touched[r] = 0u;
+        depth_key[r] = 0xFFFFFFFFu;
+        rect[r] = make_ushort4(0, 0, 0, 0);
+        return;
+    }
+    if (in_frustum) in_frustum[g] = 1;
+    const int txlo = ilo / tile_w, txhi = ihi / tile_w, tylo = jlo / tile_h, tyhi = jhi / tile_h;
+    tiles_touched[r] = (uint32_t)((txhi - txlo + 1) * (tyhi - tylo + 1));
+    depth_key[r] = __float_as_uint((float)pz);
+    rect[r] = make_ushort4((unsigned short)ilo, (unsigned short)ihi, (unsigned short)jlo, (unsigned short)jhi);
+    // inverse homography columns: A = m2 x m3, B = m3 x m1, C = m1 x m2;
+    // shifted to the float32 centre: C' = C + A cx + B cy
+    double A[3], B[3], C[3];
+    cross3d(m2, m3, A);
+    cross3d(m3, m1, B);
+    cross3d(m1, m2, C);
+    const float cx32 = (float)ccx, cy32 = (float)ccy;
+    double Cs[3];
+    for (int i = 0; i < 3; ++i) Cs[i] = (C[i] + A[i] * (double)cx32) + B[i] * (double)cy32;
+    geom[4 * r + 0] = make_float4((float)A[0], (float)A[1], (float)A[2], (float)B[0]);
+    geom[4 * r + 1] = make_float4((float)B[1], (float)B[2], (float)Cs[0], (float)Cs[1]);
+    geom[4 * r + 2] = make_float4((float)Cs[2], cx32, cy32, o32);
+    geom[4 * r + 3] = make_float4((float)m3[0], (float)m3[1], (float)m3[2], (float)L);
+    if (DEG >= 0) {
+        constexpr int K = (DEG + 1) * (DEG + 1);
+        const float* cp = cams[v].campos;
+        float d0 = means[3 * g] - cp[0], d1 = means[3 * g + 1] - cp[1], d2 = means[3 * g + 2] - cp[2];
+        const float inv = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+        d0 *= inv; d1 *= inv; d2 *= inv;
+        float Y[16];
+        sh_basis(DEG, d0, d1, d2, Y);
+        const float* shg = sh + (size_t)g * sh_stride * 3;
+        float rgb[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            rgb[0] += Y[k] * shg[3 * k + 0];
+            rgb[1] += Y[k] * shg[3 * k + 1];
+            rgb[2] += Y[k] * shg[3 * k + 2];
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0f ? rgb[ch] : 0.0f;
+        app[2 * r + 0] = make_float4(rgb[0], rgb[1], rgb[2], (float)nc[0]);
+        app[2 * r + 1] = make_float4((float)nc[1], (float)nc[2], 0.0f, 0.0f);
+    }
+}
 
-    bool any_visible = false;
-    for (int v = 0; v < V; ++v) {
-        Cam64 c;
-        load_cam64(cams[v], c);
-        const size_t r = (size_t)v * N + g;
-        double p[3], au[3], av[3], nc[3];
-        for (int i = 0; i < 3; ++i) {
-            p[i] = rowdot(&c.R[3 * i], mu[0], mu[1], mu[2]) + c.t[i];
-            au[i] = su * rowdot(&c.R[3 * i], tu[0], tu[1], tu[2]);
-            av[i] = sv * rowdot(&c.R[3 * i], tv[0], tv[1], tv[2]);
-            nc[i] = rowdot(&c.R[3 * i], nn[0], nn[1], nn[2]);
-        }
-        const double dnp = (nc[0] * p[0] + nc[1] * p[1]) + nc[2] * p[2];
-        if (dnp > 0.0) { nc[0] = -nc[0]; nc[1] = -nc[1]; nc[2] = -nc[2]; }
-        // rows of M = K [a_u a_v p]
-        double m1[3], m2[3], m3[3];
-        const double* col[3] = {au, av, p};
-        for (int j = 0; j < 3; ++j) {
-            m1[j] = c.fx * col[j][0] + c.cx * col[j][2];
-            m2[j] = c.fy * col[j][1] + c.cy * col[j][2];
-            m3[j] = col[j][2];
-        }
-        const double pz = p[2];
-        bool culled = cull_opac || (pz <= c.znear) ||
-                      ((pz * pz) <= rs2 * (au[2] * au[2] + av[2] * av[2]));
-        int ilo = 0, ihi = -1, jlo = 0, jhi = -1;
-        double ccx = 0.0, ccy = 0.0;
-        if (!culled) {
-            const double d13 = conic_dot(rs2, m1, m3), d11 = conic_dot(rs2, m1, m1);
-            const double d23 = conic_dot(rs2, m2, m3), d22 = conic_dot(rs2, m2, m2);
-            const double d33 = conic_dot(rs2, m3, m3);
-            const double dx_ = d13 * d13 - d11 * d33, dy_ = d23 * d23 - d22 * d33;
-            const double sdx = sqrt(dx_ > 0.0 ? dx_ : 0.0);
-            const double sdy = sqrt(dy_ > 0.0 ? dy_ : 0.0);
-            const double xa = (d13 - sdx) / d33, xb = (d13 + sdx) / d33;
-            const double ya = (d23 - sdy) / d33, yb = (d23 + sdy) / d33;
-            ccx = m1[2] / m3[2];
-            ccy = m2[2] / m3[2];
-            const double xmin = fmin(fmin(xa, xb), ccx - rf), xmax = fmax(fmax(xa, xb), ccx + rf);
-            const double ymin = fmin(fmin(ya, yb), ccy - rf), ymax = fmax(fmax(ya, yb), ccy + rf);
-            // numpy-style NaN propagation: any NaN operand empties the rectangle
-            const bool nan = isnan(dx_) || isnan(dy_) || isnan(xa) || isnan(xb) || isnan(ya) ||
-                             isnan(yb) || isnan(ccx) || isnan(ccy) || isnan(rf);
-            const double flo = fmax(ceil(xmin - 0.5), 0.0), fhi = fmin(floor(xmax - 0.5), c.W - 1.0);
-            const double glo = fmax(ceil(ymin - 0.5), 0.0), ghi = fmin(floor(ymax - 0.5), c.H - 1.0);
-            if (nan || !(flo <= fhi) || !(glo <= ghi)) {
-                culled = true;
-            } else {
-                ilo = (int)flo; ihi = (int)fhi; jlo = (int)glo; jhi = (int)ghi;
-            }
-        }
-        if (culled) {
-            tiles_touched[r] = 0u;
-            depth_key[r] = 0xFFFFFFFFu;
-            rect[r] = make_ushort4(0, 0, 0, 0);
-            continue;
-        }
-        any_visible = true;
-        const int txlo = ilo / tile_w, txhi = ihi / tile_w, tylo = jlo / tile_h, tyhi = jhi / tile_h;
-        tiles_touched[r] = (uint32_t)((txhi - txlo + 1) * (tyhi - tylo + 1));
-        depth_key[r] = __float_as_uint((float)pz);
-        rect[r] = make_ushort4((unsigned short)ilo, (unsigned short)ihi, (unsigned short)jlo,
-                               (unsigned short)jhi);
-        // inverse homography columns: A = m2 x m3, B = m3 x m1, C = m1 x m2;
-        // shifted to the float32 centre: C' = C + A cx + B cy
-        double A[3], B[3], C[3];
-        cross3d(m2, m3, A);
-        cross3d(m3, m1, B);
-        cross3d(m1, m2, C);
-        const float cx32 = (float)ccx, cy32 = (float)ccy;
-        double Cs[3];
-        for (int i = 0; i < 3; ++i) Cs[i] = (C[i] + A[i] * (double)cx32) + B[i] * (double)cy32;
-        geom[4 * r + 0] = make_float4((float)A[0], (float)A[1], (float)A[2], (float)B[0]);
-        geom[4 * r + 1] = make_float4((float)B[1], (float)B[2], (float)Cs[0], (float)Cs[1]);
-        geom[4 * r + 2] = make_float4((float)Cs[2], cx32, cy32, o32);
-        geom[4 * r + 3] = make_float4((float)m3[0], (float)m3[1], (float)m3[2], (float)L);
-        if (SHADE) {
-            const float* cp = cams[v].campos;
-            float d0 = mu32[0] - cp[0], d1 = mu32[1] - cp[1], d2 = mu32[2] - cp[2];
-            const float inv = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-            d0 *= inv; d1 *= inv; d2 *= inv;
-            float Y[16];
-            sh_basis(sh_degree, d0, d1, d2, Y);
-            float rgb[3];
-            for (int ch = 0; ch < 3; ++ch) {
-                float acc = 0.5f;
-                for (int k = 0; k < K; ++k) acc += Y[k] * shc[3 * k + ch];
-                rgb[ch] = acc > 0.0f ? acc : 0.0f;
-            }
-            app[2 * r + 0] = make_float4(rgb[0], rgb[1], rgb[2], (float)nc[0]);
-            app[2 * r + 1] = make_float4((float)nc[1], (float)nc[2], 0.0f, 0.0f);
-        }
-    }
-    if (in_frustum) in_frustum[g] = any_visible ? 1 : 0;
+__global__ void k_zero_u8(uint8_t* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -273,9 +275,10 @@ __device__ __forceinline__ void cross3f(const float* a, const float* b, float* o
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+template <int DEG>
 __global__ void __launch_bounds__(256)
 k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict__ scales,
-                 const float* __restrict__ quats, const float* __restrict__ sh, int sh_degree,
+                 const float* __restrict__ quats, const float* __restrict__ sh,
                  int sh_stride, int V, const sr_camera* __restrict__ cams,
                  const float4* __restrict__ geom, const float4* __restrict__ app,
                  const uint32_t* __restrict__ tiles_touched, float* __restrict__ grad_rec,
@@ -291,11 +294,12 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
     const float tu[3] = {1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y + w * z), 2.0f * (x * z - w * y)};
     const float tv[3] = {2.0f * (x * y - w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z + w * x)};
     const float nn[3] = {2.0f * (x * z + w * y), 2.0f * (y * z - w * x), 1.0f - 2.0f * (x * x + y * y)};
-    const int K = (sh_degree + 1) * (sh_degree + 1);
+    constexpr int K = (DEG + 1) * (DEG + 1);
 
     float dmu[3] = {0, 0, 0}, dsu = 0, dsv = 0, dopac = 0;
     float dtu[3] = {0, 0, 0}, dtv[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
-    float dsh[48];
+    float dsh[3 * K];
+#pragma unroll
     for (int i = 0; i < 3 * K; ++i) dsh[i] = 0.0f;
     const float* shg = sh + (size_t)g * sh_stride * 3;
 
@@ -396,9 +400,10 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
             const float il = 1.0f / len;
             d[0] *= il; d[1] *= il; d[2] *= il;
             float Y[16], gx[16], gy[16], gz[16];
-            sh_basis(sh_degree, d[0], d[1], d[2], Y);
-            sh_basis_grad(sh_degree, d[0], d[1], d[2], gx, gy, gz);
+            sh_basis(DEG, d[0], d[1], d[2], Y);
+            sh_basis_grad(DEG, d[0], d[1], d[2], gx, gy, gz);
             float dd[3] = {0, 0, 0};
+#pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float f0 = shg[3 * k], f1 = shg[3 * k + 1], f2 = shg[3 * k + 2];
                 dsh[3 * k + 0] += Y[k] * dr[0];
@@ -430,6 +435,7 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
     g_scales[2 * g + 1] += dsv;
     g_opac[g] += dopac;
     float* gs = g_sh + (size_t)g * sh_stride * 3;
+#pragma unroll
     for (int i = 0; i < 3 * K; ++i) gs[i] += dsh[i];
 }
 
@@ -441,17 +447,23 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
                              uint32_t* tiles_touched, uint32_t* depth_key, uint8_t* in_frustum,
                              hipStream_t stream) {
     if (N == 0) return hipSuccess;
-    dim3 grid((N + 255) / 256), block(256);
-    if (app)
-        hipLaunchKernelGGL(k_preprocess<true>, grid, block, 0, stream, N, means, scales, quats, opac, sh,
-                           cfg.sh_degree, cfg.sh_stride, cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev,
-                           (float4*)geom, (float4*)app, (ushort4*)rect, tiles_touched, depth_key,
-                           in_frustum);
-    else
-        hipLaunchKernelGGL(k_preprocess<false>, grid, block, 0, stream, N, means, scales, quats, opac, sh,
-                           cfg.sh_degree, cfg.sh_stride, cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev,
-                           (float4*)geom, (float4*)nullptr, (ushort4*)rect, tiles_touched, depth_key,
-                           in_frustum);
+    if (in_frustum) hipLaunchKernelGGL(k_zero_u8, dim3((N + 255) / 256), dim3(256), 0, stream, in_frustum, N);
+    const uint64_t threads = (uint64_t)N * (uint64_t)V;
+    if (threads == 0) return hipGetLastError();
+    dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+    const int deg = app ? cfg.sh_degree : -1;
+#define SR_PRE(D)                                                                                             \
+    hipLaunchKernelGGL(k_preprocess<D>, grid, block, 0, stream, N, means, scales, quats, opac, sh, cfg.sh_stride, \
+                       cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev, (float4*)geom, (float4*)app,        \
+                       (ushort4*)rect, tiles_touched, depth_key, in_frustum)
+    switch (deg) {
+        case 0: SR_PRE(0); break;
+        case 1: SR_PRE(1); break;
+        case 2: SR_PRE(2); break;
+        case 3: SR_PRE(3); break;
+        default: SR_PRE(-1); break;
+    }
+#undef SR_PRE
     return hipGetLastError();
 }
 
@@ -461,10 +473,18 @@ hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means
                                  float* grad_rec, float* g_means, float* g_scales, float* g_quats,
                                  float* g_opac, float* g_sh, hipStream_t stream) {
     if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3((N + 255) / 256), dim3(256), 0, stream, N, means, scales,
-                       quats, sh, cfg.sh_degree, cfg.sh_stride, V, cams_dev, (const float4*)geom,
-                       (const float4*)app, tiles_touched, grad_rec, g_means, g_scales, g_quats, g_opac,
-                       g_sh);
+    dim3 grid((N + 255) / 256), block(256);
+#define SR_PREB(D)                                                                                          \
+    hipLaunchKernelGGL(k_preprocess_bwd<D>, grid, block, 0, stream, N, means, scales, quats, sh,            \
+                       cfg.sh_stride, V, cams_dev, (const float4*)geom, (const float4*)app, tiles_touched, \
+                       grad_rec, g_means, g_scales, g_quats, g_opac, g_sh)
+    switch (cfg.sh_degree) {
+        case 0: SR_PREB(0); break;
+        case 1: SR_PREB(1); break;
+        case 2: SR_PREB(2); break;
+        default: SR_PREB(3); break;
+    }
+#undef SR_PREB
     return hipGetLastError();
 }
 

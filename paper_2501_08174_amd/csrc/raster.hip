@@ -22,7 +22,7 @@ namespace {
 
 // Global tile id of this workgroup; pixel coordinates of this thread.
 struct TileCtx {
-    int v, W, H, ix, iy;
+    int tile, v, W, H, ix, iy;
     bool inside;
     int64_t pix_off;
     uint32_t start, n;
@@ -33,6 +33,7 @@ template <int TW, int TH>
 __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int V,
                                          const uint2* __restrict__ ranges, TileCtx& t) {
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    t.tile = tile;
     t.v = view_of_tile(cams, V, tile);
     const sr_camera& c = cams[t.v];
     const int local = tile - c.tile_offset;
@@ -53,35 +54,47 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
 // statistics, 4 count reached/blended pairs (work accounting).
 constexpr int kShade = 1, kStats = 2, kCount = 4;
 
-template <int TW, int TH, int MODE>
-__global__ void __launch_bounds__(TW * TH)
-k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
-             const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
-             RasterConsts rc, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
-             float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
-             uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
-             float* __restrict__ max_weight, unsigned long long* __restrict__ counts) {
+// Per-pixel state at the end of the forward pass.
+struct PixFwd {
+    float T, C0, C1, C2, N0, N1, N2, S0, S1, S2, zref;
+    uint32_t last;
+};
+
+// LDS staging of the forward: NT records per batch.
+template <int NT, int MODE>
+struct FwdSmem {
+    float4 g[kGeomF4][NT];
+    float4 a[(MODE & kShade) ? kAppF4 : 1][(MODE & kShade) ? NT : 1];
+    uint32_t id[(MODE & kStats) ? NT : 1];
+};
+
+// LDS staging and per-record accumulators of the backward.
+template <int BATCH>
+struct BwdSmem {
+    float4 g[kGeomF4][BATCH];
+    float4 a[kAppF4][BATCH];
+    uint32_t rec[BATCH];
+    float acc[BATCH][kNumGrad];
+    uint32_t maxn;
+};
+
+// Front to back over the tile list; every thread owns one pixel.
+template <int NT, int MODE>
+__device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
+                                         const float4* __restrict__ app, const uint32_t* __restrict__ vals,
+                                         const RasterConsts& rc, FwdSmem<NT, MODE>& sm, PixFwd& st,
+                                         uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
+                                         float* __restrict__ max_weight, uint64_t& n_reached, uint64_t& n_blended) {
     constexpr bool SHADE = (MODE & kShade) != 0;
     constexpr bool STATS = (MODE & kStats) != 0;
     constexpr bool COUNT = (MODE & kCount) != 0;
-    constexpr int NT = TW * TH;
-    uint64_t n_reached = 0, n_blended = 0;
-    __shared__ float4 s_g[kGeomF4][NT];
-    __shared__ float4 s_a[SHADE ? kAppF4 : 1][SHADE ? NT : 1];
-    __shared__ uint32_t s_id[STATS ? NT : 1];
-    TileCtx t;
-    tile_ctx<TW, TH>(cams, V, ranges, t);
-    const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     const int tid = threadIdx.x;
     const bool lane63 = __lane_id() == 63;
-
-    float T = 1.0f;
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, S0 = 0.f, S1 = 0.f, S2 = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
-    float zref = 0.f;
+    st.T = 1.0f;
+    st.C0 = st.C1 = st.C2 = st.N0 = st.N1 = st.N2 = st.S0 = st.S1 = st.S2 = st.zref = 0.f;
+    st.last = 0;
     bool have_ref = false;
-    uint32_t last = 0;
     bool done = !t.inside;
-
     for (uint32_t base = 0; base < t.n; base += NT) {
         if (__syncthreads_and(done)) break;
         const uint32_t j = base + tid;
@@ -89,49 +102,49 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
             const uint32_t g = vals[t.start + j];
             const size_t r = (size_t)t.v * N + g;
 #pragma unroll
-            for (int q = 0; q < kGeomF4; ++q) s_g[q][tid] = geom[kGeomF4 * r + q];
+            for (int q = 0; q < kGeomF4; ++q) sm.g[q][tid] = geom[kGeomF4 * r + q];
             if (SHADE) {
 #pragma unroll
-                for (int q = 0; q < kAppF4; ++q) s_a[q][tid] = app[kAppF4 * r + q];
+                for (int q = 0; q < kAppF4; ++q) sm.a[q][tid] = app[kAppF4 * r + q];
             }
-            if (STATS) s_id[tid] = g;
+            if (STATS) sm.id[tid] = g;
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, t.n - base);
         if (ballot64(!done) == 0ull) continue;
         for (int k = 0; k < cnt; ++k) {
             PairEval e;
-            const float4 g2 = s_g[2][k], g3 = s_g[3][k];
-            eval_test(s_g[0][k], s_g[1][k], g2, g3, px, py, e);
+            const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
+            eval_test(sm.g[0][k], sm.g[1][k], g2, g3, px, py, e);
             if (COUNT) n_reached += (uint64_t)__popcll(ballot64(!done));
             bool blend = !done && e.pass;
             // no pixel of this wave takes the entry: nothing changes
             if (ballot64(blend) == 0ull) continue;
             eval_finish(g2, g3, rc.alpha_max, e);
-            float Tn = T * (1.0f - e.a);
+            const float Tn = st.T * (1.0f - e.a);
             if (blend && Tn < rc.t_min) {
                 done = true;
                 blend = false;
             }
             float wgt = 0.f;
             if (blend) {
-                wgt = e.a * T;
-                if (!have_ref) { zref = e.z; have_ref = true; }
-                const float zs = e.z - zref;
+                wgt = e.a * st.T;
+                if (!have_ref) { st.zref = e.z; have_ref = true; }
+                const float zs = e.z - st.zref;
                 if (SHADE) {
-                    const float4 a0 = s_a[0][k], a1 = s_a[1][k];
-                    C0 = __builtin_fmaf(wgt, a0.x, C0);
-                    C1 = __builtin_fmaf(wgt, a0.y, C1);
-                    C2 = __builtin_fmaf(wgt, a0.z, C2);
-                    N0 = __builtin_fmaf(wgt, a0.w, N0);
-                    N1 = __builtin_fmaf(wgt, a1.x, N1);
-                    N2 = __builtin_fmaf(wgt, a1.y, N2);
+                    const float4 a0 = sm.a[0][k], a1 = sm.a[1][k];
+                    st.C0 = __builtin_fmaf(wgt, a0.x, st.C0);
+                    st.C1 = __builtin_fmaf(wgt, a0.y, st.C1);
+                    st.C2 = __builtin_fmaf(wgt, a0.z, st.C2);
+                    st.N0 = __builtin_fmaf(wgt, a0.w, st.N0);
+                    st.N1 = __builtin_fmaf(wgt, a1.x, st.N1);
+                    st.N2 = __builtin_fmaf(wgt, a1.y, st.N2);
                 }
-                S0 += wgt;
-                S1 = __builtin_fmaf(wgt, zs, S1);
-                S2 = __builtin_fmaf(wgt * zs, zs, S2);
-                T = Tn;
-                last = base + (uint32_t)k + 1u;
+                st.S0 += wgt;
+                st.S1 = __builtin_fmaf(wgt, zs, st.S1);
+                st.S2 = __builtin_fmaf(wgt * zs, zs, st.S2);
+                st.T = Tn;
+                st.last = base + (uint32_t)k + 1u;
             }
             if (COUNT) n_blended += (uint64_t)__popcll(ballot64(blend));
             if (STATS) {
@@ -140,7 +153,7 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
                     const float ma = wave_max_to_lane63(blend ? e.a : 0.f);
                     const float mw = wave_max_to_lane63(wgt);
                     if (lane63) {
-                        const uint32_t g = s_id[k];
+                        const uint32_t g = sm.id[k];
                         atomicAdd(&hits[g], (uint32_t)__popcll(bm));
                         atomicMax((uint32_t*)&max_alpha[g], __float_as_uint(ma));
                         atomicMax((uint32_t*)&max_weight[g], __float_as_uint(mw));
@@ -150,96 +163,122 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
             if (ballot64(!done) == 0ull) break;
         }
     }
-    if (COUNT && __lane_id() == 0) {
+}
+
+// Forward outputs of one pixel from its final state.
+struct PixOut {
+    float C0, C1, C2, A, D, Dist;
+};
+
+__device__ __forceinline__ PixOut pix_outputs(const PixFwd& st, const TileCtx& t) {
+    PixOut o;
+    o.C0 = st.C0 + st.T * t.bg[0];
+    o.C1 = st.C1 + st.T * t.bg[1];
+    o.C2 = st.C2 + st.T * t.bg[2];
+    o.A = 1.0f - st.T;
+    // depth = sum w z = S1 + zref S0 ; dist = 2 (S0 S2 - S1^2) with z shifted by zref
+    o.D = __builtin_fmaf(st.zref, st.S0, st.S1);
+    const float dd = 2.0f * (st.S0 * st.S2 - st.S1 * st.S1);
+    o.Dist = dd > 0.f ? dd : 0.f;
+    return o;
+}
+
+__device__ __forceinline__ void write_outputs(const PixFwd& st, const PixOut& o, const TileCtx& t,
+                                              float* __restrict__ color, float* __restrict__ alpha,
+                                              float* __restrict__ depth, float* __restrict__ normal,
+                                              float* __restrict__ dist, float* __restrict__ T_final,
+                                              uint32_t* __restrict__ n_contrib) {
+    const int64_t HW = (int64_t)t.W * t.H;
+    const int64_t p = (int64_t)t.iy * t.W + t.ix;
+    const int64_t o1 = t.pix_off + p;
+    const int64_t o3 = 3 * t.pix_off + p;
+    color[o3] = o.C0;
+    color[o3 + HW] = o.C1;
+    color[o3 + 2 * HW] = o.C2;
+    normal[o3] = st.N0;
+    normal[o3 + HW] = st.N1;
+    normal[o3 + 2 * HW] = st.N2;
+    alpha[o1] = o.A;
+    depth[o1] = o.D;
+    dist[o1] = o.Dist;
+    T_final[o1] = st.T;
+    n_contrib[o1] = st.last;
+}
+
+template <int TW, int TH, int MODE>
+__global__ void __launch_bounds__(TW * TH)
+k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
+             const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+             RasterConsts rc, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
+             float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
+             uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
+             float* __restrict__ max_weight, unsigned long long* __restrict__ counts) {
+    constexpr int NT = TW * TH;
+    __shared__ FwdSmem<NT, MODE> sm;
+    TileCtx t;
+    tile_ctx<TW, TH>(cams, V, ranges, t);
+    const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
+    PixFwd st;
+    uint64_t n_reached = 0, n_blended = 0;
+    fwd_tile<NT, MODE>(t, px, py, N, geom, app, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached, n_blended);
+    if ((MODE & kCount) && __lane_id() == 0) {
         atomicAdd(&counts[0], (unsigned long long)n_reached);
         atomicAdd(&counts[1], (unsigned long long)n_blended);
     }
-    if (t.inside) {
-        const int64_t HW = (int64_t)t.W * t.H;
-        const int64_t p = (int64_t)t.iy * t.W + t.ix;
-        const int64_t o1 = t.pix_off + p;
-        const int64_t o3 = 3 * t.pix_off + p;
-        if (SHADE) {
-            color[o3] = C0 + T * t.bg[0];
-            color[o3 + HW] = C1 + T * t.bg[1];
-            color[o3 + 2 * HW] = C2 + T * t.bg[2];
-            normal[o3] = N0;
-            normal[o3 + HW] = N1;
-            normal[o3 + 2 * HW] = N2;
-            alpha[o1] = 1.0f - T;
-            // depth = sum w z = S1 + zref S0 ; dist = 2 (S0 S2 - S1^2) with z shifted by zref
-            depth[o1] = __builtin_fmaf(zref, S0, S1);
-            const float dd = 2.0f * (S0 * S2 - S1 * S1);
-            dist[o1] = dd > 0.f ? dd : 0.f;
-            T_final[o1] = T;
-            n_contrib[o1] = last;
-        }
+    if ((MODE & kShade) && t.inside) write_outputs(st, pix_outputs(st, t), t, color, alpha, depth, normal, dist,
+                                                   T_final, n_contrib);
+}
+
+// Per-pixel inputs of the backward.
+struct PixBwd {
+    uint32_t ncon;
+    float T, gC0, gC1, gC2, gA, gD, gN0, gN1, gN2, gS, S0, rmean, Q, Wacc;
+};
+
+__device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float Tf, uint32_t ncon, float S0,
+                                             float D, float Dist) {
+    pb.ncon = ncon;
+    pb.T = Tf;
+    pb.S0 = S0;
+    pb.rmean = 0.f;
+    pb.Q = 0.f;
+    if (S0 > 0.f) {
+        pb.rmean = D / S0;
+        pb.Q = Dist / (2.0f * S0);
     }
+    pb.Wacc = (pb.gC0 * t.bg[0] + pb.gC1 * t.bg[1] + pb.gC2 * t.bg[2]) * Tf;
 }
 
 // Backward: per pixel, walk the tile list back to front from the last
 // blended entry, recovering T_k = T_{k+1} / (1 - a_k).  With g_k the
 // derivative of the loss by the blending weight w_k of entry k and
 // W_k = sum_{j>k} g_j w_j (+ the background term), dL/da_k = T_k g_k -
-// W_k / (1 - a_k).  Per-record gradients are summed over the wavefront with
+// W_k / (1 - a_k).  Per-record gradients are summed over 16-lane rows with
 // DPP, over the workgroup in LDS, then added to grad_rec with one atomic per
 // (tile, record, component).
-template <int TW, int TH, int BATCH>
-__global__ void __launch_bounds__(TW * TH)
-k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
-             const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
-             RasterConsts rc, const float* __restrict__ alpha, const float* __restrict__ depth,
-             const float* __restrict__ dist, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
-             const float* __restrict__ dC, const float* __restrict__ dA, const float* __restrict__ dD,
-             const float* __restrict__ dNrm, const float* __restrict__ dDist, float* __restrict__ grad_rec) {
-    constexpr int NT = TW * TH;
+template <int NT, int BATCH>
+__device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
+                                         const float4* __restrict__ app, const uint32_t* __restrict__ vals,
+                                         const RasterConsts& rc, BwdSmem<BATCH>& sm, PixBwd pb,
+                                         float* __restrict__ grad_rec) {
     static_assert(BATCH <= NT, "one record per thread and batch");
-    __shared__ float4 s_g[kGeomF4][BATCH];
-    __shared__ float4 s_a[kAppF4][BATCH];
-    __shared__ uint32_t s_rec[BATCH];
-    __shared__ float s_acc[BATCH][kNumGrad];
-    __shared__ uint32_t s_maxn;
-    TileCtx t;
-    tile_ctx<TW, TH>(cams, V, ranges, t);
-    const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     const int tid = threadIdx.x;
     const bool row_last = (__lane_id() & 15) == 15;
-
-    uint32_t ncon = 0;
-    float T = 1.f, gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gA = 0.f, gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gS = 0.f;
-    float S0 = 0.f, rmean = 0.f, Q = 0.f, Wacc = 0.f;
-    if (t.inside) {
-        const int64_t HW = (int64_t)t.W * t.H;
-        const int64_t p = (int64_t)t.iy * t.W + t.ix;
-        const int64_t o1 = t.pix_off + p, o3 = 3 * t.pix_off + p;
-        ncon = n_contrib[o1];
-        T = T_final[o1];
-        if (dC) { gC0 = dC[o3]; gC1 = dC[o3 + HW]; gC2 = dC[o3 + 2 * HW]; }
-        if (dA) gA = dA[o1];
-        if (dD) gD = dD[o1];
-        if (dNrm) { gN0 = dNrm[o3]; gN1 = dNrm[o3 + HW]; gN2 = dNrm[o3 + 2 * HW]; }
-        if (dDist) gS = dDist[o1];
-        S0 = alpha[o1];
-        if (S0 > 0.f) {
-            rmean = depth[o1] / S0;
-            Q = dist[o1] / (2.0f * S0);
-        }
-        Wacc = (gC0 * t.bg[0] + gC1 * t.bg[1] + gC2 * t.bg[2]) * T;
-    }
-    if (tid == 0) s_maxn = 0u;
     __syncthreads();
-    atomicMax(&s_maxn, ncon);
+    if (tid == 0) sm.maxn = 0u;
     __syncthreads();
-    const uint32_t maxn = s_maxn;
+    atomicMax(&sm.maxn, pb.ncon);
+    __syncthreads();
+    const uint32_t maxn = sm.maxn;
     if (maxn == 0u) return;
     // entries at or beyond the wave's own last contributor concern no lane
-    uint32_t wave_maxn = ncon;
+    uint32_t wave_maxn = pb.ncon;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const uint32_t o = (uint32_t)__shfl_xor((int)wave_maxn, off, 64);
         wave_maxn = o > wave_maxn ? o : wave_maxn;
     }
-
+    float T = pb.T, Wacc = pb.Wacc;
     for (int64_t base = ((int64_t)(maxn - 1) / BATCH) * BATCH; base >= 0; base -= BATCH) {
         __syncthreads();
         if (tid < BATCH) {
@@ -248,13 +287,13 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
                 const uint32_t g = vals[t.start + j];
                 const size_t r = (size_t)t.v * N + g;
 #pragma unroll
-                for (int q = 0; q < kGeomF4; ++q) s_g[q][tid] = geom[kGeomF4 * r + q];
+                for (int q = 0; q < kGeomF4; ++q) sm.g[q][tid] = geom[kGeomF4 * r + q];
 #pragma unroll
-                for (int q = 0; q < kAppF4; ++q) s_a[q][tid] = app[kAppF4 * r + q];
-                s_rec[tid] = (uint32_t)r;
+                for (int q = 0; q < kAppF4; ++q) sm.a[q][tid] = app[kAppF4 * r + q];
+                sm.rec[tid] = (uint32_t)r;
             }
 #pragma unroll
-            for (int i = 0; i < kNumGrad; ++i) s_acc[tid][i] = 0.f;
+            for (int i = 0; i < kNumGrad; ++i) sm.acc[tid][i] = 0.f;
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)BATCH, maxn - (uint32_t)base);
@@ -262,30 +301,31 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         for (int k = kmax - 1; k >= 0; --k) {
             const uint32_t jj = (uint32_t)base + (uint32_t)k;
             PairEval e;
-            const float4 g2 = s_g[2][k], g3 = s_g[3][k];
-            eval_test(s_g[0][k], s_g[1][k], g2, g3, px, py, e);
-            const bool bl = (jj < ncon) && e.pass;
+            const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
+            eval_test(sm.g[0][k], sm.g[1][k], g2, g3, px, py, e);
+            const bool bl = (jj < pb.ncon) && e.pass;
             if (ballot64(bl) == 0ull) continue;
             eval_finish(g2, g3, rc.alpha_max, e);
             float gr[kNumGrad];
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) gr[i] = 0.f;
             if (bl) {
-                const float4 a0 = s_a[0][k], a1 = s_a[1][k];
+                const float4 a0 = sm.a[0][k], a1 = sm.a[1][k];
                 const float o = g2.w;
                 const float om = 1.0f - e.a;
                 const float rin = __builtin_amdgcn_rcpf(om);
                 const float Tk = T * rin;
                 const float wgt = e.a * Tk;
-                const float zr = e.z - rmean;
-                const float gk = gC0 * a0.x + gC1 * a0.y + gC2 * a0.z + gA + gD * e.z +
-                                 gN0 * a0.w + gN1 * a1.x + gN2 * a1.y + gS * 2.0f * (Q + S0 * zr * zr);
+                const float zr = e.z - pb.rmean;
+                const float gk = pb.gC0 * a0.x + pb.gC1 * a0.y + pb.gC2 * a0.z + pb.gA + pb.gD * e.z +
+                                 pb.gN0 * a0.w + pb.gN1 * a1.x + pb.gN2 * a1.y +
+                                 pb.gS * 2.0f * (pb.Q + pb.S0 * zr * zr);
                 const float dLda = Tk * gk - Wacc * rin;
                 Wacc = __builtin_fmaf(gk, wgt, Wacc);
                 T = Tk;
-                gr[15] = gC0 * wgt; gr[16] = gC1 * wgt; gr[17] = gC2 * wgt;
-                gr[18] = gN0 * wgt; gr[19] = gN1 * wgt; gr[20] = gN2 * wgt;
-                const float dLdz = wgt * (gD + 4.0f * gS * S0 * zr);
+                gr[15] = pb.gC0 * wgt; gr[16] = pb.gC1 * wgt; gr[17] = pb.gC2 * wgt;
+                gr[18] = pb.gN0 * wgt; gr[19] = pb.gN1 * wgt; gr[20] = pb.gN2 * wgt;
+                const float dLdz = wgt * (pb.gD + 4.0f * pb.gS * pb.S0 * zr);
                 float dLdo = 0.f, dLdG = 0.f;
                 if (!e.clamped) {
                     dLdo = dLda * e.G;
@@ -329,29 +369,135 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
             if (row_last) {
                 if (any_surf) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) atomicAdd(&s_acc[k][i], gr[i]);
-                    atomicAdd(&s_acc[k][12], gr[12]);
-                    atomicAdd(&s_acc[k][13], gr[13]);
+                    for (int i = 0; i < 9; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
+                    atomicAdd(&sm.acc[k][12], gr[12]);
+                    atomicAdd(&sm.acc[k][13], gr[13]);
                 }
                 if (any_flat) {
-                    atomicAdd(&s_acc[k][9], gr[9]);
-                    atomicAdd(&s_acc[k][10], gr[10]);
+                    atomicAdd(&sm.acc[k][9], gr[9]);
+                    atomicAdd(&sm.acc[k][10], gr[10]);
                 }
 #pragma unroll
-                for (int i = 14; i < kNumGrad; ++i) atomicAdd(&s_acc[k][i], gr[i]);
-                atomicAdd(&s_acc[k][11], gr[11]);
+                for (int i = 14; i < kNumGrad; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
+                atomicAdd(&sm.acc[k][11], gr[11]);
             }
         }
         __syncthreads();
         if (tid < cnt) {
-            float* dst = grad_rec + (size_t)s_rec[tid] * SR_GRAD_STRIDE;
+            float* dst = grad_rec + (size_t)sm.rec[tid] * SR_GRAD_STRIDE;
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) {
-                const float vsum = s_acc[tid][i];
+                const float vsum = sm.acc[tid][i];
                 if (vsum != 0.f) atomicAdd(&dst[i], vsum);
             }
         }
     }
+}
+
+template <int TW, int TH, int BATCH>
+__global__ void __launch_bounds__(TW * TH)
+k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
+             const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+             RasterConsts rc, const float* __restrict__ alpha, const float* __restrict__ depth,
+             const float* __restrict__ dist, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+             const float* __restrict__ dC, const float* __restrict__ dA, const float* __restrict__ dD,
+             const float* __restrict__ dNrm, const float* __restrict__ dDist, float* __restrict__ grad_rec) {
+    __shared__ BwdSmem<BATCH> sm;
+    TileCtx t;
+    tile_ctx<TW, TH>(cams, V, ranges, t);
+    const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
+    PixBwd pb;
+    pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = 0.f;
+    pb.ncon = 0;
+    pb.T = 1.f;
+    pb.S0 = pb.rmean = pb.Q = pb.Wacc = 0.f;
+    if (t.inside) {
+        const int64_t HW = (int64_t)t.W * t.H;
+        const int64_t p = (int64_t)t.iy * t.W + t.ix;
+        const int64_t o1 = t.pix_off + p, o3 = 3 * t.pix_off + p;
+        if (dC) { pb.gC0 = dC[o3]; pb.gC1 = dC[o3 + HW]; pb.gC2 = dC[o3 + 2 * HW]; }
+        if (dA) pb.gA = dA[o1];
+        if (dD) pb.gD = dD[o1];
+        if (dNrm) { pb.gN0 = dNrm[o3]; pb.gN1 = dNrm[o3 + HW]; pb.gN2 = dNrm[o3 + 2 * HW]; }
+        if (dDist) pb.gS = dDist[o1];
+        pix_bwd_init(pb, t, T_final[o1], n_contrib[o1], alpha[o1], depth[o1], dist[o1]);
+    }
+    bwd_tile<TW * TH, BATCH>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
+}
+
+// One training step of the compositing for a tile: forward with the
+// occlusion statistics, the masked L1 + background loss gradients of every
+// pixel (Eq. 1, Eq. 2) and the backward, with the per-pixel state kept in
+// registers between the phases.  Per-tile loss partial sums go to
+// tile_loss[2*tile] (L_b numerator, L1 numerator).
+template <int TW, int TH, int BATCH, bool STATS>
+__global__ void __launch_bounds__(TW * TH)
+k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
+               const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+               RasterConsts rc, const uint8_t* __restrict__ mask, const float* __restrict__ target, float gamma,
+               float w_c, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
+               float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
+               uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
+               float* __restrict__ max_weight, float* __restrict__ tile_loss, float* __restrict__ grad_rec) {
+    constexpr int NT = TW * TH;
+    constexpr int MODE = kShade | (STATS ? kStats : 0);
+    constexpr size_t kF = sizeof(FwdSmem<NT, MODE>), kB = sizeof(BwdSmem<BATCH>);
+    __shared__ __align__(16) unsigned char smem[kF > kB ? kF : kB];
+    __shared__ float s_red[NT];
+    TileCtx t;
+    tile_ctx<TW, TH>(cams, V, ranges, t);
+    const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
+    PixFwd st;
+    uint64_t n0 = 0, n1 = 0;
+    fwd_tile<NT, MODE>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st, hits,
+                       max_alpha, max_weight, n0, n1);
+    const PixOut o = pix_outputs(st, t);
+    PixBwd pb;
+    pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = 0.f;
+    pb.ncon = 0;
+    pb.T = 1.f;
+    pb.S0 = pb.rmean = pb.Q = pb.Wacc = 0.f;
+    float lb = 0.f, l1 = 0.f;
+    if (t.inside) {
+        write_outputs(st, o, t, color, alpha, depth, normal, dist, T_final, n_contrib);
+        // the same per-pixel loss terms and gradients as sr_background_loss
+        const int64_t HW = (int64_t)t.W * t.H;
+        const int64_t p = (int64_t)t.iy * t.W + t.ix;
+        const int64_t o1 = t.pix_off + p, o3 = 3 * t.pix_off + p;
+        const float ga = gamma / ((float)HW * (float)V);
+        const float gc = w_c / (3.0f * (float)HW * (float)V);
+        const float m = mask[o1] ? 1.0f : 0.0f;
+        lb = o.A * (1.0f - m);
+        pb.gA = ga * (1.0f - m);
+        const float Cv[3] = {o.C0, o.C1, o.C2};
+        float gC[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float d = m * Cv[ch] - m * target[o3 + ch * HW];
+            l1 += fabsf(d);
+            gC[ch] = d > 0.f ? gc * m : (d < 0.f ? -gc * m : 0.f);
+        }
+        pb.gC0 = gC[0]; pb.gC1 = gC[1]; pb.gC2 = gC[2];
+        pix_bwd_init(pb, t, st.T, st.last, o.A, o.D, o.Dist);
+    }
+    // per-tile loss partials, fixed-order tree
+    __syncthreads();
+    s_red[threadIdx.x] = lb;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s_red[threadIdx.x] += s_red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile] = s_red[0];
+    __syncthreads();
+    s_red[threadIdx.x] = l1;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s_red[threadIdx.x] += s_red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile + 1] = s_red[0];
+    bwd_tile<NT, BATCH>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec);
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, float v, uint64_t n) {
@@ -363,6 +509,10 @@ __global__ void k_prune_mask(int N, const float* __restrict__ max_alpha, float t
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g < N) mask[g] = max_alpha[g] < tau ? 1 : 0;
 }
+
+// Records per LDS batch of the backward (fewer than the workgroup size keeps
+// the LDS footprint, and hence occupancy, in check).
+constexpr int kBwdBatch = 128;
 
 template <int TW, int TH, int MODE>
 void fwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
@@ -392,10 +542,6 @@ void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cam
 #undef SR_FWD
 }
 
-// Records per LDS batch of the backward (fewer than the workgroup size keeps
-// the LDS footprint, and hence occupancy, in check).
-constexpr int kBwdBatch = 128;
-
 template <int TW, int TH>
 void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
                 const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, const float* alpha,
@@ -405,6 +551,23 @@ void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, in
     constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
     hipLaunchKernelGGL((k_render_bwd<TW, TH, B>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app, vals,
                        ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, grad_rec);
+}
+
+template <int TW, int TH>
+void train_launch(bool stats, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
+                  const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc,
+                  const uint8_t* mask, const float* target, float gamma, float w_c, float* color, float* alpha,
+                  float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits,
+                  float* max_alpha, float* max_weight, float* tile_loss, float* grad_rec) {
+    constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
+    if (stats)
+        hipLaunchKernelGGL((k_train_raster<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
+                           geom, app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist,
+                           T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec);
+    else
+        hipLaunchKernelGGL((k_train_raster<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
+                           geom, app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist,
+                           T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec);
 }
 
 // Compiled tile shapes (the binning takes any shape; the raster kernels are
@@ -459,6 +622,26 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                          (const uint2*)ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, \
                          grad_rec);                                                                           \
         return hipGetLastError();                                                                             \
+    }
+    SR_TILE_SHAPES(SR_TS)
+#undef SR_TS
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
+                               const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
+                               const uint8_t* mask, const float* target, float gamma, float w_c, float* color,
+                               float* alpha, float* depth, float* normal, float* dist, float* T_final,
+                               uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
+                               float* tile_loss, float* grad_rec, hipStream_t s) {
+    if (total_tiles == 0) return hipSuccess;
+    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+#define SR_TS(W, H)                                                                                               \
+    if (cfg.tile_w == W && cfg.tile_h == H) {                                                                    \
+        train_launch<W, H>(hits != nullptr, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, \
+                           vals, (const uint2*)ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, \
+                           dist, T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec);           \
+        return hipGetLastError();                                                                                \
     }
     SR_TILE_SHAPES(SR_TS)
 #undef SR_TS

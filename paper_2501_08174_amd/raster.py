@@ -219,6 +219,21 @@ class Rasterizer:
              _stream(stream))
         return self.loss_out
 
+    def train_step_raster(self, mask: torch.Tensor, target: torch.Tensor, gamma: float = 0.5, w_c: float = 1.0,
+                          stats=None, accumulate: bool = False, stream=None):
+        """Fused forward + loss gradients + backward compositing (one launch);
+        follow with backward_project."""
+        if getattr(self, "tile_loss", None) is None:
+            self.tile_loss = torch.zeros(2 * max(self.views.T, 1), dtype=torch.float32, device=self.device)
+        h, ma, mw = (None, None, None) if stats is None else stats
+        cfg = self._cfg(accumulate)
+        call("sr_train_step_raster", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask),
+             _ptr(target), float(gamma), float(w_c), _ptr(self.color), _ptr(self.alpha), _ptr(self.depth),
+             _ptr(self.normal), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma),
+             _ptr(mw), _ptr(self.tile_loss), _ptr(self.loss_out), _ptr(self._grad_rec()), _stream(stream))
+        return self.loss_out
+
     def prune_stats(self, hits, max_alpha, max_weight, accumulate=False, stream=None):
         cfg = self._cfg(accumulate)
         call("sr_prune_contrib", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
@@ -244,6 +259,41 @@ class Rasterizer:
             raise _lib.SurfelRasterError(_lib.SR_ERR_CAPACITY,
                                          f"instance capacity {self.capacity} exceeded: {need} needed")
         return need
+
+
+@dataclass
+class PruneStats:
+    hits: torch.Tensor          # int32 [N] blended (pixel, surfel) pairs
+    max_alpha: torch.Tensor     # float32 [N] largest blended alpha
+    max_weight: torch.Tensor    # float32 [N] largest blending weight a T
+    in_frustum: torch.Tensor    # uint8 [N] not culled in some view
+    mask: torch.Tensor          # uint8 [N] 1 = prune (max_alpha < tau)
+
+
+def prune_contrib(params: Params, cams: Sequence, views_per_chunk: int = 25, tau: float = ALPHA_MIN,
+                  tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None) -> PruneStats:
+    """Occlusion-aware pruning pass (Section 4.3) over every view: projection
+    without shading, binning and the compositing decisions, accumulating the
+    statistics over views (and over calls when ``stats`` is given), then the
+    mask.  Views are processed in chunks to bound the instance buffers."""
+    n = params.means.shape[0]
+    dev = params.means.device
+    if stats is None:
+        stats = PruneStats(torch.zeros(n, dtype=torch.int32, device=dev), torch.zeros(n, device=dev),
+                           torch.zeros(n, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
+                           torch.zeros(n, dtype=torch.uint8, device=dev))
+    for v0 in range(0, len(cams), views_per_chunk):
+        views = ViewBatch(cams[v0:v0 + views_per_chunk], tile=tile, device=dev)
+        rast = Rasterizer(n, views, 0, shade=False, device=dev)
+        rast.plan_capacity(params, slack=slack)
+        rast.preprocess(params)
+        rast.bin()
+        rast.check_capacity()
+        rast.prune_stats(stats.hits, stats.max_alpha, stats.max_weight, accumulate=True)
+        torch.bitwise_or(stats.in_frustum, rast.in_frustum[:n], out=stats.in_frustum)
+        del rast
+    stats.mask = prune_mask(stats.max_alpha, tau)
+    return stats
 
 
 def prune_mask(max_alpha: torch.Tensor, tau: float = ALPHA_MIN, stream=None) -> torch.Tensor:

@@ -243,31 +243,20 @@ def test_config5_crop():
 # --------------------------------------------------------------------------
 
 def test_config4_pruning_shell_scene():
+    """Section 4.3 on the shell scene over 100 views: every interior surfel is
+    inside the frustum of every view yet never blended (pruned), the mask is
+    exactly 'never blended', and a sampled set of surfels has the oracle's
+    statistics."""
+    from paper_2501_08174_amd.raster import prune_contrib
     sc = scenes.make_config4()
     N = sc.n
-    dev = "cuda"
     p = Params.from_scene(sc)
-    hits = torch.zeros(N, dtype=torch.int32, device=dev)
-    ma = torch.zeros(N, device=dev)
-    mw = torch.zeros(N, device=dev)
-    inf = torch.zeros(N, dtype=torch.uint8, device=dev)
-    chunk = 20
-    for v0 in range(0, sc.v, chunk):
-        views = ViewBatch(sc.cams[v0:v0 + chunk])
-        rast = Rasterizer(N, views, 0, shade=False)
-        rast.plan_capacity(p)
-        rast.preprocess(p)
-        rast.bin()
-        rast.check_capacity()
-        rast.prune_stats(hits, ma, mw, accumulate=True)
-        inf |= rast.in_frustum[:N]
-        del rast
-    mask = prune_mask(ma).cpu().numpy().astype(bool)
-    h = hits.cpu().numpy()
-    infr = inf.cpu().numpy().astype(bool)
+    st = prune_contrib(p, sc.cams, views_per_chunk=20)
+    mask = st.mask.cpu().numpy().astype(bool)
+    h = st.hits.cpu().numpy()
+    infr = st.in_frustum.cpu().numpy().astype(bool)
     n_shell, n_inner = 300_000, 700_000
     inner = slice(n_shell, n_shell + n_inner)
-    # Section 4.3: the interior is inside the frustum of every view but never blended
     assert infr[inner].all()
     assert mask[inner].all() and (h[inner] == 0).all()
     assert np.array_equal(mask, h == 0)
@@ -275,3 +264,40 @@ def test_config4_pruning_shell_scene():
     print(f"pruned {mask.sum()} of {N}; shell kept {kept_shell:.3f}; exterior kept "
           f"{(~mask[n_shell + n_inner:]).mean():.3f}; in-frustum but pruned {(infr & mask).sum()}")
     assert kept_shell > 0.5
+    # sampled per-surfel check against the oracle over the first 10 views:
+    # every pixel of a sampled surfel's rectangle, in every view keeping it
+    sub_cams = sc.cams[:10]
+    st10 = prune_contrib(p, sub_cams)
+    sub = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0, sub_cams, sc.masks[:10])
+    geoms = _geoms_parallel(sub)
+    h10 = st10.hits.cpu().numpy()
+    ma10 = st10.max_alpha.cpu().numpy()
+    inf10 = st10.in_frustum.cpu().numpy().astype(bool)
+    rng = np.random.default_rng(44)
+    cand_shell = np.nonzero(inf10[:n_shell])[0]
+    cand_out = n_shell + n_inner + np.nonzero(inf10[n_shell + n_inner:])[0]
+    sample = np.concatenate([rng.choice(cand_shell, 8, replace=False), rng.choice(cand_out, 4, replace=False)])
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0)
+    checked = 0
+    for gid in sample:
+        hits_o, ma_o, tie = 0, 0.0, False
+        for v in range(len(sub_cams)):
+            g = geoms[v]
+            if g["culled"][gid]:
+                continue
+            rc = g["rect"][gid]
+            pix = crop_pixels(rc[0], rc[2], rc[1] - rc[0] + 1, rc[3] - rc[2] + 1)
+            res = render_pixels(P64, sub_cams[v], g, pix, RP)
+            pairs, a, w = res["pairs"]
+            sel = pairs[:, 1] == gid
+            hits_o += int(sel.sum())
+            if sel.any():
+                ma_o = max(ma_o, float(a[sel].max()))
+            tie |= bool(np.isin(gid, res["flag_ids"]))
+        if tie:
+            continue
+        assert h10[gid] == hits_o, (gid, h10[gid], hits_o)
+        assert abs(ma10[gid] - ma_o) <= 1e-5
+        checked += 1
+    print(f"sampled surfels checked against the oracle: {checked} of {sample.size}")
+    assert checked >= sample.size // 2

@@ -305,3 +305,52 @@ def test_capacity_overflow_is_reported():
     assert status == 1 and stored == 100 and need > 100
     with pytest.raises(Exception):
         run["rast"].check_capacity()
+
+
+# --------------------------------------------------------------------------
+# fused training step vs the separate calls
+# --------------------------------------------------------------------------
+
+def test_fused_train_step_matches_separate_calls():
+    """sr_train_step_raster = sr_render_forward (+statistics) +
+    sr_background_loss + sr_backward_raster, in one launch: identical forward
+    outputs and statistics, equal losses and gradients (atomic order aside)."""
+    sc = _ragged_scene(39, 500, 3)
+    rng = np.random.default_rng(9)
+    views = ViewBatch(sc.cams)
+    masks = torch.tensor(np.concatenate([rng.integers(0, 2, c.width * c.height) for c in sc.cams]).astype(np.uint8),
+                         device="cuda")
+    target = torch.tensor(rng.uniform(size=3 * views.P).astype(np.float32), device="cuda")
+    p = Params.from_scene(sc)
+    out = []
+    for fused in (False, True):
+        rast = Rasterizer(sc.n, views, 3, sh_stride=16)
+        rast.plan_capacity(p)
+        rast.preprocess(p)
+        rast.bin()
+        st = (torch.zeros(sc.n, dtype=torch.int32, device="cuda"), torch.zeros(sc.n, device="cuda"),
+              torch.zeros(sc.n, device="cuda"))
+        g = Params(*[torch.zeros_like(t) for t in (p.means, p.scales, p.quats, p.opac, p.sh)])
+        if fused:
+            loss = rast.train_step_raster(masks, target, 0.5, 1.0, stats=st)
+        else:
+            rast.forward(stats=st)
+            dA = torch.zeros_like(rast.alpha)
+            dC = torch.zeros_like(rast.color)
+            loss = rast.loss(masks, target, 0.5, 1.0, dA, dC)
+            rast.backward_raster(dC=dC, dA=dA)
+        rast.backward_project(p, g)
+        torch.cuda.synchronize()
+        out.append(dict(fwd={k: getattr(rast, k).cpu().numpy() for k in
+                             ("color", "alpha", "depth", "normal", "dist", "T_final", "n_contrib")},
+                        stats=[t.cpu().numpy() for t in st], loss=loss.cpu().numpy().copy(),
+                        grads=[t.cpu().numpy().astype(np.float64) for t in (g.means, g.scales, g.quats, g.opac,
+                                                                             g.sh)]))
+    a, b = out
+    for k in a["fwd"]:
+        np.testing.assert_array_equal(a["fwd"][k], b["fwd"][k], err_msg=k)
+    for x, y in zip(a["stats"], b["stats"]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_allclose(a["loss"], b["loss"], rtol=1e-5, atol=1e-7)
+    for x, y in zip(a["grads"], b["grads"]):
+        np.testing.assert_allclose(x, y, rtol=1e-4, atol=1e-6 * np.abs(y).max())
