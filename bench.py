@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tile", default="auto", help="WxH tile shape, or 'auto' to pick by timing")
+    ap.add_argument("--no-unfused", action="store_true", help="skip timing the separate-launch step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (reference for the HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -206,15 +209,26 @@ def main():
                           "ops_per_launch": ops}
     result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd})
 
-    # the same step with separate forward / loss / backward launches
-    ns_u = len(Pipeline.STAGES_UNFUSED)
-    ev_u = [[torch.cuda.Event(enable_timing=True) for _ in range(ns_u + 1)] for _ in range(args.steps)]
-    for k in range(args.steps):
-        pipe.step(ev_u[k], fused=False)
-    torch.cuda.synchronize()
-    st_u = np.array([[ev_u[k][i].elapsed_time(ev_u[k][i + 1]) for i in range(ns_u)] for k in range(args.steps)])
-    result["unfused"] = {"ms_per_step": float(st_u.sum(axis=1).mean()),
-                         "stage_ms_mean": dict(zip(Pipeline.STAGES_UNFUSED, [float(x) for x in st_u.mean(axis=0)]))}
+    if not args.no_unfused:
+        # the same step with separate forward / loss / backward launches
+        ns_u = len(Pipeline.STAGES_UNFUSED)
+        ev_u = [[torch.cuda.Event(enable_timing=True) for _ in range(ns_u + 1)] for _ in range(args.steps)]
+        for k in range(args.steps):
+            pipe.step(ev_u[k], fused=False)
+        torch.cuda.synchronize()
+        st_u = np.array([[ev_u[k][i].elapsed_time(ev_u[k][i + 1]) for i in range(ns_u)] for k in range(args.steps)])
+        result["unfused"] = {"ms_per_step": float(st_u.sum(axis=1).mean()),
+                             "stage_ms_mean": dict(zip(Pipeline.STAGES_UNFUSED,
+                                                       [float(x) for x in st_u.mean(axis=0)]))}
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = src.numel() * 4
+        del src, dst
 
     if not args.no_graph:
         g = torch.cuda.CUDAGraph()

@@ -226,14 +226,17 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
 
     with torch.no_grad():
         nsk = reached & ~gt
-        f_cut = (reached & ((a_raw - rp.alpha_min).abs() <= TIE_CUTOFF_REL * rp.alpha_min)).any(dim=1)
-        f_term = (nsk & ~skip & ((T_before * (1 - a) - rp.t_min).abs() <= TIE_TERM_REL * rp.t_min)).any(dim=1)
-        f_branch = (blended & ((Gs - Gf).abs() <= TIE_BRANCH)).any(dim=1)
-        f_clamp = (blended & ((a_raw - rp.alpha_max).abs() <= TIE_CLAMP)).any(dim=1)
+        e_cut = reached & ((a_raw - rp.alpha_min).abs() <= TIE_CUTOFF_REL * rp.alpha_min)
+        e_term = nsk & ~skip & ((T_before * (1 - a) - rp.t_min).abs() <= TIE_TERM_REL * rp.t_min)
+        e_branch = blended & ((Gs - Gf).abs() <= TIE_BRANCH)
+        e_clamp = blended & ((a_raw - rp.alpha_max).abs() <= TIE_CLAMP)
+        f_cut, f_term = e_cut.any(dim=1), e_term.any(dim=1)
+        f_branch, f_clamp = e_branch.any(dim=1), e_clamp.any(dim=1)
+        tie_entry = e_cut | e_term | e_branch | e_clamp
     return dict(color=color, alpha=alpha, depth=depth, normal=normal, dist=dist,
                 T_final=T_final, n_contrib=n_contrib, blended=blended, reached=reached,
                 a=a, w=w, z=z, surf=surf, skip=skip, first_stop=first_stop,
-                clamp=a_raw > rp.alpha_max,
+                clamp=a_raw > rp.alpha_max, tie_entry=tie_entry,
                 flag_cut=f_cut, flag_term=f_term, flag_branch=f_branch, flag_clamp=f_clamp)
 
 
@@ -259,7 +262,7 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
     res = {k: [] for k in OUT_KEYS}
     extra = {k: [] for k in ("n_contrib", "last_gid", "nblend", "flag_cut", "flag_term",
                              "flag_branch", "flag_clamp")}
-    pairs, flag_ids, decisions = [], [], []
+    pairs, flag_ids, tie_ids, decisions = [], [], [], []
     start = 0
     step = max(1, min(Pn, 1024))
     while start < Pn:
@@ -301,6 +304,8 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
             rch = out["reached"].numpy()
             fr, fc = np.nonzero(rch & fl[:, None])
             flag_ids.append(np.unique(gid_mat[fr, fc]))
+            te = out["tie_entry"].numpy()
+            tie_ids.append(np.unique(gid_mat[te]))
         if keep_decisions:
             decisions.append({k: out[k].detach().numpy() for k in
                               ("blended", "skip", "surf", "first_stop", "clamp")} | {"gid": gid_mat})
@@ -314,6 +319,7 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
     else:
         result["pairs"] = (np.zeros((0, 2), np.int64), np.zeros(0), np.zeros(0))
     result["flag_ids"] = np.unique(np.concatenate(flag_ids)) if flag_ids else np.zeros(0, np.int64)
+    result["tie_ids"] = np.unique(np.concatenate(tie_ids)) if tie_ids else np.zeros(0, np.int64)
     if keep_decisions:
         result["decisions"] = decisions
     return result

@@ -23,6 +23,8 @@ namespace {
 constexpr int kNT = 256;            // threads per block
 constexpr int kIPT = 8;             // keys per thread per radix sub-tile
 constexpr int kTile = kNT * kIPT;   // keys per radix sub-tile
+constexpr int kMaxDigitBits = 9;    // radix digits of up to 9 bits (512 buckets)
+constexpr int kMaxRadix = 1 << kMaxDigitBits;
 
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
@@ -149,9 +151,9 @@ k_vis_compact(uint64_t VN, int G, const uint32_t* __restrict__ tiles_touched,
 __global__ void __launch_bounds__(kNT)
 k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ count, int G, int shift, int bits,
              uint32_t* __restrict__ hist) {
-    __shared__ uint32_t s_h[4][256];
+    __shared__ uint32_t s_h[4][kMaxRadix];
     const int R = 1 << bits, w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < 4 * 256; i += kNT) (&s_h[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < 4 * kMaxRadix; i += kNT) (&s_h[0][0])[i] = 0;
     __syncthreads();
     uint32_t b, e;
     radix_chunk(*count, G, &b, &e);
@@ -192,32 +194,36 @@ k_radix_digit_scan(uint32_t* __restrict__ hist, int G, uint32_t* __restrict__ to
     if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
+// Every thread owns the two digits 2*tid and 2*tid + 1 of the per-digit
+// bookkeeping (up to 512 digits).
 __global__ void __launch_bounds__(kNT)
 k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
                 const uint32_t* __restrict__ count, int G, int shift, int bits,
                 const uint32_t* __restrict__ hist, const uint32_t* __restrict__ tot,
                 uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
-    __shared__ uint32_t s_off[256];
-    __shared__ uint32_t s_wcnt[4][256];
-    __shared__ uint32_t s_lstart[256];
+    __shared__ uint32_t s_off[kMaxRadix];
+    __shared__ uint32_t s_wcnt[4][kMaxRadix];
+    __shared__ uint32_t s_lstart[kMaxRadix];
     __shared__ uint32_t s_keys[kTile];
     __shared__ uint32_t s_vals[kTile];
     __shared__ uint32_t s_w[4];
     const int R = 1 << bits;
     const uint32_t mask = (uint32_t)R - 1u;
     const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    const int d0 = 2 * tid, d1 = 2 * tid + 1;
     uint32_t b, e;
     radix_chunk(*count, G, &b, &e);
     // global start of every digit for this block
     {
-        const uint32_t t = tid < R ? tot[tid] : 0u;
+        const uint32_t t0 = d0 < R ? tot[d0] : 0u, t1 = d1 < R ? tot[d1] : 0u;
         uint32_t all;
-        const uint32_t ex = block_excl_scan<uint32_t>(t, s_w, &all);
-        s_off[tid] = tid < R ? ex + hist[(size_t)tid * G + blockIdx.x] : 0u;
+        const uint32_t ex = block_excl_scan<uint32_t>(t0 + t1, s_w, &all);
+        s_off[d0] = d0 < R ? ex + hist[(size_t)d0 * G + blockIdx.x] : 0u;
+        s_off[d1] = d1 < R ? ex + t0 + hist[(size_t)d1 * G + blockIdx.x] : 0u;
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (uint32_t tb = b; tb < e; tb += kTile) {
-        for (int i = tid; i < 4 * 256; i += kNT) (&s_wcnt[0][0])[i] = 0u;
+        for (int i = tid; i < 4 * kMaxRadix; i += kNT) (&s_wcnt[0][0])[i] = 0u;
         __syncthreads();
         uint32_t kk[kIPT], vv[kIPT], rank[kIPT];
         int dg[kIPT];
@@ -246,17 +252,25 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
             rank[r] = old + before;
         }
         __syncthreads();
-        uint32_t dtot = 0;
+        uint32_t dt0, dt1;
         {
-            const uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
-            dtot = c0 + c1 + c2 + c3;
+            uint32_t c[2][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { c[0][q] = s_wcnt[q][d0]; c[1][q] = s_wcnt[q][d1]; }
+            dt0 = c[0][0] + c[0][1] + c[0][2] + c[0][3];
+            dt1 = c[1][0] + c[1][1] + c[1][2] + c[1][3];
             uint32_t all;
-            const uint32_t ls = block_excl_scan<uint32_t>(dtot, s_w, &all);
-            s_lstart[tid] = ls;
-            s_wcnt[0][tid] = 0u;
-            s_wcnt[1][tid] = c0;
-            s_wcnt[2][tid] = c0 + c1;
-            s_wcnt[3][tid] = c0 + c1 + c2;
+            const uint32_t ls = block_excl_scan<uint32_t>(dt0 + dt1, s_w, &all);
+            s_lstart[d0] = ls;
+            s_lstart[d1] = ls + dt0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int d = h ? d1 : d0;
+                s_wcnt[0][d] = 0u;
+                s_wcnt[1][d] = c[h][0];
+                s_wcnt[2][d] = c[h][0] + c[h][1];
+                s_wcnt[3][d] = c[h][0] + c[h][1] + c[h][2];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -277,7 +291,8 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
             vals_out[dst] = s_vals[i];
         }
         __syncthreads();
-        s_off[tid] += dtot;
+        s_off[d0] += dt0;
+        s_off[d1] += dt1;
         __syncthreads();
     }
 }
@@ -440,8 +455,8 @@ BinWs carve(void* base, uint64_t VN, uint64_t cap) {
     w.vk1 = (uint32_t*)take(VN * 4); w.vv1 = (uint32_t*)take(VN * 4);
     w.ik0 = (uint32_t*)take(cap * 4); w.iv0 = (uint32_t*)take(cap * 4);
     w.ik1 = (uint32_t*)take(cap * 4); w.iv1 = (uint32_t*)take(cap * 4);
-    w.hist = (uint32_t*)take(256ull * kMaxRadixBlocks * 4);
-    w.tot = (uint32_t*)take(256 * 4);
+    w.hist = (uint32_t*)take((uint64_t)kMaxRadix * kMaxRadixBlocks * 4);
+    w.tot = (uint32_t*)take(kMaxRadix * 4);
     w.vsum = (uint32_t*)take(kMaxRadixBlocks * 4);
     w.isum = (uint64_t*)take(kMaxRadixBlocks * 8);
     w.ioff = (uint64_t*)take(VN * 8);
@@ -457,7 +472,7 @@ uint32_t* radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uin
                      const uint32_t* count, uint64_t cap, int nbits, uint32_t* hist, uint32_t* tot,
                      hipStream_t s) {
     const int G = grid_for(cap);
-    const int passes = (nbits + 7) / 8;
+    const int passes = (nbits + kMaxDigitBits - 1) / kMaxDigitBits;
     if (passes == 0) {
         hipLaunchKernelGGL(k_copy_u32, dim3(1024), dim3(256), 0, s, count, v0, vals_dst);
         return k0;

@@ -136,4 +136,24 @@ __device__ __forceinline__ void eval_finish(const float4& g2, const float4& g3, 
     e.z = e.surf ? __builtin_fmaf(g3.x, e.u, __builtin_fmaf(g3.y, e.v, g3.z)) : g3.z;
 }
 
+// Per-pixel terms of the masked losses (Eq. 1 and the L1 part of Eq. 2) and
+// their gradients for L = (1/V) sum_v (w_c L1_v + gamma L_b,v); shared by the
+// loss kernel and the fused training step so both round identically.
+__device__ __forceinline__ void pixel_loss_grad(uint8_t mask, float A, const float* C, const float* I, float gamma,
+                                                float w_c, float HW, float V, float& lb, float& l1, float& gA,
+                                                float* gC) {
+#pragma clang fp contract(off)
+    const float ga = gamma / (HW * V);
+    const float gc = w_c / (3.0f * HW * V);
+    const float m = mask ? 1.0f : 0.0f;
+    lb += A * (1.0f - m);
+    gA = ga * (1.0f - m);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float d = m * C[ch] - m * I[ch];
+        l1 += fabsf(d);
+        gC[ch] = d > 0.f ? gc * m : (d < 0.f ? -gc * m : 0.f);
+    }
+}
+
 }  // namespace sr

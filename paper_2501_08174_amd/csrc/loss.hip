@@ -39,21 +39,25 @@ k_loss_partial(const sr_camera* __restrict__ cams, int V, const float* __restric
     float lb = 0.f, l1 = 0.f;
     if (b < HW) {
         const int64_t e = b + kChunk < HW ? b + kChunk : HW;
-        const float ga = gamma / ((float)HW * (float)V);
-        const float gc = w_c / (3.0f * (float)HW * (float)V);
         for (int64_t p = b + threadIdx.x; p < e; p += kNT) {
             const int64_t o1 = c.pix_offset + p;
-            const float m = mask[o1] ? 1.0f : 0.0f;
-            const float A = alpha[o1];
-            lb += A * (1.0f - m);
-            if (dL_dalpha) dL_dalpha[o1] = ga * (1.0f - m);
+            const int64_t o3 = 3 * c.pix_offset + p;
+            float C[3] = {0.f, 0.f, 0.f}, I[3] = {0.f, 0.f, 0.f}, gC[3], gA;
             if (color) {
-                const int64_t o3 = 3 * c.pix_offset + p;
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
-                    const float d = m * color[o3 + ch * HW] - m * target[o3 + ch * HW];
-                    l1 += fabsf(d);
-                    if (dL_dcolor) dL_dcolor[o3 + ch * HW] = d > 0.f ? gc * m : (d < 0.f ? -gc * m : 0.f);
+                    C[ch] = color[o3 + ch * HW];
+                    I[ch] = target[o3 + ch * HW];
+                }
+            }
+            float l1p = 0.f;
+            pixel_loss_grad(mask[o1], alpha[o1], C, I, gamma, w_c, (float)HW, (float)V, lb, l1p, gA, gC);
+            if (dL_dalpha) dL_dalpha[o1] = gA;
+            if (color) {
+                l1 += l1p;
+                if (dL_dcolor) {
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) dL_dcolor[o3 + ch * HW] = gC[ch];
                 }
             }
         }

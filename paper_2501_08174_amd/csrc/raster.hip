@@ -171,6 +171,7 @@ struct PixOut {
 };
 
 __device__ __forceinline__ PixOut pix_outputs(const PixFwd& st, const TileCtx& t) {
+#pragma clang fp contract(off)
     PixOut o;
     o.C0 = st.C0 + st.T * t.bg[0];
     o.C1 = st.C1 + st.T * t.bg[1];
@@ -237,6 +238,7 @@ struct PixBwd {
 
 __device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float Tf, uint32_t ncon, float S0,
                                              float D, float Dist) {
+#pragma clang fp contract(off)
     pb.ncon = ncon;
     pb.T = Tf;
     pb.S0 = S0;
@@ -464,19 +466,10 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
         const int64_t HW = (int64_t)t.W * t.H;
         const int64_t p = (int64_t)t.iy * t.W + t.ix;
         const int64_t o1 = t.pix_off + p, o3 = 3 * t.pix_off + p;
-        const float ga = gamma / ((float)HW * (float)V);
-        const float gc = w_c / (3.0f * (float)HW * (float)V);
-        const float m = mask[o1] ? 1.0f : 0.0f;
-        lb = o.A * (1.0f - m);
-        pb.gA = ga * (1.0f - m);
         const float Cv[3] = {o.C0, o.C1, o.C2};
+        const float Iv[3] = {target[o3], target[o3 + HW], target[o3 + 2 * HW]};
         float gC[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            const float d = m * Cv[ch] - m * target[o3 + ch * HW];
-            l1 += fabsf(d);
-            gC[ch] = d > 0.f ? gc * m : (d < 0.f ? -gc * m : 0.f);
-        }
+        pixel_loss_grad(mask[o1], o.A, Cv, Iv, gamma, w_c, (float)HW, (float)V, lb, l1, pb.gA, gC);
         pb.gC0 = gC[0]; pb.gC1 = gC[1]; pb.gC2 = gC[2];
         pix_bwd_init(pb, t, st.T, st.last, o.A, o.D, o.Dist);
     }

@@ -145,13 +145,14 @@ def test_config2_crop_backward_and_fd_subset():
     touched = np.unique(res["pairs"][0][:, 1])
     keep_rows = np.zeros(sc.n, bool)
     keep_rows[touched] = True
-    keep_rows[res["flag_ids"]] = False
+    keep_rows[res["tie_ids"]] = False
     excl = np.nonzero(~keep_rows)[0]
+    print(f"surfels blended in the crop {touched.size}, at a tie entry {res['tie_ids'].size}", flush=True)
     _compare_grads(g, gref, excl)
     # finite differences on a 200-surfel subset, one random parameter each
     rng = np.random.default_rng(22)
     sub = rng.choice(touched, size=min(200, touched.size), replace=False)
-    flagged = set(res["flag_ids"].tolist())
+    flagged = set(res["tie_ids"].tolist())
     exempt = 0
     P0 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3)
     names = ("means", "scales", "quats", "opac", "sh")
@@ -195,9 +196,11 @@ def test_config2_crop_backward_and_fd_subset():
         worst = max(worst, err)
         assert err <= 1e-3 * 10, (name, gid, j, gg, fd)
         checked += 1
+        if checked % 50 == 0:
+            print(f"  FD: {checked} checked, worst {worst:.2e}", flush=True)
     print(f"FD subset of {sub.size} surfels: {checked} parameters checked, {exempt} exempt (tie pixels), "
           f"{sub.size - checked - exempt} with a decision change inside +-h; worst relative error {worst:.2e}")
-    assert checked >= 100
+    assert checked >= 150
 
 
 # --------------------------------------------------------------------------
@@ -208,7 +211,9 @@ def test_config3_full_size():
     sc = scenes.make_config3()
     run = gpu_run(sc, keys64=True, stats=True)
     rast = run["rast"]
+    print("config3: GPU pass done", flush=True)
     geoms = _geoms_parallel(sc)
+    print("config3: oracle geometry of 16 views done", flush=True)
     ex = _records_bit_exact(sc, rast, geoms)
     print("config3 records bit-exact; grid-tie exemptions", ex)
     vis, need, stored, status = run["status"]
@@ -251,7 +256,10 @@ def test_config4_pruning_shell_scene():
     sc = scenes.make_config4()
     N = sc.n
     p = Params.from_scene(sc)
+    print("config4: scene ready", flush=True)
     st = prune_contrib(p, sc.cams, views_per_chunk=20)
+    torch.cuda.synchronize()
+    print("config4: pruning pass over 100 views done", flush=True)
     mask = st.mask.cpu().numpy().astype(bool)
     h = st.hits.cpu().numpy()
     infr = st.in_frustum.cpu().numpy().astype(bool)
@@ -270,6 +278,7 @@ def test_config4_pruning_shell_scene():
     st10 = prune_contrib(p, sub_cams)
     sub = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0, sub_cams, sc.masks[:10])
     geoms = _geoms_parallel(sub)
+    print("config4: oracle geometry of 10 views done", flush=True)
     h10 = st10.hits.cpu().numpy()
     ma10 = st10.max_alpha.cpu().numpy()
     inf10 = st10.in_frustum.cpu().numpy().astype(bool)
@@ -293,7 +302,8 @@ def test_config4_pruning_shell_scene():
             hits_o += int(sel.sum())
             if sel.any():
                 ma_o = max(ma_o, float(a[sel].max()))
-            tie |= bool(np.isin(gid, res["flag_ids"]))
+            tie |= bool(np.isin(gid, res["tie_ids"]))
+        print(f"  surfel {gid}: gpu hits {h10[gid]} oracle {hits_o} tie {tie}", flush=True)
         if tie:
             continue
         assert h10[gid] == hits_o, (gid, h10[gid], hits_o)

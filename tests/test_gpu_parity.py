@@ -160,7 +160,7 @@ def _oracle_grads(sc, w, geoms):
                     (out["depth"] * wt["d"][r]).sum() + (out["normal"] * wt["n"][r]).sum() +
                     (out["dist"] * wt["s"][r]).sum())
         res = render_pixels(P64, cam, geoms[v], pix, RP, loss_fn=lf)
-        flagged.append(res["flag_ids"])
+        flagged.append(res["tie_ids"])
     return P64.grads(), np.unique(np.concatenate(flagged))
 
 
@@ -246,10 +246,10 @@ def test_prune_stats_match_oracle():
     for v, cam in enumerate(sc.cams):
         res = render_pixels(P64, cam, geoms[v], _full(cam), RP)
         pairs.append(res["pairs"])
-        tie_ids.append(res["flag_ids"])
+        tie_ids.append(res["tie_ids"])
     st = oracle.prune_stats64(sc.n, pairs, [g["culled"] for g in geoms])
     keep = np.ones(sc.n, bool)
-    keep[np.unique(np.concatenate(tie_ids))] = False
+    keep[np.unique(np.concatenate(tie_ids))] = False  # surfels at a tie entry
     np.testing.assert_array_equal(hits.view(np.uint32)[keep], st["hits"][keep])
     np.testing.assert_allclose(ma[keep], st["max_alpha"][keep], atol=1e-5)
     np.testing.assert_allclose(mw[keep], st["max_weight"][keep], atol=1e-5)
