@@ -68,6 +68,20 @@ __device__ __forceinline__ float row_sum16(float v) {
     return v;
 }
 
+// Row sums of n values, one DPP step at a time over all values so that
+// consecutive DPP operations do not depend on each other.
+template <int n>
+__device__ __forceinline__ void row_sum16_n(float* v) {
+#pragma unroll
+    for (int i = 0; i < n; ++i) v[i] += dpp_f<0xB1, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < n; ++i) v[i] += dpp_f<0x4E, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < n; ++i) v[i] += dpp_f<0x141, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < n; ++i) v[i] += dpp_f<0x140, 0xF>(v[i]);
+}
+
 // max of non-negative values (0 is the identity)
 __device__ __forceinline__ float wave_max_to_lane63(float v) {
     v = fmaxf(v, dpp_f<0xB1, 0xF>(v));

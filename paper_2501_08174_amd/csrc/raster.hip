@@ -258,7 +258,10 @@ __device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float
 // W_k / (1 - a_k).  Per-record gradients are summed over 16-lane rows with
 // DPP, over the workgroup in LDS, then added to grad_rec with one atomic per
 // (tile, record, component).
-template <int NT, int BATCH>
+// GEO: the loss has depth, normal or distortion terms (their upstream
+// gradients are read); without them the depth path and six of the per-record
+// components are identically zero and are not computed or reduced.
+template <int NT, int BATCH, bool GEO>
 __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, BwdSmem<BATCH>& sm, PixBwd pb,
@@ -308,80 +311,86 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
             const bool bl = (jj < pb.ncon) && e.pass;
             if (ballot64(bl) == 0ull) continue;
             eval_finish(g2, g3, rc.alpha_max, e);
+            // Gradients of this entry, branch-free: lanes that do not blend it
+            // produce exact zeros (dL/da and the weight are selected to 0, the
+            // intersection terms of low-pass lanes are selected away).
+            const float4 a0 = sm.a[0][k], a1 = sm.a[1][k];
+            const float o = g2.w;
+            const float rin = __builtin_amdgcn_rcpf(1.0f - e.a);
+            const float Tk = T * rin;
+            const float wraw = e.a * Tk;
+            const float wgt = bl ? wraw : 0.f;
+            float gk = pb.gC0 * a0.x + pb.gC1 * a0.y + pb.gC2 * a0.z + pb.gA;
+            float dLdz = 0.f;
             float gr[kNumGrad];
-#pragma unroll
-            for (int i = 0; i < kNumGrad; ++i) gr[i] = 0.f;
-            if (bl) {
-                const float4 a0 = sm.a[0][k], a1 = sm.a[1][k];
-                const float o = g2.w;
-                const float om = 1.0f - e.a;
-                const float rin = __builtin_amdgcn_rcpf(om);
-                const float Tk = T * rin;
-                const float wgt = e.a * Tk;
+            if (GEO) {
                 const float zr = e.z - pb.rmean;
-                const float gk = pb.gC0 * a0.x + pb.gC1 * a0.y + pb.gC2 * a0.z + pb.gA + pb.gD * e.z +
-                                 pb.gN0 * a0.w + pb.gN1 * a1.x + pb.gN2 * a1.y +
-                                 pb.gS * 2.0f * (pb.Q + pb.S0 * zr * zr);
-                const float dLda = Tk * gk - Wacc * rin;
-                Wacc = __builtin_fmaf(gk, wgt, Wacc);
-                T = Tk;
-                gr[15] = pb.gC0 * wgt; gr[16] = pb.gC1 * wgt; gr[17] = pb.gC2 * wgt;
+                gk += pb.gD * e.z + pb.gN0 * a0.w + pb.gN1 * a1.x + pb.gN2 * a1.y +
+                      pb.gS * 2.0f * (pb.Q + pb.S0 * zr * zr);
+                dLdz = bl ? wraw * (pb.gD + 4.0f * pb.gS * pb.S0 * zr) : 0.f;
                 gr[18] = pb.gN0 * wgt; gr[19] = pb.gN1 * wgt; gr[20] = pb.gN2 * wgt;
-                const float dLdz = wgt * (pb.gD + 4.0f * pb.gS * pb.S0 * zr);
-                float dLdo = 0.f, dLdG = 0.f;
-                if (!e.clamped) {
-                    dLdo = dLda * e.G;
-                    dLdG = dLda * o;
-                }
-                gr[11] = dLdo;
-                const float dLdrho = -e.G * dLdG;
-                if (e.surf) {
-                    const float du = dLdrho * e.u + dLdz * g3.x;
-                    const float dv = dLdrho * e.v + dLdz * g3.y;
-                    gr[12] = dLdz * e.u; gr[13] = dLdz * e.v; gr[14] = dLdz;
-                    const float dw0 = du * e.r, dw1 = dv * e.r;
-                    const float dw2 = -(du * e.u + dv * e.v) * e.r;
-                    gr[0] = dw0 * e.dx; gr[1] = dw1 * e.dx; gr[2] = dw2 * e.dx;
-                    gr[3] = dw0 * e.dy; gr[4] = dw1 * e.dy; gr[5] = dw2 * e.dy;
-                    gr[6] = dw0; gr[7] = dw1; gr[8] = dw2;
-                } else {
-                    gr[9] = -2.0f * dLdrho * e.dx;
-                    gr[10] = -2.0f * dLdrho * e.dy;
-                    gr[14] = dLdz;
-                }
             }
-            // 16-lane row sums with DPP, then the last lane of each of the
-            // four rows adds its row sum into the workgroup accumulator.
-            // Components no lane of the wave produced are skipped.
+            const float dLda = bl ? Tk * gk - Wacc * rin : 0.f;
+            Wacc = bl ? __builtin_fmaf(gk, wraw, Wacc) : Wacc;
+            T = bl ? Tk : T;
+            gr[15] = pb.gC0 * wgt; gr[16] = pb.gC1 * wgt; gr[17] = pb.gC2 * wgt;
+            const float dLdo = e.clamped ? 0.f : dLda * e.G;
+            const float dLdG = e.clamped ? 0.f : dLda * o;
+            gr[11] = dLdo;
+            const float dLdrho = -e.G * dLdG;
+            const float us = e.surf ? e.u : 0.f, vs = e.surf ? e.v : 0.f, rs = e.surf ? e.r : 0.f;
+            float du = dLdrho * us, dv = dLdrho * vs;
+            if (GEO) {
+                const float dzs = e.surf ? dLdz : 0.f;
+                du += dzs * g3.x;
+                dv += dzs * g3.y;
+                gr[12] = dzs * us; gr[13] = dzs * vs; gr[14] = dLdz;
+            }
+            const float dw0 = du * rs, dw1 = dv * rs;
+            const float dw2 = -(du * us + dv * vs) * rs;
+            gr[0] = dw0 * e.dx; gr[1] = dw1 * e.dx; gr[2] = dw2 * e.dx;
+            gr[3] = dw0 * e.dy; gr[4] = dw1 * e.dy; gr[5] = dw2 * e.dy;
+            gr[6] = dw0; gr[7] = dw1; gr[8] = dw2;
+            const float f2 = e.surf ? 0.f : -2.0f * dLdrho;
+            gr[9] = f2 * e.dx;
+            gr[10] = f2 * e.dy;
+            // 16-lane row sums with DPP, one reduction step at a time across
+            // the components (independent consecutive DPP operations), then the
+            // last lane of each of the four rows adds its row sums into the
+            // workgroup accumulator.  Components no lane of the wave produced
+            // are skipped.
             const bool any_surf = ballot64(bl && e.surf) != 0ull;
             const bool any_flat = ballot64(bl && !e.surf) != 0ull;
-            if (any_surf) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) gr[i] = row_sum16(gr[i]);
-                gr[12] = row_sum16(gr[12]);
-                gr[13] = row_sum16(gr[13]);
+            const bool any_col = ballot64(bl && (pb.gC0 != 0.f || pb.gC1 != 0.f || pb.gC2 != 0.f)) != 0ull;
+            if (any_surf) row_sum16_n<9>(gr);
+            if (any_flat) row_sum16_n<2>(gr + 9);
+            if (any_col) row_sum16_n<3>(gr + 15);
+            if (GEO) {
+                row_sum16_n<4>(gr + 11);
+                row_sum16_n<3>(gr + 18);
+            } else {
+                row_sum16_n<1>(gr + 11);
             }
-            if (any_flat) {
-                gr[9] = row_sum16(gr[9]);
-                gr[10] = row_sum16(gr[10]);
-            }
-#pragma unroll
-            for (int i = 14; i < kNumGrad; ++i) gr[i] = row_sum16(gr[i]);
-            gr[11] = row_sum16(gr[11]);
             if (row_last) {
                 if (any_surf) {
 #pragma unroll
                     for (int i = 0; i < 9; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
-                    atomicAdd(&sm.acc[k][12], gr[12]);
-                    atomicAdd(&sm.acc[k][13], gr[13]);
                 }
                 if (any_flat) {
                     atomicAdd(&sm.acc[k][9], gr[9]);
                     atomicAdd(&sm.acc[k][10], gr[10]);
                 }
-#pragma unroll
-                for (int i = 14; i < kNumGrad; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
                 atomicAdd(&sm.acc[k][11], gr[11]);
+                if (GEO) {
+#pragma unroll
+                    for (int i = 12; i < 15; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
+#pragma unroll
+                    for (int i = 18; i < 21; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
+                }
+                if (any_col) {
+#pragma unroll
+                    for (int i = 15; i < 18; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
+                }
             }
         }
         __syncthreads();
@@ -396,7 +405,7 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
     }
 }
 
-template <int TW, int TH, int BATCH>
+template <int TW, int TH, int BATCH, bool GEO>
 __global__ void __launch_bounds__(TW * TH)
 k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
              const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
@@ -424,7 +433,7 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         if (dDist) pb.gS = dDist[o1];
         pix_bwd_init(pb, t, T_final[o1], n_contrib[o1], alpha[o1], depth[o1], dist[o1]);
     }
-    bwd_tile<TW * TH, BATCH>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
+    bwd_tile<TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
 }
 
 // One training step of the compositing for a tile: forward with the
@@ -490,7 +499,8 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
         __syncthreads();
     }
     if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile + 1] = s_red[0];
-    bwd_tile<NT, BATCH>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec);
+    bwd_tile<NT, BATCH, false>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb,
+                               grad_rec);
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, float v, uint64_t n) {
@@ -542,8 +552,14 @@ void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, in
                 const float* dC, const float* dA, const float* dD, const float* dN, const float* dS,
                 float* grad_rec) {
     constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
-    hipLaunchKernelGGL((k_render_bwd<TW, TH, B>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app, vals,
-                       ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, grad_rec);
+    if (dD || dN || dS)
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom,
+                           app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
+                           grad_rec);
+    else
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
+                           geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
+                           grad_rec);
 }
 
 template <int TW, int TH>
