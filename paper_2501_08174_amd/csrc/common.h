@@ -82,6 +82,62 @@ __device__ __forceinline__ void row_sum16_n(float* v) {
     for (int i = 0; i < n; ++i) v[i] += dpp_f<0x140, 0xF>(v[i]);
 }
 
+// Wave-wide sums of N per-lane values (N = 8 or 16) by transposition: at
+// every step the values of two registers are exchanged between the two halves
+// of the lanes being combined, so each step halves both the number of
+// registers and the number of lanes that share a value.  Halves of the wave
+// (lanes l, l^32) and pairs of rows (l, l^16) are combined with the gfx950
+// permlane swaps, lanes l, l^1 and l, l^2 with DPP quad permutations, the
+// remaining lanes l, l^4, l^8 with row rotations.  On return every lane holds
+// the wave total of component wave_tsum_comp<N>(lane).
+template <int N>
+__device__ __forceinline__ int wave_tsum_comp(int lane) {
+    const int r = lane >> 4;
+    const int pr = ((r & 1) << 1) | (r >> 1);   // row 0,1,2,3 -> 0,2,1,3
+    const int p = lane & 1;
+    if (N == 16) return 8 * ((lane >> 1) & 1) + 4 * p + pr;
+    return 4 * p + pr;
+}
+
+template <int N>
+__device__ __forceinline__ float wave_tsum(const float* v) {
+    static_assert(N == 8 || N == 16, "8 or 16 components");
+    float s[N / 2];
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * j]), __float_as_uint(v[2 * j + 1]),
+                                                        false, false);
+        s[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float t[N / 4];
+#pragma unroll
+    for (int m = 0; m < N / 4; ++m) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * m]), __float_as_uint(s[2 * m + 1]),
+                                                        false, false);
+        t[m] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool odd = (__lane_id() & 1) != 0;
+    float u[N / 8];
+#pragma unroll
+    for (int n = 0; n < N / 8; ++n) {
+        const float keep = odd ? t[2 * n + 1] : t[2 * n];
+        const float send = odd ? t[2 * n] : t[2 * n + 1];
+        u[n] = keep + dpp_f<0xB1, 0xF>(send);   // quad_perm [1,0,3,2]
+    }
+    float w;
+    if (N == 16) {
+        const bool b1 = (__lane_id() & 2) != 0;
+        const float keep = b1 ? u[1] : u[0];
+        const float send = b1 ? u[0] : u[1];
+        w = keep + dpp_f<0x4E, 0xF>(send);      // quad_perm [2,3,0,1]
+    } else {
+        w = u[0] + dpp_f<0x4E, 0xF>(u[0]);
+    }
+    w += dpp_f<0x124, 0xF>(w);                  // row_ror:4
+    w += dpp_f<0x128, 0xF>(w);                  // row_ror:8
+    return w;
+}
+
 // max of non-negative values (0 is the identity)
 __device__ __forceinline__ float wave_max_to_lane63(float v) {
     v = fmaxf(v, dpp_f<0xB1, 0xF>(v));

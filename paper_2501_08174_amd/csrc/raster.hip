@@ -255,9 +255,9 @@ __device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float
 // blended entry, recovering T_k = T_{k+1} / (1 - a_k).  With g_k the
 // derivative of the loss by the blending weight w_k of entry k and
 // W_k = sum_{j>k} g_j w_j (+ the background term), dL/da_k = T_k g_k -
-// W_k / (1 - a_k).  Per-record gradients are summed over 16-lane rows with
-// DPP, over the workgroup in LDS, then added to grad_rec with one atomic per
-// (tile, record, component).
+// W_k / (1 - a_k).  Per-record gradients are summed over each wave by
+// transposition (permlane swaps and DPP), over the workgroup in LDS, then
+// added to grad_rec with one atomic per (tile, record, component).
 // GEO: the loss has depth, normal or distortion terms (their upstream
 // gradients are read); without them the depth path and six of the per-record
 // components are identically zero and are not computed or reduced.
@@ -268,7 +268,7 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                                          float* __restrict__ grad_rec) {
     static_assert(BATCH <= NT, "one record per thread and batch");
     const int tid = threadIdx.x;
-    const bool row_last = (__lane_id() & 15) == 15;
+    const int lane = __lane_id();
     __syncthreads();
     if (tid == 0) sm.maxn = 0u;
     __syncthreads();
@@ -354,43 +354,22 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
             const float f2 = e.surf ? 0.f : -2.0f * dLdrho;
             gr[9] = f2 * e.dx;
             gr[10] = f2 * e.dy;
-            // 16-lane row sums with DPP, one reduction step at a time across
-            // the components (independent consecutive DPP operations), then the
-            // last lane of each of the four rows adds its row sums into the
-            // workgroup accumulator.  Components no lane of the wave produced
-            // are skipped.
-            const bool any_surf = ballot64(bl && e.surf) != 0ull;
-            const bool any_flat = ballot64(bl && !e.surf) != 0ull;
-            const bool any_col = ballot64(bl && (pb.gC0 != 0.f || pb.gC1 != 0.f || pb.gC2 != 0.f)) != 0ull;
-            if (any_surf) row_sum16_n<9>(gr);
-            if (any_flat) row_sum16_n<2>(gr + 9);
-            if (any_col) row_sum16_n<3>(gr + 15);
-            if (GEO) {
-                row_sum16_n<4>(gr + 11);
-                row_sum16_n<3>(gr + 18);
-            } else {
-                row_sum16_n<1>(gr + 11);
+            // Wave totals by transposition; the lanes holding distinct
+            // components add them into the workgroup accumulator.
+            {
+                float c16[16];
+#pragma unroll
+                for (int i = 0; i < 12; ++i) c16[i] = gr[i];
+                c16[12] = gr[15]; c16[13] = gr[16]; c16[14] = gr[17]; c16[15] = 0.f;
+                const float tot = wave_tsum<16>(c16);
+                const int ci = wave_tsum_comp<16>(lane);
+                if ((lane & 12) == 0 && ci < 15) atomicAdd(&sm.acc[k][ci < 12 ? ci : ci + 3], tot);
             }
-            if (row_last) {
-                if (any_surf) {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
-                }
-                if (any_flat) {
-                    atomicAdd(&sm.acc[k][9], gr[9]);
-                    atomicAdd(&sm.acc[k][10], gr[10]);
-                }
-                atomicAdd(&sm.acc[k][11], gr[11]);
-                if (GEO) {
-#pragma unroll
-                    for (int i = 12; i < 15; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
-#pragma unroll
-                    for (int i = 18; i < 21; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
-                }
-                if (any_col) {
-#pragma unroll
-                    for (int i = 15; i < 18; ++i) atomicAdd(&sm.acc[k][i], gr[i]);
-                }
+            if (GEO) {
+                float c8[8] = {gr[12], gr[13], gr[14], gr[18], gr[19], gr[20], 0.f, 0.f};
+                const float tot = wave_tsum<8>(c8);
+                const int ci = wave_tsum_comp<8>(lane);
+                if ((lane & 14) == 0 && ci < 6) atomicAdd(&sm.acc[k][ci < 3 ? 12 + ci : 15 + ci], tot);
             }
         }
         __syncthreads();
