@@ -21,7 +21,7 @@ namespace sr {
 namespace {
 
 constexpr int kNT = 256;            // threads per block
-constexpr int kIPT = 8;             // keys per thread per radix sub-tile
+constexpr int kIPT = 16;            // keys per thread per radix sub-tile
 constexpr int kTile = kNT * kIPT;   // keys per radix sub-tile
 constexpr int kMaxDigitBits = 9;    // radix digits of up to 9 bits (512 buckets)
 constexpr int kMaxRadix = 1 << kMaxDigitBits;
@@ -417,6 +417,28 @@ k_ranges(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ key
     }
 }
 
+// Per-tile [start, end) by binary search of the sorted tile keys, one thread
+// per tile; empty tiles get [0, 0).
+__global__ void __launch_bounds__(kNT)
+k_ranges_search(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ keys, int total_tiles,
+                uint2* __restrict__ ranges) {
+    const int t = (int)(blockIdx.x * kNT + threadIdx.x);
+    if (t >= total_tiles) return;
+    const uint32_t n = counters[2];
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < (uint32_t)t) lo = mid + 1; else hi = mid;
+    }
+    const uint32_t s = lo;
+    hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] <= (uint32_t)t) lo = mid + 1; else hi = mid;
+    }
+    ranges[t] = s < lo ? make_uint2(s, lo) : make_uint2(0u, 0u);
+}
+
 __global__ void k_copy_u32(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ src,
                            uint32_t* __restrict__ dst) {
     const uint32_t n = counters[2];
@@ -545,6 +567,12 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     while ((1ull << nbits) < (uint64_t)total_tiles) ++nbits;
     uint32_t* sorted_keys = radix_sort(w.ik0, w.iv0, w.ik1, w.iv1, vals, counters + 2, cap, nbits, w.hist,
                                        w.tot, s);
+    if (!keys64) {
+        if (total_tiles > 0)
+            hipLaunchKernelGGL(k_ranges_search, dim3((total_tiles + kNT - 1) / kNT), dim3(kNT), 0, s, counters,
+                               sorted_keys, total_tiles, (uint2*)ranges);
+        return hipGetLastError();
+    }
     const uint64_t rblocks = ((uint64_t)cap + kNT - 1) / kNT;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)(rblocks < 1 ? 1 : (rblocks > 0x7FFFFFFF ? 0x7FFFFFFF : rblocks))),
                        dim3(kNT), 0, s, counters, sorted_keys, vals, (uint2*)ranges, keys64, depth_key, cams_dev, V,

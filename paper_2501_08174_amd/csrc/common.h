@@ -49,39 +49,6 @@ __device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
 }
 
-__device__ __forceinline__ float wave_sum_to_lane63(float v) {
-    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f<0x141, 0xF>(v);  // row_half_mirror
-    v += dpp_f<0x140, 0xF>(v);  // row_mirror: every lane of a row holds the row sum
-    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
-}
-
-// Sum over each row of 16 lanes; every lane of a row ends with its row sum.
-__device__ __forceinline__ float row_sum16(float v) {
-    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f<0x141, 0xF>(v);  // row_half_mirror
-    v += dpp_f<0x140, 0xF>(v);  // row_mirror
-    return v;
-}
-
-// Row sums of n values, one DPP step at a time over all values so that
-// consecutive DPP operations do not depend on each other.
-template <int n>
-__device__ __forceinline__ void row_sum16_n(float* v) {
-#pragma unroll
-    for (int i = 0; i < n; ++i) v[i] += dpp_f<0xB1, 0xF>(v[i]);
-#pragma unroll
-    for (int i = 0; i < n; ++i) v[i] += dpp_f<0x4E, 0xF>(v[i]);
-#pragma unroll
-    for (int i = 0; i < n; ++i) v[i] += dpp_f<0x141, 0xF>(v[i]);
-#pragma unroll
-    for (int i = 0; i < n; ++i) v[i] += dpp_f<0x140, 0xF>(v[i]);
-}
-
 // Wave-wide sums of N per-lane values (N = 8 or 16) by transposition: at
 // every step the values of two registers are exchanged between the two halves
 // of the lanes being combined, so each step halves both the number of
@@ -138,15 +105,26 @@ __device__ __forceinline__ float wave_tsum(const float* v) {
     return w;
 }
 
-// max of non-negative values (0 is the identity)
-__device__ __forceinline__ float wave_max_to_lane63(float v) {
-    v = fmaxf(v, dpp_f<0xB1, 0xF>(v));
-    v = fmaxf(v, dpp_f<0x4E, 0xF>(v));
-    v = fmaxf(v, dpp_f<0x141, 0xF>(v));
-    v = fmaxf(v, dpp_f<0x140, 0xF>(v));
-    v = fmaxf(v, dpp_f<0x142, 0xA>(v));
-    v = fmaxf(v, dpp_f<0x143, 0xC>(v));
-    return v;
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// Wave maxima of two non-negative floats, compared as their bit patterns
+// (which order like the values): the halves of the wave exchange a and b, the
+// row pairs exchange again, then each row reduces with DPP.  On return lanes
+// 0..31 hold the bits of max(a) over the wave and lanes 32..63 those of max(b).
+__device__ __forceinline__ uint32_t wave_max2_bits(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    uint32_t m = r[0] > r[1] ? r[0] : r[1];
+    const auto q = __builtin_amdgcn_permlane16_swap(m, m, false, false);
+    m = q[0] > q[1] ? q[0] : q[1];
+    uint32_t d;
+    d = dpp_u<0xB1>(m); m = m > d ? m : d;    // quad_perm [1,0,3,2]
+    d = dpp_u<0x4E>(m); m = m > d ? m : d;    // quad_perm [2,3,0,1]
+    d = dpp_u<0x141>(m); m = m > d ? m : d;   // row_half_mirror
+    d = dpp_u<0x140>(m); m = m > d ? m : d;   // row_mirror
+    return m;
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }

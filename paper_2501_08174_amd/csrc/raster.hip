@@ -89,7 +89,7 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     constexpr bool STATS = (MODE & kStats) != 0;
     constexpr bool COUNT = (MODE & kCount) != 0;
     const int tid = threadIdx.x;
-    const bool lane63 = __lane_id() == 63;
+    const int lane = __lane_id();
     st.T = 1.0f;
     st.C0 = st.C1 = st.C2 = st.N0 = st.N1 = st.N2 = st.S0 = st.S1 = st.S2 = st.zref = 0.f;
     st.last = 0;
@@ -150,13 +150,11 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
             if (STATS) {
                 const uint64_t bm = ballot64(blend);
                 if (bm != 0ull) {
-                    const float ma = wave_max_to_lane63(blend ? e.a : 0.f);
-                    const float mw = wave_max_to_lane63(wgt);
-                    if (lane63) {
+                    const uint32_t mx = wave_max2_bits(blend ? e.a : 0.f, wgt);
+                    if ((lane & 31) == 0) {
                         const uint32_t g = sm.id[k];
-                        atomicAdd(&hits[g], (uint32_t)__popcll(bm));
-                        atomicMax((uint32_t*)&max_alpha[g], __float_as_uint(ma));
-                        atomicMax((uint32_t*)&max_weight[g], __float_as_uint(mw));
+                        if (lane == 0) atomicAdd(&hits[g], (uint32_t)__popcll(bm));
+                        atomicMax(lane == 0 ? (uint32_t*)&max_alpha[g] : (uint32_t*)&max_weight[g], mx);
                     }
                 }
             }
