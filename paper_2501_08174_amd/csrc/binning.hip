@@ -299,14 +299,21 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
 
 // ---- instances ----------------------------------------------------------------
 
+// Tiles touched by every depth-sorted visible pair (gathered once into
+// depth order) and their sum per block.
 __global__ void __launch_bounds__(kNT)
 k_inst_count(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ vis_vals,
-             const uint32_t* __restrict__ tiles_touched, uint64_t* __restrict__ sums) {
+             const uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ tt_sorted,
+             uint64_t* __restrict__ sums) {
     __shared__ uint64_t s_w[4];
     uint64_t b, e;
     static_chunk(counters[0], G, &b, &e);
     uint64_t c = 0;
-    for (uint64_t i = b + threadIdx.x; i < e; i += kNT) c += tiles_touched[vis_vals[i]];
+    for (uint64_t i = b + threadIdx.x; i < e; i += kNT) {
+        const uint32_t t = tiles_touched[vis_vals[i]];
+        tt_sorted[i] = t;
+        c += t;
+    }
     uint64_t tot;
     block_excl_scan<uint64_t>(c, s_w, &tot);
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
@@ -314,16 +321,15 @@ k_inst_count(const uint32_t* __restrict__ counters, int G, const uint32_t* __res
 
 // Exclusive instance offset of every depth-sorted visible pair.
 __global__ void __launch_bounds__(kNT)
-k_inst_offsets(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ vis_vals,
-               const uint32_t* __restrict__ tiles_touched, const uint64_t* __restrict__ block_offs,
-               uint64_t* __restrict__ offs) {
+k_inst_offsets(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ tt_sorted,
+               const uint64_t* __restrict__ block_offs, uint64_t* __restrict__ offs) {
     __shared__ uint64_t s_w[4];
     uint64_t b, e;
     static_chunk(counters[0], G, &b, &e);
     uint64_t run = block_offs[blockIdx.x];
     for (uint64_t base = b; base < e; base += kNT) {
         const uint64_t i = base + threadIdx.x;
-        const uint64_t t = i < e ? (uint64_t)tiles_touched[vis_vals[i]] : 0ull;
+        const uint64_t t = i < e ? (uint64_t)tt_sorted[i] : 0ull;
         uint64_t tot;
         const uint64_t ex = block_excl_scan<uint64_t>(t, s_w, &tot);
         if (i < e) offs[i] = run + ex;
@@ -333,6 +339,24 @@ k_inst_offsets(const uint32_t* __restrict__ counters, int G, const uint32_t* __r
 
 constexpr int kEmitPerBlock = 4096;   // instances written per block
 
+// First visible pair of every emission block: the last pair whose first
+// instance is at or before the block's first output position (one thread per
+// block, binary search over the instance offsets).
+__global__ void __launch_bounds__(kNT)
+k_emit_starts(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ offs, uint32_t blocks,
+              uint32_t* __restrict__ starts) {
+    const uint32_t b = blockIdx.x * kNT + threadIdx.x;
+    if (b >= blocks) return;
+    const uint32_t n_vis = counters[0];
+    const uint64_t ob = (uint64_t)b * kEmitPerBlock;
+    uint32_t lo = 0, hi = n_vis == 0 ? 0 : n_vis - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= ob) lo = mid; else hi = mid - 1;
+    }
+    starts[b] = lo;
+}
+
 // Emits the instances in depth order.  The output space is partitioned:
 // block b writes instances [b*4096, (b+1)*4096), whatever the number of
 // surfels they come from, so surfels covering thousands of tiles (close to
@@ -341,7 +365,8 @@ __global__ void __launch_bounds__(kNT)
 k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total64, int N, int tile_w, int tile_h,
        const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals,
        const uint32_t* __restrict__ tiles_touched, const ushort4* __restrict__ rect,
-       const uint64_t* __restrict__ offs, uint32_t* __restrict__ inst_keys, uint32_t* __restrict__ inst_vals) {
+       const uint64_t* __restrict__ offs, const uint32_t* __restrict__ starts, uint32_t* __restrict__ inst_keys,
+       uint32_t* __restrict__ inst_vals) {
     __shared__ uint64_t s_off[kNT];
     __shared__ uint32_t s_g[kNT];
     __shared__ int s_base[kNT];     // global id of the rectangle's first tile
@@ -354,15 +379,7 @@ k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total
     const uint64_t oe = ob + kEmitPerBlock < stored ? ob + kEmitPerBlock : stored;
     const uint32_t n_vis = counters[0];
     const uint64_t total = *total64;
-    if (threadIdx.x == 0) {
-        // last pair whose first instance is <= ob
-        uint32_t lo = 0, hi = n_vis - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (offs[mid] <= ob) lo = mid; else hi = mid - 1;
-        }
-        s_first = lo;
-    }
+    if (threadIdx.x == 0) s_first = starts[blockIdx.x];
     __syncthreads();
     for (uint32_t e0 = s_first;; e0 += kNT) {
         const uint32_t i = e0 + threadIdx.x;
@@ -460,7 +477,7 @@ int grid_for(uint64_t elems) {
 struct BinWs {
     uint32_t *vk0, *vv0, *vk1, *vv1;     // visible pairs, ping-pong
     uint32_t *ik0, *iv0, *ik1, *iv1;     // instances, ping-pong
-    uint32_t *hist, *tot, *vsum;
+    uint32_t *hist, *tot, *vsum, *tts, *estart;
     uint64_t *isum, *ioff, *itotal;
     size_t bytes;
 };
@@ -482,6 +499,8 @@ BinWs carve(void* base, uint64_t VN, uint64_t cap) {
     w.vsum = (uint32_t*)take(kMaxRadixBlocks * 4);
     w.isum = (uint64_t*)take(kMaxRadixBlocks * 8);
     w.ioff = (uint64_t*)take(VN * 8);
+    w.tts = (uint32_t*)take(VN * 4);
+    w.estart = (uint32_t*)take(((cap + kEmitPerBlock - 1) / kEmitPerBlock) * 4);
     w.itotal = (uint64_t*)take(8);
     w.bytes = off;
     return w;
@@ -499,11 +518,13 @@ uint32_t* radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uin
         hipLaunchKernelGGL(k_copy_u32, dim3(1024), dim3(256), 0, s, count, v0, vals_dst);
         return k0;
     }
-    const int per = (nbits + passes - 1) / passes;
+    // digits as even as possible, the narrower ones first (the first pass
+    // reads the keys in emission order)
+    const int per_lo = nbits / passes, wide_from = passes - nbits % passes;
     uint32_t *sk = k0, *sv = v0;
+    int shift = 0;
     for (int p = 0; p < passes; ++p) {
-        const int shift = p * per;
-        const int bits = (shift + per <= nbits) ? per : nbits - shift;
+        const int bits = per_lo + (p >= wide_from ? 1 : 0);
         const bool last = p == passes - 1;
         uint32_t* dk = sk == k0 ? k1 : k0;
         uint32_t* dv = last ? vals_dst : (sv == v0 ? v1 : v0);
@@ -513,6 +534,7 @@ uint32_t* radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uin
                            dk, dv);
         sk = dk;
         sv = dv;
+        shift += bits;
     }
     return sk;
 }
@@ -554,14 +576,18 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     // after four passes the sorted pairs are in (vk0, vv0)
     // 3. instance offsets and emission in depth order
     const int Gi = Gv;
-    hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, tiles_touched, w.isum);
+    hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, tiles_touched, w.tts,
+                       w.isum);
     hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap, w.itotal);
-    hipLaunchKernelGGL(k_inst_offsets, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, tiles_touched, w.isum,
-                       w.ioff);
+    hipLaunchKernelGGL(k_inst_offsets, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.tts, w.isum, w.ioff);
     const uint64_t emit_blocks = ((uint64_t)cap + kEmitPerBlock - 1) / kEmitPerBlock;
-    if (emit_blocks > 0)
+    if (emit_blocks > 0) {
+        hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((emit_blocks + kNT - 1) / kNT)), dim3(kNT), 0, s, counters,
+                           w.ioff, (uint32_t)emit_blocks, w.estart);
         hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kNT), 0, s, counters, w.itotal, N, cfg.tile_w,
-                           cfg.tile_h, cams_dev, w.vv0, tiles_touched, (const ushort4*)rect, w.ioff, w.ik0, w.iv0);
+                           cfg.tile_h, cams_dev, w.vv0, tiles_touched, (const ushort4*)rect, w.ioff, w.estart, w.ik0,
+                           w.iv0);
+    }
     // 4. stable sort by tile id; values land in the caller's array
     int nbits = 0;
     while ((1ull << nbits) < (uint64_t)total_tiles) ++nbits;
