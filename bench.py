@@ -196,7 +196,7 @@ def main():
     }
 
     # work accounting for the roofline (outside the timed region)
-    R, B = pipe.rast.count_pairs()
+    R, B, WS, WB = pipe.rast.count_pairs(waves=True)
     R_bwd = int(pipe.rast.n_contrib[:P].to(torch.int64).sum().item())
     mean_ms = dict(zip(Pipeline.STAGES, stage_ms.mean(axis=0)))
     fwd_ops = FWD_OPS_BLEND * B + FWD_OPS_SKIP * (R - B)
@@ -207,7 +207,8 @@ def main():
                           "frac": achieved / (VALU_PEAK / 1e12), "traffic": None,
                           "kernel": "k_train_raster (fused forward + loss + backward compositing)",
                           "ops_per_launch": ops}
-    result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd})
+    result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd,
+                             "forward_wave_steps": WS, "forward_wave_steps_blending": WB})
 
     if not args.no_unfused:
         # the same step with separate forward / loss / backward launches

@@ -244,9 +244,10 @@ sr_status sr_prune_contrib(const sr_config *cfg, int32_t N, int32_t V, const sr_
 
 /* Work accounting of the compositing (no outputs): counts[0] = pairs
  * (pixel, tile-list entry) tested before the pixel terminated, counts[1] =
- * pairs blended; uint64 [2], overwritten.  The same decisions as
- * sr_render_forward; used to express throughput as a fraction of the VALU
- * roofline. */
+ * pairs blended, counts[2] = (64-pixel wave, entry) steps taken, counts[3] =
+ * those steps in which at least one pixel of the wave blends; uint64 [4],
+ * overwritten.  The same decisions as sr_render_forward; used to express
+ * throughput as a fraction of the VALU roofline. */
 sr_status sr_render_count(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                           const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
                           const uint32_t *ranges, uint64_t *counts, void *stream);

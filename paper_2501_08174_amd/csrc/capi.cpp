@@ -389,7 +389,7 @@ sr_status sr_render_count(const sr_config* cfg, int32_t N, int32_t V, const sr_c
     SR_NEED(counts);
     if (total_tiles > 0) { SR_NEED(geom); SR_NEED(vals); SR_NEED(ranges); }
     hipStream_t s = (hipStream_t)stream;
-    SR_TRY(hip_status(sr::fill_f32((float*)counts, 0.f, 4, s), "clear counts"));
+    SR_TRY(hip_status(sr::fill_f32((float*)counts, 0.f, 8, s), "clear counts"));
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, vals, ranges, nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                             nullptr, (unsigned long long*)counts, s),

@@ -84,7 +84,8 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, FwdSmem<NT, MODE>& sm, PixFwd& st,
                                          uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
-                                         float* __restrict__ max_weight, uint64_t& n_reached, uint64_t& n_blended) {
+                                         float* __restrict__ max_weight, uint64_t& n_reached, uint64_t& n_blended,
+                                         uint64_t& n_witer, uint64_t& n_wblend) {
     constexpr bool SHADE = (MODE & kShade) != 0;
     constexpr bool STATS = (MODE & kStats) != 0;
     constexpr bool COUNT = (MODE & kCount) != 0;
@@ -116,10 +117,14 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
             PairEval e;
             const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
             eval_test(sm.g[0][k], sm.g[1][k], g2, g3, px, py, e);
-            if (COUNT) n_reached += (uint64_t)__popcll(ballot64(!done));
+            if (COUNT) {
+                n_reached += (uint64_t)__popcll(ballot64(!done));
+                n_witer += 1;
+            }
             bool blend = !done && e.pass;
             // no pixel of this wave takes the entry: nothing changes
             if (ballot64(blend) == 0ull) continue;
+            if (COUNT) n_wblend += 1;
             eval_finish(g2, g3, rc.alpha_max, e);
             const float Tn = st.T * (1.0f - e.a);
             if (blend && Tn < rc.t_min) {
@@ -218,11 +223,14 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     tile_ctx<TW, TH>(cams, V, ranges, t);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
-    uint64_t n_reached = 0, n_blended = 0;
-    fwd_tile<NT, MODE>(t, px, py, N, geom, app, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached, n_blended);
+    uint64_t n_reached = 0, n_blended = 0, n_witer = 0, n_wblend = 0;
+    fwd_tile<NT, MODE>(t, px, py, N, geom, app, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached, n_blended,
+                       n_witer, n_wblend);
     if ((MODE & kCount) && __lane_id() == 0) {
         atomicAdd(&counts[0], (unsigned long long)n_reached);
         atomicAdd(&counts[1], (unsigned long long)n_blended);
+        atomicAdd(&counts[2], (unsigned long long)n_witer);
+        atomicAdd(&counts[3], (unsigned long long)n_wblend);
     }
     if ((MODE & kShade) && t.inside) write_outputs(st, pix_outputs(st, t), t, color, alpha, depth, normal, dist,
                                                    T_final, n_contrib);
@@ -281,6 +289,7 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
         const uint32_t o = (uint32_t)__shfl_xor((int)wave_maxn, off, 64);
         wave_maxn = o > wave_maxn ? o : wave_maxn;
     }
+    wave_maxn = __builtin_amdgcn_readfirstlane(wave_maxn);   // uniform: keep the loop control scalar
     float T = pb.T, Wacc = pb.Wacc;
     for (int64_t base = ((int64_t)(maxn - 1) / BATCH) * BATCH; base >= 0; base -= BATCH) {
         __syncthreads();
@@ -436,9 +445,9 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     tile_ctx<TW, TH>(cams, V, ranges, t);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
-    uint64_t n0 = 0, n1 = 0;
+    uint64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
     fwd_tile<NT, MODE>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st, hits,
-                       max_alpha, max_weight, n0, n1);
+                       max_alpha, max_weight, n0, n1, n2, n3);
     const PixOut o = pix_outputs(st, t);
     PixBwd pb;
     pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = 0.f;

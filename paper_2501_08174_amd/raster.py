@@ -240,12 +240,15 @@ class Rasterizer:
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.vals), _ptr(self.ranges), _ptr(hits),
              _ptr(max_alpha), _ptr(max_weight), _stream(stream))
 
-    def count_pairs(self, stream=None):
-        """(reached pairs, blended pairs) of the current binning - syncs."""
-        out = torch.zeros(2, dtype=torch.int64, device=self.device)
+    def count_pairs(self, stream=None, waves=False):
+        """(reached pairs, blended pairs) of the current binning, and with
+        ``waves`` also (wave steps, wave steps with a blend) - syncs."""
+        out = torch.zeros(4, dtype=torch.int64, device=self.device)
         call("sr_render_count", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.vals), _ptr(self.ranges), _ptr(out), _stream(stream))
         c = out.cpu().numpy()
+        if waves:
+            return int(c[0]), int(c[1]), int(c[2]), int(c[3])
         return int(c[0]), int(c[1])
 
     def status(self):

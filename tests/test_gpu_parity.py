@@ -83,6 +83,29 @@ def test_forward_config1_full_frame():
     assert flagged < 1e-2
 
 
+def test_work_counts_match_oracle():
+    """sr_render_count: blended pairs equal the oracle's per-pixel blend
+    counts (pixels with a tie flag aside); the wave-step counts bound the
+    pixel counts."""
+    sc = _ragged_scene(41, 500, 0)
+    run = gpu_run(sc)
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0)
+    nb, nb_flagged = 0, 0
+    for v, cam in enumerate(sc.cams):
+        res = render_pixels(P64, cam, geoms[v], _full(cam), RP)
+        fl = res["flag_cut"] | res["flag_term"] | res["flag_clamp"]
+        nb += int(res["nblend"][~fl].sum())
+        nb_flagged += int(res["nblend"][fl].sum())
+    R, B, WS, WB = run["rast"].count_pairs(waves=True)
+    print("reached", R, "blended", B, "oracle blended", nb, "+ flagged", nb_flagged, "wave steps", WS, WB)
+    assert B >= nb
+    if nb_flagged == 0:
+        assert B == nb
+    assert B <= R <= 64 * WS
+    assert WB <= WS and B <= 64 * WB and WB > 0
+
+
 @pytest.mark.parametrize("deg", [0, 3])
 def test_forward_multiview_ragged(deg):
     sc = _ragged_scene(33, 400, deg)
