@@ -14,6 +14,7 @@ Prints one JSON line (rank 0).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +33,33 @@ FWD_OPS_BLEND, FWD_OPS_SKIP = 45.0, 26.0
 BWD_OPS_BLEND, BWD_OPS_SKIP = 110.0, 26.0
 VALU_PEAK = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 HBM_PEAK = 8.0e12                      # bytes/s
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_train_raster_config3_traffic.md")
+
+
+def measured_traffic(workload, tile):
+    """HBM bytes per launch of the fused compositing kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel
+    calibration written there), or None when the summary is missing, was
+    taken on another workload or tile shape, or when the kernel sources have
+    changed since (their SHA-256 differs)."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            kv = dict(line.split(": ", 1) for line in f.read().splitlines() if ": " in line and
+                      line.split(": ", 1)[0] in ("workload", "kernel_sources", "kernel_source_sha256",
+                                                 "traffic_bytes_per_launch"))
+        if kv["workload"].strip() != f"{workload} {tile[0]}x{tile[1]}":
+            return None
+        h = hashlib.sha256()
+        for rel in kv["kernel_sources"].split():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != kv["kernel_source_sha256"].strip():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -204,7 +232,8 @@ def main():
     ops = fwd_ops + bwd_ops
     achieved = ops / (mean_ms["train_raster"] * 1e-3) / 1e12
     result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
-                          "frac": achieved / (VALU_PEAK / 1e12), "traffic": None,
+                          "frac": achieved / (VALU_PEAK / 1e12),
+                          "traffic": measured_traffic(args.workload, tile),
                           "kernel": "k_train_raster (fused forward + loss + backward compositing)",
                           "ops_per_launch": ops}
     result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd,
