@@ -13,6 +13,8 @@ Modules
   sh        real spherical harmonics (view-dependent colour)
   render    differentiable per-pixel front-to-back compositing (torch float64)
   loss      background loss (Eq. 1) and the masked photometric L1 (Eq. 2)
+  regularizers  the 2DGS depth distortion and normal consistency terms of
+            the total loss (Eq. 3)
   prune     occlusion-aware pruning statistics (Section 4.3)
   fd        central finite differences with decision-set filtering
 """
@@ -21,10 +23,12 @@ from .sh import real_sh_basis, sh_basis_scipy, sh_coeff_count
 from .render import render_pixels, render_view, Params64
 from .loss import background_loss64, masked_l1_64
 from .prune import prune_stats64
+from .regularizers import regularizer_loss64, depth_normal64, depth_points64, surface_depth64
 
 __all__ = [
     "RasterParams", "view_geometry64", "bin64", "tile_layout", "rotation_columns64",
     "real_sh_basis", "sh_basis_scipy", "sh_coeff_count",
     "render_pixels", "render_view", "Params64",
     "background_loss64", "masked_l1_64", "prune_stats64",
+    "regularizer_loss64", "depth_normal64", "depth_points64", "surface_depth64",
 ]
