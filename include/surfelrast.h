@@ -213,6 +213,29 @@ sr_status sr_background_loss(int32_t V, const sr_camera *cams_host, const sr_cam
                              size_t ws_bytes, float *loss, float *dL_dalpha, float *dL_dcolor,
                              void *stream);
 
+/* The 2DGS regularisers of the total loss (Eq. 3: alpha L_d + beta L_n, not
+ * masked), from the rendered alpha, depth, normal and distortion of every
+ * view, with the readings
+ *   L_d,v = (1/(H W)) sum_p dist(p)
+ *   P(p)  = s(p) ((i + 0.5 - cx)/fx, (j + 0.5 - cy)/fy, 1), s = depth/alpha
+ *           where alpha > 0, else 0 (camera-space point of pixel (i, j))
+ *   N_d(p) = n / max(|n|, 1e-12), n = (P(i,j+1) - P(i,j-1)) x (P(i+1,j) -
+ *           P(i-1,j)); 0 on the one-pixel border
+ *   L_n,v = (1/(H W)) sum_p (alpha(p) - normal(p) . N_d(p))
+ * loss [2V+1]: loss[v] = L_d,v, loss[V+v] = L_n,v,
+ *   loss[2V] = (1/V) sum_v (w_dist L_d,v + w_normal L_n,v);
+ * gradients of loss[2V] (N_d is differentiated, so depth and alpha also get
+ * the gradient through the neighbours' depth normals):
+ *   dL_dalpha [P]  ADDED to (composes with sr_background_loss, which writes it)
+ *   dL_ddepth [P], dL_dnormal [3P], dL_ddist [P]  overwritten
+ * Feed all of them to sr_backward_raster.  workspace: sr_loss_workspace_size
+ * bytes.  Per-view sums in a fixed order (deterministic). */
+sr_status sr_regularizer_loss(int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
+                              const float *alpha, const float *depth, const float *normal,
+                              const float *dist, float w_dist, float w_normal, void *workspace,
+                              size_t ws_bytes, float *loss, float *dL_dalpha, float *dL_ddepth,
+                              float *dL_dnormal, float *dL_ddist, void *stream);
+
 /* Fused training step of the compositing, one launch for all views: per
  * tile, the forward of sr_render_forward (same outputs, same decisions;
  * occlusion statistics when hits/max_alpha/max_weight are given), the masked

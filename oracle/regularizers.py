@@ -103,4 +103,4 @@ def regularizer_loss64(alphas, depths, normals, dists, cams, w_dist, w_normal):
     total.backward()
     g = lambda x: x.grad.numpy() if x.grad is not None else np.zeros(tuple(x.shape))
     grads = [{"alpha": g(t[0]), "depth": g(t[1]), "normal": g(t[2]), "dist": g(t[3])} for t in ts]
-    return {"per_view": per_view, "total": float(total), "grads": grads}
+    return {"per_view": per_view, "total": float(total.detach()), "grads": grads}

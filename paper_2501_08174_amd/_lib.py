@@ -25,7 +25,7 @@ SR_COUNTERS = 4
 EXPORTED = (
     "sr_last_error", "sr_version", "sr_tile_supported", "sr_layout_views", "sr_preprocess",
     "sr_bin_workspace_size", "sr_bin_and_sort", "sr_render_forward", "sr_render_backward",
-    "sr_backward_raster", "sr_backward_project", "sr_loss_workspace_size", "sr_background_loss", "sr_train_step_raster", "sr_prune_contrib",
+    "sr_backward_raster", "sr_backward_project", "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_train_step_raster", "sr_prune_contrib",
     "sr_render_count", "sr_prune_mask",
 )
 
@@ -75,6 +75,8 @@ def _declare(lib):
         "sr_backward_project": (c_int32, [V, c_int32, c_int32] + [V] * 16),
         "sr_loss_workspace_size": (c_int32, [c_int32, V, POINTER(c_size_t)]),
         "sr_background_loss": (c_int32, [c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V]),
+        "sr_regularizer_loss": (c_int32, [c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V, V,
+                                          V]),
         "sr_train_step_raster": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
                                  + [V] * 14),
         "sr_prune_contrib": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),

@@ -326,6 +326,30 @@ sr_status sr_background_loss(int32_t V, const sr_camera* cams_host, const sr_cam
                       "sr_background_loss");
 }
 
+sr_status sr_regularizer_loss(int32_t V, const sr_camera* cams_host, const sr_camera* cams_dev, const float* alpha,
+                              const float* depth, const float* normal, const float* dist, float w_dist,
+                              float w_normal, void* workspace, size_t ws_bytes, float* loss, float* dL_dalpha,
+                              float* dL_ddepth, float* dL_dnormal, float* dL_ddist, void* stream) {
+    if (V < 0) return fail(SR_ERR_ARG, "V < 0");
+    if (V == 0) return SR_OK;
+    SR_NEED(cams_host); SR_NEED(cams_dev); SR_NEED(alpha); SR_NEED(depth); SR_NEED(normal); SR_NEED(dist);
+    SR_NEED(loss); SR_NEED(workspace); SR_NEED(dL_dalpha); SR_NEED(dL_ddepth); SR_NEED(dL_dnormal);
+    SR_NEED(dL_ddist);
+    int64_t mhw = 0, pix = 0;
+    for (int v = 0; v < V; ++v) {
+        const sr_camera& c = cams_host[v];
+        if (c.width < 1 || c.height < 1) return fail(SR_ERR_ARG, "view %d: empty", v);
+        if (c.pix_offset != pix) return fail(SR_ERR_ARG, "view %d: pix_offset not laid out", v);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(SR_ERR_ARG, "view %d: focal lengths must be positive", v);
+        pix += (int64_t)c.width * c.height;
+        if ((int64_t)c.width * c.height > mhw) mhw = (int64_t)c.width * c.height;
+    }
+    if (ws_bytes < sr::loss_workspace_bytes(V, mhw)) return fail(SR_ERR_ARG, "regularizer workspace too small");
+    return hip_status(sr::launch_reg_loss(V, mhw, cams_dev, alpha, depth, normal, dist, w_dist, w_normal, workspace,
+                                          loss, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist, (hipStream_t)stream),
+                      "sr_regularizer_loss");
+}
+
 sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
                            const sr_camera* cams_dev, const float* geom, const uint32_t* vals, const uint32_t* ranges,
                            uint32_t* hits, float* max_alpha, float* max_weight, void* stream) {

@@ -219,6 +219,19 @@ class Rasterizer:
              _stream(stream))
         return self.loss_out
 
+    def regularizer_loss(self, w_dist: float, w_normal: float, dL_dalpha: torch.Tensor, dL_ddepth: torch.Tensor,
+                         dL_dnormal: torch.Tensor, dL_ddist: torch.Tensor, stream=None):
+        """The 2DGS terms of Eq. 3 on the current forward outputs (sr_regularizer_loss):
+        returns loss [2V+1] (L_d per view, L_n per view, weighted total);
+        dL_dalpha is added to, the other gradients are overwritten."""
+        if getattr(self, "reg_out", None) is None:
+            self.reg_out = torch.zeros(2 * self.views.V + 1, dtype=torch.float32, device=self.device)
+        call("sr_regularizer_loss", self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.alpha),
+             _ptr(self.depth), _ptr(self.normal), _ptr(self.dist), float(w_dist), float(w_normal),
+             _ptr(self.loss_ws), self.loss_ws.numel(), _ptr(self.reg_out), _ptr(dL_dalpha), _ptr(dL_ddepth),
+             _ptr(dL_dnormal), _ptr(dL_ddist), _stream(stream))
+        return self.reg_out
+
     def train_step_raster(self, mask: torch.Tensor, target: torch.Tensor, gamma: float = 0.5, w_c: float = 1.0,
                           stats=None, accumulate: bool = False, stream=None):
         """Fused forward + loss gradients + backward compositing (one launch);
@@ -364,3 +377,26 @@ class BackgroundLoss(torch.autograd.Function):
     def backward(ctx, g_total, g_loss):
         dA, dC = ctx.saved_tensors
         return (dA * g_total, (dC * g_total) if ctx.has_c else None, None, None, None, None, None, None)
+
+
+class RegularizerLoss(torch.autograd.Function):
+    """The 2DGS terms of Eq. 3 (sr_regularizer_loss) of all views: returns
+    (1/V) sum_v (w_dist L_d,v + w_normal L_n,v) and the per-view terms
+    [L_d,0..V-1, L_n,0..V-1]."""
+
+    @staticmethod
+    def forward(ctx, alpha, depth, normal, dist, views: ViewBatch, w_dist: float, w_normal: float, ws):
+        V = views.V
+        loss = torch.zeros(2 * V + 1, dtype=torch.float32, device=alpha.device)
+        dA = torch.zeros_like(alpha)
+        dD, dN, dS = torch.empty_like(depth), torch.empty_like(normal), torch.empty_like(dist)
+        call("sr_regularizer_loss", V, views.host_ptr, _ptr(views.dev), _ptr(alpha.contiguous()),
+             _ptr(depth.contiguous()), _ptr(normal.contiguous()), _ptr(dist.contiguous()), float(w_dist),
+             float(w_normal), _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _stream())
+        ctx.save_for_backward(dA, dD, dN, dS)
+        return loss[2 * V], loss[: 2 * V]
+
+    @staticmethod
+    def backward(ctx, g_total, g_loss):
+        dA, dD, dN, dS = ctx.saved_tensors
+        return dA * g_total, dD * g_total, dN * g_total, dS * g_total, None, None, None, None
