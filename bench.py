@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tile", default="auto", help="WxH tile shape, or 'auto' to pick by timing")
     ap.add_argument("--no-unfused", action="store_true", help="skip timing the separate-launch step")
+    ap.add_argument("--no-eq3", action="store_true", help="skip timing the step with the whole Eq. 3 loss")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for the HBM traffic counters)")
     return ap.parse_args()
@@ -96,14 +97,21 @@ class Pipeline:
         self.target = torch.tensor(np.concatenate([t.reshape(-1) for t in targets]), device="cuda")
         self.dA = torch.zeros_like(self.rast.alpha)
         self.dC = torch.zeros_like(self.rast.color)
+        self.dD = torch.zeros_like(self.rast.depth)
+        self.dN = torch.zeros_like(self.rast.normal)
+        self.dS = torch.zeros_like(self.rast.dist)
         self.need = self.rast.plan_capacity(params, slack=1.02)
 
     STAGES = ("preprocess", "bin_sort", "train_raster", "backward_project")
     STAGES_UNFUSED = ("preprocess", "bin_sort", "forward+stats", "loss", "backward_raster", "backward_project")
+    STAGES_EQ3 = ("preprocess", "bin_sort", "forward+stats", "loss", "regularizers", "backward_raster",
+                  "backward_project")
 
-    def step(self, ev=None, fused=True):
+    def step(self, ev=None, fused=True, eq3=None):
         """One training step; the compositing is the fused forward + loss +
-        backward launch (fused=True) or the three separate launches."""
+        backward launch (fused=True) or the three separate launches; with
+        eq3 = (w_dist, w_normal) the loss is the whole Eq. 3 (the 2DGS
+        regularisers need neighbouring pixels, so the launches are separate)."""
         r = self.rast
         rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
         rec(0)
@@ -111,7 +119,16 @@ class Pipeline:
         rec(1)
         r.bin()
         rec(2)
-        if fused:
+        if eq3 is not None:
+            r.forward(stats=self.stats, accumulate=True)
+            rec(3)
+            r.loss(self.mask, self.target, 0.5, 1.0, self.dA, self.dC)
+            rec(4)
+            r.regularizer_loss(eq3[0], eq3[1], self.dA, self.dD, self.dN, self.dS)
+            rec(5)
+            r.backward_raster(dC=self.dC, dA=self.dA, dD=self.dD, dN=self.dN, dS=self.dS)
+            rec(6)
+        elif fused:
             r.train_step_raster(self.mask, self.target, 0.5, 1.0, stats=self.stats, accumulate=True)
             rec(3)
         else:
@@ -122,7 +139,7 @@ class Pipeline:
             r.backward_raster(dC=self.dC, dA=self.dA)
             rec(5)
         r.backward_project(self.p, self.g)
-        rec(4 if fused else 6)
+        rec(7 if eq3 is not None else (4 if fused else 6))
 
 
 def cpu_baseline(scene, seconds_budget=20.0):
@@ -250,6 +267,30 @@ def main():
         result["unfused"] = {"ms_per_step": float(st_u.sum(axis=1).mean()),
                              "stage_ms_mean": dict(zip(Pipeline.STAGES_UNFUSED,
                                                        [float(x) for x in st_u.mean(axis=0)]))}
+
+    if not args.no_eq3:
+        # the whole Eq. 3: masked L1 + background + 2DGS distortion and normal
+        # consistency (2DGS's weights for bounded scenes)
+        w_dist, w_normal = 1000.0, 0.05
+        ns_e = len(Pipeline.STAGES_EQ3)
+        ev_e = [[torch.cuda.Event(enable_timing=True) for _ in range(ns_e + 1)] for _ in range(args.steps)]
+        pipe.step(eq3=(w_dist, w_normal))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            pipe.step(ev_e[k], eq3=(w_dist, w_normal))
+        torch.cuda.synchronize()
+        e_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        st_e = np.array([[ev_e[k][i].elapsed_time(ev_e[k][i + 1]) for i in range(ns_e)] for k in range(args.steps)])
+        reg_ms = float(st_e[:, Pipeline.STAGES_EQ3.index("regularizers")].mean())
+        reg_bytes = 52 * P
+        result["eq3"] = {"ms_per_step": e_ms, "Mpixel_per_s": P / (e_ms * 1e-3) / 1e6, "w_dist": w_dist,
+                         "w_normal": w_normal,
+                         "stage_ms_mean": dict(zip(Pipeline.STAGES_EQ3, [float(x) for x in st_e.mean(axis=0)])),
+                         "regularizer_roofline": {"bound": "hbm", "achieved": reg_bytes / (reg_ms * 1e-3) / 1e9,
+                                                  "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                                  "frac": reg_bytes / (reg_ms * 1e-3) / HBM_PEAK,
+                                                  "bytes_per_launch": reg_bytes}}
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -295,11 +295,15 @@ sr_status sr_loss_workspace_size(int32_t V, const sr_camera* cams_host, size_t* 
     SR_NEED(bytes_host);
     if (V > 0) SR_NEED(cams_host);
     int64_t mhw = 0;
+    int mt = 0;
     for (int v = 0; v < V; ++v) {
+        if (cams_host[v].width < 0 || cams_host[v].height < 0) return fail(SR_ERR_ARG, "view %d: negative size", v);
         const int64_t hw = (int64_t)cams_host[v].width * cams_host[v].height;
         if (hw > mhw) mhw = hw;
+        const int t = sr::reg_tile_count(cams_host[v].width, cams_host[v].height);
+        if (t > mt) mt = t;
     }
-    *bytes_host = sr::loss_workspace_bytes(V, mhw);
+    *bytes_host = sr::loss_workspace_bytes(V, mhw, mt);
     return SR_OK;
 }
 
@@ -320,7 +324,7 @@ sr_status sr_background_loss(int32_t V, const sr_camera* cams_host, const sr_cam
         pix += (int64_t)c.width * c.height;
         if ((int64_t)c.width * c.height > mhw) mhw = (int64_t)c.width * c.height;
     }
-    if (ws_bytes < sr::loss_workspace_bytes(V, mhw)) return fail(SR_ERR_ARG, "loss workspace too small");
+    if (ws_bytes < sr::loss_workspace_bytes(V, mhw, 0)) return fail(SR_ERR_ARG, "loss workspace too small");
     return hip_status(sr::launch_loss(V, mhw, cams_dev, alpha, mask, color, target, gamma, w_c, workspace, loss,
                                       dL_dalpha, dL_dcolor, (hipStream_t)stream),
                       "sr_background_loss");
@@ -335,17 +339,19 @@ sr_status sr_regularizer_loss(int32_t V, const sr_camera* cams_host, const sr_ca
     SR_NEED(cams_host); SR_NEED(cams_dev); SR_NEED(alpha); SR_NEED(depth); SR_NEED(normal); SR_NEED(dist);
     SR_NEED(loss); SR_NEED(workspace); SR_NEED(dL_dalpha); SR_NEED(dL_ddepth); SR_NEED(dL_dnormal);
     SR_NEED(dL_ddist);
-    int64_t mhw = 0, pix = 0;
+    int64_t pix = 0;
+    int mt = 0;
     for (int v = 0; v < V; ++v) {
         const sr_camera& c = cams_host[v];
         if (c.width < 1 || c.height < 1) return fail(SR_ERR_ARG, "view %d: empty", v);
         if (c.pix_offset != pix) return fail(SR_ERR_ARG, "view %d: pix_offset not laid out", v);
         if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(SR_ERR_ARG, "view %d: focal lengths must be positive", v);
         pix += (int64_t)c.width * c.height;
-        if ((int64_t)c.width * c.height > mhw) mhw = (int64_t)c.width * c.height;
+        const int t = sr::reg_tile_count(c.width, c.height);
+        if (t > mt) mt = t;
     }
-    if (ws_bytes < sr::loss_workspace_bytes(V, mhw)) return fail(SR_ERR_ARG, "regularizer workspace too small");
-    return hip_status(sr::launch_reg_loss(V, mhw, cams_dev, alpha, depth, normal, dist, w_dist, w_normal, workspace,
+    if (ws_bytes < sr::loss_workspace_bytes(V, 0, mt)) return fail(SR_ERR_ARG, "regularizer workspace too small");
+    return hip_status(sr::launch_reg_loss(V, mt, cams_dev, alpha, depth, normal, dist, w_dist, w_normal, workspace,
                                           loss, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist, (hipStream_t)stream),
                       "sr_regularizer_loss");
 }

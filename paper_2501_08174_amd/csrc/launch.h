@@ -57,11 +57,12 @@ hipError_t launch_loss_from_tiles(int V, const sr_camera* cams, const float* til
 hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, uint8_t* mask, hipStream_t s);
 
 int loss_chunks(int64_t max_hw);
-size_t loss_workspace_bytes(int V, int64_t max_hw);
+size_t loss_workspace_bytes(int V, int64_t max_hw, int max_reg_tiles);
+int reg_tile_count(int W, int H);
 hipError_t launch_loss(int V, int64_t max_hw, const sr_camera* cams, const float* alpha, const uint8_t* mask,
                        const float* color, const float* target, float gamma, float w_c, void* ws, float* loss,
                        float* dL_dalpha, float* dL_dcolor, hipStream_t s);
-hipError_t launch_reg_loss(int V, int64_t max_hw, const sr_camera* cams, const float* alpha, const float* depth,
+hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const float* alpha, const float* depth,
                            const float* normal, const float* dist, float w_dist, float w_normal, void* ws,
                            float* loss, float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
                            hipStream_t s);

@@ -128,32 +128,18 @@ k_loss_tiles(const sr_camera* __restrict__ cams, int V, const float* __restrict_
 //           the camera-space points P = (D / A) ray (0 where A = 0), zero on
 //           the one-pixel border
 //   L_reg = (1/V) sum_v (w_dist L_d,v + w_normal L_n,v)
-// Every pixel computes its own depth normal and, by gathering, the gradient
-// that its point receives through the depth normals of its four neighbours
-// (no atomics: each pixel writes only its own gradients).
+// One workgroup per 32x8 pixel tile of a view: the camera-space points of
+// the tile and a two-pixel halo are formed once in LDS, then the depth
+// normals of the tile and a one-pixel halo with the two vectors every normal
+// passes back to its neighbours' points (the gradient through n = a x b),
+// then each pixel gathers its point's gradient from its four neighbours.
+// Each pixel writes only its own gradients (no atomics); per-tile loss sums
+// go to a per-(view, tile) slot and are reduced in a fixed order.
 
 constexpr float kEpsNormal = 1e-12f;
-
-struct RegView {
-    const float* A;
-    const float* D;
-    int W, H;
-    float fx, fy, cx, cy;
-};
-
-__device__ __forceinline__ float3 reg_ray(const RegView& r, int i, int j) {
-#pragma clang fp contract(off)
-    return make_float3(((float)i + 0.5f - r.cx) / r.fx, ((float)j + 0.5f - r.cy) / r.fy, 1.0f);
-}
-
-__device__ __forceinline__ float3 reg_point(const RegView& r, int i, int j) {
-#pragma clang fp contract(off)
-    const int64_t p = (int64_t)j * r.W + i;
-    const float a = r.A[p];
-    const float s = a > 0.f ? r.D[p] / a : 0.f;
-    const float3 ray = reg_ray(r, i, j);
-    return make_float3(s * ray.x, s * ray.y, s * ray.z);
-}
+constexpr int kRegTX = 32, kRegTY = 8;                 // tile; kNT threads
+constexpr int kRegPX = kRegTX + 4, kRegPY = kRegTY + 4; // points: two-pixel halo
+constexpr int kRegNX = kRegTX + 2, kRegNY = kRegTY + 2; // normals: one-pixel halo
 
 __device__ __forceinline__ float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
 __device__ __forceinline__ float3 f3cross(float3 a, float3 b) {
@@ -165,119 +151,131 @@ __device__ __forceinline__ float f3dot(float3 a, float3 b) {
     return a.x * b.x + a.y * b.y + a.z * b.z;
 }
 
-__device__ __forceinline__ bool reg_interior(const RegView& r, int i, int j) {
-    return i >= 1 && i <= r.W - 2 && j >= 1 && j <= r.H - 2;
+__host__ __device__ inline int reg_tiles_of(int W, int H) {
+    return ((W + kRegTX - 1) / kRegTX) * ((H + kRegTY - 1) / kRegTY);
 }
-
-// Depth normal of an interior pixel: the difference vectors a (rows), b
-// (columns), the unnormalised normal length and N_d.
-struct DepthNormal {
-    float3 a, b, nd;
-    float len;
-};
-
-__device__ __forceinline__ DepthNormal reg_depth_normal(const RegView& r, int i, int j) {
-#pragma clang fp contract(off)
-    DepthNormal d;
-    d.a = f3sub(reg_point(r, i, j + 1), reg_point(r, i, j - 1));
-    d.b = f3sub(reg_point(r, i + 1, j), reg_point(r, i - 1, j));
-    const float3 n = f3cross(d.a, d.b);
-    d.len = sqrtf(f3dot(n, n));
-    const float den = d.len > kEpsNormal ? d.len : kEpsNormal;
-    d.nd = make_float3(n.x / den, n.y / den, n.z / den);
-    return d;
-}
-
-// Gradient of the loss with respect to the unnormalised normal n, given the
-// gradient g with respect to N_d = n / max(|n|, eps).
-__device__ __forceinline__ float3 reg_dn(const DepthNormal& d, float3 g) {
-#pragma clang fp contract(off)
-    if (d.len > kEpsNormal) {
-        const float k = f3dot(d.nd, g);
-        return make_float3((g.x - d.nd.x * k) / d.len, (g.y - d.nd.y * k) / d.len, (g.z - d.nd.z * k) / d.len);
-    }
-    return make_float3(g.x / kEpsNormal, g.y / kEpsNormal, g.z / kEpsNormal);
-}
+__device__ __forceinline__ int reg_tiles(int W, int H) { return reg_tiles_of(W, H); }
 
 __global__ void __launch_bounds__(kNT)
 k_reg_partial(const sr_camera* __restrict__ cams, int V, const float* __restrict__ alpha,
               const float* __restrict__ depth, const float* __restrict__ normal, const float* __restrict__ dist,
-              float w_dist, float w_normal, int nchunk, float* __restrict__ partial, float* __restrict__ dL_dalpha,
+              float w_dist, float w_normal, int nslot, float* __restrict__ partial, float* __restrict__ dL_dalpha,
               float* __restrict__ dL_ddepth, float* __restrict__ dL_dnormal, float* __restrict__ dL_ddist) {
 #pragma clang fp contract(off)
     __shared__ float s[kNT];
+    __shared__ float3 sP[kRegPY][kRegPX];
+    __shared__ float3 sGa[kRegNY][kRegNX], sGb[kRegNY][kRegNX], sNd[kRegNY][kRegNX];
     const int v = blockIdx.y;
     const sr_camera& c = cams[v];
-    const int64_t HW = (int64_t)c.width * c.height;
-    RegView r;
-    r.A = alpha + c.pix_offset;
-    r.D = depth + c.pix_offset;
-    r.W = c.width; r.H = c.height;
-    r.fx = c.fx; r.fy = c.fy; r.cx = c.cx; r.cy = c.cy;
+    const int W = c.width, H = c.height;
+    const int ntx = (W + kRegTX - 1) / kRegTX;
+    const int ntiles = ntx * ((H + kRegTY - 1) / kRegTY);
+    if ((int)blockIdx.x >= ntiles) return;                  // uniform: the whole block leaves
+    const int ty = (int)blockIdx.x / ntx, tx = (int)blockIdx.x - ty * ntx;
+    const int x0 = tx * kRegTX, y0 = ty * kRegTY;
+    const int64_t HW = (int64_t)W * H;
+    const float* A = alpha + c.pix_offset;
+    const float* D = depth + c.pix_offset;
     const float* Nr = normal + 3 * c.pix_offset;
     const float scale = 1.0f / ((float)HW * (float)V);
     const float gn = w_normal * scale;
-    const int64_t b = (int64_t)blockIdx.x * kChunk;
-    float ld = 0.f, ln = 0.f;
-    if (b < HW) {
-        const int64_t e = b + kChunk < HW ? b + kChunk : HW;
-        for (int64_t p = b + threadIdx.x; p < e; p += kNT) {
-            const int j = (int)(p / r.W), i = (int)(p - (int64_t)j * r.W);
-            const int64_t o1 = c.pix_offset + p, o3 = 3 * c.pix_offset + p;
-            const float A = r.A[p];
-            const float3 N = make_float3(Nr[p], Nr[p + HW], Nr[p + 2 * HW]);
-            float3 nd = make_float3(0.f, 0.f, 0.f);
-            if (reg_interior(r, i, j)) nd = reg_depth_normal(r, i, j).nd;
-            ld += dist[o1];
-            ln += A - f3dot(N, nd);
-            // gradient of the point of this pixel through its neighbours' normals
-            float3 dP = make_float3(0.f, 0.f, 0.f);
-            const int ni[4] = {i, i, i - 1, i + 1}, nj[4] = {j - 1, j + 1, j, j};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (!reg_interior(r, ni[q], nj[q])) continue;
-                const DepthNormal d = reg_depth_normal(r, ni[q], nj[q]);
-                const int64_t pq = (int64_t)nj[q] * r.W + ni[q];
-                const float3 g = make_float3(-gn * Nr[pq], -gn * Nr[pq + HW], -gn * Nr[pq + 2 * HW]);
-                const float3 dn = reg_dn(d, g);
-                // n = a x b: dL/da = b x dn, dL/db = dn x a
-                const float3 t = q < 2 ? f3cross(d.b, dn) : f3cross(dn, d.a);
-                const float sg = (q == 0 || q == 2) ? 1.0f : -1.0f;
-                dP = make_float3(dP.x + sg * t.x, dP.y + sg * t.y, dP.z + sg * t.z);
-            }
-            const float3 ray = reg_ray(r, i, j);
-            const float ds = f3dot(dP, ray);
-            float gA = gn, gD = 0.f;
-            if (A > 0.f) {
-                gD = ds / A;
-                gA = gA - ds * (r.D[p] / A) / A;
-            }
-            dL_dalpha[o1] += gA;
-            dL_ddepth[o1] = gD;
-            dL_dnormal[o3] = -gn * nd.x;
-            dL_dnormal[o3 + HW] = -gn * nd.y;
-            dL_dnormal[o3 + 2 * HW] = -gn * nd.z;
-            dL_ddist[o1] = w_dist * scale;
+    const float fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
+    // points P = (D / A) ray of the tile and a two-pixel halo (0 outside)
+    for (int k = threadIdx.x; k < kRegPX * kRegPY; k += kNT) {
+        const int ly = k / kRegPX, lx = k - ly * kRegPX;
+        const int i = x0 - 2 + lx, j = y0 - 2 + ly;
+        float3 P = make_float3(0.f, 0.f, 0.f);
+        if (i >= 0 && i < W && j >= 0 && j < H) {
+            const int64_t p = (int64_t)j * W + i;
+            const float a = A[p];
+            const float sd = a > 0.f ? D[p] / a : 0.f;
+            P = make_float3(sd * (((float)i + 0.5f - cx) / fx), sd * (((float)j + 0.5f - cy) / fy), sd);
         }
+        sP[ly][lx] = P;
+    }
+    __syncthreads();
+    // depth normals of the tile and a one-pixel halo; the vectors b x dn and
+    // dn x a that each normal sends to the points of its neighbours
+    for (int k = threadIdx.x; k < kRegNX * kRegNY; k += kNT) {
+        const int ly = k / kRegNX, lx = k - ly * kRegNX;
+        const int i = x0 - 1 + lx, j = y0 - 1 + ly;
+        float3 nd = make_float3(0.f, 0.f, 0.f), ga = nd, gb = nd;
+        if (i >= 1 && i <= W - 2 && j >= 1 && j <= H - 2) {
+            const int px = lx + 1, py = ly + 1;              // position in sP
+            const float3 a = f3sub(sP[py + 1][px], sP[py - 1][px]);
+            const float3 b = f3sub(sP[py][px + 1], sP[py][px - 1]);
+            const float3 n = f3cross(a, b);
+            const float len = sqrtf(f3dot(n, n));
+            const float den = len > kEpsNormal ? len : kEpsNormal;
+            nd = make_float3(n.x / den, n.y / den, n.z / den);
+            const int64_t p = (int64_t)j * W + i;
+            const float3 g = make_float3(-gn * Nr[p], -gn * Nr[p + HW], -gn * Nr[p + 2 * HW]);
+            float3 dn;
+            if (len > kEpsNormal) {
+                const float kk = f3dot(nd, g);
+                dn = make_float3((g.x - nd.x * kk) / len, (g.y - nd.y * kk) / len, (g.z - nd.z * kk) / len);
+            } else {
+                dn = make_float3(g.x / kEpsNormal, g.y / kEpsNormal, g.z / kEpsNormal);
+            }
+            ga = f3cross(b, dn);                             // dL/da
+            gb = f3cross(dn, a);                             // dL/db
+        }
+        sNd[ly][lx] = nd;
+        sGa[ly][lx] = ga;
+        sGb[ly][lx] = gb;
+    }
+    __syncthreads();
+    // one pixel per thread
+    const int lx = (int)threadIdx.x % kRegTX, ly = (int)threadIdx.x / kRegTX;
+    const int i = x0 + lx, j = y0 + ly;
+    float ld = 0.f, ln = 0.f;
+    if (i < W && j < H) {
+        const int64_t p = (int64_t)j * W + i;
+        const int64_t o1 = c.pix_offset + p, o3 = 3 * c.pix_offset + p;
+        const int nx = lx + 1, ny = ly + 1;                  // position in the normal arrays
+        const float3 nd = sNd[ny][nx];
+        const float a = A[p];
+        const float3 N = make_float3(Nr[p], Nr[p + HW], Nr[p + 2 * HW]);
+        ld = dist[o1];
+        ln = a - f3dot(N, nd);
+        // this point is P(i, j+1) of the normal above, P(i, j-1) of the one
+        // below, P(i+1, j) of the left one and P(i-1, j) of the right one
+        const float3 u = sGa[ny - 1][nx], dw = sGa[ny + 1][nx], l = sGb[ny][nx - 1], r = sGb[ny][nx + 1];
+        const float3 dP = make_float3(((u.x - dw.x) + l.x) - r.x, ((u.y - dw.y) + l.y) - r.y,
+                                      ((u.z - dw.z) + l.z) - r.z);
+        const float3 ray = make_float3(((float)i + 0.5f - cx) / fx, ((float)j + 0.5f - cy) / fy, 1.0f);
+        const float ds = f3dot(dP, ray);
+        float gA = gn, gD = 0.f;
+        if (a > 0.f) {
+            gD = ds / a;
+            gA = gA - ds * (D[p] / a) / a;
+        }
+        dL_dalpha[o1] += gA;
+        dL_ddepth[o1] = gD;
+        dL_dnormal[o3] = -gn * nd.x;
+        dL_dnormal[o3 + HW] = -gn * nd.y;
+        dL_dnormal[o3 + 2 * HW] = -gn * nd.z;
+        dL_ddist[o1] = w_dist * scale;
     }
     ld = block_sum(ld, s);
     ln = block_sum(ln, s);
     if (threadIdx.x == 0) {
-        partial[2 * ((size_t)v * nchunk + blockIdx.x)] = ld;
-        partial[2 * ((size_t)v * nchunk + blockIdx.x) + 1] = ln;
+        partial[2 * ((size_t)v * nslot + blockIdx.x)] = ld;
+        partial[2 * ((size_t)v * nslot + blockIdx.x) + 1] = ln;
     }
 }
 
 // loss[v] = L_d,v, loss[V+v] = L_n,v from the chunk partials; loss[2V] total
 __global__ void __launch_bounds__(kNT)
-k_reg_final(const sr_camera* __restrict__ cams, int V, int nchunk, const float* __restrict__ partial,
+k_reg_final(const sr_camera* __restrict__ cams, int V, int nslot, const float* __restrict__ partial,
             float* __restrict__ loss) {
     __shared__ float s[kNT];
     const int v = blockIdx.x;
+    const int nt = reg_tiles(cams[v].width, cams[v].height);
     float ld = 0.f, ln = 0.f;
-    for (int i = threadIdx.x; i < nchunk; i += kNT) {
-        ld += partial[2 * ((size_t)v * nchunk + i)];
-        ln += partial[2 * ((size_t)v * nchunk + i) + 1];
+    for (int i = threadIdx.x; i < nt; i += kNT) {
+        ld += partial[2 * ((size_t)v * nslot + i)];
+        ln += partial[2 * ((size_t)v * nslot + i) + 1];
     }
     ld = block_sum(ld, s);
     ln = block_sum(ln, s);
@@ -299,15 +297,16 @@ k_reg_total(int V, float w_dist, float w_normal, float* __restrict__ loss) {
 
 }  // namespace
 
-hipError_t launch_reg_loss(int V, int64_t max_hw, const sr_camera* cams, const float* alpha, const float* depth,
+int reg_tile_count(int W, int H) { return reg_tiles_of(W, H); }
+
+hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const float* alpha, const float* depth,
                            const float* normal, const float* dist, float w_dist, float w_normal, void* ws,
                            float* loss, float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
                            hipStream_t s) {
-    if (V == 0) return hipSuccess;
-    const int nchunk = loss_chunks(max_hw);
-    hipLaunchKernelGGL(k_reg_partial, dim3(nchunk, V), dim3(kNT), 0, s, cams, V, alpha, depth, normal, dist, w_dist,
-                       w_normal, nchunk, (float*)ws, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist);
-    hipLaunchKernelGGL(k_reg_final, dim3(V), dim3(kNT), 0, s, cams, V, nchunk, (const float*)ws, loss);
+    if (V == 0 || max_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reg_partial, dim3(max_tiles, V), dim3(kNT), 0, s, cams, V, alpha, depth, normal, dist,
+                       w_dist, w_normal, max_tiles, (float*)ws, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist);
+    hipLaunchKernelGGL(k_reg_final, dim3(V), dim3(kNT), 0, s, cams, V, max_tiles, (const float*)ws, loss);
     hipLaunchKernelGGL(k_reg_total, dim3(1), dim3(kNT), 0, s, V, w_dist, w_normal, loss);
     return hipGetLastError();
 }
@@ -322,7 +321,10 @@ hipError_t launch_loss_from_tiles(int V, const sr_camera* cams, const float* til
 
 int loss_chunks(int64_t max_hw) { return (int)((max_hw + kChunk - 1) / kChunk); }
 
-size_t loss_workspace_bytes(int V, int64_t max_hw) { return (size_t)V * loss_chunks(max_hw) * 2 * sizeof(float); }
+size_t loss_workspace_bytes(int V, int64_t max_hw, int max_reg_tiles) {
+    const int64_t slots = loss_chunks(max_hw) > max_reg_tiles ? loss_chunks(max_hw) : max_reg_tiles;
+    return (size_t)V * (size_t)slots * 2 * sizeof(float);
+}
 
 hipError_t launch_loss(int V, int64_t max_hw, const sr_camera* cams, const float* alpha, const uint8_t* mask,
                        const float* color, const float* target, float gamma, float w_c, void* ws, float* loss,

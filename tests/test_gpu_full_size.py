@@ -311,3 +311,75 @@ def test_config4_pruning_shell_scene():
         checked += 1
     print(f"sampled surfels checked against the oracle: {checked} of {sample.size}")
     assert checked >= sample.size // 2
+
+
+def test_config3_regularizers_full_size():
+    """The 2DGS terms of Eq. 3 on the full config-3 forward (16 views,
+    16.6 Mpx): per-view losses against the oracle over whole views; the
+    gradients on sampled crops (the oracle evaluated on the crop grown by the
+    two-pixel reach of the depth normals, rescaled to the whole-view means),
+    pixels whose depth normals are ill-conditioned in float32 reported apart."""
+    from paper_2501_08174_amd import _lib
+    from oracle.regularizers import regularizer_view64
+    sc = scenes.make_config3()
+    run = gpu_run(sc)
+    rast, views = run["rast"], run["views"]
+    wd, wn = 1000.0, 0.05
+    P, V = views.P, views.V
+    dA = torch.zeros(P, device="cuda")
+    dD, dN, dS = torch.zeros(P, device="cuda"), torch.zeros(3 * P, device="cuda"), torch.zeros(P, device="cuda")
+    loss = rast.regularizer_loss(wd, wn, dA, dD, dN, dS).cpu().numpy()
+    torch.cuda.synchronize()
+    print("config3 regularisers: GPU pass done", flush=True)
+    rng = np.random.default_rng(9)
+    for v in range(V):
+        pv = per_view(rast, v)
+        L_d, L_n = regularizer_view64(pv["alpha"], pv["depth"], pv["normal"], pv["dist"], sc.cams[v])
+        assert abs(loss[v] - float(L_d)) <= 1e-4 * abs(float(L_d)) + 1e-7, (v, loss[v], float(L_d))
+        assert abs(loss[V + v] - float(L_n)) <= 1e-4 * abs(float(L_n)) + 1e-7, (v, loss[V + v], float(L_n))
+    print("config3 regularisers: 16 per-view losses match", flush=True)
+    dA, dD, dN, dS = (t.cpu().numpy() for t in (dA, dD, dN, dS))
+    for v in (0, 7, 13):
+        cam = sc.cams[v]
+        W, H = cam.width, cam.height
+        pv = per_view(rast, v)
+        o, HW = views.pix_offsets[v], W * H
+        for (x0, y0) in [(0, 0), (int(rng.integers(2, W - 50)), int(rng.integers(2, H - 50)))]:
+            xe0, ye0, xe1, ye1 = max(x0 - 2, 0), max(y0 - 2, 0), min(x0 + 48 + 2, W), min(y0 + 48 + 2, H)
+            sub = {k: (pv[k][..., ye0:ye1, xe0:xe1]) for k in ("alpha", "depth", "normal", "dist")}
+            cs = scenes.Camera(viewmat=cam.viewmat, fx=cam.fx, fy=cam.fy, cx=cam.cx - xe0, cy=cam.cy - ye0,
+                               width=xe1 - xe0, height=ye1 - ye0, campos=cam.campos)
+            ref = oracle.regularizer_loss64([sub["alpha"]], [sub["depth"]], [sub["normal"]], [sub["dist"]], [cs],
+                                            wd, wn)["grads"][0]
+            k = (xe1 - xe0) * (ye1 - ye0) / (HW * V)      # crop mean -> whole-view mean over V views
+            cy, cx = slice(y0 - ye0, y0 - ye0 + 48), slice(x0 - xe0, x0 - xe0 + 48)
+            # conditioning of the depth normals the crop's gradients use
+            Pts = oracle.depth_points64(sub["alpha"], sub["depth"], cs).numpy()
+            a = np.zeros_like(Pts); b = np.zeros_like(Pts)
+            a[1:-1, 1:-1] = Pts[2:, 1:-1] - Pts[:-2, 1:-1]
+            b[1:-1, 1:-1] = Pts[1:-1, 2:] - Pts[1:-1, :-2]
+            cond = np.linalg.norm(np.cross(a, b), axis=-1) / np.maximum(
+                np.linalg.norm(a, axis=-1) * np.linalg.norm(b, axis=-1), 1e-30)
+            # pixels on the image border have no depth normal on either side
+            jj = np.arange(ye0, ye1)[:, None]; ii = np.arange(xe0, xe1)[None, :]
+            interior = (ii >= 1) & (ii <= W - 2) & (jj >= 1) & (jj <= H - 2)
+            inner_e = np.zeros(cond.shape, bool); inner_e[1:-1, 1:-1] = True
+            bad = (cond < 1e-2) & interior & inner_e
+            near = bad.copy()
+            near[1:] |= bad[:-1]; near[:-1] |= bad[1:]; near[:, 1:] |= bad[:, :-1]; near[:, :-1] |= bad[:, 1:]
+            keep = ~near[cy, cx]
+            gy = np.arange(y0, y0 + 48)[:, None] * W + np.arange(x0, x0 + 48)[None, :]
+            got = {"alpha": dA[o + gy], "depth": dD[o + gy], "dist": dS[o + gy],
+                   "normal": np.stack([dN[3 * o + c * HW + gy] for c in range(3)])}
+            for name in ("alpha", "depth", "dist", "normal"):
+                r = ref[name][..., cy, cx] * k
+                gg = got[name]
+                if name == "normal":
+                    r, gg = r[:, keep], gg[:, keep]
+                else:
+                    r, gg = r[keep], gg[keep]
+                scale = np.abs(r).max()
+                err = np.abs(gg - r).max() / max(scale, 1e-30)
+                assert err <= 1e-3, (v, x0, y0, name, err)
+            print(f"config3 view {v} crop ({x0},{y0}): gradients match; ill-conditioned pixels apart: "
+                  f"{int((~keep).sum())}", flush=True)
