@@ -21,8 +21,7 @@ namespace sr {
 namespace {
 
 constexpr int kNT = 256;            // threads per block
-constexpr int kIPT = 16;            // keys per thread per radix sub-tile
-constexpr int kTile = kNT * kIPT;   // keys per radix sub-tile
+constexpr int kTile = kNT * 32;     // block chunks are multiples of the largest radix sub-tile
 constexpr int kMaxDigitBits = 9;    // radix digits of up to 9 bits (512 buckets)
 constexpr int kMaxRadix = 1 << kMaxDigitBits;
 
@@ -196,6 +195,7 @@ k_radix_digit_scan(uint32_t* __restrict__ hist, int G, uint32_t* __restrict__ to
 
 // Every thread owns the two digits 2*tid and 2*tid + 1 of the per-digit
 // bookkeeping (up to 512 digits).
+template <int IPT>
 __global__ void __launch_bounds__(kNT)
 k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
                 const uint32_t* __restrict__ count, int G, int shift, int bits,
@@ -204,8 +204,8 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
     __shared__ uint32_t s_off[kMaxRadix];
     __shared__ uint32_t s_wcnt[4][kMaxRadix];
     __shared__ uint32_t s_lstart[kMaxRadix];
-    __shared__ uint32_t s_keys[kTile];
-    __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_keys[kNT * IPT];
+    __shared__ uint32_t s_vals[kNT * IPT];
     __shared__ uint32_t s_w[4];
     const int R = 1 << bits;
     const uint32_t mask = (uint32_t)R - 1u;
@@ -222,15 +222,15 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         s_off[d1] = d1 < R ? ex + t0 + hist[(size_t)d1 * G + blockIdx.x] : 0u;
     }
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (uint32_t tb = b; tb < e; tb += kTile) {
+    for (uint32_t tb = b; tb < e; tb += kNT * IPT) {
         for (int i = tid; i < 4 * kMaxRadix; i += kNT) (&s_wcnt[0][0])[i] = 0u;
         __syncthreads();
-        uint32_t kk[kIPT], vv[kIPT], rank[kIPT];
-        int dg[kIPT];
-        bool ok[kIPT];
-        const uint32_t seg = tb + (uint32_t)w * 64u * kIPT;
+        uint32_t kk[IPT], vv[IPT], rank[IPT];
+        int dg[IPT];
+        bool ok[IPT];
+        const uint32_t seg = tb + (uint32_t)w * 64u * IPT;
 #pragma unroll
-        for (int r = 0; r < kIPT; ++r) {
+        for (int r = 0; r < IPT; ++r) {
             const uint32_t idx = seg + (uint32_t)r * 64u + (uint32_t)lane;
             ok[r] = idx < e;
             kk[r] = ok[r] ? keys_in[idx] : 0u;
@@ -238,7 +238,7 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
             dg[r] = (int)((kk[r] >> shift) & mask);
         }
 #pragma unroll
-        for (int r = 0; r < kIPT; ++r) {
+        for (int r = 0; r < IPT; ++r) {
             uint64_t peers = ballot64(ok[r]);
             for (int bit = 0; bit < bits; ++bit) {
                 const bool set = (dg[r] >> bit) & 1;
@@ -274,7 +274,7 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kIPT; ++r) {
+        for (int r = 0; r < IPT; ++r) {
             if (ok[r]) {
                 const uint32_t lp = s_lstart[dg[r]] + s_wcnt[w][dg[r]] + rank[r];
                 s_keys[lp] = kk[r];
@@ -282,7 +282,7 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
             }
         }
         __syncthreads();
-        const uint32_t cntTile = (e - tb) < (uint32_t)kTile ? (e - tb) : (uint32_t)kTile;
+        const uint32_t cntTile = (e - tb) < (uint32_t)(kNT * IPT) ? (e - tb) : (uint32_t)(kNT * IPT);
         for (uint32_t i = tid; i < cntTile; i += kNT) {
             const uint32_t key = s_keys[i];
             const int d = (int)((key >> shift) & mask);
@@ -530,8 +530,14 @@ uint32_t* radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uin
         uint32_t* dv = last ? vals_dst : (sv == v0 ? v1 : v0);
         hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kNT), 0, s, sk, count, G, shift, bits, hist);
         hipLaunchKernelGGL(k_radix_digit_scan, dim3(1 << bits), dim3(kNT), 0, s, hist, G, tot);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kNT), 0, s, sk, sv, count, G, shift, bits, hist, tot,
-                           dk, dv);
+        // the first pass reads the instances in emission order, whose digit
+        // runs are short: larger sub-tiles give longer runs per digit on output
+        if (p == 0)
+            hipLaunchKernelGGL(k_radix_scatter<32>, dim3(G), dim3(kNT), 0, s, sk, sv, count, G, shift, bits, hist,
+                               tot, dk, dv);
+        else
+            hipLaunchKernelGGL(k_radix_scatter<16>, dim3(G), dim3(kNT), 0, s, sk, sv, count, G, shift, bits, hist,
+                               tot, dk, dv);
         sk = dk;
         sv = dv;
         shift += bits;
@@ -566,7 +572,7 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
         for (int p = 0; p < 4; ++p) {
             hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kNT), 0, s, sk, counters, G, 8 * p, 8, w.hist);
             hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kNT), 0, s, w.hist, G, w.tot);
-            hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kNT), 0, s, sk, sv, counters, G, 8 * p, 8, w.hist,
+            hipLaunchKernelGGL(k_radix_scatter<16>, dim3(G), dim3(kNT), 0, s, sk, sv, counters, G, 8 * p, 8, w.hist,
                                w.tot, dk, dv);
             uint32_t* t;
             t = sk; sk = dk; dk = t;
