@@ -15,6 +15,8 @@ Modules
   loss      background loss (Eq. 1) and the masked photometric L1 (Eq. 2)
   regularizers  the 2DGS depth distortion and normal consistency terms of
             the total loss (Eq. 3)
+  ssim      masked SSIM / D-SSIM (the rest of Eq. 2's photometric loss) and
+            masked PSNR
   prune     occlusion-aware pruning statistics (Section 4.3)
   fd        central finite differences with decision-set filtering
 """
@@ -24,6 +26,7 @@ from .render import render_pixels, render_view, Params64
 from .loss import background_loss64, masked_l1_64
 from .prune import prune_stats64
 from .regularizers import regularizer_loss64, depth_normal64, depth_points64, surface_depth64
+from .ssim import dssim_loss64, masked_ssim64, masked_psnr64, ssim_map64, gaussian_1d64, window_2d64
 
 __all__ = [
     "RasterParams", "view_geometry64", "bin64", "tile_layout", "rotation_columns64",
@@ -31,4 +34,5 @@ __all__ = [
     "render_pixels", "render_view", "Params64",
     "background_loss64", "masked_l1_64", "prune_stats64",
     "regularizer_loss64", "depth_normal64", "depth_points64", "surface_depth64",
+    "dssim_loss64", "masked_ssim64", "masked_psnr64", "ssim_map64", "gaussian_1d64", "window_2d64",
 ]
