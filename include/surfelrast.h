@@ -236,6 +236,29 @@ sr_status sr_regularizer_loss(int32_t V, const sr_camera *cams_host, const sr_ca
                               size_t ws_bytes, float *loss, float *dL_dalpha, float *dL_ddepth,
                               float *dL_dnormal, float *dL_ddist, void *stream);
 
+/* Bytes of workspace sr_ssim_loss needs for these views (with_grad != 0:
+ * room for the gradient maps too). */
+sr_status sr_ssim_workspace_size(int32_t V, const sr_camera *cams_host, int32_t with_grad,
+                                 size_t *bytes_host);
+
+/* Masked structural similarity of every view (the D-SSIM part of Eq. 2's
+ * photometric loss, applied to M*R and M*I like the L1 part) and the masked
+ * metrics.  Per colour channel, with x = M R and y = M I and G the 11x11
+ * Gaussian window (sigma 1.5, normalised; correlation with zero padding):
+ *   S(p) = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x + s_y + C2)),
+ *   mu = G*x, s_x = G*x^2 - mu_x^2, s_xy = G*(xy) - mu_x mu_y, C1 = 1e-4, C2 = 9e-4
+ * out [2V+1]: out[v] = SSIM_v (mean of S over the 3 channels and H W pixels),
+ *   out[V+v] = PSNR_v = -10 log10(mean (x - y)^2) (+inf when equal),
+ *   out[2V] = (1/V) sum_v w_s (1 - SSIM_v)
+ * dL_dcolor [3P]: the gradient of out[2V] is ADDED (compose with
+ * sr_background_loss, which writes the L1 gradient); NULL computes the
+ * metrics only.  Full 3DGS photometric loss: w_c = 1 - lambda for the L1 term
+ * and w_s = lambda (0.2).  mask [P] uint8; planar colour like the renderer.
+ * Per-view sums in a fixed order (deterministic). */
+sr_status sr_ssim_loss(int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
+                       const float *color, const float *target, const uint8_t *mask, float w_s,
+                       void *workspace, size_t ws_bytes, float *out, float *dL_dcolor, void *stream);
+
 /* Fused training step of the compositing, one launch for all views: per
  * tile, the forward of sr_render_forward (same outputs, same decisions;
  * occlusion statistics when hits/max_alpha/max_weight are given), the masked

@@ -25,7 +25,8 @@ SR_COUNTERS = 4
 EXPORTED = (
     "sr_last_error", "sr_version", "sr_tile_supported", "sr_layout_views", "sr_preprocess",
     "sr_bin_workspace_size", "sr_bin_and_sort", "sr_render_forward", "sr_render_backward",
-    "sr_backward_raster", "sr_backward_project", "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_train_step_raster", "sr_prune_contrib",
+    "sr_backward_raster", "sr_backward_project", "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_ssim_workspace_size", "sr_ssim_loss",
+    "sr_train_step_raster", "sr_prune_contrib",
     "sr_render_count", "sr_prune_mask",
 )
 
@@ -77,6 +78,8 @@ def _declare(lib):
         "sr_background_loss": (c_int32, [c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V]),
         "sr_regularizer_loss": (c_int32, [c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V, V,
                                           V]),
+        "sr_ssim_workspace_size": (c_int32, [c_int32, V, c_int32, POINTER(c_size_t)]),
+        "sr_ssim_loss": (c_int32, [c_int32, V, V, V, V, V, c_float, V, c_size_t, V, V, V]),
         "sr_train_step_raster": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
                                  + [V] * 14),
         "sr_prune_contrib": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
@@ -114,6 +117,13 @@ def call(name: str, *args):
 def workspace_bytes_bin(N: int, V: int, cap: int) -> int:
     out = c_size_t(0)
     check(lib().sr_bin_workspace_size(N, V, cap, byref(out)))
+    return out.value
+
+
+def workspace_bytes_ssim(V: int, cams_host, with_grad: bool = True) -> int:
+    out = c_size_t(0)
+    check(lib().sr_ssim_workspace_size(V, ctypes.cast(cams_host, c_void_p) if V else None, int(with_grad),
+                                       byref(out)))
     return out.value
 
 

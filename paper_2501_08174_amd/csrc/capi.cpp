@@ -356,6 +356,51 @@ sr_status sr_regularizer_loss(int32_t V, const sr_camera* cams_host, const sr_ca
                       "sr_regularizer_loss");
 }
 
+static sr_status ssim_sizes(int32_t V, const sr_camera* cams_host, int* max_slots, int64_t* P) {
+    int64_t pix = 0;
+    int ms = 0;
+    for (int v = 0; v < V; ++v) {
+        const sr_camera& c = cams_host[v];
+        if (c.width < 1 || c.height < 1) return fail(SR_ERR_ARG, "view %d: empty", v);
+        if (c.pix_offset != pix) return fail(SR_ERR_ARG, "view %d: pix_offset not laid out", v);
+        pix += (int64_t)c.width * c.height;
+        const int t = sr::ssim_slots(c.width, c.height);
+        if (t > ms) ms = t;
+    }
+    *max_slots = ms;
+    *P = pix;
+    return SR_OK;
+}
+
+sr_status sr_ssim_workspace_size(int32_t V, const sr_camera* cams_host, int32_t with_grad, size_t* bytes_host) {
+    if (V < 0) return fail(SR_ERR_ARG, "V < 0");
+    SR_NEED(bytes_host);
+    if (V == 0) { *bytes_host = 0; return SR_OK; }
+    SR_NEED(cams_host);
+    int ms = 0;
+    int64_t P = 0;
+    SR_TRY(ssim_sizes(V, cams_host, &ms, &P));
+    *bytes_host = sr::ssim_workspace_bytes(V, ms, P, with_grad != 0);
+    return SR_OK;
+}
+
+sr_status sr_ssim_loss(int32_t V, const sr_camera* cams_host, const sr_camera* cams_dev, const float* color,
+                       const float* target, const uint8_t* mask, float w_s, void* workspace, size_t ws_bytes,
+                       float* out, float* dL_dcolor, void* stream) {
+    if (V < 0) return fail(SR_ERR_ARG, "V < 0");
+    if (V == 0) return SR_OK;
+    SR_NEED(cams_host); SR_NEED(cams_dev); SR_NEED(color); SR_NEED(target); SR_NEED(mask); SR_NEED(workspace);
+    SR_NEED(out);
+    int ms = 0;
+    int64_t P = 0;
+    SR_TRY(ssim_sizes(V, cams_host, &ms, &P));
+    if (ws_bytes < sr::ssim_workspace_bytes(V, ms, P, dL_dcolor != nullptr))
+        return fail(SR_ERR_ARG, "ssim workspace too small");
+    return hip_status(sr::launch_ssim(V, ms, P, cams_dev, color, target, mask, w_s, workspace, out, dL_dcolor,
+                                      (hipStream_t)stream),
+                      "sr_ssim_loss");
+}
+
 sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
                            const sr_camera* cams_dev, const float* geom, const uint32_t* vals, const uint32_t* ranges,
                            uint32_t* hits, float* max_alpha, float* max_weight, void* stream) {

@@ -67,4 +67,10 @@ hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const fl
                            float* loss, float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
                            hipStream_t s);
 
+int ssim_slots(int W, int H);
+size_t ssim_workspace_bytes(int V, int max_slots, int64_t P, bool with_grad);
+hipError_t launch_ssim(int V, int max_slots, int64_t P, const sr_camera* cams, const float* color,
+                       const float* target, const uint8_t* mask, float w_s, void* ws, float* out,
+                       float* dL_dcolor, hipStream_t s);
+
 }  // namespace sr

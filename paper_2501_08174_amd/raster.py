@@ -232,6 +232,22 @@ class Rasterizer:
              _ptr(dL_dnormal), _ptr(dL_ddist), _stream(stream))
         return self.reg_out
 
+    def ssim_loss(self, mask: torch.Tensor, target: torch.Tensor, w_s: float = 0.2,
+                  dL_dcolor: Optional[torch.Tensor] = None, stream=None):
+        """Masked D-SSIM / SSIM / PSNR of the current colour outputs
+        (sr_ssim_loss): returns [SSIM per view, PSNR per view, weighted
+        D-SSIM]; the gradient is added to dL_dcolor when given."""
+        with_grad = dL_dcolor is not None
+        need = _lib.workspace_bytes_ssim(self.views.V, self.views.host, with_grad)
+        if getattr(self, "ssim_ws", None) is None or self.ssim_ws.numel() < need:
+            self.ssim_ws = torch.zeros(max(need, 1), dtype=torch.uint8, device=self.device)
+        if getattr(self, "ssim_out", None) is None:
+            self.ssim_out = torch.zeros(2 * self.views.V + 1, dtype=torch.float32, device=self.device)
+        call("sr_ssim_loss", self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.color),
+             _ptr(target), _ptr(mask), float(w_s), _ptr(self.ssim_ws), self.ssim_ws.numel(), _ptr(self.ssim_out),
+             _ptr(dL_dcolor), _stream(stream))
+        return self.ssim_out
+
     def train_step_raster(self, mask: torch.Tensor, target: torch.Tensor, gamma: float = 0.5, w_c: float = 1.0,
                           stats=None, accumulate: bool = False, stream=None):
         """Fused forward + loss gradients + backward compositing (one launch);
@@ -400,3 +416,23 @@ class RegularizerLoss(torch.autograd.Function):
     def backward(ctx, g_total, g_loss):
         dA, dD, dN, dS = ctx.saved_tensors
         return dA * g_total, dD * g_total, dN * g_total, dS * g_total, None, None, None, None
+
+
+class SsimLoss(torch.autograd.Function):
+    """Masked D-SSIM of all views (sr_ssim_loss): returns
+    (1/V) sum_v w_s (1 - SSIM_v) and [SSIM_0..V-1, PSNR_0..V-1]."""
+
+    @staticmethod
+    def forward(ctx, color, target, mask, views: ViewBatch, w_s: float, ws):
+        V = views.V
+        out = torch.zeros(2 * V + 1, dtype=torch.float32, device=color.device)
+        dC = torch.zeros_like(color)
+        call("sr_ssim_loss", V, views.host_ptr, _ptr(views.dev), _ptr(color.contiguous()), _ptr(target),
+             _ptr(mask), float(w_s), _ptr(ws), ws.numel(), _ptr(out), _ptr(dC), _stream())
+        ctx.save_for_backward(dC)
+        return out[2 * V], out[: 2 * V]
+
+    @staticmethod
+    def backward(ctx, g_total, g_out):
+        (dC,) = ctx.saved_tensors
+        return dC * g_total, None, None, None, None, None

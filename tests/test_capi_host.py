@@ -109,3 +109,25 @@ def test_regularizer_loss_arguments(lib):
     cams[1].pix_offset = 20
     cams[0].fx = 0.0
     assert l.sr_regularizer_loss(*args(n.value)) == lib.SR_ERR_ARG
+
+
+def test_ssim_arguments(lib):
+    """sr_ssim_loss / sr_ssim_workspace_size host checks (nothing launched)."""
+    l = lib.lib()
+    n = ctypes.c_size_t()
+    assert l.sr_ssim_workspace_size(0, None, 1, ctypes.byref(n)) == lib.SR_OK and n.value == 0
+    cams = (lib.SrCamera * 2)()
+    for c, (w, h) in zip(cams, [(40, 9), (3, 2)]):
+        c.width, c.height, c.fx, c.fy = w, h, 10.0, 10.0
+    cams[1].pix_offset = 360
+    cp = ctypes.cast(cams, ctypes.c_void_p)
+    assert l.sr_ssim_workspace_size(2, cp, 0, ctypes.byref(n)) == lib.SR_OK
+    m = n.value
+    assert l.sr_ssim_workspace_size(2, cp, 1, ctypes.byref(n)) == lib.SR_OK
+    assert n.value >= m + 9 * 366 * 4
+    p = ctypes.c_void_p(256)
+    assert l.sr_ssim_loss(2, cp, p, p, p, p, 0.2, p, n.value - 1, p, p, None) == lib.SR_ERR_ARG
+    assert l.sr_ssim_loss(2, cp, p, None, p, p, 0.2, p, n.value, p, p, None) == lib.SR_ERR_ARG
+    cams[1].pix_offset = 361
+    assert l.sr_ssim_loss(2, cp, p, p, p, p, 0.2, p, n.value, p, p, None) == lib.SR_ERR_ARG
+    assert l.sr_ssim_loss(-1, None, None, None, None, None, 0.2, None, 0, None, None, None) == lib.SR_ERR_ARG

@@ -1,0 +1,135 @@
+"""Parity of the masked SSIM / D-SSIM / PSNR (sr_ssim_loss) with the FP64
+oracle: ragged and tiny views with partial masks, the metrics-only mode, the
+gradient accumulation into an existing colour gradient, and whole config-3
+views with sampled gradient crops."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.ssim import ssim_map64
+from paper_2501_08174_amd import _lib, scenes
+from paper_2501_08174_amd.raster import SsimLoss, ViewBatch, _ptr, _stream
+from tests.gpu_helpers import gpu_run, per_view
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _flat(arrs, dtype=torch.float32):
+    return torch.tensor(np.concatenate([a.reshape(-1) for a in arrs]), dtype=dtype, device="cuda")
+
+
+def _images(cams, seed):
+    rng = np.random.default_rng(seed)
+    C, I, M = [], [], []
+    for c in cams:
+        H, W = c.height, c.width
+        jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        base = 0.5 + 0.3 * np.sin(0.2 * ii)[None] * np.cos(0.15 * jj)[None]
+        C.append((base + 0.1 * rng.standard_normal((3, H, W))).astype(np.float32))
+        I.append((base + 0.1 * rng.standard_normal((3, H, W))).astype(np.float32))
+        M.append((rng.uniform(size=(H, W)) > 0.25).astype(np.uint8))
+    return C, I, M
+
+
+def _run(cams, C, I, M, w_s, grad=True, pre=None):
+    views = ViewBatch(cams)
+    ws = torch.zeros(max(_lib.workspace_bytes_ssim(views.V, views.host, grad), 1), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.zeros(2 * views.V + 1, device="cuda")
+    dC = None
+    if grad:
+        dC = torch.zeros(3 * views.P, device="cuda") if pre is None else pre.clone()
+    tc, ti, tm = _flat(C), _flat(I), _flat(M, torch.uint8)     # kept alive across the call
+    _lib.call("sr_ssim_loss", views.V, views.host_ptr, _ptr(views.dev), _ptr(tc), _ptr(ti), _ptr(tm), w_s,
+              _ptr(ws), ws.numel(), _ptr(out), _ptr(dC), _stream())
+    torch.cuda.synchronize()
+    return views, out.cpu().numpy(), (None if dC is None else dC.cpu().numpy())
+
+
+def test_ssim_matches_oracle_ragged_views():
+    cams = [scenes.make_camera(np.eye(3), np.zeros(3), w, h) for w, h in [(45, 23), (32, 8), (7, 13), (3, 2)]]
+    C, I, M = _images(cams, 3)
+    w_s = 0.2
+    pre = torch.rand(3 * sum(c.width * c.height for c in cams), device="cuda")
+    views, out, dC = _run(cams, C, I, M, w_s, pre=pre)
+    dC = dC - pre.cpu().numpy()
+    ref = oracle.dssim_loss64(C, I, M, w_s)
+    V = len(cams)
+    for v in range(V):
+        assert abs(out[v] - ref["ssim"][v]) <= 2e-5, (v, out[v], ref["ssim"][v])
+        assert abs(out[V + v] - oracle.masked_psnr64(C[v], I[v], M[v])) <= 1e-3
+    assert abs(out[2 * V] - ref["total"]) <= 2e-5 * max(abs(ref["total"]), 1e-3)
+    for v, c in enumerate(cams):
+        o, n = views.pix_offsets[v], c.width * c.height
+        got = dC[3 * o: 3 * (o + n)]
+        exp = ref["grads"][v].reshape(-1)
+        err = np.abs(got - exp).max() / np.abs(exp).max()
+        print(f"view {v} ({c.width}x{c.height}): gradient inf-norm relative error {err:.2e}")
+        assert err <= 1e-3
+        assert np.all(got.reshape(3, -1)[:, M[v].reshape(-1) == 0] == 0)
+
+
+def test_metrics_only_and_identical_images():
+    cams = [scenes.make_camera(np.eye(3), np.zeros(3), 29, 17)]
+    C, I, M = _images(cams, 4)
+    _, out, dC = _run(cams, C, C, M, 0.2, grad=False)
+    assert dC is None
+    assert abs(out[0] - 1.0) <= 1e-5 and np.isinf(out[1]) and abs(out[2]) <= 2e-6
+    _, out2, _ = _run(cams, C, I, M, 0.2, grad=False)
+    assert abs(out2[0] - float(oracle.masked_ssim64(C[0], I[0], M[0]))) <= 2e-5
+
+
+def test_ssim_config3_full_size():
+    """Whole config-3 views: SSIM and PSNR per view against the oracle;
+    gradients on sampled crops (the oracle on the crop grown by the ten-pixel
+    reach of forward and backward filters, rescaled to whole-view means)."""
+    sc = scenes.make_config3()
+    run = gpu_run(sc)
+    rast, views = run["rast"], run["views"]
+    mask = _flat([m for m in sc.masks], torch.uint8)
+    target = _flat(sc.targets)
+    dC = torch.zeros(3 * views.P, device="cuda")
+    w_s = 0.2
+    out = rast.ssim_loss(mask, target, w_s, dL_dcolor=dC).cpu().numpy()
+    torch.cuda.synchronize()
+    dC = dC.cpu().numpy()
+    V = views.V
+    print("config3 ssim: GPU pass done", flush=True)
+    for v in range(V):
+        pv = per_view(rast, v)
+        s = float(oracle.masked_ssim64(pv["color"], sc.targets[v], sc.masks[v]))
+        assert abs(out[v] - s) <= 1e-4, (v, out[v], s)
+        assert abs(out[V + v] - oracle.masked_psnr64(pv["color"], sc.targets[v], sc.masks[v])) <= 2e-3
+    print("config3 ssim: 16 per-view SSIM and PSNR match", flush=True)
+    for v in (2, 9):
+        cam = sc.cams[v]
+        W, H = cam.width, cam.height
+        pv = per_view(rast, v)
+        o, HW = views.pix_offsets[v], W * H
+        jj, ii = np.nonzero(sc.masks[v])
+        cx, cy = int(ii.mean()), int(jj.mean())
+        crops = [(0, 0),                                                     # image corner (background)
+                 (min(max(cx - 24, 0), W - 48), min(max(cy - 24, 0), H - 48)),  # inside the object mask
+                 (min(max(int(ii.min()) - 24, 0), W - 48), min(max(cy - 24, 0), H - 48))]  # mask boundary
+        for (x0, y0) in crops:
+            xe0, ye0, xe1, ye1 = max(x0 - 10, 0), max(y0 - 10, 0), min(x0 + 48 + 10, W), min(y0 + 48 + 10, H)
+            sub = [pv["color"][:, ye0:ye1, xe0:xe1]]
+            r = oracle.dssim_loss64(sub, [sc.targets[v][:, ye0:ye1, xe0:xe1]], [sc.masks[v][ye0:ye1, xe0:xe1]],
+                                    w_s)["grads"][0]
+            k = (xe1 - xe0) * (ye1 - ye0) / (HW * V)
+            ref = r[:, y0 - ye0:y0 - ye0 + 48, x0 - xe0:x0 - xe0 + 48] * k
+            gy = np.arange(y0, y0 + 48)[:, None] * W + np.arange(x0, x0 + 48)[None, :]
+            got = np.stack([dC[3 * o + c * HW + gy] for c in range(3)])
+            err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
+            print(f"config3 view {v} crop ({x0},{y0}): gradient inf-norm relative error {err:.2e}, "
+                  f"max |grad| {np.abs(ref).max():.2e}", flush=True)
+            assert err <= 1e-3
+            if (x0, y0) != (0, 0):
+                assert np.abs(ref).max() > 0
