@@ -18,6 +18,7 @@ Modules
   ssim      masked SSIM / D-SSIM (the rest of Eq. 2's photometric loss) and
             masked PSNR
   prune     occlusion-aware pruning statistics (Section 4.3)
+  densify   the screen-space gradient statistic of the density control
   fd        central finite differences with decision-set filtering
 """
 from .geometry import (RasterParams, view_geometry64, bin64, tile_layout, rotation_columns64)
@@ -25,6 +26,7 @@ from .sh import real_sh_basis, sh_basis_scipy, sh_coeff_count
 from .render import render_pixels, render_view, Params64
 from .loss import background_loss64, masked_l1_64
 from .prune import prune_stats64
+from .densify import screen_grad_stats64
 from .regularizers import regularizer_loss64, depth_normal64, depth_points64, surface_depth64
 from .ssim import dssim_loss64, masked_ssim64, masked_psnr64, ssim_map64, gaussian_1d64, window_2d64
 
@@ -32,7 +34,7 @@ __all__ = [
     "RasterParams", "view_geometry64", "bin64", "tile_layout", "rotation_columns64",
     "real_sh_basis", "sh_basis_scipy", "sh_coeff_count",
     "render_pixels", "render_view", "Params64",
-    "background_loss64", "masked_l1_64", "prune_stats64",
+    "background_loss64", "masked_l1_64", "prune_stats64", "screen_grad_stats64",
     "regularizer_loss64", "depth_normal64", "depth_points64", "surface_depth64",
     "dssim_loss64", "masked_ssim64", "masked_psnr64", "ssim_map64", "gaussian_1d64", "window_2d64",
 ]

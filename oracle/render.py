@@ -166,6 +166,11 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
     fx, fy, cx, cy = (float(np.float32(v)) for v in (cam.fx, cam.fy, cam.cx, cam.cy))
     x = torch.as_tensor(pix[:, 0] + 0.5, dtype=DT)[:, None].expand(Pn, L)
     y = torch.as_tensor(pix[:, 1] + 0.5, dtype=DT)[:, None].expand(Pn, L)
+    if "shift" in Q:
+        # the surfel translated by delta in screen space is seen at x - delta
+        sh = g(Q["shift"])
+        x = x - sh[..., 0]
+        y = y - sh[..., 1]
     d = torch.stack([(x - cx) / fx, (y - cy) / fy, torch.ones_like(x)], dim=-1)
     # Cramer's rule for [a_u a_v -d] (u, v, tau)^T = -p
     c1, c2, c3, b = au, av, -d, -p
@@ -245,7 +250,7 @@ OUT_KEYS = ("color", "alpha", "depth", "normal", "dist", "T_final")
 
 def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = RasterParams(),
                   loss_fn: Optional[Callable] = None, max_entries: int = 1_500_000,
-                  keep_decisions: bool = False):
+                  keep_decisions: bool = False, screen_shift: Optional[torch.Tensor] = None):
     """Render the pixels ``pix`` (P,2) int (column i, row j) of one view.
 
     Returns numpy arrays: color (P,3), alpha, depth, normal (P,3), dist,
@@ -256,6 +261,10 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
     reached at a flagged pixel.  With ``loss_fn(out_chunk, rows)`` the
     returned scalar of every chunk is back-propagated into the leaves of
     ``P`` (the chunked sum is the full loss), so no graph outlives a chunk.
+    ``screen_shift`` (N,2): every surfel translated in screen space by that
+    many pixels (evaluated at x - shift); with requires_grad and zeros, the
+    chunks' backward leaves dL/d(shift), the screen-space gradient of the
+    density-control statistic.
     """
     pix = np.asarray(pix, np.int64).reshape(-1, 2)
     Pn = pix.shape[0]
@@ -277,6 +286,8 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
             valid = np.zeros_like(valid)
             colidx = np.zeros_like(colidx)
         Q = surfel_view_quantities(P, ids, cam, geom["flip"])
+        if screen_shift is not None:
+            Q["shift"] = screen_shift[torch.as_tensor(ids, dtype=torch.long)]
         out = _composite(Q, cam, sub, colidx, valid, ghost, rp)
         if loss_fn is not None:
             lval = loss_fn(out, np.arange(start, stop))
