@@ -181,7 +181,15 @@ sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const s
  * sr_backward_project: chains grad_rec to the parameter gradients (+=),
  * summed over the views, and zeroes every grad_rec record it consumed, so
  * the buffer is ready for the next step.  tiles_touched (from
- * sr_preprocess) lets it skip culled records; NULL scans every record. */
+ * sr_preprocess) lets it skip culled records; NULL scans every record.
+ * Density-control statistic (the 2DGS adaptive density control kept by
+ * Section 5.1), optional: for every record not culled, densify_count[g] += 1
+ * and densify_grad[g] += |dL/d delta|_2, the gradient of the loss with
+ * respect to a translation delta of the splat in screen space (pixels; the
+ * splat evaluated at x - delta, surface and low-pass alike), computed from
+ * the record's gradients as (dL/d low-pass centre) - (A, B) . dL/dC' for
+ * w = A dx + B dy + C'.  densify_grad [N] float, densify_count [N] uint32,
+ * both accumulated (+=); either may be NULL; they need tiles_touched. */
 sr_status sr_backward_raster(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                              const sr_camera *cams_dev, const float *geom, const float *app,
                              const uint32_t *vals, const uint32_t *ranges, const float *alpha,
@@ -193,7 +201,8 @@ sr_status sr_backward_project(const sr_config *cfg, int32_t N, int32_t V, const 
                               const sr_camera *cams_dev, const float *means, const float *scales,
                               const float *quats, const float *sh, const float *geom, const float *app,
                               const uint32_t *tiles_touched, float *grad_rec, float *g_means,
-                              float *g_scales, float *g_quats, float *g_opac, float *g_sh, void *stream);
+                              float *g_scales, float *g_quats, float *g_opac, float *g_sh,
+                              float *densify_grad, uint32_t *densify_count, void *stream);
 
 /* Bytes of workspace sr_background_loss needs for these views. */
 sr_status sr_loss_workspace_size(int32_t V, const sr_camera *cams_host, size_t *bytes_host);

@@ -254,13 +254,15 @@ sr_status sr_backward_project(const sr_config* cfg, int32_t N, int32_t V, const 
                               const sr_camera* cams_dev, const float* means, const float* scales, const float* quats,
                               const float* sh, const float* geom, const float* app, const uint32_t* tiles_touched,
                               float* grad_rec, float* g_means, float* g_scales, float* g_quats, float* g_opac,
-                              float* g_sh, void* stream) {
+                              float* g_sh, float* densify_grad, uint32_t* densify_count, void* stream) {
     SR_TRY(check_backward_project(cfg, N, V, cams_host, cams_dev, means, scales, quats, sh, geom, app, grad_rec,
                                   g_means, g_scales, g_quats, g_opac, g_sh));
+    if ((densify_grad || densify_count) && !tiles_touched)
+        return fail(SR_ERR_ARG, "the density statistics need tiles_touched (the views each surfel is seen in)");
     if (N == 0 || V == 0) return SR_OK;
     return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app,
                                                 tiles_touched, grad_rec, g_means, g_scales, g_quats, g_opac, g_sh,
-                                                (hipStream_t)stream),
+                                                densify_grad, densify_count, (hipStream_t)stream),
                       "sr_backward_project");
 }
 
@@ -286,7 +288,8 @@ sr_status sr_render_backward(const sr_config* cfg, int32_t N, int32_t V, const s
                                             dL_ddist, grad_rec, s),
                       "render backward"));
     return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app, nullptr,
-                                                grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, s),
+                                                grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, nullptr,
+                                                nullptr, s),
                       "projection backward");
 }
 

@@ -19,7 +19,8 @@ hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means
                                  const float* quats, const float* sh, int V, const sr_camera* cams_dev,
                                  const float* geom, const float* app, const uint32_t* tiles_touched,
                                  float* grad_rec, float* g_means, float* g_scales, float* g_quats,
-                                 float* g_opac, float* g_sh, hipStream_t stream);
+                                 float* g_opac, float* g_sh, float* dens_grad, uint32_t* dens_count,
+                                 hipStream_t stream);
 
 size_t bin_workspace_bytes(uint64_t VN, uint64_t cap);
 

@@ -283,9 +283,14 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
                  const float4* __restrict__ geom, const float4* __restrict__ app,
                  const uint32_t* __restrict__ tiles_touched, float* __restrict__ grad_rec,
                  float* __restrict__ g_means, float* __restrict__ g_scales, float* __restrict__ g_quats,
-                 float* __restrict__ g_opac, float* __restrict__ g_sh) {
+                 float* __restrict__ g_opac, float* __restrict__ g_sh, float* __restrict__ dens_grad,
+                 uint32_t* __restrict__ dens_count) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
+    // density-control statistic: |dL/d delta| of a screen-space translation
+    // delta of the record, summed over views, and the views not culled
+    float dens_sum = 0.0f;
+    uint32_t dens_n = 0u;
     const float mu[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
     const float su = scales[2 * g], sv = scales[2 * g + 1];
     const float q0[4] = {quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]};
@@ -306,11 +311,20 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
     for (int v = 0; v < V; ++v) {
         const size_t r = (size_t)v * N + g;
         if (tiles_touched && tiles_touched[r] == 0u) continue;
+        dens_n += 1u;
         float* gr = grad_rec + r * SR_GRAD_STRIDE;
         float G[kNumGrad];
         bool any = false;
         for (int i = 0; i < kNumGrad; ++i) { G[i] = gr[i]; any |= (G[i] != 0.0f); }
         if (!any) continue;
+        if (dens_grad) {
+            // w = A dx + B dy + C' with dx = x - c: translating by delta shifts
+            // dx by -delta, so dL/d delta = (low-pass terms) - (A, B) . dL/dC'
+            const float4 h0 = geom[4 * r], h1 = geom[4 * r + 1];
+            const float sx = G[9] - (h0.x * G[6] + h0.y * G[7] + h0.z * G[8]);
+            const float sy = G[10] - (h0.w * G[6] + h1.x * G[7] + h1.y * G[8]);
+            dens_sum += sqrtf(sx * sx + sy * sy);
+        }
         // consume: leave the accumulator zero for the next backward
         for (int i = 0; i < kNumGrad; ++i) gr[i] = 0.0f;
         const sr_camera& cam = cams[v];
@@ -437,6 +451,8 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
     float* gs = g_sh + (size_t)g * sh_stride * 3;
 #pragma unroll
     for (int i = 0; i < 3 * K; ++i) gs[i] += dsh[i];
+    if (dens_grad) dens_grad[g] += dens_sum;
+    if (dens_count) dens_count[g] += dens_n;
 }
 
 }  // namespace
@@ -471,13 +487,14 @@ hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means
                                  const float* quats, const float* sh, int V, const sr_camera* cams_dev,
                                  const float* geom, const float* app, const uint32_t* tiles_touched,
                                  float* grad_rec, float* g_means, float* g_scales, float* g_quats,
-                                 float* g_opac, float* g_sh, hipStream_t stream) {
+                                 float* g_opac, float* g_sh, float* dens_grad, uint32_t* dens_count,
+                                 hipStream_t stream) {
     if (N == 0) return hipSuccess;
     dim3 grid((N + 255) / 256), block(256);
 #define SR_PREB(D)                                                                                          \
     hipLaunchKernelGGL(k_preprocess_bwd<D>, grid, block, 0, stream, N, means, scales, quats, sh,            \
                        cfg.sh_stride, V, cams_dev, (const float4*)geom, (const float4*)app, tiles_touched, \
-                       grad_rec, g_means, g_scales, g_quats, g_opac, g_sh)
+                       grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, dens_grad, dens_count)
     switch (cfg.sh_degree) {
         case 0: SR_PREB(0); break;
         case 1: SR_PREB(1); break;

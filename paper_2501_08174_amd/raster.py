@@ -190,11 +190,15 @@ class Rasterizer:
              _ptr(self.alpha), _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib),
              _ptr(dC), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._grad_rec()), _stream(stream))
 
-    def backward_project(self, p: Params, grads: Params, stream=None):
+    def backward_project(self, p: Params, grads: Params, stream=None, densify=None):
+        """Projection backward; ``densify`` = (grad_sum float32 [N], count
+        int32 [N]) accumulates the density-control statistic."""
+        dg, dc = (None, None) if densify is None else densify
         call("sr_backward_project", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.sh), _ptr(self.geom),
              _ptr(self.app), _ptr(self.tiles_touched), _ptr(self._grad_rec()), _ptr(grads.means),
-             _ptr(grads.scales), _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _stream(stream))
+             _ptr(grads.scales), _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _ptr(dg), _ptr(dc),
+             _stream(stream))
 
     def backward(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None):
         """Both halves of the backward; the parameter gradients are added to."""
