@@ -302,6 +302,48 @@ def main():
                                            "frac": ssim_bytes / (ssim_ms * 1e-3) / HBM_PEAK,
                                            "bytes_per_call": ssim_bytes}}
 
+    if not args.no_eq3:
+        # density control and pruning of a training step: the screen-gradient
+        # statistic fused into the projection backward (its cost), and the
+        # compaction of the parameters by the occlusion-pruning mask
+        from paper_2501_08174_amd.raster import compact_surfels, prune_mask
+        dsum = torch.zeros(N, device="cuda")
+        dcnt = torch.zeros(N, dtype=torch.int32, device="cuda")
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        t_plain, t_dens = [], []
+        for k in range(args.steps):
+            pipe.rast.preprocess(pipe.p)
+            pipe.rast.bin()
+            pipe.rast.train_step_raster(pipe.mask, pipe.target, 0.5, 1.0)
+            e[0].record()
+            pipe.rast.backward_project(pipe.p, pipe.g)
+            e[1].record()
+            pipe.rast.train_step_raster(pipe.mask, pipe.target, 0.5, 1.0)
+            e[2].record()
+            pipe.rast.backward_project(pipe.p, pipe.g, densify=(dsum, dcnt))
+            e[3].record()
+            torch.cuda.synchronize()
+            t_plain.append(e[0].elapsed_time(e[1]))
+            t_dens.append(e[2].elapsed_time(e[3]))
+        pm = prune_mask(stats[1], 1.0 / 255.0)
+        arrays = [params.means, params.scales, params.quats, params.opac, params.sh]
+        compact_surfels(pm, arrays)
+        torch.cuda.synchronize()
+        e[4].record()
+        out = compact_surfels(pm, arrays)
+        e[5].record()
+        torch.cuda.synchronize()
+        kept = int(out[0].shape[0])
+        row = sum(int(np.prod(a.shape[1:])) if a.dim() > 1 else 1 for a in arrays) * 4
+        c_ms = e[4].elapsed_time(e[5])
+        c_bytes = 2 * N + kept * row * 2                   # mask read by both passes; kept rows read and written
+        result["density_and_pruning"] = {
+            "projection_backward_ms": float(np.median(t_plain)),
+            "projection_backward_with_statistic_ms": float(np.median(t_dens)),
+            "pruned": N - kept, "kept": kept,
+            "compaction_ms_incl_host_sync": c_ms,
+            "compaction_GBps": c_bytes / (c_ms * 1e-3) / 1e9}
+
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

@@ -307,6 +307,22 @@ sr_status sr_render_count(const sr_config *cfg, int32_t N, int32_t V, const sr_c
                           const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
                           const uint32_t *ranges, uint64_t *counts, void *stream);
 
+/* Stream compaction of per-surfel arrays after pruning (Section 4.3): keep
+ * surfel g when prune_mask[g] == 0 and (opac == NULL or opac[g] >=
+ * min_opacity); for every array a, dst[a] row j = src[a] row i for the j-th
+ * kept surfel i in increasing order (stable).  n_arrays <= SR_COMPACT_MAX_ARRAYS
+ * float32 arrays of widths_host[a] floats per surfel (e.g. 3 means, 2
+ * scales, 4 quats, 1 opacity, K*3 SH, and the optimiser moments alike);
+ * src_host / dst_host: host arrays of device pointers; dst must not alias
+ * src.  n_kept: device uint32, written.  workspace: sr_compact_workspace_size
+ * bytes. */
+#define SR_COMPACT_MAX_ARRAYS 8
+sr_status sr_compact_workspace_size(int32_t N, size_t *bytes_host);
+sr_status sr_compact_surfels(int32_t N, const uint8_t *prune_mask, const float *opac, float min_opacity,
+                             int32_t n_arrays, const float *const *src_host, float *const *dst_host,
+                             const int32_t *widths_host, void *workspace, size_t ws_bytes,
+                             uint32_t *n_kept, void *stream);
+
 /* prune_mask[g] = max_alpha[g] < tau (1 = prune).  With tau = alpha_min
  * this is "never blended in any view" (Section 4.3). */
 sr_status sr_prune_mask(int32_t N, const float *max_alpha, float tau, uint8_t *prune_mask, void *stream);

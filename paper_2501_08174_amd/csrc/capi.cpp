@@ -404,6 +404,35 @@ sr_status sr_ssim_loss(int32_t V, const sr_camera* cams_host, const sr_camera* c
                       "sr_ssim_loss");
 }
 
+sr_status sr_compact_workspace_size(int32_t N, size_t* bytes_host) {
+    if (N < 0) return fail(SR_ERR_ARG, "N < 0");
+    SR_NEED(bytes_host);
+    *bytes_host = sr::compact_workspace_bytes(N);
+    return SR_OK;
+}
+
+sr_status sr_compact_surfels(int32_t N, const uint8_t* prune_mask, const float* opac, float min_opacity,
+                             int32_t n_arrays, const float* const* src_host, float* const* dst_host,
+                             const int32_t* widths_host, void* workspace, size_t ws_bytes, uint32_t* n_kept,
+                             void* stream) {
+    if (N < 0) return fail(SR_ERR_ARG, "N < 0");
+    if (n_arrays < 0 || n_arrays > SR_COMPACT_MAX_ARRAYS)
+        return fail(SR_ERR_ARG, "n_arrays must be in [0, %d]", SR_COMPACT_MAX_ARRAYS);
+    SR_NEED(n_kept); SR_NEED(workspace);
+    if (N > 0) SR_NEED(prune_mask);
+    if (n_arrays > 0) { SR_NEED(src_host); SR_NEED(dst_host); SR_NEED(widths_host); }
+    for (int a = 0; a < n_arrays; ++a) {
+        if (widths_host[a] < 1) return fail(SR_ERR_ARG, "array %d: width must be positive", a);
+        if (N > 0 && (!src_host[a] || !dst_host[a])) return fail(SR_ERR_ARG, "array %d: missing pointer", a);
+        if (N > 0 && (const void*)src_host[a] == (const void*)dst_host[a])
+            return fail(SR_ERR_ARG, "array %d: dst aliases src", a);
+    }
+    if (ws_bytes < sr::compact_workspace_bytes(N)) return fail(SR_ERR_ARG, "compaction workspace too small");
+    return hip_status(sr::launch_compact(N, prune_mask, opac, min_opacity, n_arrays, src_host, dst_host,
+                                         (const int*)widths_host, workspace, n_kept, (hipStream_t)stream),
+                      "sr_compact_surfels");
+}
+
 sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
                            const sr_camera* cams_dev, const float* geom, const uint32_t* vals, const uint32_t* ranges,
                            uint32_t* hits, float* max_alpha, float* max_weight, void* stream) {

@@ -68,6 +68,10 @@ hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const fl
                            float* loss, float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
                            hipStream_t s);
 
+size_t compact_workspace_bytes(int N);
+hipError_t launch_compact(int N, const uint8_t* prune, const float* opac, float min_opac, int n_arrays,
+                          const float* const* src, float* const* dst, const int* widths, void* ws,
+                          uint32_t* n_kept, hipStream_t s);
 int ssim_slots(int W, int H);
 size_t ssim_workspace_bytes(int V, int max_slots, int64_t P, bool with_grad);
 hipError_t launch_ssim(int V, int max_slots, int64_t P, const sr_camera* cams, const float* color,

@@ -440,3 +440,31 @@ class SsimLoss(torch.autograd.Function):
     def backward(ctx, g_total, g_out):
         (dC,) = ctx.saved_tensors
         return dC * g_total, None, None, None, None, None
+
+
+def compact_surfels(prune: torch.Tensor, arrays: Sequence[torch.Tensor], opac: Optional[torch.Tensor] = None,
+                    min_opacity: float = 0.0, stream=None):
+    """Drop the pruned surfels (prune uint8 [N], 1 = drop; and, with opac,
+    those below min_opacity) from every per-surfel array (float32, first
+    dimension N), keeping the order (sr_compact_surfels).  Returns the
+    compacted arrays (new tensors) - syncs to read the kept count."""
+    N = int(prune.shape[0])
+    if len(arrays) > _lib.SR_COMPACT_MAX_ARRAYS:
+        raise ValueError(f"at most {_lib.SR_COMPACT_MAX_ARRAYS} arrays per call")
+    dev = prune.device
+    srcs = [a.contiguous().reshape(N, int(np.prod(a.shape[1:])) if a.dim() > 1 else 1) for a in arrays]
+    dsts = [torch.empty_like(a) for a in srcs]
+    widths = (ctypes.c_int32 * max(len(srcs), 1))(*[int(a.shape[1]) for a in srcs])
+    sp = (ctypes.c_void_p * max(len(srcs), 1))(*[a.data_ptr() for a in srcs])
+    dp = (ctypes.c_void_p * max(len(srcs), 1))(*[a.data_ptr() for a in dsts])
+    n = ctypes.c_size_t()
+    _lib.check(_lib.lib().sr_compact_workspace_size(N, ctypes.byref(n)))
+    ws = torch.zeros(max(n.value, 4), dtype=torch.uint8, device=dev)
+    kept = torch.zeros(1, dtype=torch.int32, device=dev)
+    pr = prune.contiguous()                      # held across the call
+    op = None if opac is None else opac.contiguous()
+    call("sr_compact_surfels", N, _ptr(pr), _ptr(op), float(min_opacity), len(srcs),
+         ctypes.cast(sp, ctypes.c_void_p), ctypes.cast(dp, ctypes.c_void_p), ctypes.cast(widths, ctypes.c_void_p),
+         _ptr(ws), ws.numel(), _ptr(kept), _stream(stream))
+    k = int(kept.item())
+    return [d[:k].reshape((k,) + tuple(a.shape[1:])) for d, a in zip(dsts, arrays)]

@@ -131,3 +131,28 @@ def test_ssim_arguments(lib):
     cams[1].pix_offset = 361
     assert l.sr_ssim_loss(2, cp, p, p, p, p, 0.2, p, n.value, p, p, None) == lib.SR_ERR_ARG
     assert l.sr_ssim_loss(-1, None, None, None, None, None, 0.2, None, 0, None, None, None) == lib.SR_ERR_ARG
+
+
+def test_compact_arguments(lib):
+    """sr_compact_surfels host checks (nothing launched)."""
+    l = lib.lib()
+    n = ctypes.c_size_t()
+    assert l.sr_compact_workspace_size(100000, ctypes.byref(n)) == lib.SR_OK and n.value >= 4 * 13
+    assert l.sr_compact_workspace_size(-1, ctypes.byref(n)) == lib.SR_ERR_ARG
+    p = ctypes.c_void_p(256)
+    src = (ctypes.c_void_p * 2)(256, 512)
+    dst = (ctypes.c_void_p * 2)(1024, 512)
+    w = (ctypes.c_int32 * 2)(3, 2)
+    cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
+    # dst aliases src for the second array
+    assert l.sr_compact_surfels(10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
+        lib.SR_ERR_ARG
+    assert l.sr_compact_surfels(10, p, None, 0.0, 9, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
+        lib.SR_ERR_ARG
+    w[0] = 0
+    dst[1] = 2048
+    assert l.sr_compact_surfels(10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
+        lib.SR_ERR_ARG
+    w[0] = 3
+    assert l.sr_compact_surfels(10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, 0, p, None) == \
+        lib.SR_ERR_ARG
