@@ -19,6 +19,8 @@ Modules
             masked PSNR
   prune     occlusion-aware pruning statistics (Section 4.3)
   densify   the screen-space gradient statistic of the density control
+  gauss3d   the pruning statistics for 3D Gaussians (Appendix B): EWA
+            projection, conservative rectangles, compositing decisions
   fd        central finite differences with decision-set filtering
 """
 from .geometry import (RasterParams, view_geometry64, bin64, tile_layout, rotation_columns64)
@@ -27,6 +29,7 @@ from .render import render_pixels, render_view, Params64
 from .loss import background_loss64, masked_l1_64
 from .prune import prune_stats64
 from .densify import screen_grad_stats64
+from .gauss3d import view_geometry3d64, prune_pixels3d
 from .regularizers import regularizer_loss64, depth_normal64, depth_points64, surface_depth64
 from .ssim import dssim_loss64, masked_ssim64, masked_psnr64, ssim_map64, gaussian_1d64, window_2d64
 
@@ -35,6 +38,7 @@ __all__ = [
     "real_sh_basis", "sh_basis_scipy", "sh_coeff_count",
     "render_pixels", "render_view", "Params64",
     "background_loss64", "masked_l1_64", "prune_stats64", "screen_grad_stats64",
+    "view_geometry3d64", "prune_pixels3d",
     "regularizer_loss64", "depth_normal64", "depth_points64", "surface_depth64",
     "dssim_loss64", "masked_ssim64", "masked_psnr64", "ssim_map64", "gaussian_1d64", "window_2d64",
 ]
