@@ -307,6 +307,31 @@ sr_status sr_render_count(const sr_config *cfg, int32_t N, int32_t V, const sr_c
                           const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
                           const uint32_t *ranges, uint64_t *counts, void *stream);
 
+/* The pruning pass for 3D Gaussians (Appendix B: Section 4.3's statistics
+ * for 3DGS).  sr_preprocess_3d: per (view, Gaussian) the EWA projection
+ * Sigma_2 = J R_v R S S^T R^T R_v^T J^T + 0.3 I (J the perspective Jacobian at
+ * the centre with x/z and y/z clamped to 1.3 tan(fov/2)), the opacity-aware
+ * conservative pixel rectangle of o exp(-q/2) >= alpha_min, q = d^T
+ * Sigma_2^-1 d (half extents sqrt(r2 Sigma_2,xx), sqrt(r2 Sigma_2,yy), r2 =
+ * 2 ln(o/alpha_min) rounded up to 2^-16), culls (near plane, opacity,
+ * degenerate, empty rectangle) and the depth key, in float64 with a fixed
+ * operation order; rect / tiles_touched / depth_key are laid out as for
+ * sr_preprocess and feed sr_bin_and_sort unchanged.  scales [N,3] (all
+ * three axes), quats [N,4], opac [N]; geom3 [V*N, 8] float32 (conic a, b, c,
+ * opacity, centre x, y, ln(o/alpha_min), 0).
+ * sr_prune_contrib_3d: the statistics of sr_prune_contrib (hits, max alpha,
+ * max weight; cleared first unless SR_FLAG_ACCUMULATE) with a = min(alpha_max,
+ * o exp(-q/2)), the same cutoff, clamp and termination, lists from
+ * sr_bin_and_sort. */
+sr_status sr_preprocess_3d(const sr_config *cfg, int32_t N, const float *means, const float *scales,
+                           const float *quats, const float *opac, int32_t V, const sr_camera *cams_host,
+                           const sr_camera *cams_dev, float *geom3, uint16_t *rect, uint32_t *tiles_touched,
+                           uint32_t *depth_key, uint8_t *in_frustum, void *stream);
+sr_status sr_prune_contrib_3d(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                              const sr_camera *cams_dev, const float *geom3, const uint32_t *vals,
+                              const uint32_t *ranges, uint32_t *hits, float *max_alpha, float *max_weight,
+                              void *stream);
+
 /* Stream compaction of per-surfel arrays after pruning (Section 4.3): keep
  * surfel g when prune_mask[g] == 0 and (opac == NULL or opac[g] >=
  * min_opacity); for every array a, dst[a] row j = src[a] row i for the j-th

@@ -130,11 +130,18 @@ def view_geometry3d64(means, scales, quats, opac, cam, rp: RasterParams = Raster
 def prune_pixels3d(geom, pix: np.ndarray, rp: RasterParams = RasterParams()):
     """Front-to-back compositing decisions of the pixels ``pix`` (P,2) (no
     shading).  Returns the blended pairs (pixel row, id, a, omega), a per
-    pixel tie flag and the ids reached at a flagged pixel."""
+    pixel tie flag and the ids of the tie entries (a cutoff, clamp or
+    termination decision within the tie windows)."""
     ok = ~geom["culled"]
     rect = geom["rect"]
     rows, gids, avals, wvals, tie_ids = [], [], [], [], []
     flagged = np.zeros(pix.shape[0], bool)
+    if pix.shape[0] == 0:
+        return {"pairs": (np.zeros((0, 2), np.int64), np.zeros(0), np.zeros(0)), "flagged": flagged,
+                "tie_ids": np.zeros(0, np.int64)}
+    # candidates: rectangles meeting the bounding box of the pixels
+    i0, i1, j0, j1 = pix[:, 0].min(), pix[:, 0].max(), pix[:, 1].min(), pix[:, 1].max()
+    ok = ok & (rect[:, 0] <= i1) & (rect[:, 1] >= i0) & (rect[:, 2] <= j1) & (rect[:, 3] >= j0)
     cand_all = np.nonzero(ok)[0]
     order = np.lexsort((cand_all, geom["depth_bits"][cand_all]))
     cand_all = cand_all[order]
@@ -151,24 +158,24 @@ def prune_pixels3d(geom, pix: np.ndarray, rp: RasterParams = RasterParams()):
         a_raw = geom["opac"][ids] * np.exp(-0.5 * q)
         a = np.minimum(rp.alpha_max, a_raw)
         T = 1.0
-        tie = False
+        ties = []                     # entries whose own decision sits on a threshold
         for n, gid in enumerate(ids):
             if abs(a_raw[n] - rp.alpha_min) <= TIE_CUTOFF_REL * rp.alpha_min:
-                tie = True
+                ties.append(gid)
             if a[n] < rp.alpha_min:
                 continue
             if abs(a_raw[n] - rp.alpha_max) <= TIE_CLAMP:
-                tie = True
+                ties.append(gid)
             Tn = T * (1.0 - a[n])
             if abs(Tn - rp.t_min) <= TIE_TERM_REL * rp.t_min:
-                tie = True
+                ties.append(gid)
             if Tn < rp.t_min:
                 break
             rows.append(k); gids.append(gid); avals.append(a[n]); wvals.append(a[n] * T)
             T = Tn
-        if tie:
+        if ties:
             flagged[k] = True
-            tie_ids.append(ids)
+            tie_ids.append(np.asarray(ties, np.int64))
     pairs = (np.stack([np.asarray(rows, np.int64), np.asarray(gids, np.int64)], axis=1) if rows
              else np.zeros((0, 2), np.int64), np.asarray(avals), np.asarray(wvals))
     return {"pairs": pairs, "flagged": flagged,

@@ -27,7 +27,7 @@ EXPORTED = (
     "sr_last_error", "sr_version", "sr_tile_supported", "sr_layout_views", "sr_preprocess",
     "sr_bin_workspace_size", "sr_bin_and_sort", "sr_render_forward", "sr_render_backward",
     "sr_backward_raster", "sr_backward_project", "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_ssim_workspace_size", "sr_ssim_loss",
-    "sr_compact_workspace_size", "sr_compact_surfels",
+    "sr_compact_workspace_size", "sr_compact_surfels", "sr_preprocess_3d", "sr_prune_contrib_3d",
     "sr_train_step_raster", "sr_prune_contrib",
     "sr_render_count", "sr_prune_mask",
 )
@@ -83,6 +83,8 @@ def _declare(lib):
         "sr_ssim_workspace_size": (c_int32, [c_int32, V, c_int32, POINTER(c_size_t)]),
         "sr_ssim_loss": (c_int32, [c_int32, V, V, V, V, V, c_float, V, c_size_t, V, V, V]),
         "sr_compact_workspace_size": (c_int32, [c_int32, POINTER(c_size_t)]),
+        "sr_preprocess_3d": (c_int32, [V, c_int32, V, V, V, V, c_int32, V, V, V, V, V, V, V, V]),
+        "sr_prune_contrib_3d": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
         "sr_compact_surfels": (c_int32, [c_int32, V, V, c_float, c_int32, V, V, V, V, c_size_t, V, V]),
         "sr_train_step_raster": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
                                  + [V] * 14),

@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsurfelrast.so")
-SOURCES = ["preprocess.hip", "binning.hip", "raster.hip", "loss.hip", "ssim.hip", "compact.hip", "capi.cpp"]
+SOURCES = ["preprocess.hip", "binning.hip", "raster.hip", "loss.hip", "ssim.hip", "compact.hip", "gauss3d.hip",
+           "capi.cpp"]
 ARCH = os.environ.get("SR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -404,6 +404,43 @@ sr_status sr_ssim_loss(int32_t V, const sr_camera* cams_host, const sr_camera* c
                       "sr_ssim_loss");
 }
 
+sr_status sr_preprocess_3d(const sr_config* cfg, int32_t N, const float* means, const float* scales,
+                           const float* quats, const float* opac, int32_t V, const sr_camera* cams_host,
+                           const sr_camera* cams_dev, float* geom3, uint16_t* rect, uint32_t* tiles_touched,
+                           uint32_t* depth_key, uint8_t* in_frustum, void* stream) {
+    SR_TRY(check_cfg(cfg));
+    SR_TRY(check_nv(N, V));
+    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, nullptr, nullptr));
+    if (N > 0) {
+        SR_NEED(means); SR_NEED(scales); SR_NEED(quats); SR_NEED(opac);
+        if (V > 0) { SR_NEED(geom3); SR_NEED(rect); SR_NEED(tiles_touched); SR_NEED(depth_key); }
+    }
+    return hip_status(sr::launch_preprocess3d(*cfg, N, means, scales, quats, opac, V, cams_dev, geom3, rect,
+                                              tiles_touched, depth_key, in_frustum, (hipStream_t)stream),
+                      "sr_preprocess_3d");
+}
+
+sr_status sr_prune_contrib_3d(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
+                              const sr_camera* cams_dev, const float* geom3, const uint32_t* vals,
+                              const uint32_t* ranges, uint32_t* hits, float* max_alpha, float* max_weight,
+                              void* stream) {
+    SR_TRY(check_cfg(cfg));
+    SR_TRY(check_nv(N, V));
+    int total_tiles = 0;
+    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr));
+    if (N > 0) { SR_NEED(hits); SR_NEED(max_alpha); SR_NEED(max_weight); }
+    if (total_tiles > 0) { SR_NEED(geom3); SR_NEED(vals); SR_NEED(ranges); }
+    hipStream_t s = (hipStream_t)stream;
+    if (!(cfg->flags & SR_FLAG_ACCUMULATE) && N > 0) {
+        SR_TRY(hip_status(sr::fill_f32((float*)hits, 0.f, (uint64_t)N, s), "clear hits"));
+        SR_TRY(hip_status(sr::fill_f32(max_alpha, 0.f, (uint64_t)N, s), "clear max_alpha"));
+        SR_TRY(hip_status(sr::fill_f32(max_weight, 0.f, (uint64_t)N, s), "clear max_weight"));
+    }
+    return hip_status(sr::launch_prune3d(*cfg, N, V, total_tiles, cams_dev, geom3, vals, ranges, hits, max_alpha,
+                                         max_weight, s),
+                      "sr_prune_contrib_3d");
+}
+
 sr_status sr_compact_workspace_size(int32_t N, size_t* bytes_host) {
     if (N < 0) return fail(SR_ERR_ARG, "N < 0");
     SR_NEED(bytes_host);

@@ -68,6 +68,13 @@ hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const fl
                            float* loss, float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
                            hipStream_t s);
 
+hipError_t launch_preprocess3d(const sr_config& cfg, int N, const float* means, const float* scales,
+                               const float* quats, const float* opac, int V, const sr_camera* cams_dev,
+                               float* geom3, uint16_t* rect, uint32_t* tiles_touched, uint32_t* depth_key,
+                               uint8_t* in_frustum, hipStream_t s);
+hipError_t launch_prune3d(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
+                          const float* geom3, const uint32_t* vals, const uint32_t* ranges, uint32_t* hits,
+                          float* max_alpha, float* max_weight, hipStream_t s);
 size_t compact_workspace_bytes(int N);
 hipError_t launch_compact(int N, const uint8_t* prune, const float* opac, float min_opac, int n_arrays,
                           const float* const* src, float* const* dst, const int* widths, void* ws,

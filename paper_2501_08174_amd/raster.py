@@ -468,3 +468,95 @@ def compact_surfels(prune: torch.Tensor, arrays: Sequence[torch.Tensor], opac: O
          _ptr(ws), ws.numel(), _ptr(kept), _stream(stream))
     k = int(kept.item())
     return [d[:k].reshape((k,) + tuple(a.shape[1:])) for d, a in zip(dsts, arrays)]
+
+
+class Pruner3D:
+    """The occlusion-pruning pass for 3D Gaussians (Appendix B):
+    sr_preprocess_3d -> sr_bin_and_sort -> sr_prune_contrib_3d over a batch
+    of views.  Parameters: means [N,3], scales [N,3], quats [N,4], opac [N]."""
+
+    def __init__(self, N: int, views: ViewBatch, capacity: int = 0, device="cuda"):
+        self.N, self.views, self.device = int(N), views, device
+        self.cfg = make_config(0, None, views.tile)
+        VN = views.V * self.N
+        z = lambda n, dt: torch.zeros(max(int(n), 1), dtype=dt, device=device)
+        self.geom3 = z(VN * 8, torch.float32)
+        self.rect = z(VN * 4, torch.int16)
+        self.tiles_touched = z(VN, torch.int32)
+        self.depth_key = z(VN, torch.int32)
+        self.in_frustum = z(self.N, torch.uint8)
+        self.ranges = z(2 * views.T, torch.int32)
+        self.counters = z(_lib.SR_COUNTERS, torch.int32)
+        self.capacity = -1
+        self.set_capacity(capacity)
+
+    def set_capacity(self, cap: int):
+        cap = int(cap)
+        if cap == self.capacity:
+            return
+        self.capacity = cap
+        self.vals = torch.zeros(max(cap, 1), dtype=torch.int32, device=self.device)
+        self.ws_bytes = _lib.workspace_bytes_bin(self.N, self.views.V, cap)
+        self.ws = torch.zeros(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
+
+    def preprocess(self, means, scales, quats, opac, stream=None):
+        call("sr_preprocess_3d", ctypes.byref(self.cfg), self.N, _ptr(means), _ptr(scales), _ptr(quats),
+             _ptr(opac), self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.geom3),
+             _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key), _ptr(self.in_frustum),
+             _stream(stream))
+
+    def plan_capacity(self, means, scales, quats, opac, slack: float = 1.05) -> int:
+        self.preprocess(means, scales, quats, opac)
+        need = int(self.tiles_touched.to(torch.int64).sum().item())
+        self.set_capacity(int(need * slack) + 1024)
+        return need
+
+    def bin(self, keys64: Optional[torch.Tensor] = None, stream=None):
+        call("sr_bin_and_sort", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key),
+             _ptr(self.ws), self.ws_bytes, self.capacity, _ptr(self.vals), _ptr(keys64), _ptr(self.ranges),
+             _ptr(self.counters), _stream(stream))
+
+    def prune_stats(self, hits, max_alpha, max_weight, accumulate: bool = False, stream=None):
+        cfg = self.cfg
+        if accumulate:
+            cfg = SrConfig.from_buffer_copy(self.cfg)
+            cfg.flags |= _lib.SR_FLAG_ACCUMULATE
+        call("sr_prune_contrib_3d", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.geom3), _ptr(self.vals), _ptr(self.ranges), _ptr(hits),
+             _ptr(max_alpha), _ptr(max_weight), _stream(stream))
+
+    def run(self, means, scales, quats, opac, hits, max_alpha, max_weight, accumulate: bool = False,
+            stream=None):
+        self.preprocess(means, scales, quats, opac, stream)
+        self.bin(stream=stream)
+        self.prune_stats(hits, max_alpha, max_weight, accumulate, stream)
+
+    def status(self):
+        c = self.counters.cpu().numpy().view(np.uint32)
+        return int(c[0]), int(c[1]), int(c[2]), int(c[3])
+
+
+def prune_contrib_3d(means, scales, quats, opac, cams: Sequence, views_per_chunk: int = 25, tau: float = ALPHA_MIN,
+                     tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None) -> PruneStats:
+    """The occlusion-pruning pass for 3D Gaussians over every view (chunks of
+    views bound the instance buffers), statistics accumulated, then the mask."""
+    n = means.shape[0]
+    dev = means.device
+    if stats is None:
+        stats = PruneStats(torch.zeros(n, dtype=torch.int32, device=dev), torch.zeros(n, device=dev),
+                           torch.zeros(n, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
+                           torch.zeros(n, dtype=torch.uint8, device=dev))
+    for v0 in range(0, len(cams), views_per_chunk):
+        views = ViewBatch(cams[v0:v0 + views_per_chunk], tile=tile, device=dev)
+        pr = Pruner3D(n, views, device=dev)
+        pr.plan_capacity(means, scales, quats, opac, slack=slack)
+        pr.bin()
+        vis, need, stored, status = pr.status()
+        if status != 0:
+            raise RuntimeError(f"instance capacity exceeded: need {need}, have {pr.capacity}")
+        pr.prune_stats(stats.hits, stats.max_alpha, stats.max_weight, accumulate=True)
+        torch.bitwise_or(stats.in_frustum, pr.in_frustum[:n], out=stats.in_frustum)
+        del pr
+    stats.mask = prune_mask(stats.max_alpha, tau)
+    return stats

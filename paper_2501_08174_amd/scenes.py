@@ -269,6 +269,18 @@ def make_config3(seed: int = 3, n: int = 1_000_000, n_views: int = 16) -> Scene:
     return Scene(means, scales, quats, opac, sh, 3, cams, masks, targets, "config3")
 
 
+def make_config4_3d(seed: int = 4, **kw):
+    """The 3D-Gaussian counterpart of config 4 for the pruning pass of
+    Appendix B: the same centres, rotations and opacities; each surfel's two
+    tangent scales plus a third (normal) scale of 0.1 times the smaller one,
+    so the shell is a closed layer of thin, opaque 3D Gaussians.  Returns
+    (scene, scales3 [N,3] float32)."""
+    sc = make_config4(seed, **kw)
+    s = sc.scales.astype(np.float64)
+    s3 = np.concatenate([s, 0.1 * s.min(axis=1, keepdims=True)], axis=1).astype(np.float32)
+    return sc, s3
+
+
 def make_config4(seed: int = 4, n_shell: int = 300_000, n_inner: int = 700_000,
                  n_outer: int = 100_000, n_views: int = 100, size: int = 800) -> Scene:
     """Occlusion pruning workload: an opaque shell on the unit sphere
