@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--tile", default="auto", help="WxH tile shape, or 'auto' to pick by timing")
     ap.add_argument("--no-unfused", action="store_true", help="skip timing the separate-launch step")
     ap.add_argument("--no-eq3", action="store_true", help="skip timing the step with the whole Eq. 3 loss")
+    ap.add_argument("--prune-legs", action="store_true",
+                    help="also time the occlusion-pruning pass (surfels and 3D Gaussians) on the shell scene")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for the HBM traffic counters)")
     return ap.parse_args()
@@ -343,6 +345,31 @@ def main():
             "pruned": N - kept, "kept": kept,
             "compaction_ms_incl_host_sync": c_ms,
             "compaction_GBps": c_bytes / (c_ms * 1e-3) / 1e9}
+
+    if args.prune_legs:
+        # the occlusion-pruning pass (Section 4.3) on the shell scene of 100
+        # views of 800x800 (1.1M primitives), for surfels and for 3D Gaussians
+        from paper_2501_08174_amd import scenes as _sc
+        from paper_2501_08174_amd.raster import prune_contrib, prune_contrib_3d
+        sc4, s3 = _sc.make_config4_3d()
+        p4 = Params.from_scene(sc4)
+        s3t = torch.tensor(s3, device="cuda")
+        P4 = sum(c.width * c.height for c in sc4.cams)
+        legs = {}
+        for name, fn in (("surfels", lambda: prune_contrib(p4, sc4.cams, views_per_chunk=20)),
+                         ("gaussians_3d", lambda: prune_contrib_3d(p4.means, s3t, p4.quats, p4.opac, sc4.cams,
+                                                                   views_per_chunk=20))):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            legs[name] = {"s": dt, "Mpixel_per_s": P4 / dt / 1e6,
+                          "pruned": int(st.mask.sum().item()), "of": sc4.n}
+        result["pruning_pass"] = {"workload": "config4 shell scene, 100 views 800x800, 1.1M primitives, "
+                                              "views in chunks of 20 (capacity planning included)", **legs}
+        del p4, s3t
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
