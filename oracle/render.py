@@ -22,7 +22,9 @@ reasons in the design notes):
     blending stops before an entry k when T (1 - a_k) < t_min;
   * omega_k = a_k T_k; C = sum omega c + T_final bg; A = 1 - T_final;
     depth = sum omega z; normal = sum omega n_c;
-    dist = sum_{i,j} omega_i omega_j (z_i - z_j)^2 over ordered pairs.
+    dist = sum_{i,j} omega_i omega_j (z_i - z_j)^2 over ordered pairs;
+    median depth = z of the last blended entry that starts with T > 1/2
+    (0 when there is none), the 2DGS median depth.
 The per-pixel list is every surfel that is not culled and whose pixel
 rectangle (``geometry.view_geometry64``) contains the pixel, in ascending
 (float32 centre depth, id).
@@ -50,6 +52,7 @@ TIE_CUTOFF_REL = 5e-5      # |o G - alpha_min| <= 5e-5 alpha_min
 TIE_TERM_REL = 2e-4        # |T (1 - a) - t_min| <= 2e-4 t_min
 TIE_BRANCH = 1e-6          # |G_s - G_f|
 TIE_CLAMP = 1e-6           # |o G - alpha_max|
+TIE_MEDIAN = 1e-5          # |T_before - 1/2| at a blended entry (median depth)
 
 
 @dataclass
@@ -228,6 +231,14 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
 
     last = torch.where(blended, k.expand(Pn, L), torch.full_like(k.expand(Pn, L), -1)).max(dim=1).values
     n_contrib = (last + 1)
+    # median depth: the depth of the last blended entry that starts with
+    # T > 1/2 (0 without one); median_idx is that entry's 1-based list index
+    med_cand = blended & (T_before > 0.5)
+    kmed = torch.where(med_cand, k.expand(Pn, L), torch.full_like(k.expand(Pn, L), -1)).max(dim=1).values
+    has_med = kmed >= 0
+    zmed = torch.gather(z, 1, kmed.clamp(min=0)[:, None])[:, 0]
+    median_depth = torch.where(has_med, zmed, torch.zeros_like(zmed))
+    median_idx = kmed + 1
 
     with torch.no_grad():
         nsk = reached & ~gt
@@ -235,6 +246,8 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
         e_term = nsk & ~skip & ((T_before * (1 - a) - rp.t_min).abs() <= TIE_TERM_REL * rp.t_min)
         e_branch = blended & ((Gs - Gf).abs() <= TIE_BRANCH)
         e_clamp = blended & ((a_raw - rp.alpha_max).abs() <= TIE_CLAMP)
+        e_median = blended & ((T_before - 0.5).abs() <= TIE_MEDIAN)
+        f_median = e_median.any(dim=1)
         f_cut, f_term = e_cut.any(dim=1), e_term.any(dim=1)
         f_branch, f_clamp = e_branch.any(dim=1), e_clamp.any(dim=1)
         tie_entry = e_cut | e_term | e_branch | e_clamp
@@ -242,10 +255,11 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
                 T_final=T_final, n_contrib=n_contrib, blended=blended, reached=reached,
                 a=a, w=w, z=z, surf=surf, skip=skip, first_stop=first_stop,
                 clamp=a_raw > rp.alpha_max, tie_entry=tie_entry,
-                flag_cut=f_cut, flag_term=f_term, flag_branch=f_branch, flag_clamp=f_clamp)
+                flag_cut=f_cut, flag_term=f_term, flag_branch=f_branch, flag_clamp=f_clamp,
+                median_depth=median_depth, median_idx=median_idx, flag_median=f_median)
 
 
-OUT_KEYS = ("color", "alpha", "depth", "normal", "dist", "T_final")
+OUT_KEYS = ("color", "alpha", "depth", "normal", "dist", "T_final", "median_depth")
 
 
 def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = RasterParams(),
@@ -270,7 +284,7 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
     Pn = pix.shape[0]
     res = {k: [] for k in OUT_KEYS}
     extra = {k: [] for k in ("n_contrib", "last_gid", "nblend", "flag_cut", "flag_term",
-                             "flag_branch", "flag_clamp")}
+                             "flag_branch", "flag_clamp", "median_idx", "flag_median")}
     pairs, flag_ids, tie_ids, decisions = [], [], [], []
     start = 0
     step = max(1, min(Pn, 1024))
@@ -299,10 +313,13 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
         ncon = out["n_contrib"].numpy()
         gid_mat = ids[colidx]
         last_gid = np.where(ncon > 0, gid_mat[np.arange(sub.shape[0]), np.maximum(ncon - 1, 0)], -1)
+        midx = out["median_idx"].numpy()
+        extra.setdefault("median_gid", []).append(
+            np.where(midx > 0, gid_mat[np.arange(sub.shape[0]), np.maximum(midx - 1, 0)], -1))
         extra["n_contrib"].append(ncon)
         extra["last_gid"].append(last_gid)
         extra["nblend"].append(bl.sum(axis=1))
-        for k in ("flag_cut", "flag_term", "flag_branch", "flag_clamp"):
+        for k in ("flag_cut", "flag_term", "flag_branch", "flag_clamp", "median_idx", "flag_median"):
             extra[k].append(out[k].numpy())
         rr, cc = np.nonzero(bl)
         pairs.append(np.stack([rr + start, gid_mat[rr, cc]], axis=1) if rr.size else np.zeros((0, 2), np.int64))
