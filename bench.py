@@ -102,6 +102,7 @@ class Pipeline:
         self.dD = torch.zeros_like(self.rast.depth)
         self.dN = torch.zeros_like(self.rast.normal)
         self.dS = torch.zeros_like(self.rast.dist)
+        self.dM = torch.zeros_like(self.rast.depth)
         self.need = self.rast.plan_capacity(params, slack=1.02)
 
     STAGES = ("preprocess", "bin_sort", "train_raster", "backward_project")
@@ -112,8 +113,10 @@ class Pipeline:
     def step(self, ev=None, fused=True, eq3=None):
         """One training step; the compositing is the fused forward + loss +
         backward launch (fused=True) or the three separate launches; with
-        eq3 = (w_dist, w_normal) the loss is the whole Eq. 3 (the 2DGS
-        regularisers need neighbouring pixels, so the launches are separate)."""
+        eq3 = (w_dist, w_normal[, median]) the loss is the whole Eq. 3 (the
+        2DGS regularisers need neighbouring pixels, so the launches are
+        separate); with median the normal term takes the median depth as its
+        surface."""
         r = self.rast
         rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
         rec(0)
@@ -123,15 +126,17 @@ class Pipeline:
         rec(2)
         if eq3 is not None:
             # L_c^M = (1 - lambda) L1 + lambda D-SSIM on the masked images (lambda = 0.2)
-            r.forward(stats=self.stats, accumulate=True)
+            med = len(eq3) > 2 and eq3[2]
+            r.forward(stats=self.stats, accumulate=True, median=med)
             rec(3)
             r.loss(self.mask, self.target, 0.5, 0.8, self.dA, self.dC)
             rec(4)
             r.ssim_loss(self.mask, self.target, 0.2, dL_dcolor=self.dC)
             rec(5)
-            r.regularizer_loss(eq3[0], eq3[1], self.dA, self.dD, self.dN, self.dS)
+            dM = self.dM if med else None
+            r.regularizer_loss(eq3[0], eq3[1], self.dA, self.dD, self.dN, self.dS, dL_dmedian=dM)
             rec(6)
-            r.backward_raster(dC=self.dC, dA=self.dA, dD=self.dD, dN=self.dN, dS=self.dS)
+            r.backward_raster(dC=self.dC, dA=self.dA, dD=self.dD, dN=self.dN, dS=self.dS, dM=dM)
             rec(7)
         elif fused:
             r.train_step_raster(self.mask, self.target, 0.5, 1.0, stats=self.stats, accumulate=True)
@@ -279,15 +284,19 @@ def main():
         # for bounded scenes)
         w_dist, w_normal = 1000.0, 0.05
         ns_e = len(Pipeline.STAGES_EQ3)
-        ev_e = [[torch.cuda.Event(enable_timing=True) for _ in range(ns_e + 1)] for _ in range(args.steps)]
-        pipe.step(eq3=(w_dist, w_normal))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            pipe.step(ev_e[k], eq3=(w_dist, w_normal))
-        torch.cuda.synchronize()
-        e_ms = (time.perf_counter() - t0) / args.steps * 1e3
-        st_e = np.array([[ev_e[k][i].elapsed_time(ev_e[k][i + 1]) for i in range(ns_e)] for k in range(args.steps)])
+
+        def eq3_leg(median):
+            ev_e = [[torch.cuda.Event(enable_timing=True) for _ in range(ns_e + 1)] for _ in range(args.steps)]
+            pipe.step(eq3=(w_dist, w_normal, median))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                pipe.step(ev_e[k], eq3=(w_dist, w_normal, median))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.steps * 1e3
+            return ms, np.array([[ev_e[k][i].elapsed_time(ev_e[k][i + 1]) for i in range(ns_e)]
+                                 for k in range(args.steps)])
+        e_ms, st_e = eq3_leg(False)
         reg_ms = float(st_e[:, Pipeline.STAGES_EQ3.index("regularizers")].mean())
         reg_bytes = 52 * P
         ssim_ms = float(st_e[:, Pipeline.STAGES_EQ3.index("ssim")].mean())
@@ -303,6 +312,10 @@ def main():
                                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                                            "frac": ssim_bytes / (ssim_ms * 1e-3) / HBM_PEAK,
                                            "bytes_per_call": ssim_bytes}}
+        # the same step with the median depth as the surface of the normal term
+        m_ms, st_m = eq3_leg(True)
+        result["eq3_median"] = {"ms_per_step": m_ms, "Mpixel_per_s": P / (m_ms * 1e-3) / 1e6,
+                                "stage_ms_mean": dict(zip(Pipeline.STAGES_EQ3, [float(x) for x in st_m.mean(axis=0)]))}
 
     if not args.no_eq3:
         # density control and pruning of a training step: the screen-gradient

@@ -147,20 +147,31 @@ sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_c
  * (z_i - z_j)^2, T_final [P], n_contrib [P] (index + 1 of the last blended
  * entry of the pixel's tile list).  When hits/max_alpha/max_weight are not
  * NULL the occlusion statistics of sr_prune_contrib are gathered in the
- * same pass.  All outputs except the statistics are required. */
+ * same pass.  Median depth (the 2DGS surface depth, an alternative to
+ * depth/alpha in the normal consistency term of Eq. 3), optional: when
+ * median_depth [P] and median_contrib [P] are not NULL (both or neither),
+ * median_depth = z of the last blended entry whose transmittance before it
+ * is above 1/2 (0 when no entry blends), median_contrib = that entry's
+ * index + 1 in the tile list (0 when none); sr_backward_raster takes
+ * median_contrib to route dL/d(median depth).  All other outputs except the
+ * statistics are required. */
 sr_status sr_render_forward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                             const sr_camera *cams_dev, const float *geom, const float *app,
                             const uint32_t *vals, const uint32_t *ranges,
                             float *color, float *alpha, float *depth, float *normal, float *dist,
                             float *T_final, uint32_t *n_contrib,
-                            uint32_t *hits, float *max_alpha, float *max_weight, void *stream);
+                            uint32_t *hits, float *max_alpha, float *max_weight,
+                            float *median_depth, uint32_t *median_contrib, void *stream);
 
 /* Gradient of a loss through the compositing and the projection (Section
  * 3.1: position, shape and appearance are updated by backpropagation).
  * Recomputes the forward back to front from T_final and n_contrib.
  * dL_d* are the upstream gradients of the five forward outputs (any may be
- * NULL = zero).  grad_rec [V*N, 24] is scratch (cleared by the call, and
- * left zero).
+ * NULL = zero); dL_dmedian [P] that of the median depth, which needs the
+ * median_contrib [P] of the same forward (both NULL without it).  The
+ * median depth is the depth of one entry, so its gradient reaches only that
+ * entry's depth (the choice of the entry is piecewise constant).
+ * grad_rec [V*N, 24] is scratch (cleared by the call, and left zero).
  * The parameter gradients are ACCUMULATED (+=) into g_means [N,3],
  * g_scales [N,2], g_quats [N,4], g_opac [N], g_sh [N,sh_stride,3]. */
 sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
@@ -170,7 +181,8 @@ sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const s
                              const uint32_t *ranges, const float *alpha, const float *depth,
                              const float *dist, const float *T_final, const uint32_t *n_contrib,
                              const float *dL_dcolor, const float *dL_dalpha, const float *dL_ddepth,
-                             const float *dL_dnormal, const float *dL_ddist, float *grad_rec,
+                             const float *dL_dnormal, const float *dL_ddist,
+                             const uint32_t *median_contrib, const float *dL_dmedian, float *grad_rec,
                              float *g_means, float *g_scales, float *g_quats, float *g_opac,
                              float *g_sh, void *stream);
 
@@ -196,6 +208,7 @@ sr_status sr_backward_raster(const sr_config *cfg, int32_t N, int32_t V, const s
                              const float *depth, const float *dist, const float *T_final,
                              const uint32_t *n_contrib, const float *dL_dcolor, const float *dL_dalpha,
                              const float *dL_ddepth, const float *dL_dnormal, const float *dL_ddist,
+                             const uint32_t *median_contrib, const float *dL_dmedian,
                              float *grad_rec, void *stream);
 sr_status sr_backward_project(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                               const sr_camera *cams_dev, const float *means, const float *scales,
@@ -227,7 +240,9 @@ sr_status sr_background_loss(int32_t V, const sr_camera *cams_host, const sr_cam
  * view, with the readings
  *   L_d,v = (1/(H W)) sum_p dist(p)
  *   P(p)  = s(p) ((i + 0.5 - cx)/fx, (j + 0.5 - cy)/fy, 1), s = depth/alpha
- *           where alpha > 0, else 0 (camera-space point of pixel (i, j))
+ *           where alpha > 0, else 0 (camera-space point of pixel (i, j));
+ *           with median [P] not NULL, s = median (the median depth of
+ *           sr_render_forward) instead
  *   N_d(p) = n / max(|n|, 1e-12), n = (P(i,j+1) - P(i,j-1)) x (P(i+1,j) -
  *           P(i-1,j)); 0 on the one-pixel border
  *   L_n,v = (1/(H W)) sum_p (alpha(p) - normal(p) . N_d(p))
@@ -237,13 +252,17 @@ sr_status sr_background_loss(int32_t V, const sr_camera *cams_host, const sr_cam
  * the gradient through the neighbours' depth normals):
  *   dL_dalpha [P]  ADDED to (composes with sr_background_loss, which writes it)
  *   dL_ddepth [P], dL_dnormal [3P], dL_ddist [P]  overwritten
+ *   dL_dmedian [P]  overwritten; required exactly when median is given
+ *                   (dL_ddepth is then zero: the surface depth no longer
+ *                   depends on depth)
  * Feed all of them to sr_backward_raster.  workspace: sr_loss_workspace_size
  * bytes.  Per-view sums in a fixed order (deterministic). */
 sr_status sr_regularizer_loss(int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
                               const float *alpha, const float *depth, const float *normal,
-                              const float *dist, float w_dist, float w_normal, void *workspace,
-                              size_t ws_bytes, float *loss, float *dL_dalpha, float *dL_ddepth,
-                              float *dL_dnormal, float *dL_ddist, void *stream);
+                              const float *dist, const float *median, float w_dist, float w_normal,
+                              void *workspace, size_t ws_bytes, float *loss, float *dL_dalpha,
+                              float *dL_ddepth, float *dL_dnormal, float *dL_ddist, float *dL_dmedian,
+                              void *stream);
 
 /* Bytes of workspace sr_ssim_loss needs for these views (with_grad != 0:
  * room for the gradient maps too). */

@@ -175,7 +175,7 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
                             const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
                             const uint32_t* ranges, float* color, float* alpha, float* depth, float* normal,
                             float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
-                            float* max_weight, void* stream) {
+                            float* max_weight, float* median_depth, uint32_t* median_contrib, void* stream) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
     int total_tiles = 0;
@@ -188,6 +188,8 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
     const bool st = hits || max_alpha || max_weight;
     if (st && !(hits && max_alpha && max_weight))
         return fail(SR_ERR_ARG, "hits, max_alpha and max_weight must be given together");
+    if ((median_depth == nullptr) != (median_contrib == nullptr))
+        return fail(SR_ERR_ARG, "median_depth and median_contrib must be given together");
     hipStream_t s = (hipStream_t)stream;
     if (st && !(cfg->flags & SR_FLAG_ACCUMULATE) && N > 0) {
         SR_TRY(hip_status(sr::fill_f32((float*)hits, 0.f, (uint64_t)N, s), "clear hits"));
@@ -196,7 +198,7 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
     }
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, color,
                                             alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                                            max_weight, nullptr, s),
+                                            max_weight, nullptr, median_depth, median_contrib, s),
                       "sr_render_forward");
 }
 
@@ -239,14 +241,16 @@ sr_status sr_backward_raster(const sr_config* cfg, int32_t N, int32_t V, const s
                              const uint32_t* ranges, const float* alpha, const float* depth, const float* dist,
                              const float* T_final, const uint32_t* n_contrib, const float* dL_dcolor,
                              const float* dL_dalpha, const float* dL_ddepth, const float* dL_dnormal,
-                             const float* dL_ddist, float* grad_rec, void* stream) {
+                             const float* dL_ddist, const uint32_t* median_contrib, const float* dL_dmedian,
+                             float* grad_rec, void* stream) {
     int total_tiles = 0;
     SR_TRY(check_backward_raster(cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, alpha, depth, dist, T_final,
                                  n_contrib, grad_rec, &total_tiles));
+    if (dL_dmedian && !median_contrib) return fail(SR_ERR_ARG, "dL_dmedian needs median_contrib");
     if (N == 0 || V == 0) return SR_OK;
     return hip_status(sr::launch_render_bwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, alpha, depth,
                                             dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
-                                            dL_ddist, grad_rec, (hipStream_t)stream),
+                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, (hipStream_t)stream),
                       "sr_backward_raster");
 }
 
@@ -272,12 +276,14 @@ sr_status sr_render_backward(const sr_config* cfg, int32_t N, int32_t V, const s
                              const uint32_t* vals, const uint32_t* ranges, const float* alpha, const float* depth,
                              const float* dist, const float* T_final, const uint32_t* n_contrib,
                              const float* dL_dcolor, const float* dL_dalpha, const float* dL_ddepth,
-                             const float* dL_dnormal, const float* dL_ddist, float* grad_rec, float* g_means,
-                             float* g_scales, float* g_quats, float* g_opac, float* g_sh, void* stream) {
+                             const float* dL_dnormal, const float* dL_ddist, const uint32_t* median_contrib,
+                             const float* dL_dmedian, float* grad_rec, float* g_means, float* g_scales,
+                             float* g_quats, float* g_opac, float* g_sh, void* stream) {
     int total_tiles = 0;
     (void)opac;
     SR_TRY(check_backward_raster(cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, alpha, depth, dist, T_final,
                                  n_contrib, grad_rec, &total_tiles));
+    if (dL_dmedian && !median_contrib) return fail(SR_ERR_ARG, "dL_dmedian needs median_contrib");
     SR_TRY(check_backward_project(cfg, N, V, cams_host, cams_dev, means, scales, quats, sh, geom, app, grad_rec,
                                   g_means, g_scales, g_quats, g_opac, g_sh));
     if (N == 0 || V == 0) return SR_OK;
@@ -285,7 +291,7 @@ sr_status sr_render_backward(const sr_config* cfg, int32_t N, int32_t V, const s
     SR_TRY(hip_status(sr::fill_f32(grad_rec, 0.f, (uint64_t)V * N * SR_GRAD_STRIDE, s), "clear grad_rec"));
     SR_TRY(hip_status(sr::launch_render_bwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, alpha, depth,
                                             dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
-                                            dL_ddist, grad_rec, s),
+                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, s),
                       "render backward"));
     return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app, nullptr,
                                                 grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, nullptr,
@@ -334,14 +340,16 @@ sr_status sr_background_loss(int32_t V, const sr_camera* cams_host, const sr_cam
 }
 
 sr_status sr_regularizer_loss(int32_t V, const sr_camera* cams_host, const sr_camera* cams_dev, const float* alpha,
-                              const float* depth, const float* normal, const float* dist, float w_dist,
-                              float w_normal, void* workspace, size_t ws_bytes, float* loss, float* dL_dalpha,
-                              float* dL_ddepth, float* dL_dnormal, float* dL_ddist, void* stream) {
+                              const float* depth, const float* normal, const float* dist, const float* median,
+                              float w_dist, float w_normal, void* workspace, size_t ws_bytes, float* loss,
+                              float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
+                              float* dL_dmedian, void* stream) {
     if (V < 0) return fail(SR_ERR_ARG, "V < 0");
     if (V == 0) return SR_OK;
     SR_NEED(cams_host); SR_NEED(cams_dev); SR_NEED(alpha); SR_NEED(depth); SR_NEED(normal); SR_NEED(dist);
     SR_NEED(loss); SR_NEED(workspace); SR_NEED(dL_dalpha); SR_NEED(dL_ddepth); SR_NEED(dL_dnormal);
     SR_NEED(dL_ddist);
+    if ((median == nullptr) != (dL_dmedian == nullptr)) return fail(SR_ERR_ARG, "median and dL_dmedian go together");
     int64_t pix = 0;
     int mt = 0;
     for (int v = 0; v < V; ++v) {
@@ -354,8 +362,9 @@ sr_status sr_regularizer_loss(int32_t V, const sr_camera* cams_host, const sr_ca
         if (t > mt) mt = t;
     }
     if (ws_bytes < sr::loss_workspace_bytes(V, 0, mt)) return fail(SR_ERR_ARG, "regularizer workspace too small");
-    return hip_status(sr::launch_reg_loss(V, mt, cams_dev, alpha, depth, normal, dist, w_dist, w_normal, workspace,
-                                          loss, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist, (hipStream_t)stream),
+    return hip_status(sr::launch_reg_loss(V, mt, cams_dev, alpha, depth, normal, dist, median, w_dist, w_normal,
+                                          workspace, loss, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist, dL_dmedian,
+                                          (hipStream_t)stream),
                       "sr_regularizer_loss");
 }
 
@@ -487,7 +496,7 @@ sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_
     }
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, vals, ranges, nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, hits, max_alpha,
-                                            max_weight, nullptr, s),
+                                            max_weight, nullptr, nullptr, nullptr, s),
                       "sr_prune_contrib");
 }
 
@@ -536,7 +545,7 @@ sr_status sr_render_count(const sr_config* cfg, int32_t N, int32_t V, const sr_c
     SR_TRY(hip_status(sr::fill_f32((float*)counts, 0.f, 8, s), "clear counts"));
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, vals, ranges, nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                            nullptr, (unsigned long long*)counts, s),
+                                            nullptr, (unsigned long long*)counts, nullptr, nullptr, s),
                       "sr_render_count");
 }
 

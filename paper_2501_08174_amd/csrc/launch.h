@@ -37,13 +37,15 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
                              uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                             unsigned long long* counts, hipStream_t s);
+                             unsigned long long* counts, float* median_depth, uint32_t* median_contrib,
+                             hipStream_t s);
 
 hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
-                             const float* dN, const float* dS, float* grad_rec, hipStream_t s);
+                             const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
+                             float* grad_rec, hipStream_t s);
 
 hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                                const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
@@ -64,9 +66,9 @@ hipError_t launch_loss(int V, int64_t max_hw, const sr_camera* cams, const float
                        const float* color, const float* target, float gamma, float w_c, void* ws, float* loss,
                        float* dL_dalpha, float* dL_dcolor, hipStream_t s);
 hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const float* alpha, const float* depth,
-                           const float* normal, const float* dist, float w_dist, float w_normal, void* ws,
-                           float* loss, float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
-                           hipStream_t s);
+                           const float* normal, const float* dist, const float* median, float w_dist,
+                           float w_normal, void* ws, float* loss, float* dL_dalpha, float* dL_ddepth,
+                           float* dL_dnormal, float* dL_ddist, float* dL_dmedian, hipStream_t s);
 
 hipError_t launch_preprocess3d(const sr_config& cfg, int N, const float* means, const float* scales,
                                const float* quats, const float* opac, int V, const sr_camera* cams_dev,

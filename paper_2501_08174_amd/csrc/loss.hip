@@ -125,8 +125,10 @@ k_loss_tiles(const sr_camera* __restrict__ cams, int V, const float* __restrict_
 // ---- 2DGS regularisers of the total loss (Eq. 3) ---------------------------
 //   L_d,v = mean_p dist(p)
 //   L_n,v = mean_p (A(p) - N(p) . N_d(p)),  N_d from central differences of
-//           the camera-space points P = (D / A) ray (0 where A = 0), zero on
-//           the one-pixel border
+//           the camera-space points P = s ray, zero on the one-pixel border;
+//           the surface depth s is D / A (0 where A = 0) or, when a median
+//           depth map is given, the median depth (its gradient then goes to
+//           that map and none to D)
 //   L_reg = (1/V) sum_v (w_dist L_d,v + w_normal L_n,v)
 // One workgroup per 32x8 pixel tile of a view: the camera-space points of
 // the tile and a two-pixel halo are formed once in LDS, then the depth
@@ -159,8 +161,9 @@ __device__ __forceinline__ int reg_tiles(int W, int H) { return reg_tiles_of(W, 
 __global__ void __launch_bounds__(kNT)
 k_reg_partial(const sr_camera* __restrict__ cams, int V, const float* __restrict__ alpha,
               const float* __restrict__ depth, const float* __restrict__ normal, const float* __restrict__ dist,
-              float w_dist, float w_normal, int nslot, float* __restrict__ partial, float* __restrict__ dL_dalpha,
-              float* __restrict__ dL_ddepth, float* __restrict__ dL_dnormal, float* __restrict__ dL_ddist) {
+              const float* __restrict__ median, float w_dist, float w_normal, int nslot, float* __restrict__ partial,
+              float* __restrict__ dL_dalpha, float* __restrict__ dL_ddepth, float* __restrict__ dL_dnormal,
+              float* __restrict__ dL_ddist, float* __restrict__ dL_dmedian) {
 #pragma clang fp contract(off)
     __shared__ float s[kNT];
     __shared__ float3 sP[kRegPY][kRegPX];
@@ -176,19 +179,25 @@ k_reg_partial(const sr_camera* __restrict__ cams, int V, const float* __restrict
     const int64_t HW = (int64_t)W * H;
     const float* A = alpha + c.pix_offset;
     const float* D = depth + c.pix_offset;
+    const float* Md = median ? median + c.pix_offset : nullptr;
     const float* Nr = normal + 3 * c.pix_offset;
     const float scale = 1.0f / ((float)HW * (float)V);
     const float gn = w_normal * scale;
     const float fx = c.fx, fy = c.fy, cx = c.cx, cy = c.cy;
-    // points P = (D / A) ray of the tile and a two-pixel halo (0 outside)
+    // points P = s ray of the tile and a two-pixel halo (0 outside)
     for (int k = threadIdx.x; k < kRegPX * kRegPY; k += kNT) {
         const int ly = k / kRegPX, lx = k - ly * kRegPX;
         const int i = x0 - 2 + lx, j = y0 - 2 + ly;
         float3 P = make_float3(0.f, 0.f, 0.f);
         if (i >= 0 && i < W && j >= 0 && j < H) {
             const int64_t p = (int64_t)j * W + i;
-            const float a = A[p];
-            const float sd = a > 0.f ? D[p] / a : 0.f;
+            float sd;
+            if (Md) {
+                sd = Md[p];
+            } else {
+                const float a = A[p];
+                sd = a > 0.f ? D[p] / a : 0.f;
+            }
             P = make_float3(sd * (((float)i + 0.5f - cx) / fx), sd * (((float)j + 0.5f - cy) / fy), sd);
         }
         sP[ly][lx] = P;
@@ -246,7 +255,9 @@ k_reg_partial(const sr_camera* __restrict__ cams, int V, const float* __restrict
         const float3 ray = make_float3(((float)i + 0.5f - cx) / fx, ((float)j + 0.5f - cy) / fy, 1.0f);
         const float ds = f3dot(dP, ray);
         float gA = gn, gD = 0.f;
-        if (a > 0.f) {
+        if (Md) {
+            dL_dmedian[o1] = ds;
+        } else if (a > 0.f) {
             gD = ds / a;
             gA = gA - ds * (D[p] / a) / a;
         }
@@ -300,12 +311,13 @@ k_reg_total(int V, float w_dist, float w_normal, float* __restrict__ loss) {
 int reg_tile_count(int W, int H) { return reg_tiles_of(W, H); }
 
 hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const float* alpha, const float* depth,
-                           const float* normal, const float* dist, float w_dist, float w_normal, void* ws,
-                           float* loss, float* dL_dalpha, float* dL_ddepth, float* dL_dnormal, float* dL_ddist,
-                           hipStream_t s) {
+                           const float* normal, const float* dist, const float* median, float w_dist,
+                           float w_normal, void* ws, float* loss, float* dL_dalpha, float* dL_ddepth,
+                           float* dL_dnormal, float* dL_ddist, float* dL_dmedian, hipStream_t s) {
     if (V == 0 || max_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reg_partial, dim3(max_tiles, V), dim3(kNT), 0, s, cams, V, alpha, depth, normal, dist,
-                       w_dist, w_normal, max_tiles, (float*)ws, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist);
+                       median, w_dist, w_normal, max_tiles, (float*)ws, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist,
+                       dL_dmedian);
     hipLaunchKernelGGL(k_reg_final, dim3(V), dim3(kNT), 0, s, cams, V, max_tiles, (const float*)ws, loss);
     hipLaunchKernelGGL(k_reg_total, dim3(1), dim3(kNT), 0, s, V, w_dist, w_normal, loss);
     return hipGetLastError();

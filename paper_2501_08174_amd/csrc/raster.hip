@@ -51,13 +51,15 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
 }
 
 // MODE bits: 1 shade (colour, depth, normal, distortion outputs), 2 occlusion
-// statistics, 4 count reached/blended pairs (work accounting).
-constexpr int kShade = 1, kStats = 2, kCount = 4;
+// statistics, 4 count reached/blended pairs (work accounting), 8 median depth
+// (the 2DGS surface depth: the depth of the last blended entry that starts
+// with transmittance above 1/2) with the 1-based list index of that entry.
+constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8;
 
 // Per-pixel state at the end of the forward pass.
 struct PixFwd {
-    float T, C0, C1, C2, N0, N1, N2, S0, S1, S2, zref;
-    uint32_t last;
+    float T, C0, C1, C2, N0, N1, N2, S0, S1, S2, zref, zmed;
+    uint32_t last, kmed;
 };
 
 // LDS staging of the forward: NT records per batch.
@@ -89,11 +91,12 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     constexpr bool SHADE = (MODE & kShade) != 0;
     constexpr bool STATS = (MODE & kStats) != 0;
     constexpr bool COUNT = (MODE & kCount) != 0;
+    constexpr bool MEDIAN = (MODE & kMedian) != 0;
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     st.T = 1.0f;
-    st.C0 = st.C1 = st.C2 = st.N0 = st.N1 = st.N2 = st.S0 = st.S1 = st.S2 = st.zref = 0.f;
-    st.last = 0;
+    st.C0 = st.C1 = st.C2 = st.N0 = st.N1 = st.N2 = st.S0 = st.S1 = st.S2 = st.zref = st.zmed = 0.f;
+    st.last = st.kmed = 0;
     bool have_ref = false;
     bool done = !t.inside;
     for (uint32_t base = 0; base < t.n; base += NT) {
@@ -148,6 +151,10 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 st.S0 += wgt;
                 st.S1 = __builtin_fmaf(wgt, zs, st.S1);
                 st.S2 = __builtin_fmaf(wgt * zs, zs, st.S2);
+                if (MEDIAN && st.T > 0.5f) {         // T before this entry
+                    st.zmed = e.z;
+                    st.kmed = base + (uint32_t)k + 1u;
+                }
                 st.T = Tn;
                 st.last = base + (uint32_t)k + 1u;
             }
@@ -216,7 +223,8 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
              RasterConsts rc, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
              float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
              uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
-             float* __restrict__ max_weight, unsigned long long* __restrict__ counts) {
+             float* __restrict__ max_weight, unsigned long long* __restrict__ counts,
+             float* __restrict__ median_depth, uint32_t* __restrict__ median_contrib) {
     constexpr int NT = TW * TH;
     __shared__ FwdSmem<NT, MODE> sm;
     TileCtx t;
@@ -234,12 +242,17 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     }
     if ((MODE & kShade) && t.inside) write_outputs(st, pix_outputs(st, t), t, color, alpha, depth, normal, dist,
                                                    T_final, n_contrib);
+    if ((MODE & kMedian) && t.inside) {
+        const int64_t o1 = t.pix_off + (int64_t)t.iy * t.W + t.ix;
+        median_depth[o1] = st.zmed;
+        median_contrib[o1] = st.kmed;
+    }
 }
 
 // Per-pixel inputs of the backward.
 struct PixBwd {
-    uint32_t ncon;
-    float T, gC0, gC1, gC2, gA, gD, gN0, gN1, gN2, gS, S0, rmean, Q, Wacc;
+    uint32_t ncon, kmed;
+    float T, gC0, gC1, gC2, gA, gD, gN0, gN1, gN2, gS, gMed, S0, rmean, Q, Wacc;
 };
 
 __device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float Tf, uint32_t ncon, float S0,
@@ -334,7 +347,9 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                 const float zr = e.z - pb.rmean;
                 gk += pb.gD * e.z + pb.gN0 * a0.w + pb.gN1 * a1.x + pb.gN2 * a1.y +
                       pb.gS * 2.0f * (pb.Q + pb.S0 * zr * zr);
-                dLdz = bl ? wraw * (pb.gD + 4.0f * pb.gS * pb.S0 * zr) : 0.f;
+                // the median depth is the depth of entry kmed - 1 (0-based)
+                const float gmed = jj + 1u == pb.kmed ? pb.gMed : 0.f;
+                dLdz = bl ? __builtin_fmaf(wraw, pb.gD + 4.0f * pb.gS * pb.S0 * zr, gmed) : 0.f;
                 gr[18] = pb.gN0 * wgt; gr[19] = pb.gN1 * wgt; gr[20] = pb.gN2 * wgt;
             }
             const float dLda = bl ? Tk * gk - Wacc * rin : 0.f;
@@ -398,14 +413,16 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
              RasterConsts rc, const float* __restrict__ alpha, const float* __restrict__ depth,
              const float* __restrict__ dist, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
              const float* __restrict__ dC, const float* __restrict__ dA, const float* __restrict__ dD,
-             const float* __restrict__ dNrm, const float* __restrict__ dDist, float* __restrict__ grad_rec) {
+             const float* __restrict__ dNrm, const float* __restrict__ dDist,
+             const uint32_t* __restrict__ median_contrib, const float* __restrict__ dMed,
+             float* __restrict__ grad_rec) {
     __shared__ BwdSmem<BATCH> sm;
     TileCtx t;
     tile_ctx<TW, TH>(cams, V, ranges, t);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixBwd pb;
-    pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = 0.f;
-    pb.ncon = 0;
+    pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = pb.gMed = 0.f;
+    pb.ncon = pb.kmed = 0;
     pb.T = 1.f;
     pb.S0 = pb.rmean = pb.Q = pb.Wacc = 0.f;
     if (t.inside) {
@@ -417,6 +434,7 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         if (dD) pb.gD = dD[o1];
         if (dNrm) { pb.gN0 = dNrm[o3]; pb.gN1 = dNrm[o3 + HW]; pb.gN2 = dNrm[o3 + 2 * HW]; }
         if (dDist) pb.gS = dDist[o1];
+        if (dMed) { pb.gMed = dMed[o1]; pb.kmed = median_contrib[o1]; }
         pix_bwd_init(pb, t, T_final[o1], n_contrib[o1], alpha[o1], depth[o1], dist[o1]);
     }
     bwd_tile<TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
@@ -450,8 +468,8 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
                        max_alpha, max_weight, n0, n1, n2, n3);
     const PixOut o = pix_outputs(st, t);
     PixBwd pb;
-    pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = 0.f;
-    pb.ncon = 0;
+    pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = pb.gMed = 0.f;
+    pb.ncon = pb.kmed = 0;
     pb.T = 1.f;
     pb.S0 = pb.rmean = pb.Q = pb.Wacc = 0.f;
     float lb = 0.f, l1 = 0.f;
@@ -507,10 +525,11 @@ template <int TW, int TH, int MODE>
 void fwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
                 const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, float* color,
                 float* alpha, float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib,
-                uint32_t* hits, float* max_alpha, float* max_weight, unsigned long long* counts) {
+                uint32_t* hits, float* max_alpha, float* max_weight, unsigned long long* counts,
+                float* median_depth, uint32_t* median_contrib) {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, MODE>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app,
                        vals, ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                       max_weight, counts);
+                       max_weight, counts, median_depth, median_contrib);
 }
 
 template <int TW, int TH>
@@ -518,13 +537,16 @@ void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cam
                   const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges,
                   RasterConsts rc, float* color, float* alpha, float* depth, float* normal, float* dist,
                   float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                  unsigned long long* counts) {
+                  unsigned long long* counts, float* median_depth, uint32_t* median_contrib) {
 #define SR_FWD(M)                                                                                        \
     fwd_launch<TW, TH, M>(total_tiles, s, cams, V, N, geom, app, vals, ranges, rc, color, alpha, depth, \
-                          normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, counts)
+                          normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, counts,          \
+                          median_depth, median_contrib)
     switch (mode) {
         case kShade: SR_FWD(kShade); break;
         case kShade | kStats: SR_FWD(kShade | kStats); break;
+        case kShade | kMedian: SR_FWD(kShade | kMedian); break;
+        case kShade | kStats | kMedian: SR_FWD(kShade | kStats | kMedian); break;
         case kStats: SR_FWD(kStats); break;
         default: SR_FWD(kCount); break;
     }
@@ -536,16 +558,16 @@ void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, in
                 const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, const float* alpha,
                 const float* depth, const float* dist, const float* T_final, const uint32_t* n_contrib,
                 const float* dC, const float* dA, const float* dD, const float* dN, const float* dS,
-                float* grad_rec) {
+                const uint32_t* median_contrib, const float* dMed, float* grad_rec) {
     constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
-    if (dD || dN || dS)
+    if (dD || dN || dS || dMed)
         hipLaunchKernelGGL((k_render_bwd<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom,
                            app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
-                           grad_rec);
+                           median_contrib, dMed, grad_rec);
     else
         hipLaunchKernelGGL((k_render_bwd<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
                            geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
-                           grad_rec);
+                           median_contrib, dMed, grad_rec);
 }
 
 template <int TW, int TH>
@@ -588,15 +610,17 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
                              uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                             unsigned long long* counts, hipStream_t s) {
+                             unsigned long long* counts, float* median_depth, uint32_t* median_contrib,
+                             hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
-    int mode = counts ? kCount : ((color ? kShade : 0) | (hits ? kStats : 0));
+    int mode = counts ? kCount
+                      : ((color ? kShade : 0) | (hits ? kStats : 0) | (color && median_depth ? kMedian : 0));
 #define SR_TS(W, H)                                                                                              \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                   \
         fwd_dispatch<W, H>(mode, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,    \
                            (const uint2*)ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, \
-                           max_alpha, max_weight, counts);                                                      \
+                           max_alpha, max_weight, counts, median_depth, median_contrib);                        \
         return hipGetLastError();                                                                               \
     }
     SR_TILE_SHAPES(SR_TS)
@@ -608,14 +632,15 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
-                             const float* dN, const float* dS, float* grad_rec, hipStream_t s) {
+                             const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
+                             float* grad_rec, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
 #define SR_TS(W, H)                                                                                            \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                 \
         bwd_launch<W, H>(total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,          \
                          (const uint2*)ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, \
-                         grad_rec);                                                                           \
+                         median_contrib, dMed, grad_rec);                                                     \
         return hipGetLastError();                                                                             \
     }
     SR_TILE_SHAPES(SR_TS)

@@ -169,13 +169,23 @@ class Rasterizer:
         cfg.flags |= _lib.SR_FLAG_ACCUMULATE
         return cfg
 
-    def forward(self, stats=None, accumulate: bool = False, stream=None):
+    def forward(self, stats=None, accumulate: bool = False, stream=None, median: bool = False):
+        """Forward compositing; ``median`` also renders the median depth
+        (self.median_depth) and its entry index (self.median_contrib)."""
         h, ma, mw = (None, None, None) if stats is None else stats
         cfg = self._cfg(accumulate)
+        md = mc = None
+        if median:
+            if getattr(self, "median_depth", None) is None:
+                P = max(self.views.P, 1)
+                self.median_depth = torch.zeros(P, dtype=torch.float32, device=self.device)
+                self.median_contrib = torch.zeros(P, dtype=torch.int32, device=self.device)
+            md, mc = self.median_depth, self.median_contrib
         call("sr_render_forward", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.color), _ptr(self.alpha), _ptr(self.depth), _ptr(self.normal), _ptr(self.dist),
-             _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw), _stream(stream))
+             _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw), _ptr(md), _ptr(mc),
+             _stream(stream))
 
     def _grad_rec(self):
         if self.grad_rec is None:
@@ -184,11 +194,21 @@ class Rasterizer:
                                         dtype=torch.float32, device=self.device)
         return self.grad_rec
 
-    def backward_raster(self, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None):
+    def _median_contrib(self, dM):
+        if dM is None:
+            return None
+        if getattr(self, "median_contrib", None) is None:
+            raise ValueError("a median-depth gradient needs a forward with median=True")
+        return self.median_contrib
+
+    def backward_raster(self, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None, dM=None):
+        """Compositing backward; ``dM`` is the gradient of the median depth
+        (after a forward with median=True)."""
         call("sr_backward_raster", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.alpha), _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib),
-             _ptr(dC), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._grad_rec()), _stream(stream))
+             _ptr(dC), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._median_contrib(dM)), _ptr(dM),
+             _ptr(self._grad_rec()), _stream(stream))
 
     def backward_project(self, p: Params, grads: Params, stream=None, densify=None):
         """Projection backward; ``densify`` = (grad_sum float32 [N], count
@@ -200,19 +220,21 @@ class Rasterizer:
              _ptr(grads.scales), _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _ptr(dg), _ptr(dc),
              _stream(stream))
 
-    def backward(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None):
+    def backward(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None,
+                 dM=None):
         """Both halves of the backward; the parameter gradients are added to."""
-        self.backward_raster(dC, dA, dD, dN, dS, stream)
+        self.backward_raster(dC, dA, dD, dN, dS, stream, dM)
         self.backward_project(p, grads, stream)
 
     def backward_combined(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None,
-                          stream=None):
+                          stream=None, dM=None):
         """The single-call form (sr_render_backward)."""
         call("sr_render_backward", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.opac), _ptr(p.sh),
              _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(self.alpha),
              _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(dC), _ptr(dA),
-             _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._grad_rec()), _ptr(grads.means), _ptr(grads.scales),
+             _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._median_contrib(dM)), _ptr(dM), _ptr(self._grad_rec()),
+             _ptr(grads.means), _ptr(grads.scales),
              _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _stream(stream))
 
     def loss(self, mask: torch.Tensor, target: Optional[torch.Tensor], gamma: float = 0.5, w_c: float = 1.0,
@@ -224,16 +246,20 @@ class Rasterizer:
         return self.loss_out
 
     def regularizer_loss(self, w_dist: float, w_normal: float, dL_dalpha: torch.Tensor, dL_ddepth: torch.Tensor,
-                         dL_dnormal: torch.Tensor, dL_ddist: torch.Tensor, stream=None):
+                         dL_dnormal: torch.Tensor, dL_ddist: torch.Tensor, stream=None,
+                         dL_dmedian: Optional[torch.Tensor] = None):
         """The 2DGS terms of Eq. 3 on the current forward outputs (sr_regularizer_loss):
         returns loss [2V+1] (L_d per view, L_n per view, weighted total);
-        dL_dalpha is added to, the other gradients are overwritten."""
+        dL_dalpha is added to, the other gradients are overwritten.  With
+        ``dL_dmedian`` the normal term uses the median depth of the last
+        forward (median=True) and its gradient is written there."""
         if getattr(self, "reg_out", None) is None:
             self.reg_out = torch.zeros(2 * self.views.V + 1, dtype=torch.float32, device=self.device)
+        med = None if dL_dmedian is None else self.median_depth
         call("sr_regularizer_loss", self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.alpha),
-             _ptr(self.depth), _ptr(self.normal), _ptr(self.dist), float(w_dist), float(w_normal),
+             _ptr(self.depth), _ptr(self.normal), _ptr(self.dist), _ptr(med), float(w_dist), float(w_normal),
              _ptr(self.loss_ws), self.loss_ws.numel(), _ptr(self.reg_out), _ptr(dL_dalpha), _ptr(dL_ddepth),
-             _ptr(dL_dnormal), _ptr(dL_ddist), _stream(stream))
+             _ptr(dL_dnormal), _ptr(dL_ddist), _ptr(dL_dmedian), _stream(stream))
         return self.reg_out
 
     def ssim_loss(self, mask: torch.Tensor, target: torch.Tensor, w_s: float = 0.2,
@@ -344,36 +370,42 @@ def prune_mask(max_alpha: torch.Tensor, tau: float = ALPHA_MIN, stream=None) -> 
 
 class SurfelRasterize(torch.autograd.Function):
     """(means, scales, quats, opac, sh) -> packed (color [3P], alpha [P],
-    depth [P], normal [3P], dist [P]) for the views of ``rast``.  The
-    rasterizer's buffers hold the saved state: call backward before the next
-    forward through the same Rasterizer."""
+    depth [P], normal [3P], dist [P]) for the views of ``rast``, and with
+    ``median`` also the median depth [P].  The rasterizer's buffers hold the
+    saved state: call backward before the next forward through the same
+    Rasterizer."""
 
     @staticmethod
-    def forward(ctx, means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True):
+    def forward(ctx, means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True, median: bool = False):
         p = Params(means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                    opac.detach().contiguous(), sh.detach().contiguous())
         rast.preprocess(p)
         rast.bin()
         if check:
             rast.check_capacity()
-        rast.forward()
+        rast.forward(median=median)
         ctx.rast = rast
         ctx.p = p
-        return (rast.color.clone(), rast.alpha.clone(), rast.depth.clone(), rast.normal.clone(),
-                rast.dist.clone())
+        ctx.median = median
+        out = (rast.color.clone(), rast.alpha.clone(), rast.depth.clone(), rast.normal.clone(), rast.dist.clone())
+        if median:
+            out = out + (rast.median_depth[: rast.views.P].clone(),)
+        return out
 
     @staticmethod
-    def backward(ctx, gC, gA, gD, gN, gS):
+    def backward(ctx, gC, gA, gD, gN, gS, gM=None):
         p, rast = ctx.p, ctx.rast
         g = Params(torch.zeros_like(p.means), torch.zeros_like(p.scales), torch.zeros_like(p.quats),
                    torch.zeros_like(p.opac), torch.zeros_like(p.sh))
         c = lambda t: None if t is None else t.contiguous()
-        rast.backward(p, g, c(gC), c(gA), c(gD), c(gN), c(gS))
-        return g.means, g.scales, g.quats, g.opac, g.sh, None, None
+        rast.backward(p, g, c(gC), c(gA), c(gD), c(gN), c(gS), dM=c(gM) if ctx.median else None)
+        return g.means, g.scales, g.quats, g.opac, g.sh, None, None, None
 
 
-def rasterize(means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True):
-    return SurfelRasterize.apply(means, scales, quats, opac, sh, rast, check)
+def rasterize(means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True, median: bool = False):
+    """Differentiable rasterization; ``median`` adds the median depth as a
+    sixth output."""
+    return SurfelRasterize.apply(means, scales, quats, opac, sh, rast, check, median)
 
 
 class BackgroundLoss(torch.autograd.Function):
@@ -402,24 +434,31 @@ class BackgroundLoss(torch.autograd.Function):
 class RegularizerLoss(torch.autograd.Function):
     """The 2DGS terms of Eq. 3 (sr_regularizer_loss) of all views: returns
     (1/V) sum_v (w_dist L_d,v + w_normal L_n,v) and the per-view terms
-    [L_d,0..V-1, L_n,0..V-1]."""
+    [L_d,0..V-1, L_n,0..V-1].  With ``median`` (the median depth [P]) the
+    normal term takes its surface depth from that map instead of D / A."""
 
     @staticmethod
-    def forward(ctx, alpha, depth, normal, dist, views: ViewBatch, w_dist: float, w_normal: float, ws):
+    def forward(ctx, alpha, depth, normal, dist, views: ViewBatch, w_dist: float, w_normal: float, ws,
+                median=None):
         V = views.V
         loss = torch.zeros(2 * V + 1, dtype=torch.float32, device=alpha.device)
         dA = torch.zeros_like(alpha)
         dD, dN, dS = torch.empty_like(depth), torch.empty_like(normal), torch.empty_like(dist)
+        med = None if median is None else median.contiguous()
+        dM = None if median is None else torch.empty_like(med)
         call("sr_regularizer_loss", V, views.host_ptr, _ptr(views.dev), _ptr(alpha.contiguous()),
-             _ptr(depth.contiguous()), _ptr(normal.contiguous()), _ptr(dist.contiguous()), float(w_dist),
-             float(w_normal), _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _stream())
-        ctx.save_for_backward(dA, dD, dN, dS)
+             _ptr(depth.contiguous()), _ptr(normal.contiguous()), _ptr(dist.contiguous()), _ptr(med),
+             float(w_dist), float(w_normal), _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN),
+             _ptr(dS), _ptr(dM), _stream())
+        ctx.save_for_backward(dA, dD, dN, dS, dM if dM is not None else torch.zeros(0, device=alpha.device))
+        ctx.has_m = dM is not None
         return loss[2 * V], loss[: 2 * V]
 
     @staticmethod
     def backward(ctx, g_total, g_loss):
-        dA, dD, dN, dS = ctx.saved_tensors
-        return dA * g_total, dD * g_total, dN * g_total, dS * g_total, None, None, None, None
+        dA, dD, dN, dS, dM = ctx.saved_tensors
+        return (dA * g_total, dD * g_total, dN * g_total, dS * g_total, None, None, None, None,
+                (dM * g_total) if ctx.has_m else None)
 
 
 class SsimLoss(torch.autograd.Function):

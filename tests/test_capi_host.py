@@ -83,27 +83,39 @@ def test_argument_errors_before_launch(lib):
     counters = ctypes.c_void_p(8)
     assert l.sr_bin_and_sort(ctypes.byref(cfg), 10, 0, None, None, None, None, None, None, 0, 100, None, None,
                              None, counters, None) == lib.SR_ERR_ARG
+    # the median depth and its entry index go together, and its gradient needs the index
+    md = ctypes.c_void_p(256)
+    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, None, None) == lib.SR_ERR_ARG
+    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, md, None) == lib.SR_OK
+    assert l.sr_backward_raster(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), None, md, None,
+                                None) == lib.SR_ERR_ARG
+    assert l.sr_render_backward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 19), None, md, None,
+                                *([None] * 6)) == lib.SR_ERR_ARG
 
 
 def test_regularizer_loss_arguments(lib):
     """sr_regularizer_loss: V = 0 is a no-op; missing buffers, unlaid-out or
-    empty views and a small workspace are argument errors (host checks only)."""
+    empty views, a small workspace and a median map without its gradient
+    buffer are argument errors (host checks only)."""
     l = lib.lib()
-    assert l.sr_regularizer_loss(0, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None, None,
-                                 None, None) == lib.SR_OK
-    assert l.sr_regularizer_loss(-1, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None, None,
-                                 None, None) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(0, None, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None,
+                                 None, None, None, None) == lib.SR_OK
+    assert l.sr_regularizer_loss(-1, None, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None,
+                                 None, None, None, None) == lib.SR_ERR_ARG
     cams = (lib.SrCamera * 2)()
     for c, (w, h) in zip(cams, [(5, 4), (3, 3)]):
         c.width, c.height, c.fx, c.fy = w, h, 10.0, 10.0
     cams[1].pix_offset = 20
     p = ctypes.c_void_p(256)    # never dereferenced: the checks fail first
-    args = lambda ws: (2, ctypes.cast(cams, ctypes.c_void_p), p, p, p, p, p, 1.0, 1.0, p, ws, p, p, p, p, p, None)
+    args = lambda ws, med=None, dmed=None: (2, ctypes.cast(cams, ctypes.c_void_p), p, p, p, p, p, med, 1.0, 1.0, p,
+                                            ws, p, p, p, p, p, dmed, None)
     n = ctypes.c_size_t()
     assert l.sr_loss_workspace_size(2, ctypes.cast(cams, ctypes.c_void_p), ctypes.byref(n)) == lib.SR_OK
     assert l.sr_regularizer_loss(*args(n.value - 1)) == lib.SR_ERR_ARG
-    assert l.sr_regularizer_loss(2, ctypes.cast(cams, ctypes.c_void_p), p, None, p, p, p, 1.0, 1.0, p, n.value, p, p,
-                                 p, p, p, None) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(2, ctypes.cast(cams, ctypes.c_void_p), p, None, p, p, p, None, 1.0, 1.0, p, n.value,
+                                 p, p, p, p, p, None, None) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(*args(n.value, med=p)) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(*args(n.value, dmed=p)) == lib.SR_ERR_ARG
     cams[1].pix_offset = 19
     assert l.sr_regularizer_loss(*args(n.value)) == lib.SR_ERR_ARG
     cams[1].pix_offset = 20

@@ -1,0 +1,279 @@
+"""Median depth (the 2DGS surface depth: the depth of the last blended entry
+that starts with transmittance above 1/2), the alternative surface of the
+normal consistency term of Eq. 3: forward values and entry ids against the
+oracle, its backward alone, the regulariser epilogue on median maps, and the
+whole Eq. 3 in that variant through the rasterizer to the surfel
+parameters."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.render import Params64, render_pixels
+from paper_2501_08174_amd import _lib, scenes
+from paper_2501_08174_amd.raster import (BackgroundLoss, Params, Rasterizer, RegularizerLoss, ViewBatch, _ptr,
+                                         _stream, rasterize)
+from tests.gpu_helpers import FWD_TOL, crop_pixels, geometry, gpu_run, per_view
+from tests.test_gpu_regularizers import _flat, _maps, _wall_scene
+
+pytestmark = pytest.mark.gpu
+
+RP = oracle.RasterParams()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _full(cam):
+    return crop_pixels(0, 0, cam.width, cam.height)
+
+
+def _ragged_scene(seed=51, n=300, deg=0):
+    return scenes.make_random_scene(seed, n, n_views=3, width=[61, 40, 17], height=[37, 64, 90],
+                                    sh_degree=deg, scale_range=(0.02, 0.3))
+
+
+def _median_gids(rast, v, pix):
+    """Surfel id of the median entry of every pixel (-1 without one), from
+    median_contrib and the sorted tile lists."""
+    views = rast.views
+    W, H = views.sizes[v]
+    o = views.pix_offsets[v]
+    i, j = pix[:, 0], pix[:, 1]
+    tw, th = views.tile
+    tile = int(views.host[v].tile_offset) + (j // th) * int(views.host[v].tiles_x) + (i // tw)
+    rg = rast.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    vals = rast.vals.cpu().numpy().view(np.uint32).astype(np.int64)
+    mc = rast.median_contrib[o: o + W * H].cpu().numpy().view(np.uint32).reshape(H, W)[j, i].astype(np.int64)
+    gid = np.where(mc > 0, vals[np.minimum(rg[tile, 0] + np.maximum(mc - 1, 0), vals.size - 1)], -1)
+    md = rast.median_depth[o: o + W * H].cpu().numpy().reshape(H, W)[j, i]
+    return gid, md, mc
+
+
+@pytest.mark.parametrize("make", [_ragged_scene, _wall_scene])
+def test_median_forward_matches_oracle(make):
+    sc = make()
+    run = gpu_run(sc)
+    rast = run["rast"]
+    base = [per_view(rast, v) for v in range(sc.v)]
+    rast.forward(median=True)
+    torch.cuda.synchronize()
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree)
+    n_pix = n_flag = n_med = 0
+    for v, cam in enumerate(sc.cams):
+        # the median outputs leave every other forward output bit for bit as it was
+        got = per_view(rast, v)
+        for k in base[v]:
+            np.testing.assert_array_equal(got[k], base[v][k], err_msg=f"view {v} {k}")
+        pix = _full(cam)
+        res = render_pixels(P64, cam, geoms[v], pix, RP)
+        gid, md, mc = _median_gids(rast, v, pix)
+        flag = res["flag_cut"] | res["flag_term"] | res["flag_branch"] | res["flag_median"]
+        ok = ~flag
+        mism = (gid != res["median_gid"]) & ok
+        assert not mism.any(), f"view {v}: {mism.sum()} pixels with a different median entry"
+        err = np.abs(md - res["median_depth"])[ok]
+        assert err.max(initial=0.0) <= FWD_TOL, (v, float(err.max()))
+        # no median entry: depth 0 and index 0; else the index is within the blended prefix
+        assert np.all(md[mc == 0] == 0.0)
+        nc = got["n_contrib"][pix[:, 1], pix[:, 0]].astype(np.int64)
+        assert np.all(mc <= nc)
+        assert np.all((mc > 0) == (nc > 0))        # the first blended entry starts with T = 1
+        n_pix += pix.shape[0]
+        n_flag += int(flag.sum())
+        n_med += int((mc > 0).sum())
+    print(f"pixels {n_pix}, with a median entry {n_med}, flagged {n_flag}")
+    assert n_med > 0.3 * n_pix and n_flag < 0.02 * n_pix
+
+
+def test_median_backward_alone_matches_oracle():
+    """The gradient of sum_p w(p) median(p) alone reaches only the depth of
+    each pixel's median entry."""
+    sc = scenes.make_random_scene(53, 150, n_views=2, width=[48, 37], height=[40, 51], spread=0.6,
+                                  scale_range=(0.03, 0.3))
+    rng = np.random.default_rng(9)
+    views = ViewBatch(sc.cams)
+    rast = Rasterizer(sc.n, views, 0, sh_stride=1)
+    p = Params.from_scene(sc)
+    rast.plan_capacity(p)
+    leaves = [t.clone().requires_grad_(True) for t in (p.means, p.scales, p.quats, p.opac, p.sh)]
+    outs = rasterize(*leaves, rast, median=True)
+    assert len(outs) == 6
+    wm = [rng.standard_normal(c.width * c.height) for c in sc.cams]
+    wt = torch.tensor(np.concatenate(wm), dtype=torch.float32, device="cuda")
+    (outs[5] * wt).sum().backward()
+    torch.cuda.synchronize()
+    g = [t.grad.cpu().numpy().astype(np.float64) for t in leaves]
+
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0, requires_grad=True)
+    excl = []
+    for v, cam in enumerate(sc.cams):
+        w = torch.tensor(wm[v])
+
+        def lf(out, rows, w=w):
+            return (out["median_depth"] * w[torch.as_tensor(rows)]).sum()
+        res = render_pixels(P64, cam, geoms[v], _full(cam), RP, loss_fn=lf)
+        excl.append(res["tie_ids"])
+        gid, _, _ = _median_gids(rast, v, _full(cam))
+        fl = res["flag_median"] | res["flag_cut"] | res["flag_term"] | res["flag_branch"]
+        excl.append(res["median_gid"][fl])
+        excl.append(gid[fl])
+    gref = [np.zeros_like(a) if b is None else b for a, b in zip(g, P64.grads())]   # None: no dependence
+    excl = np.unique(np.concatenate(excl)).astype(np.int64)
+    excl = excl[excl >= 0]
+    print("excluded surfels:", len(excl))
+    keep = np.ones(sc.n, bool)
+    keep[excl] = False
+    gm = np.abs(gref[0][keep]).max()
+    for name, a, b in zip(("means", "scales", "quats", "opac", "sh"), g, gref):
+        a, b = a[keep].reshape(-1), b[keep].reshape(-1)
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+        print(f"{name}: inf-norm relative error {err:.2e}, ref scale {np.abs(b).max():.2e}, "
+              f"largest {np.abs(a).max():.2e}")
+        if name in ("opac", "sh"):
+            # the median depth depends on neither the opacity (a piecewise
+            # constant choice) nor the colour
+            assert np.abs(a).max() == 0.0, name
+        elif name == "scales":
+            # nor on the extent of the surfel: the depth where the ray meets
+            # the surfel's plane is fixed by its centre and rotation, so the
+            # exact gradient is zero and the float32 one is cancellation
+            # noise, bounded against the means gradient (same units)
+            assert np.abs(b).max() <= 1e-9 * gm
+            assert np.abs(a).max() <= 2e-5 * gm, np.abs(a).max() / gm
+        else:
+            assert err <= 1e-3, (name, err)
+
+
+def test_regularizer_epilogue_median_matches_oracle():
+    cams = [scenes.make_camera(np.eye(3), np.zeros(3), w, h) for w, h in [(29, 21), (16, 9), (4, 3), (2, 2)]]
+    views = ViewBatch(cams)
+    A, D, N, S = _maps(cams, 6)
+    rng = np.random.default_rng(3)
+    M = []
+    for c in cams:
+        H, W = c.height, c.width
+        jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        m = (2.5 + 0.3 * np.cos(0.2 * ii) + 0.2 * np.sin(0.3 * jj + 0.4)
+             + 0.01 * rng.standard_normal((H, W))).astype(np.float32)
+        if H * W > 20:
+            m.reshape(-1)[rng.choice(H * W, 4, replace=False)] = 0.0    # pixels without a median entry
+        M.append(m)
+    wd, wn = 100.0, 0.05
+    ws = torch.zeros(_lib.workspace_bytes_loss(views.V, views.host), dtype=torch.uint8, device="cuda")
+    ta, td, tn, ts, tm = _flat(A), _flat(D), _flat(N), _flat(S), _flat(M)
+    loss = torch.zeros(2 * views.V + 1, device="cuda")
+    # dL_dalpha is added to; here it is the constant w_normal / (H W V), so
+    # the prior contents are kept small for the difference to stay exact
+    pre = 1e-5 * torch.rand(views.P, device="cuda")
+    dA = pre.clone()
+    dD, dN, dS, dM = torch.empty_like(td), torch.empty_like(tn), torch.empty_like(ts), torch.empty_like(tm)
+    _lib.call("sr_regularizer_loss", views.V, views.host_ptr, _ptr(views.dev), _ptr(ta), _ptr(td), _ptr(tn),
+              _ptr(ts), _ptr(tm), wd, wn, _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS),
+              _ptr(dM), _stream())
+    torch.cuda.synchronize()
+    ref = oracle.regularizer_loss64(A, D, N, S, cams, wd, wn, medians=M)
+    loss = loss.cpu().numpy()
+    V = views.V
+    for v in range(V):
+        L_d, L_n = ref["per_view"][v]
+        assert abs(loss[v] - L_d) <= 1e-5 * abs(L_d) + 1e-7, (v, loss[v], L_d)
+        assert abs(loss[V + v] - L_n) <= 1e-5 * abs(L_n) + 1e-7, (v, loss[V + v], L_n)
+    assert abs(loss[2 * V] - ref["total"]) <= 1e-5 * abs(ref["total"])
+    dA = (dA - pre).cpu().numpy(); dD = dD.cpu().numpy(); dN = dN.cpu().numpy(); dS = dS.cpu().numpy()
+    dM = dM.cpu().numpy()
+    for v, c in enumerate(cams):
+        o, n = views.pix_offsets[v], c.width * c.height
+        g = ref["grads"][v]
+        got = {"alpha": dA[o:o + n], "depth": dD[o:o + n], "dist": dS[o:o + n], "normal": dN[3 * o:3 * (o + n)],
+               "median": dM[o:o + n]}
+        for k in got:
+            a, b = got[k].astype(np.float64), g[k].reshape(-1)
+            scale = np.abs(b).max()
+            if scale == 0.0:
+                assert np.abs(a).max() == 0.0, (v, k)
+                continue
+            err = np.abs(a - b).max() / scale
+            assert err <= 2e-4, (v, k, err)
+        assert np.all(got["depth"] == 0.0)          # the surface no longer depends on D
+
+
+def test_eq3_median_variant_parameter_gradients_match_oracle():
+    sc = _wall_scene()
+    gamma, w_c, wd, wn = 0.5, 1.0, 10.0, 0.05
+    views = ViewBatch(sc.cams)
+    rast = Rasterizer(sc.n, views, 0, sh_stride=1)
+    p = Params.from_scene(sc)
+    rast.plan_capacity(p)
+    leaves = [t.clone().requires_grad_(True) for t in (p.means, p.scales, p.quats, p.opac, p.sh)]
+    color, alpha, depth, normal, dist, med = rasterize(*leaves, rast, median=True)
+    mask = torch.tensor(np.concatenate([m.reshape(-1) for m in sc.masks]), device="cuda")
+    target = torch.tensor(np.concatenate([t.reshape(-1) for t in sc.targets]), device="cuda")
+    ws = torch.zeros(_lib.workspace_bytes_loss(views.V, views.host), dtype=torch.uint8, device="cuda")
+    l_bg, _ = BackgroundLoss.apply(alpha, color, target, mask, views, gamma, w_c, ws)
+    ws2 = torch.zeros_like(ws)
+    l_reg, per = RegularizerLoss.apply(alpha, depth, normal, dist, views, wd, wn, ws2, med)
+    (l_bg + l_reg).backward()
+    torch.cuda.synchronize()
+    g_gpu = [t.grad.cpu().numpy().astype(np.float64) for t in leaves]
+    per = per.detach().cpu().numpy()
+
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0, requires_grad=True)
+    V = sc.v
+    maps, excl, n_med_flag = [], [], []
+    for v, cam in enumerate(sc.cams):
+        pix = _full(cam)
+        res = render_pixels(P64, cam, geoms[v], pix, RP)
+        H, W = cam.height, cam.width
+        maps.append({"color": res["color"].T.reshape(3, H, W), "alpha": res["alpha"].reshape(H, W),
+                     "depth": res["depth"].reshape(H, W), "normal": res["normal"].T.reshape(3, H, W),
+                     "dist": res["dist"].reshape(H, W), "median_depth": res["median_depth"].reshape(H, W)})
+        excl.append(res["tie_ids"])
+        gid, _, _ = _median_gids(rast, v, pix)
+        fl = res["flag_median"]
+        excl.append(res["median_gid"][fl])
+        excl.append(gid[fl])
+        n_med_flag.append(int(fl.sum()))
+    print("pixels with a median tie per view:", n_med_flag)
+    wts = []
+    for v, cam in enumerate(sc.cams):
+        t = {k: torch.tensor(a, requires_grad=True) for k, a in maps[v].items()}
+        m = torch.tensor(sc.masks[v])
+        L = (w_c * oracle.masked_l1_64(t["color"], torch.tensor(sc.targets[v], dtype=torch.float64), m) +
+             gamma * oracle.background_loss64(t["alpha"], m))
+        L_d, L_n = oracle.regularizers.regularizer_view64(t["alpha"], t["depth"], t["normal"], t["dist"], cam,
+                                                          median=t["median_depth"])
+        if n_med_flag[v] == 0:
+            assert abs(per[V + v] - float(L_n)) <= 1e-4 * abs(float(L_n)) + 1e-6, (v, per[V + v], float(L_n))
+        ((L + wd * L_d + wn * L_n) / V).backward()
+        wts.append({k: (x.grad.numpy() if x.grad is not None else np.zeros(x.shape)) for k, x in t.items()})
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0, requires_grad=True)
+    for v, cam in enumerate(sc.cams):
+        H, W = cam.height, cam.width
+        w = {"c": torch.tensor(wts[v]["color"].reshape(3, -1).T), "a": torch.tensor(wts[v]["alpha"].reshape(-1)),
+             "d": torch.tensor(wts[v]["depth"].reshape(-1)), "n": torch.tensor(wts[v]["normal"].reshape(3, -1).T),
+             "s": torch.tensor(wts[v]["dist"].reshape(-1)), "m": torch.tensor(wts[v]["median_depth"].reshape(-1))}
+
+        def lf(out, rows, w=w):
+            r = torch.as_tensor(rows)
+            return ((out["color"] * w["c"][r]).sum() + (out["alpha"] * w["a"][r]).sum() +
+                    (out["depth"] * w["d"][r]).sum() + (out["normal"] * w["n"][r]).sum() +
+                    (out["dist"] * w["s"][r]).sum() + (out["median_depth"] * w["m"][r]).sum())
+        render_pixels(P64, cam, geoms[v], _full(cam), RP, loss_fn=lf)
+    g_ref = P64.grads()
+    excl = np.unique(np.concatenate(excl)).astype(np.int64)
+    excl = excl[excl >= 0]
+    print("excluded surfels (tie decisions, median ties):", len(excl))
+    for name, a, b in zip(("means", "scales", "quats", "opac", "sh"), g_gpu, g_ref):
+        keep = np.ones(a.shape[0], bool)
+        keep[excl] = False
+        a, b = a[keep].reshape(-1), b[keep].reshape(-1)
+        err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+        print(f"{name}: inf-norm relative error {err:.2e}")
+        assert err <= 2e-3, (name, err)

@@ -62,7 +62,8 @@ def test_regularizer_epilogue_matches_oracle():
     dD, dN, dS = torch.empty_like(td), torch.empty_like(tn), torch.empty_like(ts)
     from paper_2501_08174_amd.raster import _ptr, _stream
     _lib.call("sr_regularizer_loss", views.V, views.host_ptr, _ptr(views.dev), _ptr(ta), _ptr(td), _ptr(tn),
-              _ptr(ts), wd, wn, _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _stream())
+              _ptr(ts), None, wd, wn, _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), None,
+              _stream())
     torch.cuda.synchronize()
     ref = oracle.regularizer_loss64(A, D, N, S, cams, wd, wn)
     loss = loss.cpu().numpy()
