@@ -251,8 +251,8 @@ def main():
     }
 
     # work accounting for the roofline (outside the timed region)
-    R, B, WS, WB = pipe.rast.count_pairs(waves=True)
-    R_bwd = int(pipe.rast.n_contrib[:P].to(torch.int64).sum().item())
+    R, B, WS, WB, R_bwd = pipe.rast.count_pairs(waves=True)
+    upto_last = int(pipe.rast.n_contrib[:P].to(torch.int64).sum().item())
     mean_ms = dict(zip(Pipeline.STAGES, stage_ms.mean(axis=0)))
     fwd_ops = FWD_OPS_BLEND * B + FWD_OPS_SKIP * (R - B)
     bwd_ops = BWD_OPS_BLEND * B + BWD_OPS_SKIP * max(R_bwd - B, 0)
@@ -264,6 +264,7 @@ def main():
                           "kernel": "k_train_raster (fused forward + loss + backward compositing)",
                           "ops_per_launch": ops}
     result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd,
+                             "list_entries_up_to_last": upto_last,
                              "forward_wave_steps": WS, "forward_wave_steps_blending": WB})
 
     if not args.no_unfused:

@@ -107,8 +107,12 @@ sr_status sr_layout_views(sr_camera *cams_host, int32_t V, int32_t tile_w, int32
  * contribute to; one outside is disqualified).
  * For every (view v, surfel g), record index r = v*N + g:
  *   geom  [V*N, 16]  inverse splat homography, centre, opacity, depth row
- *   app   [V*N, 8]   colour and camera-space normal (NULL: skip shading,
- *                    e.g. for the pruning pass; sh may then be NULL)
+ *   app   [V*N, 8]   colour, camera-space normal and the pixel rectangle
+ *                    packed as two uint32 (x_lo | x_hi << 16, y_lo |
+ *                    y_hi << 16; the compositing skips an entry for a
+ *                    64-pixel wave whose pixels its rectangle misses)
+ *                    (NULL: skip shading, e.g. for the pruning pass; sh may
+ *                    then be NULL)
  *   rect  [V*N, 4]   uint16 pixel rectangle [x_lo, x_hi, y_lo, y_hi]
  *   tiles_touched [V*N] number of tiles of the rectangle (0 when culled)
  *   depth_key [V*N]  bits of float32(centre depth); 0xFFFFFFFF when culled
@@ -319,12 +323,15 @@ sr_status sr_prune_contrib(const sr_config *cfg, int32_t N, int32_t V, const sr_
 /* Work accounting of the compositing (no outputs): counts[0] = pairs
  * (pixel, tile-list entry) tested before the pixel terminated, counts[1] =
  * pairs blended, counts[2] = (64-pixel wave, entry) steps taken, counts[3] =
- * those steps in which at least one pixel of the wave blends; uint64 [4],
- * overwritten.  The same decisions as sr_render_forward; used to express
- * throughput as a fraction of the VALU roofline. */
+ * those steps in which at least one pixel of the wave blends, counts[4] =
+ * pairs tested up to and including each pixel's last blended entry (the
+ * pairs its backward revisits); uint64 [5], overwritten.  Entries whose
+ * pixel rectangle misses all pixels of a wave are skipped by that wave and
+ * not counted.  The same decisions as sr_render_forward (app as given to
+ * it); used to express throughput as a fraction of the VALU roofline. */
 sr_status sr_render_count(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
-                          const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
-                          const uint32_t *ranges, uint64_t *counts, void *stream);
+                          const sr_camera *cams_dev, const float *geom, const float *app,
+                          const uint32_t *vals, const uint32_t *ranges, uint64_t *counts, void *stream);
 
 /* The pruning pass for 3D Gaussians (Appendix B: Section 4.3's statistics
  * for 3DGS).  sr_preprocess_3d: per (view, Gaussian) the EWA projection

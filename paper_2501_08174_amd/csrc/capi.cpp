@@ -533,17 +533,17 @@ sr_status sr_train_step_raster(const sr_config* cfg, int32_t N, int32_t V, const
 }
 
 sr_status sr_render_count(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
-                          const sr_camera* cams_dev, const float* geom, const uint32_t* vals, const uint32_t* ranges,
-                          uint64_t* counts, void* stream) {
+                          const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
+                          const uint32_t* ranges, uint64_t* counts, void* stream) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
     int total_tiles = 0;
     SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr));
     SR_NEED(counts);
-    if (total_tiles > 0) { SR_NEED(geom); SR_NEED(vals); SR_NEED(ranges); }
+    if (total_tiles > 0) { SR_NEED(geom); SR_NEED(app); SR_NEED(vals); SR_NEED(ranges); }
     hipStream_t s = (hipStream_t)stream;
-    SR_TRY(hip_status(sr::fill_f32((float*)counts, 0.f, 8, s), "clear counts"));
-    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, vals, ranges, nullptr,
+    SR_TRY(hip_status(sr::fill_f32((float*)counts, 0.f, 10, s), "clear counts"));
+    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                             nullptr, (unsigned long long*)counts, nullptr, nullptr, s),
                       "sr_render_count");

@@ -251,7 +251,11 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0f ? rgb[ch] : 0.0f;
         app[2 * r + 0] = make_float4(rgb[0], rgb[1], rgb[2], (float)nc[0]);
-        app[2 * r + 1] = make_float4((float)nc[1], (float)nc[2], 0.0f, 0.0f);
+        // the pixel rectangle packed in the last two slots (column and row
+        // ranges): the compositing skips, per wave, entries whose rectangle
+        // misses the wave's pixels
+        app[2 * r + 1] = make_float4((float)nc[1], (float)nc[2], __uint_as_float((uint32_t)ilo | ((uint32_t)ihi << 16)),
+                                     __uint_as_float((uint32_t)jlo | ((uint32_t)jhi << 16)));
     }
 }
 

@@ -20,9 +20,11 @@ namespace sr {
 
 namespace {
 
-// Global tile id of this workgroup; pixel coordinates of this thread.
+// Global tile id of this workgroup; pixel coordinates of this thread; the
+// pixel box [wx0, wx1] x [wy0, wy1] of this thread's wave (wave-uniform).
 struct TileCtx {
     int tile, v, W, H, ix, iy;
+    int wx0, wx1, wy0, wy1, tx0, ty0;
     bool inside;
     int64_t pix_off;
     uint32_t start, n;
@@ -42,6 +44,14 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
     t.H = c.height;
     t.ix = tx * TW + (int)(threadIdx.x % TW);
     t.iy = ty * TH + (int)(threadIdx.x / TW);
+    // row-major lanes: the wave's first and last lanes span its pixel box
+    const int first = (int)__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63;
+    t.wx0 = tx * TW + first % TW;
+    t.wy0 = ty * TH + first / TW;
+    t.wx1 = tx * TW + (first + 63) % TW;
+    t.wy1 = ty * TH + (first + 63) / TW;
+    t.tx0 = tx * TW;
+    t.ty0 = ty * TH;
     t.inside = t.ix < t.W && t.iy < t.H;
     t.pix_off = c.pix_offset;
     t.bg[0] = c.bg[0]; t.bg[1] = c.bg[1]; t.bg[2] = c.bg[2];
@@ -56,6 +66,106 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
 // with transmittance above 1/2) with the 1-based list index of that entry.
 constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8;
 
+// Per-wave culling.  Every wave of a tile covers whole rows of it (a band).
+// When an entry is staged, its thread works out which bands it can reach,
+// one bit per wave; each wave then tests 64 staged entries at once with one
+// ballot of its bit and walks only the set bits of that mask, so skipped
+// entries cost no per-entry instructions.  A band is reached when the
+// entry's pixel rectangle (packed in the last two slots of the appearance
+// record) meets it and the y-range, within the tile's columns, of the
+// entry's cutoff conic or of its low-pass disc meets the band's rows:
+//   surface  Q = (1 - tau)(w0^2 + w1^2) - 2 L (1 + tau) w2^2 <= 0 with
+//            w = A dx + B dy + C' (the pass test of eval_test with a relative
+//            slack tau): for an ellipse, Q(x, .) <= 0 is the interval between
+//            the roots of a quadratic in y, whose lower end is convex and
+//            upper end concave in x, so their extremes over the columns are
+//            at the ellipse's lowest and highest points clamped to the
+//            columns; any other conic reaches every band;
+//   disc     dx^2 + dy^2 <= L (1 + tau).
+// Float64, with a 1e-3 pixel margin on the columns and rows: an entry is
+// skipped only where the exact test fails by a relative margin, and forward
+// and backward skip the same entries.
+template <int TW, int NW>
+__device__ __forceinline__ uint32_t band_bits(const float4& g0, const float4& g1, const float4& g2, float Lf,
+                                              const float4& a1, int tx0, int ty0) {
+    static_assert(64 % TW == 0 && NW * (64 / TW) >= 1, "waves cover whole rows of the tile");
+    constexpr int RW = 64 / TW;                      // rows per wave
+    constexpr double tau = 1e-3, mg = 1e-3;
+    const uint32_t rx = __float_as_uint(a1.z), ry = __float_as_uint(a1.w);
+    const int ilo = (int)(rx & 0xffffu), ihi = (int)(rx >> 16), jlo = (int)(ry & 0xffffu), jhi = (int)(ry >> 16);
+    const int clo = ilo > tx0 ? ilo : tx0, chi = ihi < tx0 + TW - 1 ? ihi : tx0 + TW - 1;
+    if (clo > chi) return 0u;
+    const double cx = g2.y, cy = g2.z, L = Lf;
+    const double X0 = (clo + 0.5) - cx - mg, X1 = (chi + 0.5) - cx + mg;
+    // disc: |dy| <= hd
+    const double xd = fmin(fmax(0.0, X0), X1);
+    const double hd2 = L * (1.0 + tau) - xd * xd;
+    const double hd = hd2 >= 0.0 ? sqrt(hd2) : -1.0;
+    // surface: y-range [ylo, yhi] (empty when ylo > yhi)
+    double ylo = 1.0, yhi = -1.0;
+    const double s01 = 1.0 - tau, s2 = -2.0 * L * (1.0 + tau);
+    const double a0 = g0.x, a1x = g0.y, a2 = g0.z, b0 = g0.w, b1 = g1.x, b2 = g1.y, c0 = g1.z, c1 = g1.w,
+                 c2 = g2.x;
+    // Q = P x^2 + 2 R x y + S y^2 + 2 U x + 2 W y + K
+    const double P = s01 * (a0 * a0 + a1x * a1x) + s2 * (a2 * a2);
+    const double R = s01 * (a0 * b0 + a1x * b1) + s2 * (a2 * b2);
+    const double S = s01 * (b0 * b0 + b1 * b1) + s2 * (b2 * b2);
+    const double U = s01 * (a0 * c0 + a1x * c1) + s2 * (a2 * c2);
+    const double W = s01 * (b0 * c0 + b1 * c1) + s2 * (b2 * c2);
+    const double K = s01 * (c0 * c0 + c1 * c1) + s2 * (c2 * c2);
+    const double al = P * S - R * R;
+    if (!(P > 0.0 && S > 0.0 && al > 0.0)) {
+        ylo = -1e300;
+        yhi = 1e300;
+    } else {
+        // discriminant in y of Q(x, .): D(x) = -al x^2 + 2 be x + ga, >= 0 on the ellipse's columns
+        const double be = R * W - S * U, ga = W * W - S * K;
+        const double ex = be * be + al * ga;
+        if (ex >= 0.0) {
+            const double ia = 1.0 / al, sx = sqrt(ex);
+            const double xa = fmax(X0, (be - sx) * ia), xb = fmin(X1, (be + sx) * ia);
+            if (xa <= xb) {
+                // lowest and highest points: y roots of the discriminant in x, x on P x + R y + U = 0
+                const double bp = R * U - P * W, gp = U * U - P * K;
+                const double sy = sqrt(fmax(bp * bp + al * gp, 0.0));
+                const double iP = 1.0 / P, iS = 1.0 / S;
+                const double xbot = fmin(fmax(-(R * ((bp - sy) * ia) + U) * iP, xa), xb);
+                const double xtop = fmin(fmax(-(R * ((bp + sy) * ia) + U) * iP, xa), xb);
+                const double db = fmax((-al * xbot + 2.0 * be) * xbot + ga, 0.0);
+                const double dt = fmax((-al * xtop + 2.0 * be) * xtop + ga, 0.0);
+                ylo = (-(R * xbot + W) - sqrt(db)) * iS;
+                yhi = (-(R * xtop + W) + sqrt(dt)) * iS;
+            }
+        }
+    }
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int b = 0; b < NW; ++b) {
+        const int r0 = ty0 + b * RW, r1 = r0 + RW - 1;
+        const int lo = jlo > r0 ? jlo : r0, hi = jhi < r1 ? jhi : r1;
+        if (lo > hi) continue;
+        const double Y0 = (lo + 0.5) - cy - mg, Y1 = (hi + 0.5) - cy + mg;
+        const bool disc = hd >= 0.0 && Y0 <= hd && Y1 >= -hd;
+        const bool surf = ylo <= Y1 && yhi >= Y0;
+        if (disc || surf) bits |= 1u << b;
+    }
+    return bits;
+}
+
+// Mask of the entries of run c (of 64) whose band bit (kept in the last slot
+// of the staged appearance record) is set for this wave.
+__device__ __forceinline__ uint64_t wave_live_mask(const float4* __restrict__ a1, int c, int cnt) {
+    const int k = c * 64 + __lane_id();
+    const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6;
+    return ballot64(k < cnt && ((__float_as_uint(a1[k].w) >> w) & 1u));
+}
+
+// The first cnt - 64 c entries of run c, without culling.
+__device__ __forceinline__ uint64_t run_mask(int c, int cnt) {
+    const int n = cnt - c * 64;
+    return n >= 64 ? ~0ull : (n <= 0 ? 0ull : ((1ull << n) - 1ull));
+}
+
 // Per-pixel state at the end of the forward pass.
 struct PixFwd {
     float T, C0, C1, C2, N0, N1, N2, S0, S1, S2, zref, zmed;
@@ -66,7 +176,7 @@ struct PixFwd {
 template <int NT, int MODE>
 struct FwdSmem {
     float4 g[kGeomF4][NT];
-    float4 a[(MODE & kShade) ? kAppF4 : 1][(MODE & kShade) ? NT : 1];
+    float4 a[(MODE & (kShade | kCount)) ? kAppF4 : 1][(MODE & (kShade | kCount)) ? NT : 1];
     uint32_t id[(MODE & kStats) ? NT : 1];
 };
 
@@ -81,17 +191,20 @@ struct BwdSmem {
 };
 
 // Front to back over the tile list; every thread owns one pixel.
-template <int NT, int MODE>
+template <int TW, int NT, int MODE>
 __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, FwdSmem<NT, MODE>& sm, PixFwd& st,
                                          uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
                                          float* __restrict__ max_weight, uint64_t& n_reached, uint64_t& n_blended,
-                                         uint64_t& n_witer, uint64_t& n_wblend) {
+                                         uint64_t& n_witer, uint64_t& n_wblend, uint64_t& n_upto_last) {
     constexpr bool SHADE = (MODE & kShade) != 0;
     constexpr bool STATS = (MODE & kStats) != 0;
     constexpr bool COUNT = (MODE & kCount) != 0;
     constexpr bool MEDIAN = (MODE & kMedian) != 0;
+    // the appearance records (with the pixel rectangles) are staged: cull per wave
+    constexpr bool CULL = SHADE || COUNT;
+    uint32_t n_eval = 0, n_eval_last = 0;     // COUNT: entries tested by this pixel, up to its last blend
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     st.T = 1.0f;
@@ -105,24 +218,37 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
         if (j < t.n) {
             const uint32_t g = vals[t.start + j];
             const size_t r = (size_t)t.v * N + g;
+            float4 gq[kGeomF4];
 #pragma unroll
-            for (int q = 0; q < kGeomF4; ++q) sm.g[q][tid] = geom[kGeomF4 * r + q];
-            if (SHADE) {
-#pragma unroll
-                for (int q = 0; q < kAppF4; ++q) sm.a[q][tid] = app[kAppF4 * r + q];
+            for (int q = 0; q < kGeomF4; ++q) {
+                gq[q] = geom[kGeomF4 * r + q];
+                sm.g[q][tid] = gq[q];
+            }
+            if (CULL) {
+                const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
+                // the band bits replace the packed rectangle once it has served
+                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                sm.a[0][tid] = a0;
+                sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
             }
             if (STATS) sm.id[tid] = g;
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, t.n - base);
         if (ballot64(!done) == 0ull) continue;
-        for (int k = 0; k < cnt; ++k) {
+        bool wave_done = false;
+        for (int c = 0; c * 64 < cnt && !wave_done; ++c) {
+          uint64_t live = CULL ? wave_live_mask(sm.a[1], c, cnt) : run_mask(c, cnt);
+          while (live != 0ull) {
+            const int k = c * 64 + (int)__builtin_ctzll(live);
+            live &= live - 1ull;
             PairEval e;
             const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
             eval_test(sm.g[0][k], sm.g[1][k], g2, g3, px, py, e);
             if (COUNT) {
                 n_reached += (uint64_t)__popcll(ballot64(!done));
                 n_witer += 1;
+                n_eval += done ? 0u : 1u;
             }
             bool blend = !done && e.pass;
             // no pixel of this wave takes the entry: nothing changes
@@ -157,6 +283,7 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 }
                 st.T = Tn;
                 st.last = base + (uint32_t)k + 1u;
+                if (COUNT) n_eval_last = n_eval;
             }
             if (COUNT) n_blended += (uint64_t)__popcll(ballot64(blend));
             if (STATS) {
@@ -170,9 +297,14 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                     }
                 }
             }
-            if (ballot64(!done) == 0ull) break;
+            if (ballot64(!done) == 0ull) {
+                wave_done = true;
+                break;
+            }
+          }
         }
     }
+    if (COUNT) n_upto_last += n_eval_last;
 }
 
 // Forward outputs of one pixel from its final state.
@@ -231,14 +363,22 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     tile_ctx<TW, TH>(cams, V, ranges, t);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
-    uint64_t n_reached = 0, n_blended = 0, n_witer = 0, n_wblend = 0;
-    fwd_tile<NT, MODE>(t, px, py, N, geom, app, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached, n_blended,
-                       n_witer, n_wblend);
-    if ((MODE & kCount) && __lane_id() == 0) {
-        atomicAdd(&counts[0], (unsigned long long)n_reached);
-        atomicAdd(&counts[1], (unsigned long long)n_blended);
-        atomicAdd(&counts[2], (unsigned long long)n_witer);
-        atomicAdd(&counts[3], (unsigned long long)n_wblend);
+    uint64_t n_reached = 0, n_blended = 0, n_witer = 0, n_wblend = 0, n_upto = 0;
+    fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached,
+                           n_blended,
+                       n_witer, n_wblend, n_upto);
+    if (MODE & kCount) {
+        // per-pixel tally of the backward's pairs: summed over the wave first
+        uint64_t up = n_upto;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) up += (uint64_t)__shfl_xor((long long)up, off, 64);
+        if (__lane_id() == 0) {
+            atomicAdd(&counts[0], (unsigned long long)n_reached);
+            atomicAdd(&counts[1], (unsigned long long)n_blended);
+            atomicAdd(&counts[2], (unsigned long long)n_witer);
+            atomicAdd(&counts[3], (unsigned long long)n_wblend);
+            atomicAdd(&counts[4], (unsigned long long)up);
+        }
     }
     if ((MODE & kShade) && t.inside) write_outputs(st, pix_outputs(st, t), t, color, alpha, depth, normal, dist,
                                                    T_final, n_contrib);
@@ -280,7 +420,7 @@ __device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float
 // GEO: the loss has depth, normal or distortion terms (their upstream
 // gradients are read); without them the depth path and six of the per-record
 // components are identically zero and are not computed or reduced.
-template <int NT, int BATCH, bool GEO>
+template <int TW, int NT, int BATCH, bool GEO>
 __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, BwdSmem<BATCH>& sm, PixBwd pb,
@@ -311,10 +451,16 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
             if (j < maxn) {
                 const uint32_t g = vals[t.start + j];
                 const size_t r = (size_t)t.v * N + g;
+                float4 gq[kGeomF4];
 #pragma unroll
-                for (int q = 0; q < kGeomF4; ++q) sm.g[q][tid] = geom[kGeomF4 * r + q];
-#pragma unroll
-                for (int q = 0; q < kAppF4; ++q) sm.a[q][tid] = app[kAppF4 * r + q];
+                for (int q = 0; q < kGeomF4; ++q) {
+                    gq[q] = geom[kGeomF4 * r + q];
+                    sm.g[q][tid] = gq[q];
+                }
+                const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
+                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                sm.a[0][tid] = a0;
+                sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
                 sm.rec[tid] = (uint32_t)r;
             }
 #pragma unroll
@@ -323,7 +469,13 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
         __syncthreads();
         const int cnt = (int)min((uint32_t)BATCH, maxn - (uint32_t)base);
         const int kmax = (int)min((int64_t)cnt, (int64_t)wave_maxn - base);
-        for (int k = kmax - 1; k >= 0; --k) {
+        // entries skipped by the forward for this wave are skipped here too
+        for (int c = (kmax - 1) >> 6; c >= 0; --c) {
+          uint64_t live = wave_live_mask(sm.a[1], c, kmax);
+          while (live != 0ull) {
+            const int hb = 63 - (int)__builtin_clzll(live);
+            live &= ~(1ull << hb);
+            const int k = c * 64 + hb;
             const uint32_t jj = (uint32_t)base + (uint32_t)k;
             PairEval e;
             const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
@@ -393,6 +545,7 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                 const int ci = wave_tsum_comp<8>(lane);
                 if ((lane & 14) == 0 && ci < 6) atomicAdd(&sm.acc[k][ci < 3 ? 12 + ci : 15 + ci], tot);
             }
+          }
         }
         __syncthreads();
         if (tid < cnt) {
@@ -437,7 +590,7 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         if (dMed) { pb.gMed = dMed[o1]; pb.kmed = median_contrib[o1]; }
         pix_bwd_init(pb, t, T_final[o1], n_contrib[o1], alpha[o1], depth[o1], dist[o1]);
     }
-    bwd_tile<TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
+    bwd_tile<TW, TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
 }
 
 // One training step of the compositing for a tile: forward with the
@@ -463,9 +616,9 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     tile_ctx<TW, TH>(cams, V, ranges, t);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
-    uint64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
-    fwd_tile<NT, MODE>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st, hits,
-                       max_alpha, max_weight, n0, n1, n2, n3);
+    uint64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0;
+    fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st, hits,
+                       max_alpha, max_weight, n0, n1, n2, n3, n4);
     const PixOut o = pix_outputs(st, t);
     PixBwd pb;
     pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = pb.gMed = 0.f;
@@ -503,7 +656,7 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
         __syncthreads();
     }
     if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile + 1] = s_red[0];
-    bwd_tile<NT, BATCH, false>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb,
+    bwd_tile<TW, NT, BATCH, false>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb,
                                grad_rec);
 }
 

@@ -301,13 +301,15 @@ class Rasterizer:
 
     def count_pairs(self, stream=None, waves=False):
         """(reached pairs, blended pairs) of the current binning, and with
-        ``waves`` also (wave steps, wave steps with a blend) - syncs."""
-        out = torch.zeros(4, dtype=torch.int64, device=self.device)
+        ``waves`` also (wave steps, wave steps with a blend, pairs up to
+        each pixel's last blend) - syncs."""
+        out = torch.zeros(5, dtype=torch.int64, device=self.device)
         call("sr_render_count", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
-             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.vals), _ptr(self.ranges), _ptr(out), _stream(stream))
+             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(out),
+             _stream(stream))
         c = out.cpu().numpy()
         if waves:
-            return int(c[0]), int(c[1]), int(c[2]), int(c[3])
+            return int(c[0]), int(c[1]), int(c[2]), int(c[3]), int(c[4])
         return int(c[0]), int(c[1])
 
     def status(self):

@@ -97,13 +97,18 @@ def test_work_counts_match_oracle():
         fl = res["flag_cut"] | res["flag_term"] | res["flag_clamp"]
         nb += int(res["nblend"][~fl].sum())
         nb_flagged += int(res["nblend"][fl].sum())
-    R, B, WS, WB = run["rast"].count_pairs(waves=True)
-    print("reached", R, "blended", B, "oracle blended", nb, "+ flagged", nb_flagged, "wave steps", WS, WB)
+    R, B, WS, WB, RB = run["rast"].count_pairs(waves=True)
+    upto = int(run["rast"].n_contrib[: run["views"].P].to(torch.int64).sum().item())
+    print("reached", R, "blended", B, "oracle blended", nb, "+ flagged", nb_flagged, "wave steps", WS, WB,
+          "backward pairs", RB, "list entries up to the last blend", upto)
     assert B >= nb
     if nb_flagged == 0:
         assert B == nb
     assert B <= R <= 64 * WS
     assert WB <= WS and B <= 64 * WB and WB > 0
+    # the backward revisits the tested entries up to each pixel's last blend:
+    # at least the blended ones, at most every list entry up to it
+    assert B <= RB <= min(R, upto)
 
 
 @pytest.mark.parametrize("deg", [0, 3])
