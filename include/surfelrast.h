@@ -314,11 +314,14 @@ sr_status sr_train_step_raster(const sr_config *cfg, int32_t N, int32_t V, const
  * (pixel, surfel) pair: hits[g] += 1, max_alpha[g] = max(., a),
  * max_weight[g] = max(., a T).  hits [N] uint32, max_alpha [N],
  * max_weight [N] float32; cleared first unless cfg->flags has
- * SR_FLAG_ACCUMULATE.  geom comes from sr_preprocess (app not needed). */
+ * SR_FLAG_ACCUMULATE.  geom and rect come from sr_preprocess (app not
+ * needed); with rect [V*N, 4] each 64-pixel wave skips the entries that
+ * cannot reach its pixels, as sr_render_forward does (NULL: every entry is
+ * evaluated; the statistics are the same up to float32 ties). */
 sr_status sr_prune_contrib(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
-                           const sr_camera *cams_dev, const float *geom, const uint32_t *vals,
-                           const uint32_t *ranges, uint32_t *hits, float *max_alpha,
-                           float *max_weight, void *stream);
+                           const sr_camera *cams_dev, const float *geom, const uint16_t *rect,
+                           const uint32_t *vals, const uint32_t *ranges, uint32_t *hits,
+                           float *max_alpha, float *max_weight, void *stream);
 
 /* Work accounting of the compositing (no outputs): counts[0] = pairs
  * (pixel, tile-list entry) tested before the pixel terminated, counts[1] =

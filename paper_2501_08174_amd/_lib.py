@@ -88,7 +88,7 @@ def _declare(lib):
         "sr_compact_surfels": (c_int32, [c_int32, V, V, c_float, c_int32, V, V, V, V, c_size_t, V, V]),
         "sr_train_step_raster": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
                                  + [V] * 14),
-        "sr_prune_contrib": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
+        "sr_prune_contrib": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V, V]),
         "sr_render_count": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V]),
         "sr_prune_mask": (c_int32, [c_int32, V, c_float, V, V]),
     }

@@ -196,8 +196,8 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
         SR_TRY(hip_status(sr::fill_f32(max_alpha, 0.f, (uint64_t)N, s), "clear max_alpha"));
         SR_TRY(hip_status(sr::fill_f32(max_weight, 0.f, (uint64_t)N, s), "clear max_weight"));
     }
-    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, color,
-                                            alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
+    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, nullptr, vals, ranges,
+                                            color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
                                             max_weight, nullptr, median_depth, median_contrib, s),
                       "sr_render_forward");
 }
@@ -480,8 +480,9 @@ sr_status sr_compact_surfels(int32_t N, const uint8_t* prune_mask, const float* 
 }
 
 sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
-                           const sr_camera* cams_dev, const float* geom, const uint32_t* vals, const uint32_t* ranges,
-                           uint32_t* hits, float* max_alpha, float* max_weight, void* stream) {
+                           const sr_camera* cams_dev, const float* geom, const uint16_t* rect, const uint32_t* vals,
+                           const uint32_t* ranges, uint32_t* hits, float* max_alpha, float* max_weight,
+                           void* stream) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
     int total_tiles = 0;
@@ -494,9 +495,9 @@ sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_
         SR_TRY(hip_status(sr::fill_f32(max_alpha, 0.f, (uint64_t)N, s), "clear max_alpha"));
         SR_TRY(hip_status(sr::fill_f32(max_weight, 0.f, (uint64_t)N, s), "clear max_weight"));
     }
-    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, vals, ranges, nullptr,
-                                            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, hits, max_alpha,
-                                            max_weight, nullptr, nullptr, nullptr, s),
+    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, rect, vals, ranges,
+                                            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, hits,
+                                            max_alpha, max_weight, nullptr, nullptr, nullptr, s),
                       "sr_prune_contrib");
 }
 
@@ -543,7 +544,8 @@ sr_status sr_render_count(const sr_config* cfg, int32_t N, int32_t V, const sr_c
     if (total_tiles > 0) { SR_NEED(geom); SR_NEED(app); SR_NEED(vals); SR_NEED(ranges); }
     hipStream_t s = (hipStream_t)stream;
     SR_TRY(hip_status(sr::fill_f32((float*)counts, 0.f, 10, s), "clear counts"));
-    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, nullptr,
+    return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, nullptr, vals, ranges,
+                                            nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                             nullptr, (unsigned long long*)counts, nullptr, nullptr, s),
                       "sr_render_count");

@@ -34,8 +34,9 @@ bool tile_shape_supported(int tw, int th);
 hipError_t fill_f32(float* p, float v, uint64_t n, hipStream_t s);
 
 hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
-                             const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
-                             float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
+                             const float* geom, const float* app, const uint16_t* rect, const uint32_t* vals,
+                             const uint32_t* ranges, float* color, float* alpha, float* depth, float* normal,
+                             float* dist, float* T_final,
                              uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
                              unsigned long long* counts, float* median_depth, uint32_t* median_contrib,
                              hipStream_t s);

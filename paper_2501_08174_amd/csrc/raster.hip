@@ -63,8 +63,10 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
 // MODE bits: 1 shade (colour, depth, normal, distortion outputs), 2 occlusion
 // statistics, 4 count reached/blended pairs (work accounting), 8 median depth
 // (the 2DGS surface depth: the depth of the last blended entry that starts
-// with transmittance above 1/2) with the 1-based list index of that entry.
-constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8;
+// with transmittance above 1/2) with the 1-based list index of that entry,
+// 16 pixel rectangles read from the rectangle array (statistics without
+// shading: no appearance records to take them from).
+constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8, kRect = 16;
 
 // Per-wave culling.  Every wave of a tile covers whole rows of it (a band).
 // When an entry is staged, its thread works out which bands it can reach,
@@ -176,7 +178,7 @@ struct PixFwd {
 template <int NT, int MODE>
 struct FwdSmem {
     float4 g[kGeomF4][NT];
-    float4 a[(MODE & (kShade | kCount)) ? kAppF4 : 1][(MODE & (kShade | kCount)) ? NT : 1];
+    float4 a[(MODE & (kShade | kCount | kRect)) ? kAppF4 : 1][(MODE & (kShade | kCount | kRect)) ? NT : 1];
     uint32_t id[(MODE & kStats) ? NT : 1];
 };
 
@@ -193,8 +195,9 @@ struct BwdSmem {
 // Front to back over the tile list; every thread owns one pixel.
 template <int TW, int NT, int MODE>
 __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
-                                         const float4* __restrict__ app, const uint32_t* __restrict__ vals,
-                                         const RasterConsts& rc, FwdSmem<NT, MODE>& sm, PixFwd& st,
+                                         const float4* __restrict__ app, const uint2* __restrict__ rect,
+                                         const uint32_t* __restrict__ vals, const RasterConsts& rc,
+                                         FwdSmem<NT, MODE>& sm, PixFwd& st,
                                          uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
                                          float* __restrict__ max_weight, uint64_t& n_reached, uint64_t& n_blended,
                                          uint64_t& n_witer, uint64_t& n_wblend, uint64_t& n_upto_last) {
@@ -202,8 +205,10 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     constexpr bool STATS = (MODE & kStats) != 0;
     constexpr bool COUNT = (MODE & kCount) != 0;
     constexpr bool MEDIAN = (MODE & kMedian) != 0;
-    // the appearance records (with the pixel rectangles) are staged: cull per wave
-    constexpr bool CULL = SHADE || COUNT;
+    // the pixel rectangles are staged (with the appearance records, or from
+    // the rectangle array): cull per wave
+    constexpr bool RECT = (MODE & kRect) != 0 && !SHADE && !COUNT;
+    constexpr bool CULL = SHADE || COUNT || RECT;
     uint32_t n_eval = 0, n_eval_last = 0;     // COUNT: entries tested by this pixel, up to its last blend
     const int tid = threadIdx.x;
     const int lane = __lane_id();
@@ -224,7 +229,13 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 gq[q] = geom[kGeomF4 * r + q];
                 sm.g[q][tid] = gq[q];
             }
-            if (CULL) {
+            if (RECT) {
+                // ushort4 rectangle (x_lo, x_hi, y_lo, y_hi) read as two packed ranges
+                const uint2 rr = rect[r];
+                const float4 a1 = make_float4(0.f, 0.f, __uint_as_float(rr.x), __uint_as_float(rr.y));
+                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                sm.a[1][tid] = make_float4(0.f, 0.f, 0.f, __uint_as_float(bits));
+            } else if (CULL) {
                 const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
                 // the band bits replace the packed rectangle once it has served
                 const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
@@ -351,7 +362,8 @@ __device__ __forceinline__ void write_outputs(const PixFwd& st, const PixOut& o,
 template <int TW, int TH, int MODE>
 __global__ void __launch_bounds__(TW * TH)
 k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
-             const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+             const float4* __restrict__ app, const uint2* __restrict__ rect, const uint32_t* __restrict__ vals,
+             const uint2* __restrict__ ranges,
              RasterConsts rc, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
              float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
              uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
@@ -364,7 +376,7 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
     uint64_t n_reached = 0, n_blended = 0, n_witer = 0, n_wblend = 0, n_upto = 0;
-    fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached,
+    fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, rect, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached,
                            n_blended,
                        n_witer, n_wblend, n_upto);
     if (MODE & kCount) {
@@ -617,7 +629,8 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
     uint64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0;
-    fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st, hits,
+    fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, nullptr, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st,
+                           hits,
                        max_alpha, max_weight, n0, n1, n2, n3, n4);
     const PixOut o = pix_outputs(st, t);
     PixBwd pb;
@@ -676,23 +689,24 @@ constexpr int kBwdBatch = 128;
 
 template <int TW, int TH, int MODE>
 void fwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
-                const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, float* color,
+                const float4* app, const uint2* rect, const uint32_t* vals, const uint2* ranges, RasterConsts rc,
+                float* color,
                 float* alpha, float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib,
                 uint32_t* hits, float* max_alpha, float* max_weight, unsigned long long* counts,
                 float* median_depth, uint32_t* median_contrib) {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, MODE>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app,
-                       vals, ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
+                       rect, vals, ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
                        max_weight, counts, median_depth, median_contrib);
 }
 
 template <int TW, int TH>
 void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
-                  const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges,
+                  const float4* geom, const float4* app, const uint2* rect, const uint32_t* vals, const uint2* ranges,
                   RasterConsts rc, float* color, float* alpha, float* depth, float* normal, float* dist,
                   float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
                   unsigned long long* counts, float* median_depth, uint32_t* median_contrib) {
 #define SR_FWD(M)                                                                                        \
-    fwd_launch<TW, TH, M>(total_tiles, s, cams, V, N, geom, app, vals, ranges, rc, color, alpha, depth, \
+    fwd_launch<TW, TH, M>(total_tiles, s, cams, V, N, geom, app, rect, vals, ranges, rc, color, alpha, depth, \
                           normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, counts,          \
                           median_depth, median_contrib)
     switch (mode) {
@@ -701,6 +715,7 @@ void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cam
         case kShade | kMedian: SR_FWD(kShade | kMedian); break;
         case kShade | kStats | kMedian: SR_FWD(kShade | kStats | kMedian); break;
         case kStats: SR_FWD(kStats); break;
+        case kStats | kRect: SR_FWD(kStats | kRect); break;
         default: SR_FWD(kCount); break;
     }
 #undef SR_FWD
@@ -760,18 +775,20 @@ hipError_t fill_f32(float* p, float v, uint64_t n, hipStream_t s) {
 }
 
 hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
-                             const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
-                             float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
-                             uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                             unsigned long long* counts, float* median_depth, uint32_t* median_contrib,
-                             hipStream_t s) {
+                             const float* geom, const float* app, const uint16_t* rect, const uint32_t* vals,
+                             const uint32_t* ranges, float* color, float* alpha, float* depth, float* normal,
+                             float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
+                             float* max_weight, unsigned long long* counts, float* median_depth,
+                             uint32_t* median_contrib, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
     int mode = counts ? kCount
-                      : ((color ? kShade : 0) | (hits ? kStats : 0) | (color && median_depth ? kMedian : 0));
+                      : ((color ? kShade : 0) | (hits ? kStats : 0) | (color && median_depth ? kMedian : 0) |
+                         (!color && hits && rect ? kRect : 0));
 #define SR_TS(W, H)                                                                                              \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                   \
-        fwd_dispatch<W, H>(mode, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,    \
+        fwd_dispatch<W, H>(mode, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app,          \
+                           (const uint2*)rect, vals,                                                              \
                            (const uint2*)ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, \
                            max_alpha, max_weight, counts, median_depth, median_contrib);                        \
         return hipGetLastError();                                                                               \

@@ -293,11 +293,13 @@ class Rasterizer:
              _ptr(mw), _ptr(self.tile_loss), _ptr(self.loss_out), _ptr(self._grad_rec()), _stream(stream))
         return self.loss_out
 
-    def prune_stats(self, hits, max_alpha, max_weight, accumulate=False, stream=None):
+    def prune_stats(self, hits, max_alpha, max_weight, accumulate=False, stream=None, cull: bool = True):
+        """Occlusion statistics of the current binning (sr_prune_contrib);
+        ``cull`` lets each wave skip entries by their pixel rectangles."""
         cfg = self._cfg(accumulate)
         call("sr_prune_contrib", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
-             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.vals), _ptr(self.ranges), _ptr(hits),
-             _ptr(max_alpha), _ptr(max_weight), _stream(stream))
+             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.rect) if cull else None, _ptr(self.vals),
+             _ptr(self.ranges), _ptr(hits), _ptr(max_alpha), _ptr(max_weight), _stream(stream))
 
     def count_pairs(self, stream=None, waves=False):
         """(reached pairs, blended pairs) of the current binning, and with

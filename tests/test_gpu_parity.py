@@ -288,6 +288,37 @@ def test_prune_stats_match_oracle():
     print(f"pruned {mask.sum()} of {sc.n}; exempt {(~keep).sum()}")
 
 
+def test_prune_pass_culling_keeps_statistics():
+    """sr_prune_contrib (no shading) with per-wave culling by the pixel
+    rectangles, without it, and the statistics of the shaded forward: the
+    same hits and maxima (the oracle's tie surfels aside)."""
+    sc = _ragged_scene(37, 600, 0)
+    run = gpu_run(sc, stats=True)
+    ref = [t.cpu().numpy() for t in run["stats"]]
+    views = ViewBatch(sc.cams)
+    rast = Rasterizer(sc.n, views, 0, shade=False)
+    p = Params.from_scene(sc)
+    rast.plan_capacity(p)
+    rast.preprocess(p)
+    rast.bin()
+    rast.check_capacity()
+    out = {}
+    for cull in (True, False):
+        st = (torch.zeros(sc.n, dtype=torch.int32, device="cuda"), torch.zeros(sc.n, device="cuda"),
+              torch.zeros(sc.n, device="cuda"))
+        rast.prune_stats(*st, cull=cull)
+        out[cull] = [t.cpu().numpy() for t in st]
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0)
+    tie_ids = [render_pixels(P64, cam, geoms[v], _full(cam), RP)["tie_ids"] for v, cam in enumerate(sc.cams)]
+    keep = np.ones(sc.n, bool)
+    keep[np.unique(np.concatenate(tie_ids))] = False
+    for cull in (True, False):
+        for a, b in zip(out[cull], ref):
+            np.testing.assert_array_equal(a[keep], b[keep])
+    assert (ref[0] > 0).sum() > 50
+
+
 def test_prune_occluded_surfel_scene():
     from tests.oracle_scenes import front_camera, scene_from
     ID = [1.0, 0.0, 0.0, 0.0]
