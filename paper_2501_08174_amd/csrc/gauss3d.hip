@@ -116,8 +116,42 @@ k_preprocess3d(int N, const float* __restrict__ means, const float* __restrict__
     geom3[2 * r + 1] = make_float4((float)ccx, (float)ccy, (float)L, 0.0f);
 }
 
+// Bits of the waves (bands of 64 / TW rows of the tile) that the cutoff
+// ellipse q = a dx^2 + 2 b dx dy + c dy^2 <= 2 L of one record can reach
+// within the tile's columns, in float64 with a relative slack tau on 2 L and
+// a 1e-3 pixel margin (an entry is skipped only where the exact test fails by
+// a margin).  For fixed dx the ellipse is the interval of dy between the
+// roots of c dy^2 + 2 b dx dy + a dx^2 - 2 L; its lower end is convex and its
+// upper end concave in dx, so their extremes over the columns sit at the
+// lowest / highest point of the ellipse clamped to the columns.
+template <int TW, int NW>
+__device__ __forceinline__ uint32_t band_bits3d(const float4& c0, const float4& c1, int tx0, int ty0) {
+    constexpr int RW = 64 / TW;
+    constexpr double tau = 1e-3, mg = 1e-3;
+    const double a = c0.x, b = c0.y, c = c0.z, cx = c1.x, cy = c1.y;
+    const double r2 = 2.0 * (double)c1.z * (1.0 + tau);
+    const double det = a * c - b * b;
+    if (!(a > 0.0 && c > 0.0 && det > 0.0)) return (1u << NW) - 1u;     // not an ellipse: keep
+    const double X0 = (tx0 + 0.5) - cx - mg, X1 = (tx0 + TW - 0.5) - cx + mg;
+    const double hx = sqrt(r2 * c / det);                  // the ellipse's half width
+    const double xa = fmax(X0, -hx), xb = fmin(X1, hx);
+    if (xa > xb) return 0u;
+    const double hy = sqrt(r2 * a / det);                  // lowest / highest points at dy = -+hy
+    const double xbot = fmin(fmax(b * hy / a, xa), xb), xtop = fmin(fmax(-b * hy / a, xa), xb);
+    const double ylo = (-b * xbot - sqrt(fmax(r2 * c - det * xbot * xbot, 0.0))) / c;
+    const double yhi = (-b * xtop + sqrt(fmax(r2 * c - det * xtop * xtop, 0.0))) / c;
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const double Y0 = (ty0 + w * RW + 0.5) - cy - mg, Y1 = (ty0 + w * RW + RW - 0.5) - cy + mg;
+        if (ylo <= Y1 && yhi >= Y0) bits |= 1u << w;
+    }
+    return bits;
+}
+
 // Front to back over a tile's list; every thread owns one pixel; only the
-// occlusion statistics (hits, max alpha, max weight) are written.
+// occlusion statistics (hits, max alpha, max weight) are written.  Each
+// wave walks only the entries whose ellipse reaches its rows.
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH)
 k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom3,
@@ -133,6 +167,7 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
     const int local = tile - c.tile_offset;
     const int ty = local / c.tiles_x, tx = local - ty * c.tiles_x;
     const int ix = tx * TW + (int)(threadIdx.x % TW), iy = ty * TH + (int)(threadIdx.x / TW);
+    const int wv = (int)__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6;
     const float px = (float)ix + 0.5f, py = (float)iy + 0.5f;
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x, n = rg.y - rg.x;
@@ -145,14 +180,23 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
         if (j < n) {
             const uint32_t gg = vals[start + j];
             const size_t r = (size_t)v * N + gg;
-            sg[0][threadIdx.x] = geom3[2 * r];
-            sg[1][threadIdx.x] = geom3[2 * r + 1];
+            const float4 c0 = geom3[2 * r], c1 = geom3[2 * r + 1];
+            sg[0][threadIdx.x] = c0;
+            // the wave bits take the record's unused last slot
+            sg[1][threadIdx.x] = make_float4(c1.x, c1.y, c1.z,
+                                             __uint_as_float(band_bits3d<TW, NT / 64>(c0, c1, tx * TW, ty * TH)));
             sid[threadIdx.x] = gg;
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, n - base);
         if (__ballot(!done) == 0ull) continue;
-        for (int k = 0; k < cnt; ++k) {
+        bool wave_done = false;
+        for (int cr = 0; cr * 64 < cnt && !wave_done; ++cr) {
+          const int kk = cr * 64 + lane;
+          uint64_t live = __ballot(kk < cnt && ((__float_as_uint(sg[1][kk < cnt ? kk : 0].w) >> wv) & 1u));
+          while (live != 0ull) {
+            const int k = cr * 64 + (int)__builtin_ctzll(live);
+            live &= live - 1ull;
             const float4 a0 = sg[0][k], a1 = sg[1][k];
             const float dx = px - a1.x, dy = py - a1.y;
             const float q = (a0.x * dx * dx + 2.0f * a0.y * dx * dy) + a0.z * dy * dy;
@@ -177,7 +221,11 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
                     atomicMax(lane == 0 ? (uint32_t*)&max_alpha[g] : (uint32_t*)&max_weight[g], mx);
                 }
             }
-            if (__ballot(!done) == 0ull) break;
+            if (__ballot(!done) == 0ull) {
+                wave_done = true;
+                break;
+            }
+          }
         }
     }
 }
