@@ -30,7 +30,9 @@
  *     multi-channel outputs (colour, normal) are planar per view:
  *     out[3*pix_offset + ch*width*height + y*width + x].
  *     Tiles are numbered globally: view v owns ids [tile_offset,
- *     tile_offset + tiles_x*tiles_y), row-major inside the view.
+ *     tile_offset + tiles_x*tiles_y), row-major inside the view.  Tiles are
+ *     binned in groups of SR_TILE_GROUP x SR_TILE_GROUP, numbered the same
+ *     way from group_offset with groups_x groups per row.
  */
 #ifndef SURFELRAST_H
 #define SURFELRAST_H
@@ -62,7 +64,8 @@ typedef struct sr_camera {
     int32_t tiles_x, tiles_y; /* filled by sr_layout_views                */
     int32_t tile_offset;      /* filled by sr_layout_views                */
     int64_t pix_offset;       /* filled by sr_layout_views                */
-    int32_t reserved[2];
+    int32_t group_offset;     /* filled by sr_layout_views                */
+    int32_t groups_x;         /* filled by sr_layout_views                */
 } sr_camera;
 
 /* Renderer configuration. */
@@ -91,14 +94,20 @@ typedef struct sr_config {
  *   [3] status: 0 ok, 1 instance capacity exceeded (outputs invalid). */
 #define SR_COUNTERS 4
 
+/* Tiles per side of a binning group, and the surfel-id bits of a sorted
+ * instance value (the remaining 8 bits hold the group sub-rectangle). */
+#define SR_TILE_GROUP 4
+#define SR_INST_ID_BITS 24
+
 const char *sr_last_error(void);
 int32_t sr_version(void);
 /* 1 if the tile shape is compiled in, else 0. */
 int32_t sr_tile_supported(int32_t tile_w, int32_t tile_h);
 
-/* Host only.  Fills tiles_x, tiles_y, tile_offset and pix_offset of the V
- * cameras for the given tile shape and returns the total pixel and tile
- * counts.  Error: SR_ERR_ARG for V < 0, a non-positive size or tile. */
+/* Host only.  Fills tiles_x, tiles_y, tile_offset, pix_offset,
+ * group_offset and groups_x of the V cameras for the given tile shape and
+ * returns the total pixel and tile counts.  Error: SR_ERR_ARG for V < 0, a
+ * non-positive size or tile. */
 sr_status sr_layout_views(sr_camera *cams_host, int32_t V, int32_t tile_w, int32_t tile_h,
                           int64_t *total_pixels_host, int32_t *total_tiles_host);
 
@@ -126,19 +135,27 @@ sr_status sr_preprocess(const sr_config *cfg, int32_t N, const float *means, con
                         uint32_t *depth_key, uint8_t *in_frustum, void *stream);
 
 /* Bytes of workspace sr_bin_and_sort needs for N surfels, V views and an
- * instance capacity (instances are (view, tile, surfel) triples). */
+ * instance capacity (instances are (view, tile group, surfel) triples). */
 sr_status sr_bin_workspace_size(int32_t N, int32_t V, uint32_t inst_capacity, size_t *bytes_host);
 
 /* Duplicate-key generation, sort and per-tile ranges (Section 4.3: each
- * pixel blends its assigned Gaussians front to back).  Produces the list of
- * instances sorted by the 64-bit key (global tile id << 32 | depth key),
- * equal keys by surfel id:
- *   vals   [inst_capacity] surfel id of each sorted instance
+ * pixel blends its assigned Gaussians front to back).  Tiles are binned in
+ * groups of SR_TILE_GROUP x SR_TILE_GROUP: one instance per (group, surfel)
+ * whose tile rectangle meets the group, sorted by the 64-bit key (global
+ * group id << 32 | depth key), equal keys by surfel id:
+ *   vals   [inst_capacity] surfel id | sub << 24 of each sorted instance,
+ *          sub = x_lo | x_hi << 2 | y_lo << 4 | y_hi << 6: the surfel's
+ *          tile rectangle clipped to the group, in tile coordinates within
+ *          the group (N must stay below 2^SR_INST_ID_BITS)
  *   keys64 [inst_capacity] the sorted keys (NULL to skip)
- *   ranges [2*T]  [start, end) of every global tile's run, [0,0) if empty
+ *   ranges [2*T]  per global tile, [start, end) of its group's run ([0,0)
+ *          if empty); the tile's own front-to-back list is the entries of
+ *          that run whose sub-rectangle contains the tile
  *   counters [4]  see SR_COUNTERS
  * The depth part of the key is sorted once per visible (view, surfel)
- * before duplication; the tile part by a stable LSD radix sort after it. */
+ * before duplication; the group part by a stable LSD radix sort after it.
+ * Tile-list positions used elsewhere (n_contrib, median_contrib) are
+ * positions in the group run. */
 sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                           const sr_camera *cams_dev, const uint16_t *rect, const uint32_t *tiles_touched,
                           const uint32_t *depth_key, void *workspace, size_t ws_bytes,
@@ -148,8 +165,8 @@ sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_c
 /* Front-to-back alpha compositing of every view (one launch for all V
  * views).  Per pixel: colour [3P] (+ T_final * bg), alpha [P] = 1 - T_final,
  * depth [P] = sum w z, normal [3P] = sum w n, dist [P] = sum_ij w_i w_j
- * (z_i - z_j)^2, T_final [P], n_contrib [P] (index + 1 of the last blended
- * entry of the pixel's tile list).  When hits/max_alpha/max_weight are not
+ * (z_i - z_j)^2, T_final [P], n_contrib [P] (position + 1 of the last
+ * blended entry in the run of the pixel's tile group).  When hits/max_alpha/max_weight are not
  * NULL the occlusion statistics of sr_prune_contrib are gathered in the
  * same pass.  Median depth (the 2DGS surface depth, an alternative to
  * depth/alpha in the normal consistency term of Eq. 3), optional: when

@@ -22,6 +22,8 @@ SR_APP_STRIDE = 8
 SR_GRAD_STRIDE = 24
 SR_COUNTERS = 4
 SR_COMPACT_MAX_ARRAYS = 8
+SR_TILE_GROUP = 4
+SR_INST_ID_BITS = 24
 
 EXPORTED = (
     "sr_last_error", "sr_version", "sr_tile_supported", "sr_layout_views", "sr_preprocess",
@@ -44,7 +46,7 @@ class SrCamera(ctypes.Structure):
         ("viewmat", c_float * 12), ("fx", c_float), ("fy", c_float), ("cx", c_float), ("cy", c_float),
         ("campos", c_float * 3), ("znear", c_float), ("bg", c_float * 3),
         ("width", c_int32), ("height", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32),
-        ("tile_offset", c_int32), ("pix_offset", c_int64), ("reserved", c_int32 * 2),
+        ("tile_offset", c_int32), ("pix_offset", c_int64), ("group_offset", c_int32), ("groups_x", c_int32),
     ]
 
 

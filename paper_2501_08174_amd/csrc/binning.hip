@@ -2,15 +2,19 @@
 //
 // Section 4.3: each pixel blends the Gaussians assigned to it in
 // front-to-back order.  The assignment is materialised as instances
-// (view, tile, surfel) sorted by the 64-bit key (global tile id << 32 |
-// float32 depth bits), ties by surfel id.
+// (view, tile group, surfel) sorted by the 64-bit key (global group id << 32
+// | float32 depth bits), ties by surfel id, where a group is 4 x 4 tiles:
+// one instance per group the surfel's tile rectangle meets, carrying the
+// part of the rectangle inside the group, so a tile reads its group's run
+// and keeps the entries that cover it.  Grouping cuts the instances (and the
+// sort) several-fold; the tiles' lists are unchanged.
 //
 // An LSD radix sort of that key processes the depth digits first and the
-// tile digits last.  The depth of an instance is the depth of its surfel, so
-// the depth passes run once over the visible (view, surfel) pairs before
-// duplication (tens of millions of elements) instead of over the instances
-// (hundreds of millions); the instances are then emitted in depth order and
-// only the ceil(log2(tiles)) tile bits are sorted, by a stable LSD radix sort.
+// group digits last.  The depth of an instance is the depth of its surfel,
+// so the depth passes run once over the visible (view, surfel) pairs before
+// duplication instead of over the instances; the instances are then emitted
+// in depth order and only the ceil(log2(groups)) group bits are sorted, by a
+// stable LSD radix sort.
 // Every count lives in device memory, so the sequence needs no host
 // synchronisation and can be captured into a HIP graph.
 #include "common.h"
@@ -299,18 +303,25 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
 
 // ---- instances ----------------------------------------------------------------
 
-// Tiles touched by every depth-sorted visible pair (gathered once into
-// depth order) and their sum per block.
+// Tile groups met by the rectangle of a record.
+__device__ __forceinline__ uint32_t groups_of(const ushort4 rc, int tile_w, int tile_h) {
+    constexpr int GS = SR_TILE_GROUP;
+    const int gx0 = rc.x / tile_w / GS, gx1 = rc.y / tile_w / GS, gy0 = rc.z / tile_h / GS, gy1 = rc.w / tile_h / GS;
+    return (uint32_t)((gx1 - gx0 + 1) * (gy1 - gy0 + 1));
+}
+
+// Groups met by every depth-sorted visible pair (gathered once into depth
+// order) and their sum per block.
 __global__ void __launch_bounds__(kNT)
 k_inst_count(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ vis_vals,
-             const uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ tt_sorted,
+             const ushort4* __restrict__ rect, int tile_w, int tile_h, uint32_t* __restrict__ tt_sorted,
              uint64_t* __restrict__ sums) {
     __shared__ uint64_t s_w[4];
     uint64_t b, e;
     static_chunk(counters[0], G, &b, &e);
     uint64_t c = 0;
     for (uint64_t i = b + threadIdx.x; i < e; i += kNT) {
-        const uint32_t t = tiles_touched[vis_vals[i]];
+        const uint32_t t = groups_of(rect[vis_vals[i]], tile_w, tile_h);
         tt_sorted[i] = t;
         c += t;
     }
@@ -363,15 +374,16 @@ k_emit_starts(const uint32_t* __restrict__ counters, const uint64_t* __restrict_
 // a camera, first in depth order) do not serialise on a few blocks.
 __global__ void __launch_bounds__(kNT)
 k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total64, int N, int tile_w, int tile_h,
-       const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals,
-       const uint32_t* __restrict__ tiles_touched, const ushort4* __restrict__ rect,
+       const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals, const ushort4* __restrict__ rect,
        const uint64_t* __restrict__ offs, const uint32_t* __restrict__ starts, uint32_t* __restrict__ inst_keys,
        uint32_t* __restrict__ inst_vals) {
+    constexpr int GS = SR_TILE_GROUP;
     __shared__ uint64_t s_off[kNT];
     __shared__ uint32_t s_g[kNT];
-    __shared__ int s_base[kNT];     // global id of the rectangle's first tile
-    __shared__ int s_tw[kNT];       // rectangle width in tiles
-    __shared__ int s_tx[kNT];       // tiles per row of the view
+    __shared__ int s_base[kNT];     // global id of the first group met
+    __shared__ int s_tw[kNT];       // width of the met groups
+    __shared__ int s_tx[kNT];       // groups per row of the view
+    __shared__ uint2 s_rc[kNT];     // tile rectangle relative to the first group's first tile (x_lo | x_hi << 16, ...)
     __shared__ uint32_t s_first;
     const uint64_t stored = counters[2];          // min(instances, capacity)
     const uint64_t ob = (uint64_t)blockIdx.x * kEmitPerBlock;
@@ -387,13 +399,17 @@ k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total
             const uint32_t rec = vis_vals[i];
             const int v = (int)(rec / (uint32_t)N);
             const ushort4 rc = rect[rec];
-            const int tx0 = rc.x / tile_w, tx1 = rc.y / tile_w, ty0 = rc.z / tile_h;
+            const int tx0 = rc.x / tile_w, tx1 = rc.y / tile_w, ty0 = rc.z / tile_h, ty1 = rc.w / tile_h;
+            const int gx0 = tx0 / GS, gx1 = tx1 / GS, gy0 = ty0 / GS;
             const sr_camera& c = cams[v];
             s_off[threadIdx.x] = offs[i];
             s_g[threadIdx.x] = rec - (uint32_t)v * (uint32_t)N;
-            s_base[threadIdx.x] = c.tile_offset + ty0 * c.tiles_x + tx0;
-            s_tw[threadIdx.x] = tx1 - tx0 + 1;
-            s_tx[threadIdx.x] = c.tiles_x;
+            s_base[threadIdx.x] = c.group_offset + gy0 * c.groups_x + gx0;
+            s_tw[threadIdx.x] = gx1 - gx0 + 1;
+            s_tx[threadIdx.x] = c.groups_x;
+            const int ox = GS * gx0, oy = GS * gy0;
+            s_rc[threadIdx.x] = make_uint2((uint32_t)(tx0 - ox) | ((uint32_t)(tx1 - ox) << 16),
+                                           (uint32_t)(ty0 - oy) | ((uint32_t)(ty1 - oy) << 16));
         } else {
             s_off[threadIdx.x] = ~0ull;
         }
@@ -411,36 +427,44 @@ k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total
             const uint32_t tw = (uint32_t)s_tw[lo];
             const uint32_t row = k / tw, colx = k - row * tw;
             inst_keys[o] = (uint32_t)s_base[lo] + row * (uint32_t)s_tx[lo] + colx;
-            inst_vals[o] = s_g[lo];
+            // the tile rectangle clipped to this group, in its tile coordinates
+            const uint2 rr = s_rc[lo];
+            const int x0 = (int)(rr.x & 0xffffu) - GS * (int)colx, x1 = (int)(rr.x >> 16) - GS * (int)colx;
+            const int y0 = (int)(rr.y & 0xffffu) - GS * (int)row, y1 = (int)(rr.y >> 16) - GS * (int)row;
+            const uint32_t sub = (uint32_t)(x0 > 0 ? x0 : 0) | ((uint32_t)(x1 < GS - 1 ? x1 : GS - 1) << 2) |
+                                 ((uint32_t)(y0 > 0 ? y0 : 0) << 4) | ((uint32_t)(y1 < GS - 1 ? y1 : GS - 1) << 6);
+            inst_vals[o] = s_g[lo] | (sub << SR_INST_ID_BITS);
         }
         if (wend >= oe || e0 + kNT >= n_vis) break;
         __syncthreads();
     }
 }
 
+// The sorted 64-bit keys (group id << 32 | depth key).
 __global__ void __launch_bounds__(kNT)
-k_ranges(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ keys,
-         const uint32_t* __restrict__ vals, uint2* __restrict__ ranges, uint64_t* __restrict__ keys64,
-         const uint32_t* __restrict__ depth_key, const sr_camera* __restrict__ cams, int V, int N) {
+k_keys64(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ keys,
+         const uint32_t* __restrict__ vals, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ depth_key,
+         const sr_camera* __restrict__ cams, int V, int N) {
     const uint32_t n = counters[2];
     for (uint32_t i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
         const uint32_t t = keys[i];
-        if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
-        if (i + 1 == n || keys[i + 1] != t) ranges[t].y = i + 1;
-        if (keys64) {
-            const int v = view_of_tile(cams, V, (int)t);
-            keys64[i] = ((uint64_t)t << 32) | depth_key[(size_t)v * N + vals[i]];
-        }
+        const int v = view_of_group(cams, V, (int)t);
+        keys64[i] = ((uint64_t)t << 32) | depth_key[(size_t)v * N + (vals[i] & kInstIdMask)];
     }
 }
 
-// Per-tile [start, end) by binary search of the sorted tile keys, one thread
-// per tile; empty tiles get [0, 0).
+// Per tile, [start, end) of its group's run by binary search of the sorted
+// group keys, one thread per tile; empty groups give [0, 0).
 __global__ void __launch_bounds__(kNT)
 k_ranges_search(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ keys, int total_tiles,
-                uint2* __restrict__ ranges) {
-    const int t = (int)(blockIdx.x * kNT + threadIdx.x);
-    if (t >= total_tiles) return;
+                const sr_camera* __restrict__ cams, int V, uint2* __restrict__ ranges) {
+    constexpr int GS = SR_TILE_GROUP;
+    const int tile = (int)(blockIdx.x * kNT + threadIdx.x);
+    if (tile >= total_tiles) return;
+    const sr_camera& c = cams[view_of_tile(cams, V, tile)];
+    const int local = tile - c.tile_offset;
+    const int ty = local / c.tiles_x, tx = local - ty * c.tiles_x;
+    const int t = c.group_offset + (ty / GS) * c.groups_x + tx / GS;
     const uint32_t n = counters[2];
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
@@ -453,12 +477,13 @@ k_ranges_search(const uint32_t* __restrict__ counters, const uint32_t* __restric
         const uint32_t mid = lo + ((hi - lo) >> 1);
         if (keys[mid] <= (uint32_t)t) lo = mid + 1; else hi = mid;
     }
-    ranges[t] = s < lo ? make_uint2(s, lo) : make_uint2(0u, 0u);
+    ranges[tile] = s < lo ? make_uint2(s, lo) : make_uint2(0u, 0u);
 }
 
-__global__ void k_copy_u32(const uint32_t* __restrict__ counters, const uint32_t* __restrict__ src,
+// dst[0, *count) = src[0, *count)
+__global__ void k_copy_u32(const uint32_t* __restrict__ count, const uint32_t* __restrict__ src,
                            uint32_t* __restrict__ dst) {
-    const uint32_t n = counters[2];
+    const uint32_t n = *count;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
@@ -549,7 +574,8 @@ uint32_t* radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uin
 
 size_t bin_workspace_bytes(uint64_t VN, uint64_t cap) { return carve(nullptr, VN, cap).bytes; }
 
-hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams_dev,
+hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_tiles, int total_groups,
+                               const sr_camera* cams_dev,
                                const uint16_t* rect, const uint32_t* tiles_touched, const uint32_t* depth_key,
                                void* workspace, uint32_t cap, uint32_t* vals, uint64_t* keys64, uint32_t* ranges,
                                uint32_t* counters, hipStream_t s) {
@@ -582,8 +608,8 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     // after four passes the sorted pairs are in (vk0, vv0)
     // 3. instance offsets and emission in depth order
     const int Gi = Gv;
-    hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, tiles_touched, w.tts,
-                       w.isum);
+    hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, (const ushort4*)rect,
+                       cfg.tile_w, cfg.tile_h, w.tts, w.isum);
     hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap, w.itotal);
     hipLaunchKernelGGL(k_inst_offsets, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.tts, w.isum, w.ioff);
     const uint64_t emit_blocks = ((uint64_t)cap + kEmitPerBlock - 1) / kEmitPerBlock;
@@ -591,24 +617,21 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
         hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((emit_blocks + kNT - 1) / kNT)), dim3(kNT), 0, s, counters,
                            w.ioff, (uint32_t)emit_blocks, w.estart);
         hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kNT), 0, s, counters, w.itotal, N, cfg.tile_w,
-                           cfg.tile_h, cams_dev, w.vv0, tiles_touched, (const ushort4*)rect, w.ioff, w.estart, w.ik0,
-                           w.iv0);
+                           cfg.tile_h, cams_dev, w.vv0, (const ushort4*)rect, w.ioff, w.estart, w.ik0, w.iv0);
     }
-    // 4. stable sort by tile id; values land in the caller's array
+    // 4. stable sort by group id; values land in the caller's array
     int nbits = 0;
-    while ((1ull << nbits) < (uint64_t)total_tiles) ++nbits;
+    while ((1ull << nbits) < (uint64_t)total_groups) ++nbits;
     uint32_t* sorted_keys = radix_sort(w.ik0, w.iv0, w.ik1, w.iv1, vals, counters + 2, cap, nbits, w.hist,
                                        w.tot, s);
-    if (!keys64) {
-        if (total_tiles > 0)
-            hipLaunchKernelGGL(k_ranges_search, dim3((total_tiles + kNT - 1) / kNT), dim3(kNT), 0, s, counters,
-                               sorted_keys, total_tiles, (uint2*)ranges);
-        return hipGetLastError();
+    if (total_tiles > 0)
+        hipLaunchKernelGGL(k_ranges_search, dim3((total_tiles + kNT - 1) / kNT), dim3(kNT), 0, s, counters,
+                           sorted_keys, total_tiles, cams_dev, V, (uint2*)ranges);
+    if (keys64) {
+        const uint64_t rblocks = ((uint64_t)cap + kNT - 1) / kNT;
+        hipLaunchKernelGGL(k_keys64, dim3((unsigned)(rblocks < 1 ? 1 : (rblocks > 65535 ? 65535 : rblocks))),
+                           dim3(kNT), 0, s, counters, sorted_keys, vals, keys64, depth_key, cams_dev, V, N);
     }
-    const uint64_t rblocks = ((uint64_t)cap + kNT - 1) / kNT;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)(rblocks < 1 ? 1 : (rblocks > 0x7FFFFFFF ? 0x7FFFFFFF : rblocks))),
-                       dim3(kNT), 0, s, counters, sorted_keys, vals, (uint2*)ranges, keys64, depth_key, cams_dev, V,
-                       N);
     return hipGetLastError();
 }
 

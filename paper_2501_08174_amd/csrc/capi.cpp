@@ -46,27 +46,31 @@ sr_status check_cfg(const sr_config* cfg) {
 
 // Views must carry the layout sr_layout_views computes for this tile shape.
 sr_status check_views(const sr_camera* cams_host, const sr_camera* cams_dev, int V, int tw, int th,
-                      int64_t* total_pix, int* total_tiles, int64_t* max_hw) {
+                      int64_t* total_pix, int* total_tiles, int64_t* max_hw, int* total_groups = nullptr) {
     if (V < 0) return fail(SR_ERR_ARG, "V = %d < 0", V);
     if (V > 0 && (!cams_host || !cams_dev)) return fail(SR_ERR_ARG, "cams_host and cams_dev are required");
     int64_t pix = 0, mhw = 0;
-    int64_t tiles = 0;
+    int64_t tiles = 0, groups = 0;
     for (int v = 0; v < V; ++v) {
         const sr_camera& c = cams_host[v];
         if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535)
             return fail(SR_ERR_ARG, "view %d: size %dx%d outside [1, 65535]", v, c.width, c.height);
         const int tx = (c.width + tw - 1) / tw, ty = (c.height + th - 1) / th;
-        if (c.tiles_x != tx || c.tiles_y != ty || c.tile_offset != tiles || c.pix_offset != pix)
+        const int gx = (tx + SR_TILE_GROUP - 1) / SR_TILE_GROUP, gy = (ty + SR_TILE_GROUP - 1) / SR_TILE_GROUP;
+        if (c.tiles_x != tx || c.tiles_y != ty || c.tile_offset != tiles || c.pix_offset != pix ||
+            c.group_offset != groups || c.groups_x != gx)
             return fail(SR_ERR_ARG, "view %d: layout fields do not match sr_layout_views for %dx%d tiles", v, tw,
                         th);
         if (!(c.fx > 0.f && c.fy > 0.f)) return fail(SR_ERR_ARG, "view %d: focal lengths must be positive", v);
         pix += (int64_t)c.width * c.height;
         tiles += (int64_t)tx * ty;
+        groups += (int64_t)gx * gy;
         if ((int64_t)c.width * c.height > mhw) mhw = (int64_t)c.width * c.height;
     }
     if (tiles > 0x7FFFFFFF) return fail(SR_ERR_ARG, "too many tiles (%lld)", (long long)tiles);
     if (total_pix) *total_pix = pix;
     if (total_tiles) *total_tiles = (int)tiles;
+    if (total_groups) *total_groups = (int)groups;
     if (max_hw) *max_hw = mhw;
     return SR_OK;
 }
@@ -104,7 +108,7 @@ sr_status sr_layout_views(sr_camera* cams_host, int32_t V, int32_t tile_w, int32
     if (V < 0) return fail(SR_ERR_ARG, "V = %d < 0", V);
     if (tile_w < 1 || tile_h < 1) return fail(SR_ERR_ARG, "tile shape %dx%d", tile_w, tile_h);
     if (V > 0 && !cams_host) return fail(SR_ERR_ARG, "cams_host is NULL");
-    int64_t pix = 0, tiles = 0;
+    int64_t pix = 0, tiles = 0, groups = 0;
     for (int v = 0; v < V; ++v) {
         sr_camera& c = cams_host[v];
         if (c.width < 1 || c.height < 1 || c.width > 65535 || c.height > 65535)
@@ -113,6 +117,9 @@ sr_status sr_layout_views(sr_camera* cams_host, int32_t V, int32_t tile_w, int32
         c.tiles_y = (c.height + tile_h - 1) / tile_h;
         c.tile_offset = (int32_t)tiles;
         c.pix_offset = pix;
+        c.groups_x = (c.tiles_x + SR_TILE_GROUP - 1) / SR_TILE_GROUP;
+        c.group_offset = (int32_t)groups;
+        groups += (int64_t)c.groups_x * ((c.tiles_y + SR_TILE_GROUP - 1) / SR_TILE_GROUP);
         tiles += (int64_t)c.tiles_x * c.tiles_y;
         pix += (int64_t)c.width * c.height;
         if (tiles > 0x7FFFFFFF) return fail(SR_ERR_ARG, "too many tiles");
@@ -154,8 +161,11 @@ sr_status sr_bin_and_sort(const sr_config* cfg, int32_t N, int32_t V, const sr_c
                           uint32_t* vals, uint64_t* keys64, uint32_t* ranges, uint32_t* counters, void* stream) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
-    int total_tiles = 0;
-    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr));
+    if (N >= (1 << SR_INST_ID_BITS))
+        return fail(SR_ERR_UNSUPPORTED, "N = %d: binned surfel ids hold %d bits", N, SR_INST_ID_BITS);
+    int total_tiles = 0, total_groups = 0;
+    SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr,
+                       &total_groups));
     SR_NEED(counters);
     if (total_tiles > 0) SR_NEED(ranges);
     const size_t need = sr::bin_workspace_bytes((uint64_t)N * (uint64_t)V, inst_capacity);
@@ -165,7 +175,8 @@ sr_status sr_bin_and_sort(const sr_config* cfg, int32_t N, int32_t V, const sr_c
         if (inst_capacity > 0) SR_NEED(vals);
     }
     if (inst_capacity == 0xFFFFFFFFu) return fail(SR_ERR_ARG, "inst_capacity must be below 2^32 - 1");
-    return hip_status(sr::launch_bin_and_sort(*cfg, N, V, total_tiles, cams_dev, rect, tiles_touched, depth_key,
+    return hip_status(sr::launch_bin_and_sort(*cfg, N, V, total_tiles, total_groups, cams_dev, rect, tiles_touched,
+                                              depth_key,
                                               workspace, inst_capacity, vals, keys64, ranges, counters,
                                               (hipStream_t)stream),
                       "sr_bin_and_sort");

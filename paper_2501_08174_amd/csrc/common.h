@@ -40,6 +40,25 @@ __device__ __forceinline__ int view_of_tile(const sr_camera* __restrict__ cams, 
     return lo;
 }
 
+__device__ __forceinline__ int view_of_group(const sr_camera* __restrict__ cams, int V, int group) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (cams[mid].group_offset <= group) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Sorted instance values: surfel id in the low SR_INST_ID_BITS bits, the
+// surfel's tile rectangle clipped to the group (2-bit tile coordinates
+// x_lo, x_hi, y_lo, y_hi inside the group) above.
+constexpr uint32_t kInstIdMask = (1u << SR_INST_ID_BITS) - 1u;
+__device__ __forceinline__ bool inst_covers(uint32_t v, int sx, int sy) {
+    const uint32_t sub = v >> SR_INST_ID_BITS;
+    return (int)(sub & 3u) <= sx && sx <= (int)((sub >> 2) & 3u) && (int)((sub >> 4) & 3u) <= sy &&
+           sy <= (int)((sub >> 6) & 3u);
+}
+
 // ---------------------------------------------------------------------------
 // Wavefront (64 lanes) reductions with DPP row operations.  Results land in
 // lane 63.  Must be called with all 64 lanes active.

@@ -178,13 +178,19 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
         if (__syncthreads_and(done)) break;
         const uint32_t j = base + threadIdx.x;
         if (j < n) {
-            const uint32_t gg = vals[start + j];
-            const size_t r = (size_t)v * N + gg;
-            const float4 c0 = geom3[2 * r], c1 = geom3[2 * r + 1];
-            sg[0][threadIdx.x] = c0;
-            // the wave bits take the record's unused last slot
-            sg[1][threadIdx.x] = make_float4(c1.x, c1.y, c1.z,
-                                             __uint_as_float(band_bits3d<TW, NT / 64>(c0, c1, tx * TW, ty * TH)));
+            // the group's run holds entries for the other tiles of the group too
+            const uint32_t gv = vals[start + j];
+            const uint32_t gg = gv & kInstIdMask;
+            if (inst_covers(gv, tx % SR_TILE_GROUP, ty % SR_TILE_GROUP)) {
+                const size_t r = (size_t)v * N + gg;
+                const float4 c0 = geom3[2 * r], c1 = geom3[2 * r + 1];
+                sg[0][threadIdx.x] = c0;
+                // the wave bits take the record's unused last slot
+                sg[1][threadIdx.x] = make_float4(c1.x, c1.y, c1.z,
+                                                 __uint_as_float(band_bits3d<TW, NT / 64>(c0, c1, tx * TW, ty * TH)));
+            } else {
+                sg[1][threadIdx.x].w = 0.f;
+            }
             sid[threadIdx.x] = gg;
         }
         __syncthreads();

@@ -24,7 +24,8 @@ hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means
 
 size_t bin_workspace_bytes(uint64_t VN, uint64_t cap);
 
-hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams_dev,
+hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_tiles, int total_groups,
+                               const sr_camera* cams_dev,
                                const uint16_t* rect, const uint32_t* tiles_touched, const uint32_t* depth_key,
                                void* workspace, uint32_t cap, uint32_t* vals, uint64_t* keys64, uint32_t* ranges,
                                uint32_t* counters, hipStream_t s);

@@ -21,10 +21,11 @@ namespace sr {
 namespace {
 
 // Global tile id of this workgroup; pixel coordinates of this thread; the
-// pixel box [wx0, wx1] x [wy0, wy1] of this thread's wave (wave-uniform).
+// run [start, start + n) of the tile's binning group.
 struct TileCtx {
     int tile, v, W, H, ix, iy;
-    int wx0, wx1, wy0, wy1, tx0, ty0;
+    int tx0, ty0;    // first pixel column and row of the tile
+    int sx, sy;      // tile coordinates inside its binning group
     bool inside;
     int64_t pix_off;
     uint32_t start, n;
@@ -44,14 +45,10 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
     t.H = c.height;
     t.ix = tx * TW + (int)(threadIdx.x % TW);
     t.iy = ty * TH + (int)(threadIdx.x / TW);
-    // row-major lanes: the wave's first and last lanes span its pixel box
-    const int first = (int)__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63;
-    t.wx0 = tx * TW + first % TW;
-    t.wy0 = ty * TH + first / TW;
-    t.wx1 = tx * TW + (first + 63) % TW;
-    t.wy1 = ty * TH + (first + 63) / TW;
     t.tx0 = tx * TW;
     t.ty0 = ty * TH;
+    t.sx = tx % SR_TILE_GROUP;
+    t.sy = ty % SR_TILE_GROUP;
     t.inside = t.ix < t.W && t.iy < t.H;
     t.pix_off = c.pix_offset;
     t.bg[0] = c.bg[0]; t.bg[1] = c.bg[1]; t.bg[2] = c.bg[2];
@@ -162,12 +159,6 @@ __device__ __forceinline__ uint64_t wave_live_mask(const float4* __restrict__ a1
     return ballot64(k < cnt && ((__float_as_uint(a1[k].w) >> w) & 1u));
 }
 
-// The first cnt - 64 c entries of run c, without culling.
-__device__ __forceinline__ uint64_t run_mask(int c, int cnt) {
-    const int n = cnt - c * 64;
-    return n >= 64 ? ~0ull : (n <= 0 ? 0ull : ((1ull << n) - 1ull));
-}
-
 // Per-pixel state at the end of the forward pass.
 struct PixFwd {
     float T, C0, C1, C2, N0, N1, N2, S0, S1, S2, zref, zmed;
@@ -178,7 +169,7 @@ struct PixFwd {
 template <int NT, int MODE>
 struct FwdSmem {
     float4 g[kGeomF4][NT];
-    float4 a[(MODE & (kShade | kCount | kRect)) ? kAppF4 : 1][(MODE & (kShade | kCount | kRect)) ? NT : 1];
+    float4 a[kAppF4][NT];     // appearance (shading); the wave bits in a[1][.].w in every mode
     uint32_t id[(MODE & kStats) ? NT : 1];
 };
 
@@ -221,27 +212,34 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
         if (__syncthreads_and(done)) break;
         const uint32_t j = base + tid;
         if (j < t.n) {
-            const uint32_t g = vals[t.start + j];
-            const size_t r = (size_t)t.v * N + g;
-            float4 gq[kGeomF4];
+            // the group's run holds entries for the other tiles of the group too
+            const uint32_t gv = vals[t.start + j];
+            const uint32_t g = gv & kInstIdMask;
+            uint32_t bits = 0u;
+            if (inst_covers(gv, t.sx, t.sy)) {
+                const size_t r = (size_t)t.v * N + g;
+                float4 gq[kGeomF4];
 #pragma unroll
-            for (int q = 0; q < kGeomF4; ++q) {
-                gq[q] = geom[kGeomF4 * r + q];
-                sm.g[q][tid] = gq[q];
+                for (int q = 0; q < kGeomF4; ++q) {
+                    gq[q] = geom[kGeomF4 * r + q];
+                    sm.g[q][tid] = gq[q];
+                }
+                if (RECT) {
+                    // ushort4 rectangle (x_lo, x_hi, y_lo, y_hi) read as two packed ranges
+                    const uint2 rr = rect[r];
+                    const float4 a1 = make_float4(0.f, 0.f, __uint_as_float(rr.x), __uint_as_float(rr.y));
+                    bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                } else if (CULL) {
+                    const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
+                    // the band bits replace the packed rectangle once it has served
+                    bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                    sm.a[0][tid] = a0;
+                    sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
+                } else {
+                    bits = (1u << (NT / 64)) - 1u;
+                }
             }
-            if (RECT) {
-                // ushort4 rectangle (x_lo, x_hi, y_lo, y_hi) read as two packed ranges
-                const uint2 rr = rect[r];
-                const float4 a1 = make_float4(0.f, 0.f, __uint_as_float(rr.x), __uint_as_float(rr.y));
-                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
-                sm.a[1][tid] = make_float4(0.f, 0.f, 0.f, __uint_as_float(bits));
-            } else if (CULL) {
-                const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
-                // the band bits replace the packed rectangle once it has served
-                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
-                sm.a[0][tid] = a0;
-                sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
-            }
+            if (!CULL || RECT || bits == 0u) reinterpret_cast<float*>(&sm.a[1][tid])[3] = __uint_as_float(bits);
             if (STATS) sm.id[tid] = g;
         }
         __syncthreads();
@@ -249,7 +247,7 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
         if (ballot64(!done) == 0ull) continue;
         bool wave_done = false;
         for (int c = 0; c * 64 < cnt && !wave_done; ++c) {
-          uint64_t live = CULL ? wave_live_mask(sm.a[1], c, cnt) : run_mask(c, cnt);
+          uint64_t live = wave_live_mask(sm.a[1], c, cnt);
           while (live != 0ull) {
             const int k = c * 64 + (int)__builtin_ctzll(live);
             live &= live - 1ull;
@@ -461,19 +459,24 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
         if (tid < BATCH) {
             const uint32_t j = (uint32_t)base + tid;
             if (j < maxn) {
-                const uint32_t g = vals[t.start + j];
-                const size_t r = (size_t)t.v * N + g;
-                float4 gq[kGeomF4];
+                const uint32_t gv = vals[t.start + j];
+                uint32_t bits = 0u, rec = 0u;
+                if (inst_covers(gv, t.sx, t.sy)) {
+                    const size_t r = (size_t)t.v * N + (gv & kInstIdMask);
+                    float4 gq[kGeomF4];
 #pragma unroll
-                for (int q = 0; q < kGeomF4; ++q) {
-                    gq[q] = geom[kGeomF4 * r + q];
-                    sm.g[q][tid] = gq[q];
+                    for (int q = 0; q < kGeomF4; ++q) {
+                        gq[q] = geom[kGeomF4 * r + q];
+                        sm.g[q][tid] = gq[q];
+                    }
+                    const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
+                    bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                    sm.a[0][tid] = a0;
+                    sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
+                    rec = (uint32_t)r;
                 }
-                const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
-                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
-                sm.a[0][tid] = a0;
-                sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
-                sm.rec[tid] = (uint32_t)r;
+                if (bits == 0u) reinterpret_cast<float*>(&sm.a[1][tid])[3] = 0.f;
+                sm.rec[tid] = rec;
             }
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) sm.acc[tid][i] = 0.f;

@@ -92,6 +92,18 @@ class Params:
         return Params(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opac), f(scene.sh))
 
 
+def group_instances(rect: torch.Tensor, tiles_touched: torch.Tensor, VN: int, tile) -> int:
+    """Instances sr_bin_and_sort will emit: per visible record, the
+    SR_TILE_GROUP x SR_TILE_GROUP tile groups its rectangle meets (syncs)."""
+    if VN == 0:
+        return 0
+    r = rect[: 4 * VN].view(VN, 4).to(torch.int64) & 0xFFFF
+    G = _lib.SR_TILE_GROUP
+    gx = (r[:, 1] // tile[0]) // G - (r[:, 0] // tile[0]) // G + 1
+    gy = (r[:, 3] // tile[1]) // G - (r[:, 2] // tile[1]) // G + 1
+    return int(torch.where(tiles_touched[:VN] > 0, gx * gy, torch.zeros_like(gx)).sum().item())
+
+
 class Rasterizer:
     """Persistent device buffers for one (N, views, tile shape, capacity).
 
@@ -145,7 +157,7 @@ class Rasterizer:
     def plan_capacity(self, params: Params, slack: float = 1.05) -> int:
         """Projects once and sizes the instance buffers (one host sync)."""
         self.preprocess(params)
-        need = int(self.tiles_touched.to(torch.int64).sum().item())
+        need = group_instances(self.rect, self.tiles_touched, self.views.V * self.N, self.views.tile)
         self.set_capacity(int(need * slack) + 1024)
         return need
 
@@ -550,7 +562,7 @@ class Pruner3D:
 
     def plan_capacity(self, means, scales, quats, opac, slack: float = 1.05) -> int:
         self.preprocess(means, scales, quats, opac)
-        need = int(self.tiles_touched.to(torch.int64).sum().item())
+        need = group_instances(self.rect, self.tiles_touched, self.views.V * self.N, self.views.tile)
         self.set_capacity(int(need * slack) + 1024)
         return need
 

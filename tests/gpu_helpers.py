@@ -57,6 +57,19 @@ def geometry(scene, rp=oracle.RasterParams()):
     return [oracle.view_geometry64(scene.means, scene.scales, scene.quats, scene.opac, c, rp) for c in scene.cams]
 
 
+ID_MASK = np.uint32(0xFFFFFF)   # surfel-id bits of a sorted instance value
+
+
+def group_instances(geoms, group=4):
+    """Instances of grouped binning: per visible record, the tile groups its
+    tile rectangle meets."""
+    n = 0
+    for g in geoms:
+        t = g["tiles"][~g["culled"]]
+        n += int(((t[:, 1] // group - t[:, 0] // group + 1) * (t[:, 3] // group - t[:, 2] // group + 1)).sum())
+    return n
+
+
 def compare_binning(scene, run, geoms, rp=oracle.RasterParams(), full_sort=True):
     """Bit-exact comparison of the per-(view, surfel) binning outputs and,
     when ``full_sort``, of the whole sorted instance list and the ranges."""
@@ -78,9 +91,9 @@ def compare_binning(scene, run, geoms, rp=oracle.RasterParams(), full_sort=True)
     vis, need, stored, status = run["status"]
     assert status == 0
     assert vis == sum(int((~g["culled"]).sum()) for g in geoms)
-    assert need == stored == sum(int(g["tiles_touched"].sum()) for g in geoms)
+    assert need == stored == group_instances(geoms)
     if full_sort:
-        keys, vals, ranges = oracle.bin64(geoms, scene.cams, rp)
+        keys, vals, ranges = oracle.bin64(geoms, scene.cams, rp, group=4)
         gv = rast.vals[:need].cpu().numpy().view(np.uint32)
         gr = rast.ranges[: 2 * rast.views.T].cpu().numpy().view(np.uint32).reshape(-1, 2)
         np.testing.assert_array_equal(gv, vals)
@@ -129,7 +142,7 @@ def compare_forward(gpu_view, res, pix, rast=None, v=None, tol=FWD_TOL):
         tw, th = views.tile
         tile = T0 + (j // th) * tx + (i // tw)
         rg = rast.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
-        vals = rast.vals.cpu().numpy().view(np.uint32).astype(np.int64)
+        vals = (rast.vals.cpu().numpy().view(np.uint32) & ID_MASK).astype(np.int64)
         nc = gpu_view["n_contrib"][j, i].astype(np.int64)
         last = np.where(nc > 0, vals[np.minimum(rg[tile, 0] + np.maximum(nc - 1, 0), vals.size - 1)], -1)
         ok = ~f_ct

@@ -13,7 +13,7 @@ import oracle
 from oracle.render import Params64, render_pixels
 from paper_2501_08174_amd import scenes
 from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch, rasterize, prune_mask
-from tests.gpu_helpers import compare_forward, crop_pixels, gpu_run, per_view
+from tests.gpu_helpers import compare_forward, crop_pixels, gpu_run, group_instances, per_view
 
 pytestmark = pytest.mark.gpu
 RP = oracle.RasterParams()
@@ -70,14 +70,16 @@ def _sampled_tiles(sc, run, geoms, n_tiles=48, seed=0):
         h = views.host[v]
         t = int(rng.integers(0, h.tiles_x * h.tiles_y))
         want = _tile_list(geoms[v], h.tiles_x, t)
-        s, e = rg[h.tile_offset + t]
-        np.testing.assert_array_equal(vals[s:e], want)
+        tx, ty = t % h.tiles_x, t // h.tiles_x
+        ids, pos = oracle.tile_list(vals, rg, h.tile_offset + t, (tx, ty))
+        np.testing.assert_array_equal(ids, want)
         if k64 is not None:
-            exp = (np.uint64(h.tile_offset + t) << np.uint64(32)) | geoms[v]["depth_bits"][want].astype(np.uint64)
-            np.testing.assert_array_equal(k64[s:e], exp)
-    # global properties: ranges partition [0, n_inst) in tile order
+            grp = h.group_offset + (ty // 4) * h.groups_x + tx // 4
+            exp = (np.uint64(grp) << np.uint64(32)) | geoms[v]["depth_bits"][want].astype(np.uint64)
+            np.testing.assert_array_equal(k64[pos], exp)
+    # global properties: the groups' runs partition [0, n_inst) in group order
     n = run["status"][2]
-    nz = rg[rg[:, 1] > rg[:, 0]]
+    nz = np.unique(rg[rg[:, 1] > rg[:, 0]], axis=0)
     assert nz[0, 0] == 0 and nz[-1, 1] == n and np.all(nz[1:, 0] == nz[:-1, 1])
 
 
@@ -218,7 +220,7 @@ def test_config3_full_size():
     print("config3 records bit-exact; grid-tie exemptions", ex)
     vis, need, stored, status = run["status"]
     assert status == 0 and vis == sum(int((~g["culled"]).sum()) for g in geoms.values())
-    assert need == sum(int(g["tiles_touched"].sum()) for g in geoms.values())
+    assert need == group_instances(list(geoms.values()))
     _sampled_tiles(sc, run, geoms)
     P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3)
     rng = np.random.default_rng(3)

@@ -46,7 +46,7 @@ def _median_gids(rast, v, pix):
     tw, th = views.tile
     tile = int(views.host[v].tile_offset) + (j // th) * int(views.host[v].tiles_x) + (i // tw)
     rg = rast.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
-    vals = rast.vals.cpu().numpy().view(np.uint32).astype(np.int64)
+    vals = (rast.vals.cpu().numpy().view(np.uint32) & np.uint32(0xFFFFFF)).astype(np.int64)
     mc = rast.median_contrib[o: o + W * H].cpu().numpy().view(np.uint32).reshape(H, W)[j, i].astype(np.int64)
     gid = np.where(mc > 0, vals[np.minimum(rg[tile, 0] + np.maximum(mc - 1, 0), vals.size - 1)], -1)
     md = rast.median_depth[o: o + W * H].cpu().numpy().reshape(H, W)[j, i]
