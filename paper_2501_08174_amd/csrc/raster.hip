@@ -57,6 +57,13 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
     t.n = rg.y - rg.x;
 }
 
+constexpr int kMaxWaves = 8;    // waves per workgroup (tiles of up to 512 pixels)
+
+// Five waves per SIMD: the register budget (at most 96 VGPRs, no spills)
+// that keeps the compositing kernels issue-bound; the compiler would
+// otherwise spend up to 104 registers and drop to four.
+#define SR_RASTER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(5)))
+
 // MODE bits: 1 shade (colour, depth, normal, distortion outputs), 2 occlusion
 // statistics, 4 count reached/blended pairs (work accounting), 8 median depth
 // (the 2DGS surface depth: the depth of the last blended entry that starts
@@ -159,6 +166,19 @@ __device__ __forceinline__ uint64_t wave_live_mask(const float4* __restrict__ a1
     return ballot64(k < cnt && ((__float_as_uint(a1[k].w) >> w) & 1u));
 }
 
+// The same for the slots [lo, hi), keeping only run positions below maxpos.
+__device__ __forceinline__ uint64_t wave_live_mask_from(const float4* __restrict__ a1, int c, int lo, int hi,
+                                                        uint32_t maxpos) {
+    const int k = c * 64 + __lane_id();
+    const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6;
+    bool live = k >= lo && k < hi;
+    if (live) {
+        const float4 r = a1[k];
+        live = ((__float_as_uint(r.w) >> w) & 1u) && __float_as_uint(r.z) < maxpos;
+    }
+    return ballot64(live);
+}
+
 // Per-pixel state at the end of the forward pass.
 struct PixFwd {
     float T, C0, C1, C2, N0, N1, N2, S0, S1, S2, zref, zmed;
@@ -169,19 +189,72 @@ struct PixFwd {
 template <int NT, int MODE>
 struct FwdSmem {
     float4 g[kGeomF4][NT];
-    float4 a[kAppF4][NT];     // appearance (shading); the wave bits in a[1][.].w in every mode
+    // appearance (shading) in a[0], a[1].xy; the run position of the entry in
+    // a[1].z and the wave bits in a[1].w in every mode
+    float4 a[kAppF4][NT];
     uint32_t id[(MODE & kStats) ? NT : 1];
+    uint32_t wcnt[NT / 64 + 1];   // gathering: members per wave, then the resume position
 };
 
 // LDS staging and per-record accumulators of the backward.
 template <int BATCH>
 struct BwdSmem {
     float4 g[kGeomF4][BATCH];
-    float4 a[kAppF4][BATCH];
+    float4 a[kAppF4][BATCH];      // as in the forward: a[1].z run position, a[1].w wave bits
     uint32_t rec[BATCH];
     float acc[BATCH][kNumGrad];
     uint32_t maxn;
+    uint32_t wcnt[kMaxWaves + 1];
 };
+
+// Gathering of a batch from the tile's group run: the NT threads examine NT
+// run positions at once, keep the entries whose sub-rectangle covers the
+// tile, and place them in consecutive batch slots by a block-wide rank
+// (wave ballots, per-wave counts in LDS).  With ASC the slots [fill, cap)
+// receive the members of [pos, pos + NT) in run order; otherwise slots
+// (cap - 1 - fill) downwards receive the members of [pos - NT, pos), highest
+// position first.  A round that overfills the batch stops after the last
+// member placed and reports where the next batch resumes.  Returns the
+// number of members placed in this round; block-uniform.
+template <int NT, bool ASC>
+__device__ __forceinline__ int gather_round(const TileCtx& t, const uint32_t* __restrict__ vals, int64_t pos,
+                                            int fill, int cap, float4* __restrict__ a0, float4* __restrict__ a1,
+                                            uint32_t* wcnt, int64_t& next) {
+    const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+    const int64_t j = ASC ? pos + tid : pos - NT + tid;
+    const bool in = ASC ? j < (int64_t)t.n : j >= 0;
+    const uint32_t gv = in ? vals[t.start + (uint32_t)j] : 0u;
+    const bool mem = in && inst_covers(gv, t.sx, t.sy);
+    const uint64_t bm = ballot64(mem);
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) wcnt[w] = (uint32_t)__popcll(bm);
+    __syncthreads();
+    int before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const int c = (int)wcnt[i];
+        before += i < w ? c : 0;
+        tot += c;
+    }
+    const int r_asc = before + __popcll(bm & lt);
+    const int rank = ASC ? r_asc : tot - 1 - r_asc;          // order of placement
+    const int taken = fill + rank;
+    if (mem && taken < cap) {
+        const int slot = ASC ? taken : cap - 1 - taken;
+        a0[slot].x = __uint_as_float(gv);
+        a1[slot].z = __uint_as_float((uint32_t)j);
+        if (taken == cap - 1 && fill + tot > cap) wcnt[NT / 64] = (uint32_t)(ASC ? j + 1 : j);
+    }
+    __syncthreads();
+    if (fill + tot <= cap) {
+        next = ASC ? pos + NT : (pos - NT > 0 ? pos - NT : 0);
+    } else {
+        next = (int64_t)wcnt[NT / 64];
+        tot = cap - fill;
+    }
+    __syncthreads();                                          // wcnt is reused by the next round
+    return tot;
+}
 
 // Front to back over the tile list; every thread owns one pixel.
 template <int TW, int NT, int MODE>
@@ -208,42 +281,45 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     st.last = st.kmed = 0;
     bool have_ref = false;
     bool done = !t.inside;
-    for (uint32_t base = 0; base < t.n; base += NT) {
+    // batches of up to NT entries of the tile, gathered from its group's run
+    int64_t pos = 0;
+    while (pos < (int64_t)t.n) {
         if (__syncthreads_and(done)) break;
-        const uint32_t j = base + tid;
-        if (j < t.n) {
-            // the group's run holds entries for the other tiles of the group too
-            const uint32_t gv = vals[t.start + j];
+        int cnt = 0;
+        while (cnt < NT && pos < (int64_t)t.n) {
+            int64_t next;
+            cnt += gather_round<NT, true>(t, vals, pos, cnt, NT, sm.a[0], sm.a[1], sm.wcnt, next);
+            pos = next;
+        }
+        if (tid < cnt) {
+            const uint32_t gv = __float_as_uint(sm.a[0][tid].x);
+            const uint32_t jpos = __float_as_uint(sm.a[1][tid].z);
             const uint32_t g = gv & kInstIdMask;
-            uint32_t bits = 0u;
-            if (inst_covers(gv, t.sx, t.sy)) {
-                const size_t r = (size_t)t.v * N + g;
-                float4 gq[kGeomF4];
+            const size_t r = (size_t)t.v * N + g;
+            float4 gq[kGeomF4];
 #pragma unroll
-                for (int q = 0; q < kGeomF4; ++q) {
-                    gq[q] = geom[kGeomF4 * r + q];
-                    sm.g[q][tid] = gq[q];
-                }
-                if (RECT) {
-                    // ushort4 rectangle (x_lo, x_hi, y_lo, y_hi) read as two packed ranges
-                    const uint2 rr = rect[r];
-                    const float4 a1 = make_float4(0.f, 0.f, __uint_as_float(rr.x), __uint_as_float(rr.y));
-                    bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
-                } else if (CULL) {
-                    const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
-                    // the band bits replace the packed rectangle once it has served
-                    bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
-                    sm.a[0][tid] = a0;
-                    sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
-                } else {
-                    bits = (1u << (NT / 64)) - 1u;
-                }
+            for (int q = 0; q < kGeomF4; ++q) {
+                gq[q] = geom[kGeomF4 * r + q];
+                sm.g[q][tid] = gq[q];
             }
-            if (!CULL || RECT || bits == 0u) reinterpret_cast<float*>(&sm.a[1][tid])[3] = __uint_as_float(bits);
+            uint32_t bits = (1u << (NT / 64)) - 1u;
+            float2 n12 = make_float2(0.f, 0.f);
+            if (RECT) {
+                // ushort4 rectangle (x_lo, x_hi, y_lo, y_hi) read as two packed ranges
+                const uint2 rr = rect[r];
+                const float4 a1 = make_float4(0.f, 0.f, __uint_as_float(rr.x), __uint_as_float(rr.y));
+                bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+            } else if (CULL) {
+                const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
+                bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                sm.a[0][tid] = a0;
+                n12 = make_float2(a1.x, a1.y);
+            }
+            // the run position and the wave bits replace the packed rectangle
+            sm.a[1][tid] = make_float4(n12.x, n12.y, __uint_as_float(jpos), __uint_as_float(bits));
             if (STATS) sm.id[tid] = g;
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)NT, t.n - base);
         if (ballot64(!done) == 0ull) continue;
         bool wave_done = false;
         for (int c = 0; c * 64 < cnt && !wave_done; ++c) {
@@ -286,12 +362,13 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 st.S0 += wgt;
                 st.S1 = __builtin_fmaf(wgt, zs, st.S1);
                 st.S2 = __builtin_fmaf(wgt * zs, zs, st.S2);
+                const uint32_t jpos = __float_as_uint(sm.a[1][k].z);    // run position
                 if (MEDIAN && st.T > 0.5f) {         // T before this entry
                     st.zmed = e.z;
-                    st.kmed = base + (uint32_t)k + 1u;
+                    st.kmed = jpos + 1u;
                 }
                 st.T = Tn;
-                st.last = base + (uint32_t)k + 1u;
+                st.last = jpos + 1u;
                 if (COUNT) n_eval_last = n_eval;
             }
             if (COUNT) n_blended += (uint64_t)__popcll(ballot64(blend));
@@ -358,7 +435,7 @@ __device__ __forceinline__ void write_outputs(const PixFwd& st, const PixOut& o,
 }
 
 template <int TW, int TH, int MODE>
-__global__ void __launch_bounds__(TW * TH)
+__global__ void __launch_bounds__(TW * TH) SR_RASTER_OCCUPANCY
 k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
              const float4* __restrict__ app, const uint2* __restrict__ rect, const uint32_t* __restrict__ vals,
              const uint2* __restrict__ ranges,
@@ -454,44 +531,49 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
     }
     wave_maxn = __builtin_amdgcn_readfirstlane(wave_maxn);   // uniform: keep the loop control scalar
     float T = pb.T, Wacc = pb.Wacc;
-    for (int64_t base = ((int64_t)(maxn - 1) / BATCH) * BATCH; base >= 0; base -= BATCH) {
+    static_assert(NT / 64 <= kMaxWaves, "gathering counts");
+    // batches of up to BATCH entries of the tile below run position hi,
+    // gathered from its group's run highest first into slots [lo, BATCH)
+    int64_t hi = maxn;
+    while (hi > 0) {
         __syncthreads();
+        int fill = 0;
+        while (fill < BATCH && hi > 0) {
+            int64_t next;
+            fill += gather_round<NT, false>(t, vals, hi, fill, BATCH, sm.a[0], sm.a[1], sm.wcnt, next);
+            hi = next;
+        }
+        const int lo = BATCH - fill;
         if (tid < BATCH) {
-            const uint32_t j = (uint32_t)base + tid;
-            if (j < maxn) {
-                const uint32_t gv = vals[t.start + j];
-                uint32_t bits = 0u, rec = 0u;
-                if (inst_covers(gv, t.sx, t.sy)) {
-                    const size_t r = (size_t)t.v * N + (gv & kInstIdMask);
-                    float4 gq[kGeomF4];
+            if (tid >= lo) {
+                const uint32_t gv = __float_as_uint(sm.a[0][tid].x);
+                const uint32_t jpos = __float_as_uint(sm.a[1][tid].z);
+                const size_t r = (size_t)t.v * N + (gv & kInstIdMask);
+                float4 gq[kGeomF4];
 #pragma unroll
-                    for (int q = 0; q < kGeomF4; ++q) {
-                        gq[q] = geom[kGeomF4 * r + q];
-                        sm.g[q][tid] = gq[q];
-                    }
-                    const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
-                    bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
-                    sm.a[0][tid] = a0;
-                    sm.a[1][tid] = make_float4(a1.x, a1.y, a1.z, __uint_as_float(bits));
-                    rec = (uint32_t)r;
+                for (int q = 0; q < kGeomF4; ++q) {
+                    gq[q] = geom[kGeomF4 * r + q];
+                    sm.g[q][tid] = gq[q];
                 }
-                if (bits == 0u) reinterpret_cast<float*>(&sm.a[1][tid])[3] = 0.f;
-                sm.rec[tid] = rec;
+                const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
+                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                sm.a[0][tid] = a0;
+                // entries at or beyond the wave's last contributor concern no lane of it
+                sm.a[1][tid] = make_float4(a1.x, a1.y, __uint_as_float(jpos), __uint_as_float(bits));
+                sm.rec[tid] = (uint32_t)r;
             }
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) sm.acc[tid][i] = 0.f;
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)BATCH, maxn - (uint32_t)base);
-        const int kmax = (int)min((int64_t)cnt, (int64_t)wave_maxn - base);
         // entries skipped by the forward for this wave are skipped here too
-        for (int c = (kmax - 1) >> 6; c >= 0; --c) {
-          uint64_t live = wave_live_mask(sm.a[1], c, kmax);
+        for (int c = (BATCH - 1) >> 6; c >= (lo >> 6); --c) {
+          uint64_t live = wave_live_mask_from(sm.a[1], c, lo, BATCH, wave_maxn);
           while (live != 0ull) {
             const int hb = 63 - (int)__builtin_clzll(live);
             live &= ~(1ull << hb);
             const int k = c * 64 + hb;
-            const uint32_t jj = (uint32_t)base + (uint32_t)k;
+            const uint32_t jj = __float_as_uint(sm.a[1][k].z);    // run position
             PairEval e;
             const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
             eval_test(sm.g[0][k], sm.g[1][k], g2, g3, px, py, e);
@@ -563,7 +645,7 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
           }
         }
         __syncthreads();
-        if (tid < cnt) {
+        if (tid >= lo && tid < BATCH) {
             float* dst = grad_rec + (size_t)sm.rec[tid] * SR_GRAD_STRIDE;
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) {
@@ -575,7 +657,7 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
 }
 
 template <int TW, int TH, int BATCH, bool GEO>
-__global__ void __launch_bounds__(TW * TH)
+__global__ void __launch_bounds__(TW * TH) SR_RASTER_OCCUPANCY
 k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
              const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
              RasterConsts rc, const float* __restrict__ alpha, const float* __restrict__ depth,
@@ -614,7 +696,7 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
 // registers between the phases.  Per-tile loss partial sums go to
 // tile_loss[2*tile] (L_b numerator, L1 numerator).
 template <int TW, int TH, int BATCH, bool STATS>
-__global__ void __launch_bounds__(TW * TH)
+__global__ void __launch_bounds__(TW * TH) SR_RASTER_OCCUPANCY
 k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
                const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
                RasterConsts rc, const uint8_t* __restrict__ mask, const float* __restrict__ target, float gamma,
