@@ -361,7 +361,7 @@ sr_status sr_regularizer_loss(int32_t V, const sr_camera* cams_host, const sr_ca
     SR_NEED(loss); SR_NEED(workspace); SR_NEED(dL_dalpha); SR_NEED(dL_ddepth); SR_NEED(dL_dnormal);
     SR_NEED(dL_ddist);
     if ((median == nullptr) != (dL_dmedian == nullptr)) return fail(SR_ERR_ARG, "median and dL_dmedian go together");
-    int64_t pix = 0;
+    int64_t pix = 0, tt = 0;
     int mt = 0;
     for (int v = 0; v < V; ++v) {
         const sr_camera& c = cams_host[v];
@@ -371,16 +371,19 @@ sr_status sr_regularizer_loss(int32_t V, const sr_camera* cams_host, const sr_ca
         pix += (int64_t)c.width * c.height;
         const int t = sr::reg_tile_count(c.width, c.height);
         if (t > mt) mt = t;
+        tt += t;
     }
+    if (tt > 0x7FFFFFFF) return fail(SR_ERR_ARG, "too many regulariser tiles");
     if (ws_bytes < sr::loss_workspace_bytes(V, 0, mt)) return fail(SR_ERR_ARG, "regularizer workspace too small");
-    return hip_status(sr::launch_reg_loss(V, mt, cams_dev, alpha, depth, normal, dist, median, w_dist, w_normal,
+    return hip_status(sr::launch_reg_loss(V, mt, (int)tt, cams_dev, alpha, depth, normal, dist, median, w_dist, w_normal,
                                           workspace, loss, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist, dL_dmedian,
                                           (hipStream_t)stream),
                       "sr_regularizer_loss");
 }
 
-static sr_status ssim_sizes(int32_t V, const sr_camera* cams_host, int* max_slots, int64_t* P) {
-    int64_t pix = 0;
+static sr_status ssim_sizes(int32_t V, const sr_camera* cams_host, int* max_slots, int64_t* P,
+                            int* total_slots = nullptr) {
+    int64_t pix = 0, tot = 0;
     int ms = 0;
     for (int v = 0; v < V; ++v) {
         const sr_camera& c = cams_host[v];
@@ -389,9 +392,12 @@ static sr_status ssim_sizes(int32_t V, const sr_camera* cams_host, int* max_slot
         pix += (int64_t)c.width * c.height;
         const int t = sr::ssim_slots(c.width, c.height);
         if (t > ms) ms = t;
+        tot += t;
     }
+    if (tot > 0x7FFFFFFF) return fail(SR_ERR_ARG, "too many SSIM tiles");
     *max_slots = ms;
     *P = pix;
+    if (total_slots) *total_slots = (int)tot;
     return SR_OK;
 }
 
@@ -414,12 +420,12 @@ sr_status sr_ssim_loss(int32_t V, const sr_camera* cams_host, const sr_camera* c
     if (V == 0) return SR_OK;
     SR_NEED(cams_host); SR_NEED(cams_dev); SR_NEED(color); SR_NEED(target); SR_NEED(mask); SR_NEED(workspace);
     SR_NEED(out);
-    int ms = 0;
+    int ms = 0, tot = 0;
     int64_t P = 0;
-    SR_TRY(ssim_sizes(V, cams_host, &ms, &P));
+    SR_TRY(ssim_sizes(V, cams_host, &ms, &P, &tot));
     if (ws_bytes < sr::ssim_workspace_bytes(V, ms, P, dL_dcolor != nullptr))
         return fail(SR_ERR_ARG, "ssim workspace too small");
-    return hip_status(sr::launch_ssim(V, ms, P, cams_dev, color, target, mask, w_s, workspace, out, dL_dcolor,
+    return hip_status(sr::launch_ssim(V, ms, tot, P, cams_dev, color, target, mask, w_s, workspace, out, dL_dcolor,
                                       (hipStream_t)stream),
                       "sr_ssim_loss");
 }

@@ -67,7 +67,8 @@ int reg_tile_count(int W, int H);
 hipError_t launch_loss(int V, int64_t max_hw, const sr_camera* cams, const float* alpha, const uint8_t* mask,
                        const float* color, const float* target, float gamma, float w_c, void* ws, float* loss,
                        float* dL_dalpha, float* dL_dcolor, hipStream_t s);
-hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const float* alpha, const float* depth,
+hipError_t launch_reg_loss(int V, int max_tiles, int total_tiles, const sr_camera* cams, const float* alpha,
+                           const float* depth,
                            const float* normal, const float* dist, const float* median, float w_dist,
                            float w_normal, void* ws, float* loss, float* dL_dalpha, float* dL_ddepth,
                            float* dL_dnormal, float* dL_ddist, float* dL_dmedian, hipStream_t s);
@@ -85,7 +86,7 @@ hipError_t launch_compact(int N, const uint8_t* prune, const float* opac, float 
                           uint32_t* n_kept, hipStream_t s);
 int ssim_slots(int W, int H);
 size_t ssim_workspace_bytes(int V, int max_slots, int64_t P, bool with_grad);
-hipError_t launch_ssim(int V, int max_slots, int64_t P, const sr_camera* cams, const float* color,
+hipError_t launch_ssim(int V, int max_slots, int total_slots, int64_t P, const sr_camera* cams, const float* color,
                        const float* target, const uint8_t* mask, float w_s, void* ws, float* out,
                        float* dL_dcolor, hipStream_t s);
 

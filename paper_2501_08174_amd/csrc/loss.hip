@@ -168,13 +168,18 @@ k_reg_partial(const sr_camera* __restrict__ cams, int V, const float* __restrict
     __shared__ float s[kNT];
     __shared__ float3 sP[kRegPY][kRegPX];
     __shared__ float3 sGa[kRegNY][kRegNX], sGb[kRegNY][kRegNX], sNd[kRegNY][kRegNX];
-    const int v = blockIdx.y;
+    // one flat grid over the tiles of all views
+    int v = 0, tile = (int)blockIdx.x;
+    for (; v < V; ++v) {
+        const int nt = reg_tiles(cams[v].width, cams[v].height);
+        if (tile < nt) break;
+        tile -= nt;
+    }
+    if (v >= V) return;                                     // uniform: the whole block leaves
     const sr_camera& c = cams[v];
     const int W = c.width, H = c.height;
     const int ntx = (W + kRegTX - 1) / kRegTX;
-    const int ntiles = ntx * ((H + kRegTY - 1) / kRegTY);
-    if ((int)blockIdx.x >= ntiles) return;                  // uniform: the whole block leaves
-    const int ty = (int)blockIdx.x / ntx, tx = (int)blockIdx.x - ty * ntx;
+    const int ty = tile / ntx, tx = tile - ty * ntx;
     const int x0 = tx * kRegTX, y0 = ty * kRegTY;
     const int64_t HW = (int64_t)W * H;
     const float* A = alpha + c.pix_offset;
@@ -271,8 +276,8 @@ k_reg_partial(const sr_camera* __restrict__ cams, int V, const float* __restrict
     ld = block_sum(ld, s);
     ln = block_sum(ln, s);
     if (threadIdx.x == 0) {
-        partial[2 * ((size_t)v * nslot + blockIdx.x)] = ld;
-        partial[2 * ((size_t)v * nslot + blockIdx.x) + 1] = ln;
+        partial[2 * ((size_t)v * nslot + tile)] = ld;
+        partial[2 * ((size_t)v * nslot + tile) + 1] = ln;
     }
 }
 
@@ -310,12 +315,13 @@ k_reg_total(int V, float w_dist, float w_normal, float* __restrict__ loss) {
 
 int reg_tile_count(int W, int H) { return reg_tiles_of(W, H); }
 
-hipError_t launch_reg_loss(int V, int max_tiles, const sr_camera* cams, const float* alpha, const float* depth,
+hipError_t launch_reg_loss(int V, int max_tiles, int total_tiles, const sr_camera* cams, const float* alpha,
+                           const float* depth,
                            const float* normal, const float* dist, const float* median, float w_dist,
                            float w_normal, void* ws, float* loss, float* dL_dalpha, float* dL_ddepth,
                            float* dL_dnormal, float* dL_ddist, float* dL_dmedian, hipStream_t s) {
     if (V == 0 || max_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reg_partial, dim3(max_tiles, V), dim3(kNT), 0, s, cams, V, alpha, depth, normal, dist,
+    hipLaunchKernelGGL(k_reg_partial, dim3(total_tiles), dim3(kNT), 0, s, cams, V, alpha, depth, normal, dist,
                        median, w_dist, w_normal, max_tiles, (float*)ws, dL_dalpha, dL_ddepth, dL_dnormal, dL_ddist,
                        dL_dmedian);
     hipLaunchKernelGGL(k_reg_final, dim3(V), dim3(kNT), 0, s, cams, V, max_tiles, (const float*)ws, loss);

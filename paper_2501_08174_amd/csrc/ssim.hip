@@ -8,13 +8,14 @@
 //   SSIM_v = mean of S over channels and pixels; L = (1/V) sum_v w_s (1 - SSIM_v)
 //   PSNR_v = -10 log10(mean (x - y)^2)
 //
-// Forward: per 32x8 tile and channel, x and y with a five-pixel halo go to
+// Forward: per 32x16 tile and channel, x and y with a five-pixel halo go to
 // LDS, a horizontal then a vertical 11-tap pass give the five filtered
 // moments, and each pixel forms S and dL/d{mu_x, E[x^2], E[xy]}.  Backward:
 // those three maps are filtered the same way (the window is symmetric, so
 // the adjoint of the correlation is the same correlation) and combined with
-// x and y into dL/dR = M dL/dx.  Per-tile sums are reduced per view in a
-// fixed order.
+// x and y into dL/dR = M dL/dx.  One flat grid over the (view, channel,
+// tile) slots of all views; every thread finishes two pixels of its tile.
+// Per-tile sums are reduced per view in a fixed order.
 #include <cmath>
 
 #include "common.h"
@@ -25,7 +26,7 @@ namespace sr {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kTX = 32, kTY = 8;                      // output tile
+constexpr int kTX = 32, kTY = 16;                     // output tile (two rows per thread)
 constexpr int kR = 5;                                 // window radius
 constexpr int kHX = kTX + 2 * kR, kHY = kTY + 2 * kR; // tile with halo
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
@@ -48,28 +49,35 @@ __device__ __forceinline__ float block_sum(float v, float* s) {
     return r;
 }
 
-// Tile, channel and view of this workgroup; false when the slot is unused.
+// Tile, channel and view of this workgroup (slot = its index among the
+// view's 3 * tiles slots); false past the last view.
 struct SsimTile {
     int v, ch, x0, y0, W, H, slot;
     int64_t HW, off;
 };
 
-__device__ __forceinline__ bool ssim_tile(const sr_camera* cams, SsimTile& t) {
-    t.v = blockIdx.y;
+__device__ __forceinline__ bool ssim_tile(const sr_camera* cams, int V, SsimTile& t) {
+    int b = (int)blockIdx.x, v = 0;
+    for (; v < V; ++v) {
+        const int ns = 3 * tiles_of(cams[v].width, cams[v].height);
+        if (b < ns) break;
+        b -= ns;
+    }
+    if (v >= V) return false;
+    t.v = v;
     const sr_camera& c = cams[t.v];
     t.W = c.width;
     t.H = c.height;
     const int nt = tiles_of(t.W, t.H);
-    if ((int)blockIdx.x >= 3 * nt) return false;
-    t.ch = (int)blockIdx.x / nt;
-    const int tile = (int)blockIdx.x - t.ch * nt;
+    t.ch = b / nt;
+    const int tile = b - t.ch * nt;
     const int ntx = (t.W + kTX - 1) / kTX;
     const int ty = tile / ntx, tx = tile - ty * ntx;
     t.x0 = tx * kTX;
     t.y0 = ty * kTY;
     t.HW = (int64_t)t.W * t.H;
     t.off = c.pix_offset;
-    t.slot = (int)blockIdx.x;
+    t.slot = b;
     return true;
 }
 
@@ -101,7 +109,7 @@ k_ssim_fwd(const sr_camera* __restrict__ cams, int V, const float* __restrict__ 
     __shared__ float sh[5][kHY][kTX];
     __shared__ float s_red[kNT];
     SsimTile t;
-    if (!ssim_tile(cams, t)) return;                  // uniform: the whole block leaves
+    if (!ssim_tile(cams, V, t)) return;               // uniform: the whole block leaves
     const int64_t base = 3 * t.off + t.ch * t.HW;     // this channel of this view in [3P] arrays
     load_xy(t, color + base, target + base, mask + t.off, sx, sy);
     __syncthreads();
@@ -111,36 +119,39 @@ k_ssim_fwd(const sr_camera* __restrict__ cams, int V, const float* __restrict__ 
 #pragma unroll
         for (int d = 0; d <= 2 * kR; ++d) {
             const float g = taps.g[d], xv = sx[ly][lx + d], yv = sy[ly][lx + d];
-            a0 = a0 + g * xv;
-            a1 = a1 + g * yv;
-            a2 = a2 + g * (xv * xv);
-            a3 = a3 + g * (yv * yv);
-            a4 = a4 + g * (xv * yv);
+            a0 = __builtin_fmaf(g, xv, a0);
+            a1 = __builtin_fmaf(g, yv, a1);
+            a2 = __builtin_fmaf(g, (xv * xv), a2);
+            a3 = __builtin_fmaf(g, (yv * yv), a3);
+            a4 = __builtin_fmaf(g, (xv * yv), a4);
         }
         sh[0][ly][lx] = a0; sh[1][ly][lx] = a1; sh[2][ly][lx] = a2; sh[3][ly][lx] = a3; sh[4][ly][lx] = a4;
     }
     __syncthreads();
-    const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
-    const int i = t.x0 + lx, j = t.y0 + ly;
+    const int lx = (int)threadIdx.x % kTX;
     float ssum = 0.f, se = 0.f;
-    if (i < t.W && j < t.H) {
+#pragma unroll
+    for (int half = 0; half < kTY * kTX / kNT; ++half) {
+      const int ly = (int)threadIdx.x / kTX + half * (kNT / kTX);
+      const int i = t.x0 + lx, j = t.y0 + ly;
+      if (i < t.W && j < t.H) {
         float mx = 0.f, my = 0.f, ex2 = 0.f, ey2 = 0.f, exy = 0.f;
 #pragma unroll
         for (int d = 0; d <= 2 * kR; ++d) {
             const float g = taps.g[d];
-            mx = mx + g * sh[0][ly + d][lx];
-            my = my + g * sh[1][ly + d][lx];
-            ex2 = ex2 + g * sh[2][ly + d][lx];
-            ey2 = ey2 + g * sh[3][ly + d][lx];
-            exy = exy + g * sh[4][ly + d][lx];
+            mx = __builtin_fmaf(g, sh[0][ly + d][lx], mx);
+            my = __builtin_fmaf(g, sh[1][ly + d][lx], my);
+            ex2 = __builtin_fmaf(g, sh[2][ly + d][lx], ex2);
+            ey2 = __builtin_fmaf(g, sh[3][ly + d][lx], ey2);
+            exy = __builtin_fmaf(g, sh[4][ly + d][lx], exy);
         }
         const float vx = ex2 - mx * mx, vy = ey2 - my * my, cxy = exy - mx * my;
         const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * cxy + kC2;
         const float B1 = mx * mx + my * my + kC1, B2 = (vx + vy) + kC2;
         const float S = (A1 * A2) / (B1 * B2);
-        ssum = S;
+        ssum += S;
         const float xv = sx[ly + kR][lx + kR], yv = sy[ly + kR][lx + kR];
-        se = (xv - yv) * (xv - yv);
+        se += (xv - yv) * (xv - yv);
         if (gmaps) {
             // dL/dS = -w_s / (3 H W V); chain through A1, A2, B1, B2
             const float dS = -w_s / (3.0f * (float)t.HW * (float)V);
@@ -153,6 +164,7 @@ k_ssim_fwd(const sr_camera* __restrict__ cams, int V, const float* __restrict__ 
             gmaps[P3 + p] = dS * d_ex2;
             gmaps[2 * P3 + p] = dS * d_exy;
         }
+      }
     }
     ssum = block_sum(ssum, s_red);
     se = block_sum(se, s_red);
@@ -164,14 +176,15 @@ k_ssim_fwd(const sr_camera* __restrict__ cams, int V, const float* __restrict__ 
 
 // dL/dx = G*g1 + 2 x G*g2 + y G*g3; dL/dR += M dL/dx
 __global__ void __launch_bounds__(kNT)
-k_ssim_bwd(const sr_camera* __restrict__ cams, const float* __restrict__ color, const float* __restrict__ target,
+k_ssim_bwd(const sr_camera* __restrict__ cams, int V, const float* __restrict__ color,
+           const float* __restrict__ target,
            const uint8_t* __restrict__ mask, Taps taps, int64_t P3, const float* __restrict__ gmaps,
            float* __restrict__ dL_dcolor) {
 #pragma clang fp contract(off)
     __shared__ float sg[3][kHY][kHX];
     __shared__ float sh[3][kHY][kTX];
     SsimTile t;
-    if (!ssim_tile(cams, t)) return;
+    if (!ssim_tile(cams, V, t)) return;
     const int64_t base = 3 * t.off + t.ch * t.HW;
     for (int k = threadIdx.x; k < kHX * kHY; k += kNT) {
         const int ly = k / kHX, lx = k - ly * kHX;
@@ -192,23 +205,26 @@ k_ssim_bwd(const sr_camera* __restrict__ cams, const float* __restrict__ color, 
 #pragma unroll
         for (int d = 0; d <= 2 * kR; ++d) {
             const float g = taps.g[d];
-            a0 = a0 + g * sg[0][ly][lx + d];
-            a1 = a1 + g * sg[1][ly][lx + d];
-            a2 = a2 + g * sg[2][ly][lx + d];
+            a0 = __builtin_fmaf(g, sg[0][ly][lx + d], a0);
+            a1 = __builtin_fmaf(g, sg[1][ly][lx + d], a1);
+            a2 = __builtin_fmaf(g, sg[2][ly][lx + d], a2);
         }
         sh[0][ly][lx] = a0; sh[1][ly][lx] = a1; sh[2][ly][lx] = a2;
     }
     __syncthreads();
-    const int lx = (int)threadIdx.x % kTX, ly = (int)threadIdx.x / kTX;
-    const int i = t.x0 + lx, j = t.y0 + ly;
-    if (i < t.W && j < t.H) {
+    const int lx = (int)threadIdx.x % kTX;
+#pragma unroll
+    for (int half = 0; half < kTY * kTX / kNT; ++half) {
+      const int ly = (int)threadIdx.x / kTX + half * (kNT / kTX);
+      const int i = t.x0 + lx, j = t.y0 + ly;
+      if (i < t.W && j < t.H) {
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
         for (int d = 0; d <= 2 * kR; ++d) {
             const float g = taps.g[d];
-            f0 = f0 + g * sh[0][ly + d][lx];
-            f1 = f1 + g * sh[1][ly + d][lx];
-            f2 = f2 + g * sh[2][ly + d][lx];
+            f0 = __builtin_fmaf(g, sh[0][ly + d][lx], f0);
+            f1 = __builtin_fmaf(g, sh[1][ly + d][lx], f1);
+            f2 = __builtin_fmaf(g, sh[2][ly + d][lx], f2);
         }
         const int64_t q = (int64_t)j * t.W + i;
         if (mask[t.off + q]) {
@@ -216,6 +232,7 @@ k_ssim_bwd(const sr_camera* __restrict__ cams, const float* __restrict__ color, 
             const float dx = (f0 + 2.0f * xv * f1) + yv * f2;
             dL_dcolor[base + q] += dx;
         }
+      }
     }
 }
 
@@ -270,7 +287,7 @@ size_t ssim_workspace_bytes(int V, int max_slots, int64_t P, bool with_grad) {
     return b;
 }
 
-hipError_t launch_ssim(int V, int max_slots, int64_t P, const sr_camera* cams, const float* color,
+hipError_t launch_ssim(int V, int max_slots, int total_slots, int64_t P, const sr_camera* cams, const float* color,
                        const float* target, const uint8_t* mask, float w_s, void* ws, float* out,
                        float* dL_dcolor, hipStream_t s) {
     if (V == 0 || max_slots == 0) return hipSuccess;
@@ -280,10 +297,10 @@ hipError_t launch_ssim(int V, int max_slots, int64_t P, const sr_camera* cams, c
     pb = (pb + 255) & ~size_t(255);
     float* gmaps = dL_dcolor ? (float*)((char*)ws + pb) : nullptr;
     const int64_t P3 = 3 * P;
-    hipLaunchKernelGGL(k_ssim_fwd, dim3(max_slots, V), dim3(kNT), 0, s, cams, V, color, target, mask, taps, w_s,
+    hipLaunchKernelGGL(k_ssim_fwd, dim3(total_slots), dim3(kNT), 0, s, cams, V, color, target, mask, taps, w_s,
                        max_slots, P3, partial, gmaps);
     if (dL_dcolor)
-        hipLaunchKernelGGL(k_ssim_bwd, dim3(max_slots, V), dim3(kNT), 0, s, cams, color, target, mask, taps, P3,
+        hipLaunchKernelGGL(k_ssim_bwd, dim3(total_slots), dim3(kNT), 0, s, cams, V, color, target, mask, taps, P3,
                            (const float*)gmaps, dL_dcolor);
     hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(kNT), 0, s, cams, V, max_slots, (const float*)partial, w_s, out);
     return hipGetLastError();
