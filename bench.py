@@ -5,7 +5,11 @@ occlusion statistics -> masked L1 + background loss -> backward compositing
 -> projection backward, over all views of the batch (every stage is one
 launch for all views).  The default workload is the 1M-surfel batch of 16
 views with uneven sides (400..1600 px) and degree-3 colour; per-view mode
-runs the same kernels one view at a time.
+runs the same kernels one view at a time.  Besides the headline step the
+line carries the separate-launch step, the hipGraph replay, the step with
+the whole Eq. 3 loss (D-SSIM and the 2DGS regularisers, with the expected
+and with the median depth), the density statistic and compaction, and with
+--prune-legs the occlusion-pruning pass for surfels and 3D Gaussians.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config3]
 
