@@ -45,6 +45,14 @@ def test_layout_views_and_validation(lib):
     assert T.value == 3 * 2 + 3 * 3 + 1
     assert [c.tile_offset for c in cams] == [0, 6, 15]
     assert [c.pix_offset for c in cams] == [0, 840, 840 + 1584]
+    # 4x4-tile binning groups: ceil(tiles / 4) per side, numbered view after view
+    assert [c.groups_x for c in cams] == [1, 1, 1] and [c.group_offset for c in cams] == [0, 1, 2]
+    big = (SrCamera * 2)()
+    for c, (w, h) in zip(big, [(200, 130), (64, 65)]):
+        c.width, c.height, c.fx, c.fy = w, h, 10.0, 10.0
+    lib.call("sr_layout_views", ctypes.cast(big, ctypes.c_void_p), 2, 16, 16, None, None)
+    assert (big[0].tiles_x, big[0].tiles_y, big[0].groups_x) == (13, 9, 4)
+    assert (big[1].group_offset, big[1].groups_x) == (4 * 3, 1)
     bad = (SrCamera * 1)()
     bad[0].width, bad[0].height = 0, 5
     with pytest.raises(lib.SurfelRasterError) as e:
@@ -83,6 +91,10 @@ def test_argument_errors_before_launch(lib):
     counters = ctypes.c_void_p(8)
     assert l.sr_bin_and_sort(ctypes.byref(cfg), 10, 0, None, None, None, None, None, None, 0, 100, None, None,
                              None, counters, None) == lib.SR_ERR_ARG
+    # binned surfel ids hold 24 bits: larger N is rejected before anything runs
+    assert l.sr_bin_and_sort(ctypes.byref(cfg), 1 << 24, 0, None, None, None, None, None, None, 0, 100, None, None,
+                             None, counters, None) == lib.SR_ERR_UNSUPPORTED
+    assert lib.SR_TILE_GROUP == 4 and lib.SR_INST_ID_BITS == 24
     # the median depth and its entry index go together, and its gradient needs the index
     md = ctypes.c_void_p(256)
     assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, None, None) == lib.SR_ERR_ARG
