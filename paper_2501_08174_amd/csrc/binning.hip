@@ -310,19 +310,21 @@ __device__ __forceinline__ uint32_t groups_of(const ushort4 rc, int tile_w, int 
     return (uint32_t)((gx1 - gx0 + 1) * (gy1 - gy0 + 1));
 }
 
-// Groups met by every depth-sorted visible pair (gathered once into depth
-// order) and their sum per block.
+// Groups met by every depth-sorted visible pair and their sum per block;
+// the pairs' rectangles are gathered once into depth order for the emission.
 __global__ void __launch_bounds__(kNT)
 k_inst_count(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ vis_vals,
              const ushort4* __restrict__ rect, int tile_w, int tile_h, uint32_t* __restrict__ tt_sorted,
-             uint64_t* __restrict__ sums) {
+             ushort4* __restrict__ rect_sorted, uint64_t* __restrict__ sums) {
     __shared__ uint64_t s_w[4];
     uint64_t b, e;
     static_chunk(counters[0], G, &b, &e);
     uint64_t c = 0;
     for (uint64_t i = b + threadIdx.x; i < e; i += kNT) {
-        const uint32_t t = groups_of(rect[vis_vals[i]], tile_w, tile_h);
+        const ushort4 rc = rect[vis_vals[i]];
+        const uint32_t t = groups_of(rc, tile_w, tile_h);
         tt_sorted[i] = t;
+        rect_sorted[i] = rc;
         c += t;
     }
     uint64_t tot;
@@ -374,7 +376,8 @@ k_emit_starts(const uint32_t* __restrict__ counters, const uint64_t* __restrict_
 // a camera, first in depth order) do not serialise on a few blocks.
 __global__ void __launch_bounds__(kNT)
 k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total64, int N, int tile_w, int tile_h,
-       const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals, const ushort4* __restrict__ rect,
+       const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals,
+       const ushort4* __restrict__ rect_sorted,
        const uint64_t* __restrict__ offs, const uint32_t* __restrict__ starts, uint32_t* __restrict__ inst_keys,
        uint32_t* __restrict__ inst_vals) {
     constexpr int GS = SR_TILE_GROUP;
@@ -398,7 +401,7 @@ k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total
         if (i < n_vis) {
             const uint32_t rec = vis_vals[i];
             const int v = (int)(rec / (uint32_t)N);
-            const ushort4 rc = rect[rec];
+            const ushort4 rc = rect_sorted[i];
             const int tx0 = rc.x / tile_w, tx1 = rc.y / tile_w, ty0 = rc.z / tile_h, ty1 = rc.w / tile_h;
             const int gx0 = tx0 / GS, gx1 = tx1 / GS, gy0 = ty0 / GS;
             const sr_camera& c = cams[v];
@@ -504,6 +507,7 @@ struct BinWs {
     uint32_t *ik0, *iv0, *ik1, *iv1;     // instances, ping-pong
     uint32_t *hist, *tot, *vsum, *tts, *estart;
     uint64_t *isum, *ioff, *itotal;
+    ushort4* rsort;                      // rectangles of the visible pairs in depth order
     size_t bytes;
 };
 
@@ -525,6 +529,7 @@ BinWs carve(void* base, uint64_t VN, uint64_t cap) {
     w.isum = (uint64_t*)take(kMaxRadixBlocks * 8);
     w.ioff = (uint64_t*)take(VN * 8);
     w.tts = (uint32_t*)take(VN * 4);
+    w.rsort = (ushort4*)take(VN * 8);
     w.estart = (uint32_t*)take(((cap + kEmitPerBlock - 1) / kEmitPerBlock) * 4);
     w.itotal = (uint64_t*)take(8);
     w.bytes = off;
@@ -609,7 +614,7 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     // 3. instance offsets and emission in depth order
     const int Gi = Gv;
     hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, (const ushort4*)rect,
-                       cfg.tile_w, cfg.tile_h, w.tts, w.isum);
+                       cfg.tile_w, cfg.tile_h, w.tts, w.rsort, w.isum);
     hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap, w.itotal);
     hipLaunchKernelGGL(k_inst_offsets, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.tts, w.isum, w.ioff);
     const uint64_t emit_blocks = ((uint64_t)cap + kEmitPerBlock - 1) / kEmitPerBlock;
@@ -617,7 +622,7 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
         hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((emit_blocks + kNT - 1) / kNT)), dim3(kNT), 0, s, counters,
                            w.ioff, (uint32_t)emit_blocks, w.estart);
         hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kNT), 0, s, counters, w.itotal, N, cfg.tile_w,
-                           cfg.tile_h, cams_dev, w.vv0, (const ushort4*)rect, w.ioff, w.estart, w.ik0, w.iv0);
+                           cfg.tile_h, cams_dev, w.vv0, (const ushort4*)w.rsort, w.ioff, w.estart, w.ik0, w.iv0);
     }
     // 4. stable sort by group id; values land in the caller's array
     int nbits = 0;
