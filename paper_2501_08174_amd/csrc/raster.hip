@@ -193,6 +193,10 @@ struct FwdSmem {
     // a[1].z and the wave bits in a[1].w in every mode
     float4 a[kAppF4][NT];
     uint32_t id[(MODE & kStats) ? NT : 1];
+    // occlusion statistics of the batch's entries over the workgroup's waves
+    // (hits, max alpha bits, max weight bits), added to the global ones once
+    // per (tile, entry) at the end of the batch
+    uint32_t st[(MODE & kStats) ? 3 : 1][(MODE & kStats) ? NT : 1];
     uint32_t wcnt[NT / 64 + 1];   // gathering: members per wave, then the resume position
 };
 
@@ -317,11 +321,15 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
             }
             // the run position and the wave bits replace the packed rectangle
             sm.a[1][tid] = make_float4(n12.x, n12.y, __uint_as_float(jpos), __uint_as_float(bits));
-            if (STATS) sm.id[tid] = g;
+            if (STATS) {
+                sm.id[tid] = g;
+                sm.st[0][tid] = 0u;
+                sm.st[1][tid] = 0u;
+                sm.st[2][tid] = 0u;
+            }
         }
         __syncthreads();
-        if (ballot64(!done) == 0ull) continue;
-        bool wave_done = false;
+        bool wave_done = ballot64(!done) == 0ull;
         for (int c = 0; c * 64 < cnt && !wave_done; ++c) {
           uint64_t live = wave_live_mask(sm.a[1], c, cnt);
           while (live != 0ull) {
@@ -375,11 +383,11 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
             if (STATS) {
                 const uint64_t bm = ballot64(blend);
                 if (bm != 0ull) {
+                    // lane 0 holds the wave's max alpha, lane 32 its max weight
                     const uint32_t mx = wave_max2_bits(blend ? e.a : 0.f, wgt);
                     if ((lane & 31) == 0) {
-                        const uint32_t g = sm.id[k];
-                        if (lane == 0) atomicAdd(&hits[g], (uint32_t)__popcll(bm));
-                        atomicMax(lane == 0 ? (uint32_t*)&max_alpha[g] : (uint32_t*)&max_weight[g], mx);
+                        if (lane == 0) atomicAdd(&sm.st[0][k], (uint32_t)__popcll(bm));
+                        atomicMax(&sm.st[lane == 0 ? 1 : 2][k], mx);
                     }
                 }
             }
@@ -388,6 +396,15 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 break;
             }
           }
+        }
+        if (STATS) {
+            __syncthreads();
+            if (tid < cnt && sm.st[0][tid] != 0u) {
+                const uint32_t g = sm.id[tid];
+                atomicAdd(&hits[g], sm.st[0][tid]);
+                atomicMax((uint32_t*)&max_alpha[g], sm.st[1][tid]);
+                atomicMax((uint32_t*)&max_weight[g], sm.st[2][tid]);
+            }
         }
     }
     if (COUNT) n_upto_last += n_eval_last;
