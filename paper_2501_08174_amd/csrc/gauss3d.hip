@@ -161,6 +161,7 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
     constexpr int NT = TW * TH;
     __shared__ float4 sg[2][NT];
     __shared__ uint32_t sid[NT];
+    __shared__ uint32_t sst[3][NT];   // per-batch hits, max alpha, max weight over the waves
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = view_of_tile(cams, V, tile);
     const sr_camera& c = cams[v];
@@ -192,11 +193,13 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
                 sg[1][threadIdx.x].w = 0.f;
             }
             sid[threadIdx.x] = gg;
+            sst[0][threadIdx.x] = 0u;
+            sst[1][threadIdx.x] = 0u;
+            sst[2][threadIdx.x] = 0u;
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)NT, n - base);
-        if (__ballot(!done) == 0ull) continue;
-        bool wave_done = false;
+        bool wave_done = __ballot(!done) == 0ull;
         for (int cr = 0; cr * 64 < cnt && !wave_done; ++cr) {
           const int kk = cr * 64 + lane;
           uint64_t live = __ballot(kk < cnt && ((__float_as_uint(sg[1][kk < cnt ? kk : 0].w) >> wv) & 1u));
@@ -222,9 +225,8 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
             if (bm != 0ull) {
                 const uint32_t mx = wave_max2_bits(blend ? a : 0.f, wgt);
                 if ((lane & 31) == 0) {
-                    const uint32_t g = sid[k];
-                    if (lane == 0) atomicAdd(&hits[g], (uint32_t)__popcll(bm));
-                    atomicMax(lane == 0 ? (uint32_t*)&max_alpha[g] : (uint32_t*)&max_weight[g], mx);
+                    if (lane == 0) atomicAdd(&sst[0][k], (uint32_t)__popcll(bm));
+                    atomicMax(&sst[lane == 0 ? 1 : 2][k], mx);
                 }
             }
             if (__ballot(!done) == 0ull) {
@@ -232,6 +234,14 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
                 break;
             }
           }
+        }
+        // the batch's statistics reach memory once per (tile, entry)
+        __syncthreads();
+        if ((int)threadIdx.x < cnt && sst[0][threadIdx.x] != 0u) {
+            const uint32_t g = sid[threadIdx.x];
+            atomicAdd(&hits[g], sst[0][threadIdx.x]);
+            atomicMax((uint32_t*)&max_alpha[g], sst[1][threadIdx.x]);
+            atomicMax((uint32_t*)&max_weight[g], sst[2][threadIdx.x]);
         }
     }
 }
