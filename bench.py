@@ -1,15 +1,19 @@
 """Throughput of the object-centric 2DGS hot path on one MI355X.
 
-One step = projection -> binning/sort -> forward compositing with the
-occlusion statistics -> masked L1 + background loss -> backward compositing
+One step = projection -> binning/sort -> forward compositing (recording the
+blended-pixel count of every surfel, the usage the occlusion pruning of
+Section 4.3 acts on) -> masked L1 + background loss -> backward compositing
 -> projection backward, over all views of the batch (every stage is one
-launch for all views).  The default workload is the 1M-surfel batch of 16
-views with uneven sides (400..1600 px) and degree-3 colour; per-view mode
-runs the same kernels one view at a time.  Besides the headline step the
-line carries the separate-launch step, the hipGraph replay, the step with
-the whole Eq. 3 loss (D-SSIM and the 2DGS regularisers, with the expected
-and with the median depth), the density statistic and compaction, and with
---prune-legs the occlusion-pruning pass for surfels and 3D Gaussians.
+launch for all views; the compositing forward, loss and backward share one
+fused launch).  The default workload is the 1M-surfel batch of 16 views
+with uneven sides (400..1600 px) and degree-3 colour; per-view mode runs
+the same kernels one view at a time.  Besides the headline step the line
+carries the same step with the full occlusion statistics (also the maximum
+alpha and weight) and with no usage record, the separate-launch step, the
+hipGraph replay, the step with the whole Eq. 3 loss (D-SSIM and the 2DGS
+regularisers, with the expected and with the median depth), the density
+statistic and compaction, and with --prune-legs the occlusion-pruning pass
+for surfels and 3D Gaussians.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config3]
 
@@ -99,6 +103,7 @@ class Pipeline:
         self.views = ViewBatch(cams, tile=tile)
         self.rast = Rasterizer(scene.n, self.views, scene.sh_degree, sh_stride=scene.sh.shape[1])
         self.p, self.g, self.stats = params, grads, stats
+        self.used = torch.zeros(scene.n, dtype=torch.int32, device="cuda")
         self.mask = torch.tensor(np.concatenate([m.reshape(-1) for m in masks]), device="cuda")
         self.target = torch.tensor(np.concatenate([t.reshape(-1) for t in targets]), device="cuda")
         self.dA = torch.zeros_like(self.rast.alpha)
@@ -110,18 +115,24 @@ class Pipeline:
         self.need = self.rast.plan_capacity(params, slack=1.02)
 
     STAGES = ("preprocess", "bin_sort", "train_raster", "backward_project")
-    STAGES_UNFUSED = ("preprocess", "bin_sort", "forward+stats", "loss", "backward_raster", "backward_project")
-    STAGES_EQ3 = ("preprocess", "bin_sort", "forward+stats", "loss", "ssim", "regularizers", "backward_raster",
+    STAGES_UNFUSED = ("preprocess", "bin_sort", "forward", "loss", "backward_raster", "backward_project")
+    STAGES_EQ3 = ("preprocess", "bin_sort", "forward", "loss", "ssim", "regularizers", "backward_raster",
                   "backward_project")
 
-    def step(self, ev=None, fused=True, eq3=None):
+    def step(self, ev=None, fused=True, eq3=None, stats="hits"):
         """One training step; the compositing is the fused forward + loss +
         backward launch (fused=True) or the three separate launches; with
         eq3 = (w_dist, w_normal[, median]) the loss is the whole Eq. 3 (the
         2DGS regularisers need neighbouring pixels, so the launches are
         separate); with median the normal term takes the median depth as its
-        surface."""
+        surface.  stats: "hits" (default) has the forward count the blended
+        pixels of every surfel into self.used, the record of used Gaussians
+        the renderer keeps during training for the occlusion pruning applied
+        every 100 or 600 iterations (Section 4.3, Section 5.1); "full" also
+        takes the maximum alpha and weight (self.stats); None records
+        nothing."""
         r = self.rast
+        st = {"hits": self.used, "full": self.stats, None: None}[stats]
         rec = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
         rec(0)
         r.preprocess(self.p)
@@ -131,7 +142,7 @@ class Pipeline:
         if eq3 is not None:
             # L_c^M = (1 - lambda) L1 + lambda D-SSIM on the masked images (lambda = 0.2)
             med = len(eq3) > 2 and eq3[2]
-            r.forward(stats=self.stats, accumulate=True, median=med)
+            r.forward(stats=st, accumulate=True, median=med)
             rec(3)
             r.loss(self.mask, self.target, 0.5, 0.8, self.dA, self.dC)
             rec(4)
@@ -143,10 +154,10 @@ class Pipeline:
             r.backward_raster(dC=self.dC, dA=self.dA, dD=self.dD, dN=self.dN, dS=self.dS, dM=dM)
             rec(7)
         elif fused:
-            r.train_step_raster(self.mask, self.target, 0.5, 1.0, stats=self.stats, accumulate=True)
+            r.train_step_raster(self.mask, self.target, 0.5, 1.0, stats=st, accumulate=True)
             rec(3)
         else:
-            r.forward(stats=self.stats, accumulate=True)
+            r.forward(stats=st, accumulate=True)
             rec(3)
             r.loss(self.mask, self.target, 0.5, 1.0, self.dA, self.dC)
             rec(4)
@@ -265,11 +276,30 @@ def main():
     result["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
                           "frac": achieved / (VALU_PEAK / 1e12),
                           "traffic": measured_traffic(args.workload, tile),
-                          "kernel": "k_train_raster (fused forward + loss + backward compositing)",
+                          "kernel": "k_train_raster with the usage counts (fused forward + loss + backward "
+                                    "compositing)",
                           "ops_per_launch": ops}
     result["counts"].update({"reached_pairs": R, "blended_pairs": B, "backward_pairs": R_bwd,
                              "list_entries_up_to_last": upto_last,
                              "forward_wave_steps": WS, "forward_wave_steps_blending": WB})
+
+    # the same step with the full occlusion statistics in the fused launch
+    # (hits, maximum alpha and maximum weight; they feed the density/pruning
+    # leg below), and with no usage record at all
+    def stats_leg(mode):
+        ev_s = [[torch.cuda.Event(enable_timing=True) for _ in range(ns + 1)] for _ in range(args.steps)]
+        pipe.step(stats=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            pipe.step(ev_s[k], stats=mode)
+        torch.cuda.synchronize()
+        s_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        st_s = np.array([[ev_s[k][i].elapsed_time(ev_s[k][i + 1]) for i in range(ns)] for k in range(args.steps)])
+        return {"ms_per_step": s_ms, "Mpixel_per_s": P / (s_ms * 1e-3) / 1e6,
+                "stage_ms_mean": dict(zip(Pipeline.STAGES, [float(x) for x in st_s.mean(axis=0)]))}
+    result["full_prune_stats"] = stats_leg("full")
+    result["no_usage_record"] = stats_leg(None)
 
     if not args.no_unfused:
         # the same step with separate forward / loss / backward launches

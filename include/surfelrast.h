@@ -166,9 +166,14 @@ sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_c
  * views).  Per pixel: colour [3P] (+ T_final * bg), alpha [P] = 1 - T_final,
  * depth [P] = sum w z, normal [3P] = sum w n, dist [P] = sum_ij w_i w_j
  * (z_i - z_j)^2, T_final [P], n_contrib [P] (position + 1 of the last
- * blended entry in the run of the pixel's tile group).  When hits/max_alpha/max_weight are not
- * NULL the occlusion statistics of sr_prune_contrib are gathered in the
- * same pass.  Median depth (the 2DGS surface depth, an alternative to
+ * blended entry in the run of the pixel's tile group).  Occlusion
+ * statistics of sr_prune_contrib gathered in the same pass (Section 4.3: the
+ * renderer records which Gaussians the colour accumulation used), optional:
+ * hits [N] alone counts the blended pixels of every surfel (hits[g] = 0 <=>
+ * never blended, the pruning criterion at tau = alpha_min); hits with
+ * max_alpha and max_weight [N] (both or neither) also takes the maxima;
+ * cleared first unless cfg->flags has SR_FLAG_ACCUMULATE; maxima without
+ * hits are an argument error.  Median depth (the 2DGS surface depth, an alternative to
  * depth/alpha in the normal consistency term of Eq. 3), optional: when
  * median_depth [P] and median_contrib [P] are not NULL (both or neither),
  * median_depth = z of the last blended entry whose transmittance before it
@@ -310,7 +315,7 @@ sr_status sr_ssim_loss(int32_t V, const sr_camera *cams_host, const sr_camera *c
 
 /* Fused training step of the compositing, one launch for all views: per
  * tile, the forward of sr_render_forward (same outputs, same decisions;
- * occlusion statistics when hits/max_alpha/max_weight are given), the masked
+ * the same optional statistics: hits alone, or hits with both maxima), the masked
  * L1 + background loss gradients of sr_background_loss for every pixel
  * (Eq. 1, Eq. 2; mask [P] uint8, target [3P]), and the backward of
  * sr_backward_raster, with the per-pixel state kept on chip.

@@ -1,9 +1,9 @@
 """Tile-shape autotuner for the compositing kernels.
 
-Times one full training step (projection, binning, forward with statistics,
-loss, backward) for every compiled tile shape on the caller's own workload
-and keeps the fastest.  Results are cached in a JSON file keyed by GPU
-architecture, resolution bucket, surfel-count bucket and SH degree.
+Times one full training step (projection, binning, forward with the usage
+counts, loss, backward) for every compiled tile shape on the caller's own
+workload and keeps the fastest.  Results are cached in a JSON file keyed by
+GPU architecture, resolution bucket, surfel-count bucket and SH degree.
 """
 from __future__ import annotations
 
@@ -49,8 +49,10 @@ def _store(d: Dict[str, dict]):
         pass
 
 
-def time_step(rast: Rasterizer, p: Params, g: Params, mask, target, stats, steps: int = 3) -> float:
-    """Mean milliseconds of one training step on the current stream."""
+def time_step(rast: Rasterizer, p: Params, g: Params, mask, target, stats=None, steps: int = 3) -> float:
+    """Mean milliseconds of one training step on the current stream; stats
+    (the hits tensor alone, or hits with both maxima) are accumulated by the
+    forward as in Rasterizer.forward."""
 
     def step():
         rast.preprocess(p)
@@ -82,8 +84,7 @@ def autotune(cams: Sequence, p: Params, sh_degree: int, sh_stride: int, mask, ta
         return tuple(cache[key]["tile"])
     l = _lib.lib()
     g = Params(*[torch.zeros_like(t) for t in (p.means, p.scales, p.quats, p.opac, p.sh)])
-    stats = (torch.zeros(n, dtype=torch.int32, device=p.means.device), torch.zeros_like(p.opac),
-             torch.zeros_like(p.opac))
+    used = torch.zeros(n, dtype=torch.int32, device=p.means.device)
     times = {}
     for tw, th in candidates:
         if not l.sr_tile_supported(tw, th):
@@ -91,7 +92,7 @@ def autotune(cams: Sequence, p: Params, sh_degree: int, sh_stride: int, mask, ta
         views = ViewBatch(cams, tile=(tw, th))
         rast = Rasterizer(n, views, sh_degree, sh_stride=sh_stride)
         rast.plan_capacity(p, slack=1.02)
-        times[f"{tw}x{th}"] = time_step(rast, p, g, mask, target, stats, steps)
+        times[f"{tw}x{th}"] = time_step(rast, p, g, mask, target, used, steps)
         del rast
         torch.cuda.empty_cache()
     best = min(times, key=times.get)

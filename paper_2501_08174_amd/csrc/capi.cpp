@@ -182,6 +182,27 @@ sr_status sr_bin_and_sort(const sr_config* cfg, int32_t N, int32_t V, const sr_c
                       "sr_bin_and_sort");
 }
 
+namespace {
+
+// Statistics arguments of the forward and the training step: none, hits
+// alone (the usage count), or hits with both maxima.
+sr_status check_stats(const uint32_t* hits, const float* max_alpha, const float* max_weight) {
+    if ((max_alpha == nullptr) != (max_weight == nullptr))
+        return fail(SR_ERR_ARG, "max_alpha and max_weight must be given together");
+    if (max_alpha && !hits) return fail(SR_ERR_ARG, "max_alpha and max_weight need hits");
+    return SR_OK;
+}
+
+sr_status clear_stats(int32_t N, uint32_t* hits, float* max_alpha, float* max_weight, hipStream_t s) {
+    if (N == 0) return SR_OK;
+    if (hits) SR_TRY(hip_status(sr::fill_f32((float*)hits, 0.f, (uint64_t)N, s), "clear hits"));
+    if (max_alpha) SR_TRY(hip_status(sr::fill_f32(max_alpha, 0.f, (uint64_t)N, s), "clear max_alpha"));
+    if (max_weight) SR_TRY(hip_status(sr::fill_f32(max_weight, 0.f, (uint64_t)N, s), "clear max_weight"));
+    return SR_OK;
+}
+
+}  // namespace
+
 sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
                             const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
                             const uint32_t* ranges, float* color, float* alpha, float* depth, float* normal,
@@ -196,17 +217,11 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
         SR_NEED(color); SR_NEED(alpha); SR_NEED(depth); SR_NEED(normal); SR_NEED(dist); SR_NEED(T_final);
         SR_NEED(n_contrib);
     }
-    const bool st = hits || max_alpha || max_weight;
-    if (st && !(hits && max_alpha && max_weight))
-        return fail(SR_ERR_ARG, "hits, max_alpha and max_weight must be given together");
+    SR_TRY(check_stats(hits, max_alpha, max_weight));
     if ((median_depth == nullptr) != (median_contrib == nullptr))
         return fail(SR_ERR_ARG, "median_depth and median_contrib must be given together");
     hipStream_t s = (hipStream_t)stream;
-    if (st && !(cfg->flags & SR_FLAG_ACCUMULATE) && N > 0) {
-        SR_TRY(hip_status(sr::fill_f32((float*)hits, 0.f, (uint64_t)N, s), "clear hits"));
-        SR_TRY(hip_status(sr::fill_f32(max_alpha, 0.f, (uint64_t)N, s), "clear max_alpha"));
-        SR_TRY(hip_status(sr::fill_f32(max_weight, 0.f, (uint64_t)N, s), "clear max_weight"));
-    }
+    if (!(cfg->flags & SR_FLAG_ACCUMULATE)) SR_TRY(clear_stats(N, hits, max_alpha, max_weight, s));
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, nullptr, vals, ranges,
                                             color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
                                             max_weight, nullptr, median_depth, median_contrib, s),
@@ -533,15 +548,9 @@ sr_status sr_train_step_raster(const sr_config* cfg, int32_t N, int32_t V, const
         SR_NEED(color); SR_NEED(alpha); SR_NEED(depth); SR_NEED(normal); SR_NEED(dist); SR_NEED(T_final);
         SR_NEED(n_contrib); SR_NEED(tile_loss); SR_NEED(loss); SR_NEED(grad_rec);
     }
-    const bool st = hits || max_alpha || max_weight;
-    if (st && !(hits && max_alpha && max_weight))
-        return fail(SR_ERR_ARG, "hits, max_alpha and max_weight must be given together");
+    SR_TRY(check_stats(hits, max_alpha, max_weight));
     hipStream_t s = (hipStream_t)stream;
-    if (st && !(cfg->flags & SR_FLAG_ACCUMULATE) && N > 0) {
-        SR_TRY(hip_status(sr::fill_f32((float*)hits, 0.f, (uint64_t)N, s), "clear hits"));
-        SR_TRY(hip_status(sr::fill_f32(max_alpha, 0.f, (uint64_t)N, s), "clear max_alpha"));
-        SR_TRY(hip_status(sr::fill_f32(max_weight, 0.f, (uint64_t)N, s), "clear max_weight"));
-    }
+    if (!(cfg->flags & SR_FLAG_ACCUMULATE)) SR_TRY(clear_stats(N, hits, max_alpha, max_weight, s));
     if (total_tiles == 0) return SR_OK;
     SR_TRY(hip_status(sr::launch_train_raster(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, mask, target,
                                               gamma, w_c, color, alpha, depth, normal, dist, T_final, n_contrib, hits,

@@ -70,7 +70,7 @@ constexpr int kMaxWaves = 8;    // waves per workgroup (tiles of up to 512 pixel
 // with transmittance above 1/2) with the 1-based list index of that entry,
 // 16 pixel rectangles read from the rectangle array (statistics without
 // shading: no appearance records to take them from).
-constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8, kRect = 16;
+constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8, kRect = 16, kHits = 32;
 
 // Per-wave culling.  Every wave of a tile covers whole rows of it (a band).
 // When an entry is staged, its thread works out which bands it can reach,
@@ -192,11 +192,11 @@ struct FwdSmem {
     // appearance (shading) in a[0], a[1].xy; the run position of the entry in
     // a[1].z and the wave bits in a[1].w in every mode
     float4 a[kAppF4][NT];
-    uint32_t id[(MODE & kStats) ? NT : 1];
+    uint32_t id[(MODE & (kStats | kHits)) ? NT : 1];
     // occlusion statistics of the batch's entries over the workgroup's waves
-    // (hits, max alpha bits, max weight bits), added to the global ones once
-    // per (tile, entry) at the end of the batch
-    uint32_t st[(MODE & kStats) ? 3 : 1][(MODE & kStats) ? NT : 1];
+    // (hits, then with kStats the max alpha and max weight bits), added to
+    // the global ones once per (tile, entry) at the end of the batch
+    uint32_t st[(MODE & kStats) ? 3 : 1][(MODE & (kStats | kHits)) ? NT : 1];
     uint32_t wcnt[NT / 64 + 1];   // gathering: members per wave, then the resume position
 };
 
@@ -270,7 +270,8 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                                          float* __restrict__ max_weight, uint64_t& n_reached, uint64_t& n_blended,
                                          uint64_t& n_witer, uint64_t& n_wblend, uint64_t& n_upto_last) {
     constexpr bool SHADE = (MODE & kShade) != 0;
-    constexpr bool STATS = (MODE & kStats) != 0;
+    constexpr bool STATS = (MODE & kStats) != 0;              // hits and the two maxima
+    constexpr bool HITS = STATS || (MODE & kHits) != 0;       // hits (blended pixels per surfel)
     constexpr bool COUNT = (MODE & kCount) != 0;
     constexpr bool MEDIAN = (MODE & kMedian) != 0;
     // the pixel rectangles are staged (with the appearance records, or from
@@ -285,10 +286,24 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     st.last = st.kmed = 0;
     bool have_ref = false;
     bool done = !t.inside;
+    // statistics of the previous batch's entries: every thread adds its own
+    // slot to the global arrays (after a barrier), before the slot is reused
+    int prev_cnt = 0;
+    auto flush = [&]() {
+        if (tid < prev_cnt && sm.st[0][tid] != 0u) {
+            const uint32_t g = sm.id[tid];
+            atomicAdd(&hits[g], sm.st[0][tid]);
+            if (STATS) {
+                atomicMax((uint32_t*)&max_alpha[g], sm.st[1][tid]);
+                atomicMax((uint32_t*)&max_weight[g], sm.st[2][tid]);
+            }
+        }
+    };
     // batches of up to NT entries of the tile, gathered from its group's run
     int64_t pos = 0;
     while (pos < (int64_t)t.n) {
         if (__syncthreads_and(done)) break;
+        if (HITS) flush();
         int cnt = 0;
         while (cnt < NT && pos < (int64_t)t.n) {
             int64_t next;
@@ -321,9 +336,11 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
             }
             // the run position and the wave bits replace the packed rectangle
             sm.a[1][tid] = make_float4(n12.x, n12.y, __uint_as_float(jpos), __uint_as_float(bits));
-            if (STATS) {
+            if (HITS) {
                 sm.id[tid] = g;
                 sm.st[0][tid] = 0u;
+            }
+            if (STATS) {
                 sm.st[1][tid] = 0u;
                 sm.st[2][tid] = 0u;
             }
@@ -332,8 +349,11 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
         bool wave_done = ballot64(!done) == 0ull;
         for (int c = 0; c * 64 < cnt && !wave_done; ++c) {
           uint64_t live = wave_live_mask(sm.a[1], c, cnt);
+          // HITS: this wave's blended pixels of entry c * 64 + lane
+          uint32_t my_hits = 0;
           while (live != 0ull) {
-            const int k = c * 64 + (int)__builtin_ctzll(live);
+            const int bit = (int)__builtin_ctzll(live);
+            const int k = c * 64 + bit;
             live &= live - 1ull;
             PairEval e;
             const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
@@ -380,14 +400,14 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 if (COUNT) n_eval_last = n_eval;
             }
             if (COUNT) n_blended += (uint64_t)__popcll(ballot64(blend));
-            if (STATS) {
+            if (HITS) {
                 const uint64_t bm = ballot64(blend);
                 if (bm != 0ull) {
-                    // lane 0 holds the wave's max alpha, lane 32 its max weight
-                    const uint32_t mx = wave_max2_bits(blend ? e.a : 0.f, wgt);
-                    if ((lane & 31) == 0) {
-                        if (lane == 0) atomicAdd(&sm.st[0][k], (uint32_t)__popcll(bm));
-                        atomicMax(&sm.st[lane == 0 ? 1 : 2][k], mx);
+                    if (lane == bit) my_hits += (uint32_t)__popcll(bm);
+                    if (STATS) {
+                        // lane 0 holds the wave's max alpha, lane 32 its max weight
+                        const uint32_t mx = wave_max2_bits(blend ? e.a : 0.f, wgt);
+                        if ((lane & 31) == 0) atomicMax(&sm.st[lane == 0 ? 1 : 2][k], mx);
                     }
                 }
             }
@@ -396,16 +416,13 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 break;
             }
           }
+          if (HITS && my_hits != 0u) atomicAdd(&sm.st[0][c * 64 + lane], my_hits);
         }
-        if (STATS) {
-            __syncthreads();
-            if (tid < cnt && sm.st[0][tid] != 0u) {
-                const uint32_t g = sm.id[tid];
-                atomicAdd(&hits[g], sm.st[0][tid]);
-                atomicMax((uint32_t*)&max_alpha[g], sm.st[1][tid]);
-                atomicMax((uint32_t*)&max_weight[g], sm.st[2][tid]);
-            }
-        }
+        prev_cnt = cnt;
+    }
+    if (HITS) {
+        __syncthreads();
+        flush();
     }
     if (COUNT) n_upto_last += n_eval_last;
 }
@@ -707,12 +724,14 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     bwd_tile<TW, TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
 }
 
-// One training step of the compositing for a tile: forward with the
-// occlusion statistics, the masked L1 + background loss gradients of every
-// pixel (Eq. 1, Eq. 2) and the backward, with the per-pixel state kept in
-// registers between the phases.  Per-tile loss partial sums go to
-// tile_loss[2*tile] (L_b numerator, L1 numerator).
-template <int TW, int TH, int BATCH, bool STATS>
+// One training step of the compositing for a tile: forward (STATS = 1 also
+// counts the blended pixels of every surfel, the usage record of Section 4.3;
+// STATS = 2 adds the maximum alpha and weight; 0 tracks nothing), the masked
+// L1 + background loss gradients of every pixel (Eq. 1, Eq. 2) and the
+// backward, with the per-pixel state kept in registers between the phases.
+// Per-tile loss partial sums go to tile_loss[2*tile] (L_b numerator, L1
+// numerator).
+template <int TW, int TH, int BATCH, int STATS>
 __global__ void __launch_bounds__(TW * TH) SR_RASTER_OCCUPANCY
 k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
                const float4* __restrict__ app, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
@@ -722,7 +741,7 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
                uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
                float* __restrict__ max_weight, float* __restrict__ tile_loss, float* __restrict__ grad_rec) {
     constexpr int NT = TW * TH;
-    constexpr int MODE = kShade | (STATS ? kStats : 0);
+    constexpr int MODE = kShade | (STATS == 2 ? kStats : STATS == 1 ? kHits : 0);
     constexpr size_t kF = sizeof(FwdSmem<NT, MODE>), kB = sizeof(BwdSmem<BATCH>);
     __shared__ __align__(16) unsigned char smem[kF > kB ? kF : kB];
     __shared__ float s_red[NT];
@@ -802,7 +821,7 @@ void fwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, in
 }
 
 template <int TW, int TH>
-void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
+bool fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
                   const float4* geom, const float4* app, const uint2* rect, const uint32_t* vals, const uint2* ranges,
                   RasterConsts rc, float* color, float* alpha, float* depth, float* normal, float* dist,
                   float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
@@ -812,13 +831,16 @@ void fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cam
                           normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, counts,          \
                           median_depth, median_contrib)
     switch (mode) {
-        case kShade: SR_FWD(kShade); break;
-        case kShade | kStats: SR_FWD(kShade | kStats); break;
-        case kShade | kMedian: SR_FWD(kShade | kMedian); break;
-        case kShade | kStats | kMedian: SR_FWD(kShade | kStats | kMedian); break;
-        case kStats: SR_FWD(kStats); break;
-        case kStats | kRect: SR_FWD(kStats | kRect); break;
-        default: SR_FWD(kCount); break;
+        case kShade: SR_FWD(kShade); return true;
+        case kShade | kHits: SR_FWD(kShade | kHits); return true;
+        case kShade | kStats: SR_FWD(kShade | kStats); return true;
+        case kShade | kMedian: SR_FWD(kShade | kMedian); return true;
+        case kShade | kHits | kMedian: SR_FWD(kShade | kHits | kMedian); return true;
+        case kShade | kStats | kMedian: SR_FWD(kShade | kStats | kMedian); return true;
+        case kStats: SR_FWD(kStats); return true;
+        case kStats | kRect: SR_FWD(kStats | kRect); return true;
+        case kCount: SR_FWD(kCount); return true;
+        default: return false;       // not compiled
     }
 #undef SR_FWD
 }
@@ -841,20 +863,23 @@ void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, in
 }
 
 template <int TW, int TH>
-void train_launch(bool stats, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
+void train_launch(int stats, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
                   const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc,
                   const uint8_t* mask, const float* target, float gamma, float w_c, float* color, float* alpha,
                   float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits,
                   float* max_alpha, float* max_weight, float* tile_loss, float* grad_rec) {
     constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
-    if (stats)
-        hipLaunchKernelGGL((k_train_raster<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
-                           geom, app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist,
-                           T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec);
+#define SR_TRAIN(S)                                                                                              \
+    hipLaunchKernelGGL((k_train_raster<TW, TH, B, S>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, \
+                       app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist, T_final, \
+                       n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec)
+    if (stats == 2)
+        SR_TRAIN(2);
+    else if (stats == 1)
+        SR_TRAIN(1);
     else
-        hipLaunchKernelGGL((k_train_raster<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
-                           geom, app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist,
-                           T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec);
+        SR_TRAIN(0);
+#undef SR_TRAIN
 }
 
 // Compiled tile shapes (the binning takes any shape; the raster kernels are
@@ -884,15 +909,17 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              uint32_t* median_contrib, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+    const int stats = hits ? (max_alpha ? kStats : kHits) : 0;
     int mode = counts ? kCount
-                      : ((color ? kShade : 0) | (hits ? kStats : 0) | (color && median_depth ? kMedian : 0) |
+                      : ((color ? kShade : 0) | stats | (color && median_depth ? kMedian : 0) |
                          (!color && hits && rect ? kRect : 0));
 #define SR_TS(W, H)                                                                                              \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                   \
-        fwd_dispatch<W, H>(mode, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app,          \
-                           (const uint2*)rect, vals,                                                              \
-                           (const uint2*)ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, \
-                           max_alpha, max_weight, counts, median_depth, median_contrib);                        \
+        if (!fwd_dispatch<W, H>(mode, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app,     \
+                                (const uint2*)rect, vals, (const uint2*)ranges, rc, color, alpha, depth, normal, \
+                                dist, T_final, n_contrib, hits, max_alpha, max_weight, counts, median_depth,     \
+                                median_contrib))                                                                \
+            return hipErrorInvalidValue;                                                                        \
         return hipGetLastError();                                                                               \
     }
     SR_TILE_SHAPES(SR_TS)
@@ -930,7 +957,7 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
 #define SR_TS(W, H)                                                                                               \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                    \
-        train_launch<W, H>(hits != nullptr, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, \
+        train_launch<W, H>(hits ? (max_alpha ? 2 : 1) : 0, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, \
                            vals, (const uint2*)ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, \
                            dist, T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec);           \
         return hipGetLastError();                                                                                \

@@ -23,6 +23,18 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _stats(stats):
+    """(hits, max_alpha, max_weight) of a forward: stats is None, the hits
+    tensor alone (int32 [N], blended-pixel counts: the usage record of
+    Section 4.3), or the three tensors (hits and the maxima)."""
+    if stats is None:
+        return None, None, None
+    if isinstance(stats, torch.Tensor):
+        return stats, None, None
+    h, ma, mw = stats
+    return h, ma, mw
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
@@ -183,8 +195,10 @@ class Rasterizer:
 
     def forward(self, stats=None, accumulate: bool = False, stream=None, median: bool = False):
         """Forward compositing; ``median`` also renders the median depth
-        (self.median_depth) and its entry index (self.median_contrib)."""
-        h, ma, mw = (None, None, None) if stats is None else stats
+        (self.median_depth) and its entry index (self.median_contrib);
+        ``stats`` (hits alone, or hits with both maxima) accumulates the
+        occlusion statistics in the same pass."""
+        h, ma, mw = _stats(stats)
         cfg = self._cfg(accumulate)
         md = mc = None
         if median:
@@ -292,11 +306,11 @@ class Rasterizer:
 
     def train_step_raster(self, mask: torch.Tensor, target: torch.Tensor, gamma: float = 0.5, w_c: float = 1.0,
                           stats=None, accumulate: bool = False, stream=None):
-        """Fused forward + loss gradients + backward compositing (one launch);
-        follow with backward_project."""
+        """Fused forward + loss gradients + backward compositing (one launch;
+        ``stats`` as in forward); follow with backward_project."""
         if getattr(self, "tile_loss", None) is None:
             self.tile_loss = torch.zeros(2 * max(self.views.T, 1), dtype=torch.float32, device=self.device)
-        h, ma, mw = (None, None, None) if stats is None else stats
+        h, ma, mw = _stats(stats)
         cfg = self._cfg(accumulate)
         call("sr_train_step_raster", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask),

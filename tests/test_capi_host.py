@@ -103,6 +103,20 @@ def test_argument_errors_before_launch(lib):
                                 None) == lib.SR_ERR_ARG
     assert l.sr_render_backward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 19), None, md, None,
                                 *([None] * 6)) == lib.SR_ERR_ARG
+    # statistics: none, hits alone, or hits with both maxima
+    h = ctypes.c_void_p(512)
+    fwd = lambda hits, ma, mw: l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 11), hits, ma,
+                                                   mw, None, None, None)
+    step = lambda hits, ma, mw: l.sr_train_step_raster(ctypes.byref(cfg), 0, 0, None, None, None, None, None, None,
+                                                       None, None, 0.5, 1.0, *([None] * 7), hits, ma, mw, None,
+                                                       None, None, None)
+    for f in (fwd, step):
+        assert f(None, None, None) == lib.SR_OK
+        assert f(h, None, None) == lib.SR_OK
+        assert f(h, h, h) == lib.SR_OK
+        assert f(h, h, None) == lib.SR_ERR_ARG
+        assert f(h, None, h) == lib.SR_ERR_ARG
+        assert f(None, h, h) == lib.SR_ERR_ARG
 
 
 def test_regularizer_loss_arguments(lib):

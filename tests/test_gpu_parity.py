@@ -317,6 +317,60 @@ def test_prune_stats_match_oracle():
     print(f"pruned {mask.sum()} of {sc.n}; exempt {(~keep).sum()}")
 
 
+def test_usage_counts_alone():
+    """hits alone (no maxima): the usage record of Section 4.3 taken in the
+    forward and in the fused training step equals the full statistics' hits
+    and the oracle's, accumulates across calls, and leaves every forward
+    output bit-identical."""
+    sc = _ragged_scene(36, 600, 0)
+    geoms = geometry(sc)
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0)
+    pairs, tie_ids = [], []
+    for v, cam in enumerate(sc.cams):
+        res = render_pixels(P64, cam, geoms[v], _full(cam), RP)
+        pairs.append(res["pairs"])
+        tie_ids.append(res["tie_ids"])
+    ref = oracle.prune_stats64(sc.n, pairs, [g["culled"] for g in geoms])
+    keep = np.ones(sc.n, bool)
+    keep[np.unique(np.concatenate(tie_ids))] = False
+    views = ViewBatch(sc.cams)
+    rng = np.random.default_rng(4)
+    masks = torch.tensor(np.concatenate([rng.integers(0, 2, c.width * c.height) for c in sc.cams]).astype(np.uint8),
+                         device="cuda")
+    target = torch.tensor(rng.uniform(size=3 * views.P).astype(np.float32), device="cuda")
+    p = Params.from_scene(sc)
+    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1])
+    rast.plan_capacity(p)
+    rast.preprocess(p)
+    rast.bin()
+    outs = ("color", "alpha", "depth", "normal", "dist", "T_final", "n_contrib")
+    for fused in (False, True):
+        full = (torch.zeros(sc.n, dtype=torch.int32, device="cuda"), torch.zeros(sc.n, device="cuda"),
+                torch.zeros(sc.n, device="cuda"))
+        hits = torch.full((sc.n,), 7, dtype=torch.int32, device="cuda")     # cleared by the call
+        res = []
+        for st in (full, hits):
+            if fused:
+                rast.train_step_raster(masks, target, 0.5, 1.0, stats=st)
+            else:
+                rast.forward(stats=st)
+            torch.cuda.synchronize()
+            res.append({k: getattr(rast, k).clone() for k in outs})
+        for k in outs:
+            assert torch.equal(res[0][k], res[1][k]), (fused, k)
+        h = hits.cpu().numpy()
+        np.testing.assert_array_equal(h, full[0].cpu().numpy())
+        np.testing.assert_array_equal(h.view(np.uint32)[keep], ref["hits"][keep])
+        # accumulate: a second call adds the same counts
+        if fused:
+            rast.train_step_raster(masks, target, 0.5, 1.0, stats=hits, accumulate=True)
+        else:
+            rast.forward(stats=hits, accumulate=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(hits.cpu().numpy(), 2 * h)
+    print(f"used {(h > 0).sum()} of {sc.n}; exempt {(~keep).sum()}")
+
+
 def test_prune_pass_culling_keeps_statistics():
     """sr_prune_contrib (no shading) with per-wave culling by the pixel
     rectangles, without it, and the statistics of the shaded forward: the
