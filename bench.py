@@ -15,7 +15,7 @@ regularisers, with the expected and with the median depth), the density
 statistic and compaction, and with --prune-legs the occlusion-pruning pass
 for surfels and 3D Gaussians.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ragged16-1m]
 
 Prints one JSON line (rank 0).
 """
@@ -43,7 +43,7 @@ VALU_PEAK = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 HBM_PEAK = 8.0e12                      # bytes/s
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_train_raster_config3_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_train_raster_ragged16_1m_traffic.md")
 
 
 def measured_traffic(workload, tile):
@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="config3", choices=["config2", "config3", "config5"])
+    ap.add_argument("--workload", default="ragged16-1m", choices=["frame800-100k", "ragged16-1m", "wide8-3m"])
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -91,7 +91,8 @@ def parse():
 
 def make_scene(name):
     from paper_2501_08174_amd import scenes
-    return {"config2": scenes.make_config2, "config3": scenes.make_config3, "config5": scenes.make_config5}[name]()
+    return {"frame800-100k": scenes.make_frame800_100k, "ragged16-1m": scenes.make_ragged16_1m,
+            "wide8-3m": scenes.make_wide8_3m}[name]()
 
 
 class Pipeline:
@@ -399,7 +400,7 @@ def main():
         # views of 800x800 (1.1M primitives), for surfels and for 3D Gaussians
         from paper_2501_08174_amd import scenes as _sc
         from paper_2501_08174_amd.raster import prune_contrib, prune_contrib_3d
-        sc4, s3 = _sc.make_config4_3d()
+        sc4, s3 = _sc.make_shell100_3d()
         p4 = Params.from_scene(sc4)
         s3t = torch.tensor(s3, device="cuda")
         P4 = sum(c.width * c.height for c in sc4.cams)
@@ -415,7 +416,7 @@ def main():
             dt = time.perf_counter() - t0
             legs[name] = {"s": dt, "Mpixel_per_s": P4 / dt / 1e6,
                           "pruned": int(st.mask.sum().item()), "of": sc4.n}
-        result["pruning_pass"] = {"workload": "config4 shell scene, 100 views 800x800, 1.1M primitives, "
+        result["pruning_pass"] = {"workload": "shell100: shell scene, 100 views 800x800, 1.1M primitives, "
                                               "views in chunks of 20 (capacity planning included)", **legs}
         del p4, s3t
 

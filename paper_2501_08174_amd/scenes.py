@@ -223,7 +223,7 @@ def _random_views(rng, n_views, radius, sizes):
 # the five workloads
 # ----------------------------------------------------------------------------
 
-def make_config1(seed: int = 1) -> Scene:
+def make_frame64_1k(seed: int = 1) -> Scene:
     """1 view 64x64, 1,000 surfels, SH degree 0, forward only."""
     rng = np.random.default_rng(seed)
     n = 1000
@@ -234,10 +234,10 @@ def make_config1(seed: int = 1) -> Scene:
     cam = make_camera(np.eye(3), np.array([0.0, 0.0, -4.0]), 64, 64)
     mask = ellipsoid_mask(cam, (0, 0, 0), (0.6, 0.6, 0.6))
     means, scales, quats, opac, sh = _f32(means, scales, quats, opac, sh)
-    return Scene(means, scales, quats, opac, sh, 0, [cam], [mask], None, "config1")
+    return Scene(means, scales, quats, opac, sh, 0, [cam], [mask], None, "frame64-1k")
 
 
-def make_config2(seed: int = 2, n: int = 100_000, width: int = 800, height: int = 800) -> Scene:
+def make_frame800_100k(seed: int = 2, n: int = 100_000, width: int = 800, height: int = 800) -> Scene:
     """1 view 800x800, 100k surfels, SH degree 3, random target and a random
     ellipsoid mask; forward + backward."""
     rng = np.random.default_rng(seed)
@@ -251,10 +251,10 @@ def make_config2(seed: int = 2, n: int = 100_000, width: int = 800, height: int 
     mask = ellipsoid_mask(cam, centre, axes, rot)
     target = rng.uniform(0.0, 1.0, size=(3, height, width)).astype(np.float32)
     means, scales, quats, opac, sh = _f32(means, scales, quats, opac, sh)
-    return Scene(means, scales, quats, opac, sh, 3, [cam], [mask], [target], "config2")
+    return Scene(means, scales, quats, opac, sh, 3, [cam], [mask], [target], "frame800-100k")
 
 
-def make_config3(seed: int = 3, n: int = 1_000_000, n_views: int = 16) -> Scene:
+def make_ragged16_1m(seed: int = 3, n: int = 1_000_000, n_views: int = 16) -> Scene:
     """16 views of uneven resolution (sides uniform in 400..1600), 1M surfels
     (70% in the object ellipsoid, 30% background in [-3,3]^3), SH degree 3."""
     rng = np.random.default_rng(seed)
@@ -266,22 +266,22 @@ def make_config3(seed: int = 3, n: int = 1_000_000, n_views: int = 16) -> Scene:
     masks = [ellipsoid_mask(c, (0, 0, 0), OBJECT_AXES) for c in cams]
     targets = [rng.uniform(0.0, 1.0, size=(3, c.height, c.width)).astype(np.float32) for c in cams]
     means, scales, quats, opac, sh = _f32(means, scales, quats, opac, sh)
-    return Scene(means, scales, quats, opac, sh, 3, cams, masks, targets, "config3")
+    return Scene(means, scales, quats, opac, sh, 3, cams, masks, targets, "ragged16-1m")
 
 
-def make_config4_3d(seed: int = 4, **kw):
-    """The 3D-Gaussian counterpart of config 4 for the pruning pass of
+def make_shell100_3d(seed: int = 4, **kw):
+    """The 3D-Gaussian counterpart of the shell scene for the pruning pass of
     Appendix B: the same centres, rotations and opacities; each surfel's two
     tangent scales plus a third (normal) scale of 0.1 times the smaller one,
     so the shell is a closed layer of thin, opaque 3D Gaussians.  Returns
     (scene, scales3 [N,3] float32)."""
-    sc = make_config4(seed, **kw)
+    sc = make_shell100(seed, **kw)
     s = sc.scales.astype(np.float64)
     s3 = np.concatenate([s, 0.1 * s.min(axis=1, keepdims=True)], axis=1).astype(np.float32)
     return sc, s3
 
 
-def make_config4(seed: int = 4, n_shell: int = 300_000, n_inner: int = 700_000,
+def make_shell100(seed: int = 4, n_shell: int = 300_000, n_inner: int = 700_000,
                  n_outer: int = 100_000, n_views: int = 100, size: int = 800) -> Scene:
     """Occlusion pruning workload: an opaque shell on the unit sphere
     (normals radial, opacity 0.99) hiding an interior ball of radius 0.6,
@@ -319,10 +319,10 @@ def make_config4(seed: int = 4, n_shell: int = 300_000, n_inner: int = 700_000,
         cams.append(make_camera(look_at_rotation(c), c, size, size))
     masks = [np.ones((size, size), np.uint8) for _ in cams]
     means, scales, quats, opac, sh = _f32(means, scales, quats, opac, sh)
-    return Scene(means, scales, quats, opac, sh, 0, cams, masks, None, "config4")
+    return Scene(means, scales, quats, opac, sh, 0, cams, masks, None, "shell100")
 
 
-def make_config5(seed: int = 5, n: int = 3_000_000, n_views: int = 8) -> Scene:
+def make_wide8_3m(seed: int = 5, n: int = 3_000_000, n_views: int = 8) -> Scene:
     """Training-step workload: 3M surfels with the object/background mixture,
     SH degree 3, 8 views at 1960x1090 (fx = fy = 1697.41, cx = 980,
     cy = 545) on the radius-4 sphere."""
@@ -339,7 +339,7 @@ def make_config5(seed: int = 5, n: int = 3_000_000, n_views: int = 8) -> Scene:
     masks = [ellipsoid_mask(c, (0, 0, 0), OBJECT_AXES) for c in cams]
     targets = [rng.uniform(0.0, 1.0, size=(3, c.height, c.width)).astype(np.float32) for c in cams]
     means, scales, quats, opac, sh = _f32(means, scales, quats, opac, sh)
-    return Scene(means, scales, quats, opac, sh, 3, cams, masks, targets, "config5")
+    return Scene(means, scales, quats, opac, sh, 3, cams, masks, targets, "wide8-3m")
 
 
 def make_random_scene(seed: int, n: int, n_views: int = 1, width: int = 32, height: int = 32,
@@ -378,7 +378,8 @@ def make_random_scene(seed: int, n: int, n_views: int = 1, width: int = 32, heig
     return Scene(means, scales, quats, opac, sh, sh_degree, cams, masks, targets, f"random{seed}")
 
 
-CONFIGS = {1: make_config1, 2: make_config2, 3: make_config3, 4: make_config4, 5: make_config5}
+WORKLOADS = {"frame64-1k": make_frame64_1k, "frame800-100k": make_frame800_100k, "ragged16-1m": make_ragged16_1m,
+             "shell100": make_shell100, "wide8-3m": make_wide8_3m}
 
 
 def scene_digest(scene: Scene) -> str:

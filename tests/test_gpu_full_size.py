@@ -91,7 +91,7 @@ def _crop_forward(sc, rast, geoms, v, x0, y0, P64, w=64, h=64):
 
 
 # --------------------------------------------------------------------------
-# config 2: 800x800, 100k surfels, SH degree 3
+# frame800-100k: one 800x800 view, 100k surfels, SH degree 3
 # --------------------------------------------------------------------------
 
 def _gpu_crop_grads(sc, x0, y0, w, h, gamma=0.5, w_c=1.0):
@@ -131,11 +131,11 @@ def _oracle_crop_loss_fn(sc, x0, y0, w, h, gamma=0.5, w_c=1.0):
     return pix, lf
 
 
-def test_config2_crop_backward_and_fd_subset():
+def test_frame800_crop_backward_and_fd_subset():
     """Gradients of the crop loss: GPU vs oracle autograd on every surfel,
     and GPU vs central finite differences of the FP64 oracle on 200
     surfels (seed 22) visible in the crop [368, 432)^2."""
-    sc = scenes.make_config2()
+    sc = scenes.make_frame800_100k()
     x0 = y0 = 368
     g, Lg = _gpu_crop_grads(sc, x0, y0, 64, 64)
     geom = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, sc.cams[0], RP)
@@ -206,18 +206,18 @@ def test_config2_crop_backward_and_fd_subset():
 
 
 # --------------------------------------------------------------------------
-# config 3: 16 views 400..1600 px, 1M surfels (the benchmark workload)
+# ragged16-1m: 16 views 400..1600 px, 1M surfels (the benchmark workload)
 # --------------------------------------------------------------------------
 
-def test_config3_full_size():
-    sc = scenes.make_config3()
+def test_ragged16_full_size():
+    sc = scenes.make_ragged16_1m()
     run = gpu_run(sc, keys64=True, stats=True)
     rast = run["rast"]
-    print("config3: GPU pass done", flush=True)
+    print("ragged16-1m: GPU pass done", flush=True)
     geoms = _geoms_parallel(sc)
-    print("config3: oracle geometry of 16 views done", flush=True)
+    print("ragged16-1m: oracle geometry of 16 views done", flush=True)
     ex = _records_bit_exact(sc, rast, geoms)
-    print("config3 records bit-exact; grid-tie exemptions", ex)
+    print("ragged16-1m records bit-exact; grid-tie exemptions", ex)
     vis, need, stored, status = run["status"]
     assert status == 0 and vis == sum(int((~g["culled"]).sum()) for g in geoms.values())
     assert need == group_instances(list(geoms.values()))
@@ -229,39 +229,39 @@ def test_config3_full_size():
         x0 = int(rng.integers(0, cam.width - 64))
         y0 = int(rng.integers(0, cam.height - 64))
         errs, fl = _crop_forward(sc, rast, geoms, v, cam.width // 2 - 32, cam.height // 2 - 32, P64)
-        print(f"config3 view {v} centre crop errors {errs} flagged {fl}")
+        print(f"ragged16-1m view {v} centre crop errors {errs} flagged {fl}")
         errs, fl = _crop_forward(sc, rast, geoms, v, x0, y0, P64, w=32, h=32)
-        print(f"config3 view {v} crop ({x0},{y0}) errors {errs} flagged {fl}")
+        print(f"ragged16-1m view {v} crop ({x0},{y0}) errors {errs} flagged {fl}")
 
 
-def test_config5_crop():
-    sc = scenes.make_config5()
+def test_wide8_crop():
+    sc = scenes.make_wide8_3m()
     run = gpu_run(sc, stats=True)
     rast = run["rast"]
     geoms = _geoms_parallel(sc, views=[0])
     assert _records_bit_exact(sc, rast, geoms) == 0
     P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3)
     errs, fl = _crop_forward(sc, rast, geoms, 0, 948, 513, P64)
-    print("config5 crop errors", errs, "flagged", fl)
+    print("wide8-3m crop errors", errs, "flagged", fl)
 
 
 # --------------------------------------------------------------------------
-# config 4: occlusion pruning over 100 views of the shell scene
+# shell100: occlusion pruning over 100 views of the shell scene
 # --------------------------------------------------------------------------
 
-def test_config4_pruning_shell_scene():
+def test_shell100_pruning():
     """Section 4.3 on the shell scene over 100 views: every interior surfel is
     inside the frustum of every view yet never blended (pruned), the mask is
     exactly 'never blended', and a sampled set of surfels has the oracle's
     statistics."""
     from paper_2501_08174_amd.raster import prune_contrib
-    sc = scenes.make_config4()
+    sc = scenes.make_shell100()
     N = sc.n
     p = Params.from_scene(sc)
-    print("config4: scene ready", flush=True)
+    print("shell100: scene ready", flush=True)
     st = prune_contrib(p, sc.cams, views_per_chunk=20)
     torch.cuda.synchronize()
-    print("config4: pruning pass over 100 views done", flush=True)
+    print("shell100: pruning pass over 100 views done", flush=True)
     mask = st.mask.cpu().numpy().astype(bool)
     h = st.hits.cpu().numpy()
     infr = st.in_frustum.cpu().numpy().astype(bool)
@@ -280,7 +280,7 @@ def test_config4_pruning_shell_scene():
     st10 = prune_contrib(p, sub_cams)
     sub = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0, sub_cams, sc.masks[:10])
     geoms = _geoms_parallel(sub)
-    print("config4: oracle geometry of 10 views done", flush=True)
+    print("shell100: oracle geometry of 10 views done", flush=True)
     h10 = st10.hits.cpu().numpy()
     ma10 = st10.max_alpha.cpu().numpy()
     inf10 = st10.in_frustum.cpu().numpy().astype(bool)
@@ -315,7 +315,7 @@ def test_config4_pruning_shell_scene():
     assert checked >= sample.size // 2
 
 
-def test_config3_regularizers_full_size():
+def test_ragged16_regularizers_full_size():
     """The 2DGS terms of Eq. 3 on the full config-3 forward (16 views,
     16.6 Mpx): per-view losses against the oracle over whole views; the
     gradients on sampled crops (the oracle evaluated on the crop grown by the
@@ -323,7 +323,7 @@ def test_config3_regularizers_full_size():
     pixels whose depth normals are ill-conditioned in float32 reported apart."""
     from paper_2501_08174_amd import _lib
     from oracle.regularizers import regularizer_view64
-    sc = scenes.make_config3()
+    sc = scenes.make_ragged16_1m()
     run = gpu_run(sc)
     rast, views = run["rast"], run["views"]
     wd, wn = 1000.0, 0.05
@@ -332,14 +332,14 @@ def test_config3_regularizers_full_size():
     dD, dN, dS = torch.zeros(P, device="cuda"), torch.zeros(3 * P, device="cuda"), torch.zeros(P, device="cuda")
     loss = rast.regularizer_loss(wd, wn, dA, dD, dN, dS).cpu().numpy()
     torch.cuda.synchronize()
-    print("config3 regularisers: GPU pass done", flush=True)
+    print("ragged16-1m regularisers: GPU pass done", flush=True)
     rng = np.random.default_rng(9)
     for v in range(V):
         pv = per_view(rast, v)
         L_d, L_n = regularizer_view64(pv["alpha"], pv["depth"], pv["normal"], pv["dist"], sc.cams[v])
         assert abs(loss[v] - float(L_d)) <= 1e-4 * abs(float(L_d)) + 1e-7, (v, loss[v], float(L_d))
         assert abs(loss[V + v] - float(L_n)) <= 1e-4 * abs(float(L_n)) + 1e-7, (v, loss[V + v], float(L_n))
-    print("config3 regularisers: 16 per-view losses match", flush=True)
+    print("ragged16-1m regularisers: 16 per-view losses match", flush=True)
     dA, dD, dN, dS = (t.cpu().numpy() for t in (dA, dD, dN, dS))
     for v in (0, 7, 13):
         cam = sc.cams[v]
@@ -383,5 +383,5 @@ def test_config3_regularizers_full_size():
                 scale = np.abs(r).max()
                 err = np.abs(gg - r).max() / max(scale, 1e-30)
                 assert err <= 1e-3, (v, x0, y0, name, err)
-            print(f"config3 view {v} crop ({x0},{y0}): gradients match; ill-conditioned pixels apart: "
+            print(f"ragged16-1m view {v} crop ({x0},{y0}): gradients match; ill-conditioned pixels apart: "
                   f"{int((~keep).sum())}", flush=True)

@@ -87,13 +87,13 @@ def test_binning_bit_exact_and_statistics():
 
 
 def test_shell_scene_3d_over_100_views():
-    sc, s3 = scenes.make_config4_3d()
+    sc, s3 = scenes.make_shell100_3d()
     N = sc.n
     args = [_t(sc.means), _t(s3), _t(sc.quats), _t(sc.opac)]
-    print("config4-3d: scene ready", flush=True)
+    print("shell100 3D Gaussians: scene ready", flush=True)
     st = prune_contrib_3d(*args, sc.cams, views_per_chunk=20)
     torch.cuda.synchronize()
-    print("config4-3d: pruning pass over 100 views done", flush=True)
+    print("shell100 3D Gaussians: pruning pass over 100 views done", flush=True)
     mask = st.mask.cpu().numpy().astype(bool)
     h = st.hits.cpu().numpy()
     infr = st.in_frustum.cpu().numpy().astype(bool)

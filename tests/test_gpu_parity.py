@@ -35,7 +35,7 @@ def _ragged_scene(seed=31, n=300, deg=0):
 # binning
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("make", [lambda: _ragged_scene(), lambda: scenes.make_config1(),
+@pytest.mark.parametrize("make", [lambda: _ragged_scene(), lambda: scenes.make_frame64_1k(),
                                   lambda: scenes.make_random_scene(32, 2000, n_views=2, width=[100, 129],
                                                                    height=[77, 50], scale_range=(0.01, 0.6))])
 def test_binning_bit_exact(make):
@@ -71,15 +71,15 @@ def test_every_tile_shape_bins_and_renders(tile):
 # forward
 # --------------------------------------------------------------------------
 
-def test_forward_config1_full_frame():
-    sc = scenes.make_config1()
+def test_forward_frame64_full_frame():
+    sc = scenes.make_frame64_1k()
     run = gpu_run(sc)
     geoms = geometry(sc)
     pix = _full(sc.cams[0])
     res = render_pixels(Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 0), sc.cams[0],
                         geoms[0], pix, RP)
     errs, flagged = compare_forward(per_view(run["rast"], 0), res, pix, run["rast"], 0)
-    print("config1 errors", errs, "flagged", flagged)
+    print("frame64-1k errors", errs, "flagged", flagged)
     assert flagged < 1e-2
 
 
@@ -441,7 +441,7 @@ def test_edge_cases_empty_and_tiny():
 
 
 def test_capacity_overflow_is_reported():
-    sc = scenes.make_config1()
+    sc = scenes.make_frame64_1k()
     run = gpu_run(sc, capacity=100)
     vis, need, stored, status = run["status"]
     assert status == 1 and stored == 100 and need > 100

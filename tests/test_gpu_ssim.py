@@ -86,11 +86,11 @@ def test_metrics_only_and_identical_images():
     assert abs(out2[0] - float(oracle.masked_ssim64(C[0], I[0], M[0]))) <= 2e-5
 
 
-def test_ssim_config3_full_size():
+def test_ssim_ragged16_full_size():
     """Whole config-3 views: SSIM and PSNR per view against the oracle;
     gradients on sampled crops (the oracle on the crop grown by the ten-pixel
     reach of forward and backward filters, rescaled to whole-view means)."""
-    sc = scenes.make_config3()
+    sc = scenes.make_ragged16_1m()
     run = gpu_run(sc)
     rast, views = run["rast"], run["views"]
     mask = _flat([m for m in sc.masks], torch.uint8)
@@ -101,13 +101,13 @@ def test_ssim_config3_full_size():
     torch.cuda.synchronize()
     dC = dC.cpu().numpy()
     V = views.V
-    print("config3 ssim: GPU pass done", flush=True)
+    print("ragged16-1m ssim: GPU pass done", flush=True)
     for v in range(V):
         pv = per_view(rast, v)
         s = float(oracle.masked_ssim64(pv["color"], sc.targets[v], sc.masks[v]))
         assert abs(out[v] - s) <= 1e-4, (v, out[v], s)
         assert abs(out[V + v] - oracle.masked_psnr64(pv["color"], sc.targets[v], sc.masks[v])) <= 2e-3
-    print("config3 ssim: 16 per-view SSIM and PSNR match", flush=True)
+    print("ragged16-1m ssim: 16 per-view SSIM and PSNR match", flush=True)
     for v in (2, 9):
         cam = sc.cams[v]
         W, H = cam.width, cam.height
@@ -128,7 +128,7 @@ def test_ssim_config3_full_size():
             gy = np.arange(y0, y0 + 48)[:, None] * W + np.arange(x0, x0 + 48)[None, :]
             got = np.stack([dC[3 * o + c * HW + gy] for c in range(3)])
             err = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
-            print(f"config3 view {v} crop ({x0},{y0}): gradient inf-norm relative error {err:.2e}, "
+            print(f"ragged16-1m view {v} crop ({x0},{y0}): gradient inf-norm relative error {err:.2e}, "
                   f"max |grad| {np.abs(ref).max():.2e}", flush=True)
             assert err <= 1e-3
             if (x0, y0) != (0, 0):

@@ -290,8 +290,8 @@ def test_rect_contains_every_contributing_pixel(rp):
 # invariants on random scenes
 # --------------------------------------------------------------------------
 
-def test_invariants_config1(rp):
-    sc = scenes.make_config1()
+def test_invariants_frame64(rp):
+    sc = scenes.make_frame64_1k()
     res, pix, g = _render(sc, rp)
     A, T = res["alpha"], res["T_final"]
     assert np.all(A >= 0) and np.all(A <= 1 - rp.t_min + 1e-15)
