@@ -123,26 +123,23 @@ __device__ __forceinline__ void cross3d(const double* a, const double* b, double
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// The per-(view, surfel) outputs of the projection.
+struct PreRec {
+    float4 geom[4];
+    float4 app[2];
+    uint32_t rx, ry;          // x_lo | x_hi << 16, y_lo | y_hi << 16: the ushort4 rectangle's bytes
+    uint32_t tiles, key;      // tiles = 0: culled (geom, app not written)
+};
+
 // DEG: SH degree of the colour (0..3), or -1 to skip shading (pruning pass).
-// One thread per (surfel g, view v), t = g * V + v: the views of one surfel
-// sit in adjacent lanes, so the parameter loads of a wave are shared and the
-// surfel is read from HBM once per batch; in_frustum must hold zeros on entry
-// (each thread that keeps the surfel stores 1).
+// Projects surfel g into view v; returns false when it is culled.
 template <int DEG>
-__global__ void __launch_bounds__(256)
-k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ scales,
-             const float* __restrict__ quats, const float* __restrict__ opac,
-             const float* __restrict__ sh, int sh_stride, float alpha_min,
-             int tile_w, int tile_h, int V, const sr_camera* __restrict__ cams,
-             float4* __restrict__ geom, float4* __restrict__ app, ushort4* __restrict__ rect,
-             uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_key,
-             uint8_t* __restrict__ in_frustum) {
+__device__ __forceinline__ bool project_record(int g, int v, int N, const float* __restrict__ means,
+                                               const float* __restrict__ scales, const float* __restrict__ quats,
+                                               const float* __restrict__ opac, const float* __restrict__ sh,
+                                               int sh_stride, float alpha_min, int tile_w, int tile_h,
+                                               const sr_camera* __restrict__ cams, PreRec& out) {
 #pragma clang fp contract(off)
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (uint64_t)N * (uint64_t)V) return;
-    const int g = (int)(t / (uint64_t)V);
-    const int v = (int)(t - (uint64_t)g * (uint64_t)V);
-    const size_t r = (size_t)v * N + g;
     const double mu[3] = {(double)means[3 * g], (double)means[3 * g + 1], (double)means[3 * g + 2]};
     const double su = scales[2 * g], sv = scales[2 * g + 1];
     const float o32 = opac[g];
@@ -209,16 +206,16 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
         }
     }
     if (culled) {
-        tiles_touched[r] = 0u;
-        depth_key[r] = 0xFFFFFFFFu;
-        rect[r] = make_ushort4(0, 0, 0, 0);
-        return;
+        out.tiles = 0u;
+        out.key = 0xFFFFFFFFu;
+        out.rx = out.ry = 0u;
+        return false;
     }
-    if (in_frustum) in_frustum[g] = 1;
     const int txlo = ilo / tile_w, txhi = ihi / tile_w, tylo = jlo / tile_h, tyhi = jhi / tile_h;
-    tiles_touched[r] = (uint32_t)((txhi - txlo + 1) * (tyhi - tylo + 1));
-    depth_key[r] = __float_as_uint((float)pz);
-    rect[r] = make_ushort4((unsigned short)ilo, (unsigned short)ihi, (unsigned short)jlo, (unsigned short)jhi);
+    out.tiles = (uint32_t)((txhi - txlo + 1) * (tyhi - tylo + 1));
+    out.key = __float_as_uint((float)pz);
+    out.rx = (uint32_t)ilo | ((uint32_t)ihi << 16);
+    out.ry = (uint32_t)jlo | ((uint32_t)jhi << 16);
     // inverse homography columns: A = m2 x m3, B = m3 x m1, C = m1 x m2;
     // shifted to the float32 centre: C' = C + A cx + B cy
     double A[3], B[3], C[3];
@@ -228,10 +225,10 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
     const float cx32 = (float)ccx, cy32 = (float)ccy;
     double Cs[3];
     for (int i = 0; i < 3; ++i) Cs[i] = (C[i] + A[i] * (double)cx32) + B[i] * (double)cy32;
-    geom[4 * r + 0] = make_float4((float)A[0], (float)A[1], (float)A[2], (float)B[0]);
-    geom[4 * r + 1] = make_float4((float)B[1], (float)B[2], (float)Cs[0], (float)Cs[1]);
-    geom[4 * r + 2] = make_float4((float)Cs[2], cx32, cy32, o32);
-    geom[4 * r + 3] = make_float4((float)m3[0], (float)m3[1], (float)m3[2], (float)L);
+    out.geom[0] = make_float4((float)A[0], (float)A[1], (float)A[2], (float)B[0]);
+    out.geom[1] = make_float4((float)B[1], (float)B[2], (float)Cs[0], (float)Cs[1]);
+    out.geom[2] = make_float4((float)Cs[2], cx32, cy32, o32);
+    out.geom[3] = make_float4((float)m3[0], (float)m3[1], (float)m3[2], (float)L);
     if (DEG >= 0) {
         constexpr int K = (DEG + 1) * (DEG + 1);
         const float* cp = cams[v].campos;
@@ -250,12 +247,109 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
         }
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0f ? rgb[ch] : 0.0f;
-        app[2 * r + 0] = make_float4(rgb[0], rgb[1], rgb[2], (float)nc[0]);
+        out.app[0] = make_float4(rgb[0], rgb[1], rgb[2], (float)nc[0]);
         // the pixel rectangle packed in the last two slots (column and row
         // ranges): the compositing skips, per wave, entries whose rectangle
         // misses the wave's pixels
-        app[2 * r + 1] = make_float4((float)nc[1], (float)nc[2], __uint_as_float((uint32_t)ilo | ((uint32_t)ihi << 16)),
-                                     __uint_as_float((uint32_t)jlo | ((uint32_t)jhi << 16)));
+        out.app[1] = make_float4((float)nc[1], (float)nc[2], __uint_as_float(out.rx),
+                                 __uint_as_float(out.ry));
+    }
+    return true;
+}
+
+// Records of one workgroup staged in LDS (STAGED path).
+struct PreStage {
+    float4 geom[4][256];
+    float4 app[2][256];
+    uint2 rect[256];
+    uint32_t tiles[256], key[256];
+};
+
+// One thread per (surfel g, view v), t = g * V + v: the views of one surfel
+// sit in adjacent lanes, so the parameter loads of a wave are shared and the
+// surfel is read from HBM once per batch; in_frustum must hold zeros on entry
+// (each thread that keeps the surfel stores 1).  STAGED (V divides the
+// workgroup size, so a workgroup holds 256 / V whole surfels): the records are
+// assembled in LDS and written view by view, each view's records of the
+// workgroup a contiguous run, instead of one scattered piece per lane.
+template <int DEG, bool STAGED>
+__global__ void __launch_bounds__(256)
+k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ scales,
+             const float* __restrict__ quats, const float* __restrict__ opac,
+             const float* __restrict__ sh, int sh_stride, float alpha_min,
+             int tile_w, int tile_h, int V, const sr_camera* __restrict__ cams,
+             float4* __restrict__ geom, float4* __restrict__ app, uint2* __restrict__ rect,
+             uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_key,
+             uint8_t* __restrict__ in_frustum) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = t < (uint64_t)N * (uint64_t)V;
+    const int g = (int)(t / (uint64_t)V);
+    const int v = (int)(t - (uint64_t)g * (uint64_t)V);
+    PreRec rec;
+    rec.tiles = 0u;
+    rec.key = 0xFFFFFFFFu;
+    rec.rx = rec.ry = 0u;
+    bool vis = false;
+    if (live) {
+        vis = project_record<DEG>(g, v, N, means, scales, quats, opac, sh, sh_stride, alpha_min, tile_w, tile_h,
+                                  cams, rec);
+        if (vis && in_frustum) in_frustum[g] = 1;
+    }
+    if (!STAGED) {
+        if (!live) return;
+        const size_t r = (size_t)v * N + g;
+        tiles_touched[r] = rec.tiles;
+        depth_key[r] = rec.key;
+        rect[r] = make_uint2(rec.rx, rec.ry);
+        if (!vis) return;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) geom[4 * r + q] = rec.geom[q];
+        if (DEG >= 0) {
+            app[2 * r + 0] = rec.app[0];
+            app[2 * r + 1] = rec.app[1];
+        }
+        return;
+    }
+    __shared__ PreStage sm;
+    const int tid = threadIdx.x;
+    sm.tiles[tid] = rec.tiles;
+    sm.key[tid] = rec.key;
+    sm.rect[tid] = make_uint2(rec.rx, rec.ry);
+    if (vis) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sm.geom[q][tid] = rec.geom[q];
+        if (DEG >= 0) {
+            sm.app[0][tid] = rec.app[0];
+            sm.app[1][tid] = rec.app[1];
+        }
+    }
+    __syncthreads();
+    // slot s = (surfel - G0) * V + view; output position p = view * ng + (surfel - G0)
+    const int lv = __builtin_ctz((unsigned)V);
+    const int lng = 8 - lv;                     // ng = 256 / V surfels per workgroup
+    const int G0 = (int)blockIdx.x << lng;
+    {
+        const int vv = tid >> lng, gl = tid & ((1 << lng) - 1), s = (gl << lv) + vv, gg = G0 + gl;
+        if (gg < N) {
+            const size_t r = (size_t)vv * N + gg;
+            tiles_touched[r] = sm.tiles[s];
+            depth_key[r] = sm.key[s];
+            rect[r] = sm.rect[s];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = i * 256 + tid, pp = j >> 2, q = j & 3;
+        const int vv = pp >> lng, gl = pp & ((1 << lng) - 1), s = (gl << lv) + vv, gg = G0 + gl;
+        if (gg < N && sm.tiles[s] != 0u) geom[4 * ((size_t)vv * N + gg) + q] = sm.geom[q][s];
+    }
+    if (DEG >= 0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int j = i * 256 + tid, pp = j >> 1, q = j & 1;
+            const int vv = pp >> lng, gl = pp & ((1 << lng) - 1), s = (gl << lv) + vv, gg = G0 + gl;
+            if (gg < N && sm.tiles[s] != 0u) app[2 * ((size_t)vv * N + gg) + q] = sm.app[q][s];
+        }
     }
 }
 
@@ -472,10 +566,17 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
     if (threads == 0) return hipGetLastError();
     dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     const int deg = app ? cfg.sh_degree : -1;
-#define SR_PRE(D)                                                                                             \
-    hipLaunchKernelGGL(k_preprocess<D>, grid, block, 0, stream, N, means, scales, quats, opac, sh, cfg.sh_stride, \
-                       cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev, (float4*)geom, (float4*)app,        \
-                       (ushort4*)rect, tiles_touched, depth_key, in_frustum)
+    // staged writes when V divides the workgroup size (V a power of two <= 256)
+    const bool staged = V <= 256 && (256 % V) == 0;
+#define SR_PRE(D)                                                                                                 \
+    if (staged)                                                                                                   \
+        hipLaunchKernelGGL((k_preprocess<D, true>), grid, block, 0, stream, N, means, scales, quats, opac, sh,    \
+                           cfg.sh_stride, cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev, (float4*)geom,      \
+                           (float4*)app, (uint2*)rect, tiles_touched, depth_key, in_frustum);                     \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_preprocess<D, false>), grid, block, 0, stream, N, means, scales, quats, opac, sh,   \
+                           cfg.sh_stride, cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev, (float4*)geom,      \
+                           (float4*)app, (uint2*)rect, tiles_touched, depth_key, in_frustum)
     switch (deg) {
         case 0: SR_PRE(0); break;
         case 1: SR_PRE(1); break;
