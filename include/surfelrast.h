@@ -315,7 +315,8 @@ sr_status sr_ssim_loss(int32_t V, const sr_camera *cams_host, const sr_camera *c
 
 /* Fused training step of the compositing, one launch for all views: per
  * tile, the forward of sr_render_forward (same outputs, same decisions;
- * the same optional statistics: hits alone, or hits with both maxima), the masked
+ * the same optional statistics: hits alone, counted by the backward phase
+ * from the same blend decisions, or hits with both maxima), the masked
  * L1 + background loss gradients of sr_background_loss for every pixel
  * (Eq. 1, Eq. 2; mask [P] uint8, target [3P]), and the backward of
  * sr_backward_raster, with the per-pixel state kept on chip.

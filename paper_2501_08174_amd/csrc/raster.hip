@@ -541,12 +541,17 @@ __device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float
 // GEO: the loss has depth, normal or distortion terms (their upstream
 // gradients are read); without them the depth path and six of the per-record
 // components are identically zero and are not computed or reduced.
-template <int TW, int NT, int BATCH, bool GEO>
+// HITS (without GEO): the backward also counts, per entry, the pixels that
+// blend it (the forward's blend decisions, recomputed: positions below the
+// pixel's last contributor that pass the cutoff), in the free component of
+// the wave reduction, and adds the count to hits[g] at the flush.
+template <int TW, int NT, int BATCH, bool GEO, bool HITS = false>
 __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, BwdSmem<BATCH>& sm, PixBwd pb,
-                                         float* __restrict__ grad_rec) {
+                                         float* __restrict__ grad_rec, uint32_t* __restrict__ hits = nullptr) {
     static_assert(BATCH <= NT, "one record per thread and batch");
+    static_assert(!(HITS && GEO), "the count takes a component slot of the depth terms");
     const int tid = threadIdx.x;
     const int lane = __lane_id();
     __syncthreads();
@@ -665,10 +670,14 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                 float c16[16];
 #pragma unroll
                 for (int i = 0; i < 12; ++i) c16[i] = gr[i];
-                c16[12] = gr[15]; c16[13] = gr[16]; c16[14] = gr[17]; c16[15] = 0.f;
+                c16[12] = gr[15]; c16[13] = gr[16]; c16[14] = gr[17];
+                // HITS: the blending pixels, summed exactly (at most 64 per wave)
+                c16[15] = HITS && bl ? 1.f : 0.f;
                 const float tot = wave_tsum<16>(c16);
                 const int ci = wave_tsum_comp<16>(lane);
-                if ((lane & 12) == 0 && ci < 15) atomicAdd(&sm.acc[k][ci < 12 ? ci : ci + 3], tot);
+                // components 12..14 go to slots 15..17; the count to slot 12 (a depth slot)
+                if ((lane & 12) == 0 && ci < (HITS ? 16 : 15))
+                    atomicAdd(&sm.acc[k][ci < 12 ? ci : (ci < 15 ? ci + 3 : 12)], tot);
             }
             if (GEO) {
                 float c8[8] = {gr[12], gr[13], gr[14], gr[18], gr[19], gr[20], 0.f, 0.f};
@@ -683,8 +692,13 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
             float* dst = grad_rec + (size_t)sm.rec[tid] * SR_GRAD_STRIDE;
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) {
+                if (HITS && i == 12) continue;
                 const float vsum = sm.acc[tid][i];
                 if (vsum != 0.f) atomicAdd(&dst[i], vsum);
+            }
+            if (HITS) {
+                const uint32_t n = (uint32_t)sm.acc[tid][12];
+                if (n != 0u) atomicAdd(&hits[sm.rec[tid] - (uint32_t)t.v * (uint32_t)N], n);
             }
         }
     }
@@ -724,13 +738,14 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     bwd_tile<TW, TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
 }
 
-// One training step of the compositing for a tile: forward (STATS = 1 also
-// counts the blended pixels of every surfel, the usage record of Section 4.3;
-// STATS = 2 adds the maximum alpha and weight; 0 tracks nothing), the masked
-// L1 + background loss gradients of every pixel (Eq. 1, Eq. 2) and the
-// backward, with the per-pixel state kept in registers between the phases.
-// Per-tile loss partial sums go to tile_loss[2*tile] (L_b numerator, L1
-// numerator).
+// One training step of the compositing for a tile: forward, the masked L1 +
+// background loss gradients of every pixel (Eq. 1, Eq. 2) and the backward,
+// with the per-pixel state kept in registers between the phases.  STATS = 1
+// counts the blended pixels of every surfel (the usage record of Section
+// 4.3), taken by the backward, which recomputes the same blend decisions;
+// STATS = 2 has the forward take the count and the maximum alpha and weight;
+// 0 records nothing.  Per-tile loss partial sums go to tile_loss[2*tile]
+// (L_b numerator, L1 numerator).
 template <int TW, int TH, int BATCH, int STATS>
 __global__ void __launch_bounds__(TW * TH) SR_RASTER_OCCUPANCY
 k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom,
@@ -741,7 +756,7 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
                uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
                float* __restrict__ max_weight, float* __restrict__ tile_loss, float* __restrict__ grad_rec) {
     constexpr int NT = TW * TH;
-    constexpr int MODE = kShade | (STATS == 2 ? kStats : STATS == 1 ? kHits : 0);
+    constexpr int MODE = kShade | (STATS == 2 ? kStats : 0);
     constexpr size_t kF = sizeof(FwdSmem<NT, MODE>), kB = sizeof(BwdSmem<BATCH>);
     __shared__ __align__(16) unsigned char smem[kF > kB ? kF : kB];
     __shared__ float s_red[NT];
@@ -790,8 +805,8 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
         __syncthreads();
     }
     if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile + 1] = s_red[0];
-    bwd_tile<TW, NT, BATCH, false>(t, px, py, N, geom, app, vals, rc, *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb,
-                               grad_rec);
+    bwd_tile<TW, NT, BATCH, false, STATS == 1>(t, px, py, N, geom, app, vals, rc,
+                                               *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec, hits);
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, float v, uint64_t n) {
