@@ -249,7 +249,7 @@ def main():
     ms_per_step = wall / args.steps * 1e3
 
     result = {
-        "metric": "fwd+bwd Mpixel/s (batched, 1M surfels)",
+        "metric": f"fwd+bwd Mpixel/s (batched, {N / 1e6:g}M surfels)",
         "value": P / (ms_per_step * 1e-3) / 1e6,
         "unit": "Mpixel/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
