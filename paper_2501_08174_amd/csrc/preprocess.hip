@@ -401,9 +401,17 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
 
     float dmu[3] = {0, 0, 0}, dsu = 0, dsv = 0, dopac = 0;
     float dtu[3] = {0, 0, 0}, dtv[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
-    float dsh[3 * K];
+    // SH gradient accumulators: registers up to degree 1, a private LDS
+    // column per thread above (48 floats at degree 3 would halve occupancy)
+    constexpr bool SH_LDS = DEG >= 2;
+    __shared__ float s_dsh[SH_LDS ? 3 * K : 1][SH_LDS ? 256 : 1];
+    float dsh[SH_LDS ? 1 : 3 * K];
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < 3 * K; ++i) dsh[i] = 0.0f;
+    for (int i = 0; i < 3 * K; ++i) {
+        if (SH_LDS) s_dsh[i][tid] = 0.0f;
+        else dsh[i] = 0.0f;
+    }
     const float* shg = sh + (size_t)g * sh_stride * 3;
 
     for (int v = 0; v < V; ++v) {
@@ -518,9 +526,15 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float f0 = shg[3 * k], f1 = shg[3 * k + 1], f2 = shg[3 * k + 2];
-                dsh[3 * k + 0] += Y[k] * dr[0];
-                dsh[3 * k + 1] += Y[k] * dr[1];
-                dsh[3 * k + 2] += Y[k] * dr[2];
+                if (SH_LDS) {
+                    s_dsh[3 * k + 0][tid] += Y[k] * dr[0];
+                    s_dsh[3 * k + 1][tid] += Y[k] * dr[1];
+                    s_dsh[3 * k + 2][tid] += Y[k] * dr[2];
+                } else {
+                    dsh[3 * k + 0] += Y[k] * dr[0];
+                    dsh[3 * k + 1] += Y[k] * dr[1];
+                    dsh[3 * k + 2] += Y[k] * dr[2];
+                }
                 const float s = f0 * dr[0] + f1 * dr[1] + f2 * dr[2];
                 dd[0] += s * gx[k];
                 dd[1] += s * gy[k];
@@ -548,7 +562,7 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
     g_opac[g] += dopac;
     float* gs = g_sh + (size_t)g * sh_stride * 3;
 #pragma unroll
-    for (int i = 0; i < 3 * K; ++i) gs[i] += dsh[i];
+    for (int i = 0; i < 3 * K; ++i) gs[i] += SH_LDS ? s_dsh[i][tid] : dsh[SH_LDS ? 0 : i];
     if (dens_grad) dens_grad[g] += dens_sum;
     if (dens_count) dens_count[g] += dens_n;
 }
