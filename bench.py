@@ -405,9 +405,9 @@ def main():
         s3t = torch.tensor(s3, device="cuda")
         P4 = sum(c.width * c.height for c in sc4.cams)
         legs = {}
-        for name, fn in (("surfels", lambda: prune_contrib(p4, sc4.cams, views_per_chunk=20)),
+        for name, fn in (("surfels", lambda: prune_contrib(p4, sc4.cams, views_per_chunk=32)),
                          ("gaussians_3d", lambda: prune_contrib_3d(p4.means, s3t, p4.quats, p4.opac, sc4.cams,
-                                                                   views_per_chunk=20))):
+                                                                   views_per_chunk=32))):
             fn()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -417,7 +417,7 @@ def main():
             legs[name] = {"s": dt, "Mpixel_per_s": P4 / dt / 1e6,
                           "pruned": int(st.mask.sum().item()), "of": sc4.n}
         result["pruning_pass"] = {"workload": "shell100: shell scene, 100 views 800x800, 1.1M primitives, "
-                                              "views in chunks of 20 (capacity planning included)", **legs}
+                                              "views in chunks of 32 (capacity planning included)", **legs}
         del p4, s3t
 
     if args.copy_calibration:

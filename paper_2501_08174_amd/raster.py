@@ -362,7 +362,7 @@ class PruneStats:
     mask: torch.Tensor          # uint8 [N] 1 = prune (max_alpha < tau)
 
 
-def prune_contrib(params: Params, cams: Sequence, views_per_chunk: int = 25, tau: float = ALPHA_MIN,
+def prune_contrib(params: Params, cams: Sequence, views_per_chunk: int = 32, tau: float = ALPHA_MIN,
                   tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None) -> PruneStats:
     """Occlusion-aware pruning pass (Section 4.3) over every view: projection
     without shading, binning and the compositing decisions, accumulating the
@@ -606,7 +606,7 @@ class Pruner3D:
         return int(c[0]), int(c[1]), int(c[2]), int(c[3])
 
 
-def prune_contrib_3d(means, scales, quats, opac, cams: Sequence, views_per_chunk: int = 25, tau: float = ALPHA_MIN,
+def prune_contrib_3d(means, scales, quats, opac, cams: Sequence, views_per_chunk: int = 32, tau: float = ALPHA_MIN,
                      tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None) -> PruneStats:
     """The occlusion-pruning pass for 3D Gaussians over every view (chunks of
     views bound the instance buffers), statistics accumulated, then the mask."""
