@@ -323,6 +323,16 @@ sr_status sr_ssim_loss(int32_t V, const sr_camera *cams_host, const sr_camera *c
  *   tile_loss [2T]  scratch: per-tile partial sums
  *   loss [2V+1]     as sr_background_loss (sums in tile order)
  *   grad_rec        as sr_backward_raster (zeros on entry; gradients added)
+ *   tile_order [T]  optional (NULL: the default order): the tile of each
+ *                   workgroup, a permutation of 0..T-1 as sr_tile_order
+ *                   writes it (heaviest tiles first); results do not depend
+ *                   on it (gradients up to the rounding order of float
+ *                   atomics); an entry >= T leaves its workgroup idle, so an
+ *                   array that is not a permutation leaves tiles unrendered
+ *   tile_cost [T]   optional (NULL: not recorded): written with each tile's
+ *                   cost, the largest n_contrib of its pixels (the run
+ *                   positions the tile works through), for the next call's
+ *                   order
  * Follow with sr_backward_project for the parameter gradients. */
 sr_status sr_train_step_raster(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                                const sr_camera *cams_dev, const float *geom, const float *app,
@@ -330,7 +340,20 @@ sr_status sr_train_step_raster(const sr_config *cfg, int32_t N, int32_t V, const
                                const float *target, float gamma, float w_c, float *color, float *alpha,
                                float *depth, float *normal, float *dist, float *T_final,
                                uint32_t *n_contrib, uint32_t *hits, float *max_alpha, float *max_weight,
-                               float *tile_loss, float *loss, float *grad_rec, void *stream);
+                               float *tile_loss, float *loss, float *grad_rec, const uint32_t *tile_order,
+                               uint32_t *tile_cost, void *stream);
+
+/* Dispatch order for sr_train_step_raster: the T tile ids sorted by
+ * descending tile_cost [T] (costs above 2^24 - 1 count as 2^24 - 1; equal
+ * costs keep ascending tile id), written to tile_order [T].  The per-tile
+ * work of a training step varies by two orders of magnitude (tiles near a
+ * camera, under large splats); launched heaviest first, no heavy tile is left
+ * for the end of the grid.  The costs of one step order the next (the views
+ * and, slowly, the parameters change between steps).  workspace: device
+ * memory of sr_tile_order_workspace_size bytes; no host synchronisation. */
+sr_status sr_tile_order_workspace_size(int32_t T, size_t *bytes_host);
+sr_status sr_tile_order(int32_t T, const uint32_t *tile_cost, void *workspace, size_t ws_bytes,
+                        uint32_t *tile_order, void *stream);
 
 /* Occlusion-aware pruning statistics (Section 4.3): the compositing
  * decisions of sr_render_forward without shading.  For every blended

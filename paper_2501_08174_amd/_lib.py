@@ -31,7 +31,7 @@ EXPORTED = (
     "sr_backward_raster", "sr_backward_project", "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_ssim_workspace_size", "sr_ssim_loss",
     "sr_compact_workspace_size", "sr_compact_surfels", "sr_preprocess_3d", "sr_prune_contrib_3d",
     "sr_train_step_raster", "sr_prune_contrib",
-    "sr_render_count", "sr_prune_mask",
+    "sr_render_count", "sr_prune_mask", "sr_tile_order_workspace_size", "sr_tile_order",
 )
 
 
@@ -89,7 +89,9 @@ def _declare(lib):
         "sr_prune_contrib_3d": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
         "sr_compact_surfels": (c_int32, [c_int32, V, V, c_float, c_int32, V, V, V, V, c_size_t, V, V]),
         "sr_train_step_raster": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
-                                 + [V] * 14),
+                                 + [V] * 16),
+        "sr_tile_order_workspace_size": (c_int32, [c_int32, POINTER(c_size_t)]),
+        "sr_tile_order": (c_int32, [c_int32, V, V, c_size_t, V, V]),
         "sr_prune_contrib": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V, V]),
         "sr_render_count": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V]),
         "sr_prune_mask": (c_int32, [c_int32, V, c_float, V, V]),

@@ -640,4 +640,65 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     return hipGetLastError();
 }
 
+// ---- tile dispatch order ------------------------------------------------------
+//
+// Tiles sorted by descending cost (ties keep ascending tile id), for a
+// launch that takes its heaviest tiles first: the per-tile cost varies by
+// two orders of magnitude, and a heavy tile dispatched late leaves the rest
+// of the chip idle at the end of the grid.
+
+namespace {
+
+constexpr int kOrderBits = 24;
+constexpr uint32_t kOrderMax = (1u << kOrderBits) - 1u;
+
+__global__ void k_order_keys(int T, const uint32_t* __restrict__ cost, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ ids, uint32_t* __restrict__ count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *count = (uint32_t)T;
+    if (i < T) {
+        const uint32_t c = cost[i] < kOrderMax ? cost[i] : kOrderMax;
+        keys[i] = kOrderMax - c;     // ascending key = descending cost
+        ids[i] = (uint32_t)i;
+    }
+}
+
+struct OrderWs {
+    uint32_t *k0, *v0, *k1, *v1, *hist, *tot, *count;
+};
+
+size_t order_ws_layout(int T, void* base, OrderWs* w) {
+    const uint64_t G = (uint64_t)grid_for((uint64_t)T);
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) -> uint32_t* {
+        uint32_t* p = base ? (uint32_t*)((char*)base + off) : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    w->k0 = take((uint64_t)T * 4);
+    w->v0 = take((uint64_t)T * 4);
+    w->k1 = take((uint64_t)T * 4);
+    w->v1 = take((uint64_t)T * 4);
+    w->hist = take((uint64_t)kMaxRadix * G * 4);
+    w->tot = take(kMaxRadix * 4);
+    w->count = take(4);
+    return (size_t)off;
+}
+
+}  // namespace
+
+size_t tile_order_workspace(int T) {
+    OrderWs w;
+    return order_ws_layout(T, nullptr, &w);
+}
+
+hipError_t launch_tile_order(int T, const uint32_t* cost, void* ws, uint32_t* order, hipStream_t s) {
+    if (T == 0) return hipSuccess;
+    OrderWs w;
+    order_ws_layout(T, ws, &w);
+    hipLaunchKernelGGL(k_order_keys, dim3((T + kNT - 1) / kNT), dim3(kNT), 0, s, T, cost, w.k0, w.v0, w.count);
+    radix_sort(w.k0, w.v0, w.k1, w.v1, order, w.count, (uint64_t)T, kOrderBits, w.hist, w.tot, s);
+    return hipGetLastError();
+}
+
 }  // namespace sr

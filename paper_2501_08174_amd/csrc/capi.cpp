@@ -538,7 +538,8 @@ sr_status sr_train_step_raster(const sr_config* cfg, int32_t N, int32_t V, const
                                const uint32_t* ranges, const uint8_t* mask, const float* target, float gamma,
                                float w_c, float* color, float* alpha, float* depth, float* normal, float* dist,
                                float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
-                               float* max_weight, float* tile_loss, float* loss, float* grad_rec, void* stream) {
+                               float* max_weight, float* tile_loss, float* loss, float* grad_rec,
+                               const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
     int total_tiles = 0;
@@ -554,7 +555,7 @@ sr_status sr_train_step_raster(const sr_config* cfg, int32_t N, int32_t V, const
     if (total_tiles == 0) return SR_OK;
     SR_TRY(hip_status(sr::launch_train_raster(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, mask, target,
                                               gamma, w_c, color, alpha, depth, normal, dist, T_final, n_contrib, hits,
-                                              max_alpha, max_weight, tile_loss, grad_rec, s),
+                                              max_alpha, max_weight, tile_loss, grad_rec, tile_order, tile_cost, s),
                       "sr_train_step_raster"));
     return hip_status(sr::launch_loss_from_tiles(V, cams_dev, tile_loss, gamma, w_c, loss, s), "loss totals");
 }
@@ -581,6 +582,24 @@ sr_status sr_prune_mask(int32_t N, const float* max_alpha, float tau, uint8_t* p
     if (N < 0) return fail(SR_ERR_ARG, "N < 0");
     if (N > 0) { SR_NEED(max_alpha); SR_NEED(prune_mask); }
     return hip_status(sr::launch_prune_mask(N, max_alpha, tau, prune_mask, (hipStream_t)stream), "sr_prune_mask");
+}
+
+sr_status sr_tile_order_workspace_size(int32_t T, size_t* bytes_host) {
+    if (T < 0) return fail(SR_ERR_ARG, "T = %d < 0", T);
+    SR_NEED(bytes_host);
+    *bytes_host = T > 0 ? sr::tile_order_workspace(T) : 0;
+    return SR_OK;
+}
+
+sr_status sr_tile_order(int32_t T, const uint32_t* tile_cost, void* workspace, size_t ws_bytes,
+                        uint32_t* tile_order, void* stream) {
+    if (T < 0) return fail(SR_ERR_ARG, "T = %d < 0", T);
+    if (T == 0) return SR_OK;
+    SR_NEED(tile_cost); SR_NEED(workspace); SR_NEED(tile_order);
+    if (ws_bytes < sr::tile_order_workspace(T))
+        return fail(SR_ERR_ARG, "workspace of %zu bytes < %zu", ws_bytes, sr::tile_order_workspace(T));
+    return hip_status(sr::launch_tile_order(T, tile_cost, workspace, tile_order, (hipStream_t)stream),
+                      "sr_tile_order");
 }
 
 }  // extern "C"

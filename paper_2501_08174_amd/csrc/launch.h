@@ -23,6 +23,8 @@ hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means
                                  hipStream_t stream);
 
 size_t bin_workspace_bytes(uint64_t VN, uint64_t cap);
+size_t tile_order_workspace(int T);
+hipError_t launch_tile_order(int T, const uint32_t* cost, void* ws, uint32_t* order, hipStream_t s);
 
 hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_tiles, int total_groups,
                                const sr_camera* cams_dev,
@@ -54,7 +56,8 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
                                const uint8_t* mask, const float* target, float gamma, float w_c, float* color,
                                float* alpha, float* depth, float* normal, float* dist, float* T_final,
                                uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                               float* tile_loss, float* grad_rec, hipStream_t s);
+                               float* tile_loss, float* grad_rec, const uint32_t* tile_order,
+                               uint32_t* tile_cost, hipStream_t s);
 
 hipError_t launch_loss_from_tiles(int V, const sr_camera* cams, const float* tile_loss, float gamma, float w_c,
                                   float* loss, hipStream_t s);

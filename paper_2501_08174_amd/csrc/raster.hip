@@ -33,9 +33,19 @@ struct TileCtx {
 };
 
 template <int TW, int TH>
+// order (optional): the tile of each workgroup, a permutation of the tile ids
+// (heaviest first); an id beyond the grid marks the workgroup idle
+// (t.n = 0, nothing inside).
 __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int V,
-                                         const uint2* __restrict__ ranges, TileCtx& t) {
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+                                         const uint2* __restrict__ ranges, TileCtx& t,
+                                         const uint32_t* __restrict__ order = nullptr) {
+    int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    bool idle = false;
+    if (order) {
+        const uint32_t o = order[blockIdx.x];
+        idle = o >= gridDim.x;
+        tile = idle ? 0 : (int)o;
+    }
     t.tile = tile;
     t.v = view_of_tile(cams, V, tile);
     const sr_camera& c = cams[t.v];
@@ -49,12 +59,12 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
     t.ty0 = ty * TH;
     t.sx = tx % SR_TILE_GROUP;
     t.sy = ty % SR_TILE_GROUP;
-    t.inside = t.ix < t.W && t.iy < t.H;
+    t.inside = !idle && t.ix < t.W && t.iy < t.H;
     t.pix_off = c.pix_offset;
     t.bg[0] = c.bg[0]; t.bg[1] = c.bg[1]; t.bg[2] = c.bg[2];
     const uint2 rg = ranges[tile];
     t.start = rg.x;
-    t.n = rg.y - rg.x;
+    t.n = idle ? 0u : rg.y - rg.x;
 }
 
 constexpr int kMaxWaves = 8;    // waves per workgroup (tiles of up to 512 pixels)
@@ -549,7 +559,8 @@ template <int TW, int NT, int BATCH, bool GEO, bool HITS = false>
 __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, BwdSmem<BATCH>& sm, PixBwd pb,
-                                         float* __restrict__ grad_rec, uint32_t* __restrict__ hits = nullptr) {
+                                         float* __restrict__ grad_rec, uint32_t* __restrict__ hits = nullptr,
+                                         uint32_t* __restrict__ cost_out = nullptr) {
     static_assert(BATCH <= NT, "one record per thread and batch");
     static_assert(!(HITS && GEO), "the count takes a component slot of the depth terms");
     const int tid = threadIdx.x;
@@ -560,6 +571,8 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
     atomicMax(&sm.maxn, pb.ncon);
     __syncthreads();
     const uint32_t maxn = sm.maxn;
+    // the tile's cost for the next launch's order: the run positions it works through
+    if (cost_out && tid == 0) *cost_out = maxn;
     if (maxn == 0u) return;
     // entries at or beyond the wave's own last contributor concern no lane
     uint32_t wave_maxn = pb.ncon;
@@ -754,14 +767,18 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
                float w_c, float* __restrict__ color, float* __restrict__ alpha, float* __restrict__ depth,
                float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
                uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
-               float* __restrict__ max_weight, float* __restrict__ tile_loss, float* __restrict__ grad_rec) {
+               float* __restrict__ max_weight, float* __restrict__ tile_loss, float* __restrict__ grad_rec,
+               const uint32_t* __restrict__ tile_order, uint32_t* __restrict__ tile_cost) {
     constexpr int NT = TW * TH;
     constexpr int MODE = kShade | (STATS == 2 ? kStats : 0);
     constexpr size_t kF = sizeof(FwdSmem<NT, MODE>), kB = sizeof(BwdSmem<BATCH>);
     __shared__ __align__(16) unsigned char smem[kF > kB ? kF : kB];
     __shared__ float s_red[NT];
     TileCtx t;
-    tile_ctx<TW, TH>(cams, V, ranges, t);
+    // an order entry beyond the grid leaves the workgroup idle (not a valid
+    // permutation: nothing of it is written)
+    if (tile_order && tile_order[blockIdx.x] >= gridDim.x) return;
+    tile_ctx<TW, TH>(cams, V, ranges, t, tile_order);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
     uint64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0;
@@ -806,7 +823,8 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     }
     if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile + 1] = s_red[0];
     bwd_tile<TW, NT, BATCH, false, STATS == 1>(t, px, py, N, geom, app, vals, rc,
-                                               *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec, hits);
+                                               *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec, hits,
+                                               tile_cost ? tile_cost + t.tile : nullptr);
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, float v, uint64_t n) {
@@ -882,12 +900,13 @@ void train_launch(int stats, int total_tiles, hipStream_t s, const sr_camera* ca
                   const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc,
                   const uint8_t* mask, const float* target, float gamma, float w_c, float* color, float* alpha,
                   float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits,
-                  float* max_alpha, float* max_weight, float* tile_loss, float* grad_rec) {
+                  float* max_alpha, float* max_weight, float* tile_loss, float* grad_rec, const uint32_t* tile_order,
+                  uint32_t* tile_cost) {
     constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
 #define SR_TRAIN(S)                                                                                              \
     hipLaunchKernelGGL((k_train_raster<TW, TH, B, S>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, \
                        app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist, T_final, \
-                       n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec)
+                       n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec, tile_order, tile_cost)
     if (stats == 2)
         SR_TRAIN(2);
     else if (stats == 1)
@@ -967,14 +986,16 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
                                const uint8_t* mask, const float* target, float gamma, float w_c, float* color,
                                float* alpha, float* depth, float* normal, float* dist, float* T_final,
                                uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                               float* tile_loss, float* grad_rec, hipStream_t s) {
+                               float* tile_loss, float* grad_rec, const uint32_t* tile_order, uint32_t* tile_cost,
+                               hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
 #define SR_TS(W, H)                                                                                               \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                    \
         train_launch<W, H>(hits ? (max_alpha ? 2 : 1) : 0, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, \
                            vals, (const uint2*)ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, \
-                           dist, T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec);           \
+                           dist, T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec,           \
+                           tile_order, tile_cost);                                                                \
         return hipGetLastError();                                                                                \
     }
     SR_TILE_SHAPES(SR_TS)

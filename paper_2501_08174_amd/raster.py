@@ -305,18 +305,39 @@ class Rasterizer:
         return self.ssim_out
 
     def train_step_raster(self, mask: torch.Tensor, target: torch.Tensor, gamma: float = 0.5, w_c: float = 1.0,
-                          stats=None, accumulate: bool = False, stream=None):
+                          stats=None, accumulate: bool = False, stream=None, schedule: bool = True):
         """Fused forward + loss gradients + backward compositing (one launch;
-        ``stats`` as in forward); follow with backward_project."""
+        ``stats`` as in forward); follow with backward_project.  With
+        ``schedule`` every call records the per-tile costs and launches in the
+        order of the previous call's costs, heaviest tiles first (the first
+        call uses the default order; results do not depend on the order)."""
         if getattr(self, "tile_loss", None) is None:
             self.tile_loss = torch.zeros(2 * max(self.views.T, 1), dtype=torch.float32, device=self.device)
         h, ma, mw = _stats(stats)
         cfg = self._cfg(accumulate)
+        order = cost = None
+        T = self.views.T
+        if schedule and T > 0:
+            if getattr(self, "tile_cost", None) is None:
+                self.tile_cost = torch.zeros(T, dtype=torch.int32, device=self.device)
+                self.tile_order = torch.zeros(T, dtype=torch.int32, device=self.device)
+                n = ctypes.c_size_t(0)
+                call("sr_tile_order_workspace_size", T, ctypes.byref(n))
+                self.order_ws = torch.zeros(max(n.value, 1), dtype=torch.uint8, device=self.device)
+                self.costs_recorded = False
+            if self.costs_recorded:
+                call("sr_tile_order", T, _ptr(self.tile_cost), _ptr(self.order_ws), self.order_ws.numel(),
+                     _ptr(self.tile_order), _stream(stream))
+                order = self.tile_order
+            cost = self.tile_cost
         call("sr_train_step_raster", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask),
              _ptr(target), float(gamma), float(w_c), _ptr(self.color), _ptr(self.alpha), _ptr(self.depth),
              _ptr(self.normal), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma),
-             _ptr(mw), _ptr(self.tile_loss), _ptr(self.loss_out), _ptr(self._grad_rec()), _stream(stream))
+             _ptr(mw), _ptr(self.tile_loss), _ptr(self.loss_out), _ptr(self._grad_rec()), _ptr(order), _ptr(cost),
+             _stream(stream))
+        if cost is not None:
+            self.costs_recorded = True
         return self.loss_out
 
     def prune_stats(self, hits, max_alpha, max_weight, accumulate=False, stream=None, cull: bool = True):

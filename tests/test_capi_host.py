@@ -109,7 +109,7 @@ def test_argument_errors_before_launch(lib):
                                                    mw, None, None, None)
     step = lambda hits, ma, mw: l.sr_train_step_raster(ctypes.byref(cfg), 0, 0, None, None, None, None, None, None,
                                                        None, None, 0.5, 1.0, *([None] * 7), hits, ma, mw, None,
-                                                       None, None, None)
+                                                       None, None, None, None, None)
     for f in (fwd, step):
         assert f(None, None, None) == lib.SR_OK
         assert f(h, None, None) == lib.SR_OK
@@ -194,3 +194,18 @@ def test_compact_arguments(lib):
     w[0] = 3
     assert l.sr_compact_surfels(10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, 0, p, None) == \
         lib.SR_ERR_ARG
+
+
+def test_tile_order_arguments(lib):
+    """sr_tile_order / sr_tile_order_workspace_size host checks (nothing launched)."""
+    l = lib.lib()
+    n = ctypes.c_size_t()
+    assert l.sr_tile_order_workspace_size(0, ctypes.byref(n)) == lib.SR_OK and n.value == 0
+    assert l.sr_tile_order_workspace_size(-1, ctypes.byref(n)) == lib.SR_ERR_ARG
+    assert l.sr_tile_order_workspace_size(65788, ctypes.byref(n)) == lib.SR_OK and n.value >= 4 * 4 * 65788
+    p = ctypes.c_void_p(256)
+    assert l.sr_tile_order(0, None, None, 0, None, None) == lib.SR_OK
+    assert l.sr_tile_order(-3, p, p, n.value, p, None) == lib.SR_ERR_ARG
+    assert l.sr_tile_order(65788, p, p, n.value - 1, p, None) == lib.SR_ERR_ARG
+    assert l.sr_tile_order(65788, None, p, n.value, p, None) == lib.SR_ERR_ARG
+    assert l.sr_tile_order(65788, p, p, n.value, None, None) == lib.SR_ERR_ARG

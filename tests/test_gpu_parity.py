@@ -371,6 +371,62 @@ def test_usage_counts_alone():
     print(f"used {(h > 0).sum()} of {sc.n}; exempt {(~keep).sum()}")
 
 
+def test_cost_ordered_dispatch():
+    """The fused step records each tile's cost (the largest n_contrib of its
+    pixels); sr_tile_order sorts the tiles by descending cost, equal costs by
+    ascending id; launched in that order the step gives bit-identical forward
+    outputs, usage counts and losses, and the gradients up to the rounding
+    order of float atomics."""
+    sc = scenes.make_random_scene(44, 4000, n_views=3, width=[150, 97, 64], height=[80, 121, 64], sh_degree=3,
+                                  scale_range=(0.01, 0.4))
+    rng = np.random.default_rng(6)
+    views = ViewBatch(sc.cams)
+    mask = torch.tensor(rng.integers(0, 2, views.P).astype(np.uint8), device="cuda")
+    target = torch.tensor(rng.uniform(size=3 * views.P).astype(np.float32), device="cuda")
+    p = Params.from_scene(sc)
+    g = Params(*[torch.zeros_like(t) for t in (p.means, p.scales, p.quats, p.opac, p.sh)])
+    grads = (g.means, g.scales, g.quats, g.opac, g.sh)
+    hits = torch.zeros(sc.n, dtype=torch.int32, device="cuda")
+    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1])
+    rast.plan_capacity(p)
+    outs = ("color", "alpha", "depth", "normal", "dist", "T_final", "n_contrib")
+
+    def run(schedule):
+        for t in grads:
+            t.zero_()
+        rast.preprocess(p)
+        rast.bin()
+        loss = rast.train_step_raster(mask, target, 0.5, 1.0, stats=hits, schedule=schedule)
+        rast.backward_project(p, g)
+        torch.cuda.synchronize()
+        return ({k: getattr(rast, k).clone() for k in outs}, hits.clone(), loss.clone(), [t.clone() for t in grads])
+
+    ref = run(False)
+    run(True)                                   # first scheduled call: default order, costs recorded
+    T = views.T
+    cost = rast.tile_cost.cpu().numpy().astype(np.int64)
+    ncon = rast.n_contrib[: views.P].cpu().numpy().astype(np.int64)
+    want = np.zeros(T, np.int64)
+    for v in range(views.V):
+        c = views.host[v]
+        img = ncon[c.pix_offset: c.pix_offset + c.width * c.height].reshape(c.height, c.width)
+        for ty in range(c.tiles_y):
+            for tx in range(c.tiles_x):
+                want[c.tile_offset + ty * c.tiles_x + tx] = img[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16].max()
+    np.testing.assert_array_equal(cost, want)
+    assert len(np.unique(cost)) > 3
+    got = run(True)                             # ordered by the recorded costs
+    order = rast.tile_order.cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(order, np.lexsort((np.arange(T), -cost)))
+    for k in outs:
+        assert torch.equal(got[0][k], ref[0][k]), k
+    assert torch.equal(got[1], ref[1])
+    assert torch.equal(got[2], ref[2])
+    for x, y in zip(got[3], ref[3]):
+        assert float((x - y).abs().max().item()) <= 1e-5 * float(y.abs().max().item()) + 1e-12
+    print(f"{T} tiles, costs {cost.min()}..{cost.max()}, heaviest first: {order[:5].tolist()}")
+
+
 def test_prune_pass_culling_keeps_statistics():
     """sr_prune_contrib (no shading) with per-wave culling by the pixel
     rectangles, without it, and the statistics of the shaded forward: the
