@@ -179,15 +179,18 @@ sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_c
  * median_depth = z of the last blended entry whose transmittance before it
  * is above 1/2 (0 when no entry blends), median_contrib = that entry's
  * index + 1 in the tile list (0 when none); sr_backward_raster takes
- * median_contrib to route dL/d(median depth).  All other outputs except the
- * statistics are required. */
+ * median_contrib to route dL/d(median depth).  tile_order [T] / tile_cost
+ * [T], optional: as for sr_train_step_raster (launch order; each tile's
+ * largest n_contrib, which orders this step's sr_backward_raster through
+ * sr_tile_order).  All other outputs except the statistics are required. */
 sr_status sr_render_forward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                             const sr_camera *cams_dev, const float *geom, const float *app,
                             const uint32_t *vals, const uint32_t *ranges,
                             float *color, float *alpha, float *depth, float *normal, float *dist,
                             float *T_final, uint32_t *n_contrib,
                             uint32_t *hits, float *max_alpha, float *max_weight,
-                            float *median_depth, uint32_t *median_contrib, void *stream);
+                            float *median_depth, uint32_t *median_contrib,
+                            const uint32_t *tile_order, uint32_t *tile_cost, void *stream);
 
 /* Gradient of a loss through the compositing and the projection (Section
  * 3.1: position, shape and appearance are updated by backpropagation).
@@ -215,7 +218,9 @@ sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const s
 /* The two halves of sr_render_backward, one kernel each.
  * sr_backward_raster: the compositing backward only; ADDS the per-record
  * gradients to grad_rec [V*N, 24], which must hold zeros on entry (as left
- * by sr_backward_project or a fresh zeroed buffer).
+ * by sr_backward_project or a fresh zeroed buffer).  tile_order [T],
+ * optional: launch order as for sr_train_step_raster (sr_tile_order of the
+ * tile costs the same step's sr_render_forward recorded).
  * sr_backward_project: chains grad_rec to the parameter gradients (+=),
  * summed over the views, and zeroes every grad_rec record it consumed, so
  * the buffer is ready for the next step.  tiles_touched (from
@@ -235,7 +240,7 @@ sr_status sr_backward_raster(const sr_config *cfg, int32_t N, int32_t V, const s
                              const uint32_t *n_contrib, const float *dL_dcolor, const float *dL_dalpha,
                              const float *dL_ddepth, const float *dL_dnormal, const float *dL_ddist,
                              const uint32_t *median_contrib, const float *dL_dmedian,
-                             float *grad_rec, void *stream);
+                             float *grad_rec, const uint32_t *tile_order, void *stream);
 sr_status sr_backward_project(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                               const sr_camera *cams_dev, const float *means, const float *scales,
                               const float *quats, const float *sh, const float *geom, const float *app,

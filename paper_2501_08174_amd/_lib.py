@@ -74,9 +74,9 @@ def _declare(lib):
         "sr_preprocess": (c_int32, [V, c_int32, V, V, V, V, V, c_int32, V, V, V, V, V, V, V, V, V]),
         "sr_bin_workspace_size": (c_int32, [c_int32, c_int32, c_uint32, POINTER(c_size_t)]),
         "sr_bin_and_sort": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, c_size_t, c_uint32, V, V, V, V, V]),
-        "sr_render_forward": (c_int32, [V, c_int32, c_int32] + [V] * 19),
+        "sr_render_forward": (c_int32, [V, c_int32, c_int32] + [V] * 21),
         "sr_render_backward": (c_int32, [V, c_int32, c_int32, V, V] + [V] * 28),
-        "sr_backward_raster": (c_int32, [V, c_int32, c_int32] + [V] * 20),
+        "sr_backward_raster": (c_int32, [V, c_int32, c_int32] + [V] * 21),
         "sr_backward_project": (c_int32, [V, c_int32, c_int32] + [V] * 18),
         "sr_loss_workspace_size": (c_int32, [c_int32, V, POINTER(c_size_t)]),
         "sr_background_loss": (c_int32, [c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V]),

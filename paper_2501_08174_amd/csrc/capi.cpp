@@ -207,7 +207,8 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
                             const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
                             const uint32_t* ranges, float* color, float* alpha, float* depth, float* normal,
                             float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
-                            float* max_weight, float* median_depth, uint32_t* median_contrib, void* stream) {
+                            float* max_weight, float* median_depth, uint32_t* median_contrib,
+                            const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
     int total_tiles = 0;
@@ -224,7 +225,8 @@ sr_status sr_render_forward(const sr_config* cfg, int32_t N, int32_t V, const sr
     if (!(cfg->flags & SR_FLAG_ACCUMULATE)) SR_TRY(clear_stats(N, hits, max_alpha, max_weight, s));
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, nullptr, vals, ranges,
                                             color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                                            max_weight, nullptr, median_depth, median_contrib, s),
+                                            max_weight, nullptr, median_depth, median_contrib, tile_order,
+                                            tile_cost, s),
                       "sr_render_forward");
 }
 
@@ -268,7 +270,7 @@ sr_status sr_backward_raster(const sr_config* cfg, int32_t N, int32_t V, const s
                              const float* T_final, const uint32_t* n_contrib, const float* dL_dcolor,
                              const float* dL_dalpha, const float* dL_ddepth, const float* dL_dnormal,
                              const float* dL_ddist, const uint32_t* median_contrib, const float* dL_dmedian,
-                             float* grad_rec, void* stream) {
+                             float* grad_rec, const uint32_t* tile_order, void* stream) {
     int total_tiles = 0;
     SR_TRY(check_backward_raster(cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, alpha, depth, dist, T_final,
                                  n_contrib, grad_rec, &total_tiles));
@@ -276,7 +278,8 @@ sr_status sr_backward_raster(const sr_config* cfg, int32_t N, int32_t V, const s
     if (N == 0 || V == 0) return SR_OK;
     return hip_status(sr::launch_render_bwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, alpha, depth,
                                             dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
-                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, (hipStream_t)stream),
+                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, tile_order,
+                                            (hipStream_t)stream),
                       "sr_backward_raster");
 }
 
@@ -317,7 +320,7 @@ sr_status sr_render_backward(const sr_config* cfg, int32_t N, int32_t V, const s
     SR_TRY(hip_status(sr::fill_f32(grad_rec, 0.f, (uint64_t)V * N * SR_GRAD_STRIDE, s), "clear grad_rec"));
     SR_TRY(hip_status(sr::launch_render_bwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, alpha, depth,
                                             dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
-                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, s),
+                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, nullptr, s),
                       "render backward"));
     return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app, nullptr,
                                                 grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, nullptr,
@@ -529,7 +532,7 @@ sr_status sr_prune_contrib(const sr_config* cfg, int32_t N, int32_t V, const sr_
     }
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, nullptr, rect, vals, ranges,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, hits,
-                                            max_alpha, max_weight, nullptr, nullptr, nullptr, s),
+                                            max_alpha, max_weight, nullptr, nullptr, nullptr, nullptr, nullptr, s),
                       "sr_prune_contrib");
 }
 
@@ -574,7 +577,8 @@ sr_status sr_render_count(const sr_config* cfg, int32_t N, int32_t V, const sr_c
     return hip_status(sr::launch_render_fwd(*cfg, N, V, total_tiles, cams_dev, geom, app, nullptr, vals, ranges,
                                             nullptr,
                                             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                            nullptr, (unsigned long long*)counts, nullptr, nullptr, s),
+                                            nullptr, (unsigned long long*)counts, nullptr, nullptr, nullptr, nullptr,
+                                            s),
                       "sr_render_count");
 }
 

@@ -42,14 +42,14 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              float* dist, float* T_final,
                              uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
                              unsigned long long* counts, float* median_depth, uint32_t* median_contrib,
-                             hipStream_t s);
+                             const uint32_t* tile_order, uint32_t* tile_cost, hipStream_t s);
 
 hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
                              const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
-                             float* grad_rec, hipStream_t s);
+                             float* grad_rec, const uint32_t* tile_order, hipStream_t s);
 
 hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                                const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,

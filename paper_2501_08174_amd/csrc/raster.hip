@@ -487,11 +487,15 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
              float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
              uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
              float* __restrict__ max_weight, unsigned long long* __restrict__ counts,
-             float* __restrict__ median_depth, uint32_t* __restrict__ median_contrib) {
+             float* __restrict__ median_depth, uint32_t* __restrict__ median_contrib,
+             const uint32_t* __restrict__ tile_order, uint32_t* __restrict__ tile_cost) {
     constexpr int NT = TW * TH;
     __shared__ FwdSmem<NT, MODE> sm;
+    __shared__ uint32_t s_cost;
+    // an order entry beyond the grid leaves the workgroup idle
+    if (tile_order && tile_order[blockIdx.x] >= gridDim.x) return;
     TileCtx t;
-    tile_ctx<TW, TH>(cams, V, ranges, t);
+    tile_ctx<TW, TH>(cams, V, ranges, t, tile_order);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
     uint64_t n_reached = 0, n_blended = 0, n_witer = 0, n_wblend = 0, n_upto = 0;
@@ -517,6 +521,14 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         const int64_t o1 = t.pix_off + (int64_t)t.iy * t.W + t.ix;
         median_depth[o1] = st.zmed;
         median_contrib[o1] = st.kmed;
+    }
+    if (tile_cost) {
+        // the tile's cost for a later launch's order: its largest n_contrib
+        if (threadIdx.x == 0) s_cost = 0u;
+        __syncthreads();
+        if (t.inside) atomicMax(&s_cost, st.last);
+        __syncthreads();
+        if (threadIdx.x == 0) tile_cost[t.tile] = s_cost;
     }
 }
 
@@ -726,10 +738,12 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
              const float* __restrict__ dC, const float* __restrict__ dA, const float* __restrict__ dD,
              const float* __restrict__ dNrm, const float* __restrict__ dDist,
              const uint32_t* __restrict__ median_contrib, const float* __restrict__ dMed,
-             float* __restrict__ grad_rec) {
+             float* __restrict__ grad_rec, const uint32_t* __restrict__ tile_order) {
     __shared__ BwdSmem<BATCH> sm;
+    // an order entry beyond the grid leaves the workgroup idle
+    if (tile_order && tile_order[blockIdx.x] >= gridDim.x) return;
     TileCtx t;
-    tile_ctx<TW, TH>(cams, V, ranges, t);
+    tile_ctx<TW, TH>(cams, V, ranges, t, tile_order);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixBwd pb;
     pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = pb.gMed = 0.f;
@@ -847,10 +861,10 @@ void fwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, in
                 float* color,
                 float* alpha, float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib,
                 uint32_t* hits, float* max_alpha, float* max_weight, unsigned long long* counts,
-                float* median_depth, uint32_t* median_contrib) {
+                float* median_depth, uint32_t* median_contrib, const uint32_t* tile_order, uint32_t* tile_cost) {
     hipLaunchKernelGGL((k_render_fwd<TW, TH, MODE>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, app,
                        rect, vals, ranges, rc, color, alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha,
-                       max_weight, counts, median_depth, median_contrib);
+                       max_weight, counts, median_depth, median_contrib, tile_order, tile_cost);
 }
 
 template <int TW, int TH>
@@ -858,11 +872,12 @@ bool fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cam
                   const float4* geom, const float4* app, const uint2* rect, const uint32_t* vals, const uint2* ranges,
                   RasterConsts rc, float* color, float* alpha, float* depth, float* normal, float* dist,
                   float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                  unsigned long long* counts, float* median_depth, uint32_t* median_contrib) {
+                  unsigned long long* counts, float* median_depth, uint32_t* median_contrib,
+                  const uint32_t* tile_order, uint32_t* tile_cost) {
 #define SR_FWD(M)                                                                                        \
     fwd_launch<TW, TH, M>(total_tiles, s, cams, V, N, geom, app, rect, vals, ranges, rc, color, alpha, depth, \
                           normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, counts,          \
-                          median_depth, median_contrib)
+                          median_depth, median_contrib, tile_order, tile_cost)
     switch (mode) {
         case kShade: SR_FWD(kShade); return true;
         case kShade | kHits: SR_FWD(kShade | kHits); return true;
@@ -883,16 +898,16 @@ void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, in
                 const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, const float* alpha,
                 const float* depth, const float* dist, const float* T_final, const uint32_t* n_contrib,
                 const float* dC, const float* dA, const float* dD, const float* dN, const float* dS,
-                const uint32_t* median_contrib, const float* dMed, float* grad_rec) {
+                const uint32_t* median_contrib, const float* dMed, float* grad_rec, const uint32_t* tile_order) {
     constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
     if (dD || dN || dS || dMed)
         hipLaunchKernelGGL((k_render_bwd<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom,
                            app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
-                           median_contrib, dMed, grad_rec);
+                           median_contrib, dMed, grad_rec, tile_order);
     else
         hipLaunchKernelGGL((k_render_bwd<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
                            geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
-                           median_contrib, dMed, grad_rec);
+                           median_contrib, dMed, grad_rec, tile_order);
 }
 
 template <int TW, int TH>
@@ -940,7 +955,8 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              const uint32_t* ranges, float* color, float* alpha, float* depth, float* normal,
                              float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
                              float* max_weight, unsigned long long* counts, float* median_depth,
-                             uint32_t* median_contrib, hipStream_t s) {
+                             uint32_t* median_contrib, const uint32_t* tile_order, uint32_t* tile_cost,
+                             hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
     const int stats = hits ? (max_alpha ? kStats : kHits) : 0;
@@ -952,7 +968,7 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
         if (!fwd_dispatch<W, H>(mode, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app,     \
                                 (const uint2*)rect, vals, (const uint2*)ranges, rc, color, alpha, depth, normal, \
                                 dist, T_final, n_contrib, hits, max_alpha, max_weight, counts, median_depth,     \
-                                median_contrib))                                                                \
+                                median_contrib, tile_order, tile_cost))                                         \
             return hipErrorInvalidValue;                                                                        \
         return hipGetLastError();                                                                               \
     }
@@ -966,14 +982,14 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
                              const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
-                             float* grad_rec, hipStream_t s) {
+                             float* grad_rec, const uint32_t* tile_order, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
 #define SR_TS(W, H)                                                                                            \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                 \
         bwd_launch<W, H>(total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,          \
                          (const uint2*)ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, \
-                         median_contrib, dMed, grad_rec);                                                     \
+                         median_contrib, dMed, grad_rec, tile_order);                                         \
         return hipGetLastError();                                                                             \
     }
     SR_TILE_SHAPES(SR_TS)

@@ -193,12 +193,37 @@ class Rasterizer:
         cfg.flags |= _lib.SR_FLAG_ACCUMULATE
         return cfg
 
-    def forward(self, stats=None, accumulate: bool = False, stream=None, median: bool = False):
+    def _schedule(self, stream=None):
+        """(order, cost) of a scheduled launch: the tile order sorted from the
+        last recorded tile costs, heaviest first (None before any), and the
+        buffer the launch records this step's costs into."""
+        T = self.views.T
+        if T == 0:
+            return None, None
+        if getattr(self, "tile_cost", None) is None:
+            self.tile_cost = torch.zeros(T, dtype=torch.int32, device=self.device)
+            self.tile_order = torch.zeros(T, dtype=torch.int32, device=self.device)
+            n = ctypes.c_size_t(0)
+            call("sr_tile_order_workspace_size", T, ctypes.byref(n))
+            self.order_ws = torch.zeros(max(n.value, 1), dtype=torch.uint8, device=self.device)
+            self.costs_recorded = False
+        order = None
+        if self.costs_recorded:
+            call("sr_tile_order", T, _ptr(self.tile_cost), _ptr(self.order_ws), self.order_ws.numel(),
+                 _ptr(self.tile_order), _stream(stream))
+            order = self.tile_order
+        return order, self.tile_cost
+
+    def forward(self, stats=None, accumulate: bool = False, stream=None, median: bool = False,
+                schedule: bool = True):
         """Forward compositing; ``median`` also renders the median depth
         (self.median_depth) and its entry index (self.median_contrib);
         ``stats`` (hits alone, or hits with both maxima) accumulates the
-        occlusion statistics in the same pass."""
+        occlusion statistics in the same pass.  ``schedule`` as in
+        train_step_raster: tiles launched heaviest first by the last recorded
+        costs; backward_raster reuses the order."""
         h, ma, mw = _stats(stats)
+        order, cost = self._schedule(stream) if schedule else (None, None)
         cfg = self._cfg(accumulate)
         md = mc = None
         if median:
@@ -211,7 +236,10 @@ class Rasterizer:
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.color), _ptr(self.alpha), _ptr(self.depth), _ptr(self.normal), _ptr(self.dist),
              _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw), _ptr(md), _ptr(mc),
-             _stream(stream))
+             _ptr(order), _ptr(cost), _stream(stream))
+        self.last_order = order
+        if cost is not None:
+            self.costs_recorded = True
 
     def _grad_rec(self):
         if self.grad_rec is None:
@@ -227,14 +255,17 @@ class Rasterizer:
             raise ValueError("a median-depth gradient needs a forward with median=True")
         return self.median_contrib
 
-    def backward_raster(self, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None, dM=None):
+    def backward_raster(self, dC=None, dA=None, dD=None, dN=None, dS=None, stream=None, dM=None,
+                        schedule: bool = True):
         """Compositing backward; ``dM`` is the gradient of the median depth
-        (after a forward with median=True)."""
+        (after a forward with median=True); ``schedule``: launched in the
+        order of the last forward (heaviest tiles first)."""
+        order = getattr(self, "last_order", None) if schedule else None
         call("sr_backward_raster", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.alpha), _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib),
              _ptr(dC), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._median_contrib(dM)), _ptr(dM),
-             _ptr(self._grad_rec()), _stream(stream))
+             _ptr(self._grad_rec()), _ptr(order), _stream(stream))
 
     def backward_project(self, p: Params, grads: Params, stream=None, densify=None):
         """Projection backward; ``densify`` = (grad_sum float32 [N], count
@@ -315,21 +346,7 @@ class Rasterizer:
             self.tile_loss = torch.zeros(2 * max(self.views.T, 1), dtype=torch.float32, device=self.device)
         h, ma, mw = _stats(stats)
         cfg = self._cfg(accumulate)
-        order = cost = None
-        T = self.views.T
-        if schedule and T > 0:
-            if getattr(self, "tile_cost", None) is None:
-                self.tile_cost = torch.zeros(T, dtype=torch.int32, device=self.device)
-                self.tile_order = torch.zeros(T, dtype=torch.int32, device=self.device)
-                n = ctypes.c_size_t(0)
-                call("sr_tile_order_workspace_size", T, ctypes.byref(n))
-                self.order_ws = torch.zeros(max(n.value, 1), dtype=torch.uint8, device=self.device)
-                self.costs_recorded = False
-            if self.costs_recorded:
-                call("sr_tile_order", T, _ptr(self.tile_cost), _ptr(self.order_ws), self.order_ws.numel(),
-                     _ptr(self.tile_order), _stream(stream))
-                order = self.tile_order
-            cost = self.tile_cost
+        order, cost = self._schedule(stream) if schedule else (None, None)
         call("sr_train_step_raster", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask),
              _ptr(target), float(gamma), float(w_c), _ptr(self.color), _ptr(self.alpha), _ptr(self.depth),

@@ -97,16 +97,18 @@ def test_argument_errors_before_launch(lib):
     assert lib.SR_TILE_GROUP == 4 and lib.SR_INST_ID_BITS == 24
     # the median depth and its entry index go together, and its gradient needs the index
     md = ctypes.c_void_p(256)
-    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, None, None) == lib.SR_ERR_ARG
-    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, md, None) == lib.SR_OK
-    assert l.sr_backward_raster(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), None, md, None,
+    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, None, None, None,
+                               None) == lib.SR_ERR_ARG
+    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, md, None, None,
+                               None) == lib.SR_OK
+    assert l.sr_backward_raster(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), None, md, None, None,
                                 None) == lib.SR_ERR_ARG
     assert l.sr_render_backward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 19), None, md, None,
                                 *([None] * 6)) == lib.SR_ERR_ARG
     # statistics: none, hits alone, or hits with both maxima
     h = ctypes.c_void_p(512)
     fwd = lambda hits, ma, mw: l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 11), hits, ma,
-                                                   mw, None, None, None)
+                                                   mw, None, None, None, None, None)
     step = lambda hits, ma, mw: l.sr_train_step_raster(ctypes.byref(cfg), 0, 0, None, None, None, None, None, None,
                                                        None, None, 0.5, 1.0, *([None] * 7), hits, ma, mw, None,
                                                        None, None, None, None, None)

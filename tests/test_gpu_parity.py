@@ -426,6 +426,35 @@ def test_cost_ordered_dispatch():
         assert float((x - y).abs().max().item()) <= 1e-5 * float(y.abs().max().item()) + 1e-12
     print(f"{T} tiles, costs {cost.min()}..{cost.max()}, heaviest first: {order[:5].tolist()}")
 
+    # the separate launches: the forward records the same costs, forward and
+    # backward launch in the order of the last recorded costs
+    def run_sep(schedule):
+        for t in grads:
+            t.zero_()
+        rast.preprocess(p)
+        rast.bin()
+        rast.forward(stats=hits, schedule=schedule)
+        dA = torch.zeros_like(rast.alpha)
+        dC = torch.zeros_like(rast.color)
+        loss = rast.loss(mask, target, 0.5, 1.0, dA, dC)
+        rast.backward_raster(dC=dC, dA=dA, schedule=schedule)
+        rast.backward_project(p, g)
+        torch.cuda.synchronize()
+        return ({k: getattr(rast, k).clone() for k in outs}, hits.clone(), loss.clone(), [t.clone() for t in grads])
+
+    ref_sep = run_sep(False)
+    rast.tile_cost.zero_()
+    got_sep = run_sep(True)
+    assert rast.last_order is not None
+    np.testing.assert_array_equal(rast.tile_cost.cpu().numpy().astype(np.int64), want)
+    for k in outs:
+        assert torch.equal(got_sep[0][k], ref_sep[0][k]), k
+        assert torch.equal(got_sep[0][k], ref[0][k]), k      # separate and fused forwards agree
+    assert torch.equal(got_sep[1], ref_sep[1])
+    assert torch.equal(got_sep[2], ref_sep[2])
+    for x, y in zip(got_sep[3], ref_sep[3]):
+        assert float((x - y).abs().max().item()) <= 1e-5 * float(y.abs().max().item()) + 1e-12
+
 
 def test_prune_pass_culling_keeps_statistics():
     """sr_prune_contrib (no shading) with per-wave culling by the pixel
