@@ -456,6 +456,30 @@ def test_cost_ordered_dispatch():
         assert float((x - y).abs().max().item()) <= 1e-5 * float(y.abs().max().item()) + 1e-12
 
 
+def test_tile_order_sort_edge_cases():
+    """sr_tile_order alone: a ragged tile count (not a multiple of any block
+    size), many equal costs, costs above the 24-bit clamp; the order equals
+    numpy's stable sort by descending clamped cost."""
+    import ctypes
+    from paper_2501_08174_amd import _lib
+    rng = np.random.default_rng(12)
+    for T in (1, 7, 100003):
+        cost = rng.integers(0, 40, size=T).astype(np.int64)           # many ties
+        big = rng.random(T) < 0.01
+        cost[big] = rng.integers(1 << 23, 1 << 31, size=int(big.sum()))   # some above the clamp
+        n = ctypes.c_size_t(0)
+        _lib.call("sr_tile_order_workspace_size", T, ctypes.byref(n))
+        ws = torch.zeros(max(n.value, 1), dtype=torch.uint8, device="cuda")
+        c = torch.tensor(cost.astype(np.uint32).view(np.int32), device="cuda")
+        out = torch.full((T,), -1, dtype=torch.int32, device="cuda")
+        _lib.call("sr_tile_order", T, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        clamped = np.minimum(cost, (1 << 24) - 1)
+        np.testing.assert_array_equal(out.cpu().numpy().astype(np.int64), np.lexsort((np.arange(T), -clamped)))
+    _lib.call("sr_tile_order", 0, None, None, 0, None, None)      # empty: a no-op
+
+
 def test_prune_pass_culling_keeps_statistics():
     """sr_prune_contrib (no shading) with per-wave culling by the pixel
     rectangles, without it, and the statistics of the shaded forward: the
