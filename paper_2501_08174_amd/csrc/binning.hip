@@ -161,14 +161,32 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ cou
     uint32_t b, e;
     radix_chunk(*count, G, &b, &e);
     const uint32_t mask = (uint32_t)R - 1u;
-    // eight independent loads in flight per thread
+    const int lane = __lane_id();
+    // eight independent loads in flight per thread; a digit held by many
+    // lanes of the wave (skewed digits: the top byte of positive depths, the
+    // high bits of group ids) is added once for all of them instead of by
+    // every lane into the same LDS word
     uint32_t i = b + threadIdx.x;
     for (; i + 7u * kNT < e; i += 8u * kNT) {
         uint32_t k[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) k[u] = keys[i + (uint32_t)u * kNT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) atomicAdd(&s_h[w][(k[u] >> shift) & mask], 1u);
+        for (int u = 0; u < 8; ++u) {
+            // d0: the digit of the wave's first active lane (the loop bound
+            // depends on the thread, so lane 0 may have left at a chunk's end)
+            const uint32_t d = (k[u] >> shift) & mask;
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+            const int leader = __builtin_amdgcn_readfirstlane(lane);
+            const uint64_t same = __ballot(d == d0);
+            const int n0 = __popcll(same);
+            if (n0 >= 16) {
+                if (lane == leader) atomicAdd(&s_h[w][d0], (uint32_t)n0);
+                if (d != d0) atomicAdd(&s_h[w][d], 1u);
+            } else {
+                atomicAdd(&s_h[w][d], 1u);
+            }
+        }
     }
     for (; i < e; i += kNT) atomicAdd(&s_h[w][(keys[i] >> shift) & mask], 1u);
     __syncthreads();
