@@ -349,8 +349,11 @@ sr_status sr_train_step_raster(const sr_config *cfg, int32_t N, int32_t V, const
                                uint32_t *tile_cost, void *stream);
 
 /* Dispatch order for sr_train_step_raster: the T tile ids sorted by
- * descending tile_cost [T] (costs above 2^24 - 1 count as 2^24 - 1; equal
- * costs keep ascending tile id), written to tile_order [T].  The per-tile
+ * descending cost class of tile_cost [T], written to tile_order [T]; equal
+ * classes keep ascending tile id.  The class of a cost c is c below 16 and
+ * (e - 3) * 16 + ((c >> (e - 4)) & 15) above, e = floor(log2 c): a
+ * logarithmic scale with 16 classes per octave (the order only needs to be
+ * approximately longest first; one radix pass).  The per-tile
  * work of a training step varies by two orders of magnitude (tiles near a
  * camera, under large splats); launched heaviest first, no heavy tile is left
  * for the end of the grid.  The costs of one step order the next (the views

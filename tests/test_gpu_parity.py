@@ -417,7 +417,7 @@ def test_cost_ordered_dispatch():
     assert len(np.unique(cost)) > 3
     got = run(True)                             # ordered by the recorded costs
     order = rast.tile_order.cpu().numpy().astype(np.int64)
-    np.testing.assert_array_equal(order, np.lexsort((np.arange(T), -cost)))
+    np.testing.assert_array_equal(order, np.lexsort((np.arange(T), -_cost_class(cost))))
     for k in outs:
         assert torch.equal(got[0][k], ref[0][k]), k
     assert torch.equal(got[1], ref[1])
@@ -456,17 +456,28 @@ def test_cost_ordered_dispatch():
         assert float((x - y).abs().max().item()) <= 1e-5 * float(y.abs().max().item()) + 1e-12
 
 
+def _cost_class(c):
+    """The logarithmic cost class of sr_tile_order, written out: c below 16,
+    above that 16 classes per octave."""
+    c = np.asarray(c, dtype=np.int64)
+    e = np.floor(np.log2(np.maximum(c, 1))).astype(np.int64)
+    # the float log2 of a 32-bit integer is exact enough to give its msb, but
+    # check it against the integer definition
+    assert np.all((c < 16) | ((1 << e) <= c) & (c < (1 << (e + 1))))
+    return np.where(c < 16, c, (e - 3) * 16 + ((c >> np.maximum(e - 4, 0)) & 15))
+
+
 def test_tile_order_sort_edge_cases():
     """sr_tile_order alone: a ragged tile count (not a multiple of any block
-    size), many equal costs, costs above the 24-bit clamp; the order equals
-    numpy's stable sort by descending clamped cost."""
+    size), many equal costs, large costs; the order equals numpy's stable
+    sort by descending cost class."""
     import ctypes
     from paper_2501_08174_amd import _lib
     rng = np.random.default_rng(12)
     for T in (1, 7, 100003):
         cost = rng.integers(0, 40, size=T).astype(np.int64)           # many ties
         big = rng.random(T) < 0.01
-        cost[big] = rng.integers(1 << 23, 1 << 31, size=int(big.sum()))   # some above the clamp
+        cost[big] = rng.integers(1 << 4, 1 << 32, size=int(big.sum()))   # up to the full 32 bits
         n = ctypes.c_size_t(0)
         _lib.call("sr_tile_order_workspace_size", T, ctypes.byref(n))
         ws = torch.zeros(max(n.value, 1), dtype=torch.uint8, device="cuda")
@@ -475,8 +486,8 @@ def test_tile_order_sort_edge_cases():
         _lib.call("sr_tile_order", T, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         torch.cuda.synchronize()
-        clamped = np.minimum(cost, (1 << 24) - 1)
-        np.testing.assert_array_equal(out.cpu().numpy().astype(np.int64), np.lexsort((np.arange(T), -clamped)))
+        np.testing.assert_array_equal(out.cpu().numpy().astype(np.int64),
+                                      np.lexsort((np.arange(T), -_cost_class(cost))))
     _lib.call("sr_tile_order", 0, None, None, 0, None, None)      # empty: a no-op
 
 
