@@ -23,8 +23,7 @@ Modules
             projection, conservative rectangles, compositing decisions
   fd        central finite differences with decision-set filtering
 """
-from .geometry import (RasterParams, view_geometry64, bin64, tile_layout, group_layout, tile_list,
-                       rotation_columns64)
+from .geometry import RasterParams, view_geometry64, bin64, tile_layout, rotation_columns64
 from .sh import real_sh_basis, sh_basis_scipy, sh_coeff_count
 from .render import render_pixels, render_view, Params64
 from .loss import background_loss64, masked_l1_64
@@ -35,7 +34,7 @@ from .regularizers import regularizer_loss64, depth_normal64, depth_points64, su
 from .ssim import dssim_loss64, masked_ssim64, masked_psnr64, ssim_map64, gaussian_1d64, window_2d64
 
 __all__ = [
-    "RasterParams", "view_geometry64", "bin64", "tile_layout", "group_layout", "tile_list", "rotation_columns64",
+    "RasterParams", "view_geometry64", "bin64", "tile_layout", "rotation_columns64",
     "real_sh_basis", "sh_basis_scipy", "sh_coeff_count",
     "render_pixels", "render_view", "Params64",
     "background_loss64", "masked_l1_64", "prune_stats64", "screen_grad_stats64",

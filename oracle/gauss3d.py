@@ -1,9 +1,10 @@
 """Occlusion-aware pruning statistics for 3D Gaussians (oracle; test
 infrastructure only).
 
-Appendix B applies the pruning of Section 4.3 to 3DGS: the same tracking of
-which Gaussians take part in the alpha blending of any rendered pixel, with
-3D Gaussians splatted as 2D Gaussians (EWA splatting).  The projection and
+Appendix B applies the pruning of Section 4.3 to 3DGS: the renderer again
+records, over all views, whether each Gaussian contributed to the colour of
+at least one pixel, now with 3D Gaussians splatted as 2D Gaussians (EWA
+splatting).  The projection and
 compositing details are those of 3DGS; the readings (listed with reasons in
 the design notes) are
 

@@ -235,37 +235,23 @@ def instances64(geom, view_tile_offset: int, tiles_x: int):
     return keys, gid.astype(np.uint32)
 
 
-def bin64(geoms, cams, rp: RasterParams = RasterParams(), group: int = 1):
-    """Sorted instance list and per-tile ranges over all views.
-
-    group = 1: one instance per (tile, surfel); keys (uint64) = tile id << 32
-    | depth bits ascending, ties by surfel id ascending (np.lexsort); vals =
-    surfel ids; ranges (T,2) uint32 with [start, end) of every global tile,
-    [0,0) when empty.
-
-    group = G > 1: tiles are binned in G x G groups (group_layout): one
-    instance per (group, surfel) whose tile rectangle meets the group; keys =
-    group id << 32 | depth bits; vals = surfel id | (x_lo | x_hi << 2 | y_lo
-    << 4 | y_hi << 6) << 24 with the surfel's tile rectangle clipped to the
-    group, in tile coordinates within the group (G = 4); ranges[t] = [start,
-    end) of the list of the group of tile t.  Tile t's own list is the
-    entries of that range whose sub-rectangle contains t (tile_list).
-    """
+def bin64(geoms, cams, rp: RasterParams = RasterParams()):
+    """Sorted instance list and per-tile ranges over all views: one instance
+    per (tile, surfel) of the surfel's tile rectangle; keys (uint64) = global
+    tile id << 32 | depth bits ascending, ties by surfel id ascending
+    (np.lexsort); vals = surfel ids; ranges (T,2) uint32 with [start, end)
+    of every global tile, [0,0) when empty."""
     lay, total_tiles = tile_layout(cams, rp)
-    ks, vs, glay = [], [], group_layout(cams, rp, group)
-    for g, (tx, ty, off), (gx, gy, goff) in zip(geoms, lay, glay):
-        if group == 1:
-            k, v = instances64(g, off, tx)
-        else:
-            k, v = group_instances64(g, goff, gx, group)
+    ks, vs = [], []
+    for g, (tx, ty, off) in zip(geoms, lay):
+        k, v = instances64(g, off, tx)
         ks.append(k)
         vs.append(v)
     keys = np.concatenate(ks) if ks else np.zeros(0, np.uint64)
     vals = np.concatenate(vs) if vs else np.zeros(0, np.uint32)
-    order = np.lexsort((vals & np.uint32(0xFFFFFF) if group > 1 else vals, keys))
+    order = np.lexsort((vals, keys))
     keys, vals = keys[order], vals[order]
-    ngroups = sum(gx * gy for gx, gy, _ in glay)
-    granges = np.zeros((ngroups, 2), np.uint32)
+    ranges = np.zeros((total_tiles, 2), np.uint32)
     if keys.size:
         tile = (keys >> np.uint64(32)).astype(np.int64)
         first = np.ones(keys.size, bool)
@@ -273,62 +259,6 @@ def bin64(geoms, cams, rp: RasterParams = RasterParams(), group: int = 1):
         last = np.ones(keys.size, bool)
         last[:-1] = tile[1:] != tile[:-1]
         idx = np.arange(keys.size, dtype=np.int64)
-        granges[tile[first], 0] = idx[first]
-        granges[tile[last], 1] = idx[last] + 1
-    if group == 1:
-        return keys, vals, granges
-    ranges = np.zeros((total_tiles, 2), np.uint32)
-    for (tx, ty, off), (gx, gy, goff) in zip(lay, glay):
-        t = np.arange(tx * ty)
-        gid = goff + (t // tx // group) * gx + (t % tx) // group
-        ranges[off + t] = granges[gid]
+        ranges[tile[first], 0] = idx[first]
+        ranges[tile[last], 1] = idx[last] + 1
     return keys, vals, ranges
-
-
-def group_layout(cams, rp: RasterParams = RasterParams(), group: int = 1):
-    """Per view (groups_x, groups_y, group_offset) of G x G tile groups,
-    global across the views, view-major then row-major."""
-    out, off = [], 0
-    for tx, ty, _ in tile_layout(cams, rp)[0]:
-        gx, gy = (tx + group - 1) // group, (ty + group - 1) // group
-        out.append((gx, gy, off))
-        off += gx * gy
-    return out
-
-
-def group_instances64(geom, view_group_offset: int, groups_x: int, group: int):
-    """Unsorted (key, packed value) instances of one view at G x G tile
-    groups (see bin64)."""
-    assert group == 4, "the sub-rectangle packing holds 2-bit tile coordinates"
-    ok = np.nonzero(~geom["culled"])[0]
-    t = geom["tiles"][ok]
-    g0x, g1x, g0y, g1y = t[:, 0] // group, t[:, 1] // group, t[:, 2] // group, t[:, 3] // group
-    counts = (g1x - g0x + 1) * (g1y - g0y + 1)
-    total = int(counts.sum())
-    rep = lambda a: np.repeat(a, counts)
-    gid = rep(ok)
-    start = rep(np.cumsum(counts) - counts)
-    local = np.arange(total) - start
-    w = rep(g1x - g0x + 1)
-    gxx = rep(g0x) + local % w
-    gyy = rep(g0y) + local // w
-    xlo = np.maximum(rep(t[:, 0]), group * gxx) - group * gxx
-    xhi = np.minimum(rep(t[:, 1]), group * gxx + group - 1) - group * gxx
-    ylo = np.maximum(rep(t[:, 2]), group * gyy) - group * gyy
-    yhi = np.minimum(rep(t[:, 3]), group * gyy + group - 1) - group * gyy
-    sub = (xlo | (xhi << 2) | (ylo << 4) | (yhi << 6)).astype(np.uint32)
-    keys = ((view_group_offset + gyy * groups_x + gxx).astype(np.uint64) << np.uint64(32)) | \
-        geom["depth_bits"][gid].astype(np.uint64)
-    return keys, gid.astype(np.uint32) | (sub << np.uint32(24))
-
-
-def tile_list(vals, ranges, t: int, tile_xy, group: int = 4):
-    """Surfel ids of tile t (tile coordinates tile_xy within its view) from
-    grouped lists: the entries of its group's range whose sub-rectangle
-    contains the tile, in list order, with their list positions."""
-    s, e = (int(x) for x in ranges[t])
-    v = np.asarray(vals[s:e], np.uint32)
-    sub = v >> np.uint32(24)
-    x, y = tile_xy[0] % group, tile_xy[1] % group
-    inside = ((sub & 3) <= x) & (x <= ((sub >> 2) & 3)) & (((sub >> 4) & 3) <= y) & (y <= ((sub >> 6) & 3))
-    return (v & np.uint32(0xFFFFFF))[inside], np.arange(s, e)[inside]

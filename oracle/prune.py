@@ -1,10 +1,10 @@
 """Occlusion-aware pruning statistics (oracle; test infrastructure only).
 
-Section 4.3: a Gaussian is "visible" when it is involved in the alpha
-blending of any rendered pixel, i.e. it passed the alpha cutoff before the
-pixel's transmittance terminated; Gaussians that are never blended in any
-view are pruned, even when they lie inside the viewing frustum (the 3DGS
-visibility filter, which only records "inside the frustum", keeps them).
+Section 4.3: a Gaussian counts as visible when some pixel of some view
+blends it, i.e. it passed the alpha cutoff before that pixel's transmittance
+terminated; Gaussians that no pixel of any view blends are pruned, even when
+they lie inside the viewing frustum (the 3DGS visibility filter, which only
+records "inside the frustum", keeps them).
 
 For every blended (pixel, surfel) pair over all views:
   hits[g] += 1, max_alpha[g] = max(max_alpha[g], a), max_weight[g] =

@@ -478,7 +478,8 @@ def rasterize(means, scales, quats, opac, sh, rast: Rasterizer, check: bool = Tr
 
 class BackgroundLoss(torch.autograd.Function):
     """Masked losses (Eq. 1 and the L1 part of Eq. 2) of all views:
-    returns (1/V) sum_v (w_c L1_v + gamma L_b,v) and the per-view terms."""
+    returns (1/V) sum_v (w_c L1_v + gamma L_b,v) and the per-view terms
+    (non-differentiable: a loss built from them raises in backward)."""
 
     @staticmethod
     def forward(ctx, alpha, color, target, mask, views: ViewBatch, gamma: float, w_c: float, ws):
@@ -491,7 +492,10 @@ class BackgroundLoss(torch.autograd.Function):
              _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dC), _stream())
         ctx.save_for_backward(dA, dC if dC is not None else torch.zeros(0, device=alpha.device))
         ctx.has_c = dC is not None
-        return loss[2 * V], loss[: 2 * V]
+        per_view = loss[: 2 * V]
+        # the per-view terms are reported, not differentiated: only the total carries a gradient
+        ctx.mark_non_differentiable(per_view)
+        return loss[2 * V], per_view
 
     @staticmethod
     def backward(ctx, g_total, g_loss):
@@ -520,7 +524,9 @@ class RegularizerLoss(torch.autograd.Function):
              _ptr(dS), _ptr(dM), _stream())
         ctx.save_for_backward(dA, dD, dN, dS, dM if dM is not None else torch.zeros(0, device=alpha.device))
         ctx.has_m = dM is not None
-        return loss[2 * V], loss[: 2 * V]
+        per_view = loss[: 2 * V]
+        ctx.mark_non_differentiable(per_view)
+        return loss[2 * V], per_view
 
     @staticmethod
     def backward(ctx, g_total, g_loss):
@@ -541,7 +547,9 @@ class SsimLoss(torch.autograd.Function):
         call("sr_ssim_loss", V, views.host_ptr, _ptr(views.dev), _ptr(color.contiguous()), _ptr(target),
              _ptr(mask), float(w_s), _ptr(ws), ws.numel(), _ptr(out), _ptr(dC), _stream())
         ctx.save_for_backward(dC)
-        return out[2 * V], out[: 2 * V]
+        per_view = out[: 2 * V]
+        ctx.mark_non_differentiable(per_view)
+        return out[2 * V], per_view
 
     @staticmethod
     def backward(ctx, g_total, g_out):

@@ -8,6 +8,7 @@ import torch
 import oracle
 from oracle.render import Params64, render_pixels
 from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch
+from tests.grouping import expand_to_tile_lists, grouped_from_rectangles, instance_count
 
 FWD_TOL = 1e-4
 
@@ -60,19 +61,12 @@ def geometry(scene, rp=oracle.RasterParams()):
 ID_MASK = np.uint32(0xFFFFFF)   # surfel-id bits of a sorted instance value
 
 
-def group_instances(geoms, group=4):
-    """Instances of grouped binning: per visible record, the tile groups its
-    tile rectangle meets."""
-    n = 0
-    for g in geoms:
-        t = g["tiles"][~g["culled"]]
-        n += int(((t[:, 1] // group - t[:, 0] // group + 1) * (t[:, 3] // group - t[:, 2] // group + 1)).sum())
-    return n
-
-
-def compare_binning(scene, run, geoms, rp=oracle.RasterParams(), full_sort=True):
+def compare_binning(scene, run, geoms, rp=oracle.RasterParams(), full_sort=True, expand=True):
     """Bit-exact comparison of the per-(view, surfel) binning outputs and,
-    when ``full_sort``, of the whole sorted instance list and the ranges."""
+    when ``full_sort``, of the whole sorted grouped instance list, its 64-bit
+    keys and the per-tile ranges with the layout built from the oracle's
+    tile rectangles; with ``expand`` the GPU's group runs are also expanded
+    to every tile's list and compared with the oracle's per-tile lists."""
     rast = run["rast"]
     N, V = scene.n, scene.v
     tt = rast.tiles_touched[: V * N].cpu().numpy().view(np.uint32).reshape(V, N)
@@ -91,9 +85,9 @@ def compare_binning(scene, run, geoms, rp=oracle.RasterParams(), full_sort=True)
     vis, need, stored, status = run["status"]
     assert status == 0
     assert vis == sum(int((~g["culled"]).sum()) for g in geoms)
-    assert need == stored == group_instances(geoms)
+    assert need == stored == instance_count(geoms)
     if full_sort:
-        keys, vals, ranges = oracle.bin64(geoms, scene.cams, rp, group=4)
+        keys, vals, ranges = grouped_from_rectangles(geoms, scene.cams, rp.tile_w, rp.tile_h)
         gv = rast.vals[:need].cpu().numpy().view(np.uint32)
         gr = rast.ranges[: 2 * rast.views.T].cpu().numpy().view(np.uint32).reshape(-1, 2)
         np.testing.assert_array_equal(gv, vals)
@@ -101,6 +95,11 @@ def compare_binning(scene, run, geoms, rp=oracle.RasterParams(), full_sort=True)
         if run["keys64"] is not None:
             gk = run["keys64"][:need].cpu().numpy().view(np.uint64)
             np.testing.assert_array_equal(gk, keys)
+        if expand:
+            _, v1, r1 = oracle.bin64(geoms, scene.cams, rp)
+            ids, rg = expand_to_tile_lists(gv, gr, scene.cams, rp.tile_w, rp.tile_h)
+            np.testing.assert_array_equal(ids, v1)
+            np.testing.assert_array_equal(rg, r1)
     return exempt
 
 

@@ -13,7 +13,8 @@ import oracle
 from oracle.render import Params64, render_pixels
 from paper_2501_08174_amd import scenes
 from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch, rasterize, prune_mask
-from tests.gpu_helpers import compare_forward, crop_pixels, gpu_run, group_instances, per_view
+from tests.gpu_helpers import compare_forward, crop_pixels, gpu_run, per_view
+from tests.grouping import grouped_from_rectangles, instance_count, tile_list
 
 pytestmark = pytest.mark.gpu
 RP = oracle.RasterParams()
@@ -71,7 +72,7 @@ def _sampled_tiles(sc, run, geoms, n_tiles=48, seed=0):
         t = int(rng.integers(0, h.tiles_x * h.tiles_y))
         want = _tile_list(geoms[v], h.tiles_x, t)
         tx, ty = t % h.tiles_x, t // h.tiles_x
-        ids, pos = oracle.tile_list(vals, rg, h.tile_offset + t, (tx, ty))
+        ids, pos = tile_list(vals, rg, h.tile_offset + t, (tx, ty))
         np.testing.assert_array_equal(ids, want)
         if k64 is not None:
             grp = h.group_offset + (ty // 4) * h.groups_x + tx // 4
@@ -220,7 +221,7 @@ def test_ragged16_full_size():
     print("ragged16-1m records bit-exact; grid-tie exemptions", ex)
     vis, need, stored, status = run["status"]
     assert status == 0 and vis == sum(int((~g["culled"]).sum()) for g in geoms.values())
-    assert need == group_instances(list(geoms.values()))
+    assert need == instance_count(list(geoms.values()))
     _sampled_tiles(sc, run, geoms)
     P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, 3)
     rng = np.random.default_rng(3)

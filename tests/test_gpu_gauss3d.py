@@ -12,7 +12,8 @@ import oracle
 from oracle.gauss3d import prune_pixels3d, view_geometry3d64
 from paper_2501_08174_amd import scenes
 from paper_2501_08174_amd.raster import Pruner3D, ViewBatch, prune_contrib_3d
-from tests.gpu_helpers import crop_pixels, group_instances
+from tests.gpu_helpers import crop_pixels
+from tests.grouping import grouped_from_rectangles, instance_count
 
 pytestmark = pytest.mark.gpu
 RP = oracle.RasterParams()
@@ -62,8 +63,8 @@ def test_binning_bit_exact_and_statistics():
         assert not bad.any(), f"view {v}: {bad.sum()} records differ, e.g. {np.nonzero(bad)[0][:5]}"
         exempt += int(mism.sum())
     vis, need, stored, status = pr.status()
-    assert status == 0 and need == group_instances(geoms)
-    keys, vals, ranges = oracle.bin64(geoms, sc.cams, RP, group=4)
+    assert status == 0 and need == instance_count(geoms)
+    keys, vals, ranges = grouped_from_rectangles(geoms, sc.cams, RP.tile_w, RP.tile_h)
     np.testing.assert_array_equal(pr.vals[:need].cpu().numpy().view(np.uint32), vals)
     np.testing.assert_array_equal(pr.ranges[: 2 * views.T].cpu().numpy().view(np.uint32).reshape(-1, 2), ranges)
     np.testing.assert_array_equal(k64[:need].cpu().numpy().view(np.uint64), keys)

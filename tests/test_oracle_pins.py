@@ -369,35 +369,25 @@ def test_bin64_tile_lists_brute_force(rp):
     assert covered == keys.size == int(sum(g["tiles_touched"].sum() for g in geoms))
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
-def test_grouped_lists_expand_to_tile_lists(tile):
-    """Binning in 4x4 tile groups: every tile's entries of its group list
-    (sub-rectangle contains the tile) are exactly its per-tile list, in the
-    same order; each (group, surfel) pair appears once, when the surfel's
-    tile rectangle meets the group."""
-    rp = oracle.RasterParams(tile_w=tile[0], tile_h=tile[1])
-    sc = scenes.make_random_scene(16, 300, n_views=3, width=[140, 61, 17], height=[97, 130, 33],
-                                  scale_range=(0.02, 0.6))
-    geoms = [oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, c, rp) for c in sc.cams]
-    k1, v1, r1 = oracle.bin64(geoms, sc.cams, rp)
-    k4, v4, r4 = oracle.bin64(geoms, sc.cams, rp, group=4)
-    lay, T = oracle.tile_layout(sc.cams, rp)
-    glay = oracle.group_layout(sc.cams, rp, 4)
-    n_groups = 0
-    for v, ((tx, ty, off), (gx, gy, goff)) in enumerate(zip(lay, glay)):
-        for t in range(tx * ty):
-            ids, pos = oracle.tile_list(v4, r4, off + t, (t % tx, t // tx))
-            s, e = r1[off + t]
-            np.testing.assert_array_equal(ids, v1[s:e])
-        g = geoms[v]
-        ok = ~g["culled"]
-        tl = g["tiles"][ok]
-        n_groups += int(((tl[:, 1] // 4 - tl[:, 0] // 4 + 1) * (tl[:, 3] // 4 - tl[:, 2] // 4 + 1)).sum())
-    assert k4.size == n_groups < k1.size
-    gk = (k4 >> np.uint64(32)).astype(np.int64)
-    pair = gk * (sc.n + 1) + (v4 & np.uint32(0xFFFFFF)).astype(np.int64)
-    assert np.unique(pair).size == pair.size
-    assert np.all(np.diff(gk) >= 0)
+def test_prune_statistics_hand_computed(rp):
+    """prune_stats64 of two stacked scenes against hand-computed hits, largest
+    alpha and largest blending weight (tests/golden/prune_stack.json): a
+    dropped termination, a sum instead of a maximum, the alpha taken for the
+    weight or the weight read at the pixel of the largest alpha would each
+    change a stored value."""
+    gold = json.load(open(os.path.join(GOLDEN, "prune_stack.json")))
+    cam = front_camera(9)
+    assert cam.cx == 4.5 and cam.cy == 4.5
+    for case in gold["scenes"]:
+        n = len(case["opacity"])
+        means = [[0.0, 0.0, z] for z in case["world_z"]]
+        sc = scene_from(means, [(0.05, 0.05)] * n, [ID] * n, case["opacity"], [(0.5, 0.5, 0.5)] * n, [cam])
+        res, pix, g = _render(sc, rp)
+        st = oracle.prune_stats64(n, [res["pairs"]], [g["culled"]])
+        np.testing.assert_array_equal(st["hits"], case["hits"], err_msg=case["name"])
+        np.testing.assert_allclose(st["max_alpha"], case["max_alpha"], rtol=0, atol=1e-12, err_msg=case["name"])
+        np.testing.assert_allclose(st["max_weight"], case["max_weight"], rtol=0, atol=1e-12, err_msg=case["name"])
+        assert not st["prune"].any() and st["in_frustum"].all()
 
 
 def test_near_plane_and_opacity_culls(rp):
