@@ -43,13 +43,19 @@ from .sh import sh_colour
 DT = torch.float64
 
 # Tie windows for the flags that mark pixels where a float32 evaluation may
-# legitimately take the other side of a threshold.  A float32 evaluation of
-# o G carries a relative error of a few 1e-6 (rounding of the record and of
-# rho, exp); T(1 - a) accumulates that error over the blended entries,
-# amplified by a / (1 - a) <= 99 per entry near the alpha clamp.  The windows
-# are an order of magnitude wider than those errors.
-TIE_CUTOFF_REL = 5e-5      # |o G - alpha_min| <= 5e-5 alpha_min
-TIE_TERM_REL = 2e-4        # |T (1 - a) - t_min| <= 2e-4 t_min
+# legitimately take the other side of a threshold (both results are then
+# correct; ``render_alternatives`` gives the other one).  A float32
+# evaluation of o G is exact to a few float32 ulps of the exponent (a
+# relative error of order 1e-7 to 1e-6: rounding of the record, of
+# rho = u^2 + v^2 and of the log-space cutoff); T (1 - a) accumulates the
+# rounding of one product per blended entry (order 1e-6 after a hundred).
+# Measured on 64x64 crops of the 16-view, 1M-surfel benchmark scene
+# (131,072 pixels, about 11,000 entries within 1e-3 of a threshold): where
+# only one result matched, float32 took the other side at relative
+# distances up to 3.3e-7 (cutoff and termination alike).  The windows are
+# ten and thirty times that.
+TIE_CUTOFF_REL = 3e-6      # |o G - alpha_min| <= 3e-6 alpha_min
+TIE_TERM_REL = 1e-5        # |T (1 - a) - t_min| <= 1e-5 t_min
 TIE_BRANCH = 1e-6          # |G_s - G_f|
 TIE_CLAMP = 1e-6           # |o G - alpha_max|
 TIE_MEDIAN = 1e-5          # |T_before - 1/2| at a blended entry (median depth)
@@ -160,8 +166,12 @@ def _pixel_lists(geom, pix: np.ndarray, margin: int = 1):
     return cand, colorder, valid, ghost
 
 
-def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
-    """Front-to-back compositing of a chunk of pixels."""
+def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams, flip=None):
+    """Front-to-back compositing of a chunk of pixels.  ``flip`` (optional)
+    holds (P,L) boolean masks "cut", "term" and "branch" of entries whose
+    decision is taken the other way: the cutoff test, the termination test
+    and the surface/low-pass choice (an alternative result where float32
+    may land on the other side of a threshold)."""
     Pn, L = colidx.shape
     ci = torch.as_tensor(colidx, dtype=torch.long)
     g = lambda t: t[ci]                                    # (P,L,...)
@@ -189,6 +199,8 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
     dy = y - ctr[..., 1]
     Gf = torch.exp(-(dx * dx + dy * dy))
     surf = Gs >= Gf
+    if flip is not None:
+        surf = surf ^ torch.as_tensor(flip["branch"])
     G = torch.where(surf, Gs, Gf)
     z = torch.where(surf, tau, p[..., 2])
     o = g(Q["o"])
@@ -197,11 +209,17 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
 
     vt = torch.as_tensor(valid)
     gt = torch.as_tensor(ghost)
-    skip = (a < rp.alpha_min) | ~vt | gt
+    cut = a < rp.alpha_min
+    if flip is not None:
+        cut = cut ^ torch.as_tensor(flip["cut"])
+    skip = cut | ~vt | gt
     one_minus = torch.where(skip, torch.ones_like(a), 1 - a)
     T_after = torch.cumprod(one_minus, dim=1)
     T_before = torch.cat([torch.ones_like(T_after[:, :1]), T_after[:, :-1]], dim=1)
-    stop = (~skip) & (T_after < rp.t_min)
+    term = T_after < rp.t_min
+    if flip is not None:
+        term = term ^ torch.as_tensor(flip["term"])
+    stop = (~skip) & term
     has_stop = stop.any(dim=1)
     first_stop = torch.where(has_stop, stop.to(torch.int64).argmax(dim=1), torch.full((Pn,), L))
     k = torch.arange(L)[None, :]
@@ -241,8 +259,10 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
     median_idx = kmed + 1
 
     with torch.no_grad():
+        # an entry outside its surfel's pixel rectangle (bit-exact on both
+        # sides) is never evaluated, so it cannot make a tie
         nsk = reached & ~gt
-        e_cut = reached & ((a_raw - rp.alpha_min).abs() <= TIE_CUTOFF_REL * rp.alpha_min)
+        e_cut = nsk & ((a_raw - rp.alpha_min).abs() <= TIE_CUTOFF_REL * rp.alpha_min)
         e_term = nsk & ~skip & ((T_before * (1 - a) - rp.t_min).abs() <= TIE_TERM_REL * rp.t_min)
         e_branch = blended & ((Gs - Gf).abs() <= TIE_BRANCH)
         e_clamp = blended & ((a_raw - rp.alpha_max).abs() <= TIE_CLAMP)
@@ -251,7 +271,13 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
         f_cut, f_term = e_cut.any(dim=1), e_term.any(dim=1)
         f_branch, f_clamp = e_branch.any(dim=1), e_clamp.any(dim=1)
         tie_entry = e_cut | e_term | e_branch | e_clamp
-    return dict(color=color, alpha=alpha, depth=depth, normal=normal, dist=dist,
+        tie_kinds = torch.stack([e_cut, e_term, e_branch, e_clamp, e_median], dim=-1)
+        # signed distance of each entry from each threshold (relative for the
+        # cutoff and the termination test)
+        tie_dist = torch.stack([(a_raw - rp.alpha_min) / rp.alpha_min,
+                                (T_before * (1 - a) - rp.t_min) / rp.t_min,
+                                Gs - Gf, a_raw - rp.alpha_max, T_before - 0.5], dim=-1)
+    return dict(tie_kinds=tie_kinds, tie_dist=tie_dist, color=color, alpha=alpha, depth=depth, normal=normal, dist=dist,
                 T_final=T_final, n_contrib=n_contrib, blended=blended, reached=reached,
                 a=a, w=w, z=z, surf=surf, skip=skip, first_stop=first_stop,
                 clamp=a_raw > rp.alpha_max, tie_entry=tie_entry,
@@ -260,11 +286,13 @@ def _composite(Q, cam, pix, colidx, valid, ghost, rp: RasterParams):
 
 
 OUT_KEYS = ("color", "alpha", "depth", "normal", "dist", "T_final", "median_depth")
+TIE_KINDS = ("cut", "term", "branch", "clamp", "median")
 
 
 def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = RasterParams(),
                   loss_fn: Optional[Callable] = None, max_entries: int = 1_500_000,
-                  keep_decisions: bool = False, screen_shift: Optional[torch.Tensor] = None):
+                  keep_decisions: bool = False, screen_shift: Optional[torch.Tensor] = None,
+                  flips: Optional[dict] = None):
     """Render the pixels ``pix`` (P,2) int (column i, row j) of one view.
 
     Returns numpy arrays: color (P,3), alpha, depth, normal (P,3), dist,
@@ -279,13 +307,20 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
     many pixels (evaluated at x - shift); with requires_grad and zeros, the
     chunks' backward leaves dL/d(shift), the screen-space gradient of the
     density-control statistic.
+    ``tie_list`` (K,3) lists the tie entries: (row of ``pix``, surfel id,
+    kind) with kind TIE_KINDS.index of the threshold it sits at, and
+    ``tie_dist`` (K,) each one's signed distance from that threshold
+    (relative to it for the cutoff and the termination test).
+    ``flips`` {row: [(surfel id, kind), ...]} takes the decision of those
+    entries of that pixel the other way (kind "cut", "term" or "branch"; see
+    ``render_alternatives``).
     """
     pix = np.asarray(pix, np.int64).reshape(-1, 2)
     Pn = pix.shape[0]
     res = {k: [] for k in OUT_KEYS}
     extra = {k: [] for k in ("n_contrib", "last_gid", "nblend", "flag_cut", "flag_term",
                              "flag_branch", "flag_clamp", "median_idx", "flag_median")}
-    pairs, flag_ids, tie_ids, decisions = [], [], [], []
+    pairs, flag_ids, tie_ids, decisions, tie_list, tie_dist = [], [], [], [], [], []
     start = 0
     step = max(1, min(Pn, 1024))
     while start < Pn:
@@ -302,7 +337,14 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
         Q = surfel_view_quantities(P, ids, cam, geom["flip"])
         if screen_shift is not None:
             Q["shift"] = screen_shift[torch.as_tensor(ids, dtype=torch.long)]
-        out = _composite(Q, cam, sub, colidx, valid, ghost, rp)
+        fl_masks = None
+        if flips:
+            gm = ids[colidx]
+            fl_masks = {k: np.zeros(colidx.shape, bool) for k in ("cut", "term", "branch")}
+            for r in range(start, stop):
+                for gid, kind in flips.get(r, ()):
+                    fl_masks[kind][r - start] |= valid[r - start] & (gm[r - start] == gid)
+        out = _composite(Q, cam, sub, colidx, valid, ghost, rp, flip=fl_masks)
         if loss_fn is not None:
             lval = loss_fn(out, np.arange(start, stop))
             if lval is not None and lval.requires_grad:
@@ -321,6 +363,12 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
         extra["nblend"].append(bl.sum(axis=1))
         for k in ("flag_cut", "flag_term", "flag_branch", "flag_clamp", "median_idx", "flag_median"):
             extra[k].append(out[k].numpy())
+        tk = out["tie_kinds"].numpy()
+        tr, tc, tkind = np.nonzero(tk)
+        if tr.size:
+            gid_t = (ids[colidx])[tr, tc]
+            tie_list.append(np.stack([tr + start, gid_t, tkind], axis=1))
+            tie_dist.append(out["tie_dist"].detach().numpy()[tr, tc, tkind])
         rr, cc = np.nonzero(bl)
         pairs.append(np.stack([rr + start, gid_mat[rr, cc]], axis=1) if rr.size else np.zeros((0, 2), np.int64))
         pairs_a = out["a"].detach().numpy()[rr, cc]
@@ -348,6 +396,13 @@ def render_pixels(P: Params64, cam, geom, pix: np.ndarray, rp: RasterParams = Ra
         result["pairs"] = (np.zeros((0, 2), np.int64), np.zeros(0), np.zeros(0))
     result["flag_ids"] = np.unique(np.concatenate(flag_ids)) if flag_ids else np.zeros(0, np.int64)
     result["tie_ids"] = np.unique(np.concatenate(tie_ids)) if tie_ids else np.zeros(0, np.int64)
+    if tie_list:
+        tl = np.concatenate(tie_list).astype(np.int64)
+        td = np.concatenate(tie_dist)
+        o = np.lexsort((tl[:, 2], tl[:, 1], tl[:, 0]))
+        result["tie_list"], result["tie_dist"] = tl[o], td[o]
+    else:
+        result["tie_list"], result["tie_dist"] = np.zeros((0, 3), np.int64), np.zeros(0)
     if keep_decisions:
         result["decisions"] = decisions
     return result
@@ -361,3 +416,39 @@ def render_view(P: Params64, cam, geom, rp: RasterParams = RasterParams(), crop=
     jj, ii = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
     pix = np.stack([ii.ravel(), jj.ravel()], axis=1)
     return render_pixels(P, cam, geom, pix, rp, **kw), pix
+
+
+def render_alternatives(P: Params64, cam, geom, pix: np.ndarray, tie_list: np.ndarray,
+                        rp: RasterParams = RasterParams(), max_ties: int = 4,
+                        kinds=("cut", "term", "branch")):
+    """The other correct results of pixels whose list holds a tie entry.
+
+    Where a value sits within float32 reach of a threshold (the alpha cutoff
+    and the termination test of Section 4.3's front-to-back blending, and
+    the surface/low-pass choice), an exact evaluation and a float32 one may
+    decide it differently, and both results are correct.  For every pixel
+    row of ``pix`` with at most ``max_ties`` tie entries of the given kinds
+    (``tie_list`` of ``render_pixels``), the pixel is rendered once per
+    non-empty subset of those entries taken the other way.
+
+    Returns (alts, results, unresolved): ``alts`` a list of (row, flips)
+    with flips a tuple of (surfel id, kind); ``results`` the render_pixels
+    output whose i-th pixel is alts[i]; ``unresolved`` the rows with more
+    tie entries than ``max_ties``.
+    """
+    codes = [TIE_KINDS.index(k) for k in kinds]
+    tl = tie_list[np.isin(tie_list[:, 2], codes)] if len(tie_list) else np.zeros((0, 3), np.int64)
+    alts, unresolved = [], []
+    for row in np.unique(tl[:, 0]):
+        ent = [(int(g), TIE_KINDS[int(k)]) for _, g, k in tl[tl[:, 0] == row]]
+        if len(ent) > max_ties:
+            unresolved.append(int(row))
+            continue
+        for m in range(1, 1 << len(ent)):
+            alts.append((int(row), tuple(e for b, e in enumerate(ent) if m >> b & 1)))
+    if not alts:
+        return alts, None, unresolved
+    alt_pix = np.asarray([pix[r] for r, _ in alts], np.int64).reshape(-1, 2)
+    flips = {i: list(f) for i, (_, f) in enumerate(alts)}
+    res = render_pixels(P, cam, geom, alt_pix, rp, flips=flips)
+    return alts, res, unresolved

@@ -174,7 +174,10 @@ def test_termination_count(rp):
 # brute force: sequential loop with numpy.linalg.solve on tiny scenes
 # --------------------------------------------------------------------------
 
-def _brute_pixel(sc, cam, i, j, rp, frames):
+def _brute_pixel(sc, cam, i, j, rp, frames, flip=()):
+    """Sequential front-to-back loop at pixel (i, j); ``flip`` holds
+    (surfel id, kind) decisions taken the other way (kind "cut": the cutoff
+    test, "term": the termination test, "branch": surface vs low-pass)."""
     x = np.array([i + 0.5, j + 0.5])
     vm = cam.viewmat.astype(np.float64)
     R, t = vm[:, :3], vm[:, 3]
@@ -206,10 +209,13 @@ def _brute_pixel(sc, cam, i, j, rp, frames):
             Gs = 0.0
         ctr = np.array([cam.fx * p[0] / p[2] + cam.cx, cam.fy * p[1] / p[2] + cam.cy])
         Gf = math.exp(-float((x - ctr) @ (x - ctr)))
-        a = min(rp.alpha_max, o * max(Gs, Gf))
-        if a < rp.alpha_min:
+        surf = Gs >= Gf
+        if (gidx, "branch") in flip:
+            surf = not surf
+        a = min(rp.alpha_max, o * (Gs if surf else Gf))
+        if (a < rp.alpha_min) != ((gidx, "cut") in flip):
             continue
-        if T * (1 - a) < rp.t_min:
+        if (T * (1 - a) < rp.t_min) != ((gidx, "term") in flip):
             break
         rgb = np.maximum(sc.sh[gidx, 0].astype(np.float64) * Y00 + 0.5, 0)
         C += a * T * rgb
@@ -231,6 +237,77 @@ def test_brute_force_loop_matches(rp):
         np.testing.assert_allclose(res["color"][k], C, atol=1e-10)
         assert abs(res["alpha"][k] - A) < 1e-10
         assert res["nblend"][k] == len(lst)
+
+
+def test_alternative_decisions_match_brute_force(rp):
+    """render_pixels with decisions taken the other way (the alternative
+    results of the tie protocol) equals the sequential loop with the same
+    decisions flipped, for random entries of random pixels."""
+    from oracle.render import TIE_KINDS
+    sc = scenes.make_random_scene(11, 25, width=24, height=20, scale_range=(0.05, 0.4))
+    cam = sc.cams[0]
+    res, pix, g = _render(sc, rp)
+    frames = oracle.rotation_columns64(sc.quats)
+    P = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree)
+    rng = np.random.default_rng(5)
+    rows = [int(k) for k in rng.choice(pix.shape[0], 120, replace=False)]
+    flips, want = {}, {}
+    for r in rows:
+        i, j = pix[r]
+        inside = np.nonzero((~g["culled"]) & (g["rect"][:, 0] <= i) & (i <= g["rect"][:, 1]) &
+                            (g["rect"][:, 2] <= j) & (j <= g["rect"][:, 3]))[0]
+        if inside.size == 0:
+            continue
+        pick = rng.choice(inside, size=min(2, inside.size), replace=False)
+        f = [(int(gid), str(rng.choice(["cut", "term", "branch"]))) for gid in pick]
+        flips[r] = f
+        want[r] = _brute_pixel(sc, cam, i, j, rp, frames, flip=set(f))
+    assert len(flips) > 30
+    alt = render_pixels(P, cam, g, pix, rp, flips=flips)
+    changed = 0
+    for r, (C, A, lst) in want.items():
+        np.testing.assert_allclose(alt["color"][r], C, atol=1e-10)
+        assert abs(alt["alpha"][r] - A) < 1e-10
+        assert alt["nblend"][r] == len(lst)
+        changed += abs(alt["alpha"][r] - res["alpha"][r]) > 1e-6
+    assert changed > 5
+    # rows without flips are unchanged
+    other = np.setdiff1d(np.arange(pix.shape[0]), list(flips))
+    np.testing.assert_array_equal(alt["alpha"][other], res["alpha"][other])
+    assert TIE_KINDS[:3] == ("cut", "term", "branch")
+
+
+def test_termination_taken_the_other_way(rp):
+    """The termination scene of tests/golden/termination.json with the
+    fourth surfel's termination test taken the other way: all four blend,
+    T_final = 0.05^4 = 6.25e-6 (by hand); with the first surfel's cutoff
+    taken the other way it is skipped: three blend, T_final = 0.05^3,
+    the last blended is the fourth; render_alternatives lists exactly the
+    flips of the tie entries it is given (both flips: two blend)."""
+    from oracle.render import TIE_KINDS, render_alternatives
+    gold = json.load(open(os.path.join(GOLDEN, "termination.json")))
+    cam = front_camera(32)
+    means = [centre_on_pixel(cam, 16, 16, d) for d in gold["depths"]]
+    sc = scene_from(means, [(0.5, 0.5)] * 4, [ID] * 4, [gold["opacity"]] * 4, [(0.5, 0.5, 0.5)] * 4, [cam])
+    g = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, cam, rp)
+    P = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree)
+    pix = np.array([[16, 16]])
+    r = render_pixels(P, cam, g, pix, rp, flips={0: [(3, "term")]})
+    assert r["nblend"][0] == 4 and r["last_gid"][0] == 3
+    q = 1 - float(np.float32(gold["opacity"]))       # 1 - a with the float32 opacity
+    assert abs(r["T_final"][0] - q ** 4) < 1e-10
+    r = render_pixels(P, cam, g, pix, rp, flips={0: [(0, "cut")]})
+    assert r["nblend"][0] == 3 and r["last_gid"][0] == 3
+    assert abs(r["T_final"][0] - q ** 3) < 1e-9
+    tl = np.array([[0, 3, TIE_KINDS.index("term")], [0, 0, TIE_KINDS.index("cut")]])
+    alts, ares, unres = render_alternatives(P, cam, g, pix, tl, rp)
+    assert sorted(f for _, f in alts) == sorted([((3, "term"),), ((0, "cut"),), ((3, "term"), (0, "cut"))])
+    k = [f for _, f in alts].index(((3, "term"), (0, "cut")))
+    # the first skipped, the fourth's test (1.25e-4 >= 1e-4, not a stop by
+    # itself) taken as a stop: the second and third blend
+    assert ares["nblend"][k] == 2 and ares["last_gid"][k] == 2
+    assert abs(ares["T_final"][k] - q ** 2) < 1e-9
+    assert unres == []
 
 
 def test_rect_is_conservative_vs_full_frame_lists(rp):
