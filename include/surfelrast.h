@@ -12,12 +12,20 @@
  *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
  *     enqueues work on it: none synchronises, so a sequence of calls can be
  *     captured into a HIP graph.
+ *   - Every call that enqueues device work takes a context (sr_create): the
+ *     device it runs on and that device's status word.  Calls made while
+ *     another device is current return SR_ERR_STATE.
  *   - Arguments are validated on the host before anything is enqueued; an
  *     invalid call returns SR_ERR_ARG (or SR_ERR_UNSUPPORTED) and leaves the
  *     message in sr_last_error().  A HIP launch failure returns SR_ERR_HIP.
  *     Data-dependent failures (instance capacity exceeded) cannot be returned
- *     without a synchronisation: they are written to the device counters
- *     array (see sr_bin_and_sort) for the caller to check after the step.
+ *     without a synchronisation: sr_bin_and_sort records them in the
+ *     context's device status word, every later compositing call of the
+ *     context sees the word and flags its outputs instead of computing them
+ *     (per-pixel outputs and losses NaN, no gradients, no statistics, an
+ *     empty prune mask), and the caller reads the word with sr_read_status
+ *     after the step or graph replay.  The word stays set until
+ *     sr_read_status (clear != 0) or sr_clear_status resets it.
  *   - Surfel parameters (Section 3.1: position, shape, appearance), N surfels:
  *       means  [N,3]  centre mu in world space
  *       scales [N,2]  tangent scales (s_u, s_v) > 0, already activated
@@ -50,6 +58,14 @@ typedef int32_t sr_status;
 #define SR_ERR_CAPACITY (-2)
 #define SR_ERR_HIP (-3)
 #define SR_ERR_UNSUPPORTED (-4)
+#define SR_ERR_STATE (-5)
+
+/* Bits of the device status word. */
+#define SR_STATUS_CAPACITY 1u   /* a binning needed more instances than its capacity */
+
+/* A context: the HIP device a sequence of calls runs on and that device's
+ * status word (16 bytes of device memory, allocated by sr_create). */
+typedef struct sr_ctx sr_ctx;
 
 /* Pinhole camera with OpenCV axes (x right, y down, z forward); pixel (i,j)
  * is sampled at (i+0.5, j+0.5).  128 bytes; the device copy passed as
@@ -101,6 +117,26 @@ typedef struct sr_config {
 
 const char *sr_last_error(void);
 int32_t sr_version(void);
+
+/* sr_create: a context on HIP device `device` (its status word zeroed);
+ * the only allocation the library makes.  Host-synchronous.  Errors:
+ * SR_ERR_ARG (NULL out pointer, no such device), SR_ERR_HIP.
+ * sr_destroy: frees it (NULL is a no-op); the caller must not destroy a
+ * context while work that uses it is still queued. */
+sr_status sr_create(sr_ctx **ctx_out_host, int32_t device);
+sr_status sr_destroy(sr_ctx *ctx);
+
+/* Reads the status word after the work queued on `stream`: synchronises
+ * the stream, writes the SR_STATUS_* bits to *status_bits_host and the
+ * largest instance count any failed binning needed to *needed_capacity_host
+ * (either may be NULL), and with clear != 0 resets the word.  Returns
+ * SR_OK when no bit is set, SR_ERR_CAPACITY (with a message) when the
+ * capacity bit is. */
+sr_status sr_read_status(sr_ctx *ctx, void *stream, int32_t clear, uint32_t *status_bits_host,
+                         uint64_t *needed_capacity_host);
+/* Enqueues a reset of the status word on `stream` (a kernel, so it can be
+ * captured in a HIP graph before the steps it guards). */
+sr_status sr_clear_status(sr_ctx *ctx, void *stream);
 /* 1 if the tile shape is compiled in, else 0. */
 int32_t sr_tile_supported(int32_t tile_w, int32_t tile_h);
 
@@ -125,10 +161,12 @@ sr_status sr_layout_views(sr_camera *cams_host, int32_t V, int32_t tile_w, int32
  *   rect  [V*N, 4]   uint16 pixel rectangle [x_lo, x_hi, y_lo, y_hi]
  *   tiles_touched [V*N] number of tiles of the rectangle (0 when culled)
  *   depth_key [V*N]  bits of float32(centre depth); 0xFFFFFFFF when culled
- *   in_frustum [N]   1 if not culled in some view (NULL to skip)
+ *   in_frustum [N]   1 if not culled in some view (NULL to skip); with
+ *                    SR_FLAG_ACCUMULATE only set, never cleared (OR over
+ *                    calls)
  * Culling, rectangle and depth key are evaluated in float64 in a fixed
  * operation order, so they are reproducible bit for bit. */
-sr_status sr_preprocess(const sr_config *cfg, int32_t N, const float *means, const float *scales,
+sr_status sr_preprocess(sr_ctx *ctx, const sr_config *cfg, int32_t N, const float *means, const float *scales,
                         const float *quats, const float *opac, const float *sh,
                         int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
                         float *geom, float *app, uint16_t *rect, uint32_t *tiles_touched,
@@ -137,6 +175,15 @@ sr_status sr_preprocess(const sr_config *cfg, int32_t N, const float *means, con
 /* Bytes of workspace sr_bin_and_sort needs for N surfels, V views and an
  * instance capacity (instances are (view, tile group, surfel) triples). */
 sr_status sr_bin_workspace_size(int32_t N, int32_t V, uint32_t inst_capacity, size_t *bytes_host);
+
+/* Bytes of one workspace that serves every call of a training step over
+ * these views that takes one (sr_bin_and_sort with this capacity,
+ * sr_background_loss, sr_regularizer_loss, sr_ssim_loss with gradients,
+ * sr_tile_order, sr_compact_surfels): the largest of their sizes.  Each
+ * call is done with its workspace when its work on the stream ends, so
+ * calls on one stream may share it. */
+sr_status sr_workspace_size(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+                            uint32_t inst_capacity, size_t *bytes_host);
 
 /* Duplicate-key generation, sort and per-tile ranges (Section 4.3: each
  * pixel blends its assigned Gaussians front to back).  Tiles are binned in
@@ -152,11 +199,17 @@ sr_status sr_bin_workspace_size(int32_t N, int32_t V, uint32_t inst_capacity, si
  *          if empty); the tile's own front-to-back list is the entries of
  *          that run whose sub-rectangle contains the tile
  *   counters [4]  see SR_COUNTERS
+ * When the instances exceed inst_capacity the first inst_capacity of them
+ * (in depth order) are sorted, counters[3] is 1 and the context's status
+ * word gets SR_STATUS_CAPACITY and the count: later compositing calls of
+ * the context flag their outputs.  inst_capacity 0 with vals NULL is a
+ * count-only call: counters [0..1] and empty ranges, nothing emitted, the
+ * status word untouched (capacity planning).
  * The depth part of the key is sorted once per visible (view, surfel)
  * before duplication; the group part by a stable LSD radix sort after it.
  * Tile-list positions used elsewhere (n_contrib, median_contrib) are
  * positions in the group run. */
-sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_bin_and_sort(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                           const sr_camera *cams_dev, const uint16_t *rect, const uint32_t *tiles_touched,
                           const uint32_t *depth_key, void *workspace, size_t ws_bytes,
                           uint32_t inst_capacity, uint32_t *vals, uint64_t *keys64, uint32_t *ranges,
@@ -183,7 +236,7 @@ sr_status sr_bin_and_sort(const sr_config *cfg, int32_t N, int32_t V, const sr_c
  * [T], optional: as for sr_train_step_raster (launch order; each tile's
  * largest n_contrib, which orders this step's sr_backward_raster through
  * sr_tile_order).  All other outputs except the statistics are required. */
-sr_status sr_render_forward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_render_forward(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                             const sr_camera *cams_dev, const float *geom, const float *app,
                             const uint32_t *vals, const uint32_t *ranges,
                             float *color, float *alpha, float *depth, float *normal, float *dist,
@@ -203,7 +256,7 @@ sr_status sr_render_forward(const sr_config *cfg, int32_t N, int32_t V, const sr
  * grad_rec [V*N, 24] is scratch (cleared by the call, and left zero).
  * The parameter gradients are ACCUMULATED (+=) into g_means [N,3],
  * g_scales [N,2], g_quats [N,4], g_opac [N], g_sh [N,sh_stride,3]. */
-sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_render_backward(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                              const sr_camera *cams_dev, const float *means, const float *scales,
                              const float *quats, const float *opac, const float *sh,
                              const float *geom, const float *app, const uint32_t *vals,
@@ -233,7 +286,7 @@ sr_status sr_render_backward(const sr_config *cfg, int32_t N, int32_t V, const s
  * the record's gradients as (dL/d low-pass centre) - (A, B) . dL/dC' for
  * w = A dx + B dy + C'.  densify_grad [N] float, densify_count [N] uint32,
  * both accumulated (+=); either may be NULL; they need tiles_touched. */
-sr_status sr_backward_raster(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_backward_raster(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                              const sr_camera *cams_dev, const float *geom, const float *app,
                              const uint32_t *vals, const uint32_t *ranges, const float *alpha,
                              const float *depth, const float *dist, const float *T_final,
@@ -241,7 +294,7 @@ sr_status sr_backward_raster(const sr_config *cfg, int32_t N, int32_t V, const s
                              const float *dL_ddepth, const float *dL_dnormal, const float *dL_ddist,
                              const uint32_t *median_contrib, const float *dL_dmedian,
                              float *grad_rec, const uint32_t *tile_order, void *stream);
-sr_status sr_backward_project(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_backward_project(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                               const sr_camera *cams_dev, const float *means, const float *scales,
                               const float *quats, const float *sh, const float *geom, const float *app,
                               const uint32_t *tiles_touched, float *grad_rec, float *g_means,
@@ -260,7 +313,7 @@ sr_status sr_loss_workspace_size(int32_t V, const sr_camera *cams_host, size_t *
  *   dL_dcolor [3P] = w_c M sign(C - I) / (3 H W V)         (overwritten)
  * mask [P] uint8 in {0,1}.  color, target and dL_dcolor may all be NULL.
  * The per-view sums use a fixed reduction order (deterministic). */
-sr_status sr_background_loss(int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
+sr_status sr_background_loss(sr_ctx *ctx, int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
                              const float *alpha, const uint8_t *mask, const float *color,
                              const float *target, float gamma, float w_c, void *workspace,
                              size_t ws_bytes, float *loss, float *dL_dalpha, float *dL_dcolor,
@@ -288,7 +341,7 @@ sr_status sr_background_loss(int32_t V, const sr_camera *cams_host, const sr_cam
  *                   depends on depth)
  * Feed all of them to sr_backward_raster.  workspace: sr_loss_workspace_size
  * bytes.  Per-view sums in a fixed order (deterministic). */
-sr_status sr_regularizer_loss(int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
+sr_status sr_regularizer_loss(sr_ctx *ctx, int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
                               const float *alpha, const float *depth, const float *normal,
                               const float *dist, const float *median, float w_dist, float w_normal,
                               void *workspace, size_t ws_bytes, float *loss, float *dL_dalpha,
@@ -314,7 +367,7 @@ sr_status sr_ssim_workspace_size(int32_t V, const sr_camera *cams_host, int32_t 
  * metrics only.  Full 3DGS photometric loss: w_c = 1 - lambda for the L1 term
  * and w_s = lambda (0.2).  mask [P] uint8; planar colour like the renderer.
  * Per-view sums in a fixed order (deterministic). */
-sr_status sr_ssim_loss(int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
+sr_status sr_ssim_loss(sr_ctx *ctx, int32_t V, const sr_camera *cams_host, const sr_camera *cams_dev,
                        const float *color, const float *target, const uint8_t *mask, float w_s,
                        void *workspace, size_t ws_bytes, float *out, float *dL_dcolor, void *stream);
 
@@ -339,7 +392,7 @@ sr_status sr_ssim_loss(int32_t V, const sr_camera *cams_host, const sr_camera *c
  *                   positions the tile works through), for the next call's
  *                   order
  * Follow with sr_backward_project for the parameter gradients. */
-sr_status sr_train_step_raster(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_train_step_raster(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                                const sr_camera *cams_dev, const float *geom, const float *app,
                                const uint32_t *vals, const uint32_t *ranges, const uint8_t *mask,
                                const float *target, float gamma, float w_c, float *color, float *alpha,
@@ -360,10 +413,11 @@ sr_status sr_train_step_raster(const sr_config *cfg, int32_t N, int32_t V, const
  * and, slowly, the parameters change between steps).  workspace: device
  * memory of sr_tile_order_workspace_size bytes; no host synchronisation. */
 sr_status sr_tile_order_workspace_size(int32_t T, size_t *bytes_host);
-sr_status sr_tile_order(int32_t T, const uint32_t *tile_cost, void *workspace, size_t ws_bytes,
+sr_status sr_tile_order(sr_ctx *ctx, int32_t T, const uint32_t *tile_cost, void *workspace, size_t ws_bytes,
                         uint32_t *tile_order, void *stream);
 
-/* Occlusion-aware pruning statistics (Section 4.3): the compositing
+/* Occlusion-aware pruning statistics of one binned batch of views (Section
+ * 4.3), the statistics stage of sr_prune_contrib: the compositing
  * decisions of sr_render_forward without shading.  For every blended
  * (pixel, surfel) pair: hits[g] += 1, max_alpha[g] = max(., a),
  * max_weight[g] = max(., a T).  hits [N] uint32, max_alpha [N],
@@ -372,7 +426,7 @@ sr_status sr_tile_order(int32_t T, const uint32_t *tile_cost, void *workspace, s
  * needed); with rect [V*N, 4] each 64-pixel wave skips the entries that
  * cannot reach its pixels, as sr_render_forward does (NULL: every entry is
  * evaluated; the statistics are the same up to float32 ties). */
-sr_status sr_prune_contrib(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_prune_stats(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                            const sr_camera *cams_dev, const float *geom, const uint16_t *rect,
                            const uint32_t *vals, const uint32_t *ranges, uint32_t *hits,
                            float *max_alpha, float *max_weight, void *stream);
@@ -386,7 +440,7 @@ sr_status sr_prune_contrib(const sr_config *cfg, int32_t N, int32_t V, const sr_
  * pixel rectangle misses all pixels of a wave are skipped by that wave and
  * not counted.  The same decisions as sr_render_forward (app as given to
  * it); used to express throughput as a fraction of the VALU roofline. */
-sr_status sr_render_count(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_render_count(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                           const sr_camera *cams_dev, const float *geom, const float *app,
                           const uint32_t *vals, const uint32_t *ranges, uint64_t *counts, void *stream);
 
@@ -402,15 +456,15 @@ sr_status sr_render_count(const sr_config *cfg, int32_t N, int32_t V, const sr_c
  * sr_preprocess and feed sr_bin_and_sort unchanged.  scales [N,3] (all
  * three axes), quats [N,4], opac [N]; geom3 [V*N, 8] float32 (conic a, b, c,
  * opacity, centre x, y, ln(o/alpha_min), 0).
- * sr_prune_contrib_3d: the statistics of sr_prune_contrib (hits, max alpha,
+ * sr_prune_stats_3d: the statistics of sr_prune_stats (hits, max alpha,
  * max weight; cleared first unless SR_FLAG_ACCUMULATE) with a = min(alpha_max,
  * o exp(-q/2)), the same cutoff, clamp and termination, lists from
  * sr_bin_and_sort. */
-sr_status sr_preprocess_3d(const sr_config *cfg, int32_t N, const float *means, const float *scales,
+sr_status sr_preprocess_3d(sr_ctx *ctx, const sr_config *cfg, int32_t N, const float *means, const float *scales,
                            const float *quats, const float *opac, int32_t V, const sr_camera *cams_host,
                            const sr_camera *cams_dev, float *geom3, uint16_t *rect, uint32_t *tiles_touched,
                            uint32_t *depth_key, uint8_t *in_frustum, void *stream);
-sr_status sr_prune_contrib_3d(const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
+sr_status sr_prune_stats_3d(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                               const sr_camera *cams_dev, const float *geom3, const uint32_t *vals,
                               const uint32_t *ranges, uint32_t *hits, float *max_alpha, float *max_weight,
                               void *stream);
@@ -426,14 +480,59 @@ sr_status sr_prune_contrib_3d(const sr_config *cfg, int32_t N, int32_t V, const 
  * bytes. */
 #define SR_COMPACT_MAX_ARRAYS 8
 sr_status sr_compact_workspace_size(int32_t N, size_t *bytes_host);
-sr_status sr_compact_surfels(int32_t N, const uint8_t *prune_mask, const float *opac, float min_opacity,
+sr_status sr_compact_surfels(sr_ctx *ctx, int32_t N, const uint8_t *prune_mask, const float *opac, float min_opacity,
                              int32_t n_arrays, const float *const *src_host, float *const *dst_host,
                              const int32_t *widths_host, void *workspace, size_t ws_bytes,
                              uint32_t *n_kept, void *stream);
 
+/* The whole occlusion-aware pruning pass (Section 4.3; Section 5.3 and
+ * Appendix B run it over every training view of a trained model): for
+ * every view, projection without shading, binning and the compositing
+ * decisions, the statistics accumulated over all V views, then the mask.
+ *   prim      SR_PRIM_SURFEL (2D Gaussians: scales [N,2]) or SR_PRIM_GAUSS3D
+ *             (3D Gaussians: scales [N,3], the EWA path of sr_preprocess_3d)
+ *   means [N,3], scales, quats [N,4], opac [N]: as sr_preprocess
+ *   cams      V views laid out together by sr_layout_views (host and device
+ *             copies); they are processed views_per_chunk at a time
+ *             (bounding the per-view records), each chunk binned with
+ *             inst_capacity instances (sr_prune_plan gives the count)
+ *   workspace sr_prune_workspace_size bytes
+ *   hits [N] uint32, max_alpha [N], max_weight [N] float32: the statistics
+ *             of sr_prune_stats over all views; in_frustum [N] uint8: 1 if
+ *             not culled in some view (NULL to skip); all cleared first
+ *             unless cfg->flags has SR_FLAG_ACCUMULATE (accumulation over
+ *             calls: sum, max, OR)
+ *   prune_mask [N] uint8: max_alpha < tau (1 = prune; tau = alpha_min is
+ *             "never blended in any view"); NULL to skip
+ * Enqueued on `stream`, no synchronisation.  A chunk whose instances exceed
+ * inst_capacity sets the status word; the statistics of that chunk and of
+ * every later one are not taken and the mask is left all zero (prune
+ * nothing): check sr_read_status. */
+#define SR_PRIM_SURFEL 0
+#define SR_PRIM_GAUSS3D 1
+sr_status sr_prune_workspace_size(const sr_config *cfg, int32_t prim, int32_t N, int32_t V,
+                                  const sr_camera *cams_host, int32_t views_per_chunk, uint32_t inst_capacity,
+                                  size_t *bytes_host);
+sr_status sr_prune_contrib(sr_ctx *ctx, const sr_config *cfg, int32_t prim, int32_t N, const float *means,
+                           const float *scales, const float *quats, const float *opac, int32_t V,
+                           const sr_camera *cams_host, const sr_camera *cams_dev, int32_t views_per_chunk,
+                           float tau, uint32_t inst_capacity, void *workspace, size_t ws_bytes, uint32_t *hits,
+                           float *max_alpha, float *max_weight, uint8_t *in_frustum, uint8_t *prune_mask,
+                           void *stream);
+/* Capacity planning for sr_prune_contrib: projects and counts the
+ * instances of every chunk (count-only binning) and writes the largest
+ * count to *inst_capacity_host.  SYNCHRONISES `stream` (the one pruning
+ * call that does).  workspace: sr_prune_workspace_size bytes for
+ * inst_capacity 0. */
+sr_status sr_prune_plan(sr_ctx *ctx, const sr_config *cfg, int32_t prim, int32_t N, const float *means,
+                        const float *scales, const float *quats, const float *opac, int32_t V,
+                        const sr_camera *cams_host, const sr_camera *cams_dev, int32_t views_per_chunk,
+                        void *workspace, size_t ws_bytes, uint32_t *inst_capacity_host, void *stream);
+
 /* prune_mask[g] = max_alpha[g] < tau (1 = prune).  With tau = alpha_min
- * this is "never blended in any view" (Section 4.3). */
-sr_status sr_prune_mask(int32_t N, const float *max_alpha, float tau, uint8_t *prune_mask, void *stream);
+ * this is "never blended in any view" (Section 4.3).  While the context's
+ * status word is set the mask is written all zero (prune nothing). */
+sr_status sr_prune_mask(sr_ctx *ctx, int32_t N, const float *max_alpha, float tau, uint8_t *prune_mask, void *stream);
 
 #ifdef __cplusplus
 }

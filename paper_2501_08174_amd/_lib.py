@@ -16,6 +16,10 @@ SR_ERR_ARG = -1
 SR_ERR_CAPACITY = -2
 SR_ERR_HIP = -3
 SR_ERR_UNSUPPORTED = -4
+SR_ERR_STATE = -5
+SR_STATUS_CAPACITY = 1
+SR_PRIM_SURFEL = 0
+SR_PRIM_GAUSS3D = 1
 SR_FLAG_ACCUMULATE = 1
 SR_GEOM_STRIDE = 16
 SR_APP_STRIDE = 8
@@ -26,11 +30,12 @@ SR_TILE_GROUP = 4
 SR_INST_ID_BITS = 24
 
 EXPORTED = (
-    "sr_last_error", "sr_version", "sr_tile_supported", "sr_layout_views", "sr_preprocess",
-    "sr_bin_workspace_size", "sr_bin_and_sort", "sr_render_forward", "sr_render_backward",
-    "sr_backward_raster", "sr_backward_project", "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_ssim_workspace_size", "sr_ssim_loss",
-    "sr_compact_workspace_size", "sr_compact_surfels", "sr_preprocess_3d", "sr_prune_contrib_3d",
-    "sr_train_step_raster", "sr_prune_contrib",
+    "sr_last_error", "sr_version", "sr_create", "sr_destroy", "sr_read_status", "sr_clear_status",
+    "sr_tile_supported", "sr_layout_views", "sr_preprocess", "sr_bin_workspace_size", "sr_workspace_size",
+    "sr_bin_and_sort", "sr_render_forward", "sr_render_backward", "sr_backward_raster", "sr_backward_project",
+    "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_ssim_workspace_size",
+    "sr_ssim_loss", "sr_compact_workspace_size", "sr_compact_surfels", "sr_preprocess_3d", "sr_prune_stats_3d",
+    "sr_train_step_raster", "sr_prune_stats", "sr_prune_workspace_size", "sr_prune_plan", "sr_prune_contrib",
     "sr_render_count", "sr_prune_mask", "sr_tile_order_workspace_size", "sr_tile_order",
 )
 
@@ -69,32 +74,45 @@ def _declare(lib):
     sig = {
         "sr_last_error": (c_char_p, []),
         "sr_version": (c_int32, []),
+        "sr_create": (c_int32, [V, c_int32]),
+        "sr_destroy": (c_int32, [V]),
+        "sr_read_status": (c_int32, [V, V, c_int32, V, V]),
+        "sr_clear_status": (c_int32, [V, V]),
         "sr_tile_supported": (c_int32, [c_int32, c_int32]),
         "sr_layout_views": (c_int32, [V, c_int32, c_int32, c_int32, POINTER(c_int64), POINTER(c_int32)]),
-        "sr_preprocess": (c_int32, [V, c_int32, V, V, V, V, V, c_int32, V, V, V, V, V, V, V, V, V]),
+        "sr_preprocess": (c_int32, [V, V, c_int32, V, V, V, V, V, c_int32, V, V, V, V, V, V, V, V, V]),
         "sr_bin_workspace_size": (c_int32, [c_int32, c_int32, c_uint32, POINTER(c_size_t)]),
-        "sr_bin_and_sort": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, c_size_t, c_uint32, V, V, V, V, V]),
-        "sr_render_forward": (c_int32, [V, c_int32, c_int32] + [V] * 21),
-        "sr_render_backward": (c_int32, [V, c_int32, c_int32, V, V] + [V] * 28),
-        "sr_backward_raster": (c_int32, [V, c_int32, c_int32] + [V] * 21),
-        "sr_backward_project": (c_int32, [V, c_int32, c_int32] + [V] * 18),
+        "sr_workspace_size": (c_int32, [V, c_int32, c_int32, V, c_uint32, POINTER(c_size_t)]),
+        "sr_bin_and_sort": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, c_size_t, c_uint32, V, V, V, V,
+                                      V]),
+        "sr_render_forward": (c_int32, [V, V, c_int32, c_int32] + [V] * 21),
+        "sr_render_backward": (c_int32, [V, V, c_int32, c_int32, V, V] + [V] * 28),
+        "sr_backward_raster": (c_int32, [V, V, c_int32, c_int32] + [V] * 21),
+        "sr_backward_project": (c_int32, [V, V, c_int32, c_int32] + [V] * 18),
         "sr_loss_workspace_size": (c_int32, [c_int32, V, POINTER(c_size_t)]),
-        "sr_background_loss": (c_int32, [c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V]),
-        "sr_regularizer_loss": (c_int32, [c_int32, V, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V, V,
-                                          V, V, V]),
+        "sr_background_loss": (c_int32, [V, c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V,
+                                         V]),
+        "sr_regularizer_loss": (c_int32, [V, c_int32, V, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V,
+                                          V, V, V, V, V]),
         "sr_ssim_workspace_size": (c_int32, [c_int32, V, c_int32, POINTER(c_size_t)]),
-        "sr_ssim_loss": (c_int32, [c_int32, V, V, V, V, V, c_float, V, c_size_t, V, V, V]),
+        "sr_ssim_loss": (c_int32, [V, c_int32, V, V, V, V, V, c_float, V, c_size_t, V, V, V]),
         "sr_compact_workspace_size": (c_int32, [c_int32, POINTER(c_size_t)]),
-        "sr_preprocess_3d": (c_int32, [V, c_int32, V, V, V, V, c_int32, V, V, V, V, V, V, V, V]),
-        "sr_prune_contrib_3d": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
-        "sr_compact_surfels": (c_int32, [c_int32, V, V, c_float, c_int32, V, V, V, V, c_size_t, V, V]),
-        "sr_train_step_raster": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
+        "sr_preprocess_3d": (c_int32, [V, V, c_int32, V, V, V, V, c_int32, V, V, V, V, V, V, V, V]),
+        "sr_prune_stats_3d": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
+        "sr_compact_surfels": (c_int32, [V, c_int32, V, V, c_float, c_int32, V, V, V, V, c_size_t, V, V]),
+        "sr_train_step_raster": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
                                  + [V] * 16),
         "sr_tile_order_workspace_size": (c_int32, [c_int32, POINTER(c_size_t)]),
-        "sr_tile_order": (c_int32, [c_int32, V, V, c_size_t, V, V]),
-        "sr_prune_contrib": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V, V, V]),
-        "sr_render_count": (c_int32, [V, c_int32, c_int32, V, V, V, V, V, V, V, V]),
-        "sr_prune_mask": (c_int32, [c_int32, V, c_float, V, V]),
+        "sr_tile_order": (c_int32, [V, c_int32, V, V, c_size_t, V, V]),
+        "sr_prune_stats": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, V, V]),
+        "sr_prune_workspace_size": (c_int32, [V, c_int32, c_int32, c_int32, V, c_int32, c_uint32,
+                                              POINTER(c_size_t)]),
+        "sr_prune_plan": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, c_int32, V, V, c_int32, V, c_size_t,
+                                    POINTER(c_uint32), V]),
+        "sr_prune_contrib": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, c_int32, V, V, c_int32, c_float,
+                                       c_uint32, V, c_size_t, V, V, V, V, V, V]),
+        "sr_render_count": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V]),
+        "sr_prune_mask": (c_int32, [V, c_int32, V, c_float, V, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -141,3 +159,49 @@ def workspace_bytes_loss(V: int, cams_host) -> int:
     out = c_size_t(0)
     check(lib().sr_loss_workspace_size(V, ctypes.cast(cams_host, c_void_p) if V else None, byref(out)))
     return out.value
+
+
+class Context:
+    """An sr_ctx: the HIP device its calls run on and that device's status
+    word (instance-capacity failures of the binning, read with
+    ``read_status``)."""
+
+    def __init__(self, device: int):
+        h = c_void_p()
+        check(lib().sr_create(byref(h), int(device)))
+        self.handle = h
+        self.device = int(device)
+
+    @property
+    def ptr(self):
+        return self.handle
+
+    def read_status(self, stream=None, clear: bool = True):
+        """(status bits, largest instance count a failed binning needed);
+        synchronises the stream."""
+        bits, need = c_uint32(0), ctypes.c_uint64(0)
+        st = lib().sr_read_status(self.handle, stream, int(clear), byref(bits), byref(need))
+        if st not in (SR_OK, SR_ERR_CAPACITY):
+            check(st)
+        return int(bits.value), int(need.value)
+
+    def clear_status(self, stream=None):
+        check(lib().sr_clear_status(self.handle, stream))
+
+    def __del__(self):
+        import sys
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and not sys.is_finalizing() and _lib is not None:
+            _lib.sr_destroy(h)
+            self.handle = None
+
+
+_default_ctx = {}
+
+
+def default_context(device: int) -> Context:
+    """One context per device for the calls that do not belong to a
+    rasterizer (losses, masks, compaction)."""
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]

@@ -99,7 +99,7 @@ k_vis_count(uint64_t VN, int G, const uint32_t* __restrict__ tiles_touched, uint
 template <typename T>
 __global__ void __launch_bounds__(kNT)
 k_scan_small(T* __restrict__ data, int n, uint32_t* __restrict__ counters, int slot, uint32_t capacity,
-             uint64_t* __restrict__ total64) {
+             uint64_t* __restrict__ total64, uint32_t* __restrict__ status = nullptr) {
     __shared__ T s_w[4];
     const int per = (n + kNT - 1) / kNT;
     const int b = threadIdx.x * per;
@@ -124,6 +124,12 @@ k_scan_small(T* __restrict__ data, int n, uint32_t* __restrict__ counters, int s
             counters[1] = t64 > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t64;
             counters[2] = t64 > capacity ? capacity : (uint32_t)t64;
             counters[3] = t64 > capacity ? 1u : 0u;
+            if (t64 > capacity && status) {
+                // sticky until the caller clears it: later compositing calls
+                // of the context see truncated lists and flag their outputs
+                atomicOr(&status[0], (uint32_t)SR_STATUS_CAPACITY);
+                atomicMax(&status[1], counters[1]);
+            }
         }
     }
 }
@@ -601,7 +607,7 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
                                const sr_camera* cams_dev,
                                const uint16_t* rect, const uint32_t* tiles_touched, const uint32_t* depth_key,
                                void* workspace, uint32_t cap, uint32_t* vals, uint64_t* keys64, uint32_t* ranges,
-                               uint32_t* counters, hipStream_t s) {
+                               uint32_t* counters, uint32_t* status, bool count_only, hipStream_t s) {
     const uint64_t VN = (uint64_t)V * (uint64_t)N;
     BinWs w = carve(workspace, VN, cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, counters, 0u, (uint64_t)SR_COUNTERS);
@@ -633,7 +639,9 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     const int Gi = Gv;
     hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, (const ushort4*)rect,
                        cfg.tile_w, cfg.tile_h, w.tts, w.rsort, w.isum);
-    hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap, w.itotal);
+    hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap, w.itotal,
+                       count_only ? nullptr : status);
+    if (count_only) return hipGetLastError();     // the instance count is all that was asked for
     hipLaunchKernelGGL(k_inst_offsets, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.tts, w.isum, w.ioff);
     const uint64_t emit_blocks = ((uint64_t)cap + kEmitPerBlock - 1) / kEmitPerBlock;
     if (emit_blocks > 0) {
@@ -655,6 +663,35 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
         hipLaunchKernelGGL(k_keys64, dim3((unsigned)(rblocks < 1 ? 1 : (rblocks > 65535 ? 65535 : rblocks))),
                            dim3(kNT), 0, s, counters, sorted_keys, vals, keys64, depth_key, cams_dev, V, N);
     }
+    return hipGetLastError();
+}
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(n < 1024 * 256 ? (unsigned)((n + 255) / 256) : 1024u), dim3(256), 0, s, p, v,
+                       n);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Cameras [v0, v0 + Vc) of a batch laid out together, as a batch of their
+// own: the tile, pixel and group offsets restart at zero.
+__global__ void k_rebase_cams(const sr_camera* __restrict__ src, int Vc, sr_camera* __restrict__ dst) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= Vc) return;
+    sr_camera c = src[v];
+    c.tile_offset -= src[0].tile_offset;
+    c.pix_offset -= src[0].pix_offset;
+    c.group_offset -= src[0].group_offset;
+    dst[v] = c;
+}
+
+}  // namespace
+
+hipError_t launch_rebase_cams(const sr_camera* src, int Vc, sr_camera* dst, hipStream_t s) {
+    if (Vc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rebase_cams, dim3((Vc + 63) / 64), dim3(64), 0, s, src, Vc, dst);
     return hipGetLastError();
 }
 

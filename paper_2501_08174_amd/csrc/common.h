@@ -18,7 +18,15 @@ struct RasterConsts {
     float alpha_max;
     float t_min;
     uint32_t flags;
+    // the context's device status word (NULL: none); while it is set the
+    // instance lists are truncated and the compositing kernels compute nothing
+    const uint32_t* status;
 };
+
+// The status word's verdict, read once per workgroup (uniform).
+__device__ __forceinline__ bool status_failed(const RasterConsts& rc) {
+    return rc.status != nullptr && *rc.status != 0u;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Neighbouring tiles read mostly the same surfel records, so give every XCD a

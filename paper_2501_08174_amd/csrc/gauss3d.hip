@@ -162,6 +162,7 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
     __shared__ float4 sg[2][NT];
     __shared__ uint32_t sid[NT];
     __shared__ uint32_t sst[3][NT];   // per-batch hits, max alpha, max weight over the waves
+    if (status_failed(rc)) return;    // truncated lists: no statistics
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = view_of_tile(cams, V, tile);
     const sr_camera& c = cams[v];
@@ -253,7 +254,8 @@ hipError_t launch_preprocess3d(const sr_config& cfg, int N, const float* means, 
                                float* geom3, uint16_t* rect, uint32_t* tiles_touched, uint32_t* depth_key,
                                uint8_t* in_frustum, hipStream_t s) {
     if (N == 0) return hipSuccess;
-    if (in_frustum) hipLaunchKernelGGL(k_zero_flags, dim3((N + 255) / 256), dim3(256), 0, s, in_frustum, N);
+    if (in_frustum && !(cfg.flags & SR_FLAG_ACCUMULATE))
+        hipLaunchKernelGGL(k_zero_flags, dim3((N + 255) / 256), dim3(256), 0, s, in_frustum, N);
     const uint64_t threads = (uint64_t)N * (uint64_t)V;
     if (threads == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_preprocess3d, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, N, means, scales,
@@ -264,9 +266,9 @@ hipError_t launch_preprocess3d(const sr_config& cfg, int N, const float* means, 
 
 hipError_t launch_prune3d(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                           const float* geom3, const uint32_t* vals, const uint32_t* ranges, uint32_t* hits,
-                          float* max_alpha, float* max_weight, hipStream_t s) {
+                          float* max_alpha, float* max_weight, const uint32_t* status, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
-    const RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+    const RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
 #define SR_P3(TW, TH)                                                                                          \
     if (cfg.tile_w == TW && cfg.tile_h == TH) {                                                              \
         hipLaunchKernelGGL((k_prune3d<TW, TH>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,          \

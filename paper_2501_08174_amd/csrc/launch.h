@@ -30,7 +30,9 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
                                const sr_camera* cams_dev,
                                const uint16_t* rect, const uint32_t* tiles_touched, const uint32_t* depth_key,
                                void* workspace, uint32_t cap, uint32_t* vals, uint64_t* keys64, uint32_t* ranges,
-                               uint32_t* counters, hipStream_t s);
+                               uint32_t* counters, uint32_t* status, bool count_only, hipStream_t s);
+hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_rebase_cams(const sr_camera* src, int Vc, sr_camera* dst, hipStream_t s);
 
 bool tile_shape_supported(int tw, int th);
 
@@ -42,14 +44,15 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              float* dist, float* T_final,
                              uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
                              unsigned long long* counts, float* median_depth, uint32_t* median_contrib,
-                             const uint32_t* tile_order, uint32_t* tile_cost, hipStream_t s);
+                             const uint32_t* tile_order, uint32_t* tile_cost, const uint32_t* status,
+                             hipStream_t s);
 
 hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                              const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
                              const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
-                             float* grad_rec, const uint32_t* tile_order, hipStream_t s);
+                             float* grad_rec, const uint32_t* tile_order, const uint32_t* status, hipStream_t s);
 
 hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                                const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
@@ -57,12 +60,13 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
                                float* alpha, float* depth, float* normal, float* dist, float* T_final,
                                uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
                                float* tile_loss, float* grad_rec, const uint32_t* tile_order,
-                               uint32_t* tile_cost, hipStream_t s);
+                               uint32_t* tile_cost, const uint32_t* status, hipStream_t s);
 
 hipError_t launch_loss_from_tiles(int V, const sr_camera* cams, const float* tile_loss, float gamma, float w_c,
                                   float* loss, hipStream_t s);
 
-hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, uint8_t* mask, hipStream_t s);
+hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, const uint32_t* status, uint8_t* mask,
+                             hipStream_t s);
 
 int loss_chunks(int64_t max_hw);
 size_t loss_workspace_bytes(int V, int64_t max_hw, int max_reg_tiles);
@@ -82,7 +86,7 @@ hipError_t launch_preprocess3d(const sr_config& cfg, int N, const float* means, 
                                uint8_t* in_frustum, hipStream_t s);
 hipError_t launch_prune3d(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                           const float* geom3, const uint32_t* vals, const uint32_t* ranges, uint32_t* hits,
-                          float* max_alpha, float* max_weight, hipStream_t s);
+                          float* max_alpha, float* max_weight, const uint32_t* status, hipStream_t s);
 size_t compact_workspace_bytes(int N);
 hipError_t launch_compact(int N, const uint8_t* prune, const float* opac, float min_opac, int n_arrays,
                           const float* const* src, float* const* dst, const int* widths, void* ws,

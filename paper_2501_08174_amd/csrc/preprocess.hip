@@ -575,7 +575,8 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
                              uint32_t* tiles_touched, uint32_t* depth_key, uint8_t* in_frustum,
                              hipStream_t stream) {
     if (N == 0) return hipSuccess;
-    if (in_frustum) hipLaunchKernelGGL(k_zero_u8, dim3((N + 255) / 256), dim3(256), 0, stream, in_frustum, N);
+    if (in_frustum && !(cfg.flags & SR_FLAG_ACCUMULATE))
+        hipLaunchKernelGGL(k_zero_u8, dim3((N + 255) / 256), dim3(256), 0, stream, in_frustum, N);
     const uint64_t threads = (uint64_t)N * (uint64_t)V;
     if (threads == 0) return hipGetLastError();
     dim3 grid((unsigned)((threads + 255) / 256)), block(256);

@@ -437,6 +437,14 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     if (COUNT) n_upto_last += n_eval_last;
 }
 
+// The final state of a pixel of a tile that computed nothing because the
+// status word was set: every output NaN, no blended entry.
+__device__ __forceinline__ void poison(PixFwd& st) {
+    const float q = __builtin_nanf("");
+    st.T = st.C0 = st.C1 = st.C2 = st.N0 = st.N1 = st.N2 = st.S0 = st.S1 = st.S2 = st.zref = st.zmed = q;
+    st.last = st.kmed = 0u;
+}
+
 // Forward outputs of one pixel from its final state.
 struct PixOut {
     float C0, C1, C2, A, D, Dist;
@@ -452,7 +460,7 @@ __device__ __forceinline__ PixOut pix_outputs(const PixFwd& st, const TileCtx& t
     // depth = sum w z = S1 + zref S0 ; dist = 2 (S0 S2 - S1^2) with z shifted by zref
     o.D = __builtin_fmaf(st.zref, st.S0, st.S1);
     const float dd = 2.0f * (st.S0 * st.S2 - st.S1 * st.S1);
-    o.Dist = dd > 0.f ? dd : 0.f;
+    o.Dist = (dd > 0.f || dd != dd) ? dd : 0.f;      // a NaN state stays NaN
     return o;
 }
 
@@ -496,12 +504,15 @@ k_render_fwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
     if (tile_order && tile_order[blockIdx.x] >= gridDim.x) return;
     TileCtx t;
     tile_ctx<TW, TH>(cams, V, ranges, t, tile_order);
+    const bool failed = status_failed(rc);
+    if (failed) t.n = 0u;
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
     uint64_t n_reached = 0, n_blended = 0, n_witer = 0, n_wblend = 0, n_upto = 0;
     fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, rect, vals, rc, sm, st, hits, max_alpha, max_weight, n_reached,
                            n_blended,
                        n_witer, n_wblend, n_upto);
+    if (failed) poison(st);
     if (MODE & kCount) {
         // per-pixel tally of the backward's pairs: summed over the wave first
         uint64_t up = n_upto;
@@ -740,8 +751,10 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
              const uint32_t* __restrict__ median_contrib, const float* __restrict__ dMed,
              float* __restrict__ grad_rec, const uint32_t* __restrict__ tile_order) {
     __shared__ BwdSmem<BATCH> sm;
-    // an order entry beyond the grid leaves the workgroup idle
+    // an order entry beyond the grid leaves the workgroup idle; so does a set
+    // status word (no gradients)
     if (tile_order && tile_order[blockIdx.x] >= gridDim.x) return;
+    if (status_failed(rc)) return;
     TileCtx t;
     tile_ctx<TW, TH>(cams, V, ranges, t, tile_order);
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
@@ -793,12 +806,16 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     // permutation: nothing of it is written)
     if (tile_order && tile_order[blockIdx.x] >= gridDim.x) return;
     tile_ctx<TW, TH>(cams, V, ranges, t, tile_order);
+    // a set status word: nothing blended, NaN outputs and losses, no gradients
+    const bool failed = status_failed(rc);
+    if (failed) t.n = 0u;
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
     uint64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0;
     fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, nullptr, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st,
                            hits,
                        max_alpha, max_weight, n0, n1, n2, n3, n4);
+    if (failed) poison(st);
     const PixOut o = pix_outputs(st, t);
     PixBwd pb;
     pb.gC0 = pb.gC1 = pb.gC2 = pb.gA = pb.gD = pb.gN0 = pb.gN1 = pb.gN2 = pb.gS = pb.gMed = 0.f;
@@ -846,9 +863,12 @@ __global__ void k_fill_f32(float* __restrict__ p, float v, uint64_t n) {
         p[i] = v;
 }
 
-__global__ void k_prune_mask(int N, const float* __restrict__ max_alpha, float tau, uint8_t* __restrict__ mask) {
+// A set status word (statistics incomplete) prunes nothing.
+__global__ void k_prune_mask(int N, const float* __restrict__ max_alpha, float tau, const uint32_t* __restrict__ status,
+                             uint8_t* __restrict__ mask) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < N) mask[g] = max_alpha[g] < tau ? 1 : 0;
+    const bool failed = status != nullptr && *status != 0u;
+    if (g < N) mask[g] = (!failed && max_alpha[g] < tau) ? 1 : 0;
 }
 
 // Records per LDS batch of the backward (fewer than the workgroup size keeps
@@ -956,9 +976,9 @@ hipError_t launch_render_fwd(const sr_config& cfg, int N, int V, int total_tiles
                              float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
                              float* max_weight, unsigned long long* counts, float* median_depth,
                              uint32_t* median_contrib, const uint32_t* tile_order, uint32_t* tile_cost,
-                             hipStream_t s) {
+                             const uint32_t* status, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
-    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
     const int stats = hits ? (max_alpha ? kStats : kHits) : 0;
     int mode = counts ? kCount
                       : ((color ? kShade : 0) | stats | (color && median_depth ? kMedian : 0) |
@@ -982,9 +1002,9 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
                              const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
-                             float* grad_rec, const uint32_t* tile_order, hipStream_t s) {
+                             float* grad_rec, const uint32_t* tile_order, const uint32_t* status, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
-    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
 #define SR_TS(W, H)                                                                                            \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                 \
         bwd_launch<W, H>(total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,          \
@@ -1003,9 +1023,9 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
                                float* alpha, float* depth, float* normal, float* dist, float* T_final,
                                uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
                                float* tile_loss, float* grad_rec, const uint32_t* tile_order, uint32_t* tile_cost,
-                               hipStream_t s) {
+                               const uint32_t* status, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
-    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags};
+    RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
 #define SR_TS(W, H)                                                                                               \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                    \
         train_launch<W, H>(hits ? (max_alpha ? 2 : 1) : 0, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, \
@@ -1019,9 +1039,10 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, uint8_t* mask, hipStream_t s) {
+hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, const uint32_t* status, uint8_t* mask,
+                             hipStream_t s) {
     if (N == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prune_mask, dim3((N + 255) / 256), dim3(256), 0, s, N, max_alpha, tau, mask);
+    hipLaunchKernelGGL(k_prune_mask, dim3((N + 255) / 256), dim3(256), 0, s, N, max_alpha, tau, status, mask);
     return hipGetLastError();
 }
 

@@ -40,6 +40,18 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _device_index(device) -> int:
+    d = torch.device(device)
+    if d.type != "cuda":
+        raise ValueError(f"the surfel rasterizer runs on a GPU, not on {d}")
+    return d.index if d.index is not None else torch.cuda.current_device()
+
+
+def _ctx(t: torch.Tensor):
+    """The per-device default context for calls outside a Rasterizer."""
+    return _lib.default_context(_device_index(t.device)).ptr
+
+
 def make_config(sh_degree: int = 0, sh_stride: Optional[int] = None, tile=(16, 16), flags: int = 0,
                 alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, t_min=T_MIN) -> SrConfig:
     K = (sh_degree + 1) ** 2
@@ -104,29 +116,21 @@ class Params:
         return Params(f(scene.means), f(scene.scales), f(scene.quats), f(scene.opac), f(scene.sh))
 
 
-def group_instances(rect: torch.Tensor, tiles_touched: torch.Tensor, VN: int, tile) -> int:
-    """Instances sr_bin_and_sort will emit: per visible record, the
-    SR_TILE_GROUP x SR_TILE_GROUP tile groups its rectangle meets (syncs)."""
-    if VN == 0:
-        return 0
-    r = rect[: 4 * VN].view(VN, 4).to(torch.int64) & 0xFFFF
-    G = _lib.SR_TILE_GROUP
-    gx = (r[:, 1] // tile[0]) // G - (r[:, 0] // tile[0]) // G + 1
-    gy = (r[:, 3] // tile[1]) // G - (r[:, 2] // tile[1]) // G + 1
-    return int(torch.where(tiles_touched[:VN] > 0, gx * gy, torch.zeros_like(gx)).sum().item())
-
-
 class Rasterizer:
     """Persistent device buffers for one (N, views, tile shape, capacity).
 
     preprocess -> bin -> forward -> (loss) -> backward, each one C-ABI call
     on the current torch stream; no host synchronisation except
-    ``plan_capacity`` and ``status``.
+    ``plan_capacity``, ``status`` and ``check_capacity``.  The rasterizer
+    owns a context (sr_ctx): a binning that exceeds the capacity sets its
+    status word, the later compositing calls flag their outputs (NaN) and
+    ``check_capacity`` reports and clears it.
     """
 
     def __init__(self, N: int, views: ViewBatch, sh_degree: int, sh_stride: Optional[int] = None,
                  capacity: int = 0, device="cuda", shade: bool = True):
         self.N, self.views, self.device = int(N), views, device
+        self.ctx = _lib.Context(_device_index(device))
         self.cfg = make_config(sh_degree, sh_stride, views.tile)
         self.shade = shade
         V, P, T = views.V, views.P, views.T
@@ -166,22 +170,30 @@ class Rasterizer:
         self.ws = torch.zeros(max(ws, 1), dtype=torch.uint8, device=self.device)
         self.ws_bytes = ws
 
+    def count_instances(self, stream=None) -> int:
+        """Instances the binning of the current projection needs: a
+        count-only sr_bin_and_sort (one host sync)."""
+        call("sr_bin_and_sort", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key),
+             _ptr(self.ws), self.ws_bytes, 0, None, None, _ptr(self.ranges), _ptr(self.counters), _stream(stream))
+        return int(self.counters[1:2].cpu().numpy().view(np.uint32)[0])
+
     def plan_capacity(self, params: Params, slack: float = 1.05) -> int:
         """Projects once and sizes the instance buffers (one host sync)."""
         self.preprocess(params)
-        need = group_instances(self.rect, self.tiles_touched, self.views.V * self.N, self.views.tile)
+        need = self.count_instances()
         self.set_capacity(int(need * slack) + 1024)
         return need
 
     # -- steps ------------------------------------------------------------
     def preprocess(self, p: Params, stream=None):
-        call("sr_preprocess", ctypes.byref(self.cfg), self.N, _ptr(p.means), _ptr(p.scales), _ptr(p.quats),
+        call("sr_preprocess", self.ctx.ptr, ctypes.byref(self.cfg), self.N, _ptr(p.means), _ptr(p.scales), _ptr(p.quats),
              _ptr(p.opac), _ptr(p.sh), self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.geom),
              _ptr(self.app) if self.shade else None, _ptr(self.rect), _ptr(self.tiles_touched),
              _ptr(self.depth_key), _ptr(self.in_frustum), _stream(stream))
 
     def bin(self, keys64: Optional[torch.Tensor] = None, stream=None):
-        call("sr_bin_and_sort", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_bin_and_sort", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key),
              _ptr(self.ws), self.ws_bytes, self.capacity, _ptr(self.vals), _ptr(keys64), _ptr(self.ranges),
              _ptr(self.counters), _stream(stream))
@@ -209,7 +221,7 @@ class Rasterizer:
             self.costs_recorded = False
         order = None
         if self.costs_recorded:
-            call("sr_tile_order", T, _ptr(self.tile_cost), _ptr(self.order_ws), self.order_ws.numel(),
+            call("sr_tile_order", self.ctx.ptr, T, _ptr(self.tile_cost), _ptr(self.order_ws), self.order_ws.numel(),
                  _ptr(self.tile_order), _stream(stream))
             order = self.tile_order
         return order, self.tile_cost
@@ -232,7 +244,7 @@ class Rasterizer:
                 self.median_depth = torch.zeros(P, dtype=torch.float32, device=self.device)
                 self.median_contrib = torch.zeros(P, dtype=torch.int32, device=self.device)
             md, mc = self.median_depth, self.median_contrib
-        call("sr_render_forward", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_render_forward", self.ctx.ptr, ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.color), _ptr(self.alpha), _ptr(self.depth), _ptr(self.normal), _ptr(self.dist),
              _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw), _ptr(md), _ptr(mc),
@@ -261,7 +273,7 @@ class Rasterizer:
         (after a forward with median=True); ``schedule``: launched in the
         order of the last forward (heaviest tiles first)."""
         order = getattr(self, "last_order", None) if schedule else None
-        call("sr_backward_raster", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_backward_raster", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.alpha), _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib),
              _ptr(dC), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._median_contrib(dM)), _ptr(dM),
@@ -271,7 +283,7 @@ class Rasterizer:
         """Projection backward; ``densify`` = (grad_sum float32 [N], count
         int32 [N]) accumulates the density-control statistic."""
         dg, dc = (None, None) if densify is None else densify
-        call("sr_backward_project", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_backward_project", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.sh), _ptr(self.geom),
              _ptr(self.app), _ptr(self.tiles_touched), _ptr(self._grad_rec()), _ptr(grads.means),
              _ptr(grads.scales), _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _ptr(dg), _ptr(dc),
@@ -286,7 +298,7 @@ class Rasterizer:
     def backward_combined(self, p: Params, grads: Params, dC=None, dA=None, dD=None, dN=None, dS=None,
                           stream=None, dM=None):
         """The single-call form (sr_render_backward)."""
-        call("sr_render_backward", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_render_backward", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.opac), _ptr(p.sh),
              _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(self.alpha),
              _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(dC), _ptr(dA),
@@ -296,7 +308,7 @@ class Rasterizer:
 
     def loss(self, mask: torch.Tensor, target: Optional[torch.Tensor], gamma: float = 0.5, w_c: float = 1.0,
              dL_dalpha: Optional[torch.Tensor] = None, dL_dcolor: Optional[torch.Tensor] = None, stream=None):
-        call("sr_background_loss", self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.alpha),
+        call("sr_background_loss", self.ctx.ptr, self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.alpha),
              _ptr(mask), _ptr(self.color) if target is not None else None, _ptr(target), float(gamma), float(w_c),
              _ptr(self.loss_ws), self.loss_ws.numel(), _ptr(self.loss_out), _ptr(dL_dalpha), _ptr(dL_dcolor),
              _stream(stream))
@@ -313,7 +325,7 @@ class Rasterizer:
         if getattr(self, "reg_out", None) is None:
             self.reg_out = torch.zeros(2 * self.views.V + 1, dtype=torch.float32, device=self.device)
         med = None if dL_dmedian is None else self.median_depth
-        call("sr_regularizer_loss", self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.alpha),
+        call("sr_regularizer_loss", self.ctx.ptr, self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.alpha),
              _ptr(self.depth), _ptr(self.normal), _ptr(self.dist), _ptr(med), float(w_dist), float(w_normal),
              _ptr(self.loss_ws), self.loss_ws.numel(), _ptr(self.reg_out), _ptr(dL_dalpha), _ptr(dL_ddepth),
              _ptr(dL_dnormal), _ptr(dL_ddist), _ptr(dL_dmedian), _stream(stream))
@@ -330,7 +342,7 @@ class Rasterizer:
             self.ssim_ws = torch.zeros(max(need, 1), dtype=torch.uint8, device=self.device)
         if getattr(self, "ssim_out", None) is None:
             self.ssim_out = torch.zeros(2 * self.views.V + 1, dtype=torch.float32, device=self.device)
-        call("sr_ssim_loss", self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.color),
+        call("sr_ssim_loss", self.ctx.ptr, self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.color),
              _ptr(target), _ptr(mask), float(w_s), _ptr(self.ssim_ws), self.ssim_ws.numel(), _ptr(self.ssim_out),
              _ptr(dL_dcolor), _stream(stream))
         return self.ssim_out
@@ -347,7 +359,7 @@ class Rasterizer:
         h, ma, mw = _stats(stats)
         cfg = self._cfg(accumulate)
         order, cost = self._schedule(stream) if schedule else (None, None)
-        call("sr_train_step_raster", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_train_step_raster", self.ctx.ptr, ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask),
              _ptr(target), float(gamma), float(w_c), _ptr(self.color), _ptr(self.alpha), _ptr(self.depth),
              _ptr(self.normal), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma),
@@ -358,10 +370,10 @@ class Rasterizer:
         return self.loss_out
 
     def prune_stats(self, hits, max_alpha, max_weight, accumulate=False, stream=None, cull: bool = True):
-        """Occlusion statistics of the current binning (sr_prune_contrib);
+        """Occlusion statistics of the current binning (sr_prune_stats);
         ``cull`` lets each wave skip entries by their pixel rectangles."""
         cfg = self._cfg(accumulate)
-        call("sr_prune_contrib", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_prune_stats", self.ctx.ptr, ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.rect) if cull else None, _ptr(self.vals),
              _ptr(self.ranges), _ptr(hits), _ptr(max_alpha), _ptr(max_weight), _stream(stream))
 
@@ -370,7 +382,7 @@ class Rasterizer:
         ``waves`` also (wave steps, wave steps with a blend, pairs up to
         each pixel's last blend) - syncs."""
         out = torch.zeros(5, dtype=torch.int64, device=self.device)
-        call("sr_render_count", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_render_count", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(out),
              _stream(stream))
         c = out.cpu().numpy()
@@ -383,11 +395,16 @@ class Rasterizer:
         c = self.counters.cpu().numpy().view(np.uint32)
         return int(c[0]), int(c[1]), int(c[2]), int(c[3])
 
-    def check_capacity(self):
+    def check_capacity(self, stream=None):
+        """Reads and clears the context's status word (syncs); raises when a
+        binning since the last check exceeded the capacity (the compositing
+        calls after it flagged their outputs).  Returns the instance count
+        of the last binning."""
+        bits, need_max = self.ctx.read_status(_stream(stream), clear=True)
         vis, need, stored, st = self.status()
-        if st != 0:
+        if bits & _lib.SR_STATUS_CAPACITY:
             raise _lib.SurfelRasterError(_lib.SR_ERR_CAPACITY,
-                                         f"instance capacity {self.capacity} exceeded: {need} needed")
+                                         f"instance capacity {self.capacity} exceeded: {need_max} needed")
         return need
 
 
@@ -400,35 +417,70 @@ class PruneStats:
     mask: torch.Tensor          # uint8 [N] 1 = prune (max_alpha < tau)
 
 
-def prune_contrib(params: Params, cams: Sequence, views_per_chunk: int = 32, tau: float = ALPHA_MIN,
-                  tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None) -> PruneStats:
-    """Occlusion-aware pruning pass (Section 4.3) over every view: projection
-    without shading, binning and the compositing decisions, accumulating the
-    statistics over views (and over calls when ``stats`` is given), then the
-    mask.  Views are processed in chunks to bound the instance buffers."""
-    n = params.means.shape[0]
-    dev = params.means.device
+def _new_prune_stats(n: int, dev) -> PruneStats:
+    return PruneStats(torch.zeros(n, dtype=torch.int32, device=dev), torch.zeros(n, device=dev),
+                      torch.zeros(n, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
+                      torch.zeros(n, dtype=torch.uint8, device=dev))
+
+
+def _prune_pass(prim: int, means, scales, quats, opac, cams: Sequence, views_per_chunk: int, tau: float, tile,
+                slack: float, stats: Optional[PruneStats], check: bool, stream=None) -> PruneStats:
+    """sr_prune_plan (capacity, one host sync) then sr_prune_contrib (the
+    whole pass on the device) over every view, in chunks of views."""
+    n = int(means.shape[0])
+    dev = means.device
+    accumulate = stats is not None
     if stats is None:
-        stats = PruneStats(torch.zeros(n, dtype=torch.int32, device=dev), torch.zeros(n, device=dev),
-                           torch.zeros(n, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
-                           torch.zeros(n, dtype=torch.uint8, device=dev))
-    for v0 in range(0, len(cams), views_per_chunk):
-        views = ViewBatch(cams[v0:v0 + views_per_chunk], tile=tile, device=dev)
-        rast = Rasterizer(n, views, 0, shade=False, device=dev)
-        rast.plan_capacity(params, slack=slack)
-        rast.preprocess(params)
-        rast.bin()
-        rast.check_capacity()
-        rast.prune_stats(stats.hits, stats.max_alpha, stats.max_weight, accumulate=True)
-        torch.bitwise_or(stats.in_frustum, rast.in_frustum[:n], out=stats.in_frustum)
-        del rast
-    stats.mask = prune_mask(stats.max_alpha, tau)
+        stats = _new_prune_stats(n, dev)
+    views = ViewBatch(cams, tile=tile, device=dev)
+    ctx = _lib.Context(_device_index(dev))
+    cfg = make_config(0, None, views.tile, flags=_lib.SR_FLAG_ACCUMULATE if accumulate else 0)
+    V = views.V
+    vpc = max(1, min(int(views_per_chunk), max(V, 1)))
+    args = (n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac), V, views.host_ptr, _ptr(views.dev), vpc)
+
+    def ws_bytes(cap):
+        b = ctypes.c_size_t(0)
+        call("sr_prune_workspace_size", ctypes.byref(cfg), prim, n, V, views.host_ptr if V else None, vpc, cap,
+             ctypes.byref(b))
+        return b.value
+
+    b0 = ws_bytes(0)
+    ws = torch.zeros(max(b0, 1), dtype=torch.uint8, device=dev)
+    cap = ctypes.c_uint32(0)
+    call("sr_prune_plan", ctx.ptr, ctypes.byref(cfg), prim, *args, _ptr(ws), b0, ctypes.byref(cap), _stream(stream))
+    capacity = int(cap.value * slack) + 1024
+    b1 = ws_bytes(capacity)
+    del ws
+    ws = torch.empty(max(b1, 1), dtype=torch.uint8, device=dev)
+    call("sr_prune_contrib", ctx.ptr, ctypes.byref(cfg), prim, *args, float(tau), capacity, _ptr(ws), b1,
+         _ptr(stats.hits), _ptr(stats.max_alpha), _ptr(stats.max_weight), _ptr(stats.in_frustum), _ptr(stats.mask),
+         _stream(stream))
+    if check:
+        bits, need = ctx.read_status(_stream(stream), clear=True)
+        if bits & _lib.SR_STATUS_CAPACITY:
+            raise _lib.SurfelRasterError(_lib.SR_ERR_CAPACITY, f"pruning pass: {need} instances needed, "
+                                                               f"capacity {capacity}")
     return stats
+
+
+def prune_contrib(params: Params, cams: Sequence, views_per_chunk: int = 32, tau: float = ALPHA_MIN,
+                  tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None,
+                  check: bool = True) -> PruneStats:
+    """Occlusion-aware pruning pass (Section 4.3) over every view
+    (sr_prune_contrib): projection without shading, binning and the
+    compositing decisions, accumulating the statistics over views (and over
+    calls when ``stats`` is given), then the mask.  Views are processed in
+    chunks to bound the per-view records; the capacity is planned by
+    sr_prune_plan.  ``check`` reads the status word at the end (syncs)."""
+    return _prune_pass(_lib.SR_PRIM_SURFEL, params.means, params.scales, params.quats, params.opac, cams,
+                       views_per_chunk, tau, tile, slack, stats, check)
 
 
 def prune_mask(max_alpha: torch.Tensor, tau: float = ALPHA_MIN, stream=None) -> torch.Tensor:
     out = torch.empty(max_alpha.numel(), dtype=torch.uint8, device=max_alpha.device)
-    call("sr_prune_mask", max_alpha.numel(), _ptr(max_alpha), float(tau), _ptr(out), _stream(stream))
+    call("sr_prune_mask", _ctx(max_alpha), max_alpha.numel(), _ptr(max_alpha), float(tau), _ptr(out),
+         _stream(stream))
     return out
 
 
@@ -444,7 +496,7 @@ class SurfelRasterize(torch.autograd.Function):
     Rasterizer."""
 
     @staticmethod
-    def forward(ctx, means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True, median: bool = False):
+    def forward(ctx, means, scales, quats, opac, sh, rast: Rasterizer, check: bool = False, median: bool = False):
         p = Params(means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                    opac.detach().contiguous(), sh.detach().contiguous())
         rast.preprocess(p)
@@ -470,9 +522,11 @@ class SurfelRasterize(torch.autograd.Function):
         return g.means, g.scales, g.quats, g.opac, g.sh, None, None, None
 
 
-def rasterize(means, scales, quats, opac, sh, rast: Rasterizer, check: bool = True, median: bool = False):
+def rasterize(means, scales, quats, opac, sh, rast: Rasterizer, check: bool = False, median: bool = False):
     """Differentiable rasterization; ``median`` adds the median depth as a
-    sixth output."""
+    sixth output.  ``check`` reads the capacity status after the binning
+    (a host sync, so not inside a captured graph); without it a binning
+    over capacity shows as NaN outputs and in ``rast.check_capacity()``."""
     return SurfelRasterize.apply(means, scales, quats, opac, sh, rast, check, median)
 
 
@@ -487,7 +541,8 @@ class BackgroundLoss(torch.autograd.Function):
         loss = torch.zeros(2 * V + 1, dtype=torch.float32, device=alpha.device)
         dA = torch.empty_like(alpha)
         dC = torch.empty_like(color) if target is not None else None
-        call("sr_background_loss", V, views.host_ptr, _ptr(views.dev), _ptr(alpha.contiguous()), _ptr(mask),
+        call("sr_background_loss", _ctx(alpha), V, views.host_ptr, _ptr(views.dev), _ptr(alpha.contiguous()),
+             _ptr(mask),
              _ptr(color.contiguous()) if target is not None else None, _ptr(target), float(gamma), float(w_c),
              _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dC), _stream())
         ctx.save_for_backward(dA, dC if dC is not None else torch.zeros(0, device=alpha.device))
@@ -518,7 +573,7 @@ class RegularizerLoss(torch.autograd.Function):
         dD, dN, dS = torch.empty_like(depth), torch.empty_like(normal), torch.empty_like(dist)
         med = None if median is None else median.contiguous()
         dM = None if median is None else torch.empty_like(med)
-        call("sr_regularizer_loss", V, views.host_ptr, _ptr(views.dev), _ptr(alpha.contiguous()),
+        call("sr_regularizer_loss", _ctx(alpha), V, views.host_ptr, _ptr(views.dev), _ptr(alpha.contiguous()),
              _ptr(depth.contiguous()), _ptr(normal.contiguous()), _ptr(dist.contiguous()), _ptr(med),
              float(w_dist), float(w_normal), _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN),
              _ptr(dS), _ptr(dM), _stream())
@@ -544,7 +599,8 @@ class SsimLoss(torch.autograd.Function):
         V = views.V
         out = torch.zeros(2 * V + 1, dtype=torch.float32, device=color.device)
         dC = torch.zeros_like(color)
-        call("sr_ssim_loss", V, views.host_ptr, _ptr(views.dev), _ptr(color.contiguous()), _ptr(target),
+        call("sr_ssim_loss", _ctx(color), V, views.host_ptr, _ptr(views.dev), _ptr(color.contiguous()),
+             _ptr(target),
              _ptr(mask), float(w_s), _ptr(ws), ws.numel(), _ptr(out), _ptr(dC), _stream())
         ctx.save_for_backward(dC)
         per_view = out[: 2 * V]
@@ -578,7 +634,7 @@ def compact_surfels(prune: torch.Tensor, arrays: Sequence[torch.Tensor], opac: O
     kept = torch.zeros(1, dtype=torch.int32, device=dev)
     pr = prune.contiguous()                      # held across the call
     op = None if opac is None else opac.contiguous()
-    call("sr_compact_surfels", N, _ptr(pr), _ptr(op), float(min_opacity), len(srcs),
+    call("sr_compact_surfels", _ctx(prune), N, _ptr(pr), _ptr(op), float(min_opacity), len(srcs),
          ctypes.cast(sp, ctypes.c_void_p), ctypes.cast(dp, ctypes.c_void_p), ctypes.cast(widths, ctypes.c_void_p),
          _ptr(ws), ws.numel(), _ptr(kept), _stream(stream))
     k = int(kept.item())
@@ -592,6 +648,7 @@ class Pruner3D:
 
     def __init__(self, N: int, views: ViewBatch, capacity: int = 0, device="cuda"):
         self.N, self.views, self.device = int(N), views, device
+        self.ctx = _lib.Context(_device_index(device))
         self.cfg = make_config(0, None, views.tile)
         VN = views.V * self.N
         z = lambda n, dt: torch.zeros(max(int(n), 1), dtype=dt, device=device)
@@ -615,19 +672,24 @@ class Pruner3D:
         self.ws = torch.zeros(max(self.ws_bytes, 1), dtype=torch.uint8, device=self.device)
 
     def preprocess(self, means, scales, quats, opac, stream=None):
-        call("sr_preprocess_3d", ctypes.byref(self.cfg), self.N, _ptr(means), _ptr(scales), _ptr(quats),
+        call("sr_preprocess_3d", self.ctx.ptr, ctypes.byref(self.cfg), self.N, _ptr(means), _ptr(scales), _ptr(quats),
              _ptr(opac), self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.geom3),
              _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key), _ptr(self.in_frustum),
              _stream(stream))
 
     def plan_capacity(self, means, scales, quats, opac, slack: float = 1.05) -> int:
+        """Projects and counts the instances (count-only binning, one host
+        sync), then sizes the instance buffers."""
         self.preprocess(means, scales, quats, opac)
-        need = group_instances(self.rect, self.tiles_touched, self.views.V * self.N, self.views.tile)
+        call("sr_bin_and_sort", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+             _ptr(self.views.dev), _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key),
+             _ptr(self.ws), self.ws_bytes, 0, None, None, _ptr(self.ranges), _ptr(self.counters), _stream())
+        need = int(self.counters[1:2].cpu().numpy().view(np.uint32)[0])
         self.set_capacity(int(need * slack) + 1024)
         return need
 
     def bin(self, keys64: Optional[torch.Tensor] = None, stream=None):
-        call("sr_bin_and_sort", ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_bin_and_sort", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.rect), _ptr(self.tiles_touched), _ptr(self.depth_key),
              _ptr(self.ws), self.ws_bytes, self.capacity, _ptr(self.vals), _ptr(keys64), _ptr(self.ranges),
              _ptr(self.counters), _stream(stream))
@@ -637,7 +699,7 @@ class Pruner3D:
         if accumulate:
             cfg = SrConfig.from_buffer_copy(self.cfg)
             cfg.flags |= _lib.SR_FLAG_ACCUMULATE
-        call("sr_prune_contrib_3d", ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
+        call("sr_prune_stats_3d", self.ctx.ptr, ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(self.geom3), _ptr(self.vals), _ptr(self.ranges), _ptr(hits),
              _ptr(max_alpha), _ptr(max_weight), _stream(stream))
 
@@ -653,25 +715,10 @@ class Pruner3D:
 
 
 def prune_contrib_3d(means, scales, quats, opac, cams: Sequence, views_per_chunk: int = 32, tau: float = ALPHA_MIN,
-                     tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None) -> PruneStats:
-    """The occlusion-pruning pass for 3D Gaussians over every view (chunks of
-    views bound the instance buffers), statistics accumulated, then the mask."""
-    n = means.shape[0]
-    dev = means.device
-    if stats is None:
-        stats = PruneStats(torch.zeros(n, dtype=torch.int32, device=dev), torch.zeros(n, device=dev),
-                           torch.zeros(n, device=dev), torch.zeros(n, dtype=torch.uint8, device=dev),
-                           torch.zeros(n, dtype=torch.uint8, device=dev))
-    for v0 in range(0, len(cams), views_per_chunk):
-        views = ViewBatch(cams[v0:v0 + views_per_chunk], tile=tile, device=dev)
-        pr = Pruner3D(n, views, device=dev)
-        pr.plan_capacity(means, scales, quats, opac, slack=slack)
-        pr.bin()
-        vis, need, stored, status = pr.status()
-        if status != 0:
-            raise RuntimeError(f"instance capacity exceeded: need {need}, have {pr.capacity}")
-        pr.prune_stats(stats.hits, stats.max_alpha, stats.max_weight, accumulate=True)
-        torch.bitwise_or(stats.in_frustum, pr.in_frustum[:n], out=stats.in_frustum)
-        del pr
-    stats.mask = prune_mask(stats.max_alpha, tau)
-    return stats
+                     tile=(16, 16), slack: float = 1.02, stats: Optional[PruneStats] = None,
+                     check: bool = True) -> PruneStats:
+    """The occlusion-pruning pass for 3D Gaussians over every view
+    (sr_prune_contrib with SR_PRIM_GAUSS3D; chunks of views bound the
+    per-view records), statistics accumulated, then the mask."""
+    return _prune_pass(_lib.SR_PRIM_GAUSS3D, means, scales, quats, opac, cams, views_per_chunk, tau, tile, slack,
+                       stats, check)

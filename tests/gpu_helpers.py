@@ -6,7 +6,7 @@ import numpy as np
 import torch
 
 import oracle
-from oracle.render import Params64, render_pixels
+from oracle.render import TIE_KINDS, Params64, render_alternatives, render_pixels
 from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch
 from tests.grouping import expand_to_tile_lists, grouped_from_rectangles, instance_count
 
@@ -115,36 +115,154 @@ def crop_pixels(x0, y0, w, h):
     return np.stack([ii.ravel(), jj.ravel()], axis=1)
 
 
-def compare_forward(gpu_view, res, pix, rast=None, v=None, tol=FWD_TOL):
-    """Max abs errors on unflagged pixels; returns (errors dict, flagged fraction)."""
+def _gpu_last_gid(gpu_view, pix, rast, v):
+    """Surfel id of the last blended entry of each pixel (-1 if none), read
+    from the GPU's n_contrib and its sorted lists."""
     i, j = pix[:, 0], pix[:, 1]
-    f_ct = res["flag_cut"] | res["flag_term"]
-    f_geo = f_ct | res["flag_branch"]
+    views = rast.views
+    T0 = int(views.host[v].tile_offset)
+    tx = int(views.host[v].tiles_x)
+    tw, th = views.tile
+    tile = T0 + (j // th) * tx + (i // tw)
+    rg = rast.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    vals = (rast.vals.cpu().numpy().view(np.uint32) & ID_MASK).astype(np.int64)
+    nc = gpu_view["n_contrib"][j, i].astype(np.int64)
+    return np.where(nc > 0, vals[np.minimum(rg[tile, 0] + np.maximum(nc - 1, 0), vals.size - 1)], -1)
+
+
+def _gpu_values(gpu_view, pix):
+    i, j = pix[:, 0], pix[:, 1]
+    return {"color": gpu_view["color"][:, j, i].T, "alpha": gpu_view["alpha"][j, i],
+            "depth": gpu_view["depth"][j, i], "normal": gpu_view["normal"][:, j, i].T,
+            "dist": gpu_view["dist"][j, i]}
+
+
+def _row_err(g, ref, rows_g, rows_r, names=("color", "alpha", "depth", "normal", "dist")):
+    e = np.zeros(len(rows_g))
+    for k in names:
+        d = np.abs(np.asarray(g[k])[rows_g] - np.asarray(ref[k])[rows_r])
+        e = np.maximum(e, d.reshape(len(rows_g), -1).max(axis=1))
+    return e
+
+
+def compare_forward(gpu_view, res, pix, rast=None, v=None, tol=FWD_TOL, oracle_ctx=None):
+    """Forward parity with the tie protocol.
+
+    Pixels whose list holds no tie entry must match the oracle within
+    ``tol`` on every output, and (with ``rast``) blend the same last surfel.
+    A pixel with a tie entry (a value within float32 reach of the cutoff,
+    the termination test or the surface/low-pass choice) must match one of
+    the oracle's correct results (``oracle.render.render_alternatives``:
+    each subset of its tie entries taken the other way), when
+    ``oracle_ctx`` = (P64, cam, geom, rp) is given; without it such pixels
+    are only counted.
+
+    Returns (max abs errors of the pixels without a tie entry, tie-pixel
+    fraction, report) with report: ``choice`` {row: flips} of the tie pixels
+    whose match took some tie the other way (feed it as ``flips`` to the
+    oracle's gradient pass), ``entries`` [(kind, distance, taken other
+    way)] for every tie entry of a resolved pixel, ``unresolved`` rows."""
+    f_geo = res["flag_cut"] | res["flag_term"] | res["flag_branch"]
+    ok = ~f_geo
+    g = _gpu_values(gpu_view, pix)
     errs = {}
-    checks = (("color", lambda d: d["color"][:, j, i].T, f_ct), ("alpha", lambda d: d["alpha"][j, i], f_ct),
-              ("depth", lambda d: d["depth"][j, i], f_geo), ("normal", lambda d: d["normal"][:, j, i].T, f_ct),
-              ("dist", lambda d: d["dist"][j, i], f_geo))
-    for name, get, flag in checks:
-        a = get(gpu_view)
-        b = res[name]
-        ok = ~flag
-        e = np.abs(a[ok] - b[ok])
+    for name in ("color", "alpha", "depth", "normal", "dist"):
+        e = np.abs(np.asarray(g[name])[ok] - np.asarray(res[name])[ok])
         errs[name] = float(e.max()) if e.size else 0.0
     for name, e in errs.items():
         assert e <= tol, f"{name}: max abs error {e:.3e} > {tol}"
-    if rast is not None:
-        # the last blended surfel of every unflagged pixel
-        views = rast.views
-        W, H = views.sizes[v]
-        T0 = int(rast.views.host[v].tile_offset)
-        tx = int(rast.views.host[v].tiles_x)
-        tw, th = views.tile
-        tile = T0 + (j // th) * tx + (i // tw)
-        rg = rast.ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
-        vals = (rast.vals.cpu().numpy().view(np.uint32) & ID_MASK).astype(np.int64)
-        nc = gpu_view["n_contrib"][j, i].astype(np.int64)
-        last = np.where(nc > 0, vals[np.minimum(rg[tile, 0] + np.maximum(nc - 1, 0), vals.size - 1)], -1)
-        ok = ~f_ct
-        mism = (last.astype(np.int64) != res["last_gid"]) & ok
+    last = _gpu_last_gid(gpu_view, pix, rast, v) if rast is not None else None
+    if last is not None:
+        mism = (last != res["last_gid"]) & ok
         assert not mism.any(), f"{mism.sum()} pixels with a different last blended surfel"
-    return errs, float(f_geo.mean())
+    report = {"choice": {}, "entries": [], "unresolved": []}
+    rows = np.nonzero(f_geo)[0]
+    if rows.size == 0 or oracle_ctx is None:
+        report["unresolved"] = rows.tolist() if oracle_ctx is None else []
+        return errs, float(f_geo.mean()), report
+    P64, cam, geom, rp = oracle_ctx
+    alts, ares, unres = render_alternatives(P64, cam, geom, pix, res["tie_list"], rp)
+    report["unresolved"] = unres
+    tl, td = res["tie_list"], res["tie_dist"]
+    for r in rows:
+        if r in unres:
+            continue
+        cands = [()] + [f for (rr, f) in alts if rr == r]
+        idx = [None] + [k for k, (rr, f) in enumerate(alts) if rr == r]
+        errs_c, lasts = [], []
+        for c in idx:
+            if c is None:
+                errs_c.append(float(_row_err(g, res, [r], [r])[0]))
+                lasts.append(int(res["last_gid"][r]))
+            else:
+                errs_c.append(float(_row_err(g, ares, [r], [c])[0]))
+                lasts.append(int(ares["last_gid"][c]))
+        good = [k for k in range(len(cands)) if errs_c[k] <= tol and (last is None or lasts[k] == last[r])]
+        assert good, (f"tie pixel {pix[r].tolist()} matches none of its {len(cands)} correct results: "
+                      f"errors {errs_c}, last surfel gpu {None if last is None else last[r]} vs {lasts}")
+        best = min(good, key=lambda k: errs_c[k])
+        if cands[best]:
+            report["choice"][int(r)] = list(cands[best])
+        taken = set(cands[best])
+        for (rr, gid, kind), d in zip(tl[tl[:, 0] == r], td[tl[:, 0] == r]):
+            if kind <= 2:
+                report["entries"].append((TIE_KINDS[kind], float(d), (int(gid), TIE_KINDS[kind]) in taken))
+    return errs, float(f_geo.mean()), report
+
+
+GRAD_RTOL = 1e-3
+
+
+def compare_grads(g, gref, excl=(), names=("means", "scales", "quats", "opac", "sh"), rtol=GRAD_RTOL):
+    """The gradient bar: per tensor ||g - g_ref||_inf <= rtol ||g_ref||_inf,
+    and |g - g_ref| <= rtol |g_ref| for every element with |g_ref| >=
+    1e-2 ||g_ref||_inf; rows (surfels) in ``excl`` are left out."""
+    report = {}
+    for name, a, b in zip(names, g, gref):
+        keep = np.ones(a.shape[0], bool)
+        keep[np.asarray(excl, np.int64)] = False
+        a, b = a[keep].reshape(-1), b[keep].reshape(-1)
+        scale = np.abs(b).max()
+        err = np.abs(a - b).max()
+        big = np.abs(b) >= 1e-2 * scale
+        rel = (np.abs(a - b)[big] / np.abs(b)[big]).max() if big.any() else 0.0
+        report[name] = (float(err / max(scale, 1e-30)), float(rel))
+    print("gradient errors (inf-norm relative, elementwise relative):", report, flush=True)
+    for name, (e, r) in report.items():
+        assert e <= rtol, f"{name}: inf-norm relative error {e:.2e}"
+        assert r <= rtol, f"{name}: elementwise relative error {r:.2e}"
+    return report
+
+
+def clamp_tie_ids(res):
+    """Surfels with an entry at the alpha clamp (within float32 reach): the
+    value is continuous there but its derivative in the opacity is not."""
+    tl = res["tie_list"]
+    return np.unique(tl[tl[:, 2] == TIE_KINDS.index("clamp"), 1]) if len(tl) else np.zeros(0, np.int64)
+
+
+def masked_loss_fn(mask_v, target_v, pix, HW, V, gamma, w_c):
+    """The per-pixel masked L1 + background loss (Eq. 1, Eq. 2) of the
+    pixels ``pix`` of one view, as a loss_fn for render_pixels: its sum over
+    the chunks is (1/V) (w_c L1_v + gamma L_b,v) restricted to ``pix``."""
+    m = torch.tensor(mask_v[pix[:, 1], pix[:, 0]], dtype=torch.float64)
+    tgt = torch.tensor(np.asarray(target_v)[:, pix[:, 1], pix[:, 0]].T, dtype=torch.float64)
+
+    def lf(out, rows):
+        r = torch.as_tensor(rows)
+        mm = m[r]
+        l1 = (mm[:, None] * out["color"] - mm[:, None] * tgt[r]).abs().sum() / (3 * HW)
+        lb = (out["alpha"] * (1 - mm)).sum() / HW
+        return (w_c * l1 + gamma * lb) / V
+    return lf
+
+
+def masked_terms(res, mask_v, target_v, pix, HW):
+    """(L1_v, L_b,v) of Eq. 2 / Eq. 1 summed over the pixels ``pix`` from the
+    oracle's outputs (the view's terms when the rest of the view contributes
+    nothing)."""
+    m = mask_v[pix[:, 1], pix[:, 0]].astype(np.float64)
+    tgt = np.asarray(target_v, np.float64)[:, pix[:, 1], pix[:, 0]].T
+    l1 = float(np.abs(m[:, None] * res["color"] - m[:, None] * tgt).sum() / (3 * HW))
+    lb = float((res["alpha"] * (1 - m)).sum() / HW)
+    return l1, lb

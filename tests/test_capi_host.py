@@ -66,50 +66,50 @@ def test_argument_errors_before_launch(lib):
     from paper_2501_08174_amd._lib import SrConfig
     l = lib.lib()
     cfg = SrConfig(12, 12, 0, 1, 1 / 255, 0.99, 1e-4, 0)
-    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+    assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_UNSUPPORTED
     assert l.sr_tile_supported(16, 16) == 1 and l.sr_tile_supported(8, 8) == 1 and l.sr_tile_supported(7, 3) == 0
     cfg = SrConfig(16, 16, 4, 25, 1 / 255, 0.99, 1e-4, 0)
-    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+    assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_UNSUPPORTED
     cfg = SrConfig(16, 16, 3, 9, 1 / 255, 0.99, 1e-4, 0)
-    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+    assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_ARG
     cfg = SrConfig(16, 16, 0, 1, 0.5, 0.4, 1e-4, 0)
-    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+    assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_ARG
     cfg = SrConfig(16, 16, 0, 1, 1 / 255, 0.99, 1e-4, 0)
-    assert l.sr_preprocess(ctypes.byref(cfg), -1, None, None, None, None, None, 0, None, None, None, None, None,
+    assert l.sr_preprocess(None, ctypes.byref(cfg), -1, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_ARG
     # N = 0 and V = 0 are valid no-ops
-    assert l.sr_preprocess(ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+    assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_OK
     n = ctypes.c_size_t()
     assert l.sr_bin_workspace_size(1000, 4, 12345, ctypes.byref(n)) == lib.SR_OK and n.value > 0
     assert l.sr_bin_workspace_size(-5, 4, 12345, ctypes.byref(n)) == lib.SR_ERR_ARG
     # workspace too small is an argument error
     counters = ctypes.c_void_p(8)
-    assert l.sr_bin_and_sort(ctypes.byref(cfg), 10, 0, None, None, None, None, None, None, 0, 100, None, None,
+    assert l.sr_bin_and_sort(None, ctypes.byref(cfg), 10, 0, None, None, None, None, None, None, 0, 100, None, None,
                              None, counters, None) == lib.SR_ERR_ARG
     # binned surfel ids hold 24 bits: larger N is rejected before anything runs
-    assert l.sr_bin_and_sort(ctypes.byref(cfg), 1 << 24, 0, None, None, None, None, None, None, 0, 100, None, None,
+    assert l.sr_bin_and_sort(None, ctypes.byref(cfg), 1 << 24, 0, None, None, None, None, None, None, 0, 100, None, None,
                              None, counters, None) == lib.SR_ERR_UNSUPPORTED
     assert lib.SR_TILE_GROUP == 4 and lib.SR_INST_ID_BITS == 24
     # the median depth and its entry index go together, and its gradient needs the index
     md = ctypes.c_void_p(256)
-    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, None, None, None,
+    assert l.sr_render_forward(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, None, None, None,
                                None) == lib.SR_ERR_ARG
-    assert l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, md, None, None,
+    assert l.sr_render_forward(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, md, None, None,
                                None) == lib.SR_OK
-    assert l.sr_backward_raster(ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), None, md, None, None,
+    assert l.sr_backward_raster(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), None, md, None, None,
                                 None) == lib.SR_ERR_ARG
-    assert l.sr_render_backward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 19), None, md, None,
+    assert l.sr_render_backward(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 19), None, md, None,
                                 *([None] * 6)) == lib.SR_ERR_ARG
     # statistics: none, hits alone, or hits with both maxima
     h = ctypes.c_void_p(512)
-    fwd = lambda hits, ma, mw: l.sr_render_forward(ctypes.byref(cfg), 0, 0, None, None, *([None] * 11), hits, ma,
+    fwd = lambda hits, ma, mw: l.sr_render_forward(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 11), hits, ma,
                                                    mw, None, None, None, None, None)
-    step = lambda hits, ma, mw: l.sr_train_step_raster(ctypes.byref(cfg), 0, 0, None, None, None, None, None, None,
+    step = lambda hits, ma, mw: l.sr_train_step_raster(None, ctypes.byref(cfg), 0, 0, None, None, None, None, None, None,
                                                        None, None, 0.5, 1.0, *([None] * 7), hits, ma, mw, None,
                                                        None, None, None, None, None)
     for f in (fwd, step):
@@ -126,9 +126,9 @@ def test_regularizer_loss_arguments(lib):
     empty views, a small workspace and a median map without its gradient
     buffer are argument errors (host checks only)."""
     l = lib.lib()
-    assert l.sr_regularizer_loss(0, None, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None,
+    assert l.sr_regularizer_loss(None, 0, None, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None,
                                  None, None, None, None) == lib.SR_OK
-    assert l.sr_regularizer_loss(-1, None, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None,
+    assert l.sr_regularizer_loss(None, -1, None, None, None, None, None, None, None, 0.0, 0.0, None, 0, None, None, None,
                                  None, None, None, None) == lib.SR_ERR_ARG
     cams = (lib.SrCamera * 2)()
     for c, (w, h) in zip(cams, [(5, 4), (3, 3)]):
@@ -139,16 +139,16 @@ def test_regularizer_loss_arguments(lib):
                                             ws, p, p, p, p, p, dmed, None)
     n = ctypes.c_size_t()
     assert l.sr_loss_workspace_size(2, ctypes.cast(cams, ctypes.c_void_p), ctypes.byref(n)) == lib.SR_OK
-    assert l.sr_regularizer_loss(*args(n.value - 1)) == lib.SR_ERR_ARG
-    assert l.sr_regularizer_loss(2, ctypes.cast(cams, ctypes.c_void_p), p, None, p, p, p, None, 1.0, 1.0, p, n.value,
+    assert l.sr_regularizer_loss(None, *args(n.value - 1)) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(None, 2, ctypes.cast(cams, ctypes.c_void_p), p, None, p, p, p, None, 1.0, 1.0, p, n.value,
                                  p, p, p, p, p, None, None) == lib.SR_ERR_ARG
-    assert l.sr_regularizer_loss(*args(n.value, med=p)) == lib.SR_ERR_ARG
-    assert l.sr_regularizer_loss(*args(n.value, dmed=p)) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(None, *args(n.value, med=p)) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(None, *args(n.value, dmed=p)) == lib.SR_ERR_ARG
     cams[1].pix_offset = 19
-    assert l.sr_regularizer_loss(*args(n.value)) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(None, *args(n.value)) == lib.SR_ERR_ARG
     cams[1].pix_offset = 20
     cams[0].fx = 0.0
-    assert l.sr_regularizer_loss(*args(n.value)) == lib.SR_ERR_ARG
+    assert l.sr_regularizer_loss(None, *args(n.value)) == lib.SR_ERR_ARG
 
 
 def test_ssim_arguments(lib):
@@ -166,11 +166,11 @@ def test_ssim_arguments(lib):
     assert l.sr_ssim_workspace_size(2, cp, 1, ctypes.byref(n)) == lib.SR_OK
     assert n.value >= m + 9 * 366 * 4
     p = ctypes.c_void_p(256)
-    assert l.sr_ssim_loss(2, cp, p, p, p, p, 0.2, p, n.value - 1, p, p, None) == lib.SR_ERR_ARG
-    assert l.sr_ssim_loss(2, cp, p, None, p, p, 0.2, p, n.value, p, p, None) == lib.SR_ERR_ARG
+    assert l.sr_ssim_loss(None, 2, cp, p, p, p, p, 0.2, p, n.value - 1, p, p, None) == lib.SR_ERR_ARG
+    assert l.sr_ssim_loss(None, 2, cp, p, None, p, p, 0.2, p, n.value, p, p, None) == lib.SR_ERR_ARG
     cams[1].pix_offset = 361
-    assert l.sr_ssim_loss(2, cp, p, p, p, p, 0.2, p, n.value, p, p, None) == lib.SR_ERR_ARG
-    assert l.sr_ssim_loss(-1, None, None, None, None, None, 0.2, None, 0, None, None, None) == lib.SR_ERR_ARG
+    assert l.sr_ssim_loss(None, 2, cp, p, p, p, p, 0.2, p, n.value, p, p, None) == lib.SR_ERR_ARG
+    assert l.sr_ssim_loss(None, -1, None, None, None, None, None, 0.2, None, 0, None, None, None) == lib.SR_ERR_ARG
 
 
 def test_compact_arguments(lib):
@@ -185,16 +185,16 @@ def test_compact_arguments(lib):
     w = (ctypes.c_int32 * 2)(3, 2)
     cast = lambda a: ctypes.cast(a, ctypes.c_void_p)
     # dst aliases src for the second array
-    assert l.sr_compact_surfels(10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
+    assert l.sr_compact_surfels(None, 10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
         lib.SR_ERR_ARG
-    assert l.sr_compact_surfels(10, p, None, 0.0, 9, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
+    assert l.sr_compact_surfels(None, 10, p, None, 0.0, 9, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
         lib.SR_ERR_ARG
     w[0] = 0
     dst[1] = 2048
-    assert l.sr_compact_surfels(10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
+    assert l.sr_compact_surfels(None, 10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, n.value, p, None) == \
         lib.SR_ERR_ARG
     w[0] = 3
-    assert l.sr_compact_surfels(10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, 0, p, None) == \
+    assert l.sr_compact_surfels(None, 10, p, None, 0.0, 2, cast(src), cast(dst), cast(w), p, 0, p, None) == \
         lib.SR_ERR_ARG
 
 
@@ -206,8 +206,62 @@ def test_tile_order_arguments(lib):
     assert l.sr_tile_order_workspace_size(-1, ctypes.byref(n)) == lib.SR_ERR_ARG
     assert l.sr_tile_order_workspace_size(65788, ctypes.byref(n)) == lib.SR_OK and n.value >= 4 * 4 * 65788
     p = ctypes.c_void_p(256)
-    assert l.sr_tile_order(0, None, None, 0, None, None) == lib.SR_OK
-    assert l.sr_tile_order(-3, p, p, n.value, p, None) == lib.SR_ERR_ARG
-    assert l.sr_tile_order(65788, p, p, n.value - 1, p, None) == lib.SR_ERR_ARG
-    assert l.sr_tile_order(65788, None, p, n.value, p, None) == lib.SR_ERR_ARG
-    assert l.sr_tile_order(65788, p, p, n.value, None, None) == lib.SR_ERR_ARG
+    assert l.sr_tile_order(None, 0, None, None, 0, None, None) == lib.SR_OK
+    assert l.sr_tile_order(None, -3, p, p, n.value, p, None) == lib.SR_ERR_ARG
+    assert l.sr_tile_order(None, 65788, p, p, n.value - 1, p, None) == lib.SR_ERR_ARG
+    assert l.sr_tile_order(None, 65788, None, p, n.value, p, None) == lib.SR_ERR_ARG
+    assert l.sr_tile_order(None, 65788, p, p, n.value, None, None) == lib.SR_ERR_ARG
+
+
+def test_context_status_and_workspace_arguments(lib):
+    """The context calls, the step workspace and the whole pruning pass:
+    host checks only (no device is touched; without a GPU sr_create finds
+    no device)."""
+    l = lib.lib()
+    assert lib.SR_ERR_STATE == -5 and lib.SR_STATUS_CAPACITY == 1
+    assert l.sr_destroy(None) == lib.SR_OK
+    assert l.sr_create(None, 0) == lib.SR_ERR_ARG
+    h = ctypes.c_void_p()
+    assert l.sr_create(ctypes.byref(h), -1) == lib.SR_ERR_ARG
+    assert l.sr_read_status(None, None, 1, None, None) == lib.SR_ERR_ARG
+    assert l.sr_clear_status(None, None) == lib.SR_ERR_ARG
+    cams = (lib.SrCamera * 3)()
+    for c, (w, hh) in zip(cams, [(40, 21), (33, 48), (64, 64)]):
+        c.width, c.height, c.fx, c.fy = w, hh, 10.0, 10.0
+    cp = ctypes.cast(cams, ctypes.c_void_p)
+    lib.call("sr_layout_views", cp, 3, 16, 16, None, None)
+    cfg = lib.SrConfig(16, 16, 0, 1, 1 / 255, 0.99, 1e-4, 0)
+    n, part = ctypes.c_size_t(), ctypes.c_size_t()
+    # one step workspace covers each call's own
+    assert l.sr_workspace_size(ctypes.byref(cfg), 500, 3, cp, 7000, ctypes.byref(n)) == lib.SR_OK
+    assert l.sr_bin_workspace_size(500, 3, 7000, ctypes.byref(part)) == lib.SR_OK and n.value >= part.value
+    assert l.sr_loss_workspace_size(3, cp, ctypes.byref(part)) == lib.SR_OK and n.value >= part.value
+    assert l.sr_ssim_workspace_size(3, cp, 1, ctypes.byref(part)) == lib.SR_OK and n.value >= part.value
+    assert l.sr_tile_order_workspace_size(3 * 2 + 3 * 3 + 16, ctypes.byref(part)) == lib.SR_OK
+    assert n.value >= part.value
+    assert l.sr_workspace_size(ctypes.byref(cfg), -1, 3, cp, 7000, ctypes.byref(n)) == lib.SR_ERR_ARG
+    # the pruning pass: primitive kind, chunking, sizes
+    ws = lambda prim, vpc, cap: (l.sr_prune_workspace_size(ctypes.byref(cfg), prim, 1000, 3, cp, vpc, cap,
+                                                           ctypes.byref(n)), n.value)
+    assert ws(2, 2, 0)[0] == lib.SR_ERR_ARG
+    assert ws(lib.SR_PRIM_SURFEL, 0, 0)[0] == lib.SR_ERR_ARG
+    st, one = ws(lib.SR_PRIM_SURFEL, 1, 0)
+    st2, two = ws(lib.SR_PRIM_SURFEL, 2, 0)
+    st3, big = ws(lib.SR_PRIM_SURFEL, 2, 100000)
+    assert st == st2 == st3 == lib.SR_OK and one < two < big
+    assert ws(lib.SR_PRIM_GAUSS3D, 2, 0)[1] < two       # 8 floats of geometry per record instead of 16
+    p = ctypes.c_void_p(256)
+    prune = lambda ctx, ws_bytes, vpc=2: l.sr_prune_contrib(ctx, ctypes.byref(cfg), lib.SR_PRIM_SURFEL, 1000, p, p, p,
+                                                            p, 3, cp, p, vpc, 1 / 255, 0, p, ws_bytes, p, p, p, None,
+                                                            p, None)
+    assert prune(None, two - 1) == lib.SR_ERR_ARG                      # workspace too small
+    assert prune(None, two, vpc=0) == lib.SR_ERR_ARG
+    assert prune(None, two) == lib.SR_ERR_ARG                          # valid but for the context
+    assert b"ctx" in l.sr_last_error()
+    cap = ctypes.c_uint32()
+    assert l.sr_prune_plan(None, ctypes.byref(cfg), lib.SR_PRIM_SURFEL, 1000, p, p, p, p, 3, cp, p, 2, p, two,
+                           ctypes.byref(cap), None) == lib.SR_ERR_ARG
+    # a call with work to enqueue needs a context; one without returns at once
+    assert l.sr_prune_mask(None, 10, p, 0.5, p, None) == lib.SR_ERR_ARG and b"ctx" in l.sr_last_error()
+    assert l.sr_prune_mask(None, 0, None, 0.5, None, None) == lib.SR_OK
+    assert l.sr_tile_order(None, 0, None, None, 0, None, None) == lib.SR_OK

@@ -11,8 +11,8 @@ import torch
 import oracle
 from oracle.render import Params64, render_pixels
 from paper_2501_08174_amd import _lib, scenes
-from paper_2501_08174_amd.raster import (BackgroundLoss, Params, Rasterizer, RegularizerLoss, ViewBatch, _ptr,
-                                         _stream, rasterize)
+from paper_2501_08174_amd.raster import (BackgroundLoss, Params, Rasterizer, RegularizerLoss, ViewBatch, _ctx,
+                                         _ptr, _stream, rasterize)
 from tests.gpu_helpers import FWD_TOL, crop_pixels, geometry, gpu_run, per_view
 from tests.test_gpu_regularizers import _flat, _maps, _wall_scene
 
@@ -173,7 +173,7 @@ def test_regularizer_epilogue_median_matches_oracle():
     pre = 1e-5 * torch.rand(views.P, device="cuda")
     dA = pre.clone()
     dD, dN, dS, dM = torch.empty_like(td), torch.empty_like(tn), torch.empty_like(ts), torch.empty_like(tm)
-    _lib.call("sr_regularizer_loss", views.V, views.host_ptr, _ptr(views.dev), _ptr(ta), _ptr(td), _ptr(tn),
+    _lib.call("sr_regularizer_loss", _ctx(ta), views.V, views.host_ptr, _ptr(views.dev), _ptr(ta), _ptr(td), _ptr(tn),
               _ptr(ts), _ptr(tm), wd, wn, _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS),
               _ptr(dM), _stream())
     torch.cuda.synchronize()

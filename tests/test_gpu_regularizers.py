@@ -60,8 +60,8 @@ def test_regularizer_epilogue_matches_oracle():
     pre = torch.rand(views.P, device="cuda")          # dL_dalpha is added to
     dA = pre.clone()
     dD, dN, dS = torch.empty_like(td), torch.empty_like(tn), torch.empty_like(ts)
-    from paper_2501_08174_amd.raster import _ptr, _stream
-    _lib.call("sr_regularizer_loss", views.V, views.host_ptr, _ptr(views.dev), _ptr(ta), _ptr(td), _ptr(tn),
+    from paper_2501_08174_amd.raster import _ctx, _ptr, _stream
+    _lib.call("sr_regularizer_loss", _ctx(ta), views.V, views.host_ptr, _ptr(views.dev), _ptr(ta), _ptr(td), _ptr(tn),
               _ptr(ts), None, wd, wn, _ptr(ws), ws.numel(), _ptr(loss), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), None,
               _stream())
     torch.cuda.synchronize()

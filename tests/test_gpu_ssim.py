@@ -9,7 +9,7 @@ import torch
 import oracle
 from oracle.ssim import ssim_map64
 from paper_2501_08174_amd import _lib, scenes
-from paper_2501_08174_amd.raster import SsimLoss, ViewBatch, _ptr, _stream
+from paper_2501_08174_amd.raster import SsimLoss, ViewBatch, _ctx, _ptr, _stream
 from tests.gpu_helpers import gpu_run, per_view
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +47,7 @@ def _run(cams, C, I, M, w_s, grad=True, pre=None):
     if grad:
         dC = torch.zeros(3 * views.P, device="cuda") if pre is None else pre.clone()
     tc, ti, tm = _flat(C), _flat(I), _flat(M, torch.uint8)     # kept alive across the call
-    _lib.call("sr_ssim_loss", views.V, views.host_ptr, _ptr(views.dev), _ptr(tc), _ptr(ti), _ptr(tm), w_s,
+    _lib.call("sr_ssim_loss", _ctx(tc), views.V, views.host_ptr, _ptr(views.dev), _ptr(tc), _ptr(ti), _ptr(tm), w_s,
               _ptr(ws), ws.numel(), _ptr(out), _ptr(dC), _stream())
     torch.cuda.synchronize()
     return views, out.cpu().numpy(), (None if dC is None else dC.cpu().numpy())
