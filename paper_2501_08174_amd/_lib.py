@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from ctypes import POINTER, byref, c_float, c_int32, c_int64, c_size_t, c_uint32, c_void_p, c_char_p
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsurfelrast.so")
@@ -189,7 +190,6 @@ class Context:
         check(lib().sr_clear_status(self.handle, stream))
 
     def __del__(self):
-        import sys
         h = getattr(self, "handle", None)
         if h is not None and h.value and not sys.is_finalizing() and _lib is not None:
             _lib.sr_destroy(h)
