@@ -18,6 +18,9 @@ Modules
   ssim      masked SSIM / D-SSIM (the rest of Eq. 2's photometric loss) and
             masked PSNR
   prune     occlusion-aware pruning statistics (Section 4.3)
+  prune_native  the same statistics from a plain-C per-pixel loop
+            (prune_native.c, built with gcc on first use) for scenes of a
+            million surfels over a hundred views
   densify   the screen-space gradient statistic of the density control
   gauss3d   the pruning statistics for 3D Gaussians (Appendix B): EWA
             projection, conservative rectangles, compositing decisions
