@@ -41,6 +41,11 @@ FWD_OPS_BLEND, FWD_OPS_SKIP = 45.0, 26.0
 BWD_OPS_BLEND, BWD_OPS_SKIP = 110.0, 26.0
 VALU_PEAK = 256 * 64 * 2.4e9          # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 HBM_PEAK = 8.0e12                      # bytes/s
+# masked D-SSIM with its gradient, per pixel: colour and target read (24 B),
+# mask (1 B), the colour gradient read and written (24 B); per channel 5
+# moments x 11 taps x 2 passes (110 FMA) + 3 products + ~22 for S and its
+# three derivatives, backward 3 maps x 22 taps + ~6 to combine: ~207, x 3
+SSIM_BYTES_PX, SSIM_OPS_PX = 49, 620
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_train_raster_ragged16_1m_traffic.md")
@@ -86,6 +91,7 @@ def parse():
                     help="also time the occlusion-pruning pass (surfels and 3D Gaussians) on the shell scene")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for the HBM traffic counters)")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -168,12 +174,12 @@ class Pipeline:
         rec(8 if eq3 is not None else (4 if fused else 6))
 
 
-def cpu_baseline(scene, seconds_budget=20.0):
-    """Oracle forward + backward (FP64 autograd) over 64x64 crops of view 0."""
+def _oracle_crops(scene, seconds_budget, threads):
+    """Oracle forward + backward (FP64 autograd) over 64x64 crops of view 0:
+    (pixels per second, crops, seconds)."""
     import torch
     import oracle
     from oracle.render import Params64, render_pixels
-    threads = len(os.sched_getaffinity(0))
     torch.set_num_threads(threads)
     rp = oracle.RasterParams()
     cam = scene.cams[0]
@@ -192,17 +198,85 @@ def cpu_baseline(scene, seconds_budget=20.0):
             break
         x0 = (x0 + 64) % max(cam.width - 64, 1)
     dt = time.perf_counter() - t0
-    return {"value": done_px / dt / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
-            "sample": f"{crops} crops of 64x64 px of view 0 ({cam.width}x{cam.height}), fwd+bwd FP64, "
-                      f"{scene.n} surfels, {dt:.1f} s"}
+    return done_px / dt, crops, dt
+
+
+def cpu_baseline_child(workload):
+    """The crop leg on one core (run as a child process with
+    OMP_NUM_THREADS=1, started before the parent touches the GPU)."""
+    scene = make_scene(workload)
+    px_s, crops, dt = _oracle_crops(scene, 20.0, 1)
+    print(json.dumps({"value": px_s / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+                      "sample": f"{crops} crop(s) of 64x64 px of view 0, fwd+bwd FP64, {scene.n} surfels, "
+                                f"{dt:.1f} s"}), flush=True)
+
+
+def start_one_core_baseline(workload):
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", HIP_VISIBLE_DEVICES="",
+               CUDA_VISIBLE_DEVICES="")
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                             "--workload", workload], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, env=env,
+                            text=True)
+
+
+def cpu_baseline(scene, one_core_proc=None, seconds_budget=20.0):
+    """The oracle timed on the host: the headline leg (fwd+bwd on 64x64 crops
+    of view 0 of the benchmark workload, all cores), the same on one core
+    (child process), the 64x64 single-view workload's full frame (forward),
+    and a sample of the shell-scene pruning statistics (the plain-C oracle
+    loop over four of its 100 views)."""
+    import oracle
+    from oracle.prune_native import prune_stats_views64
+    from oracle.render import Params64, render_view
+    from paper_2501_08174_amd import scenes
+    threads = len(os.sched_getaffinity(0))
+    px_s, crops, dt = _oracle_crops(scene, seconds_budget, threads)
+    out = {"value": px_s / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
+           "sample": f"{crops} crops of 64x64 px of view 0 ({scene.cams[0].width}x{scene.cams[0].height}), "
+                     f"fwd+bwd FP64, {scene.n} surfels, {dt:.1f} s"}
+    legs = {}
+    rp = oracle.RasterParams()
+    f1 = scenes.make_frame64_1k()
+    cam = f1.cams[0]
+    g = oracle.view_geometry64(f1.means, f1.scales, f1.quats, f1.opac, cam, rp)
+    P = Params64.from_arrays(f1.means, f1.scales, f1.quats, f1.opac, f1.sh, f1.sh_degree)
+    t0 = time.perf_counter()
+    render_view(P, cam, g, rp)
+    t1 = time.perf_counter() - t0
+    legs["frame64_1k_forward"] = {"value": cam.width * cam.height / t1 / 1e6, "unit": "Mpixel/s",
+                                  "cores": threads, "sample": f"the full 64x64 frame, 1k surfels, forward FP64, "
+                                                              f"{t1:.2f} s"}
+    sh = scenes.make_shell100()
+    t0 = time.perf_counter()
+    prune_stats_views64(sh.means, sh.scales, sh.quats, sh.opac, sh.cams[:4], rp, workers=min(threads, 16))
+    t4 = time.perf_counter() - t0
+    px4 = sum(c.width * c.height for c in sh.cams[:4])
+    legs["shell100_pruning_sample"] = {"value": px4 / t4 / 1e6, "unit": "Mpixel/s", "cores": min(threads, 16),
+                                       "sample": f"occlusion statistics of 4 of the 100 views (800x800, 1.1M "
+                                                 f"surfels), plain-C FP64 loop, {t4:.1f} s"}
+    if one_core_proc is not None:
+        try:
+            txt, _ = one_core_proc.communicate(timeout=120)
+            legs["one_core"] = json.loads(txt.strip().splitlines()[-1])
+        except Exception as e:  # the headline leg stands without it
+            legs["one_core"] = {"error": repr(e)[:200]}
+    out["legs"] = legs
+    return out
 
 
 def main():
     args = parse()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a "
               f"design (view sharding + one all-reduce of the surfel gradients), not built.", file=sys.stderr)
         sys.exit(2)
+    # the one-core oracle leg runs beside the GPU work, in a child started
+    # before this process touches the GPU
+    one_core = None if args.no_cpu_baseline else start_one_core_baseline(args.workload)
     import torch
     from paper_2501_08174_amd.raster import Params
 
@@ -336,7 +410,7 @@ def main():
         reg_ms = float(st_e[:, Pipeline.STAGES_EQ3.index("regularizers")].mean())
         reg_bytes = 52 * P
         ssim_ms = float(st_e[:, Pipeline.STAGES_EQ3.index("ssim")].mean())
-        ssim_bytes = 146 * P
+        ssim_bytes = SSIM_BYTES_PX * P
         result["eq3"] = {"ms_per_step": e_ms, "Mpixel_per_s": P / (e_ms * 1e-3) / 1e6, "w_dist": w_dist,
                          "w_normal": w_normal,
                          "stage_ms_mean": dict(zip(Pipeline.STAGES_EQ3, [float(x) for x in st_e.mean(axis=0)])),
@@ -347,7 +421,9 @@ def main():
                          "ssim_roofline": {"bound": "hbm", "achieved": ssim_bytes / (ssim_ms * 1e-3) / 1e9,
                                            "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                                            "frac": ssim_bytes / (ssim_ms * 1e-3) / HBM_PEAK,
-                                           "bytes_per_call": ssim_bytes}}
+                                           "bytes_per_call": ssim_bytes,
+                                           "valu_frac": SSIM_OPS_PX * P / (ssim_ms * 1e-3) / VALU_PEAK,
+                                           "lane_ops_per_call": SSIM_OPS_PX * P}}
         # the same step with the median depth as the surface of the normal term
         m_ms, st_m = eq3_leg(True)
         result["eq3_median"] = {"ms_per_step": m_ms, "Mpixel_per_s": P / (m_ms * 1e-3) / 1e6,
@@ -476,7 +552,7 @@ def main():
         del pipes
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene)
+        result["cpu_baseline"] = cpu_baseline(scene, one_core)
     print(json.dumps(result), flush=True)
 
 

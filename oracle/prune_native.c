@@ -21,9 +21,13 @@
  *          hits += 1, max_alpha = max(., a), max_weight = max(., a T) and
  *          T *= 1 - a.
  *   ties   a reached entry within the relative windows tie_cut of alpha_min
- *          (o G) or tie_term of t_min (T (1 - a)) is counted in its
- *          surfel's tie[] (float32 may decide it the other way; each such
- *          entry can change that surfel's hits by one).
+ *          (o G) or tie_term of t_min (T (1 - a)) may be decided the other
+ *          way in float32; then every later decision of the pixel may change
+ *          too (a cutoff tie scales the transmittance of the later entries by
+ *          1 - a), up to m more entries past the stop for m ties.  Each
+ *          entry so exposed - from the pixel's first tie entry on, and the
+ *          next m entries past the stop that pass the cutoff - adds one to
+ *          its surfel's tie[], the most its hits can change by.
  *
  * Finding a pixel's list: the surfels are bucketed by the 8x8-pixel cells
  * their rectangles meet (a lookup aid only); a pixel scans its cell's
@@ -88,6 +92,8 @@ int prune_view_stats(int64_t n_vis, const int64_t* id, const int32_t* rect, cons
             const double md[3] = {-d[0], -d[1], -d[2]};
             const int64_t c = (int64_t)(j / CELL) * cw + i / CELL;
             double T = 1.0;
+            int64_t ties = 0;        /* tie entries met so far at this pixel */
+            int64_t past = -1;       /* entries still to mark past the stop (-1: not stopped) */
             for (int64_t b = start[c]; b < start[c + 1]; ++b) {
                 const int64_t k = bucket[b];
                 const int32_t* r = rect + 4 * k;
@@ -112,14 +118,29 @@ int prune_view_stats(int64_t n_vis, const int64_t* id, const int32_t* rect, cons
                 const double a_raw = opac[k] * G;
                 const double a = a_raw < alpha_max ? a_raw : alpha_max;
                 const int64_t g = id[k];
+                if (past >= 0) {
+                    /* past the stop: entries that pass the cutoff are exposed */
+                    if (a >= alpha_min) {
+                        tie[g] += 1;
+                        if (--past == 0) break;
+                    }
+                    continue;
+                }
                 const int cut_tie = fabs(a_raw - alpha_min) <= tie_cut * alpha_min;
                 if (a < alpha_min) {
+                    /* a skip does not depend on the transmittance: only its own tie exposes it */
+                    ties += cut_tie;
                     tie[g] += cut_tie;
                     continue;
                 }
                 const double Tn = T * (1.0 - a);
-                tie[g] += cut_tie || fabs(Tn - t_min) <= tie_term * t_min;
-                if (Tn < t_min) break;
+                ties += cut_tie || fabs(Tn - t_min) <= tie_term * t_min;
+                tie[g] += ties > 0;
+                if (Tn < t_min) {
+                    if (ties == 0) break;
+                    past = ties;
+                    continue;
+                }
                 hits[g] += 1;
                 if (a > max_alpha[g]) max_alpha[g] = a;
                 if (a * T > max_weight[g]) max_weight[g] = a * T;

@@ -17,8 +17,8 @@ import subprocess
 
 import numpy as np
 
+from . import render as _render
 from .geometry import RasterParams, view_geometry64
-from .render import TIE_CUTOFF_REL, TIE_TERM_REL
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "prune_native.c")
@@ -53,11 +53,12 @@ def _ptr(a):
 
 
 def prune_stats_view64(means, scales, quats, opac, cam, rp: RasterParams = RasterParams(), geom=None,
-                       pix_mask=None):
+                       pix_mask=None, windows=None):
     """Statistics of one view: dict(hits int64 [N], max_alpha, max_weight
-    float64 [N], tie uint32 [N] (each surfel's reached entries within the
-    tie windows: float32 may change its hits by at most that many),
-    visible bool [N])."""
+    float64 [N], tie uint32 [N] (each surfel's entries exposed to a float32
+    tie of their pixel: its hits can change by at most that many),
+    visible bool [N]).  ``windows`` = (cutoff, termination) relative tie
+    windows, by default those of oracle.render."""
     n = np.asarray(means).shape[0]
     g = geom if geom is not None else view_geometry64(means, scales, quats, opac, cam, rp)
     vis = np.nonzero(~g["culled"])[0]
@@ -72,10 +73,10 @@ def prune_stats_view64(means, scales, quats, opac, cam, rp: RasterParams = Raste
                tie=np.zeros(n, np.uint32), visible=~g["culled"])
     pm = None if pix_mask is None else c(pix_mask, np.uint8)
     f32 = lambda v: float(np.float32(v))
+    w_cut, w_term = (_render.TIE_CUTOFF_REL, _render.TIE_TERM_REL) if windows is None else windows
     st = _load().prune_view_stats(ids.size, _ptr(ids), _ptr(rect), _ptr(p), _ptr(au), _ptr(av), _ptr(ctr), _ptr(op),
                                   f32(cam.fx), f32(cam.fy), f32(cam.cx), f32(cam.cy), int(cam.width),
-                                  int(cam.height), rp.alpha_min, rp.alpha_max, rp.t_min, TIE_CUTOFF_REL,
-                                  TIE_TERM_REL, _ptr(pm), _ptr(out["hits"]), _ptr(out["max_alpha"]),
+                                  int(cam.height), rp.alpha_min, rp.alpha_max, rp.t_min, w_cut, w_term, _ptr(pm), _ptr(out["hits"]), _ptr(out["max_alpha"]),
                                   _ptr(out["max_weight"]), _ptr(out["tie"]))
     if st != 0:
         raise MemoryError("prune_view_stats: out of memory")
@@ -83,7 +84,7 @@ def prune_stats_view64(means, scales, quats, opac, cam, rp: RasterParams = Raste
 
 
 def prune_stats_views64(means, scales, quats, opac, cams, rp: RasterParams = RasterParams(), workers: int = 1,
-                        tau: float = None):
+                        tau: float = None, windows=None):
     """Statistics accumulated over the views ``cams`` (sums of the hits and
     tie counts, maxima, OR of the in-frustum flags), and the mask max_alpha < tau
     (tau = alpha_min by default); views are spread over ``workers``
@@ -93,7 +94,7 @@ def prune_stats_views64(means, scales, quats, opac, cams, rp: RasterParams = Ras
                tie=np.zeros(n, np.uint32), in_frustum=np.zeros(n, bool))
 
     def one(cam):
-        return prune_stats_view64(means, scales, quats, opac, cam, rp)
+        return prune_stats_view64(means, scales, quats, opac, cam, rp, windows=windows)
 
     with cf.ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
         for r in ex.map(one, cams):

@@ -190,10 +190,15 @@ class Context:
         check(lib().sr_clear_status(self.handle, stream))
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h is not None and h.value and not sys.is_finalizing() and _lib is not None:
-            _lib.sr_destroy(h)
-            self.handle = None
+        # at interpreter exit the module's globals may already be gone: the
+        # process end releases the context instead
+        try:
+            h = getattr(self, "handle", None)
+            if h is not None and h.value and not sys.is_finalizing() and _lib is not None:
+                _lib.sr_destroy(h)
+                self.handle = None
+        except Exception:
+            pass
 
 
 _default_ctx = {}

@@ -6,7 +6,8 @@ import numpy as np
 import torch
 
 import oracle
-from oracle.render import TIE_KINDS, Params64, render_alternatives, render_pixels
+from oracle.render import (TIE_KINDS, WIDE_CUTOFF_REL, WIDE_TERM_REL, Params64, render_alternatives,
+                           render_pixels)
 from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch
 from tests.grouping import expand_to_tile_lists, grouped_from_rectangles, instance_count
 
@@ -145,69 +146,104 @@ def _row_err(g, ref, rows_g, rows_r, names=("color", "alpha", "depth", "normal",
     return e
 
 
+def _match(g, last, r_gpu, cands, ref_rows, tol):
+    """Indices of the candidate results (res, row) that the GPU's pixel
+    r_gpu matches within tol (and, with ``last``, by its last blended
+    surfel), and their errors."""
+    errs, good = [], []
+    for k, (ref, rr) in enumerate(zip(cands, ref_rows)):
+        e = float(_row_err(g, ref, [r_gpu], [rr])[0])
+        errs.append(e)
+        if e <= tol and (last is None or int(ref["last_gid"][rr]) == last[r_gpu]):
+            good.append(k)
+    return good, errs
+
+
+def _resolve(g, last, r_gpu, res, row, alts, ares, tol, what):
+    """The flips (possibly none) of the correct result the GPU's pixel
+    matches best; asserts that it matches one."""
+    cands, rows, flips = [res], [row], [()]
+    for k, (rr, f) in enumerate(alts):
+        if rr == row:
+            cands.append(ares)
+            rows.append(k)
+            flips.append(f)
+    good, errs = _match(g, last, r_gpu, cands, rows, tol)
+    assert good, (f"{what} pixel matches none of its {len(cands)} correct results: errors {errs}, last surfel "
+                  f"gpu {None if last is None else last[r_gpu]} vs {[int(c['last_gid'][r]) for c, r in zip(cands, rows)]}")
+    return list(flips[min(good, key=lambda k: errs[k])])
+
+
 def compare_forward(gpu_view, res, pix, rast=None, v=None, tol=FWD_TOL, oracle_ctx=None):
     """Forward parity with the tie protocol.
 
-    Pixels whose list holds no tie entry must match the oracle within
-    ``tol`` on every output, and (with ``rast``) blend the same last surfel.
+    A pixel whose list holds no tie entry must match the oracle within
+    ``tol`` on every output and (with ``rast``) blend the same last surfel.
     A pixel with a tie entry (a value within float32 reach of the cutoff,
-    the termination test or the surface/low-pass choice) must match one of
-    the oracle's correct results (``oracle.render.render_alternatives``:
-    each subset of its tie entries taken the other way), when
-    ``oracle_ctx`` = (P64, cam, geom, rp) is given; without it such pixels
-    are only counted.
+    the termination test or the surface/low-pass choice: the primary
+    windows) must match one of the oracle's correct results
+    (``render_alternatives``: each subset of its tie entries taken the other
+    way).  A pixel without a tie entry that does not match is re-examined
+    under the wide windows (WIDE_CUTOFF_REL, WIDE_TERM_REL) and must then
+    match one of its correct results.  Needs ``oracle_ctx`` = (P64, cam,
+    geom, rp) for the alternatives (without it tie pixels are only counted).
 
-    Returns (max abs errors of the pixels without a tie entry, tie-pixel
-    fraction, report) with report: ``choice`` {row: flips} of the tie pixels
-    whose match took some tie the other way (feed it as ``flips`` to the
-    oracle's gradient pass), ``entries`` [(kind, distance, taken other
-    way)] for every tie entry of a resolved pixel, ``unresolved`` rows."""
+    Returns (max abs errors of the pixels matched without a tie, fraction of
+    pixels resolved through a tie, report) with report: ``choice`` {row:
+    flips} of the pixels whose match took some tie the other way (feed it as
+    ``flips`` to the oracle's gradient pass), ``entries`` [(kind, distance,
+    taken other way)] of the primary tie entries, ``wide`` the rows resolved
+    under the wide windows, ``unresolved`` rows with too many ties."""
     f_geo = res["flag_cut"] | res["flag_term"] | res["flag_branch"]
-    ok = ~f_geo
     g = _gpu_values(gpu_view, pix)
+    last = _gpu_last_gid(gpu_view, pix, rast, v) if rast is not None else None
+    n = pix.shape[0]
+    row_err = _row_err(g, res, np.arange(n), np.arange(n))
+    bad = ~f_geo & (row_err > tol)
+    if last is not None:
+        bad |= ~f_geo & (last != res["last_gid"])
+    report = {"choice": {}, "entries": [], "unresolved": [], "wide": []}
+    if oracle_ctx is None:
+        assert not bad.any(), f"{bad.sum()} pixels differ (max error {row_err[bad].max():.3e})"
+        report["unresolved"] = np.nonzero(f_geo)[0].tolist()
+    else:
+        P64, cam, geom, rp = oracle_ctx
+        rows = np.nonzero(f_geo)[0]
+        if rows.size:
+            alts, ares, unres = render_alternatives(P64, cam, geom, pix, res["tie_list"], rp)
+            report["unresolved"] = unres
+            tl, td = res["tie_list"], res["tie_dist"]
+            for r in rows:
+                if r in unres:
+                    continue
+                fl = _resolve(g, last, r, res, r, alts, ares, tol, f"tie pixel {pix[r].tolist()}")
+                if fl:
+                    report["choice"][int(r)] = fl
+                for (_, gid, kind), d in zip(tl[tl[:, 0] == r], td[tl[:, 0] == r]):
+                    if kind <= 2:
+                        report["entries"].append((TIE_KINDS[kind], float(d), (int(gid), TIE_KINDS[kind]) in fl))
+        brows = np.nonzero(bad)[0]
+        if brows.size:
+            wide = (WIDE_CUTOFF_REL, WIDE_TERM_REL)
+            sub = pix[brows]
+            res_w = render_pixels(P64, cam, geom, sub, rp, windows=wide)
+            alts, ares, unres = render_alternatives(P64, cam, geom, sub, res_w["tie_list"], rp, windows=wide)
+            gs = {k: np.asarray(a)[brows] for k, a in g.items()}
+            ls = None if last is None else last[brows]
+            for i, r in enumerate(brows):
+                assert i not in unres, f"pixel {pix[r].tolist()}: too many ties under the wide windows"
+                fl = _resolve(gs, ls, i, res_w, i, alts, ares, tol, f"pixel {pix[r].tolist()} (wide windows)")
+                if fl:
+                    report["choice"][int(r)] = fl
+            report["wide"] = brows.tolist()
+    ok = ~f_geo & ~bad
     errs = {}
     for name in ("color", "alpha", "depth", "normal", "dist"):
         e = np.abs(np.asarray(g[name])[ok] - np.asarray(res[name])[ok])
         errs[name] = float(e.max()) if e.size else 0.0
     for name, e in errs.items():
         assert e <= tol, f"{name}: max abs error {e:.3e} > {tol}"
-    last = _gpu_last_gid(gpu_view, pix, rast, v) if rast is not None else None
-    if last is not None:
-        mism = (last != res["last_gid"]) & ok
-        assert not mism.any(), f"{mism.sum()} pixels with a different last blended surfel"
-    report = {"choice": {}, "entries": [], "unresolved": []}
-    rows = np.nonzero(f_geo)[0]
-    if rows.size == 0 or oracle_ctx is None:
-        report["unresolved"] = rows.tolist() if oracle_ctx is None else []
-        return errs, float(f_geo.mean()), report
-    P64, cam, geom, rp = oracle_ctx
-    alts, ares, unres = render_alternatives(P64, cam, geom, pix, res["tie_list"], rp)
-    report["unresolved"] = unres
-    tl, td = res["tie_list"], res["tie_dist"]
-    for r in rows:
-        if r in unres:
-            continue
-        cands = [()] + [f for (rr, f) in alts if rr == r]
-        idx = [None] + [k for k, (rr, f) in enumerate(alts) if rr == r]
-        errs_c, lasts = [], []
-        for c in idx:
-            if c is None:
-                errs_c.append(float(_row_err(g, res, [r], [r])[0]))
-                lasts.append(int(res["last_gid"][r]))
-            else:
-                errs_c.append(float(_row_err(g, ares, [r], [c])[0]))
-                lasts.append(int(ares["last_gid"][c]))
-        good = [k for k in range(len(cands)) if errs_c[k] <= tol and (last is None or lasts[k] == last[r])]
-        assert good, (f"tie pixel {pix[r].tolist()} matches none of its {len(cands)} correct results: "
-                      f"errors {errs_c}, last surfel gpu {None if last is None else last[r]} vs {lasts}")
-        best = min(good, key=lambda k: errs_c[k])
-        if cands[best]:
-            report["choice"][int(r)] = list(cands[best])
-        taken = set(cands[best])
-        for (rr, gid, kind), d in zip(tl[tl[:, 0] == r], td[tl[:, 0] == r]):
-            if kind <= 2:
-                report["entries"].append((TIE_KINDS[kind], float(d), (int(gid), TIE_KINDS[kind]) in taken))
-    return errs, float(f_geo.mean()), report
+    return errs, float((f_geo | bad).mean()), report
 
 
 GRAD_RTOL = 1e-3
