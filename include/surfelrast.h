@@ -401,6 +401,28 @@ sr_status sr_train_step_raster(sr_ctx *ctx, const sr_config *cfg, int32_t N, int
                                float *tile_loss, float *loss, float *grad_rec, const uint32_t *tile_order,
                                uint32_t *tile_cost, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sr_train_step_raster with the per-tile loss partials in a scratch array of
+ * the library instead of tile_loss.  The array (2 floats per tile, at most
+ * SR_NOALLOC_MAX_TILES tiles = 2 MiB) is a static device array, one per GPU
+ * the library runs on, held until the process ends; its address is taken
+ * when the context is created.  The call allocates nothing.  Views with more
+ * than SR_NOALLOC_MAX_TILES tiles in total: SR_ERR_ARG.  Every call on one
+ * GPU shares that GPU's array (each tile overwrites its own partials, so
+ * nothing has to start at zero): calls that can overlap on one GPU (streams
+ * without an ordering between them) race, and their losses are undefined.
+ * Arguments, outputs and errors otherwise as sr_train_step_raster. */
+#define SR_NOALLOC_MAX_TILES 262144
+sr_status sr_train_step_raster_noalloc(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V,
+                                       const sr_camera *cams_host, const sr_camera *cams_dev, const float *geom,
+                                       const float *app, const uint32_t *vals, const uint32_t *ranges,
+                                       const uint8_t *mask, const float *target, float gamma, float w_c,
+                                       float *color, float *alpha, float *depth, float *normal, float *dist,
+                                       float *T_final, uint32_t *n_contrib, uint32_t *hits, float *max_alpha,
+                                       float *max_weight, float *loss, float *grad_rec,
+                                       const uint32_t *tile_order, uint32_t *tile_cost, void *stream);
+
 /* Dispatch order for sr_train_step_raster: the T tile ids sorted by
  * descending cost class of tile_cost [T], written to tile_order [T]; equal
  * classes keep ascending tile id.  The class of a cost c is c below 16 and

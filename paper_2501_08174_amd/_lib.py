@@ -29,6 +29,7 @@ SR_COUNTERS = 4
 SR_COMPACT_MAX_ARRAYS = 8
 SR_TILE_GROUP = 4
 SR_INST_ID_BITS = 24
+SR_NOALLOC_MAX_TILES = 262144
 
 EXPORTED = (
     "sr_last_error", "sr_version", "sr_create", "sr_destroy", "sr_read_status", "sr_clear_status",
@@ -36,8 +37,8 @@ EXPORTED = (
     "sr_bin_and_sort", "sr_render_forward", "sr_render_backward", "sr_backward_raster", "sr_backward_project",
     "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_ssim_workspace_size",
     "sr_ssim_loss", "sr_compact_workspace_size", "sr_compact_surfels", "sr_preprocess_3d", "sr_prune_stats_3d",
-    "sr_train_step_raster", "sr_prune_stats", "sr_prune_workspace_size", "sr_prune_plan", "sr_prune_contrib",
-    "sr_render_count", "sr_prune_mask", "sr_tile_order_workspace_size", "sr_tile_order",
+    "sr_train_step_raster", "sr_train_step_raster_noalloc", "sr_prune_stats", "sr_prune_workspace_size",
+    "sr_prune_plan", "sr_prune_contrib", "sr_render_count", "sr_prune_mask", "sr_tile_order_workspace_size", "sr_tile_order",
 )
 
 
@@ -103,6 +104,8 @@ def _declare(lib):
         "sr_compact_surfels": (c_int32, [V, c_int32, V, V, c_float, c_int32, V, V, V, V, c_size_t, V, V]),
         "sr_train_step_raster": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
                                  + [V] * 16),
+        "sr_train_step_raster_noalloc": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float,
+                                                   c_float] + [V] * 15),
         "sr_tile_order_workspace_size": (c_int32, [c_int32, POINTER(c_size_t)]),
         "sr_tile_order": (c_int32, [V, c_int32, V, V, c_size_t, V, V]),
         "sr_prune_stats": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, V, V]),

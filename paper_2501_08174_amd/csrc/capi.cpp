@@ -23,6 +23,7 @@ static_assert(sizeof(sr_camera) == 128, "sr_camera must stay 128 bytes");
 struct sr_ctx {
     int device;
     uint32_t* status;
+    float* scratch;     // the device's scratch array (sr_train_step_raster_noalloc)
 };
 
 namespace {
@@ -135,15 +136,18 @@ sr_status sr_create(sr_ctx** ctx_out_host, int32_t device) {
     SR_TRY(hip_status(hipGetDevice(&prev), "hipGetDevice"));
     SR_TRY(hip_status(hipSetDevice(device), "hipSetDevice"));
     void* p = nullptr;
+    float* scratch = nullptr;
     hipError_t e = hipMalloc(&p, 4 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(p, 0, 4 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
+    // the address of this device's copy of the scratch array, with the device current
+    if (e == hipSuccess) e = sr::scratch_address(device, &scratch);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         if (p) hipFree(p);
         return hip_status(e, "sr_create");
     }
-    sr_ctx* c = new (std::nothrow) sr_ctx{device, (uint32_t*)p};
+    sr_ctx* c = new (std::nothrow) sr_ctx{device, (uint32_t*)p, scratch};
     if (!c) {
         hipFree(p);
         return fail(SR_ERR_ARG, "out of host memory");
@@ -640,25 +644,37 @@ sr_status sr_prune_stats(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V
                       "sr_prune_stats");
 }
 
-sr_status sr_train_step_raster(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
-                               const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
-                               const uint32_t* ranges, const uint8_t* mask, const float* target, float gamma,
-                               float w_c, float* color, float* alpha, float* depth, float* normal, float* dist,
-                               float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
-                               float* max_weight, float* tile_loss, float* loss, float* grad_rec,
-                               const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
+namespace {
+
+// The fused training step with its per-tile loss partials in tile_loss
+// (the caller's buffer, or the context's scratch array).
+sr_status train_step(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
+                     const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
+                     const uint32_t* ranges, const uint8_t* mask, const float* target, float gamma, float w_c,
+                     float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
+                     uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight, float* tile_loss,
+                     float* loss, float* grad_rec, const uint32_t* tile_order, uint32_t* tile_cost, void* stream,
+                     bool noalloc) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
     int total_tiles = 0;
     SR_TRY(check_views(cams_host, cams_dev, V, cfg->tile_w, cfg->tile_h, nullptr, &total_tiles, nullptr));
+    if (noalloc && total_tiles > SR_NOALLOC_MAX_TILES)
+        return fail(SR_ERR_ARG, "%d tiles exceed the scratch array's %d (SR_NOALLOC_MAX_TILES)", total_tiles,
+                    SR_NOALLOC_MAX_TILES);
     if (total_tiles > 0) {
         SR_NEED(geom); SR_NEED(app); SR_NEED(vals); SR_NEED(ranges); SR_NEED(mask); SR_NEED(target);
         SR_NEED(color); SR_NEED(alpha); SR_NEED(depth); SR_NEED(normal); SR_NEED(dist); SR_NEED(T_final);
-        SR_NEED(n_contrib); SR_NEED(tile_loss); SR_NEED(loss); SR_NEED(grad_rec);
+        SR_NEED(n_contrib); SR_NEED(loss); SR_NEED(grad_rec);
+        if (!noalloc) SR_NEED(tile_loss);
     }
     SR_TRY(check_stats(hits, max_alpha, max_weight));
     if (N == 0 && total_tiles == 0) return SR_OK;  // nothing to enqueue
     SR_TRY(check_ctx(ctx));
+    if (noalloc) {
+        if (!ctx->scratch) return fail(SR_ERR_STATE, "the context has no scratch array address");
+        tile_loss = ctx->scratch;
+    }
     hipStream_t s = (hipStream_t)stream;
     if (!(cfg->flags & SR_FLAG_ACCUMULATE)) SR_TRY(clear_stats(N, hits, max_alpha, max_weight, s));
     if (total_tiles == 0) return SR_OK;
@@ -668,6 +684,33 @@ sr_status sr_train_step_raster(sr_ctx* ctx, const sr_config* cfg, int32_t N, int
                                               ctx->status, s),
                       "sr_train_step_raster"));
     return hip_status(sr::launch_loss_from_tiles(V, cams_dev, tile_loss, gamma, w_c, loss, s), "loss totals");
+}
+
+}  // namespace
+
+sr_status sr_train_step_raster(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
+                               const sr_camera* cams_dev, const float* geom, const float* app, const uint32_t* vals,
+                               const uint32_t* ranges, const uint8_t* mask, const float* target, float gamma,
+                               float w_c, float* color, float* alpha, float* depth, float* normal, float* dist,
+                               float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
+                               float* max_weight, float* tile_loss, float* loss, float* grad_rec,
+                               const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
+    return train_step(ctx, cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, mask, target, gamma, w_c, color,
+                      alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, loss,
+                      grad_rec, tile_order, tile_cost, stream, false);
+}
+
+sr_status sr_train_step_raster_noalloc(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V,
+                                       const sr_camera* cams_host, const sr_camera* cams_dev, const float* geom,
+                                       const float* app, const uint32_t* vals, const uint32_t* ranges,
+                                       const uint8_t* mask, const float* target, float gamma, float w_c,
+                                       float* color, float* alpha, float* depth, float* normal, float* dist,
+                                       float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
+                                       float* max_weight, float* loss, float* grad_rec,
+                                       const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
+    return train_step(ctx, cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, mask, target, gamma, w_c, color,
+                      alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, nullptr, loss,
+                      grad_rec, tile_order, tile_cost, stream, true);
 }
 
 sr_status sr_render_count(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,

@@ -62,6 +62,10 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
                                float* tile_loss, float* grad_rec, const uint32_t* tile_order,
                                uint32_t* tile_cost, const uint32_t* status, hipStream_t s);
 
+// The device address of the training step's file-scope scratch array on
+// `device` (which must be current at the first call for that device).
+hipError_t scratch_address(int device, float** out);
+
 hipError_t launch_loss_from_tiles(int V, const sr_camera* cams, const float* tile_loss, float gamma, float w_c,
                                   float* loss, hipStream_t s);
 

@@ -13,6 +13,8 @@
 // per workgroup-size entries; every pair is evaluated with the shared
 // eval_test()/eval_finish() so that forward, backward and pruning take identical
 // decisions.
+#include <mutex>
+
 #include "common.h"
 #include "launch.h"
 
@@ -1037,6 +1039,35 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
     SR_TILE_SHAPES(SR_TS)
 #undef SR_TS
     return hipErrorInvalidValue;
+}
+
+// ---- the allocation-free training step ------------------------------------------
+//
+// The per-tile loss partials of sr_train_step_raster_noalloc live in this
+// file-scope device array (one copy per GPU, held until the process ends)
+// instead of a caller buffer.  On the host its name is a stand-in symbol, not
+// a device address: host code uses only the address hipGetSymbolAddress
+// returns, taken once per device with that device current.
+__device__ __align__(256) float scratch[2 * SR_NOALLOC_MAX_TILES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, float** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[device] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
 }
 
 hipError_t launch_prune_mask(int N, const float* max_alpha, float tau, const uint32_t* status, uint8_t* mask,

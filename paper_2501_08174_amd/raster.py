@@ -348,23 +348,29 @@ class Rasterizer:
         return self.ssim_out
 
     def train_step_raster(self, mask: torch.Tensor, target: torch.Tensor, gamma: float = 0.5, w_c: float = 1.0,
-                          stats=None, accumulate: bool = False, stream=None, schedule: bool = True):
+                          stats=None, accumulate: bool = False, stream=None, schedule: bool = True,
+                          noalloc: bool = False):
         """Fused forward + loss gradients + backward compositing (one launch;
         ``stats`` as in forward); follow with backward_project.  With
         ``schedule`` every call records the per-tile costs and launches in the
         order of the previous call's costs, heaviest tiles first (the first
-        call uses the default order; results do not depend on the order)."""
-        if getattr(self, "tile_loss", None) is None:
-            self.tile_loss = torch.zeros(2 * max(self.views.T, 1), dtype=torch.float32, device=self.device)
+        call uses the default order; results do not depend on the order).
+        ``noalloc``: sr_train_step_raster_noalloc, the per-tile loss partials
+        in the library's scratch array instead of a buffer of this object."""
         h, ma, mw = _stats(stats)
         cfg = self._cfg(accumulate)
         order, cost = self._schedule(stream) if schedule else (None, None)
-        call("sr_train_step_raster", self.ctx.ptr, ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
-             _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask),
-             _ptr(target), float(gamma), float(w_c), _ptr(self.color), _ptr(self.alpha), _ptr(self.depth),
-             _ptr(self.normal), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma),
-             _ptr(mw), _ptr(self.tile_loss), _ptr(self.loss_out), _ptr(self._grad_rec()), _ptr(order), _ptr(cost),
-             _stream(stream))
+        common = (self.ctx.ptr, ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr, _ptr(self.views.dev),
+                  _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask), _ptr(target),
+                  float(gamma), float(w_c), _ptr(self.color), _ptr(self.alpha), _ptr(self.depth), _ptr(self.normal),
+                  _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw))
+        tail = (_ptr(self.loss_out), _ptr(self._grad_rec()), _ptr(order), _ptr(cost), _stream(stream))
+        if noalloc:
+            call("sr_train_step_raster_noalloc", *common, *tail)
+        else:
+            if getattr(self, "tile_loss", None) is None:
+                self.tile_loss = torch.zeros(2 * max(self.views.T, 1), dtype=torch.float32, device=self.device)
+            call("sr_train_step_raster", *common, _ptr(self.tile_loss), *tail)
         if cost is not None:
             self.costs_recorded = True
         return self.loss_out
