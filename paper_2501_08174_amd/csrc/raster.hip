@@ -296,8 +296,8 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     st.T = 1.0f;
     st.C0 = st.C1 = st.C2 = st.N0 = st.N1 = st.N2 = st.S0 = st.S1 = st.S2 = st.zref = st.zmed = 0.f;
     st.last = st.kmed = 0;
-    bool have_ref = false;
-    bool done = !t.inside;
+    uint32_t px_live = t.inside ? 1u : 0u;    // 0 once the pixel has terminated (or lies outside)
+    constexpr bool PLAIN = !COUNT && !HITS;
     // statistics of the previous batch's entries: every thread adds its own
     // slot to the global arrays (after a barrier), before the slot is reused
     int prev_cnt = 0;
@@ -314,7 +314,7 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
     // batches of up to NT entries of the tile, gathered from its group's run
     int64_t pos = 0;
     while (pos < (int64_t)t.n) {
-        if (__syncthreads_and(done)) break;
+        if (__syncthreads_and(px_live == 0u)) break;
         if (HITS) flush();
         int cnt = 0;
         while (cnt < NT && pos < (int64_t)t.n) {
@@ -358,7 +358,7 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
             }
         }
         __syncthreads();
-        bool wave_done = ballot64(!done) == 0ull;
+        bool wave_done = ballot64(px_live != 0u) == 0ull;
         for (int c = 0; c * 64 < cnt && !wave_done; ++c) {
           uint64_t live = wave_live_mask(sm.a[1], c, cnt);
           // HITS: this wave's blended pixels of entry c * 64 + lane
@@ -370,25 +370,12 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
             PairEval e;
             const float4 g2 = sm.g[2][k], g3 = sm.g[3][k];
             eval_test(sm.g[0][k], sm.g[1][k], g2, g3, px, py, e);
-            if (COUNT) {
-                n_reached += (uint64_t)__popcll(ballot64(!done));
-                n_witer += 1;
-                n_eval += done ? 0u : 1u;
-            }
-            bool blend = !done && e.pass;
-            // no pixel of this wave takes the entry: nothing changes
-            if (ballot64(blend) == 0ull) continue;
-            if (COUNT) n_wblend += 1;
-            eval_finish(g2, g3, rc.alpha_max, e);
-            const float Tn = st.T * (1.0f - e.a);
-            if (blend && Tn < rc.t_min) {
-                done = true;
-                blend = false;
-            }
-            float wgt = 0.f;
-            if (blend) {
-                wgt = e.a * st.T;
-                if (!have_ref) { st.zref = e.z; have_ref = true; }
+            // blends entry k into the pixel state (before the transmittance update)
+            auto accumulate = [&](float wgt) {
+                // the depth reference of the distortion sums is the depth of
+                // the pixel's first blended entry: T is exactly 1 until then
+                // (every blended alpha is at least alpha_min)
+                st.zref = st.T == 1.0f ? e.z : st.zref;
                 const float zs = e.z - st.zref;
                 if (SHADE) {
                     const float4 a0 = sm.a[0][k], a1 = sm.a[1][k];
@@ -407,8 +394,48 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                     st.zmed = e.z;
                     st.kmed = jpos + 1u;
                 }
-                st.T = Tn;
                 st.last = jpos + 1u;
+            };
+            if (PLAIN) {
+                // no per-wave bookkeeping: the lanes that do not blend skip the
+                // block, and the wave skips it when none does
+                if (px_live != 0u && e.pass) {
+                    eval_finish(g2, g3, rc.alpha_max, e);
+                    const float Tn = st.T * (1.0f - e.a);
+                    if (Tn < rc.t_min) {
+                        px_live = 0u;
+                    } else {
+                        accumulate(e.a * st.T);
+                        st.T = Tn;
+                    }
+                }
+                if (ballot64(px_live != 0u) == 0ull) {
+                    wave_done = true;
+                    break;
+                }
+                continue;
+            }
+            const bool done = px_live == 0u;
+            if (COUNT) {
+                n_reached += (uint64_t)__popcll(ballot64(!done));
+                n_witer += 1;
+                n_eval += done ? 0u : 1u;
+            }
+            bool blend = !done && e.pass;
+            // no pixel of this wave takes the entry: nothing changes
+            if (ballot64(blend) == 0ull) continue;
+            if (COUNT) n_wblend += 1;
+            eval_finish(g2, g3, rc.alpha_max, e);
+            const float Tn = st.T * (1.0f - e.a);
+            if (blend && Tn < rc.t_min) {
+                px_live = 0u;
+                blend = false;
+            }
+            float wgt = 0.f;
+            if (blend) {
+                wgt = e.a * st.T;
+                accumulate(wgt);
+                st.T = Tn;
                 if (COUNT) n_eval_last = n_eval;
             }
             if (COUNT) n_blended += (uint64_t)__popcll(ballot64(blend));
@@ -423,7 +450,7 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                     }
                 }
             }
-            if (ballot64(!done) == 0ull) {
+            if (ballot64(px_live != 0u) == 0ull) {
                 wave_done = true;
                 break;
             }
