@@ -5,8 +5,9 @@
 // outside is disqualified.  Section 3.1: a surfel carries position, shape
 // and appearance, all updated by backpropagation.
 //
-// One thread per surfel loops over the views, so the parameters (up to 232
-// bytes with degree-3 colour) are read from HBM once per batch.  Culling,
+// The parameters (up to 232 bytes with degree-3 colour) are read from HBM
+// once per batch: one thread per surfel loops over the views (large
+// batches), or the views of a surfel sit in adjacent lanes.  Culling,
 // the pixel rectangle and the depth key are evaluated in float64 in a fixed
 // operation order (no contraction, IEEE division and square root) so that
 // they are reproducible bit for bit; the records handed to the raster
@@ -19,6 +20,9 @@ namespace sr {
 namespace {
 
 constexpr double kGrid = 65536.0;   // the cutoff radii are rounded up to 2^-16
+// the surfel-loop projection kernel from this many surfels on (three
+// workgroups of 256 threads per compute unit)
+constexpr int kPreprocessLoopMinSurfels = 3 * 256 * 256;
 
 // Real spherical harmonics up to degree 3 (orthonormal, Condon-Shortley
 // phase), l-major, m = -l..l.  Constants: 1/(2 sqrt(pi)), sqrt(3/(4 pi)),
@@ -131,32 +135,73 @@ struct PreRec {
     uint32_t tiles, key;      // tiles = 0: culled (geom, app not written)
 };
 
-// DEG: SH degree of the colour (0..3), or -1 to skip shading (pruning pass).
-// Projects surfel g into view v; returns false when it is culled.
-template <int DEG>
-__device__ __forceinline__ bool project_record(int g, int v, int N, const float* __restrict__ means,
-                                               const float* __restrict__ scales, const float* __restrict__ quats,
-                                               const float* __restrict__ opac, const float* __restrict__ sh,
-                                               int sh_stride, float alpha_min, int tile_w, int tile_h,
-                                               const sr_camera* __restrict__ cams, PreRec& out) {
+// Colour of a surfel seen from campos: max(0, sum_k Y_k(d) f_k + 1/2) per
+// channel, d the unit direction from the camera centre to the surfel
+// (float32; coefficients at f[i * SH_STEP]).
+template <int DEG, int SH_STEP>
+__device__ __forceinline__ void view_colour(const float* mu32, const float* campos, const float* f, float* rgb) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    float d0 = mu32[0] - campos[0], d1 = mu32[1] - campos[1], d2 = mu32[2] - campos[2];
+    const float inv = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+    d0 *= inv; d1 *= inv; d2 *= inv;
+    float Y[16];
+    sh_basis(DEG, d0, d1, d2, Y);
+    rgb[0] = rgb[1] = rgb[2] = 0.5f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        rgb[0] = __builtin_fmaf(Y[k], f[(3 * k + 0) * SH_STEP], rgb[0]);
+        rgb[1] = __builtin_fmaf(Y[k], f[(3 * k + 1) * SH_STEP], rgb[1]);
+        rgb[2] = __builtin_fmaf(Y[k], f[(3 * k + 2) * SH_STEP], rgb[2]);
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0f ? rgb[ch] : 0.0f;
+}
+
+// The view-independent terms of a surfel's projection.
+struct SurfelTerms {
+    double mu[3], su, sv;
+    double tu[3], tv[3], nn[3];     // frame: columns of R(q / |q|)
+    double L, rs2, rf;              // ln(o / alpha_min), squared cutoff radii, low-pass radius
+    float o32;
+    bool cull_opac;
+};
+
+__device__ __forceinline__ void surfel_terms(int g, const float* __restrict__ means,
+                                             const float* __restrict__ scales, const float* __restrict__ quats,
+                                             const float* __restrict__ opac, float alpha_min, SurfelTerms& s) {
 #pragma clang fp contract(off)
-    const double mu[3] = {(double)means[3 * g], (double)means[3 * g + 1], (double)means[3 * g + 2]};
-    const double su = scales[2 * g], sv = scales[2 * g + 1];
-    const float o32 = opac[g];
-    const double o = o32;
+    s.mu[0] = means[3 * g]; s.mu[1] = means[3 * g + 1]; s.mu[2] = means[3 * g + 2];
+    s.su = scales[2 * g]; s.sv = scales[2 * g + 1];
+    s.o32 = opac[g];
+    const double o = s.o32;
     // unit quaternion and the frame (t_u, t_v, n) = columns of R(q)
     double w = quats[4 * g], x = quats[4 * g + 1], y = quats[4 * g + 2], z = quats[4 * g + 3];
     const double nrm = sqrt(((w * w + x * x) + y * y) + z * z);
     w = w / nrm; x = x / nrm; y = y / nrm; z = z / nrm;
-    const double tu[3] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y)};
-    const double tv[3] = {2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x)};
-    const double nn[3] = {2.0 * (x * z + w * y), 2.0 * (y * z - w * x), 1.0 - 2.0 * (x * x + y * y)};
+    s.tu[0] = 1.0 - 2.0 * (y * y + z * z); s.tu[1] = 2.0 * (x * y + w * z); s.tu[2] = 2.0 * (x * z - w * y);
+    s.tv[0] = 2.0 * (x * y - w * z); s.tv[1] = 1.0 - 2.0 * (x * x + z * z); s.tv[2] = 2.0 * (y * z + w * x);
+    s.nn[0] = 2.0 * (x * z + w * y); s.nn[1] = 2.0 * (y * z - w * x); s.nn[2] = 1.0 - 2.0 * (x * x + y * y);
     // cutoff radii: o G >= alpha_min  <=>  rho <= L
-    const double L = log(o / (double)alpha_min);
-    const double rs2 = ceil_grid(2.0 * L);
-    const double rf2 = ceil_grid(L);
-    const double rf = sqrt(rf2);
-    const bool cull_opac = o32 < alpha_min;
+    s.L = log(o / (double)alpha_min);
+    s.rs2 = ceil_grid(2.0 * s.L);
+    s.rf = sqrt(ceil_grid(s.L));
+    s.cull_opac = s.o32 < alpha_min;
+}
+
+// DEG: SH degree of the colour (0..3), or -1 to skip shading (pruning pass).
+// Projects surfel g (its view-independent terms s, its float32 centre mu32
+// and colour coefficients shg[i * SH_STEP]) into view v; returns false when
+// it is culled.
+template <int DEG, int SH_STEP>
+__device__ __forceinline__ bool project_view(const SurfelTerms& s, const float* mu32, const float* shg, int v,
+                                             int tile_wl, int tile_hl, const sr_camera* __restrict__ cams,
+                                             PreRec& out) {
+#pragma clang fp contract(off)
+    const double* mu = s.mu;
+    const double su = s.su, sv = s.sv, L = s.L, rs2 = s.rs2, rf = s.rf;
+    const double *tu = s.tu, *tv = s.tv, *nn = s.nn;
+    const float o32 = s.o32;
+    const bool cull_opac = s.cull_opac;
 
     Cam64 c;
     load_cam64(cams[v], c);
@@ -211,7 +256,7 @@ __device__ __forceinline__ bool project_record(int g, int v, int N, const float*
         out.rx = out.ry = 0u;
         return false;
     }
-    const int txlo = ilo / tile_w, txhi = ihi / tile_w, tylo = jlo / tile_h, tyhi = jhi / tile_h;
+    const int txlo = ilo >> tile_wl, txhi = ihi >> tile_wl, tylo = jlo >> tile_hl, tyhi = jhi >> tile_hl;
     out.tiles = (uint32_t)((txhi - txlo + 1) * (tyhi - tylo + 1));
     out.key = __float_as_uint((float)pz);
     out.rx = (uint32_t)ilo | ((uint32_t)ihi << 16);
@@ -230,23 +275,8 @@ __device__ __forceinline__ bool project_record(int g, int v, int N, const float*
     out.geom[2] = make_float4((float)Cs[2], cx32, cy32, o32);
     out.geom[3] = make_float4((float)m3[0], (float)m3[1], (float)m3[2], (float)L);
     if (DEG >= 0) {
-        constexpr int K = (DEG + 1) * (DEG + 1);
-        const float* cp = cams[v].campos;
-        float d0 = means[3 * g] - cp[0], d1 = means[3 * g + 1] - cp[1], d2 = means[3 * g + 2] - cp[2];
-        const float inv = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-        d0 *= inv; d1 *= inv; d2 *= inv;
-        float Y[16];
-        sh_basis(DEG, d0, d1, d2, Y);
-        const float* shg = sh + (size_t)g * sh_stride * 3;
-        float rgb[3] = {0.5f, 0.5f, 0.5f};
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            rgb[0] += Y[k] * shg[3 * k + 0];
-            rgb[1] += Y[k] * shg[3 * k + 1];
-            rgb[2] += Y[k] * shg[3 * k + 2];
-        }
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) rgb[ch] = rgb[ch] > 0.0f ? rgb[ch] : 0.0f;
+        float rgb[3];
+        view_colour<DEG, SH_STEP>(mu32, cams[v].campos, shg, rgb);
         out.app[0] = make_float4(rgb[0], rgb[1], rgb[2], (float)nc[0]);
         // the pixel rectangle packed in the last two slots (column and row
         // ranges): the compositing skips, per wave, entries whose rectangle
@@ -255,6 +285,18 @@ __device__ __forceinline__ bool project_record(int g, int v, int N, const float*
                                  __uint_as_float(out.ry));
     }
     return true;
+}
+
+template <int DEG>
+__device__ __forceinline__ bool project_record(int g, int v, const float* __restrict__ means,
+                                               const float* __restrict__ scales, const float* __restrict__ quats,
+                                               const float* __restrict__ opac, const float* __restrict__ sh,
+                                               int sh_stride, float alpha_min, int tile_wl, int tile_hl,
+                                               const sr_camera* __restrict__ cams, PreRec& out) {
+    SurfelTerms s;
+    surfel_terms(g, means, scales, quats, opac, alpha_min, s);
+    return project_view<DEG, 1>(s, means + 3 * g, DEG >= 0 ? sh + (size_t)g * sh_stride * 3 : nullptr, v, tile_wl,
+                                tile_hl, cams, out);
 }
 
 // Records of one workgroup staged in LDS (STAGED path).
@@ -277,7 +319,7 @@ __global__ void __launch_bounds__(256)
 k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ scales,
              const float* __restrict__ quats, const float* __restrict__ opac,
              const float* __restrict__ sh, int sh_stride, float alpha_min,
-             int tile_w, int tile_h, int V, const sr_camera* __restrict__ cams,
+             int tile_wl, int tile_hl, int V, const sr_camera* __restrict__ cams,
              float4* __restrict__ geom, float4* __restrict__ app, uint2* __restrict__ rect,
              uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_key,
              uint8_t* __restrict__ in_frustum) {
@@ -291,7 +333,7 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
     rec.rx = rec.ry = 0u;
     bool vis = false;
     if (live) {
-        vis = project_record<DEG>(g, v, N, means, scales, quats, opac, sh, sh_stride, alpha_min, tile_w, tile_h,
+        vis = project_record<DEG>(g, v, means, scales, quats, opac, sh, sh_stride, alpha_min, tile_wl, tile_hl,
                                   cams, rec);
         if (vis && in_frustum) in_frustum[g] = 1;
     }
@@ -351,6 +393,63 @@ k_preprocess(int N, const float* __restrict__ means, const float* __restrict__ s
             if (gg < N && sm.tiles[s] != 0u) app[2 * ((size_t)vv * N + gg) + q] = sm.app[q][s];
         }
     }
+}
+
+// One thread per surfel, looping over the views (for batches with enough
+// surfels to fill the device): the view-independent terms (unit quaternion,
+// frame, cutoff radii) and the colour coefficients are evaluated and loaded
+// once per surfel instead of once per (surfel, view), and the camera of an
+// iteration is uniform across the wave.  Each view's records are written at
+// r = v N + g, so a wave's stores of one view cover a contiguous run.  The
+// records are bit for bit those of k_preprocess (the same functions).
+template <int DEG>
+__global__ void __launch_bounds__(256)
+k_preprocess_views(int N, const float* __restrict__ means, const float* __restrict__ scales,
+                   const float* __restrict__ quats, const float* __restrict__ opac,
+                   const float* __restrict__ sh, int sh_stride, float alpha_min,
+                   int tile_wl, int tile_hl, int V, const sr_camera* __restrict__ cams,
+                   float4* __restrict__ geom, float4* __restrict__ app, uint2* __restrict__ rect,
+                   uint32_t* __restrict__ tiles_touched, uint32_t* __restrict__ depth_key,
+                   uint8_t* __restrict__ in_frustum) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    SurfelTerms s;
+    surfel_terms(g, means, scales, quats, opac, alpha_min, s);
+    const float mu32[3] = {means[3 * g], means[3 * g + 1], means[3 * g + 2]};
+    // colour coefficients: registers up to degree 1, a private LDS column per
+    // thread above (48 floats at degree 3 would cut the occupancy)
+    constexpr int K3 = DEG >= 0 ? 3 * (DEG + 1) * (DEG + 1) : 1;
+    constexpr bool SH_LDS = DEG >= 2;
+    __shared__ float s_sh[SH_LDS ? K3 : 1][SH_LDS ? 256 : 1];
+    float shr[SH_LDS ? 1 : K3];
+    if (DEG >= 0) {
+        const float* shg = sh + (size_t)g * sh_stride * 3;
+#pragma unroll
+        for (int i = 0; i < K3; ++i) {
+            if (SH_LDS) s_sh[i][threadIdx.x] = shg[i];
+            else shr[i] = shg[i];
+        }
+    }
+    bool any = false;
+    for (int v = 0; v < V; ++v) {
+        PreRec rec;
+        const bool vis = SH_LDS ? project_view<DEG, 256>(s, mu32, &s_sh[0][threadIdx.x], v, tile_wl, tile_hl, cams, rec)
+                                : project_view<DEG, 1>(s, mu32, shr, v, tile_wl, tile_hl, cams, rec);
+        const size_t r = (size_t)v * N + g;
+        tiles_touched[r] = rec.tiles;
+        depth_key[r] = rec.key;
+        rect[r] = make_uint2(rec.rx, rec.ry);
+        if (vis) {
+            any = true;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) geom[4 * r + q] = rec.geom[q];
+            if (DEG >= 0) {
+                app[2 * r + 0] = rec.app[0];
+                app[2 * r + 1] = rec.app[1];
+            }
+        }
+    }
+    if (any && in_frustum) in_frustum[g] = 1;
 }
 
 __global__ void k_zero_u8(uint8_t* __restrict__ p, int n) {
@@ -575,22 +674,33 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
                              uint32_t* tiles_touched, uint32_t* depth_key, uint8_t* in_frustum,
                              hipStream_t stream) {
     if (N == 0) return hipSuccess;
+    // the supported tile shapes are powers of two
+    if ((cfg.tile_w & (cfg.tile_w - 1)) != 0 || (cfg.tile_h & (cfg.tile_h - 1)) != 0) return hipErrorInvalidValue;
     if (in_frustum && !(cfg.flags & SR_FLAG_ACCUMULATE))
         hipLaunchKernelGGL(k_zero_u8, dim3((N + 255) / 256), dim3(256), 0, stream, in_frustum, N);
     const uint64_t threads = (uint64_t)N * (uint64_t)V;
     if (threads == 0) return hipGetLastError();
     dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     const int deg = app ? cfg.sh_degree : -1;
-    // staged writes when V divides the workgroup size (V a power of two <= 256)
+    // enough surfels for several workgroups of 256 per compute unit: one
+    // thread per surfel looping over the views; else one thread per (surfel,
+    // view), with staged writes when V divides the workgroup size (V a power
+    // of two <= 256)
+    const bool per_surfel = N >= kPreprocessLoopMinSurfels || V == 1;
+    const int twl = __builtin_ctz((unsigned)cfg.tile_w), thl = __builtin_ctz((unsigned)cfg.tile_h);
     const bool staged = V <= 256 && (256 % V) == 0;
 #define SR_PRE(D)                                                                                                 \
-    if (staged)                                                                                                   \
+    if (per_surfel)                                                                                               \
+        hipLaunchKernelGGL((k_preprocess_views<D>), dim3((N + 255) / 256), block, 0, stream, N, means, scales,    \
+                           quats, opac, sh, cfg.sh_stride, cfg.alpha_min, twl, thl, V, cams_dev,                  \
+                           (float4*)geom, (float4*)app, (uint2*)rect, tiles_touched, depth_key, in_frustum);      \
+    else if (staged)                                                                                              \
         hipLaunchKernelGGL((k_preprocess<D, true>), grid, block, 0, stream, N, means, scales, quats, opac, sh,    \
-                           cfg.sh_stride, cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev, (float4*)geom,      \
+                           cfg.sh_stride, cfg.alpha_min, twl, thl, V, cams_dev, (float4*)geom,                    \
                            (float4*)app, (uint2*)rect, tiles_touched, depth_key, in_frustum);                     \
     else                                                                                                          \
         hipLaunchKernelGGL((k_preprocess<D, false>), grid, block, 0, stream, N, means, scales, quats, opac, sh,   \
-                           cfg.sh_stride, cfg.alpha_min, cfg.tile_w, cfg.tile_h, V, cams_dev, (float4*)geom,      \
+                           cfg.sh_stride, cfg.alpha_min, twl, thl, V, cams_dev, (float4*)geom,                    \
                            (float4*)app, (uint2*)rect, tiles_touched, depth_key, in_frustum)
     switch (deg) {
         case 0: SR_PRE(0); break;

@@ -49,6 +49,62 @@ def test_binning_bit_exact(make):
     assert exempt == 0
 
 
+def _projection_records(sc, n, shade):
+    """Projection records (tiles, depth key, rectangle, geometry and, when
+    shading, appearance) of the first n surfels of sc, projected alone."""
+    views = ViewBatch(sc.cams)
+    rast = Rasterizer(n, views, sc.sh_degree, sh_stride=sc.sh.shape[1], shade=shade)
+    p = Params.from_scene(sc)
+    p = Params(p.means[:n].contiguous(), p.scales[:n].contiguous(), p.quats[:n].contiguous(),
+               p.opac[:n].contiguous(), p.sh[:n].contiguous())
+    rast.preprocess(p)
+    torch.cuda.synchronize()
+    V = sc.v
+    out = {"tiles": rast.tiles_touched[: V * n].cpu().numpy().view(np.uint32).reshape(V, n),
+           "key": rast.depth_key[: V * n].cpu().numpy().view(np.uint32).reshape(V, n),
+           "rect": rast.rect[: 4 * V * n].cpu().numpy().view(np.uint16).reshape(V, n, 4),
+           "geom": rast.geom[: V * n * 16].cpu().numpy().view(np.uint32).reshape(V, n, 16),
+           "in_frustum": rast.in_frustum[:n].cpu().numpy()}
+    if shade:
+        out["app"] = rast.app[: V * n * 8].cpu().numpy().view(np.uint32).reshape(V, n, 8)
+    return out
+
+
+@pytest.mark.parametrize("deg,shade", [(3, True), (1, True), (0, False)])
+def test_projection_kernels_agree(deg, shade):
+    """The projection has a one-thread-per-surfel kernel (looping over the
+    views; batches of 196608 surfels and more) and a one-thread-per-(surfel,
+    view) kernel (smaller batches; with four views its staged variant).
+    The same surfels projected in a batch of 200003 and in a batch of their
+    first 60001 give bit-identical records (every visible record's geometry
+    and appearance too), and the large batch's binning records equal the
+    oracle's."""
+    sc = scenes.make_random_scene(71, 200_003, n_views=4, width=[333, 64, 1000, 500], height=[201, 999, 77, 500],
+                                  sh_degree=deg, scale_range=(0.002, 0.05))
+    big = _projection_records(sc, sc.n, shade)
+    small = _projection_records(sc, 60_001, shade)
+    m = 60_001
+    for k in ("tiles", "key", "rect"):
+        np.testing.assert_array_equal(big[k][:, :m], small[k], err_msg=k)
+    vis = small["tiles"] != 0
+    assert vis.sum() > 1000 and (~vis).sum() > 100, (vis.sum(), (~vis).sum())
+    np.testing.assert_array_equal(big["geom"][:, :m][vis], small["geom"][vis])
+    if shade:
+        np.testing.assert_array_equal(big["app"][:, :m][vis], small["app"][vis])
+    np.testing.assert_array_equal(big["in_frustum"][:m], small["in_frustum"])
+    rp = oracle.RasterParams()
+    for v, cam in enumerate(sc.cams):
+        g = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, cam, rp)
+        ok = ~g["culled"]
+        mism = (big["tiles"][v] != g["tiles_touched"]) | (ok & (big["key"][v] != g["depth_bits"])) | \
+            (ok[:, None] & (big["rect"][v].astype(np.int64) != g["rect"])).any(axis=1)
+        bad = mism & ~g["grid_tie"]
+        assert not bad.any(), f"view {v}: {bad.sum()} records differ, e.g. {np.nonzero(bad)[0][:5]}"
+        print(f"view {v}: {int(ok.sum())} visible of {sc.n}, grid-tie exemptions {int(mism.sum())}")
+    np.testing.assert_array_equal(big["in_frustum"].astype(bool),
+                                  np.any([big["tiles"][v] != 0 for v in range(sc.v)], axis=0))
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (16, 8), (8, 8), (32, 8)])
 def test_every_tile_shape_bins_and_renders(tile):
     """Binning bit-exact and forward parity for each compiled tile shape."""
