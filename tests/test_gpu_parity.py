@@ -37,13 +37,31 @@ def _ragged_scene(seed=31, n=300, deg=0):
 # binning
 # --------------------------------------------------------------------------
 
+def _wide_depth_scene():
+    """Random scene plus surfels on view 0's optical axis from depth 0.25
+    to 50000: visible depth keys spanning more than 2^27 (every byte of
+    the key differs between the nearest and the farthest surfel)."""
+    sc = scenes.make_random_scene(33, 2000, n_views=2, width=[100, 129], height=[77, 50], scale_range=(0.01, 0.3))
+    depths = np.array([0.25, 0.3, 0.5, 20000.0, 35000.0, 50000.0])
+    k = depths.size
+    sc.means[:k] = np.stack([np.zeros(k), np.zeros(k), depths - 4.0], axis=1).astype(np.float32)
+    sc.scales[:k] = np.stack([depths * 0.02, depths * 0.03], axis=1).astype(np.float32)
+    sc.opac[:k] = 0.9
+    return sc
+
+
 @pytest.mark.parametrize("make", [lambda: _ragged_scene(), lambda: scenes.make_frame64_1k(),
                                   lambda: scenes.make_random_scene(32, 2000, n_views=2, width=[100, 129],
-                                                                   height=[77, 50], scale_range=(0.01, 0.6))])
+                                                                   height=[77, 50], scale_range=(0.01, 0.6)),
+                                  _wide_depth_scene])
 def test_binning_bit_exact(make):
     sc = make()
     run = gpu_run(sc, keys64=True)
     geoms = geometry(sc)
+    keys = np.concatenate([g["depth_bits"][~g["culled"]] for g in geoms]).astype(np.int64)
+    print(f"visible depth-key range {keys.max() - keys.min()}")
+    if make is _wide_depth_scene:
+        assert not geoms[0]["culled"][:6].any() and keys.max() - keys.min() >= (1 << 27)
     exempt = compare_binning(sc, run, geoms)
     print(f"binning exact; grid-tie exemptions: {exempt}")
     assert exempt == 0
