@@ -84,7 +84,10 @@ def parse():
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--tile", default="auto", help="WxH tile shape, or 'auto' to pick by timing")
+    ap.add_argument("--tile", default="auto",
+                    help="WxH tile shape, or 'auto' to pick the tile shape and backward batch by timing")
+    ap.add_argument("--bwd-batch", type=int, default=0,
+                    help="backward LDS batch with an explicit --tile (0: the library's default)")
     ap.add_argument("--no-unfused", action="store_true", help="skip timing the separate-launch step")
     ap.add_argument("--no-eq3", action="store_true", help="skip timing the step with the whole Eq. 3 loss")
     ap.add_argument("--prune-legs", action="store_true",
@@ -104,11 +107,12 @@ def make_scene(name):
 class Pipeline:
     """Persistent buffers and one training step over a set of views."""
 
-    def __init__(self, scene, cams, masks, targets, params, grads, stats, tile=(16, 16)):
+    def __init__(self, scene, cams, masks, targets, params, grads, stats, tile=(16, 16), bwd_batch=0):
         import torch
         from paper_2501_08174_amd.raster import Rasterizer, ViewBatch
         self.views = ViewBatch(cams, tile=tile)
-        self.rast = Rasterizer(scene.n, self.views, scene.sh_degree, sh_stride=scene.sh.shape[1])
+        self.rast = Rasterizer(scene.n, self.views, scene.sh_degree, sh_stride=scene.sh.shape[1],
+                               bwd_batch=bwd_batch)
         self.p, self.g, self.stats = params, grads, stats
         self.used = torch.zeros(scene.n, dtype=torch.int32, device="cuda")
         self.mask = torch.tensor(np.concatenate([m.reshape(-1) for m in masks]), device="cuda")
@@ -299,13 +303,14 @@ def main():
         from paper_2501_08174_amd.autotune import autotune
         mask = torch.tensor(np.concatenate([m.reshape(-1) for m in scene.masks]), device="cuda")
         target = torch.tensor(np.concatenate([t.reshape(-1) for t in scene.targets]), device="cuda")
-        tile = autotune(scene.cams, params, scene.sh_degree, scene.sh.shape[1], mask, target, use_cache=False,
-                        report=tune)
+        tile, bwd_batch = autotune(scene.cams, params, scene.sh_degree, scene.sh.shape[1], mask, target,
+                                   use_cache=False, report=tune)
         del mask, target
         torch.cuda.empty_cache()
     else:
         tile = tuple(int(x) for x in args.tile.split("x"))
-    pipe = Pipeline(scene, scene.cams, scene.masks, scene.targets, params, grads, stats, tile)
+        bwd_batch = args.bwd_batch
+    pipe = Pipeline(scene, scene.cams, scene.masks, scene.targets, params, grads, stats, tile, bwd_batch)
     P = pipe.views.P
 
     for _ in range(args.warmup):
@@ -336,7 +341,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {V} views, {P} px, {N} surfels, SH degree {scene.sh_degree}",
-                   "views": V, "pixels": P, "surfels": N, "mode": "batched", "tile": f"{tile[0]}x{tile[1]}"},
+                   "views": V, "pixels": P, "surfels": N, "mode": "batched", "tile": f"{tile[0]}x{tile[1]}",
+                   "bwd_batch": pipe.rast.cfg.bwd_batch},
         "autotune_ms": tune.get("ms"),
         "views_per_s": V / (ms_per_step * 1e-3),
         "median_step_ms_events": float(np.median(step_ms)),
@@ -531,7 +537,8 @@ def main():
     if not args.no_per_view:
         pipes = []
         for v in range(V):
-            pv = Pipeline(scene, [scene.cams[v]], [scene.masks[v]], [scene.targets[v]], params, grads, stats, tile)
+            pv = Pipeline(scene, [scene.cams[v]], [scene.masks[v]], [scene.targets[v]], params, grads, stats, tile,
+                          bwd_batch)
             pipes.append(pv)
         for _ in range(args.warmup):
             for pv in pipes:

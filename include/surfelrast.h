@@ -93,6 +93,12 @@ typedef struct sr_config {
     float alpha_max;          /* alpha clamp, float32(0.99)                   */
     float t_min;              /* transmittance stop, float32(1e-4)            */
     uint32_t flags;           /* SR_FLAG_*                                    */
+    int32_t bwd_batch;        /* records staged per LDS batch by the backward
+                                 compositing (sr_render_backward and the
+                                 training steps): 32, 64, 128 or 256, at most
+                                 the tile's pixel count; 0 picks
+                                 min(128, tile pixels).  A tuning knob: the
+                                 gradients are the same up to summation order */
 } sr_config;
 
 /* sr_render_forward / sr_prune_contrib: add to the statistics instead of
@@ -139,6 +145,11 @@ sr_status sr_read_status(sr_ctx *ctx, void *stream, int32_t clear, uint32_t *sta
 sr_status sr_clear_status(sr_ctx *ctx, void *stream);
 /* 1 if the tile shape is compiled in, else 0. */
 int32_t sr_tile_supported(int32_t tile_w, int32_t tile_h);
+
+/* 1 if the backward compositing is compiled with `batch` records per LDS
+ * batch for this tile shape (batch 0: the default, min(128, pixels)), else 0.
+ * Host only; no error is recorded. */
+int32_t sr_bwd_batch_supported(int32_t tile_w, int32_t tile_h, int32_t batch);
 
 /* Host only.  Fills tiles_x, tiles_y, tile_offset, pix_offset,
  * group_offset and groups_x of the V cameras for the given tile shape and

@@ -33,7 +33,7 @@ SR_NOALLOC_MAX_TILES = 262144
 
 EXPORTED = (
     "sr_last_error", "sr_version", "sr_create", "sr_destroy", "sr_read_status", "sr_clear_status",
-    "sr_tile_supported", "sr_layout_views", "sr_preprocess", "sr_bin_workspace_size", "sr_workspace_size",
+    "sr_tile_supported", "sr_bwd_batch_supported", "sr_layout_views", "sr_preprocess", "sr_bin_workspace_size", "sr_workspace_size",
     "sr_bin_and_sort", "sr_render_forward", "sr_render_backward", "sr_backward_raster", "sr_backward_project",
     "sr_loss_workspace_size", "sr_background_loss", "sr_regularizer_loss", "sr_ssim_workspace_size",
     "sr_ssim_loss", "sr_compact_workspace_size", "sr_compact_surfels", "sr_preprocess_3d", "sr_prune_stats_3d",
@@ -61,11 +61,12 @@ class SrConfig(ctypes.Structure):
     _fields_ = [
         ("tile_w", c_int32), ("tile_h", c_int32), ("sh_degree", c_int32), ("sh_stride", c_int32),
         ("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("flags", c_uint32),
+        ("bwd_batch", c_int32),
     ]
 
 
 assert ctypes.sizeof(SrCamera) == 128
-assert ctypes.sizeof(SrConfig) == 32
+assert ctypes.sizeof(SrConfig) == 36
 
 _lib = None
 P = c_void_p   # device or host pointer passed as an integer address
@@ -81,6 +82,7 @@ def _declare(lib):
         "sr_read_status": (c_int32, [V, V, c_int32, V, V]),
         "sr_clear_status": (c_int32, [V, V]),
         "sr_tile_supported": (c_int32, [c_int32, c_int32]),
+        "sr_bwd_batch_supported": (c_int32, [c_int32, c_int32, c_int32]),
         "sr_layout_views": (c_int32, [V, c_int32, c_int32, c_int32, POINTER(c_int64), POINTER(c_int32)]),
         "sr_preprocess": (c_int32, [V, V, c_int32, V, V, V, V, V, c_int32, V, V, V, V, V, V, V, V, V]),
         "sr_bin_workspace_size": (c_int32, [c_int32, c_int32, c_uint32, POINTER(c_size_t)]),

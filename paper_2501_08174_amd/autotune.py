@@ -1,9 +1,11 @@
-"""Tile-shape autotuner for the compositing kernels.
+"""Autotuner for the compositing kernels: tile shape x backward LDS batch.
 
 Times one full training step (projection, binning, forward with the usage
-counts, loss, backward) for every compiled tile shape on the caller's own
-workload and keeps the fastest.  Results are cached in a JSON file keyed by
-GPU architecture, resolution bucket, surfel-count bucket and SH degree.
+counts, loss, backward) for every compiled tile shape and, for each, every
+compiled backward batch (records staged per LDS batch: 32, 64, 128, 256 up
+to the tile's pixel count) on the caller's own workload, and keeps the
+fastest pair.  Results are cached in a JSON file keyed by GPU architecture,
+resolution bucket, surfel-count bucket and SH degree.
 """
 from __future__ import annotations
 
@@ -18,6 +20,7 @@ from . import _lib
 from .raster import Params, Rasterizer, ViewBatch
 
 CANDIDATES: Tuple[Tuple[int, int], ...] = ((16, 16), (16, 8), (8, 8), (32, 8))
+BATCHES: Tuple[int, ...] = (32, 64, 128, 256)
 CACHE = os.environ.get("SR_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "surfelrast",
                                                          "autotune.json"))
 
@@ -72,16 +75,17 @@ def time_step(rast: Rasterizer, p: Params, g: Params, mask, target, stats=None, 
 
 
 def autotune(cams: Sequence, p: Params, sh_degree: int, sh_stride: int, mask, target,
-             candidates: Sequence[Tuple[int, int]] = CANDIDATES, steps: int = 3, use_cache: bool = True,
-             report: Optional[dict] = None) -> Tuple[int, int]:
-    """Fastest compiled tile shape for this workload (times each candidate)."""
+             candidates: Sequence[Tuple[int, int]] = CANDIDATES, batches: Sequence[int] = BATCHES, steps: int = 3,
+             use_cache: bool = True, report: Optional[dict] = None) -> Tuple[Tuple[int, int], int]:
+    """Fastest compiled (tile shape, backward batch) for this workload: times
+    every pair, returns ((tile_w, tile_h), batch)."""
     n = p.means.shape[0]
     key = cache_key(cams, n, sh_degree)
     cache = _load() if use_cache else {}
-    if key in cache:
+    if key in cache and "batch" in cache[key]:
         if report is not None:
             report.update(cache[key])
-        return tuple(cache[key]["tile"])
+        return tuple(cache[key]["tile"]), int(cache[key]["batch"])
     l = _lib.lib()
     g = Params(*[torch.zeros_like(t) for t in (p.means, p.scales, p.quats, p.opac, p.sh)])
     used = torch.zeros(n, dtype=torch.int32, device=p.means.device)
@@ -92,15 +96,20 @@ def autotune(cams: Sequence, p: Params, sh_degree: int, sh_stride: int, mask, ta
         views = ViewBatch(cams, tile=(tw, th))
         rast = Rasterizer(n, views, sh_degree, sh_stride=sh_stride)
         rast.plan_capacity(p, slack=1.02)
-        times[f"{tw}x{th}"] = time_step(rast, p, g, mask, target, used, steps)
+        for b in batches:
+            if not l.sr_bwd_batch_supported(tw, th, b):
+                continue
+            rast.set_bwd_batch(b)
+            times[f"{tw}x{th}/b{b}"] = time_step(rast, p, g, mask, target, used, steps)
         del rast
         torch.cuda.empty_cache()
     best = min(times, key=times.get)
-    tile = tuple(int(x) for x in best.split("x"))
-    entry = {"tile": list(tile), "ms": times}
+    ts, bs = best.split("/b")
+    tile = tuple(int(x) for x in ts.split("x"))
+    entry = {"tile": list(tile), "batch": int(bs), "ms": times}
     if use_cache:
         cache[key] = entry
         _store(cache)
     if report is not None:
         report.update(entry)
-    return tile
+    return tile, int(bs)

@@ -55,6 +55,9 @@ sr_status check_cfg(const sr_config* cfg) {
     if (!(cfg->alpha_min > 0.f && cfg->alpha_min < cfg->alpha_max && cfg->alpha_max < 1.f))
         return fail(SR_ERR_ARG, "need 0 < alpha_min < alpha_max < 1");
     if (!(cfg->t_min > 0.f && cfg->t_min < 1.f)) return fail(SR_ERR_ARG, "need 0 < t_min < 1");
+    if (cfg->bwd_batch != 0 && !sr::bwd_batch_supported(cfg->tile_w, cfg->tile_h, cfg->bwd_batch))
+        return fail(SR_ERR_UNSUPPORTED, "backward batch %d is not compiled in for %dx%d tiles", cfg->bwd_batch,
+                    cfg->tile_w, cfg->tile_h);
     return SR_OK;
 }
 
@@ -124,7 +127,7 @@ extern "C" {
 
 const char* sr_last_error(void) { return g_err; }
 
-int32_t sr_version(void) { return 2; }
+int32_t sr_version(void) { return 3; }
 
 sr_status sr_create(sr_ctx** ctx_out_host, int32_t device) {
     if (!ctx_out_host) return fail(SR_ERR_ARG, "ctx_out_host is NULL");
@@ -191,6 +194,10 @@ sr_status sr_clear_status(sr_ctx* ctx, void* stream) {
 }
 
 int32_t sr_tile_supported(int32_t tile_w, int32_t tile_h) { return sr::tile_shape_supported(tile_w, tile_h) ? 1 : 0; }
+
+int32_t sr_bwd_batch_supported(int32_t tile_w, int32_t tile_h, int32_t batch) {
+    return sr::bwd_batch_supported(tile_w, tile_h, batch) ? 1 : 0;
+}
 
 sr_status sr_layout_views(sr_camera* cams_host, int32_t V, int32_t tile_w, int32_t tile_h,
                           int64_t* total_pixels_host, int32_t* total_tiles_host) {

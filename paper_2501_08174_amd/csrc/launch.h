@@ -35,6 +35,8 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_rebase_cams(const sr_camera* src, int Vc, sr_camera* dst, hipStream_t s);
 
 bool tile_shape_supported(int tw, int th);
+// a backward batch compiled for the tile shape (0: the default one)
+bool bwd_batch_supported(int tw, int th, int batch);
 
 hipError_t fill_f32(float* p, float v, uint64_t n, hipStream_t s);
 

@@ -15,6 +15,8 @@
 // decisions.
 #include <mutex>
 
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -900,9 +902,30 @@ __global__ void k_prune_mask(int N, const float* __restrict__ max_alpha, float t
     if (g < N) mask[g] = (!failed && max_alpha[g] < tau) ? 1 : 0;
 }
 
-// Records per LDS batch of the backward (fewer than the workgroup size keeps
-// the LDS footprint, and hence occupancy, in check).
+// Records per LDS batch of the backward: compiled for 32, 64, 128 and 256,
+// each at most the tile's pixel count (one staging thread per record).  The
+// default, min(128, pixels), keeps the separate backward's LDS footprint and
+// hence its occupancy in check; in the fused kernel the forward's staging
+// area is as large, so only 256 costs occupancy there.
 constexpr int kBwdBatch = 128;
+
+constexpr int resolve_batch(int pixels, int batch) {
+    return batch != 0 ? batch : (pixels < kBwdBatch ? pixels : kBwdBatch);
+}
+
+// Calls f(integral_constant<int, B>) for the compiled batch B == batch (a
+// value of resolve_batch); false when it is not compiled for this tile.
+template <int PIX, typename F>
+bool with_batch(int batch, F&& f) {
+    switch (batch) {
+        case 32: if constexpr (32 <= PIX) { f(std::integral_constant<int, 32>{}); return true; } break;
+        case 64: if constexpr (64 <= PIX) { f(std::integral_constant<int, 64>{}); return true; } break;
+        case 128: if constexpr (128 <= PIX) { f(std::integral_constant<int, 128>{}); return true; } break;
+        case 256: if constexpr (256 <= PIX) { f(std::integral_constant<int, 256>{}); return true; } break;
+        default: break;
+    }
+    return false;
+}
 
 template <int TW, int TH, int MODE>
 void fwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
@@ -943,41 +966,46 @@ bool fwd_dispatch(int mode, int total_tiles, hipStream_t s, const sr_camera* cam
 }
 
 template <int TW, int TH>
-void bwd_launch(int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
+bool bwd_launch(int batch, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N, const float4* geom,
                 const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, const float* alpha,
                 const float* depth, const float* dist, const float* T_final, const uint32_t* n_contrib,
                 const float* dC, const float* dA, const float* dD, const float* dN, const float* dS,
                 const uint32_t* median_contrib, const float* dMed, float* grad_rec, const uint32_t* tile_order) {
-    constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
-    if (dD || dN || dS || dMed)
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom,
-                           app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
-                           median_contrib, dMed, grad_rec, tile_order);
-    else
-        hipLaunchKernelGGL((k_render_bwd<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
-                           geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS,
-                           median_contrib, dMed, grad_rec, tile_order);
+    const bool geo = dD || dN || dS || dMed;
+    return with_batch<TW * TH>(resolve_batch(TW * TH, batch), [&](auto bc) {
+        constexpr int B = decltype(bc)::value;
+        if (geo)
+            hipLaunchKernelGGL((k_render_bwd<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
+                               geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN,
+                               dS, median_contrib, dMed, grad_rec, tile_order);
+        else
+            hipLaunchKernelGGL((k_render_bwd<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
+                               geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN,
+                               dS, median_contrib, dMed, grad_rec, tile_order);
+    });
 }
 
 template <int TW, int TH>
-void train_launch(int stats, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
+bool train_launch(int stats, int batch, int total_tiles, hipStream_t s, const sr_camera* cams, int V, int N,
                   const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc,
                   const uint8_t* mask, const float* target, float gamma, float w_c, float* color, float* alpha,
                   float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits,
                   float* max_alpha, float* max_weight, float* tile_loss, float* grad_rec, const uint32_t* tile_order,
                   uint32_t* tile_cost) {
-    constexpr int B = (TW * TH < kBwdBatch) ? TW * TH : kBwdBatch;
+    return with_batch<TW * TH>(resolve_batch(TW * TH, batch), [&](auto bc) {
+        constexpr int B = decltype(bc)::value;
 #define SR_TRAIN(S)                                                                                              \
     hipLaunchKernelGGL((k_train_raster<TW, TH, B, S>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, \
                        app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist, T_final, \
                        n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec, tile_order, tile_cost)
-    if (stats == 2)
-        SR_TRAIN(2);
-    else if (stats == 1)
-        SR_TRAIN(1);
-    else
-        SR_TRAIN(0);
+        if (stats == 2)
+            SR_TRAIN(2);
+        else if (stats == 1)
+            SR_TRAIN(1);
+        else
+            SR_TRAIN(0);
 #undef SR_TRAIN
+    });
 }
 
 // Compiled tile shapes (the binning takes any shape; the raster kernels are
@@ -991,6 +1019,12 @@ bool tile_shape_supported(int tw, int th) {
     SR_TILE_SHAPES(SR_TS)
 #undef SR_TS
     return false;
+}
+
+bool bwd_batch_supported(int tw, int th, int batch) {
+    if (!tile_shape_supported(tw, th)) return false;
+    const int b = resolve_batch(tw * th, batch);
+    return (b == 32 || b == 64 || b == 128 || b == 256) && b <= tw * th;
 }
 
 hipError_t fill_f32(float* p, float v, uint64_t n, hipStream_t s) {
@@ -1036,9 +1070,10 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
 #define SR_TS(W, H)                                                                                            \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                 \
-        bwd_launch<W, H>(total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, vals,          \
-                         (const uint2*)ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN, dS, \
-                         median_contrib, dMed, grad_rec, tile_order);                                         \
+        if (!bwd_launch<W, H>(cfg.bwd_batch, total_tiles, s, cams, V, N, (const float4*)geom,                 \
+                              (const float4*)app, vals, (const uint2*)ranges, rc, alpha, depth, dist, T_final,  \
+                              n_contrib, dC, dA, dD, dN, dS, median_contrib, dMed, grad_rec, tile_order))       \
+            return hipErrorInvalidValue;                                                                      \
         return hipGetLastError();                                                                             \
     }
     SR_TILE_SHAPES(SR_TS)
@@ -1057,10 +1092,11 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
 #define SR_TS(W, H)                                                                                               \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                    \
-        train_launch<W, H>(hits ? (max_alpha ? 2 : 1) : 0, total_tiles, s, cams, V, N, (const float4*)geom, (const float4*)app, \
-                           vals, (const uint2*)ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, \
-                           dist, T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec,           \
-                           tile_order, tile_cost);                                                                \
+        if (!train_launch<W, H>(hits ? (max_alpha ? 2 : 1) : 0, cfg.bwd_batch, total_tiles, s, cams, V, N,      \
+                                (const float4*)geom, (const float4*)app, vals, (const uint2*)ranges, rc, mask,   \
+                                target, gamma, w_c, color, alpha, depth, normal, dist, T_final, n_contrib, hits, \
+                                max_alpha, max_weight, tile_loss, grad_rec, tile_order, tile_cost))             \
+            return hipErrorInvalidValue;                                                                         \
         return hipGetLastError();                                                                                \
     }
     SR_TILE_SHAPES(SR_TS)

@@ -53,10 +53,12 @@ def _ctx(t: torch.Tensor):
 
 
 def make_config(sh_degree: int = 0, sh_stride: Optional[int] = None, tile=(16, 16), flags: int = 0,
-                alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, t_min=T_MIN) -> SrConfig:
+                alpha_min=ALPHA_MIN, alpha_max=ALPHA_MAX, t_min=T_MIN, bwd_batch: int = 0) -> SrConfig:
+    """Renderer configuration; bwd_batch: records per LDS batch of the
+    backward compositing (32/64/128/256, 0: the library's default)."""
     K = (sh_degree + 1) ** 2
     return SrConfig(tile[0], tile[1], sh_degree, K if sh_stride is None else sh_stride,
-                    alpha_min, alpha_max, t_min, flags)
+                    alpha_min, alpha_max, t_min, flags, bwd_batch)
 
 
 class ViewBatch:
@@ -128,10 +130,11 @@ class Rasterizer:
     """
 
     def __init__(self, N: int, views: ViewBatch, sh_degree: int, sh_stride: Optional[int] = None,
-                 capacity: int = 0, device="cuda", shade: bool = True):
+                 capacity: int = 0, device="cuda", shade: bool = True, bwd_batch: int = 0):
         self.N, self.views, self.device = int(N), views, device
         self.ctx = _lib.Context(_device_index(device))
         self.cfg = make_config(sh_degree, sh_stride, views.tile)
+        self.set_bwd_batch(bwd_batch)
         self.shade = shade
         V, P, T = views.V, views.P, views.T
         VN = V * self.N
@@ -186,6 +189,14 @@ class Rasterizer:
         return need
 
     # -- steps ------------------------------------------------------------
+    def set_bwd_batch(self, batch: int):
+        """Records per LDS batch of the backward compositing (0: the
+        library's default for the tile shape)."""
+        tw, th = self.views.tile
+        if not _lib.lib().sr_bwd_batch_supported(tw, th, int(batch)):
+            raise ValueError(f"backward batch {batch} is not compiled for {tw}x{th} tiles")
+        self.cfg.bwd_batch = int(batch)
+
     def preprocess(self, p: Params, stream=None):
         call("sr_preprocess", self.ctx.ptr, ctypes.byref(self.cfg), self.N, _ptr(p.means), _ptr(p.scales), _ptr(p.quats),
              _ptr(p.opac), _ptr(p.sh), self.views.V, self.views.host_ptr, _ptr(self.views.dev), _ptr(self.geom),

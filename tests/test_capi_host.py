@@ -69,6 +69,17 @@ def test_argument_errors_before_launch(lib):
     assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_UNSUPPORTED
     assert l.sr_tile_supported(16, 16) == 1 and l.sr_tile_supported(8, 8) == 1 and l.sr_tile_supported(7, 3) == 0
+    # backward LDS batches: 32..256, at most the tile's pixels (0: the default)
+    for b in (0, 32, 64, 128, 256):
+        assert l.sr_bwd_batch_supported(16, 16, b) == 1 and l.sr_bwd_batch_supported(32, 8, b) == 1
+    assert l.sr_bwd_batch_supported(16, 8, 128) == 1 and l.sr_bwd_batch_supported(16, 8, 256) == 0
+    assert l.sr_bwd_batch_supported(8, 8, 0) == 1 and l.sr_bwd_batch_supported(8, 8, 64) == 1
+    assert l.sr_bwd_batch_supported(8, 8, 128) == 0 and l.sr_bwd_batch_supported(16, 16, 48) == 0
+    assert l.sr_bwd_batch_supported(7, 3, 0) == 0
+    cfg = SrConfig(8, 8, 0, 1, 1 / 255, 0.99, 1e-4, 0, 128)
+    assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
+                           None, None, None, None) == lib.SR_ERR_UNSUPPORTED
+    assert b"batch" in l.sr_last_error()
     cfg = SrConfig(16, 16, 4, 25, 1 / 255, 0.99, 1e-4, 0)
     assert l.sr_preprocess(None, ctypes.byref(cfg), 0, None, None, None, None, None, 0, None, None, None, None, None,
                            None, None, None, None) == lib.SR_ERR_UNSUPPORTED

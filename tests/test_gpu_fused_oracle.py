@@ -18,6 +18,7 @@ from paper_2501_08174_amd import scenes
 from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch
 from tests.gpu_helpers import (clamp_tie_ids, compare_forward, compare_grads, crop_pixels, masked_loss_fn,
                                masked_terms, per_view)
+from tests.test_gpu_parity import BWD_VARIANTS
 
 pytestmark = pytest.mark.gpu
 RP = oracle.RasterParams()
@@ -30,12 +31,12 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _fused(sc, masks, targets, gamma, w_c, level):
+def _fused(sc, masks, targets, gamma, w_c, level, tile=(16, 16), bwd_batch=0):
     """One fused step on the GPU: level 0 no statistics, 1 the usage counts,
     2 counts and both maxima.  Returns the rasterizer (outputs), the loss
     vector, the statistics and the five parameter gradients."""
-    views = ViewBatch(sc.cams)
-    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1])
+    views = ViewBatch(sc.cams, tile=tile)
+    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1], bwd_batch=bwd_batch)
     p = Params.from_scene(sc)
     rast.plan_capacity(p)
     rast.preprocess(p)
@@ -111,6 +112,51 @@ def test_fused_step_matches_oracle_small(level):
     print(f"surfels used {(st['hits'] > 0).sum()} of {sc.n}; clamp-tie surfels left out of the gradients "
           f"{excl.size}")
     compare_grads(g, P64.grads(), excl)
+
+
+@pytest.fixture(scope="module")
+def _small_ref():
+    """The ragged three-view scene's masked losses, statistics and gradients
+    from the oracle (ties taken as the GPU's forward took them)."""
+    sc = _ragged(seed=63, n=400)
+    rng = np.random.default_rng(64)
+    masks = [rng.integers(0, 2, size=(c.height, c.width)).astype(np.uint8) for c in sc.cams]
+    targets = [rng.uniform(size=(3, c.height, c.width)).astype(np.float32) for c in sc.cams]
+    gamma, w_c = 0.5, 1.0
+    rast, _, _, _ = _fused(sc, masks, targets, gamma, w_c, 2)
+    V = sc.v
+    P64 = Params64.from_arrays(sc.means, sc.scales, sc.quats, sc.opac, sc.sh, sc.sh_degree, requires_grad=True)
+    pairs, excl, losses = [], [], np.zeros(2 * V + 1)
+    for v, cam in enumerate(sc.cams):
+        HW = cam.width * cam.height
+        pix = crop_pixels(0, 0, cam.width, cam.height)
+        geom = oracle.view_geometry64(sc.means, sc.scales, sc.quats, sc.opac, cam, RP)
+        res = render_pixels(P64, cam, geom, pix, RP)
+        _, _, rep = compare_forward(per_view(rast, v), res, pix, rast, v, oracle_ctx=(P64, cam, geom, RP))
+        assert not rep["unresolved"]
+        lf = masked_loss_fn(masks[v], targets[v], pix, HW, V, gamma, w_c)
+        resg = render_pixels(P64, cam, geom, pix, RP, loss_fn=lf, flips=rep["choice"])
+        pairs.append(resg["pairs"])
+        excl.append(clamp_tie_ids(res))
+        l1, lb = masked_terms(resg, masks[v], targets[v], pix, HW)
+        losses[v], losses[V + v] = lb, l1
+        losses[2 * V] += (w_c * l1 + gamma * lb) / V
+    st = oracle.prune_stats64(sc.n, pairs)
+    return sc, masks, targets, gamma, w_c, losses, st, P64.grads(), np.unique(np.concatenate(excl))
+
+
+@pytest.mark.parametrize("tile,batch", BWD_VARIANTS, ids=[f"{t[0]}x{t[1]}-b{b}" for t, b in BWD_VARIANTS])
+def test_fused_step_every_lds_batch(_small_ref, tile, batch):
+    """The fused step (full statistics) with every compiled tile shape and
+    backward LDS batch: losses, statistics and gradients against the
+    oracle."""
+    sc, masks, targets, gamma, w_c, losses, st, gref, excl = _small_ref
+    _, loss, stats, g = _fused(sc, masks, targets, gamma, w_c, 2, tile=tile, bwd_batch=batch)
+    np.testing.assert_allclose(loss, losses, rtol=1e-5, atol=1e-8)
+    np.testing.assert_array_equal(stats[0], st["hits"])
+    np.testing.assert_allclose(stats[1], st["max_alpha"], atol=1e-5, rtol=0)
+    np.testing.assert_allclose(stats[2], st["max_weight"], atol=1e-5, rtol=0)
+    compare_grads(g, gref, excl)
 
 
 def _crop_runs(sc, v, x0, y0, w=64, h=64, level=1):

@@ -232,9 +232,9 @@ def _weights(sc, rng):
     return w
 
 
-def _gpu_grads(sc, w):
-    views = ViewBatch(sc.cams)
-    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1])
+def _gpu_grads(sc, w, tile=(16, 16), bwd_batch=0):
+    views = ViewBatch(sc.cams, tile=tile)
+    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1], bwd_batch=bwd_batch)
     p = Params.from_scene(sc)
     rast.plan_capacity(p)
     leaves = [t.clone().requires_grad_(True) for t in (p.means, p.scales, p.quats, p.opac, p.sh)]
@@ -295,6 +295,35 @@ def test_backward_matches_oracle_autograd(deg):
     g, rast = _gpu_grads(sc, w)
     gref, excl = _oracle_grads(sc, w, geometry(sc), rast)
     print("surfels left out (an entry at the alpha clamp):", len(excl))
+    compare_grads(g, gref, excl)
+
+
+# every compiled (tile shape, backward LDS batch)
+BWD_VARIANTS = ([((16, 16), b) for b in (32, 64, 128, 256)] + [((32, 8), b) for b in (32, 64, 128, 256)] +
+                [((16, 8), b) for b in (32, 64, 128)] + [((8, 8), b) for b in (32, 64)])
+
+
+@pytest.fixture(scope="module")
+def _bwd_case():
+    """A scene, upstream weights of all five outputs and the oracle's
+    gradients (ties taken as the GPU's forward took them: the forward does
+    not depend on the tile shape or the batch)."""
+    sc = scenes.make_random_scene(46, 200, n_views=2, width=[48, 37], height=[40, 51], sh_degree=3,
+                                  spread=0.6, scale_range=(0.03, 0.3))
+    w = _weights(sc, np.random.default_rng(8))
+    _, rast = _gpu_grads(sc, w)
+    gref, excl = _oracle_grads(sc, w, geometry(sc), rast)
+    return sc, w, gref, excl
+
+
+@pytest.mark.parametrize("tile,batch", BWD_VARIANTS, ids=[f"{t[0]}x{t[1]}-b{b}" for t, b in BWD_VARIANTS])
+def test_backward_every_lds_batch(_bwd_case, tile, batch):
+    """The backward compositing with every compiled LDS batch and tile shape
+    (the autotuner's search space) against the oracle's gradients."""
+    from paper_2501_08174_amd import _lib
+    assert _lib.lib().sr_bwd_batch_supported(tile[0], tile[1], batch) == 1
+    sc, w, gref, excl = _bwd_case
+    g, _ = _gpu_grads(sc, w, tile=tile, bwd_batch=batch)
     compare_grads(g, gref, excl)
 
 
