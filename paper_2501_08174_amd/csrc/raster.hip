@@ -193,6 +193,23 @@ __device__ __forceinline__ uint64_t wave_live_mask_from(const float4* __restrict
     return ballot64(live);
 }
 
+// Wave bits of the staged entries kept from the forward to the backward of
+// the fused step (LDS, 4 bits per run position, 16 bytes per thread of the
+// workgroup: positions below 32 per thread; the backward recomputes the bits
+// of later positions).  The backward stages only positions the forward
+// staged (below the largest last contributor), so every cached position it
+// reads was written.
+template <int NT>
+struct BitCache {
+    static constexpr int kWords = 4 * NT;
+    static constexpr uint32_t kPos = 8u * kWords;
+};
+
+template <int NT>
+__device__ __forceinline__ void bitcache_put(uint32_t* c, uint32_t jpos, uint32_t bits) {
+    if (jpos < BitCache<NT>::kPos) atomicOr(&c[jpos >> 3], bits << ((jpos & 7u) << 2));
+}
+
 // Per-pixel state at the end of the forward pass.
 struct PixFwd {
     float T, C0, C1, C2, N0, N1, N2, S0, S1, S2, zref, zmed;
@@ -282,7 +299,9 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                                          FwdSmem<NT, MODE>& sm, PixFwd& st,
                                          uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
                                          float* __restrict__ max_weight, uint64_t& n_reached, uint64_t& n_blended,
-                                         uint64_t& n_witer, uint64_t& n_wblend, uint64_t& n_upto_last) {
+                                         uint64_t& n_witer, uint64_t& n_wblend, uint64_t& n_upto_last,
+                                         uint32_t* bitcache = nullptr) {
+    static_assert(NT / 64 <= 4, "four wave bits per cached entry");
     constexpr bool SHADE = (MODE & kShade) != 0;
     constexpr bool STATS = (MODE & kStats) != 0;              // hits and the two maxima
     constexpr bool HITS = STATS || (MODE & kHits) != 0;       // hits (blended pixels per surfel)
@@ -347,6 +366,7 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
                 sm.a[0][tid] = a0;
                 n12 = make_float2(a1.x, a1.y);
+                if (bitcache) bitcache_put<NT>(bitcache, jpos, bits);
             }
             // the run position and the wave bits replace the packed rectangle
             sm.a[1][tid] = make_float4(n12.x, n12.y, __uint_as_float(jpos), __uint_as_float(bits));
@@ -614,7 +634,8 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, BwdSmem<BATCH>& sm, PixBwd pb,
                                          float* __restrict__ grad_rec, uint32_t* __restrict__ hits = nullptr,
-                                         uint32_t* __restrict__ cost_out = nullptr) {
+                                         uint32_t* __restrict__ cost_out = nullptr,
+                                         const uint32_t* bitcache = nullptr) {
     static_assert(BATCH <= NT, "one record per thread and batch");
     static_assert(!(HITS && GEO), "the count takes a component slot of the depth terms");
     const int tid = threadIdx.x;
@@ -662,7 +683,10 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                     sm.g[q][tid] = gq[q];
                 }
                 const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
-                const uint32_t bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                // the forward's wave bits of this position when cached
+                const uint32_t bits = (bitcache && jpos < BitCache<NT>::kPos)
+                                          ? (bitcache[jpos >> 3] >> ((jpos & 7u) << 2)) & 0xFu
+                                          : band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
                 sm.a[0][tid] = a0;
                 // entries at or beyond the wave's last contributor concern no lane of it
                 sm.a[1][tid] = make_float4(a1.x, a1.y, __uint_as_float(jpos), __uint_as_float(bits));
@@ -832,6 +856,10 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     constexpr size_t kF = sizeof(FwdSmem<NT, MODE>), kB = sizeof(BwdSmem<BATCH>);
     __shared__ __align__(16) unsigned char smem[kF > kB ? kF : kB];
     __shared__ float s_red[NT];
+    // the wave-bit cache, except with the full statistics (whose larger
+    // forward staging would lose a workgroup per CU to the extra LDS)
+    constexpr bool CACHE = STATS != 2;
+    __shared__ uint32_t s_bits[CACHE ? BitCache<NT>::kWords : 1];
     TileCtx t;
     // an order entry beyond the grid leaves the workgroup idle (not a valid
     // permutation: nothing of it is written)
@@ -843,9 +871,12 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     const float px = (float)t.ix + 0.5f, py = (float)t.iy + 0.5f;
     PixFwd st;
     uint64_t n0 = 0, n1 = 0, n2 = 0, n3 = 0, n4 = 0;
+    if (CACHE) {
+        for (int i = threadIdx.x; i < BitCache<NT>::kWords; i += NT) s_bits[i] = 0u;
+        __syncthreads();
+    }
     fwd_tile<TW, NT, MODE>(t, px, py, N, geom, app, nullptr, vals, rc, *reinterpret_cast<FwdSmem<NT, MODE>*>(smem), st,
-                           hits,
-                       max_alpha, max_weight, n0, n1, n2, n3, n4);
+                           hits, max_alpha, max_weight, n0, n1, n2, n3, n4, CACHE ? s_bits : nullptr);
     if (failed) poison(st);
     const PixOut o = pix_outputs(st, t);
     PixBwd pb;
@@ -886,7 +917,7 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile + 1] = s_red[0];
     bwd_tile<TW, NT, BATCH, false, STATS == 1>(t, px, py, N, geom, app, vals, rc,
                                                *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec, hits,
-                                               tile_cost ? tile_cost + t.tile : nullptr);
+                                               tile_cost ? tile_cost + t.tile : nullptr, CACHE ? s_bits : nullptr);
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, float v, uint64_t n) {
