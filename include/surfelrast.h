@@ -104,6 +104,14 @@ typedef struct sr_config {
 /* sr_render_forward / sr_prune_contrib: add to the statistics instead of
  * overwriting them (accumulation across views and calls). */
 #define SR_FLAG_ACCUMULATE 1u
+/* sr_backward_project: consume only the records marked by the compositing
+ * backward (bit 31 of tiles_touched, set through grad_marks of
+ * sr_backward_raster / sr_train_step_raster), and clear the marks.  Every
+ * compositing backward since the last sr_backward_project must then have
+ * been given the marks (records it added to without marking would be left
+ * in grad_rec); marks are lost when sr_preprocess rewrites tiles_touched,
+ * so grad_rec is consumed before the next projection. */
+#define SR_FLAG_MARKED_GRADIENTS 2u
 
 /* Per-record float counts of the intermediate buffers. */
 #define SR_GEOM_STRIDE 16   /* geometry record per (view, surfel)          */
@@ -285,10 +293,17 @@ sr_status sr_render_backward(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32
  * by sr_backward_project or a fresh zeroed buffer).  tile_order [T],
  * optional: launch order as for sr_train_step_raster (sr_tile_order of the
  * tile costs the same step's sr_render_forward recorded).
+ * grad_marks [V*N], optional: the tiles_touched array of the same
+ * sr_preprocess; bit 31 of every record given a non-zero gradient is set
+ * (atomic OR; the counts below it are untouched).
  * sr_backward_project: chains grad_rec to the parameter gradients (+=),
  * summed over the views, and zeroes every grad_rec record it consumed, so
  * the buffer is ready for the next step.  tiles_touched (from
  * sr_preprocess) lets it skip culled records; NULL scans every record.
+ * With SR_FLAG_MARKED_GRADIENTS in cfg->flags it reads only the records
+ * whose bit 31 is set and clears that bit: records that received no
+ * gradient (visible but never blended: most of an object's interior) are
+ * not read at all.
  * Density-control statistic (the 2DGS adaptive density control kept by
  * Section 5.1), optional: for every record not culled, densify_count[g] += 1
  * and densify_grad[g] += |dL/d delta|_2, the gradient of the loss with
@@ -304,11 +319,11 @@ sr_status sr_backward_raster(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32
                              const uint32_t *n_contrib, const float *dL_dcolor, const float *dL_dalpha,
                              const float *dL_ddepth, const float *dL_dnormal, const float *dL_ddist,
                              const uint32_t *median_contrib, const float *dL_dmedian,
-                             float *grad_rec, const uint32_t *tile_order, void *stream);
+                             float *grad_rec, uint32_t *grad_marks, const uint32_t *tile_order, void *stream);
 sr_status sr_backward_project(sr_ctx *ctx, const sr_config *cfg, int32_t N, int32_t V, const sr_camera *cams_host,
                               const sr_camera *cams_dev, const float *means, const float *scales,
                               const float *quats, const float *sh, const float *geom, const float *app,
-                              const uint32_t *tiles_touched, float *grad_rec, float *g_means,
+                              uint32_t *tiles_touched, float *grad_rec, float *g_means,
                               float *g_scales, float *g_quats, float *g_opac, float *g_sh,
                               float *densify_grad, uint32_t *densify_count, void *stream);
 
@@ -392,6 +407,7 @@ sr_status sr_ssim_loss(sr_ctx *ctx, int32_t V, const sr_camera *cams_host, const
  *   tile_loss [2T]  scratch: per-tile partial sums
  *   loss [2V+1]     as sr_background_loss (sums in tile order)
  *   grad_rec        as sr_backward_raster (zeros on entry; gradients added)
+ *   grad_marks      optional, as sr_backward_raster
  *   tile_order [T]  optional (NULL: the default order): the tile of each
  *                   workgroup, a permutation of 0..T-1 as sr_tile_order
  *                   writes it (heaviest tiles first); results do not depend
@@ -409,8 +425,8 @@ sr_status sr_train_step_raster(sr_ctx *ctx, const sr_config *cfg, int32_t N, int
                                const float *target, float gamma, float w_c, float *color, float *alpha,
                                float *depth, float *normal, float *dist, float *T_final,
                                uint32_t *n_contrib, uint32_t *hits, float *max_alpha, float *max_weight,
-                               float *tile_loss, float *loss, float *grad_rec, const uint32_t *tile_order,
-                               uint32_t *tile_cost, void *stream);
+                               float *tile_loss, float *loss, float *grad_rec, uint32_t *grad_marks,
+                               const uint32_t *tile_order, uint32_t *tile_cost, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -431,7 +447,7 @@ sr_status sr_train_step_raster_noalloc(sr_ctx *ctx, const sr_config *cfg, int32_
                                        const uint8_t *mask, const float *target, float gamma, float w_c,
                                        float *color, float *alpha, float *depth, float *normal, float *dist,
                                        float *T_final, uint32_t *n_contrib, uint32_t *hits, float *max_alpha,
-                                       float *max_weight, float *loss, float *grad_rec,
+                                       float *max_weight, float *loss, float *grad_rec, uint32_t *grad_marks,
                                        const uint32_t *tile_order, uint32_t *tile_cost, void *stream);
 
 /* Dispatch order for sr_train_step_raster: the T tile ids sorted by

@@ -22,6 +22,7 @@ SR_STATUS_CAPACITY = 1
 SR_PRIM_SURFEL = 0
 SR_PRIM_GAUSS3D = 1
 SR_FLAG_ACCUMULATE = 1
+SR_FLAG_MARKED_GRADIENTS = 2
 SR_GEOM_STRIDE = 16
 SR_APP_STRIDE = 8
 SR_GRAD_STRIDE = 24
@@ -91,7 +92,7 @@ def _declare(lib):
                                       V]),
         "sr_render_forward": (c_int32, [V, V, c_int32, c_int32] + [V] * 21),
         "sr_render_backward": (c_int32, [V, V, c_int32, c_int32, V, V] + [V] * 28),
-        "sr_backward_raster": (c_int32, [V, V, c_int32, c_int32] + [V] * 21),
+        "sr_backward_raster": (c_int32, [V, V, c_int32, c_int32] + [V] * 22),
         "sr_backward_project": (c_int32, [V, V, c_int32, c_int32] + [V] * 18),
         "sr_loss_workspace_size": (c_int32, [c_int32, V, POINTER(c_size_t)]),
         "sr_background_loss": (c_int32, [V, c_int32, V, V, V, V, V, V, c_float, c_float, V, c_size_t, V, V, V,
@@ -105,9 +106,9 @@ def _declare(lib):
         "sr_prune_stats_3d": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, V]),
         "sr_compact_surfels": (c_int32, [V, c_int32, V, V, c_float, c_int32, V, V, V, V, c_size_t, V, V]),
         "sr_train_step_raster": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float, c_float]
-                                 + [V] * 16),
+                                 + [V] * 17),
         "sr_train_step_raster_noalloc": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, c_float,
-                                                   c_float] + [V] * 15),
+                                                   c_float] + [V] * 16),
         "sr_tile_order_workspace_size": (c_int32, [c_int32, POINTER(c_size_t)]),
         "sr_tile_order": (c_int32, [V, c_int32, V, V, c_size_t, V, V]),
         "sr_prune_stats": (c_int32, [V, V, c_int32, c_int32, V, V, V, V, V, V, V, V, V, V]),

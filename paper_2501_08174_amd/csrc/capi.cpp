@@ -371,7 +371,7 @@ sr_status sr_backward_raster(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32
                              const float* T_final, const uint32_t* n_contrib, const float* dL_dcolor,
                              const float* dL_dalpha, const float* dL_ddepth, const float* dL_dnormal,
                              const float* dL_ddist, const uint32_t* median_contrib, const float* dL_dmedian,
-                             float* grad_rec, const uint32_t* tile_order, void* stream) {
+                             float* grad_rec, uint32_t* grad_marks, const uint32_t* tile_order, void* stream) {
     int total_tiles = 0;
     SR_TRY(check_backward_raster(cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, alpha, depth, dist, T_final,
                                  n_contrib, grad_rec, &total_tiles));
@@ -380,20 +380,22 @@ sr_status sr_backward_raster(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32
     SR_TRY(check_ctx(ctx));
     return hip_status(sr::launch_render_bwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, alpha, depth,
                                             dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
-                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, tile_order,
+                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, grad_marks, tile_order,
                                             ctx->status, (hipStream_t)stream),
                       "sr_backward_raster");
 }
 
 sr_status sr_backward_project(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,
                               const sr_camera* cams_dev, const float* means, const float* scales, const float* quats,
-                              const float* sh, const float* geom, const float* app, const uint32_t* tiles_touched,
+                              const float* sh, const float* geom, const float* app, uint32_t* tiles_touched,
                               float* grad_rec, float* g_means, float* g_scales, float* g_quats, float* g_opac,
                               float* g_sh, float* densify_grad, uint32_t* densify_count, void* stream) {
     SR_TRY(check_backward_project(cfg, N, V, cams_host, cams_dev, means, scales, quats, sh, geom, app, grad_rec,
                                   g_means, g_scales, g_quats, g_opac, g_sh));
     if ((densify_grad || densify_count) && !tiles_touched)
         return fail(SR_ERR_ARG, "the density statistics need tiles_touched (the views each surfel is seen in)");
+    if ((cfg->flags & SR_FLAG_MARKED_GRADIENTS) && !tiles_touched)
+        return fail(SR_ERR_ARG, "SR_FLAG_MARKED_GRADIENTS needs tiles_touched (the marks live there)");
     if (N == 0 || V == 0) return SR_OK;
     SR_TRY(check_ctx(ctx));
     return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app,
@@ -424,9 +426,12 @@ sr_status sr_render_backward(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32
     SR_TRY(hip_status(sr::fill_f32(grad_rec, 0.f, (uint64_t)V * N * SR_GRAD_STRIDE, s), "clear grad_rec"));
     SR_TRY(hip_status(sr::launch_render_bwd(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, alpha, depth,
                                             dist, T_final, n_contrib, dL_dcolor, dL_dalpha, dL_ddepth, dL_dnormal,
-                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, nullptr, ctx->status, s),
+                                            dL_ddist, median_contrib, dL_dmedian, grad_rec, nullptr, nullptr,
+                                            ctx->status, s),
                       "render backward"));
-    return hip_status(sr::launch_preprocess_bwd(*cfg, N, means, scales, quats, sh, V, cams_dev, geom, app, nullptr,
+    sr_config pcfg = *cfg;
+    pcfg.flags &= ~SR_FLAG_MARKED_GRADIENTS;     // no marks here: every record is read
+    return hip_status(sr::launch_preprocess_bwd(pcfg, N, means, scales, quats, sh, V, cams_dev, geom, app, nullptr,
                                                 grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, nullptr,
                                                 nullptr, s),
                       "projection backward");
@@ -660,8 +665,8 @@ sr_status train_step(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, co
                      const uint32_t* ranges, const uint8_t* mask, const float* target, float gamma, float w_c,
                      float* color, float* alpha, float* depth, float* normal, float* dist, float* T_final,
                      uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight, float* tile_loss,
-                     float* loss, float* grad_rec, const uint32_t* tile_order, uint32_t* tile_cost, void* stream,
-                     bool noalloc) {
+                     float* loss, float* grad_rec, uint32_t* grad_marks, const uint32_t* tile_order,
+                     uint32_t* tile_cost, void* stream, bool noalloc) {
     SR_TRY(check_cfg(cfg));
     SR_TRY(check_nv(N, V));
     int total_tiles = 0;
@@ -687,8 +692,8 @@ sr_status train_step(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, co
     if (total_tiles == 0) return SR_OK;
     SR_TRY(hip_status(sr::launch_train_raster(*cfg, N, V, total_tiles, cams_dev, geom, app, vals, ranges, mask, target,
                                               gamma, w_c, color, alpha, depth, normal, dist, T_final, n_contrib, hits,
-                                              max_alpha, max_weight, tile_loss, grad_rec, tile_order, tile_cost,
-                                              ctx->status, s),
+                                              max_alpha, max_weight, tile_loss, grad_rec, grad_marks, tile_order,
+                                              tile_cost, ctx->status, s),
                       "sr_train_step_raster"));
     return hip_status(sr::launch_loss_from_tiles(V, cams_dev, tile_loss, gamma, w_c, loss, s), "loss totals");
 }
@@ -701,10 +706,10 @@ sr_status sr_train_step_raster(sr_ctx* ctx, const sr_config* cfg, int32_t N, int
                                float w_c, float* color, float* alpha, float* depth, float* normal, float* dist,
                                float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
                                float* max_weight, float* tile_loss, float* loss, float* grad_rec,
-                               const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
+                               uint32_t* grad_marks, const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
     return train_step(ctx, cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, mask, target, gamma, w_c, color,
                       alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, tile_loss, loss,
-                      grad_rec, tile_order, tile_cost, stream, false);
+                      grad_rec, grad_marks, tile_order, tile_cost, stream, false);
 }
 
 sr_status sr_train_step_raster_noalloc(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V,
@@ -713,11 +718,11 @@ sr_status sr_train_step_raster_noalloc(sr_ctx* ctx, const sr_config* cfg, int32_
                                        const uint8_t* mask, const float* target, float gamma, float w_c,
                                        float* color, float* alpha, float* depth, float* normal, float* dist,
                                        float* T_final, uint32_t* n_contrib, uint32_t* hits, float* max_alpha,
-                                       float* max_weight, float* loss, float* grad_rec,
+                                       float* max_weight, float* loss, float* grad_rec, uint32_t* grad_marks,
                                        const uint32_t* tile_order, uint32_t* tile_cost, void* stream) {
     return train_step(ctx, cfg, N, V, cams_host, cams_dev, geom, app, vals, ranges, mask, target, gamma, w_c, color,
                       alpha, depth, normal, dist, T_final, n_contrib, hits, max_alpha, max_weight, nullptr, loss,
-                      grad_rec, tile_order, tile_cost, stream, true);
+                      grad_rec, grad_marks, tile_order, tile_cost, stream, true);
 }
 
 sr_status sr_render_count(sr_ctx* ctx, const sr_config* cfg, int32_t N, int32_t V, const sr_camera* cams_host,

@@ -17,7 +17,7 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
 
 hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means, const float* scales,
                                  const float* quats, const float* sh, int V, const sr_camera* cams_dev,
-                                 const float* geom, const float* app, const uint32_t* tiles_touched,
+                                 const float* geom, const float* app, uint32_t* tiles_touched,
                                  float* grad_rec, float* g_means, float* g_scales, float* g_quats,
                                  float* g_opac, float* g_sh, float* dens_grad, uint32_t* dens_count,
                                  hipStream_t stream);
@@ -54,14 +54,15 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
                              const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
-                             float* grad_rec, const uint32_t* tile_order, const uint32_t* status, hipStream_t s);
+                             float* grad_rec, uint32_t* grad_marks, const uint32_t* tile_order,
+                             const uint32_t* status, hipStream_t s);
 
 hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_tiles, const sr_camera* cams,
                                const float* geom, const float* app, const uint32_t* vals, const uint32_t* ranges,
                                const uint8_t* mask, const float* target, float gamma, float w_c, float* color,
                                float* alpha, float* depth, float* normal, float* dist, float* T_final,
                                uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                               float* tile_loss, float* grad_rec, const uint32_t* tile_order,
+                               float* tile_loss, float* grad_rec, uint32_t* grad_marks, const uint32_t* tile_order,
                                uint32_t* tile_cost, const uint32_t* status, hipStream_t s);
 
 // The device address of the training step's file-scope scratch array on

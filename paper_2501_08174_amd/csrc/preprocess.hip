@@ -461,7 +461,10 @@ __global__ void k_zero_u8(uint8_t* __restrict__ p, int n) {
 // Backward of the projection: chains the per-record gradients accumulated by
 // the raster backward (layout below) to the surfel parameters, summed over
 // the views, and clears every accumulator it consumed.  One thread per
-// surfel; the parameter gradients are added to.
+// surfel; the parameter gradients are added to.  With `marked`, only the
+// records whose bit 31 of tiles_touched the raster backward set are read
+// (and the bit is cleared): a visible record that no pixel blended holds
+// zeros, and most of a batch's visible records are such (occluded).
 //   grad_rec[r*24 + ...]: [0..2] dA (= sum dL/dw * dx), [3..5] dB, [6..8] dC',
 //   [9..10] d centre (low-pass), [11] d opacity, [12..14] d m3,
 //   [15..17] d rgb, [18..20] d normal.
@@ -478,7 +481,7 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
                  const float* __restrict__ quats, const float* __restrict__ sh,
                  int sh_stride, int V, const sr_camera* __restrict__ cams,
                  const float4* __restrict__ geom, const float4* __restrict__ app,
-                 const uint32_t* __restrict__ tiles_touched, float* __restrict__ grad_rec,
+                 uint32_t* __restrict__ tiles_touched, bool marked, float* __restrict__ grad_rec,
                  float* __restrict__ g_means, float* __restrict__ g_scales, float* __restrict__ g_quats,
                  float* __restrict__ g_opac, float* __restrict__ g_sh, float* __restrict__ dens_grad,
                  uint32_t* __restrict__ dens_count) {
@@ -515,8 +518,18 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
 
     for (int v = 0; v < V; ++v) {
         const size_t r = (size_t)v * N + g;
-        if (tiles_touched && tiles_touched[r] == 0u) continue;
-        dens_n += 1u;
+        if (tiles_touched) {
+            const uint32_t tt = tiles_touched[r];
+            if ((tt & 0x7FFFFFFFu) == 0u) continue;          // culled in this view
+            dens_n += 1u;
+            if (marked) {
+                // only records the compositing backward marked hold gradients
+                if ((tt >> 31) == 0u) continue;
+                tiles_touched[r] = tt & 0x7FFFFFFFu;
+            }
+        } else {
+            dens_n += 1u;
+        }
         float* gr = grad_rec + r * SR_GRAD_STRIDE;
         float G[kNumGrad];
         bool any = false;
@@ -715,16 +728,17 @@ hipError_t launch_preprocess(const sr_config& cfg, int N, const float* means, co
 
 hipError_t launch_preprocess_bwd(const sr_config& cfg, int N, const float* means, const float* scales,
                                  const float* quats, const float* sh, int V, const sr_camera* cams_dev,
-                                 const float* geom, const float* app, const uint32_t* tiles_touched,
+                                 const float* geom, const float* app, uint32_t* tiles_touched,
                                  float* grad_rec, float* g_means, float* g_scales, float* g_quats,
                                  float* g_opac, float* g_sh, float* dens_grad, uint32_t* dens_count,
                                  hipStream_t stream) {
     if (N == 0) return hipSuccess;
     dim3 grid((N + 255) / 256), block(256);
+    const bool marked = tiles_touched && (cfg.flags & SR_FLAG_MARKED_GRADIENTS);
 #define SR_PREB(D)                                                                                          \
     hipLaunchKernelGGL(k_preprocess_bwd<D>, grid, block, 0, stream, N, means, scales, quats, sh,            \
-                       cfg.sh_stride, V, cams_dev, (const float4*)geom, (const float4*)app, tiles_touched, \
-                       grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, dens_grad, dens_count)
+                       cfg.sh_stride, V, cams_dev, (const float4*)geom, (const float4*)app, tiles_touched,   \
+                       marked, grad_rec, g_means, g_scales, g_quats, g_opac, g_sh, dens_grad, dens_count)
     switch (cfg.sh_degree) {
         case 0: SR_PREB(0); break;
         case 1: SR_PREB(1); break;

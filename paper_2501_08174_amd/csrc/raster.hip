@@ -621,7 +621,9 @@ __device__ __forceinline__ void pix_bwd_init(PixBwd& pb, const TileCtx& t, float
 // W_k = sum_{j>k} g_j w_j (+ the background term), dL/da_k = T_k g_k -
 // W_k / (1 - a_k).  Per-record gradients are summed over each wave by
 // transposition (permlane swaps and DPP), over the workgroup in LDS, then
-// added to grad_rec with one atomic per (tile, record, component).
+// added to grad_rec with one atomic per (tile, record, component); with
+// grad_marks (the projection's tiles_touched) bit 31 of every record given a
+// gradient is set.
 // GEO: the loss has depth, normal or distortion terms (their upstream
 // gradients are read); without them the depth path and six of the per-record
 // components are identically zero and are not computed or reduced.
@@ -633,7 +635,8 @@ template <int TW, int NT, int BATCH, bool GEO, bool HITS = false>
 __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, int N, const float4* __restrict__ geom,
                                          const float4* __restrict__ app, const uint32_t* __restrict__ vals,
                                          const RasterConsts& rc, BwdSmem<BATCH>& sm, PixBwd pb,
-                                         float* __restrict__ grad_rec, uint32_t* __restrict__ hits = nullptr,
+                                         float* __restrict__ grad_rec, uint32_t* __restrict__ grad_marks,
+                                         uint32_t* __restrict__ hits = nullptr,
                                          uint32_t* __restrict__ cost_out = nullptr,
                                          const uint32_t* bitcache = nullptr) {
     static_assert(BATCH <= NT, "one record per thread and batch");
@@ -781,12 +784,18 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
         __syncthreads();
         if (tid >= lo && tid < BATCH) {
             float* dst = grad_rec + (size_t)sm.rec[tid] * SR_GRAD_STRIDE;
+            bool any = false;
 #pragma unroll
             for (int i = 0; i < kNumGrad; ++i) {
                 if (HITS && i == 12) continue;
                 const float vsum = sm.acc[tid][i];
-                if (vsum != 0.f) atomicAdd(&dst[i], vsum);
+                if (vsum != 0.f) {
+                    atomicAdd(&dst[i], vsum);
+                    any = true;
+                }
             }
+            // mark the record for the projection backward (bit 31)
+            if (grad_marks && any) atomicOr(&grad_marks[sm.rec[tid]], 0x80000000u);
             if (HITS) {
                 const uint32_t n = (uint32_t)sm.acc[tid][12];
                 if (n != 0u) atomicAdd(&hits[sm.rec[tid] - (uint32_t)t.v * (uint32_t)N], n);
@@ -804,7 +813,8 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
              const float* __restrict__ dC, const float* __restrict__ dA, const float* __restrict__ dD,
              const float* __restrict__ dNrm, const float* __restrict__ dDist,
              const uint32_t* __restrict__ median_contrib, const float* __restrict__ dMed,
-             float* __restrict__ grad_rec, const uint32_t* __restrict__ tile_order) {
+             float* __restrict__ grad_rec, uint32_t* __restrict__ grad_marks,
+             const uint32_t* __restrict__ tile_order) {
     __shared__ BwdSmem<BATCH> sm;
     // an order entry beyond the grid leaves the workgroup idle; so does a set
     // status word (no gradients)
@@ -830,7 +840,7 @@ k_render_bwd(const sr_camera* __restrict__ cams, int V, int N, const float4* __r
         if (dMed) { pb.gMed = dMed[o1]; pb.kmed = median_contrib[o1]; }
         pix_bwd_init(pb, t, T_final[o1], n_contrib[o1], alpha[o1], depth[o1], dist[o1]);
     }
-    bwd_tile<TW, TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec);
+    bwd_tile<TW, TW * TH, BATCH, GEO>(t, px, py, N, geom, app, vals, rc, sm, pb, grad_rec, grad_marks);
 }
 
 // One training step of the compositing for a tile: forward, the masked L1 +
@@ -850,6 +860,7 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
                float* __restrict__ normal, float* __restrict__ dist, float* __restrict__ T_final,
                uint32_t* __restrict__ n_contrib, uint32_t* __restrict__ hits, float* __restrict__ max_alpha,
                float* __restrict__ max_weight, float* __restrict__ tile_loss, float* __restrict__ grad_rec,
+               uint32_t* __restrict__ grad_marks,
                const uint32_t* __restrict__ tile_order, uint32_t* __restrict__ tile_cost) {
     constexpr int NT = TW * TH;
     constexpr int MODE = kShade | (STATS == 2 ? kStats : 0);
@@ -916,7 +927,7 @@ k_train_raster(const sr_camera* __restrict__ cams, int V, int N, const float4* _
     }
     if (threadIdx.x == 0) tile_loss[2 * (size_t)t.tile + 1] = s_red[0];
     bwd_tile<TW, NT, BATCH, false, STATS == 1>(t, px, py, N, geom, app, vals, rc,
-                                               *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec, hits,
+                                               *reinterpret_cast<BwdSmem<BATCH>*>(smem), pb, grad_rec, grad_marks, hits,
                                                tile_cost ? tile_cost + t.tile : nullptr, CACHE ? s_bits : nullptr);
 }
 
@@ -1001,18 +1012,19 @@ bool bwd_launch(int batch, int total_tiles, hipStream_t s, const sr_camera* cams
                 const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc, const float* alpha,
                 const float* depth, const float* dist, const float* T_final, const uint32_t* n_contrib,
                 const float* dC, const float* dA, const float* dD, const float* dN, const float* dS,
-                const uint32_t* median_contrib, const float* dMed, float* grad_rec, const uint32_t* tile_order) {
+                const uint32_t* median_contrib, const float* dMed, float* grad_rec, uint32_t* grad_marks,
+                const uint32_t* tile_order) {
     const bool geo = dD || dN || dS || dMed;
     return with_batch<TW * TH>(resolve_batch(TW * TH, batch), [&](auto bc) {
         constexpr int B = decltype(bc)::value;
         if (geo)
             hipLaunchKernelGGL((k_render_bwd<TW, TH, B, true>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
                                geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN,
-                               dS, median_contrib, dMed, grad_rec, tile_order);
+                               dS, median_contrib, dMed, grad_rec, grad_marks, tile_order);
         else
             hipLaunchKernelGGL((k_render_bwd<TW, TH, B, false>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N,
                                geom, app, vals, ranges, rc, alpha, depth, dist, T_final, n_contrib, dC, dA, dD, dN,
-                               dS, median_contrib, dMed, grad_rec, tile_order);
+                               dS, median_contrib, dMed, grad_rec, grad_marks, tile_order);
     });
 }
 
@@ -1021,14 +1033,15 @@ bool train_launch(int stats, int batch, int total_tiles, hipStream_t s, const sr
                   const float4* geom, const float4* app, const uint32_t* vals, const uint2* ranges, RasterConsts rc,
                   const uint8_t* mask, const float* target, float gamma, float w_c, float* color, float* alpha,
                   float* depth, float* normal, float* dist, float* T_final, uint32_t* n_contrib, uint32_t* hits,
-                  float* max_alpha, float* max_weight, float* tile_loss, float* grad_rec, const uint32_t* tile_order,
+                  float* max_alpha, float* max_weight, float* tile_loss, float* grad_rec, uint32_t* grad_marks,
+                  const uint32_t* tile_order,
                   uint32_t* tile_cost) {
     return with_batch<TW * TH>(resolve_batch(TW * TH, batch), [&](auto bc) {
         constexpr int B = decltype(bc)::value;
 #define SR_TRAIN(S)                                                                                              \
     hipLaunchKernelGGL((k_train_raster<TW, TH, B, S>), dim3(total_tiles), dim3(TW * TH), 0, s, cams, V, N, geom, \
                        app, vals, ranges, rc, mask, target, gamma, w_c, color, alpha, depth, normal, dist, T_final, \
-                       n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec, tile_order, tile_cost)
+                       n_contrib, hits, max_alpha, max_weight, tile_loss, grad_rec, grad_marks, tile_order, tile_cost)
         if (stats == 2)
             SR_TRAIN(2);
         else if (stats == 1)
@@ -1096,14 +1109,16 @@ hipError_t launch_render_bwd(const sr_config& cfg, int N, int V, int total_tiles
                              const float* alpha, const float* depth, const float* dist, const float* T_final,
                              const uint32_t* n_contrib, const float* dC, const float* dA, const float* dD,
                              const float* dN, const float* dS, const uint32_t* median_contrib, const float* dMed,
-                             float* grad_rec, const uint32_t* tile_order, const uint32_t* status, hipStream_t s) {
+                             float* grad_rec, uint32_t* grad_marks, const uint32_t* tile_order,
+                             const uint32_t* status, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
 #define SR_TS(W, H)                                                                                            \
     if (cfg.tile_w == W && cfg.tile_h == H) {                                                                 \
         if (!bwd_launch<W, H>(cfg.bwd_batch, total_tiles, s, cams, V, N, (const float4*)geom,                 \
                               (const float4*)app, vals, (const uint2*)ranges, rc, alpha, depth, dist, T_final,  \
-                              n_contrib, dC, dA, dD, dN, dS, median_contrib, dMed, grad_rec, tile_order))       \
+                              n_contrib, dC, dA, dD, dN, dS, median_contrib, dMed, grad_rec, grad_marks,       \
+                              tile_order))                                                                      \
             return hipErrorInvalidValue;                                                                      \
         return hipGetLastError();                                                                             \
     }
@@ -1117,7 +1132,8 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
                                const uint8_t* mask, const float* target, float gamma, float w_c, float* color,
                                float* alpha, float* depth, float* normal, float* dist, float* T_final,
                                uint32_t* n_contrib, uint32_t* hits, float* max_alpha, float* max_weight,
-                               float* tile_loss, float* grad_rec, const uint32_t* tile_order, uint32_t* tile_cost,
+                               float* tile_loss, float* grad_rec, uint32_t* grad_marks, const uint32_t* tile_order,
+                               uint32_t* tile_cost,
                                const uint32_t* status, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     RasterConsts rc{cfg.alpha_min, cfg.alpha_max, cfg.t_min, cfg.flags, status};
@@ -1126,7 +1142,7 @@ hipError_t launch_train_raster(const sr_config& cfg, int N, int V, int total_til
         if (!train_launch<W, H>(hits ? (max_alpha ? 2 : 1) : 0, cfg.bwd_batch, total_tiles, s, cams, V, N,      \
                                 (const float4*)geom, (const float4*)app, vals, (const uint2*)ranges, rc, mask,   \
                                 target, gamma, w_c, color, alpha, depth, normal, dist, T_final, n_contrib, hits, \
-                                max_alpha, max_weight, tile_loss, grad_rec, tile_order, tile_cost))             \
+                                max_alpha, max_weight, tile_loss, grad_rec, grad_marks, tile_order, tile_cost)) \
             return hipErrorInvalidValue;                                                                         \
         return hipGetLastError();                                                                                \
     }

@@ -288,13 +288,17 @@ class Rasterizer:
              _ptr(self.views.dev), _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges),
              _ptr(self.alpha), _ptr(self.depth), _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib),
              _ptr(dC), _ptr(dA), _ptr(dD), _ptr(dN), _ptr(dS), _ptr(self._median_contrib(dM)), _ptr(dM),
-             _ptr(self._grad_rec()), _ptr(order), _stream(stream))
+             _ptr(self._grad_rec()), _ptr(self.tiles_touched), _ptr(order), _stream(stream))
 
     def backward_project(self, p: Params, grads: Params, stream=None, densify=None):
         """Projection backward; ``densify`` = (grad_sum float32 [N], count
         int32 [N]) accumulates the density-control statistic."""
         dg, dc = (None, None) if densify is None else densify
-        call("sr_backward_project", self.ctx.ptr, ctypes.byref(self.cfg), self.N, self.views.V, self.views.host_ptr,
+        # every compositing backward of this object marks the records it
+        # gives gradients (bit 31 of tiles_touched): read only those
+        cfg = SrConfig.from_buffer_copy(self.cfg)
+        cfg.flags |= _lib.SR_FLAG_MARKED_GRADIENTS
+        call("sr_backward_project", self.ctx.ptr, ctypes.byref(cfg), self.N, self.views.V, self.views.host_ptr,
              _ptr(self.views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.sh), _ptr(self.geom),
              _ptr(self.app), _ptr(self.tiles_touched), _ptr(self._grad_rec()), _ptr(grads.means),
              _ptr(grads.scales), _ptr(grads.quats), _ptr(grads.opac), _ptr(grads.sh), _ptr(dg), _ptr(dc),
@@ -375,7 +379,8 @@ class Rasterizer:
                   _ptr(self.geom), _ptr(self.app), _ptr(self.vals), _ptr(self.ranges), _ptr(mask), _ptr(target),
                   float(gamma), float(w_c), _ptr(self.color), _ptr(self.alpha), _ptr(self.depth), _ptr(self.normal),
                   _ptr(self.dist), _ptr(self.T_final), _ptr(self.n_contrib), _ptr(h), _ptr(ma), _ptr(mw))
-        tail = (_ptr(self.loss_out), _ptr(self._grad_rec()), _ptr(order), _ptr(cost), _stream(stream))
+        tail = (_ptr(self.loss_out), _ptr(self._grad_rec()), _ptr(self.tiles_touched), _ptr(order), _ptr(cost),
+                _stream(stream))
         if noalloc:
             call("sr_train_step_raster_noalloc", *common, *tail)
         else:

@@ -113,7 +113,7 @@ def test_argument_errors_before_launch(lib):
     assert l.sr_render_forward(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), md, md, None, None,
                                None) == lib.SR_OK
     assert l.sr_backward_raster(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 14), None, md, None, None,
-                                None) == lib.SR_ERR_ARG
+                                None, None) == lib.SR_ERR_ARG
     assert l.sr_render_backward(None, ctypes.byref(cfg), 0, 0, None, None, *([None] * 19), None, md, None,
                                 *([None] * 6)) == lib.SR_ERR_ARG
     # statistics: none, hits alone, or hits with both maxima
@@ -122,7 +122,7 @@ def test_argument_errors_before_launch(lib):
                                                    mw, None, None, None, None, None)
     step = lambda hits, ma, mw: l.sr_train_step_raster(None, ctypes.byref(cfg), 0, 0, None, None, None, None, None, None,
                                                        None, None, 0.5, 1.0, *([None] * 7), hits, ma, mw, None,
-                                                       None, None, None, None, None)
+                                                       None, None, None, None, None, None)
     for f in (fwd, step):
         assert f(None, None, None) == lib.SR_OK
         assert f(h, None, None) == lib.SR_OK

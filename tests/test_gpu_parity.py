@@ -327,6 +327,63 @@ def test_backward_every_lds_batch(_bwd_case, tile, batch):
     compare_grads(g, gref, excl)
 
 
+def test_gradient_marks():
+    """The compositing backward marks (bit 31 of tiles_touched) exactly the
+    records it gives a gradient; the projection backward with the marks
+    reads only those, clears the marks and the accumulator, and gives the
+    gradients of the unmarked read of every record."""
+    import ctypes
+    from paper_2501_08174_amd import _lib
+    from paper_2501_08174_amd._lib import SrConfig
+    from paper_2501_08174_amd.raster import _ptr
+    # large surfels: about half of the visible records are occluded everywhere
+    sc = scenes.make_random_scene(47, 3000, n_views=3, width=[90, 64, 120], height=[70, 100, 33], sh_degree=3,
+                                  scale_range=(0.05, 0.4))
+    rng = np.random.default_rng(48)
+    views = ViewBatch(sc.cams)
+    mask = torch.tensor(rng.integers(0, 2, views.P).astype(np.uint8), device="cuda")
+    target = torch.tensor(rng.uniform(size=3 * views.P).astype(np.float32), device="cuda")
+    p = Params.from_scene(sc)
+    rast = Rasterizer(sc.n, views, sc.sh_degree, sh_stride=sc.sh.shape[1])
+    rast.plan_capacity(p)
+    VN = sc.v * sc.n
+
+    def step(marked):
+        g = Params(*[torch.zeros_like(t) for t in (p.means, p.scales, p.quats, p.opac, p.sh)])
+        rast.preprocess(p)
+        rast.bin()
+        rast.train_step_raster(mask, target, 0.5, 1.0, schedule=False)
+        torch.cuda.synchronize()
+        tt = rast.tiles_touched[:VN].cpu().numpy().view(np.uint32).copy()
+        rec = rast.grad_rec[: VN * _lib.SR_GRAD_STRIDE].cpu().numpy().reshape(VN, -1)
+        has = (rec != 0).any(axis=1)
+        if marked:
+            rast.backward_project(p, g)
+        else:
+            cfg = SrConfig.from_buffer_copy(rast.cfg)
+            _lib.call("sr_backward_project", rast.ctx.ptr, ctypes.byref(cfg), rast.N, views.V, views.host_ptr,
+                      _ptr(views.dev), _ptr(p.means), _ptr(p.scales), _ptr(p.quats), _ptr(p.sh), _ptr(rast.geom),
+                      _ptr(rast.app), _ptr(rast.tiles_touched), _ptr(rast.grad_rec), _ptr(g.means),
+                      _ptr(g.scales), _ptr(g.quats), _ptr(g.opac), _ptr(g.sh), None, None, None)
+        torch.cuda.synchronize()
+        after = rast.tiles_touched[:VN].cpu().numpy().view(np.uint32)
+        return tt, has, after, [t.cpu().numpy() for t in (g.means, g.scales, g.quats, g.opac, g.sh)]
+
+    tt, has, after, g_marked = step(True)
+    marks = (tt >> 31) == 1
+    np.testing.assert_array_equal(marks, has)
+    unmarked_visible = int((~has & ((tt & 0x7FFFFFFF) != 0)).sum())
+    assert has.sum() > 1000 and unmarked_visible > 1000, (int(has.sum()), unmarked_visible)
+    np.testing.assert_array_equal(after, tt & 0x7FFFFFFF)
+    assert not rast.grad_rec.any().item()
+    tt2, has2, after2, g_all = step(False)
+    np.testing.assert_array_equal(has2, has)
+    np.testing.assert_array_equal(after2, tt2)          # the unmarked read leaves the marks
+    for a, b in zip(g_marked, g_all):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-5 * max(float(np.abs(b).max()), 1e-30))
+    print(f"{int(has.sum())} of {int(((tt & 0x7FFFFFFF) != 0).sum())} visible records hold gradients")
+
+
 def test_large_surfels_across_tile_groups():
     """Surfels whose rectangles span many 4x4-tile groups next to small ones,
     on views whose tile grids are not multiples of the group: bit-exact

@@ -71,5 +71,5 @@ def test_noalloc_rejects_more_tiles_than_the_array_holds():
     cfg = make_config(0)
     dummy = ctypes.c_void_p(256)        # never dereferenced: the size check fails first
     st = _lib.lib().sr_train_step_raster_noalloc(ctx.ptr, ctypes.byref(cfg), 10, 2, ctypes.cast(cams, ctypes.c_void_p),
-                                                  dummy, *([None] * 6), 0.5, 1.0, *([None] * 15))
+                                                  dummy, *([None] * 6), 0.5, 1.0, *([None] * 16))
     assert st == _lib.SR_ERR_ARG and b"SR_NOALLOC_MAX_TILES" in _lib.lib().sr_last_error()
