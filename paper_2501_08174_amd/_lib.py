@@ -21,6 +21,7 @@ SR_ERR_STATE = -5
 SR_STATUS_CAPACITY = 1
 SR_PRIM_SURFEL = 0
 SR_PRIM_GAUSS3D = 1
+ABI_VERSION = 4           # sr_version() of the library these signatures describe
 SR_FLAG_ACCUMULATE = 1
 SR_FLAG_MARKED_GRADIENTS = 2
 SR_GEOM_STRIDE = 16
@@ -136,6 +137,9 @@ def lib():
                                f"'python -m paper_2501_08174_amd.build' (no CPU fallback exists)")
         l = ctypes.CDLL(LIB_PATH)
         _declare(l)
+        if l.sr_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {l.sr_version()}, this binding is written for "
+                               f"{ABI_VERSION}: rebuild it with 'python -m paper_2501_08174_amd.build'")
         _lib = l
     return _lib
 

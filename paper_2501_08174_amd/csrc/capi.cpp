@@ -127,7 +127,7 @@ extern "C" {
 
 const char* sr_last_error(void) { return g_err; }
 
-int32_t sr_version(void) { return 3; }
+int32_t sr_version(void) { return 4; }
 
 sr_status sr_create(sr_ctx** ctx_out_host, int32_t device) {
     if (!ctx_out_host) return fail(SR_ERR_ARG, "ctx_out_host is NULL");
