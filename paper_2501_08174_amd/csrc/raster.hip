@@ -24,6 +24,8 @@ namespace sr {
 
 namespace {
 
+constexpr int kWaveBlock = 8;   // side of the square block of pixels one wave covers
+
 // Global tile id of this workgroup; pixel coordinates of this thread; the
 // run [start, start + n) of the tile's binning group.
 struct TileCtx {
@@ -57,8 +59,11 @@ __device__ __forceinline__ void tile_ctx(const sr_camera* __restrict__ cams, int
     const int ty = local / c.tiles_x, tx = local - ty * c.tiles_x;
     t.W = c.width;
     t.H = c.height;
-    t.ix = tx * TW + (int)(threadIdx.x % TW);
-    t.iy = ty * TH + (int)(threadIdx.x / TW);
+    // wave w covers the 8x8 block (w % (TW / 8), w / (TW / 8)) of the tile
+    constexpr int WB = kWaveBlock;
+    const int w = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+    t.ix = tx * TW + (w % (TW / WB)) * WB + (l % WB);
+    t.iy = ty * TH + (w / (TW / WB)) * WB + l / WB;
     t.tx0 = tx * TW;
     t.ty0 = ty * TH;
     t.sx = tx % SR_TILE_GROUP;
@@ -86,21 +91,25 @@ constexpr int kMaxWaves = 8;    // waves per workgroup (tiles of up to 512 pixel
 // shading: no appearance records to take them from).
 constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8, kRect = 16, kHits = 32;
 
-// Per-wave culling.  Every wave of a tile covers whole rows of it (a band).
-// When an entry is staged, its thread works out which bands it can reach,
-// one bit per wave; each wave then tests 64 staged entries at once with one
-// ballot of its bit and walks only the set bits of that mask, so skipped
-// entries cost no per-entry instructions.  A band is reached when the
-// entry's pixel rectangle (packed in the last two slots of the appearance
-// record) meets it and the y-range, within the tile's columns, of the
-// entry's cutoff conic or of its low-pass disc meets the band's rows:
+// Per-wave culling.  Every wave of a tile covers an 8x8 block of its pixels
+// (wave w: block column w % (TW / 8), block row w / (TW / 8)); a square
+// footprint has the shortest boundary for its 64 pixels, so fewer of a
+// wave's lanes sit outside the splats it works through than with a strip of
+// rows.  When an entry is staged, its thread works out which blocks it can
+// reach, one bit per wave; each wave then tests 64 staged entries at once
+// with one ballot of its bit and walks only the set bits of that mask, so
+// skipped entries cost no per-entry instructions.  A block is reached when
+// the entry's pixel rectangle (packed in the last two slots of the appearance
+// record) meets it and the y-range, within the tile's columns that the
+// rectangle meets, of the entry's cutoff conic or of its low-pass disc meets
+// the block's rows:
 //   surface  Q = (1 - tau)(w0^2 + w1^2) - 2 L (1 + tau) w2^2 <= 0 with
 //            w = A dx + B dy + C' (the pass test of eval_test with a relative
 //            slack tau): for an ellipse, Q(x, .) <= 0 is the interval between
 //            the roots of a quadratic in y, whose lower end is convex and
 //            upper end concave in x, so their extremes over the columns are
 //            at the ellipse's lowest and highest points clamped to the
-//            columns; any other conic reaches every band;
+//            columns; any other conic reaches every block;
 //   disc     dx^2 + dy^2 <= L (1 + tau).
 // Float64, with a 1e-3 pixel margin on the columns and rows: an entry is
 // skipped only where the exact test fails by a relative margin, and forward
@@ -108,8 +117,9 @@ constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8, kRect = 16, kHits
 template <int TW, int NW>
 __device__ __forceinline__ uint32_t band_bits(const float4& g0, const float4& g1, const float4& g2, float Lf,
                                               const float4& a1, int tx0, int ty0) {
-    static_assert(64 % TW == 0 && NW * (64 / TW) >= 1, "waves cover whole rows of the tile");
-    constexpr int RW = 64 / TW;                      // rows per wave
+    constexpr int WB = kWaveBlock;
+    static_assert(TW % WB == 0 && NW % (TW / WB) == 0, "waves cover whole 8x8 blocks of the tile");
+    constexpr int BX = TW / WB, BY = NW / BX;     // blocks per tile row and column
     constexpr double tau = 1e-3, mg = 1e-3;
     const uint32_t rx = __float_as_uint(a1.z), ry = __float_as_uint(a1.w);
     const int ilo = (int)(rx & 0xffffu), ihi = (int)(rx >> 16), jlo = (int)(ry & 0xffffu), jhi = (int)(ry >> 16);
@@ -160,19 +170,25 @@ __device__ __forceinline__ uint32_t band_bits(const float4& g0, const float4& g1
     }
     uint32_t bits = 0u;
 #pragma unroll
-    for (int b = 0; b < NW; ++b) {
-        const int r0 = ty0 + b * RW, r1 = r0 + RW - 1;
+    for (int by = 0; by < BY; ++by) {
+        const int r0 = ty0 + by * WB, r1 = r0 + WB - 1;
         const int lo = jlo > r0 ? jlo : r0, hi = jhi < r1 ? jhi : r1;
         if (lo > hi) continue;
         const double Y0 = (lo + 0.5) - cy - mg, Y1 = (hi + 0.5) - cy + mg;
         const bool disc = hd >= 0.0 && Y0 <= hd && Y1 >= -hd;
         const bool surf = ylo <= Y1 && yhi >= Y0;
-        if (disc || surf) bits |= 1u << b;
+        if (!(disc || surf)) continue;
+        // the blocks of this row that the rectangle's columns meet
+#pragma unroll
+        for (int bx = 0; bx < BX; ++bx) {
+            const int k0 = tx0 + bx * WB, k1 = k0 + WB - 1;
+            if (clo <= k1 && chi >= k0) bits |= 1u << (by * BX + bx);
+        }
     }
     return bits;
 }
 
-// Mask of the entries of run c (of 64) whose band bit (kept in the last slot
+// Mask of the entries of run c (of 64) whose wave bit (kept in the last slot
 // of the staged appearance record) is set for this wave.
 __device__ __forceinline__ uint64_t wave_live_mask(const float4* __restrict__ a1, int c, int cnt) {
     const int k = c * 64 + __lane_id();
