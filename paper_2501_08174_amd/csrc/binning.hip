@@ -315,7 +315,7 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
             const uint32_t key = s_keys[i];
             const int d = (int)((key >> shift) & mask);
             const uint32_t dst = s_off[d] + (i - s_lstart[d]);
-            keys_out[dst] = key;
+            if (keys_out) keys_out[dst] = key;
             vals_out[dst] = s_vals[i];
         }
         __syncthreads();
@@ -327,26 +327,45 @@ k_radix_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict
 
 // ---- instances ----------------------------------------------------------------
 
-// Tile groups met by the rectangle of a record.
-__device__ __forceinline__ uint32_t groups_of(const ushort4 rc, int tile_w, int tile_h) {
-    constexpr int GS = SR_TILE_GROUP;
-    const int gx0 = rc.x / tile_w / GS, gx1 = rc.y / tile_w / GS, gy0 = rc.z / tile_h / GS, gy1 = rc.w / tile_h / GS;
+// Tile groups met by the rectangle of a record; a group spans
+// 2^gsx x 2^gsy pixels (tile sides are powers of two).
+__device__ __forceinline__ uint32_t groups_of(const ushort4 rc, int gsx, int gsy) {
+    const int gx0 = rc.x >> gsx, gx1 = rc.y >> gsx, gy0 = rc.z >> gsy, gy1 = rc.w >> gsy;
     return (uint32_t)((gx1 - gx0 + 1) * (gy1 - gy0 + 1));
 }
 
 // Groups met by every depth-sorted visible pair and their sum per block;
 // the pairs' rectangles are gathered once into depth order for the emission.
+// The gather is random over the rectangle array: four independent gathers
+// per thread are kept in flight.
 __global__ void __launch_bounds__(kNT)
 k_inst_count(const uint32_t* __restrict__ counters, int G, const uint32_t* __restrict__ vis_vals,
-             const ushort4* __restrict__ rect, int tile_w, int tile_h, uint32_t* __restrict__ tt_sorted,
+             const ushort4* __restrict__ rect, int gsx, int gsy, uint32_t* __restrict__ tt_sorted,
              ushort4* __restrict__ rect_sorted, uint64_t* __restrict__ sums) {
     __shared__ uint64_t s_w[4];
+    constexpr int U = 4;
     uint64_t b, e;
     static_chunk(counters[0], G, &b, &e);
     uint64_t c = 0;
-    for (uint64_t i = b + threadIdx.x; i < e; i += kNT) {
+    uint64_t i = b + threadIdx.x;
+    for (; i + (uint64_t)(U - 1) * kNT < e; i += (uint64_t)U * kNT) {
+        uint32_t r[U];
+        ushort4 rc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = vis_vals[i + (uint64_t)u * kNT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) rc[u] = rect[r[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t t = groups_of(rc[u], gsx, gsy);
+            tt_sorted[i + (uint64_t)u * kNT] = t;
+            rect_sorted[i + (uint64_t)u * kNT] = rc[u];
+            c += t;
+        }
+    }
+    for (; i < e; i += kNT) {
         const ushort4 rc = rect[vis_vals[i]];
-        const uint32_t t = groups_of(rc, tile_w, tile_h);
+        const uint32_t t = groups_of(rc, gsx, gsy);
         tt_sorted[i] = t;
         rect_sorted[i] = rc;
         c += t;
@@ -399,7 +418,7 @@ k_emit_starts(const uint32_t* __restrict__ counters, const uint64_t* __restrict_
 // surfels they come from, so surfels covering thousands of tiles (close to
 // a camera, first in depth order) do not serialise on a few blocks.
 __global__ void __launch_bounds__(kNT)
-k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total64, int N, int tile_w, int tile_h,
+k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total64, int N, int tsx, int tsy,
        const sr_camera* __restrict__ cams, const uint32_t* __restrict__ vis_vals,
        const ushort4* __restrict__ rect_sorted,
        const uint64_t* __restrict__ offs, const uint32_t* __restrict__ starts, uint32_t* __restrict__ inst_keys,
@@ -426,7 +445,8 @@ k_emit(const uint32_t* __restrict__ counters, const uint64_t* __restrict__ total
             const uint32_t rec = vis_vals[i];
             const int v = (int)(rec / (uint32_t)N);
             const ushort4 rc = rect_sorted[i];
-            const int tx0 = rc.x / tile_w, tx1 = rc.y / tile_w, ty0 = rc.z / tile_h, ty1 = rc.w / tile_h;
+            // tile sides 2^tsx x 2^tsy pixels
+            const int tx0 = rc.x >> tsx, tx1 = rc.y >> tsx, ty0 = rc.z >> tsy, ty1 = rc.w >> tsy;
             const int gx0 = tx0 / GS, gx1 = tx1 / GS, gy0 = ty0 / GS;
             const sr_camera& c = cams[v];
             s_off[threadIdx.x] = offs[i];
@@ -604,6 +624,13 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
                                void* workspace, uint32_t cap, uint32_t* vals, uint64_t* keys64, uint32_t* ranges,
                                uint32_t* counters, uint32_t* status, bool count_only, hipStream_t s) {
     const uint64_t VN = (uint64_t)V * (uint64_t)N;
+    // pixel sides of a tile group as powers of two (a group is 4 x 4 tiles)
+    static_assert(SR_TILE_GROUP == 4, "group sides are two bits of tile coordinates");
+    int gsx = 0, gsy = 0;
+    while ((1 << gsx) < SR_TILE_GROUP * cfg.tile_w) ++gsx;
+    while ((1 << gsy) < SR_TILE_GROUP * cfg.tile_h) ++gsy;
+    if ((1 << gsx) != SR_TILE_GROUP * cfg.tile_w || (1 << gsy) != SR_TILE_GROUP * cfg.tile_h)
+        return hipErrorInvalidValue;
     BinWs w = carve(workspace, VN, cap);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, counters, 0u, (uint64_t)SR_COUNTERS);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, ranges, 0u, 2ull * (uint64_t)total_tiles);
@@ -624,8 +651,9 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
             hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kNT), 0, s, w.hist, G, w.tot);
             // sub-tiles of 2048 pairs (8 per digit on average): faster than
             // 1024, 4096 or 8192 in a sweep on the 1M-surfel, 16-view batch
+            // the sorted depth keys themselves are not used after the last pass
             hipLaunchKernelGGL(k_radix_scatter<8>, dim3(G), dim3(kNT), 0, s, sk, sv, counters, G, 8 * p, 8, w.hist,
-                               w.tot, dk, dv);
+                               w.tot, p == 3 ? nullptr : dk, dv);
             uint32_t* t;
             t = sk; sk = dk; dk = t;
             t = sv; sv = dv; dv = t;
@@ -634,8 +662,8 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     // after four passes the sorted pairs are in (vk0, vv0)
     // 3. instance offsets and emission in depth order
     const int Gi = Gv;
-    hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, (const ushort4*)rect,
-                       cfg.tile_w, cfg.tile_h, w.tts, w.rsort, w.isum);
+    hipLaunchKernelGGL(k_inst_count, dim3(Gi), dim3(kNT), 0, s, counters, Gi, w.vv0, (const ushort4*)rect, gsx, gsy,
+                       w.tts, w.rsort, w.isum);
     hipLaunchKernelGGL(k_scan_small<uint64_t>, dim3(1), dim3(kNT), 0, s, w.isum, Gi, counters, 1, cap, w.itotal,
                        count_only ? nullptr : status);
     if (count_only) return hipGetLastError();     // the instance count is all that was asked for
@@ -644,8 +672,8 @@ hipError_t launch_bin_and_sort(const sr_config& cfg, int N, int V, int total_til
     if (emit_blocks > 0) {
         hipLaunchKernelGGL(k_emit_starts, dim3((unsigned)((emit_blocks + kNT - 1) / kNT)), dim3(kNT), 0, s, counters,
                            w.ioff, (uint32_t)emit_blocks, w.estart);
-        hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kNT), 0, s, counters, w.itotal, N, cfg.tile_w,
-                           cfg.tile_h, cams_dev, w.vv0, (const ushort4*)w.rsort, w.ioff, w.estart, w.ik0, w.iv0);
+        hipLaunchKernelGGL(k_emit, dim3((unsigned)emit_blocks), dim3(kNT), 0, s, counters, w.itotal, N,
+                           gsx - 2, gsy - 2, cams_dev, w.vv0, (const ushort4*)w.rsort, w.ioff, w.estart, w.ik0, w.iv0);
     }
     // 4. stable sort by group id; values land in the caller's array
     int nbits = 0;
