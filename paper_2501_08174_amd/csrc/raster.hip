@@ -26,6 +26,22 @@ namespace {
 
 constexpr int kWaveBlock = 8;   // side of the square block of pixels one wave covers
 
+// Square root and reciprocal for the culling bounds: the hardware estimates
+// refined by one Newton step, far more accurate than the culling's 1e-3
+// margins need and a fraction of the instructions of the correctly rounded
+// operations.  x >= 0 for the root: below 1e-300 it is taken as 0 (an error
+// under 1e-150 px), an infinite x stays infinite; the reciprocal is taken of
+// positive normal numbers.
+__device__ __forceinline__ double cull_sqrt(double x) {
+    const double y = __builtin_amdgcn_rsq(x);                 // 1/sqrt(x), refined as y (3 - x y^2) / 2
+    const double r = x * (y * (1.5 - 0.5 * x * y * y));
+    return x > 1e-300 ? (x <= 1.7e308 ? r : x) : 0.0;
+}
+__device__ __forceinline__ double cull_rcp(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return r * (2.0 - x * r);
+}
+
 // Global tile id of this workgroup; pixel coordinates of this thread; the
 // run [start, start + n) of the tile's binning group.
 struct TileCtx {
@@ -123,16 +139,8 @@ __device__ __forceinline__ uint32_t band_bits(const float4& g0, const float4& g1
     constexpr double tau = 1e-3, mg = 1e-3;
     const uint32_t rx = __float_as_uint(a1.z), ry = __float_as_uint(a1.w);
     const int ilo = (int)(rx & 0xffffu), ihi = (int)(rx >> 16), jlo = (int)(ry & 0xffffu), jhi = (int)(ry >> 16);
-    const int clo = ilo > tx0 ? ilo : tx0, chi = ihi < tx0 + TW - 1 ? ihi : tx0 + TW - 1;
-    if (clo > chi) return 0u;
     const double cx = g2.y, cy = g2.z, L = Lf;
-    const double X0 = (clo + 0.5) - cx - mg, X1 = (chi + 0.5) - cx + mg;
-    // disc: |dy| <= hd
-    const double xd = fmin(fmax(0.0, X0), X1);
-    const double hd2 = L * (1.0 + tau) - xd * xd;
-    const double hd = hd2 >= 0.0 ? sqrt(hd2) : -1.0;
-    // surface: y-range [ylo, yhi] (empty when ylo > yhi)
-    double ylo = 1.0, yhi = -1.0;
+    // the conic's coefficients, independent of the columns
     const double s01 = 1.0 - tau, s2 = -2.0 * L * (1.0 + tau);
     const double a0 = g0.x, a1x = g0.y, a2 = g0.z, b0 = g0.w, b1 = g1.x, b2 = g1.y, c0 = g1.z, c1 = g1.w,
                  c2 = g2.x;
@@ -144,45 +152,60 @@ __device__ __forceinline__ uint32_t band_bits(const float4& g0, const float4& g1
     const double W = s01 * (b0 * c0 + b1 * c1) + s2 * (b2 * c2);
     const double K = s01 * (c0 * c0 + c1 * c1) + s2 * (c2 * c2);
     const double al = P * S - R * R;
-    if (!(P > 0.0 && S > 0.0 && al > 0.0)) {
-        ylo = -1e300;
-        yhi = 1e300;
-    } else {
-        // discriminant in y of Q(x, .): D(x) = -al x^2 + 2 be x + ga, >= 0 on the ellipse's columns
-        const double be = R * W - S * U, ga = W * W - S * K;
-        const double ex = be * be + al * ga;
-        if (ex >= 0.0) {
-            const double ia = 1.0 / al, sx = sqrt(ex);
-            const double xa = fmax(X0, (be - sx) * ia), xb = fmin(X1, (be + sx) * ia);
-            if (xa <= xb) {
-                // lowest and highest points: y roots of the discriminant in x, x on P x + R y + U = 0
-                const double bp = R * U - P * W, gp = U * U - P * K;
-                const double sy = sqrt(fmax(bp * bp + al * gp, 0.0));
-                const double iP = 1.0 / P, iS = 1.0 / S;
-                const double xbot = fmin(fmax(-(R * ((bp - sy) * ia) + U) * iP, xa), xb);
-                const double xtop = fmin(fmax(-(R * ((bp + sy) * ia) + U) * iP, xa), xb);
-                const double db = fmax((-al * xbot + 2.0 * be) * xbot + ga, 0.0);
-                const double dt = fmax((-al * xtop + 2.0 * be) * xtop + ga, 0.0);
-                ylo = (-(R * xbot + W) - sqrt(db)) * iS;
-                yhi = (-(R * xtop + W) + sqrt(dt)) * iS;
-            }
-        }
+    const bool ellipse = P > 0.0 && S > 0.0 && al > 0.0;
+    // discriminant in y of Q(x, .): D(x) = -al x^2 + 2 be x + ga, >= 0 on the ellipse's columns
+    const double be = R * W - S * U, ga = W * W - S * K;
+    const double ex = be * be + al * ga;
+    // the ellipse's columns [xl, xr] (empty unless ex >= 0) and the x of its
+    // lowest and highest points (on P x + R y + U = 0, y roots of the
+    // discriminant in x)
+    double xl = 1.0, xr = -1.0, xb0 = 0.0, xt0 = 0.0, iS = 0.0;
+    if (ellipse && ex >= 0.0) {
+        const double ia = cull_rcp(al), sx = cull_sqrt(ex);
+        xl = (be - sx) * ia;
+        xr = (be + sx) * ia;
+        const double bp = R * U - P * W, gp = U * U - P * K;
+        const double sy = cull_sqrt(fmax(bp * bp + al * gp, 0.0));
+        const double iP = cull_rcp(P);
+        iS = cull_rcp(S);
+        xb0 = -(R * ((bp - sy) * ia) + U) * iP;
+        xt0 = -(R * ((bp + sy) * ia) + U) * iP;
     }
     uint32_t bits = 0u;
+#pragma unroll 1
+    for (int bx = 0; bx < BX; ++bx) {
+        const int k0 = tx0 + bx * WB, k1 = k0 + WB - 1;
+        const int clo = ilo > k0 ? ilo : k0, chi = ihi < k1 ? ihi : k1;
+        if (clo > chi) continue;
+        const double X0 = (clo + 0.5) - cx - mg, X1 = (chi + 0.5) - cx + mg;
+        // disc: |dy| <= hd
+        const double xd = fmin(fmax(0.0, X0), X1);
+        const double hd2 = L * (1.0 + tau) - xd * xd;
+        const double hd = hd2 >= 0.0 ? cull_sqrt(hd2) : -1.0;
+        // surface: y-range [ylo, yhi] over these columns (empty when ylo > yhi)
+        double ylo = -1e300, yhi = 1e300;
+        if (ellipse) {
+            ylo = 1.0;
+            yhi = -1.0;
+            const double xa = fmax(X0, xl), xb = fmin(X1, xr);
+            if (xa <= xb) {
+                const double xbot = fmin(fmax(xb0, xa), xb);
+                const double xtop = fmin(fmax(xt0, xa), xb);
+                const double db = fmax((-al * xbot + 2.0 * be) * xbot + ga, 0.0);
+                const double dt = fmax((-al * xtop + 2.0 * be) * xtop + ga, 0.0);
+                ylo = (-(R * xbot + W) - cull_sqrt(db)) * iS;
+                yhi = (-(R * xtop + W) + cull_sqrt(dt)) * iS;
+            }
+        }
 #pragma unroll
-    for (int by = 0; by < BY; ++by) {
-        const int r0 = ty0 + by * WB, r1 = r0 + WB - 1;
-        const int lo = jlo > r0 ? jlo : r0, hi = jhi < r1 ? jhi : r1;
-        if (lo > hi) continue;
-        const double Y0 = (lo + 0.5) - cy - mg, Y1 = (hi + 0.5) - cy + mg;
-        const bool disc = hd >= 0.0 && Y0 <= hd && Y1 >= -hd;
-        const bool surf = ylo <= Y1 && yhi >= Y0;
-        if (!(disc || surf)) continue;
-        // the blocks of this row that the rectangle's columns meet
-#pragma unroll
-        for (int bx = 0; bx < BX; ++bx) {
-            const int k0 = tx0 + bx * WB, k1 = k0 + WB - 1;
-            if (clo <= k1 && chi >= k0) bits |= 1u << (by * BX + bx);
+        for (int by = 0; by < BY; ++by) {
+            const int r0 = ty0 + by * WB, r1 = r0 + WB - 1;
+            const int lo = jlo > r0 ? jlo : r0, hi = jhi < r1 ? jhi : r1;
+            if (lo > hi) continue;
+            const double Y0 = (lo + 0.5) - cy - mg, Y1 = (hi + 0.5) - cy + mg;
+            const bool disc = hd >= 0.0 && Y0 <= hd && Y1 >= -hd;
+            const bool surf = ylo <= Y1 && yhi >= Y0;
+            if (disc || surf) bits |= 1u << (by * BX + bx);
         }
     }
     return bits;
@@ -379,13 +402,18 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
             } else if (CULL) {
                 const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
-                bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                // the appearance is stored first: fewer registers live across the bounds
                 sm.a[0][tid] = a0;
                 n12 = make_float2(a1.x, a1.y);
+                reinterpret_cast<float2*>(&sm.a[1][tid])[0] = n12;
+                bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
                 if (bitcache) bitcache_put<NT>(bitcache, jpos, bits);
             }
             // the run position and the wave bits replace the packed rectangle
-            sm.a[1][tid] = make_float4(n12.x, n12.y, __uint_as_float(jpos), __uint_as_float(bits));
+            if (CULL && !RECT)
+                reinterpret_cast<float2*>(&sm.a[1][tid])[1] = make_float2(__uint_as_float(jpos), __uint_as_float(bits));
+            else
+                sm.a[1][tid] = make_float4(n12.x, n12.y, __uint_as_float(jpos), __uint_as_float(bits));
             if (HITS) {
                 sm.id[tid] = g;
                 sm.st[0][tid] = 0u;
@@ -702,13 +730,14 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                     sm.g[q][tid] = gq[q];
                 }
                 const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
+                sm.a[0][tid] = a0;
+                reinterpret_cast<float2*>(&sm.a[1][tid])[0] = make_float2(a1.x, a1.y);
                 // the forward's wave bits of this position when cached
                 const uint32_t bits = (bitcache && jpos < BitCache<NT>::kPos)
                                           ? (bitcache[jpos >> 3] >> ((jpos & 7u) << 2)) & 0xFu
                                           : band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
-                sm.a[0][tid] = a0;
                 // entries at or beyond the wave's last contributor concern no lane of it
-                sm.a[1][tid] = make_float4(a1.x, a1.y, __uint_as_float(jpos), __uint_as_float(bits));
+                reinterpret_cast<float2*>(&sm.a[1][tid])[1] = make_float2(__uint_as_float(jpos), __uint_as_float(bits));
                 sm.rec[tid] = (uint32_t)r;
             }
 #pragma unroll
