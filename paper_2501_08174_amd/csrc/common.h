@@ -207,7 +207,9 @@ __device__ __forceinline__ void eval_finish(const float4& g2, const float4& g3, 
     e.G = __builtin_amdgcn_exp2f(-1.4426950408889634f * e.rho);
     const float oG = g2.w * e.G;
     e.clamped = oG > alpha_max;
-    e.a = e.clamped ? alpha_max : oG;
+    // min(oG, alpha_max) as the median of (oG, 0, alpha_max): oG >= 0, and
+    // one instruction where the select needs the bound in a vector register
+    e.a = __builtin_amdgcn_fmed3f(oG, 0.0f, alpha_max);
     e.z = e.surf ? __builtin_fmaf(g3.x, e.u, __builtin_fmaf(g3.y, e.v, g3.z)) : g3.z;
 }
 
