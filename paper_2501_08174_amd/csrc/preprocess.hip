@@ -516,9 +516,17 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
     }
     const float* shg = sh + (size_t)g * sh_stride * 3;
 
-    for (int v = 0; v < V; ++v) {
-        const size_t r = (size_t)v * N + g;
-        if (tiles_touched) {
+    // views in chunks of 32: the records' visibility and marks are read for
+    // the whole chunk first (independent loads in flight), then only the
+    // views that hold gradients are worked through
+    for (int v0 = 0; v0 < V; v0 += 32) {
+      const int vn = V - v0 < 32 ? V - v0 : 32;
+      uint32_t todo = 0u;
+      if (tiles_touched) {
+#pragma unroll 8
+        for (int j = 0; j < 32; ++j) {
+            if (j >= vn) break;
+            const size_t r = (size_t)(v0 + j) * N + g;
             const uint32_t tt = tiles_touched[r];
             if ((tt & 0x7FFFFFFFu) == 0u) continue;          // culled in this view
             dens_n += 1u;
@@ -527,9 +535,16 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
                 if ((tt >> 31) == 0u) continue;
                 tiles_touched[r] = tt & 0x7FFFFFFFu;
             }
-        } else {
-            dens_n += 1u;
+            todo |= 1u << j;
         }
+      } else {
+        dens_n += (uint32_t)vn;
+        todo = vn == 32 ? 0xFFFFFFFFu : ((1u << vn) - 1u);
+      }
+      while (todo != 0u) {
+        const int v = v0 + __builtin_ctz(todo);
+        todo &= todo - 1u;
+        const size_t r = (size_t)v * N + g;
         float* gr = grad_rec + r * SR_GRAD_STRIDE;
         float G[kNumGrad];
         bool any = false;
@@ -655,6 +670,7 @@ k_preprocess_bwd(int N, const float* __restrict__ means, const float* __restrict
             const float dp = d[0] * dd[0] + d[1] * dd[1] + d[2] * dd[2];
             for (int k = 0; k < 3; ++k) dmu[k] += (dd[k] - d[k] * dp) * il;
         }
+      }
     }
     // rotation matrix R(q^) with columns (t_u, t_v, n): dR_ik
     const float d00 = dtu[0], d10 = dtu[1], d20 = dtu[2];
