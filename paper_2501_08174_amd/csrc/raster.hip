@@ -116,7 +116,7 @@ constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8, kRect = 16, kHits
 // with one ballot of its bit and walks only the set bits of that mask, so
 // skipped entries cost no per-entry instructions.  A block is reached when
 // the entry's pixel rectangle (packed in the last two slots of the appearance
-// record) meets it and the y-range, within the tile's columns that the
+// record) meets it and the y-range, within the block's columns that the
 // rectangle meets, of the entry's cutoff conic or of its low-pass disc meets
 // the block's rows:
 //   surface  Q = (1 - tau)(w0^2 + w1^2) - 2 L (1 + tau) w2^2 <= 0 with
@@ -131,7 +131,7 @@ constexpr int kShade = 1, kStats = 2, kCount = 4, kMedian = 8, kRect = 16, kHits
 // skipped only where the exact test fails by a relative margin, and forward
 // and backward skip the same entries.
 template <int TW, int NW>
-__device__ __forceinline__ uint32_t band_bits(const float4& g0, const float4& g1, const float4& g2, float Lf,
+__device__ __forceinline__ uint32_t wave_bits(const float4& g0, const float4& g1, const float4& g2, float Lf,
                                               const float4& a1, int tx0, int ty0) {
     constexpr int WB = kWaveBlock;
     static_assert(TW % WB == 0 && NW % (TW / WB) == 0, "waves cover whole 8x8 blocks of the tile");
@@ -399,14 +399,14 @@ __device__ __forceinline__ void fwd_tile(const TileCtx& t, float px, float py, i
                 // ushort4 rectangle (x_lo, x_hi, y_lo, y_hi) read as two packed ranges
                 const uint2 rr = rect[r];
                 const float4 a1 = make_float4(0.f, 0.f, __uint_as_float(rr.x), __uint_as_float(rr.y));
-                bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                bits = wave_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
             } else if (CULL) {
                 const float4 a0 = app[kAppF4 * r], a1 = app[kAppF4 * r + 1];
                 // the appearance is stored first: fewer registers live across the bounds
                 sm.a[0][tid] = a0;
                 n12 = make_float2(a1.x, a1.y);
                 reinterpret_cast<float2*>(&sm.a[1][tid])[0] = n12;
-                bits = band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                bits = wave_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
                 if (bitcache) bitcache_put<NT>(bitcache, jpos, bits);
             }
             // the run position and the wave bits replace the packed rectangle
@@ -735,7 +735,7 @@ __device__ __forceinline__ void bwd_tile(const TileCtx& t, float px, float py, i
                 // the forward's wave bits of this position when cached
                 const uint32_t bits = (bitcache && jpos < BitCache<NT>::kPos)
                                           ? (bitcache[jpos >> 3] >> ((jpos & 7u) << 2)) & 0xFu
-                                          : band_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
+                                          : wave_bits<TW, NT / 64>(gq[0], gq[1], gq[2], gq[3].w, a1, t.tx0, t.ty0);
                 // entries at or beyond the wave's last contributor concern no lane of it
                 reinterpret_cast<float2*>(&sm.a[1][tid])[1] = make_float2(__uint_as_float(jpos), __uint_as_float(bits));
                 sm.rec[tid] = (uint32_t)r;
