@@ -368,6 +368,18 @@ def test_backward_matches_oracle_autograd(deg):
     compare_grads(g, gref, excl)
 
 
+def test_extreme_shapes_gradients():
+    """The backward on the needle / edge-on / sub-pixel / large scene against
+    the oracle's autograd at the gradient bar: the culling bits the backward
+    reads and the pair gradients near degenerate conics."""
+    sc = _extreme_scene()
+    w = _weights(sc, np.random.default_rng(9))
+    g, rast = _gpu_grads(sc, w)
+    gref, excl = _oracle_grads(sc, w, geometry(sc), rast)
+    print("surfels left out (an entry at the alpha clamp):", len(excl))
+    compare_grads(g, gref, excl)
+
+
 # every compiled (tile shape, backward LDS batch)
 BWD_VARIANTS = ([((16, 16), b) for b in (32, 64, 128, 256)] + [((32, 8), b) for b in (32, 64, 128, 256)] +
                 [((16, 8), b) for b in (32, 64, 128)] + [((8, 8), b) for b in (32, 64)])
