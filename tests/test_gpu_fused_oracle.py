@@ -18,7 +18,7 @@ from paper_2501_08174_amd import scenes
 from paper_2501_08174_amd.raster import Params, Rasterizer, ViewBatch
 from tests.gpu_helpers import (clamp_tie_ids, compare_forward, compare_grads, crop_pixels, masked_loss_fn,
                                masked_terms, per_view)
-from tests.test_gpu_parity import BWD_VARIANTS
+from tests.test_gpu_parity import BWD_VARIANTS, _extreme_scene
 
 pytestmark = pytest.mark.gpu
 RP = oracle.RasterParams()
@@ -69,11 +69,13 @@ def _ragged(seed=61, n=500, deg=3):
                                     scale_range=(0.02, 0.3))
 
 
-@pytest.mark.parametrize("level", [1, 2])
-def test_fused_step_matches_oracle_small(level):
-    """Ragged three-view scene, whole views: outputs, per-view losses,
-    statistics and gradients of the fused launch against the oracle."""
-    sc = _ragged()
+@pytest.mark.parametrize("level,make", [(1, _ragged), (2, _ragged), (1, _extreme_scene)],
+                         ids=["ragged-counts", "ragged-full", "degenerate-counts"])
+def test_fused_step_matches_oracle_small(level, make):
+    """Ragged three-view scene (and the scene of needles, edge-on, sub-pixel
+    and large surfels), whole views: outputs, per-view losses, statistics
+    and gradients of the fused launch against the oracle."""
+    sc = make()
     rng = np.random.default_rng(62)
     masks = [rng.integers(0, 2, size=(c.height, c.width)).astype(np.uint8) for c in sc.cams]
     targets = [rng.uniform(size=(3, c.height, c.width)).astype(np.float32) for c in sc.cams]
