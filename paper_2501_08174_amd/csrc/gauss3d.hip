@@ -116,42 +116,50 @@ k_preprocess3d(int N, const float* __restrict__ means, const float* __restrict__
     geom3[2 * r + 1] = make_float4((float)ccx, (float)ccy, (float)L, 0.0f);
 }
 
-// Bits of the waves (bands of 64 / TW rows of the tile) that the cutoff
-// ellipse q = a dx^2 + 2 b dx dy + c dy^2 <= 2 L of one record can reach
-// within the tile's columns, in float64 with a relative slack tau on 2 L and
-// a 1e-3 pixel margin (an entry is skipped only where the exact test fails by
-// a margin).  For fixed dx the ellipse is the interval of dy between the
-// roots of c dy^2 + 2 b dx dy + a dx^2 - 2 L; its lower end is convex and its
-// upper end concave in dx, so their extremes over the columns sit at the
-// lowest / highest point of the ellipse clamped to the columns.
+// Bits of the waves that the cutoff ellipse q = a dx^2 + 2 b dx dy + c dy^2
+// <= 2 L of one record can reach.  Every wave covers an 8x8 block of the tile
+// (wave w: block column w % (TW / 8), block row w / (TW / 8)); float64 with a
+// relative slack tau on 2 L and a 1e-3 pixel margin (an entry is skipped
+// only where the exact test fails by a margin).  For fixed dx the ellipse is
+// the interval of dy between the roots of c dy^2 + 2 b dx dy + a dx^2 - 2 L;
+// its lower end is convex and its upper end concave in dx, so their extremes
+// over a block's columns sit at the lowest / highest point of the ellipse
+// clamped to those columns.
+constexpr int kWaveBlock3d = 8;
+
 template <int TW, int NW>
 __device__ __forceinline__ uint32_t band_bits3d(const float4& c0, const float4& c1, int tx0, int ty0) {
-    constexpr int RW = 64 / TW;
+    constexpr int WB = kWaveBlock3d;
+    static_assert(TW % WB == 0 && NW % (TW / WB) == 0, "waves cover whole 8x8 blocks of the tile");
+    constexpr int BX = TW / WB, BY = NW / BX;
     constexpr double tau = 1e-3, mg = 1e-3;
     const double a = c0.x, b = c0.y, c = c0.z, cx = c1.x, cy = c1.y;
     const double r2 = 2.0 * (double)c1.z * (1.0 + tau);
     const double det = a * c - b * b;
     if (!(a > 0.0 && c > 0.0 && det > 0.0)) return (1u << NW) - 1u;     // not an ellipse: keep
-    const double X0 = (tx0 + 0.5) - cx - mg, X1 = (tx0 + TW - 0.5) - cx + mg;
     const double hx = sqrt(r2 * c / det);                  // the ellipse's half width
-    const double xa = fmax(X0, -hx), xb = fmin(X1, hx);
-    if (xa > xb) return 0u;
     const double hy = sqrt(r2 * a / det);                  // lowest / highest points at dy = -+hy
-    const double xbot = fmin(fmax(b * hy / a, xa), xb), xtop = fmin(fmax(-b * hy / a, xa), xb);
-    const double ylo = (-b * xbot - sqrt(fmax(r2 * c - det * xbot * xbot, 0.0))) / c;
-    const double yhi = (-b * xtop + sqrt(fmax(r2 * c - det * xtop * xtop, 0.0))) / c;
     uint32_t bits = 0u;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const double Y0 = (ty0 + w * RW + 0.5) - cy - mg, Y1 = (ty0 + w * RW + RW - 0.5) - cy + mg;
-        if (ylo <= Y1 && yhi >= Y0) bits |= 1u << w;
+    for (int bx = 0; bx < BX; ++bx) {
+        const double X0 = (tx0 + bx * WB + 0.5) - cx - mg, X1 = (tx0 + bx * WB + WB - 0.5) - cx + mg;
+        const double xa = fmax(X0, -hx), xb = fmin(X1, hx);
+        if (xa > xb) continue;
+        const double xbot = fmin(fmax(b * hy / a, xa), xb), xtop = fmin(fmax(-b * hy / a, xa), xb);
+        const double ylo = (-b * xbot - sqrt(fmax(r2 * c - det * xbot * xbot, 0.0))) / c;
+        const double yhi = (-b * xtop + sqrt(fmax(r2 * c - det * xtop * xtop, 0.0))) / c;
+#pragma unroll
+        for (int by = 0; by < BY; ++by) {
+            const double Y0 = (ty0 + by * WB + 0.5) - cy - mg, Y1 = (ty0 + by * WB + WB - 0.5) - cy + mg;
+            if (ylo <= Y1 && yhi >= Y0) bits |= 1u << (by * BX + bx);
+        }
     }
     return bits;
 }
 
 // Front to back over a tile's list; every thread owns one pixel; only the
 // occlusion statistics (hits, max alpha, max weight) are written.  Each
-// wave walks only the entries whose ellipse reaches its rows.
+// wave walks only the entries whose ellipse reaches its block.
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH)
 k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __restrict__ geom3,
@@ -168,7 +176,10 @@ k_prune3d(const sr_camera* __restrict__ cams, int V, int N, const float4* __rest
     const sr_camera& c = cams[v];
     const int local = tile - c.tile_offset;
     const int ty = local / c.tiles_x, tx = local - ty * c.tiles_x;
-    const int ix = tx * TW + (int)(threadIdx.x % TW), iy = ty * TH + (int)(threadIdx.x / TW);
+    // wave w covers the 8x8 block (w % (TW / 8), w / (TW / 8)) of the tile
+    constexpr int WB = kWaveBlock3d;
+    const int wt = (int)threadIdx.x >> 6, lt = (int)threadIdx.x & 63;
+    const int ix = tx * TW + (wt % (TW / WB)) * WB + (lt % WB), iy = ty * TH + (wt / (TW / WB)) * WB + lt / WB;
     const int wv = (int)__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6;
     const float px = (float)ix + 0.5f, py = (float)iy + 0.5f;
     const uint2 rg = ranges[tile];
